@@ -1,0 +1,220 @@
+"""FP64 CPU oracle for the OctTree solver (Wuensch et al. 2018).
+
+TEST INFRASTRUCTURE ONLY: tests/, the smoke check and the benchmark's CPU
+baseline are the only callers.  The C sources in this directory are plain,
+slow and independent of the GPU library (no shared code, headers or tables).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+SOURCES = ["octoracle.c", "ewald.c"]
+
+ERRORS = {1: "bad level/coord", 2: "duplicate block", 3: "overlapping blocks",
+          4: "hole in the block tiling", 5: "bad density", 6: "unsupported BCs"}
+
+
+def build(force=True):
+    """Compile liboracle.so with gcc (FP64, no FMA contraction, OpenMP)."""
+    if not force and os.path.exists(LIB):
+        return LIB
+    srcs = [os.path.join(HERE, s) for s in SOURCES]
+    tmp = LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-fopenmp",
+           "-ffp-contract=off", "-fno-fast-math", "-o", tmp] + srcs + ["-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+class Params(C.Structure):
+    _fields_ = [("nroot", C.c_int32 * 3), ("bc", C.c_int32 * 3), ("root_size", C.c_double),
+                ("origin", C.c_double * 3), ("G", C.c_double), ("theta", C.c_double),
+                ("eta_sb", C.c_double), ("a_lim", C.c_double), ("theta_pix", C.c_double),
+                ("mac", C.c_int32), ("ewald", C.c_int32), ("ew_n", C.c_int32),
+                ("ew_rcut2", C.c_int32), ("ew_fcut2", C.c_int32), ("pad_", C.c_int32),
+                ("ew_alpha", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        vp, i64, dp = C.c_void_p, C.c_int64, C.POINTER(C.c_double)
+        L.or_tree_new.restype = vp
+        L.or_tree_new.argtypes = [C.POINTER(Params), i64, vp, vp, vp, C.POINTER(C.c_int)]
+        L.or_tree_free.argtypes = [vp]
+        L.or_tree_na.restype = i64
+        L.or_tree_na.argtypes = [vp]
+        L.or_tree_nn.restype = i64
+        L.or_tree_nn.argtypes = [vp]
+        L.or_tree_export.argtypes = [vp] + [vp] * 7
+        L.or_block_list.restype = i64
+        L.or_block_list.argtypes = [vp, i64, vp, i64]
+        L.or_walk_group.argtypes = [vp, vp, vp, vp]
+        L.or_walk_group_blocks.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.or_walk_percell.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.or_direct.argtypes = [vp, i64, vp, vp, vp]
+        L.or_morton.restype = C.c_uint64
+        L.or_morton.argtypes = [C.c_uint64] * 3
+        L.or_ewald_eval.argtypes = [C.c_int, vp, C.c_double, C.c_int, C.c_int, C.c_int, i64, vp, vp]
+        L.or_ewald_table.argtypes = [C.c_int, vp, C.c_double, C.c_int, C.c_int, C.c_int, vp]
+        L.or_ewald_table_lookup.argtypes = [C.c_int, vp, C.c_int, vp, i64, vp, vp]
+        L.or_itilde.argtypes = [C.c_double, C.c_double, C.c_double, vp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+BC_ISO, BC_3P, BC_2P1I = 0, 1, 2
+
+
+def bctype(bc):
+    bc = tuple(int(b) for b in bc)
+    if bc == (0, 0, 0):
+        return BC_ISO
+    if bc == (1, 1, 1):
+        return BC_3P
+    if bc == (1, 1, 0):
+        return BC_2P1I
+    raise ValueError("unsupported boundary combination")
+
+
+def make_params(grid, theta=0.5, eta_sb=1.2, mac="bh", a_lim=0.0, theta_pix=0.0, G=1.0,
+                ewald="exact", ew_n=64, ew_alpha=0.0, ew_rcut2=0, ew_fcut2=0, bc=None):
+    p = Params()
+    for k in range(3):
+        p.nroot[k] = int(grid.nroot[k])
+        p.bc[k] = int((bc if bc is not None else grid.bc)[k])
+        p.origin[k] = float(grid.origin[k])
+    p.root_size = float(grid.root_size)
+    p.G, p.theta, p.eta_sb, p.a_lim, p.theta_pix = G, theta, eta_sb, a_lim, theta_pix
+    p.mac = {"bh": 0, "ape": 1}[mac]
+    p.ewald = {"exact": 0, "table": 1}[ewald]
+    p.ew_n, p.ew_alpha, p.ew_rcut2, p.ew_fcut2 = ew_n, ew_alpha, ew_rcut2, ew_fcut2
+    return p
+
+
+class Tree:
+    """Oracle tree over a workloads.Grid (FP64 moments, walks, direct sums)."""
+
+    def __init__(self, grid, **kw):
+        self.grid = grid
+        self.params = make_params(grid, **kw)
+        self.level = np.ascontiguousarray(grid.level, dtype=np.int32)
+        self.coord = np.ascontiguousarray(grid.coord, dtype=np.int32)
+        self.rho = np.ascontiguousarray(grid.rho, dtype=np.float64)
+        err = C.c_int(0)
+        self.h = lib().or_tree_new(C.byref(self.params), grid.nb, _ptr(self.level),
+                                   _ptr(self.coord), _ptr(self.rho), C.byref(err))
+        if not self.h:
+            raise ValueError(f"oracle rejected the grid: {ERRORS.get(err.value, err.value)}")
+        self.nb = grid.nb
+        self.na = lib().or_tree_na(self.h)
+        self.nn = lib().or_tree_nn(self.h)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().or_tree_free(self.h)
+            self.h = None
+
+    def export(self):
+        na, nn = self.na, self.nn
+        out = dict(alev=np.empty(na, np.int32), acoord=np.empty((na, 3), np.int32),
+                   aleaf=np.empty(na, np.int64), achild=np.empty((na, 8), np.int64),
+                   akey=np.empty(na, np.uint64), M=np.empty(nn), com=np.empty((nn, 3)))
+        lib().or_tree_export(self.h, *(_ptr(out[k]) for k in
+                                       ("alev", "acoord", "aleaf", "achild", "akey", "M", "com")))
+        return out
+
+    def block_list(self, lb):
+        n = lib().or_block_list(self.h, lb, None, 0)
+        ids = np.empty(n, np.int64)
+        lib().or_block_list(self.h, lb, _ptr(ids), n)
+        return ids
+
+    def walk_group(self, blocks=None):
+        if blocks is None:
+            nc = 512 * self.nb
+            phi, acc, nint = np.empty(nc), np.empty((3, nc)), np.empty(self.nb, np.int64)
+            lib().or_walk_group(self.h, _ptr(phi), _ptr(acc), _ptr(nint))
+        else:
+            sel = np.ascontiguousarray(blocks, dtype=np.int64)
+            nc = 512 * sel.size
+            phi, acc, nint = np.empty(nc), np.empty((3, nc)), np.empty(sel.size, np.int64)
+            lib().or_walk_group_blocks(self.h, sel.size, _ptr(sel), _ptr(phi), _ptr(acc), _ptr(nint))
+        return phi, acc, nint
+
+    def walk_percell(self, targets):
+        tg = np.ascontiguousarray(targets, dtype=np.int64)
+        phi, acc, nint = np.empty(tg.size), np.empty((3, tg.size)), np.empty(tg.size, np.int64)
+        lib().or_walk_percell(self.h, tg.size, _ptr(tg), _ptr(phi), _ptr(acc), _ptr(nint))
+        return phi, acc, nint
+
+    def direct(self, targets=None):
+        if targets is None:
+            targets = np.arange(512 * self.nb)
+        tg = np.ascontiguousarray(targets, dtype=np.int64)
+        phi, acc = np.empty(tg.size), np.empty((3, tg.size))
+        lib().or_direct(self.h, tg.size, _ptr(tg), _ptr(phi), _ptr(acc))
+        return phi, acc
+
+
+def morton(x, y, z):
+    return int(lib().or_morton(int(x), int(y), int(z)))
+
+
+def ewald_eval(bc, box, d, alpha=0.0, rcut2=0, fcut2=10, correction=False):
+    """phi, A (3), H (6: xx yy zz xy xz yz) of the Ewald series at offsets d [n, 3]."""
+    bt = bctype(bc)
+    if rcut2 <= 0:
+        rcut2 = 15 if bt == BC_3P else 10
+    box = np.ascontiguousarray(box, dtype=np.float64)
+    d = np.ascontiguousarray(np.atleast_2d(d), dtype=np.float64)
+    out = np.empty((d.shape[0], 10))
+    a = alpha if alpha > 0 else 2.0 / box[0]
+    lib().or_ewald_eval(bt, _ptr(box), a, rcut2, fcut2, int(correction), d.shape[0], _ptr(d), _ptr(out))
+    return out
+
+
+def ewald_table(bc, box, n=64, alpha=0.0, rcut2=0, fcut2=10):
+    bt = bctype(bc)
+    if rcut2 <= 0:
+        rcut2 = 15 if bt == BC_3P else 10
+    box = np.ascontiguousarray(box, dtype=np.float64)
+    out = np.empty((n, n, n, 10))
+    a = alpha if alpha > 0 else 2.0 / box[0]
+    lib().or_ewald_table(bt, _ptr(box), a, rcut2, fcut2, n, _ptr(out))
+    return out
+
+
+def ewald_table_lookup(bc, box, table, d):
+    bt = bctype(bc)
+    box = np.ascontiguousarray(box, dtype=np.float64)
+    table = np.ascontiguousarray(table, dtype=np.float64)
+    d = np.ascontiguousarray(np.atleast_2d(d), dtype=np.float64)
+    out = np.empty((d.shape[0], 4))
+    lib().or_ewald_table_lookup(bt, _ptr(box), table.shape[0], _ptr(table), d.shape[0], _ptr(d), _ptr(out))
+    return out
+
+
+def itilde(s, zeta, gam):
+    """2P1I integral Itilde(s, gamma) and its first two gamma-derivatives
+    (s = 0: the regularised l = 0 term I(0, 0, gamma))."""
+    out = np.empty(3)
+    lib().or_itilde(float(s), float(zeta), float(gam), _ptr(out))
+    return out

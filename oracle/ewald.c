@@ -1,0 +1,348 @@
+/*
+ * Ewald kernels for periodic (3P) and mixed (2P1I) boundary conditions.
+ * TEST INFRASTRUCTURE ONLY (FP64 oracle, see octoracle.h).
+ *
+ * phi(d) is the potential kernel of a unit mass (Phi = -G M phi) and
+ * A = -grad phi (a = -G M A), App. A.
+ *   3P   (Sec. 2.2.2, Eq. (9); App. A.1):
+ *        phi = sum_i erfc(alpha|d - n_i|)/|d - n_i|
+ *            + 1/(pi b c Lx) sum_{l != 0} E(l) cos(k.d),
+ *        E(l) = exp(-zeta Q)/Q, Q = l1^2 + (l2/b)^2 + (l3/c)^2.
+ *   2P1I (Sec. 2.2.3, Eq. (15) with the code form in its footnote; App. A.2):
+ *        phi = sum_{i1,i2} erfc(alpha|d - n_i|)/|d - n_i|
+ *            + 1/(pi Lx b) sum_{l1,l2} cos(v_l) Itilde(l1, l2, dz).
+ * Itilde is evaluated at |gamma| (it is even in gamma, its derivative odd).
+ * The l = 0 term uses I(0,0) of Eq. (14); its derivative is -pi erf(gamma/2 sqrt(zeta)).
+ *
+ * Readings: the printed 3P potential has no k = 0 constant and it is kept
+ * that way; real-space cut-off |i|^2 <= 15 (3P) and <= 10 (2P1I), Fourier
+ * cut-off <= 10 (both); alpha = 2/Lx unless a test sets another value.
+ * Long double is used where cancellation or large exponentials would cost
+ * digits; the l = 0 real-space term of the correction, -erf(alpha r)/r, uses
+ * its Taylor series below alpha r = 0.2.
+ *
+ * Table (Sec. 2.2.4, second approach): phi_c = phi - 1/r, A_c and the six
+ * second derivatives of phi_c on a uniform grid over the folded domain
+ * (phi_c even, A_c,k odd in d_k): [0, Lx/2] x [0, Ly/2] x [0, Lz/2] for 3P and
+ * [0, Lx/2] x [0, Ly/2] x [0, min(Lz, 2 Lx)] for 2P1I, n points per axis with
+ * both ends.  Look-up: nearest grid point, first-order Taylor expansion of
+ * phi_c and of each component of A_c.  For 2P1I and |dz| > 2 Lx the analytic
+ * limit is used: phi -> -2 pi |dz| / (b Lx^2) + sqrt(pi) / (b Lx), whose sign
+ * follows from the l = 0 term (the paper prints the magnitude).
+ */
+#include "oracle_internal.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define PI_L 3.141592653589793238462643383279502884L
+
+static const long double SQRTPI_L = 1.772453850905516027298167483341145183L;
+
+/* real-space image term f(r) = erfc(alpha r)/r: value, D1 = f'/r, D2 = (D1)'/r */
+static void erfc_term(long double a, long double r, long double *f, long double *D1,
+                      long double *D2) {
+  long double r2 = r * r;
+  long double ex = (2.0L * a / SQRTPI_L) * expl(-a * a * r2);
+  long double ec = erfcl(a * r);
+  *f = ec / r;
+  *D1 = -(ex / r2 + ec / (r2 * r));
+  *D2 = ex * (2.0L * a * a / r2 + 3.0L / (r2 * r2)) + 3.0L * ec / (r2 * r2 * r);
+}
+
+/* correction term g(r) = -erf(alpha r)/r (= erfc/r - 1/r): value, D1, D2 */
+static void erf_corr_term(long double a, long double r, long double *g, long double *D1,
+                          long double *D2) {
+  long double x = a * r;
+  if (x < 0.2L) {
+    /* erf(x)/x = 2/sqrt(pi) sum_n (-1)^n x^{2n} / (n! (2n+1)) */
+    long double c = 2.0L * a / SQRTPI_L;
+    long double s0 = 0, s1 = 0, s2 = 0, fact = 1, x2 = x * x;
+    long double p0 = 1, p1 = 0, p2 = 0; /* x^{2n}, x^{2n-2}, x^{2n-4} */
+    for (int n = 0; n < 16; ++n) {
+      if (n > 0) fact *= n;
+      long double an = ((n & 1) ? -1.0L : 1.0L) / (fact * (2 * n + 1));
+      s0 += an * p0;
+      if (n >= 1) s1 += 2.0L * n * an * p1;
+      if (n >= 2) s2 += 2.0L * n * (2.0L * n - 2.0L) * an * p2;
+      p2 = (n >= 1) ? p1 : 0;
+      p1 = p0;
+      p0 *= x2;
+    }
+    *g = -c * s0;
+    *D1 = -c * a * a * s1;
+    *D2 = -c * a * a * a * a * s2;
+    return;
+  }
+  long double r2 = r * r;
+  long double ex = (2.0L * a / SQRTPI_L) * expl(-a * a * r2);
+  long double ef = erfl(x);
+  *g = -ef / r;
+  *D1 = -ex / r2 + ef / (r2 * r);
+  *D2 = ex * (2.0L * a * a / r2 + 3.0L / (r2 * r2)) - 3.0L * ef / (r2 * r2 * r);
+}
+
+/* add radial term (value f, D1, D2) at offset x (|x| = r) to phi, A, H */
+static void add_radial(long double f, long double D1, long double D2, const long double x[3],
+                       long double *phi, long double A[3], long double H[6]) {
+  *phi += f;
+  for (int k = 0; k < 3; ++k) A[k] -= D1 * x[k];
+  if (H) {
+    H[0] += D2 * x[0] * x[0] + D1;
+    H[1] += D2 * x[1] * x[1] + D1;
+    H[2] += D2 * x[2] * x[2] + D1;
+    H[3] += D2 * x[0] * x[1];
+    H[4] += D2 * x[0] * x[2];
+    H[5] += D2 * x[1] * x[2];
+  }
+}
+
+/* 2P1I: Itilde, its first and second derivative in gamma, for s > 0 */
+static void itilde(long double s, long double zeta, long double gam, long double *I0,
+                   long double *I1, long double *I2) {
+  long double sg = gam < 0 ? -1.0L : 1.0L;
+  long double g = fabsl(gam);
+  long double sz = sqrtl(zeta);
+  long double Ap = sz * s + g / (2.0L * sz);
+  long double Am = sz * s - g / (2.0L * sz);
+  long double E1 = expl(g * s) * erfcl(Ap);  /* = exp(-g^2/4z - z s^2) erfcx(Ap) */
+  long double E2 = expl(-g * s) * erfcl(Am);
+  long double gauss = expl(-zeta * s * s - g * g / (4.0L * zeta));
+  *I0 = PI_L / (2.0L * s) * (E1 + E2);
+  *I1 = sg * (PI_L / 2.0L) * (E1 - E2);
+  *I2 = (PI_L / 2.0L) * (s * (E1 + E2) - 2.0L / sqrtl(PI_L * zeta) * gauss);
+}
+
+/* 2P1I: the l1 = l2 = 0 term I(0,0) of Eq. (14) and its derivatives */
+static void i00(long double zeta, long double gam, long double *I0, long double *I1,
+                long double *I2) {
+  long double sz = sqrtl(zeta);
+  long double e = erfl(gam / (2.0L * sz));
+  long double gauss = expl(-gam * gam / (4.0L * zeta));
+  *I0 = -PI_L * (gam * e + 2.0L * sqrtl(zeta / PI_L) * gauss) + 2.0L * sqrtl(PI_L * zeta);
+  *I1 = -PI_L * e;
+  *I2 = -(SQRTPI_L / sz) * gauss;
+}
+
+void or_ewald_series(const or_ewald *e, const double dd[3], int correction, double *phi_out,
+                     double A_out[3], double H_out[6]) {
+  long double d[3] = {dd[0], dd[1], dd[2]};
+  long double Lx = e->Lx, b = e->b, c = e->c, a = e->alpha, zeta = e->zeta;
+  long double phi = 0, A[3] = {0, 0, 0}, Hs[6] = {0, 0, 0, 0, 0, 0};
+  long double *H = H_out ? Hs : NULL;
+  int three = e->bctype == OR_BC_3P;
+  /* loop bounds that cover the cut-off ellipsoids */
+  double rr = sqrt((double)e->rcut2), fr = sqrt((double)e->fcut2);
+  int R1 = (int)ceil(rr) + 1, R2 = (int)ceil(rr / e->b) + 1, R3 = three ? (int)ceil(rr / e->c) + 1 : 0;
+  int F1 = (int)ceil(fr) + 1, F2 = (int)ceil(fr * e->b) + 1, F3 = (int)ceil(fr * e->c) + 1;
+  /* real space */
+  for (int i3 = -R3; i3 <= R3; ++i3)
+    for (int i2 = -R2; i2 <= R2; ++i2)
+      for (int i1 = -R1; i1 <= R1; ++i1) {
+        long double q = (long double)i1 * i1 + (b * i2) * (b * i2) + (c * i3) * (c * i3);
+        if (q > e->rcut2) continue;
+        long double x[3] = {d[0] - i1 * Lx, d[1] - i2 * b * Lx, d[2] - i3 * c * Lx};
+        long double r = sqrtl(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        long double f, D1, D2;
+        if (i1 == 0 && i2 == 0 && i3 == 0 && correction) {
+          erf_corr_term(a, r, &f, &D1, &D2);
+        } else {
+          if (r == 0) continue; /* not used: the d = 0 pair is excluded */
+          erfc_term(a, r, &f, &D1, &D2);
+        }
+        add_radial(f, D1, D2, x, &phi, A, H);
+      }
+  long double kap = 2.0L * PI_L / Lx;
+  if (three) {
+    long double pre = 1.0L / (PI_L * b * c * Lx);
+    for (int l3 = -F3; l3 <= F3; ++l3)
+      for (int l2 = -F2; l2 <= F2; ++l2)
+        for (int l1 = -F1; l1 <= F1; ++l1) {
+          if (!l1 && !l2 && !l3) continue;
+          long double qv[3] = {(long double)l1, l2 / b, l3 / c};
+          long double Q = qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2];
+          if (Q > e->fcut2) continue;
+          long double E = expl(-zeta * Q) / Q;
+          long double v = kap * (qv[0] * d[0] + qv[1] * d[1] + qv[2] * d[2]);
+          long double cv = cosl(v), sv = sinl(v);
+          phi += pre * E * cv;
+          for (int k = 0; k < 3; ++k) A[k] += pre * kap * qv[k] * E * sv;
+          if (H) {
+            long double hk = -pre * kap * kap * E * cv;
+            H[0] += hk * qv[0] * qv[0];
+            H[1] += hk * qv[1] * qv[1];
+            H[2] += hk * qv[2] * qv[2];
+            H[3] += hk * qv[0] * qv[1];
+            H[4] += hk * qv[0] * qv[2];
+            H[5] += hk * qv[1] * qv[2];
+          }
+        }
+  } else {
+    long double pre = 1.0L / (PI_L * Lx * b);
+    long double gam = kap * d[2];
+    for (int l2 = -F2; l2 <= F2; ++l2)
+      for (int l1 = -F1; l1 <= F1; ++l1) {
+        long double qv[2] = {(long double)l1, l2 / b};
+        long double Q = qv[0] * qv[0] + qv[1] * qv[1];
+        if (Q > e->fcut2) continue;
+        long double I0, I1, I2;
+        if (!l1 && !l2) i00(zeta, gam, &I0, &I1, &I2);
+        else itilde(sqrtl(Q), zeta, gam, &I0, &I1, &I2);
+        long double v = kap * (qv[0] * d[0] + qv[1] * d[1]);
+        long double cv = cosl(v), sv = sinl(v);
+        phi += pre * cv * I0;
+        A[0] += pre * kap * qv[0] * sv * I0;
+        A[1] += pre * kap * qv[1] * sv * I0;
+        A[2] -= pre * kap * cv * I1;
+        if (H) {
+          long double k2 = pre * kap * kap;
+          H[0] -= k2 * qv[0] * qv[0] * cv * I0;
+          H[1] -= k2 * qv[1] * qv[1] * cv * I0;
+          H[2] += k2 * cv * I2;
+          H[3] -= k2 * qv[0] * qv[1] * cv * I0;
+          H[4] -= k2 * qv[0] * sv * I1;
+          H[5] -= k2 * qv[1] * sv * I1;
+        }
+      }
+  }
+  *phi_out = (double)phi;
+  for (int k = 0; k < 3; ++k) A_out[k] = (double)A[k];
+  if (H_out) for (int k = 0; k < 6; ++k) H_out[k] = (double)Hs[k];
+}
+
+int or_ewald_setup(or_ewald *e, int bctype, const double box[3], double alpha, int rcut2,
+                   int fcut2, int n, int with_table) {
+  memset(e, 0, sizeof(*e));
+  e->bctype = bctype;
+  if (bctype == OR_BC_ISO) return 0;
+  e->Lx = box[0];
+  e->b = box[1] / box[0];
+  e->c = box[2] / box[0];
+  e->alpha = alpha > 0 ? alpha : 2.0 / box[0];
+  e->zeta = (M_PI * M_PI) / ((e->alpha * e->Lx) * (e->alpha * e->Lx));
+  e->rcut2 = rcut2;
+  e->fcut2 = fcut2;
+  e->n = n;
+  e->ext[0] = 0.5 * box[0];
+  e->ext[1] = 0.5 * box[1];
+  if (bctype == OR_BC_3P) e->ext[2] = 0.5 * box[2];
+  else e->ext[2] = box[2] < 2.0 * box[0] ? box[2] : 2.0 * box[0];
+  for (int k = 0; k < 3; ++k) e->step[k] = e->ext[k] / (double)(n - 1);
+  if (!with_table) return 0;
+  int64_t np = (int64_t)n * n * n;
+  e->tab = (double *)malloc(sizeof(double) * 10 * np);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t q = 0; q < np; ++q) {
+    int ix = (int)(q % n), iy = (int)((q / n) % n), iz = (int)(q / ((int64_t)n * n));
+    double u[3] = {ix * e->step[0], iy * e->step[1], iz * e->step[2]};
+    double ph, A[3], H[6];
+    or_ewald_series(e, u, 1, &ph, A, H);
+    double *o = e->tab + 10 * q;
+    o[0] = ph;
+    for (int k = 0; k < 3; ++k) o[1 + k] = A[k];
+    for (int k = 0; k < 6; ++k) o[4 + k] = H[k];
+  }
+  return 0;
+}
+
+void or_ewald_release(or_ewald *e) {
+  free(e->tab);
+  e->tab = NULL;
+}
+
+/* first-order Taylor look-up of the correction at offset d (min image) */
+static void table_lookup(const or_ewald *e, const double d[3], double *phic, double Ac[3]) {
+  double u[3], s[3], dl[3];
+  int g[3];
+  for (int k = 0; k < 3; ++k) {
+    s[k] = d[k] < 0 ? -1.0 : 1.0;
+    u[k] = fabs(d[k]);
+    int gi = (int)floor(u[k] / e->step[k] + 0.5);
+    if (gi > e->n - 1) gi = e->n - 1;
+    g[k] = gi;
+    dl[k] = u[k] - gi * e->step[k];
+  }
+  const double *T = e->tab + 10 * (((int64_t)g[2] * e->n + g[1]) * e->n + g[0]);
+  /* H index of (k, j) */
+  static const int hidx[3][3] = {{4, 7, 8}, {7, 5, 9}, {8, 9, 6}};
+  *phic = T[0] - (T[1] * dl[0] + T[2] * dl[1] + T[3] * dl[2]);
+  for (int k = 0; k < 3; ++k) {
+    double v = T[1 + k];
+    for (int j = 0; j < 3; ++j) v -= T[hidx[k][j]] * dl[j];
+    Ac[k] = s[k] * v;
+  }
+}
+
+void or_ewald_total(const or_tree *t, const double d[3], double *phi, double A[3]) {
+  const or_ewald *e = &t->ew;
+  double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  double r = sqrt(r2);
+  if (t->p.ewald == 0 || !e->tab) {
+    or_ewald_series(e, d, 0, phi, A, NULL);
+    return;
+  }
+  if (e->bctype == OR_BC_2P1I && fabs(d[2]) > 2.0 * e->Lx) {
+    double bL2 = e->b * e->Lx * e->Lx;
+    *phi = -2.0 * M_PI * fabs(d[2]) / bL2 + sqrt(M_PI) / (e->b * e->Lx);
+    A[0] = 0.0;
+    A[1] = 0.0;
+    A[2] = (d[2] < 0 ? -2.0 : 2.0) * M_PI / bL2;
+    return;
+  }
+  double phic, Ac[3];
+  table_lookup(e, d, &phic, Ac);
+  *phi = 1.0 / r + phic;
+  double r3 = r2 * r;
+  for (int k = 0; k < 3; ++k) A[k] = d[k] / r3 + Ac[k];
+}
+
+/* ----------------------------------------------------------- test exports */
+/* Evaluate the series at npts offsets; out[10*i]: phi, A(3), H(6). */
+void or_ewald_eval(int bctype, const double box[3], double alpha, int rcut2, int fcut2,
+                   int correction, int64_t npts, const double *d, double *out) {
+  or_ewald e;
+  or_ewald_setup(&e, bctype, box, alpha, rcut2, fcut2, 2, 0);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < npts; ++i) {
+    double ph, A[3], H[6];
+    or_ewald_series(&e, d + 3 * i, correction, &ph, A, H);
+    out[10 * i] = ph;
+    for (int k = 0; k < 3; ++k) out[10 * i + 1 + k] = A[k];
+    for (int k = 0; k < 6; ++k) out[10 * i + 4 + k] = H[k];
+  }
+}
+
+/* Build the folded table (n^3 x 10, x fastest). */
+void or_ewald_table(int bctype, const double box[3], double alpha, int rcut2, int fcut2, int n,
+                    double *out) {
+  or_ewald e;
+  or_ewald_setup(&e, bctype, box, alpha, rcut2, fcut2, n, 1);
+  memcpy(out, e.tab, sizeof(double) * 10 * (int64_t)n * n * n);
+  or_ewald_release(&e);
+}
+
+/* Table look-up (correction only) at npts offsets: out[4*i] = phi_c, A_c. */
+void or_ewald_table_lookup(int bctype, const double box[3], int n, const double *tab,
+                           int64_t npts, const double *d, double *out) {
+  or_ewald e;
+  or_ewald_setup(&e, bctype, box, 0.0, 15, 10, n, 0);
+  e.tab = (double *)tab;
+  for (int64_t i = 0; i < npts; ++i) {
+    double ph, A[3];
+    table_lookup(&e, d + 3 * i, &ph, A);
+    out[4 * i] = ph;
+    for (int k = 0; k < 3; ++k) out[4 * i + 1 + k] = A[k];
+  }
+}
+
+/* 2P1I integrals for tests: out = {Itilde, dItilde/dgamma, d2Itilde/dgamma2};
+ * s = 0 selects the l1 = l2 = 0 term I(0,0) of Eq. (14). */
+void or_itilde(double s, double zeta, double gam, double *out) {
+  long double I0, I1, I2;
+  if (s == 0.0) i00(zeta, gam, &I0, &I1, &I2);
+  else itilde(s, zeta, gam, &I0, &I1, &I2);
+  out[0] = (double)I0;
+  out[1] = (double)I1;
+  out[2] = (double)I2;
+}

@@ -1,0 +1,561 @@
+/*
+ * FP64 CPU oracle: grid, tree build, MACs, tree walks and direct sums.
+ *
+ * TEST INFRASTRUCTURE ONLY (see octoracle.h).  Everything here follows the
+ * paper's definitions step by step:
+ *   - amr-tree of blocks and block-trees down to cells (Sec. 2, first part);
+ *   - node moments: total mass and centre of mass, built bottom-up (Sec. 2.1);
+ *   - depth-first walk from the roots; a node is accepted by the MAC suite or
+ *     opened (Sec. 2.1); geometric BH MAC, Eq. (1), with the safe box;
+ *   - APE MAC, Eq. (6) with p = 1, against an absolute limit, Eq. (4);
+ *   - monopole potential and acceleration, Eqs. (7) and (8);
+ *   - reference solution by direct summation over all other cells (Sec. 3).
+ *
+ * Readings of the paper taken here (they bind the GPU library as well):
+ *   - sums over the 8 children run in octant order o = 0..7 (bit 0 = x,
+ *     bit 1 = y, bit 2 = z), left to right, in FP64 without FMA;
+ *     S = sum of m x over the node, COM = S / M (geometric centre if M = 0);
+ *     a cell's COM is its geometric centre (Sec. 2.1);
+ *   - the safe box is a cuboid of edge eta_SB h centred on the node's
+ *     geometric centre; the target (point or box) must lie strictly outside;
+ *   - the MAC distance is from the node's COM to the closest target point;
+ *     BH accepts if h^2 < theta^2 d^2, APE if G M h^2 < a_lim d^4;
+ *   - leaf nodes (cells) are always accepted; the target cell itself is
+ *     skipped by r^2 = 0 (the direct sum runs over "all the other cells");
+ *   - periodic axes use the minimum image, wrapped to [-L/2, L/2).
+ */
+#include "octoracle.h"
+#include "oracle_internal.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ utils */
+static uint64_t spread3(uint64_t v) {
+  uint64_t r = 0;
+  for (int b = 0; b < 21; ++b) r |= ((v >> b) & 1ULL) << (3 * b);
+  return r;
+}
+
+uint64_t or_morton(uint64_t x, uint64_t y, uint64_t z) {
+  return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+typedef struct {
+  int32_t level;
+  int32_t c[3];
+  uint64_t key;
+  int64_t leaf; /* leaf block index or -1 */
+} anode;
+
+static int cmp_anode(const void *a, const void *b) {
+  const anode *x = (const anode *)a, *y = (const anode *)b;
+  if (x->level != y->level) return x->level < y->level ? -1 : 1;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  /* equal keys: leaves first so duplicates are easy to spot */
+  if (x->leaf != y->leaf) return x->leaf > y->leaf ? -1 : 1;
+  return 0;
+}
+
+double or_size_at(const or_tree *t, int lev) {
+  return t->p.root_size / (double)(1LL << (lev - 1));
+}
+
+double or_wrap(const or_tree *t, int k, double d) {
+  if (!t->p.bc[k]) return d;
+  double L = t->box[k];
+  return d - L * floor(d / L + 0.5);
+}
+
+static int64_t find_anode(const or_tree *t, int lev, const int32_t c[3]) {
+  int sh = t->lmax - lev;
+  uint64_t key = or_morton((uint64_t)c[0] << sh, (uint64_t)c[1] << sh, (uint64_t)c[2] << sh);
+  int64_t lo = 0, hi = t->na - 1;
+  while (lo <= hi) {
+    int64_t mid = (lo + hi) / 2;
+    int32_t ml = t->alev[mid];
+    uint64_t mk = t->akey[mid];
+    if (ml == lev && mk == key) return mid;
+    if (ml < lev || (ml == lev && mk < key)) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+/* --------------------------------------------------------------- geometry */
+/* Node kind, size and geometric centre from its global id. */
+int or_node_geom(const or_tree *t, int64_t id, double *size, double gc[3]) {
+  const double *o = t->p.origin;
+  if (id < t->na) {
+    int l = t->alev[id];
+    double s = or_size_at(t, l);
+    *size = s;
+    for (int k = 0; k < 3; ++k) gc[k] = o[k] + ((double)t->acoord[3 * id + k] + 0.5) * s;
+    return OR_KIND_AMR;
+  }
+  int64_t r = id - t->na;
+  if (r < 8 * t->nb) {
+    int64_t lb = r / 8;
+    int o1 = (int)(r % 8);
+    double s = or_size_at(t, t->blev[lb]) / 2.0;
+    *size = s;
+    for (int k = 0; k < 3; ++k) {
+      int64_t pos = 2 * (int64_t)t->bcoord[3 * lb + k] + ((o1 >> k) & 1);
+      gc[k] = o[k] + ((double)pos + 0.5) * s;
+    }
+    return OR_KIND_P1;
+  }
+  r -= 8 * t->nb;
+  if (r < 64 * t->nb) {
+    int64_t lb = r / 64;
+    int q = (int)(r % 64), o1 = q / 8, o2 = q % 8;
+    double s = or_size_at(t, t->blev[lb]) / 4.0;
+    *size = s;
+    for (int k = 0; k < 3; ++k) {
+      int64_t pos = 4 * (int64_t)t->bcoord[3 * lb + k] + 2 * ((o1 >> k) & 1) + ((o2 >> k) & 1);
+      gc[k] = o[k] + ((double)pos + 0.5) * s;
+    }
+    return OR_KIND_P2;
+  }
+  r -= 64 * t->nb;
+  int64_t lb = r / 512;
+  int ci = (int)(r % 512);
+  int ijk[3] = {ci % 8, (ci / 8) % 8, ci / 64};
+  double s = or_size_at(t, t->blev[lb]) / 8.0;
+  *size = s;
+  for (int k = 0; k < 3; ++k) {
+    int64_t pos = 8 * (int64_t)t->bcoord[3 * lb + k] + ijk[k];
+    gc[k] = o[k] + ((double)pos + 0.5) * s;
+  }
+  return OR_KIND_CELL;
+}
+
+int64_t or_id_p1(const or_tree *t, int64_t lb, int o1) { return t->na + 8 * lb + o1; }
+int64_t or_id_p2(const or_tree *t, int64_t lb, int o1, int o2) {
+  return t->na + 8 * t->nb + 64 * lb + 8 * o1 + o2;
+}
+int64_t or_id_cell(const or_tree *t, int64_t lb, int ci) {
+  return t->na + 72 * t->nb + 512 * lb + ci;
+}
+/* cell index i + 8 j + 64 k of the cell in octant o3 of +2 node (o1, o2) */
+static int cell_of(int o1, int o2, int o3) {
+  int ijk[3];
+  for (int k = 0; k < 3; ++k)
+    ijk[k] = 4 * ((o1 >> k) & 1) + 2 * ((o2 >> k) & 1) + ((o3 >> k) & 1);
+  return ijk[0] + 8 * ijk[1] + 64 * ijk[2];
+}
+
+/* children of a node in octant order; returns the count (0 for a cell) */
+int or_children(const or_tree *t, int64_t id, int64_t ch[8]) {
+  if (id < t->na) {
+    if (t->aleaf[id] >= 0) {
+      for (int o = 0; o < 8; ++o) ch[o] = or_id_p1(t, t->aleaf[id], o);
+    } else {
+      for (int o = 0; o < 8; ++o) ch[o] = t->achild[8 * id + o];
+    }
+    return 8;
+  }
+  int64_t r = id - t->na;
+  if (r < 8 * t->nb) {
+    int64_t lb = r / 8;
+    int o1 = (int)(r % 8);
+    for (int o = 0; o < 8; ++o) ch[o] = or_id_p2(t, lb, o1, o);
+    return 8;
+  }
+  r -= 8 * t->nb;
+  if (r < 64 * t->nb) {
+    int64_t lb = r / 64;
+    int q = (int)(r % 64);
+    for (int o = 0; o < 8; ++o) ch[o] = or_id_cell(t, lb, cell_of(q / 8, q % 8, o));
+    return 8;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------- tree build */
+/* Bottom-up moments, Sec. 2.1: M = sum of child masses, S = sum of child
+ * mass-weighted positions, both in octant order; COM = S / M. */
+static void moments(or_tree *t, int64_t id) {
+  double size, gc[3];
+  int kind = or_node_geom(t, id, &size, gc);
+  if (kind == OR_KIND_CELL) {
+    int64_t r = id - t->na - 72 * t->nb;
+    int64_t lb = r / 512;
+    int ci = (int)(r % 512);
+    double hcube = size * size * size;
+    double m = t->rho[512 * lb + ci] * hcube;
+    t->M[id] = m;
+    for (int k = 0; k < 3; ++k) {
+      t->S[3 * id + k] = m * gc[k];
+      t->com[3 * id + k] = gc[k];
+    }
+    return;
+  }
+  int64_t ch[8];
+  or_children(t, id, ch);
+  double M = 0.0, S[3] = {0.0, 0.0, 0.0};
+  for (int o = 0; o < 8; ++o) {
+    moments(t, ch[o]);
+    M = M + t->M[ch[o]];
+    for (int k = 0; k < 3; ++k) S[k] = S[k] + t->S[3 * ch[o] + k];
+  }
+  t->M[id] = M;
+  for (int k = 0; k < 3; ++k) {
+    t->S[3 * id + k] = S[k];
+    t->com[3 * id + k] = M > 0.0 ? S[k] / M : gc[k];
+  }
+}
+
+or_tree *or_tree_new(const or_params *p, int64_t nb, const int32_t *level,
+                     const int32_t *coord, const double *rho, int *err) {
+  *err = 0;
+  if (nb <= 0) { *err = 1; return NULL; }
+  int lmax = 1;
+  for (int64_t b = 0; b < nb; ++b) {
+    if (level[b] < 1 || level[b] > 20) { *err = 1; return NULL; }
+    for (int k = 0; k < 3; ++k) {
+      int64_t nmax = (int64_t)p->nroot[k] << (level[b] - 1);
+      if (coord[3 * b + k] < 0 || coord[3 * b + k] >= nmax) { *err = 1; return NULL; }
+    }
+    if (level[b] > lmax) lmax = level[b];
+  }
+  if (rho) {
+    for (int64_t i = 0; i < 512 * nb; ++i)
+      if (!(rho[i] >= 0.0) || !isfinite(rho[i])) { *err = 5; return NULL; }
+  }
+  int bct;
+  if (!p->bc[0] && !p->bc[1] && !p->bc[2]) bct = OR_BC_ISO;
+  else if (p->bc[0] && p->bc[1] && p->bc[2]) bct = OR_BC_3P;
+  else if (p->bc[0] && p->bc[1] && !p->bc[2]) bct = OR_BC_2P1I;
+  else { *err = 6; return NULL; }
+  or_tree *t = (or_tree *)calloc(1, sizeof(or_tree));
+  t->p = *p;
+  t->bctype = bct;
+  t->nb = nb;
+  t->lmax = lmax;
+  for (int k = 0; k < 3; ++k) t->box[k] = p->nroot[k] * p->root_size;
+  t->blev = (int32_t *)malloc(sizeof(int32_t) * nb);
+  t->bcoord = (int32_t *)malloc(sizeof(int32_t) * 3 * nb);
+  memcpy(t->blev, level, sizeof(int32_t) * nb);
+  memcpy(t->bcoord, coord, sizeof(int32_t) * 3 * nb);
+
+  /* every leaf block and every ancestor of it */
+  int64_t cap = 0;
+  for (int64_t b = 0; b < nb; ++b) cap += level[b];
+  anode *all = (anode *)malloc(sizeof(anode) * cap);
+  int64_t n = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    for (int l = level[b]; l >= 1; --l) {
+      anode a;
+      a.level = l;
+      int sh = level[b] - l;
+      for (int k = 0; k < 3; ++k) a.c[k] = coord[3 * b + k] >> sh;
+      int sf = lmax - l;
+      a.key = or_morton((uint64_t)a.c[0] << sf, (uint64_t)a.c[1] << sf, (uint64_t)a.c[2] << sf);
+      a.leaf = (l == level[b]) ? b : -1;
+      all[n++] = a;
+    }
+  }
+  qsort(all, n, sizeof(anode), cmp_anode);
+  /* unique; a key that is a leaf must appear exactly once */
+  int64_t na = 0;
+  for (int64_t i = 0; i < n;) {
+    int64_t j = i + 1;
+    while (j < n && all[j].level == all[i].level && all[j].key == all[i].key) ++j;
+    int nleaf = 0;
+    for (int64_t q = i; q < j; ++q) nleaf += all[q].leaf >= 0;
+    if (nleaf > 1) { *err = 2; free(all); or_tree_free(t); return NULL; }
+    if (nleaf == 1 && j - i > 1) { *err = 3; free(all); or_tree_free(t); return NULL; }
+    all[na++] = all[i];
+    i = j;
+  }
+  t->na = na;
+  t->alev = (int32_t *)malloc(sizeof(int32_t) * na);
+  t->acoord = (int32_t *)malloc(sizeof(int32_t) * 3 * na);
+  t->akey = (uint64_t *)malloc(sizeof(uint64_t) * na);
+  t->aleaf = (int64_t *)malloc(sizeof(int64_t) * na);
+  t->achild = (int64_t *)malloc(sizeof(int64_t) * 8 * na);
+  for (int64_t i = 0; i < na; ++i) {
+    t->alev[i] = all[i].level;
+    for (int k = 0; k < 3; ++k) t->acoord[3 * i + k] = all[i].c[k];
+    t->akey[i] = all[i].key;
+    t->aleaf[i] = all[i].leaf;
+  }
+  free(all);
+  /* children of internal amr nodes must all exist (no holes) */
+  for (int64_t i = 0; i < na; ++i) {
+    for (int o = 0; o < 8; ++o) t->achild[8 * i + o] = -1;
+    if (t->aleaf[i] >= 0) continue;
+    for (int o = 0; o < 8; ++o) {
+      int32_t c[3];
+      for (int k = 0; k < 3; ++k) c[k] = 2 * t->acoord[3 * i + k] + ((o >> k) & 1);
+      int64_t ch = find_anode(t, t->alev[i] + 1, c);
+      if (ch < 0) { *err = 4; or_tree_free(t); return NULL; }
+      t->achild[8 * i + o] = ch;
+    }
+  }
+  /* all root positions must be present */
+  int64_t nr = 0;
+  for (int64_t i = 0; i < na; ++i) nr += t->alev[i] == 1;
+  if (nr != (int64_t)p->nroot[0] * p->nroot[1] * p->nroot[2]) { *err = 4; or_tree_free(t); return NULL; }
+  t->nroots = nr;
+  t->roots = (int64_t *)malloc(sizeof(int64_t) * nr);
+  nr = 0;
+  for (int64_t i = 0; i < na; ++i)
+    if (t->alev[i] == 1) t->roots[nr++] = i;
+
+  t->nn = na + 72 * nb + 512 * nb;
+  if (bct != OR_BC_ISO) {
+    int rc = p->ew_rcut2 > 0 ? p->ew_rcut2 : (bct == OR_BC_3P ? 15 : 10);
+    int fc = p->ew_fcut2 > 0 ? p->ew_fcut2 : 10;
+    or_ewald_setup(&t->ew, bct, t->box, p->ew_alpha, rc, fc, p->ew_n > 1 ? p->ew_n : 64,
+                   p->ewald == 1);
+  }
+  if (rho) {
+    t->rho = rho;
+    t->M = (double *)malloc(sizeof(double) * t->nn);
+    t->S = (double *)malloc(sizeof(double) * 3 * t->nn);
+    t->com = (double *)malloc(sizeof(double) * 3 * t->nn);
+    for (int64_t r = 0; r < t->nroots; ++r) moments(t, t->roots[r]);
+    t->rho = NULL;
+  }
+  return t;
+}
+
+void or_tree_free(or_tree *t) {
+  if (!t) return;
+  free(t->blev); free(t->bcoord); free(t->alev); free(t->acoord); free(t->akey);
+  free(t->aleaf); free(t->achild); free(t->roots); free(t->M); free(t->S); free(t->com);
+  or_ewald_release(&t->ew);
+  free(t);
+}
+int64_t or_tree_na(const or_tree *t) { return t->na; }
+int64_t or_tree_nn(const or_tree *t) { return t->nn; }
+
+/* Export of the amr-tree topology and all node moments. */
+void or_tree_export(const or_tree *t, int32_t *alev, int32_t *acoord, int64_t *aleaf,
+                    int64_t *achild, uint64_t *akey, double *M, double *com) {
+  if (alev) memcpy(alev, t->alev, sizeof(int32_t) * t->na);
+  if (acoord) memcpy(acoord, t->acoord, sizeof(int32_t) * 3 * t->na);
+  if (aleaf) memcpy(aleaf, t->aleaf, sizeof(int64_t) * t->na);
+  if (achild) memcpy(achild, t->achild, sizeof(int64_t) * 8 * t->na);
+  if (akey) memcpy(akey, t->akey, sizeof(uint64_t) * t->na);
+  if (M) memcpy(M, t->M, sizeof(double) * t->nn);
+  if (com) memcpy(com, t->com, sizeof(double) * 3 * t->nn);
+}
+
+/* -------------------------------------------------------------------- MAC */
+/* MAC suite for a target box (centre cT, half-extent ext per axis; ext = 0
+ * for a single target point).  Returns 1 to accept, 0 to open. */
+int or_accept(const or_tree *t, int64_t id, const double cT[3], double ext) {
+  const or_params *p = &t->p;
+  double h, gc[3];
+  or_node_geom(t, id, &h, gc);
+  /* safe box: strictly outside the eta_SB-enlarged node cuboid */
+  double half = 0.5 * p->eta_sb * h;
+  int outside = 0;
+  for (int k = 0; k < 3; ++k) {
+    double d = or_wrap(t, k, cT[k] - gc[k]);
+    if (fabs(d) - ext > half) outside = 1;
+  }
+  if (!outside) return 0;
+  /* squared distance from the COM to the closest target point */
+  double d2 = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    double d = or_wrap(t, k, cT[k] - t->com[3 * id + k]);
+    double e = fabs(d) - ext;
+    if (e > 0.0) d2 = d2 + e * e;
+  }
+  int ok;
+  if (p->mac == 0) {
+    ok = h * h < p->theta * p->theta * d2;
+  } else {
+    ok = p->G * t->M[id] * h * h < p->a_lim * d2 * d2;
+  }
+  if (p->theta_pix > 0.0) ok = ok && (h * h < p->theta_pix * p->theta_pix * d2);
+  return ok;
+}
+
+/* ------------------------------------------------------------------- walk */
+typedef struct {
+  int64_t *v;
+  int64_t n, cap;
+} idlist;
+
+static void push(idlist *l, int64_t x) {
+  if (l->n == l->cap) {
+    l->cap = l->cap ? 2 * l->cap : 1024;
+    l->v = (int64_t *)realloc(l->v, sizeof(int64_t) * l->cap);
+  }
+  l->v[l->n++] = x;
+}
+
+/* depth-first traversal, Sec. 2.1: accept or open; cells always accepted */
+static void visit(const or_tree *t, int64_t id, const double cT[3], double ext, idlist *out) {
+  int64_t ch[8];
+  if (id >= t->na + 72 * t->nb) { push(out, id); return; }
+  if (or_accept(t, id, cT, ext)) { push(out, id); return; }
+  int nc = or_children(t, id, ch);
+  for (int o = 0; o < nc; ++o) visit(t, ch[o], cT, ext, out);
+}
+
+void or_block_target(const or_tree *t, int64_t lb, double cT[3], double *ext) {
+  double s = or_size_at(t, t->blev[lb]);
+  for (int k = 0; k < 3; ++k) cT[k] = t->p.origin[k] + ((double)t->bcoord[3 * lb + k] + 0.5) * s;
+  *ext = 3.5 * (s / 8.0);
+}
+
+static idlist group_list(const or_tree *t, int64_t lb) {
+  double cT[3], ext;
+  or_block_target(t, lb, cT, &ext);
+  idlist l = {0, 0, 0};
+  for (int64_t r = 0; r < t->nroots; ++r) visit(t, t->roots[r], cT, ext, &l);
+  return l;
+}
+
+/* Interaction list of leaf block lb under the group MAC (ids, walk order). */
+int64_t or_block_list(const or_tree *t, int64_t lb, int64_t *out, int64_t cap) {
+  idlist l = group_list(t, lb);
+  int64_t n = l.n;
+  if (out) for (int64_t i = 0; i < n && i < cap; ++i) out[i] = l.v[i];
+  free(l.v);
+  return n;
+}
+
+/* Neumaier-compensated sum */
+typedef struct { double s, c; } nsum;
+static void nadd(nsum *a, double x) {
+  double t = a->s + x;
+  if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x; else a->c += (x - t) + a->s;
+  a->s = t;
+}
+static double nval(const nsum *a) { return a->s + a->c; }
+
+/* contribution of a source of unit mass at offset d = r - r_a:
+ * phi (potential kernel, Phi = -G M phi) and A (a = -G M A), Eqs. (7), (8)
+ * and, for periodic/mixed BCs, the Ewald forms of Sec. 2.2.2-2.2.3. */
+static void pair_kernel(const or_tree *t, const double d[3], double *phi, double A[3]) {
+  if (t->bctype == OR_BC_ISO) {
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    double r = sqrt(r2);
+    *phi = 1.0 / r;
+    double r3 = r2 * r;
+    for (int k = 0; k < 3; ++k) A[k] = d[k] / r3;
+    return;
+  }
+  or_ewald_total(t, d, phi, A);
+}
+
+/* potential and acceleration at cell (lb, ci) from a list of nodes */
+static void sum_list(const or_tree *t, const double x[3], const int64_t *ids, int64_t n,
+                     double *phi_out, double acc_out[3]) {
+  nsum ph = {0, 0}, ac[3] = {{0, 0}, {0, 0}, {0, 0}};
+  for (int64_t q = 0; q < n; ++q) {
+    int64_t id = ids[q];
+    double d[3];
+    for (int k = 0; k < 3; ++k) d[k] = or_wrap(t, k, x[k] - t->com[3 * id + k]);
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (r2 == 0.0) continue; /* the target cell itself */
+    double phi, A[3];
+    pair_kernel(t, d, &phi, A);
+    double GM = t->p.G * t->M[id];
+    nadd(&ph, -GM * phi);
+    for (int k = 0; k < 3; ++k) nadd(&ac[k], -GM * A[k]);
+  }
+  *phi_out = nval(&ph);
+  for (int k = 0; k < 3; ++k) acc_out[k] = nval(&ac[k]);
+}
+
+void or_cell_centre(const or_tree *t, int64_t lb, int ci, double x[3]) {
+  double s, gc[3];
+  or_node_geom(t, or_id_cell(t, lb, ci), &s, gc);
+  for (int k = 0; k < 3; ++k) x[k] = gc[k];
+}
+
+/* Group walk (one interaction list per leaf block, closest-point MAC).
+ * phi [nb*512], acc [3][nb*512], nint [nb] (list lengths). */
+void or_walk_group(const or_tree *t, double *phi, double *acc, int64_t *nint) {
+  int64_t nb = t->nb, ncell = 512 * nb;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t lb = 0; lb < nb; ++lb) {
+    idlist l = group_list(t, lb);
+    if (nint) nint[lb] = l.n;
+    for (int ci = 0; ci < 512; ++ci) {
+      double x[3], ph, a[3];
+      or_cell_centre(t, lb, ci, x);
+      sum_list(t, x, l.v, l.n, &ph, a);
+      phi[512 * lb + ci] = ph;
+      for (int k = 0; k < 3; ++k) acc[k * ncell + 512 * lb + ci] = a[k];
+    }
+    free(l.v);
+  }
+}
+
+/* Same, for a subset of leaf blocks; outputs are [nsel*512] / [3][nsel*512]. */
+void or_walk_group_blocks(const or_tree *t, int64_t nsel, const int64_t *sel, double *phi,
+                          double *acc, int64_t *nint) {
+  int64_t ncell = 512 * nsel;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t q = 0; q < nsel; ++q) {
+    int64_t lb = sel[q];
+    idlist l = group_list(t, lb);
+    if (nint) nint[q] = l.n;
+    for (int ci = 0; ci < 512; ++ci) {
+      double x[3], ph, a[3];
+      or_cell_centre(t, lb, ci, x);
+      sum_list(t, x, l.v, l.n, &ph, a);
+      phi[512 * q + ci] = ph;
+      for (int k = 0; k < 3; ++k) acc[k * ncell + 512 * q + ci] = a[k];
+    }
+    free(l.v);
+  }
+}
+
+/* Paper-literal walk: one depth-first traversal per target cell (point MAC).
+ * Targets are global cell indices 512*lb + ci. */
+void or_walk_percell(const or_tree *t, int64_t ntg, const int64_t *tg, double *phi,
+                     double *acc, int64_t *nint) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t q = 0; q < ntg; ++q) {
+    int64_t lb = tg[q] / 512;
+    int ci = (int)(tg[q] % 512);
+    double x[3], ph, a[3];
+    or_cell_centre(t, lb, ci, x);
+    idlist l = {0, 0, 0};
+    for (int64_t r = 0; r < t->nroots; ++r) visit(t, t->roots[r], x, 0.0, &l);
+    sum_list(t, x, l.v, l.n, &ph, a);
+    phi[q] = ph;
+    for (int k = 0; k < 3; ++k) acc[k * ntg + q] = a[k];
+    if (nint) nint[q] = l.n;
+    free(l.v);
+  }
+}
+
+/* Reference solution: direct summation over all other cells (Sec. 3).
+ * Targets are global cell indices; outputs [ntg], [3][ntg]. */
+void or_direct(const or_tree *t, int64_t ntg, const int64_t *tg, double *phi, double *acc) {
+  int64_t ncell = 512 * t->nb;
+  int64_t base = t->na + 72 * t->nb;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t q = 0; q < ntg; ++q) {
+    int64_t lb = tg[q] / 512;
+    int ci = (int)(tg[q] % 512);
+    double x[3];
+    or_cell_centre(t, lb, ci, x);
+    nsum ph = {0, 0}, ac[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int64_t j = 0; j < ncell; ++j) {
+      int64_t id = base + j;
+      double d[3];
+      for (int k = 0; k < 3; ++k) d[k] = or_wrap(t, k, x[k] - t->com[3 * id + k]);
+      double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      if (r2 == 0.0) continue;
+      double phk, A[3];
+      pair_kernel(t, d, &phk, A);
+      double GM = t->p.G * t->M[id];
+      nadd(&ph, -GM * phk);
+      for (int k = 0; k < 3; ++k) nadd(&ac[k], -GM * A[k]);
+    }
+    phi[q] = nval(&ph);
+    for (int k = 0; k < 3; ++k) acc[k * ntg + q] = nval(&ac[k]);
+  }
+}

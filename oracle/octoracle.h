@@ -1,0 +1,44 @@
+/*
+ * FP64 CPU oracle for the OctTree solver of Wuensch, Walch, Dinnbier &
+ * Whitworth (2018), "Tree-based solvers for adaptive mesh refinement code
+ * FLASH - I".
+ *
+ * TEST INFRASTRUCTURE ONLY.  Plain, slow, obviously correct C: recursion,
+ * per-cell loops, no blocking or fusion.  It shares no code with the GPU
+ * library and must only be called from tests, the smoke check and the
+ * benchmark's CPU-baseline leg.
+ */
+#ifndef OCTORACLE_H
+#define OCTORACLE_H
+#include <stdint.h>
+
+typedef struct {
+  int32_t nroot[3];   /* root blocks per axis (forest, Sec. 2 footnote)      */
+  int32_t bc[3];      /* per axis: 0 isolated, 1 periodic (Sec. 2.2.2-2.2.3) */
+  double root_size;   /* edge of a cubic root block                         */
+  double origin[3];
+  double G;           /* gravitational constant                             */
+  double theta;       /* BH opening angle theta_lim, Eq. (1)                */
+  double eta_sb;      /* safe-box factor eta_SB (Sec. 2.1)                  */
+  double a_lim;       /* APE absolute acceleration limit, Eqs. (4), (6)     */
+  double theta_pix;   /* extra BH angle when columns are on; <= 0: off      */
+  int32_t mac;        /* 0 = BH, 1 = APE                                    */
+  int32_t ewald;      /* 0 = exact series, 1 = table (periodic/mixed only)  */
+  int32_t ew_n;       /* table points per axis                              */
+  int32_t ew_rcut2;   /* real-space cut-off |i|^2 (<= 0: 15 for 3P, 10 2P1I) */
+  int32_t ew_fcut2;   /* Fourier cut-off |l|^2 (<= 0: 10)                    */
+  int32_t pad_;
+  double ew_alpha;    /* Ewald splitting alpha (<= 0: 2 / Lx)               */
+} or_params;
+
+typedef struct or_tree or_tree;
+
+/* Returns NULL on an invalid grid; *err receives a short reason code:
+ * 1 bad level/coord, 2 duplicate block, 3 overlap, 4 hole, 5 bad density,
+ * 6 unsupported boundary combination. */
+or_tree *or_tree_new(const or_params *p, int64_t nb, const int32_t *level,
+                     const int32_t *coord, const double *rho, int *err);
+void or_tree_free(or_tree *t);
+int64_t or_tree_na(const or_tree *t);
+int64_t or_tree_nn(const or_tree *t);
+#endif

@@ -1,0 +1,61 @@
+/* Internal declarations of the FP64 oracle (test infrastructure only). */
+#ifndef ORACLE_INTERNAL_H
+#define ORACLE_INTERNAL_H
+#include "octoracle.h"
+
+enum { OR_KIND_AMR = 0, OR_KIND_P1 = 1, OR_KIND_P2 = 2, OR_KIND_CELL = 3 };
+enum { OR_BC_ISO = 0, OR_BC_3P = 1, OR_BC_2P1I = 2 };
+
+/* Ewald set-up for periodic (3P) and mixed (2P1I) boundaries, Sec. 2.2.2-2.2.4 */
+typedef struct {
+  int bctype;
+  double Lx, b, c;      /* box: Lx, Ly = b Lx, Lz = c Lx                    */
+  double alpha, zeta;   /* alpha (2/Lx by default), zeta = pi^2/(alpha Lx)^2 */
+  int rcut2, fcut2;     /* real-space and Fourier cut-offs (squared radii)   */
+  int n;                /* table points per axis                            */
+  double ext[3];        /* folded table extent per axis                     */
+  double step[3];       /* ext / (n - 1)                                    */
+  double *tab;          /* [n][n][n][10]: phi_c, A_c (3), H_c (xx,yy,zz,xy,xz,yz) */
+} or_ewald;
+
+struct or_tree {
+  or_params p;
+  int bctype;
+  double box[3];
+  int64_t nb;
+  int32_t lmax;
+  int32_t *blev, *bcoord;
+  int64_t na;
+  int32_t *alev, *acoord;
+  uint64_t *akey;
+  int64_t *aleaf, *achild;
+  int64_t nroots;
+  int64_t *roots;
+  int64_t nn;
+  const double *rho; /* only during construction */
+  double *M, *S, *com;
+  or_ewald ew;
+};
+
+uint64_t or_morton(uint64_t x, uint64_t y, uint64_t z);
+double or_size_at(const or_tree *t, int lev);
+double or_wrap(const or_tree *t, int k, double d);
+int or_node_geom(const or_tree *t, int64_t id, double *size, double gc[3]);
+int or_children(const or_tree *t, int64_t id, int64_t ch[8]);
+int64_t or_id_p1(const or_tree *t, int64_t lb, int o1);
+int64_t or_id_p2(const or_tree *t, int64_t lb, int o1, int o2);
+int64_t or_id_cell(const or_tree *t, int64_t lb, int ci);
+int or_accept(const or_tree *t, int64_t id, const double cT[3], double ext);
+void or_block_target(const or_tree *t, int64_t lb, double cT[3], double *ext);
+void or_cell_centre(const or_tree *t, int64_t lb, int ci, double x[3]);
+
+/* Ewald */
+int or_ewald_setup(or_ewald *e, int bctype, const double box[3], double alpha, int rcut2,
+                   int fcut2, int n, int with_table);
+void or_ewald_release(or_ewald *e);
+/* full kernel phi, A (and Hessian if H != NULL); with correction != 0 the
+ * Newtonian 1/r part is removed: phi_c = phi - 1/r, A_c = A - d/r^3 */
+void or_ewald_series(const or_ewald *e, const double d[3], int correction, double *phi,
+                     double A[3], double H[6]);
+void or_ewald_total(const or_tree *t, const double d[3], double *phi, double A[3]);
+#endif
