@@ -1,0 +1,139 @@
+"""Throughput of the tree-solver hot path on one MI355X.
+
+Workload: 128^3 cells (4,096 blocks of 8^3) of lognormal density
+exp(1.5 delta - 1.125), delta a seeded P(k) ~ k^-4 Gaussian random field;
+isolated boundaries; APE MAC with a_lim = 1e-3 * max|a| (max|a| from one BH
+theta = 0.5 FP64 walk before timing, as the paper derives a_lim from the
+initial acceleration field).  A step is one pass of the whole path: tree
+build (moments), interaction lists, per-cell potential + acceleration in FP32
+with Kahan-compensated potential.  Inputs are resident in HBM before timing.
+
+Prints one JSON line (see the design doc for the roofline and baseline notes).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# Algorithmic FP32 work of one (cell, node) interaction of the isolated walk:
+# 3 sub (d), 5 (r^2: 3 mul + 2 add), rsqrt (1), m/r (1), m/r^3 (2 mul),
+# 3 FMA for the acceleration (6), Kahan update of the potential (4).
+FLOP_PAIR_ISO = 22
+PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X vector FP32 (256 CU x 2.4 GHz, packed)
+PEAK_FP64_VALU = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=128, help="cells per axis")
+    ap.add_argument("--cpu-blocks", type=int, default=24, help="oracle sample size (blocks)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    return ap.parse_args()
+
+
+def timed_steps(solver, rho, outs, fp64, steps, warmup):
+    import torch
+    solve = solver.solve64 if fp64 else solver.solve
+    for _ in range(warmup):
+        solver.build(rho)
+        solve(*outs)
+    torch.cuda.synchronize()
+    evals, lists, builds = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        solver.build(rho)
+        st = solve(*outs)
+        evals.append(st.ms_eval)
+        lists.append(st.ms_list)
+        builds.append(st.ms_build)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt / steps * 1e3, st, float(np.mean(evals)), float(np.mean(lists)), float(np.mean(builds))
+
+
+def cpu_baseline(grid, a_lim, nblk):
+    """The FP64 oracle's group walk on a seeded sample of blocks, host cores."""
+    import oracle
+    threads = os.cpu_count() or 1
+    os.environ.setdefault("OMP_NUM_THREADS", str(threads))
+    sel = np.random.default_rng(7).choice(grid.nb, nblk, replace=False)
+    t0 = time.perf_counter()
+    t = oracle.Tree(grid, mac="ape", a_lim=a_lim)
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    t.walk_group(sel)
+    tw = time.perf_counter() - t0
+    cells = 512 * nblk
+    # tree build is O(all cells): charge the sample its share
+    sec = tw + tb * (nblk / grid.nb)
+    return {"value": cells / sec, "unit": "cells/s", "cores": int(os.environ["OMP_NUM_THREADS"]),
+            "kind": "oracle",
+            "sample": f"{nblk} seeded blocks ({cells} cells) of the same workload, APE same a_lim; "
+                      f"walk {tw:.2f} s + build share {tb * nblk / grid.nb:.3f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import paper_1708_06142_amd as ot
+    import workloads
+
+    grid = workloads.c2_lognormal(args.n)
+    ncell = grid.ncells
+    rho = torch.from_numpy(grid.rho.reshape(-1).copy()).cuda()
+    s = ot.Solver.for_grid(grid, mac="ape", eps_lim=1e-3, theta=0.5)
+    s.build(rho)
+    phi = torch.empty(ncell, device="cuda", dtype=torch.float32)
+    acc = torch.empty(3 * ncell, device="cuda", dtype=torch.float32)
+    st0 = s.solve(phi, acc)  # derives a_lim from the BH pre-pass (untimed)
+    a_lim = st0.a_lim_used
+    s.close()
+    s = ot.Solver.for_grid(grid, mac="ape", a_lim=a_lim, theta=0.5)
+
+    ms, st, ms_eval, ms_list, ms_build = timed_steps(s, rho, (phi, acc), False, args.steps, args.warmup)
+    value = ncell / (ms * 1e-3)
+    flops = st.n_interactions * FLOP_PAIR_ISO
+    achieved = flops / (ms_eval * 1e-3) / 1e12
+    out = {
+        "metric": "cells/s for potential+accel+N_pix column densities at <=1e-3 rel err",
+        "value": value, "unit": "cells/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"lognormal {args.n}^3 (sigma_ln 1.5, P(k)~k^-4, seed 2), isolated, "
+                               "APE a_lim=1e-3 a_max, FP32-Kahan walk",
+                   "cells": ncell, "blocks": grid.nb, "a_lim": a_lim, "columns": 0},
+        "phases_ms": {"build": ms_build, "lists": ms_list, "eval": ms_eval},
+        "interactions": {"n_int": st.n_interactions, "per_cell": st.n_interactions / ncell,
+                         "max_list": st.max_list},
+        "roofline": {"bound": "alu", "kernel": "k_eval32 (isolated)", "achieved": achieved,
+                     "peak": PEAK_FP32_VALU, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
+                     "traffic": None, "flop_per_pair": FLOP_PAIR_ISO},
+    }
+    if not args.no_fp64:
+        phi64 = torch.empty(ncell, device="cuda", dtype=torch.float64)
+        acc64 = torch.empty(3 * ncell, device="cuda", dtype=torch.float64)
+        ms64, st64, e64, _, _ = timed_steps(s, rho, (phi64, acc64), True, max(2, args.steps // 2), 1)
+        a64 = st64.n_interactions * FLOP_PAIR_ISO / (e64 * 1e-3) / 1e12
+        out["fp64_walk"] = {"value": ncell / (ms64 * 1e-3), "ms_per_step": ms64, "ms_eval": e64,
+                            "achieved_tflops": a64, "frac_fp64_peak": a64 / PEAK_FP64_VALU}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(grid, a_lim, args.cpu_blocks)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,234 @@
+"""Python binding of libocttree (C ABI in include/octtree.h).
+
+Argument marshalling only: torch tensors supply device memory and the HIP
+stream; every step of the solver runs in the library's HIP kernels.  There is
+no CPU fallback: if the library is missing, importing the binding succeeds but
+any solver call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libocttree.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "octtree.h")
+
+OT_OK, OT_ERR_INVALID_ARG, OT_ERR_BAD_GRID, OT_ERR_NUMERIC = 0, -1, -2, -3
+OT_ERR_STATE, OT_ERR_OOM, OT_ERR_DEVICE, OT_ERR_UNSUPPORTED = -4, -5, -6, -7
+STATUS = {0: "OK", -1: "INVALID_ARG", -2: "BAD_GRID", -3: "NUMERIC", -4: "STATE", -5: "OOM",
+          -6: "DEVICE", -7: "UNSUPPORTED"}
+
+
+class OTError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("nroot", C.c_int32 * 3), ("bc", C.c_int32 * 3), ("root_size", C.c_double),
+                ("origin", C.c_double * 3), ("G", C.c_double), ("theta_lim", C.c_double),
+                ("eta_sb", C.c_double), ("mac", C.c_int32), ("ewald", C.c_int32),
+                ("a_lim", C.c_double), ("eps_lim", C.c_double), ("ewald_n", C.c_int32),
+                ("ewald_rcut2", C.c_int32), ("ewald_fcut2", C.c_int32), ("device", C.c_int32),
+                ("ewald_alpha", C.c_double), ("max_device_bytes", C.c_uint64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_interactions", C.c_int64), ("max_list", C.c_int64), ("total_list", C.c_int64),
+                ("a_lim_used", C.c_double), ("ms_build", C.c_double), ("ms_list", C.c_double),
+                ("ms_eval", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libocttree.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"{LIBPATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIBPATH)
+        vp, i64 = C.c_void_p, C.c_int64
+        L.ot_params_default.argtypes = [C.POINTER(Params)]
+        L.ot_create.argtypes = [C.POINTER(Params), C.POINTER(vp)]
+        L.ot_set_blocks.argtypes = [vp, i64, vp, vp]
+        L.ot_build.argtypes = [vp, vp, vp]
+        L.ot_solve.argtypes = [vp, vp, vp, C.POINTER(Stats), vp]
+        L.ot_solve64.argtypes = [vp, vp, vp, C.POINTER(Stats), vp]
+        L.ot_ewald_prepare.argtypes = [vp, vp]
+        L.ot_num_amr_nodes.restype = i64
+        L.ot_num_amr_nodes.argtypes = [vp]
+        L.ot_export_topology.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.ot_export_moments.argtypes = [vp, vp, vp]
+        L.ot_export_list.argtypes = [vp, i64, vp, i64, C.POINTER(i64)]
+        L.ot_export_ewald_table.argtypes = [vp, vp]
+        L.ot_last_error.restype = C.c_char_p
+        L.ot_last_error.argtypes = [vp]
+        L.ot_destroy.argtypes = [vp]
+        for name in ("ot_create", "ot_set_blocks", "ot_build", "ot_solve", "ot_solve64",
+                     "ot_ewald_prepare", "ot_export_topology", "ot_export_moments",
+                     "ot_export_list", "ot_export_ewald_table"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def header_symbols():
+    """Entry points declared in include/octtree.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(ot_[a-z0-9_]+)\s*\(", txt)))
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dev_ptr(t, dtype):
+    import torch
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+MAC = {"bh": 0, "ape": 1}
+
+
+def make_params(nroot=(1, 1, 1), root_size=1.0, origin=(0.0, 0.0, 0.0), bc=(0, 0, 0), G=1.0,
+                theta=0.5, eta_sb=1.2, mac="bh", a_lim=0.0, eps_lim=1e-3, ewald="table",
+                ewald_n=64, ewald_rcut2=0, ewald_fcut2=0, ewald_alpha=0.0, device=0,
+                max_device_bytes=0):
+    p = Params()
+    lib().ot_params_default(C.byref(p))
+    for k in range(3):
+        p.nroot[k], p.bc[k], p.origin[k] = int(nroot[k]), int(bc[k]), float(origin[k])
+    p.root_size, p.G, p.theta_lim, p.eta_sb = float(root_size), float(G), float(theta), float(eta_sb)
+    p.mac = MAC[mac]
+    p.ewald = {"table": 0, "exact": 1}[ewald]
+    p.a_lim, p.eps_lim = float(a_lim), float(eps_lim)
+    p.ewald_n, p.ewald_rcut2, p.ewald_fcut2 = int(ewald_n), int(ewald_rcut2), int(ewald_fcut2)
+    p.ewald_alpha, p.device, p.max_device_bytes = float(ewald_alpha), int(device), int(max_device_bytes)
+    return p
+
+
+class Solver:
+    """One libocttree context: blocks -> build -> solve."""
+
+    def __init__(self, **kw):
+        self.params = make_params(**kw)
+        h = C.c_void_p()
+        st = lib().ot_create(C.byref(self.params), C.byref(h))
+        self.h = h
+        if st != OT_OK:
+            msg = lib().ot_last_error(h).decode() if h.value else "ot_create failed"
+            self.close()
+            raise OTError(st, msg)
+        self.nb = 0
+        self.na = 0
+
+    @classmethod
+    def for_grid(cls, grid, **kw):
+        s = cls(nroot=grid.nroot, root_size=grid.root_size, origin=grid.origin, bc=grid.bc, **kw)
+        s.set_blocks(grid.level, grid.coord)
+        return s
+
+    def _check(self, st):
+        if st != OT_OK:
+            raise OTError(st, lib().ot_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().ot_destroy(self.h)
+        self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_blocks(self, level, coord):
+        lv = np.ascontiguousarray(level, dtype=np.int32)
+        cd = np.ascontiguousarray(coord, dtype=np.int32).reshape(-1, 3)
+        self._check(lib().ot_set_blocks(self.h, lv.shape[0], _np_ptr(lv), _np_ptr(cd)))
+        self.nb = int(lv.shape[0])
+        self.na = int(lib().ot_num_amr_nodes(self.h))
+
+    def build(self, rho, stream=None):
+        import torch
+        self._check(lib().ot_build(self.h, _dev_ptr(rho, torch.float64), _stream(stream)))
+
+    def solve(self, phi, acc, stream=None):
+        import torch
+        st = Stats()
+        self._check(lib().ot_solve(self.h, _dev_ptr(phi, torch.float32), _dev_ptr(acc, torch.float32),
+                                   C.byref(st), _stream(stream)))
+        return st
+
+    def solve64(self, phi, acc, stream=None):
+        import torch
+        st = Stats()
+        self._check(lib().ot_solve64(self.h, _dev_ptr(phi, torch.float64), _dev_ptr(acc, torch.float64),
+                                     C.byref(st), _stream(stream)))
+        return st
+
+    def ewald_prepare(self, stream=None):
+        self._check(lib().ot_ewald_prepare(self.h, _stream(stream)))
+
+    # ---- inspection
+    def export_topology(self):
+        na = self.na
+        out = dict(alev=np.empty(na, np.int32), acoord=np.empty((na, 3), np.int32),
+                   aleaf=np.empty(na, np.int64), achild=np.empty((na, 8), np.int64),
+                   akey=np.empty(na, np.uint64))
+        self._check(lib().ot_export_topology(self.h, *(_np_ptr(out[k]) for k in
+                                                       ("alev", "acoord", "aleaf", "achild", "akey"))))
+        return out
+
+    def export_moments(self):
+        nn = self.na + 584 * self.nb
+        M, com = np.empty(nn), np.empty((nn, 3))
+        self._check(lib().ot_export_moments(self.h, _np_ptr(M), _np_ptr(com)))
+        return M, com
+
+    def export_list(self, b):
+        n = C.c_int64(0)
+        self._check(lib().ot_export_list(self.h, int(b), None, 0, C.byref(n)))
+        ids = np.empty(n.value, np.int32)
+        self._check(lib().ot_export_list(self.h, int(b), _np_ptr(ids), n.value, C.byref(n)))
+        return ids
+
+    def export_ewald_table(self):
+        n = self.params.ewald_n
+        tab = np.empty((n, n, n, 10))
+        self._check(lib().ot_export_ewald_table(self.h, _np_ptr(tab)))
+        return tab
+
+
+def run(grid, fp64=False, stream=None, **kw):
+    """Convenience: build + solve on cuda:0; returns (phi, acc, stats) as torch tensors."""
+    import torch
+    s = Solver.for_grid(grid, **kw)
+    rho = torch.from_numpy(np.ascontiguousarray(grid.rho.reshape(-1))).to("cuda")
+    s.build(rho, stream)
+    dt = torch.float64 if fp64 else torch.float32
+    phi = torch.empty(grid.nb * 512, dtype=dt, device="cuda")
+    acc = torch.empty(3 * grid.nb * 512, dtype=dt, device="cuda")
+    st = (s.solve64 if fp64 else s.solve)(phi, acc, stream)
+    return phi, acc.view(3, -1), st, s

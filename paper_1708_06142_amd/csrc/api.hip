@@ -1,0 +1,522 @@
+// C ABI of libocttree: parameter validation, device memory, and the order of
+// the solver phases (tree build -> interaction lists -> per-cell evaluation).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "ctx.hpp"
+#include "kernels.hpp"
+
+using ot::DevBuf;
+
+namespace {
+
+ot_status fail(ot_ctx *c, ot_status s, const std::string &msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+ot_status dev_fail(ot_ctx *c, hipError_t e, const char *what) {
+  c->err = std::string(what) + ": " + hipGetErrorString(e);
+  return (e == hipErrorOutOfMemory) ? OT_ERR_OOM : OT_ERR_DEVICE;
+}
+
+#define HIPCHK(x)                                 \
+  do {                                            \
+    hipError_t e_ = (x);                          \
+    if (e_ != hipSuccess) return dev_fail(c, e_, #x); \
+  } while (0)
+
+#define OTCHK(x)                 \
+  do {                           \
+    ot_status s_ = (x);          \
+    if (s_ != OT_OK) return s_;  \
+  } while (0)
+
+void release(ot_ctx *c, DevBuf &b) {
+  if (b.ptr) {
+    (void)hipFree(b.ptr);
+    c->dev_bytes -= b.bytes;
+  }
+  b.ptr = nullptr;
+  b.bytes = 0;
+}
+
+// Grow-only device allocation accounted against max_device_bytes.
+ot_status dalloc(ot_ctx *c, DevBuf &b, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (b.ptr && b.bytes >= bytes) return OT_OK;
+  release(c, b);
+  if (c->p.max_device_bytes && c->dev_bytes + bytes > c->p.max_device_bytes)
+    return fail(c, OT_ERR_OOM, "device allocation of " + std::to_string(bytes) +
+                                   " bytes exceeds max_device_bytes");
+  hipError_t e = hipMalloc(&b.ptr, bytes);
+  if (e != hipSuccess) {
+    b.ptr = nullptr;
+    (void)hipGetLastError();
+    return fail(c, e == hipErrorOutOfMemory ? OT_ERR_OOM : OT_ERR_DEVICE,
+                std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  b.bytes = bytes;
+  c->dev_bytes += bytes;
+  return OT_OK;
+}
+
+template <typename T>
+T *P(DevBuf &b) {
+  return static_cast<T *>(b.ptr);
+}
+
+ot::DevTree dev_tree(ot_ctx *c) {
+  ot::DevTree T;
+  T.alev = P<int32_t>(c->alev);
+  T.acoord = P<int32_t>(c->acoord);
+  T.achild0 = P<int32_t>(c->achild0);
+  T.aleaf = P<int32_t>(c->aleaf);
+  T.blev = P<int32_t>(c->blev);
+  T.bcoord = P<int32_t>(c->bcoord);
+  T.bamr = P<int32_t>(c->bamr);
+  T.amc = P<double4>(c->amc);
+  T.aS = P<double4>(c->aS);
+  T.btmc = P<double4>(c->btmc);
+  T.cm = P<double>(c->cm);
+  T.na = c->topo.na;
+  T.nb = c->topo.nb;
+  T.nroots = (int32_t)c->topo.nroots;
+  for (int k = 0; k < 3; ++k) {
+    T.per[k] = c->p.bc[k];
+    T.org[k] = c->p.origin[k];
+    T.L[k] = c->box[k];
+  }
+  T.root_size = c->p.root_size;
+  return T;
+}
+
+template <typename V>
+ot_status upload(ot_ctx *c, DevBuf &b, const std::vector<V> &h, hipStream_t st) {
+  OTCHK(dalloc(c, b, h.size() * sizeof(V)));
+  HIPCHK(hipMemcpyAsync(b.ptr, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice, st));
+  return OT_OK;
+}
+
+ot_status upload_topology(ot_ctx *c, hipStream_t st) {
+  const ot::Topology &t = c->topo;
+  std::vector<int32_t> child0(t.na), leaf(t.na), bamr(t.nb);
+  for (int64_t i = 0; i < t.na; ++i) {
+    child0[i] = t.aleaf[i] >= 0 ? -1 : (int32_t)t.achild[8 * i];
+    leaf[i] = (int32_t)t.aleaf[i];
+  }
+  for (int64_t b = 0; b < t.nb; ++b) bamr[b] = (int32_t)t.bamr[b];
+  OTCHK(upload(c, c->alev, t.alev, st));
+  OTCHK(upload(c, c->acoord, t.acoord, st));
+  OTCHK(upload(c, c->achild0, child0, st));
+  OTCHK(upload(c, c->aleaf, leaf, st));
+  OTCHK(upload(c, c->blev, t.blev, st));
+  OTCHK(upload(c, c->bcoord, t.bcoord, st));
+  OTCHK(upload(c, c->bamr, bamr, st));
+  OTCHK(dalloc(c, c->amc, t.na * sizeof(double4)));
+  OTCHK(dalloc(c, c->aS, t.na * sizeof(double4)));
+  OTCHK(dalloc(c, c->btmc, t.nb * 72 * sizeof(double4)));
+  OTCHK(dalloc(c, c->cm, t.nb * 512 * sizeof(double)));
+  OTCHK(dalloc(c, c->flag, 64));
+  HIPCHK(hipStreamSynchronize(st));
+  c->dev_topo = true;
+  return OT_OK;
+}
+
+ot::EwaldP ewald_desc(const ot_ctx *c) {
+  ot::EwaldP E;
+  memset(&E, 0, sizeof(E));
+  E.bctype = c->bctype;
+  E.n = c->ew_n;
+  for (int k = 0; k < 3; ++k) {
+    E.L[k] = c->box[k];
+    E.step[k] = c->ew_step[k];
+    E.inv_step[k] = c->ew_step[k] > 0 ? 1.0 / c->ew_step[k] : 0.0;
+  }
+  if (c->bctype == ot::BC_2P1I) {
+    const double Lx = c->box[0], b = c->box[1] / c->box[0];
+    const double bL2 = b * Lx * Lx;
+    E.zfar = 2.0 * Lx;
+    E.far_phi_a = -2.0 * M_PI / bL2;
+    E.far_phi_b = std::sqrt(M_PI) / (b * Lx);
+    E.far_az = 2.0 * M_PI / bL2;
+  }
+  E.tab64 = static_cast<const double *>(c->tab64.ptr);
+  E.tab32 = static_cast<const float4 *>(c->tab32.ptr);
+  return E;
+}
+
+ot_status ewald_prepare(ot_ctx *c, hipStream_t st) {
+  if (c->bctype == ot::BC_ISO) return fail(c, OT_ERR_STATE, "Ewald table needs periodic or mixed boundaries");
+  if (c->ewald_ready) return OT_OK;
+  HIPCHK(hipSetDevice(c->p.device));
+  const int n = c->p.ewald_n;
+  c->ew_n = n;
+  c->ew_rcut2 = c->p.ewald_rcut2 > 0 ? c->p.ewald_rcut2 : (c->bctype == ot::BC_3P ? 15 : 10);
+  c->ew_fcut2 = c->p.ewald_fcut2 > 0 ? c->p.ewald_fcut2 : 10;
+  c->ew_alpha = c->p.ewald_alpha > 0 ? c->p.ewald_alpha : 2.0 / c->box[0];
+  c->ew_ext[0] = 0.5 * c->box[0];
+  c->ew_ext[1] = 0.5 * c->box[1];
+  c->ew_ext[2] = c->bctype == ot::BC_3P ? 0.5 * c->box[2]
+                                        : (c->box[2] < 2.0 * c->box[0] ? c->box[2] : 2.0 * c->box[0]);
+  for (int k = 0; k < 3; ++k) c->ew_step[k] = c->ew_ext[k] / (double)(n - 1);
+  const size_t np = (size_t)n * n * n;
+  OTCHK(dalloc(c, c->tab64, np * 10 * sizeof(double)));
+  OTCHK(dalloc(c, c->tab32, np * 3 * sizeof(float4)));
+  ot::EwaldP E = ewald_desc(c);
+  HIPCHK(ot::launch_ewald_table(E, c->ew_alpha, c->ew_rcut2, c->ew_fcut2, P<double>(c->tab64),
+                                P<float4>(c->tab32), st));
+  HIPCHK(hipStreamSynchronize(st));
+  c->ewald_ready = true;
+  return OT_OK;
+}
+
+// Interaction lists for the given MAC: count, scan, fill.
+ot_status build_lists(ot_ctx *c, const ot::MacP &mp, hipStream_t st) {
+  const ot::Topology &t = c->topo;
+  ot::DevTree T = dev_tree(c);
+  int64_t capA = 0;
+  for (int l = 1; l <= t.lmax; ++l) capA = std::max(capA, t.level_begin[l + 1] - t.level_begin[l]);
+  const int64_t stride = 2 * capA + 9 * t.nb;
+  int64_t grid = std::min<int64_t>(t.nb, 2048);
+  const int64_t budget = (int64_t)1 << 30;  // scratch bytes
+  while (grid > 64 && grid * stride * 4 > budget) grid /= 2;
+  OTCHK(dalloc(c, c->lscratch, (size_t)(grid * stride * 4)));
+  OTCHK(dalloc(c, c->lcount, t.nb * sizeof(int32_t)));
+  OTCHK(dalloc(c, c->loff, (t.nb + 1) * sizeof(int64_t)));
+  HIPCHK(ot::launch_lists(false, T, mp, (int)grid, P<int32_t>(c->lcount), nullptr, nullptr, nullptr,
+                          P<int32_t>(c->lscratch), stride, capA, st));
+  HIPCHK(ot::launch_scan(P<int32_t>(c->lcount), t.nb, P<int64_t>(c->loff), st));
+  int64_t total = 0;
+  HIPCHK(hipMemcpyAsync(&total, P<int64_t>(c->loff) + t.nb, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  OTCHK(dalloc(c, c->lrec, (size_t)total * sizeof(double4)));
+  OTCHK(dalloc(c, c->lid, (size_t)total * sizeof(int32_t)));
+  HIPCHK(ot::launch_lists(true, T, mp, (int)grid, P<int32_t>(c->lcount), P<int64_t>(c->loff),
+                          P<double4>(c->lrec), P<int32_t>(c->lid), P<int32_t>(c->lscratch), stride,
+                          capA, st));
+  c->list_cap = total;
+  return OT_OK;
+}
+
+ot::MacP mac_params(const ot_ctx *c, int mac, double a_lim) {
+  ot::MacP m;
+  m.theta2 = c->p.theta_lim * c->p.theta_lim;
+  m.half_eta = 0.5 * c->p.eta_sb;
+  m.G = c->p.G;
+  m.a_lim = a_lim;
+  m.tpix2 = 0.0;
+  m.mac = mac;
+  m.use_pix = 0;
+  return m;
+}
+
+// a_lim = eps_lim * max |a| from a BH FP64 walk (Sec. 3)
+ot_status ape_limit(ot_ctx *c, hipStream_t st, double *alim) {
+  if (c->p.a_lim > 0) {
+    *alim = c->p.a_lim;
+    return OT_OK;
+  }
+  if (!c->alim_valid) {
+    OTCHK(build_lists(c, mac_params(c, OT_MAC_BH, 0.0), st));
+    const int64_t ncell = c->topo.nb * 512;
+    DevBuf phi, acc, mx;
+    OTCHK(dalloc(c, phi, ncell * sizeof(double)));
+    ot_status s = dalloc(c, acc, 3 * ncell * sizeof(double));
+    if (s == OT_OK) s = dalloc(c, mx, sizeof(unsigned long long));
+    unsigned long long bits = 0;
+    hipError_t e = hipSuccess;
+    if (s == OT_OK) {
+      ot::DevTree T = dev_tree(c);
+      e = hipMemsetAsync(mx.ptr, 0, sizeof(unsigned long long), st);
+      if (e == hipSuccess)
+        e = ot::launch_eval64(T, ewald_desc(c), P<int64_t>(c->loff), P<double4>(c->lrec),
+                              P<double>(phi), P<double>(acc), c->p.G, st);
+      if (e == hipSuccess) e = ot::launch_amax(P<double>(acc), ncell, P<unsigned long long>(mx), st);
+      if (e == hipSuccess) e = hipMemcpyAsync(&bits, mx.ptr, sizeof(bits), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    release(c, phi);
+    release(c, acc);
+    release(c, mx);
+    if (s != OT_OK) return s;
+    if (e != hipSuccess) return dev_fail(c, e, "a_max pre-pass");
+    double a2;
+    memcpy(&a2, &bits, sizeof(double));
+    c->alim = c->p.eps_lim * std::sqrt(a2);
+    c->alim_valid = true;
+  }
+  *alim = c->alim;
+  return OT_OK;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return -1.f;
+  return ms;
+}
+
+ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, ot_stats *stats, void *stream) {
+  if (!c) return OT_ERR_INVALID_ARG;
+  c->err.clear();
+  if (!phi || !acc) return fail(c, OT_ERR_INVALID_ARG, "phi and acc must be device pointers");
+  if (!c->built) return fail(c, OT_ERR_STATE, "ot_solve before a successful ot_build");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->p.device));
+  if (c->bctype != ot::BC_ISO) {
+    if (c->p.ewald != OT_EWALD_TABLE)
+      return fail(c, OT_ERR_UNSUPPORTED, "per-pair exact Ewald series is not built into the walk");
+    OTCHK(ewald_prepare(c, st));
+  }
+  double alim = 0.0;
+  if (c->p.mac == OT_MAC_APE) OTCHK(ape_limit(c, st, &alim));
+  for (int i = 0; i < 4; ++i)
+    if (!c->ev[i]) HIPCHK(hipEventCreate(&c->ev[i]));
+  HIPCHK(hipEventRecord(c->ev[0], st));
+  OTCHK(build_lists(c, mac_params(c, c->p.mac, alim), st));
+  HIPCHK(hipEventRecord(c->ev[1], st));
+  ot::DevTree T = dev_tree(c);
+  ot::EwaldP E = ewald_desc(c);
+  if (fp64)
+    HIPCHK(ot::launch_eval64(T, E, P<int64_t>(c->loff), P<double4>(c->lrec), (double *)phi,
+                             (double *)acc, c->p.G, st));
+  else
+    HIPCHK(ot::launch_eval32(T, E, P<int64_t>(c->loff), P<double4>(c->lrec), (float *)phi,
+                             (float *)acc, c->p.G, st));
+  HIPCHK(hipEventRecord(c->ev[2], st));
+  c->off_host.resize(c->topo.nb + 1);
+  HIPCHK(hipMemcpyAsync(c->off_host.data(), c->loff.ptr, (c->topo.nb + 1) * sizeof(int64_t),
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  c->lists_valid = true;
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    int64_t mx = 0;
+    for (int64_t b = 0; b < c->topo.nb; ++b) mx = std::max(mx, c->off_host[b + 1] - c->off_host[b]);
+    stats->total_list = c->off_host[c->topo.nb];
+    stats->max_list = mx;
+    stats->n_interactions = 512 * (stats->total_list - c->topo.nb);
+    stats->a_lim_used = alim;
+    stats->ms_list = elapsed(c->ev[0], c->ev[1]);
+    stats->ms_eval = elapsed(c->ev[1], c->ev[2]);
+    stats->ms_build = c->ms_build;
+  }
+  return OT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ot_params_default(ot_params *p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->nroot[0] = p->nroot[1] = p->nroot[2] = 1;
+  p->root_size = 1.0;
+  p->G = 1.0;
+  p->theta_lim = 0.5;
+  p->eta_sb = 1.2;
+  p->mac = OT_MAC_BH;
+  p->ewald = OT_EWALD_TABLE;
+  p->a_lim = 0.0;
+  p->eps_lim = 1e-3;
+  p->ewald_n = 64;
+  p->device = 0;
+}
+
+ot_status ot_create(const ot_params *p, ot_ctx **out) {
+  if (!p || !out) return OT_ERR_INVALID_ARG;
+  *out = nullptr;
+  ot_ctx *c = new (std::nothrow) ot_ctx();
+  if (!c) return OT_ERR_OOM;
+  c->p = *p;
+  auto bad = [&](const char *m) {
+    // keep the context so the caller can read the message, then let them destroy it
+    c->err = m;
+    *out = c;
+    return OT_ERR_INVALID_ARG;
+  };
+  for (int k = 0; k < 3; ++k) {
+    if (p->nroot[k] < 1) return bad("nroot must be >= 1");
+    if (p->bc[k] != 0 && p->bc[k] != 1) return bad("bc must be 0 (isolated) or 1 (periodic)");
+    c->box[k] = p->nroot[k] * p->root_size;
+  }
+  if (!(p->root_size > 0) || !std::isfinite(p->root_size)) return bad("root_size must be > 0");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(p->origin[k])) return bad("origin must be finite");
+  if (!(p->G > 0) || !std::isfinite(p->G)) return bad("G must be > 0");
+  if (!(p->theta_lim > 0) || !std::isfinite(p->theta_lim)) return bad("theta_lim must be > 0");
+  if (!(p->eta_sb >= 0) || !std::isfinite(p->eta_sb)) return bad("eta_sb must be >= 0");
+  if (p->mac != OT_MAC_BH && p->mac != OT_MAC_APE) return bad("unknown MAC");
+  if (p->ewald != OT_EWALD_TABLE && p->ewald != OT_EWALD_EXACT) return bad("unknown Ewald mode");
+  if (p->mac == OT_MAC_APE && !(p->a_lim > 0) && !(p->eps_lim > 0)) return bad("APE needs a_lim > 0 or eps_lim > 0");
+  if (p->ewald_n < 2 || p->ewald_n > 512) return bad("ewald_n must be in [2, 512]");
+  const int nper = p->bc[0] + p->bc[1] + p->bc[2];
+  if (nper == 0) c->bctype = ot::BC_ISO;
+  else if (nper == 3) c->bctype = ot::BC_3P;
+  else if (p->bc[0] && p->bc[1] && !p->bc[2]) c->bctype = ot::BC_2P1I;
+  else {
+    c->err = "boundary combination not supported (isolated, 3P and x,y-periodic 2P1I are)";
+    *out = c;
+    return OT_ERR_UNSUPPORTED;
+  }
+  *out = c;
+  return OT_OK;
+}
+
+ot_status ot_set_blocks(ot_ctx *c, int64_t nb, const int32_t *level, const int32_t *coord) {
+  if (!c) return OT_ERR_INVALID_ARG;
+  c->err.clear();
+  if (nb <= 0 || !level || !coord) return fail(c, OT_ERR_INVALID_ARG, "need nb > 0 and host level/coord arrays");
+  ot::Topology t;
+  std::string why = ot::build_topology(c->p.nroot, nb, level, coord, t);
+  if (!why.empty()) return fail(c, OT_ERR_BAD_GRID, why);
+  if (t.na + 584 * t.nb >= ((int64_t)1 << 31))
+    return fail(c, OT_ERR_UNSUPPORTED, "more than 2^31 tree nodes");
+  c->topo = std::move(t);
+  c->have_blocks = true;
+  c->dev_topo = false;
+  c->built = false;
+  c->lists_valid = false;
+  c->alim_valid = false;
+  return OT_OK;
+}
+
+ot_status ot_build(ot_ctx *c, const double *rho, void *stream) {
+  if (!c) return OT_ERR_INVALID_ARG;
+  c->err.clear();
+  if (!c->have_blocks) return fail(c, OT_ERR_STATE, "ot_build before ot_set_blocks");
+  if (!rho) return fail(c, OT_ERR_INVALID_ARG, "rho must be a device pointer");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->p.device));
+  c->built = false;
+  c->lists_valid = false;
+  c->alim_valid = false;
+  if (!c->dev_topo) OTCHK(upload_topology(c, st));
+  for (int i = 0; i < 4; ++i)
+    if (!c->ev[i]) HIPCHK(hipEventCreate(&c->ev[i]));
+  int bad = 0;
+  HIPCHK(hipMemsetAsync(c->flag.ptr, 0, sizeof(int), st));
+  HIPCHK(hipEventRecord(c->ev[0], st));
+  ot::DevTree T = dev_tree(c);
+  HIPCHK(ot::launch_build(T, rho, P<int>(c->flag), c->topo.level_begin, c->topo.lmax, st));
+  HIPCHK(hipEventRecord(c->ev[3], st));
+  HIPCHK(hipMemcpyAsync(&bad, c->flag.ptr, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  c->ms_build = elapsed(c->ev[0], c->ev[3]);
+  if (bad) return fail(c, OT_ERR_NUMERIC, "density must be finite and >= 0");
+  c->built = true;
+  return OT_OK;
+}
+
+ot_status ot_solve(ot_ctx *c, float *phi, float *acc, ot_stats *stats, void *stream) {
+  return solve_impl(c, false, phi, acc, stats, stream);
+}
+
+ot_status ot_solve64(ot_ctx *c, double *phi, double *acc, ot_stats *stats, void *stream) {
+  return solve_impl(c, true, phi, acc, stats, stream);
+}
+
+ot_status ot_ewald_prepare(ot_ctx *c, void *stream) {
+  if (!c) return OT_ERR_INVALID_ARG;
+  c->err.clear();
+  return ewald_prepare(c, (hipStream_t)stream);
+}
+
+int64_t ot_num_amr_nodes(const ot_ctx *c) { return c && c->have_blocks ? c->topo.na : -1; }
+
+ot_status ot_export_topology(const ot_ctx *cc, int32_t *level, int32_t *coord, int64_t *leaf,
+                             int64_t *child, uint64_t *key) {
+  ot_ctx *c = const_cast<ot_ctx *>(cc);
+  if (!c) return OT_ERR_INVALID_ARG;
+  if (!c->have_blocks) return fail(c, OT_ERR_STATE, "no blocks set");
+  const ot::Topology &t = c->topo;
+  if (level) memcpy(level, t.alev.data(), t.na * sizeof(int32_t));
+  if (coord) memcpy(coord, t.acoord.data(), 3 * t.na * sizeof(int32_t));
+  if (leaf) memcpy(leaf, t.aleaf.data(), t.na * sizeof(int64_t));
+  if (child) memcpy(child, t.achild.data(), 8 * t.na * sizeof(int64_t));
+  if (key) memcpy(key, t.akey.data(), t.na * sizeof(uint64_t));
+  return OT_OK;
+}
+
+ot_status ot_export_moments(ot_ctx *c, double *M, double *com) {
+  if (!c) return OT_ERR_INVALID_ARG;
+  if (!c->built) return fail(c, OT_ERR_STATE, "no tree built");
+  if (!M || !com) return fail(c, OT_ERR_INVALID_ARG, "null output");
+  HIPCHK(hipSetDevice(c->p.device));
+  const ot::Topology &t = c->topo;
+  std::vector<double4> a(t.na), bt(72 * t.nb);
+  std::vector<double> cm(512 * t.nb);
+  HIPCHK(hipMemcpy(a.data(), c->amc.ptr, t.na * sizeof(double4), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(bt.data(), c->btmc.ptr, 72 * t.nb * sizeof(double4), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(cm.data(), c->cm.ptr, 512 * t.nb * sizeof(double), hipMemcpyDeviceToHost));
+  auto put = [&](int64_t id, const double4 &v) {
+    M[id] = v.w;
+    com[3 * id] = v.x;
+    com[3 * id + 1] = v.y;
+    com[3 * id + 2] = v.z;
+  };
+  for (int64_t i = 0; i < t.na; ++i) put(i, a[i]);
+  for (int64_t lb = 0; lb < t.nb; ++lb) {
+    for (int o = 0; o < 8; ++o) put(t.na + 8 * lb + o, bt[72 * lb + o]);
+    for (int q = 0; q < 64; ++q) put(t.na + 8 * t.nb + 64 * lb + q, bt[72 * lb + 8 + q]);
+    const double h = ot::size_at(c->p.root_size, t.blev[lb]) / 8.0;
+    for (int ci = 0; ci < 512; ++ci) {
+      const int ijk[3] = {ci & 7, (ci >> 3) & 7, ci >> 6};
+      double4 v;
+      double x[3];
+      for (int k = 0; k < 3; ++k)
+        x[k] = c->p.origin[k] + ((double)(8 * (int64_t)t.bcoord[3 * lb + k] + ijk[k]) + 0.5) * h;
+      v.x = x[0];
+      v.y = x[1];
+      v.z = x[2];
+      v.w = cm[512 * lb + ci];
+      put(t.na + 72 * t.nb + 512 * lb + ci, v);
+    }
+  }
+  return OT_OK;
+}
+
+ot_status ot_export_list(ot_ctx *c, int64_t b, int32_t *ids, int64_t cap, int64_t *len) {
+  if (!c) return OT_ERR_INVALID_ARG;
+  if (!c->lists_valid) return fail(c, OT_ERR_STATE, "no lists: call ot_solve first");
+  if (b < 0 || b >= c->topo.nb || !len) return fail(c, OT_ERR_INVALID_ARG, "bad block index");
+  const int64_t n = c->off_host[b + 1] - c->off_host[b];
+  *len = n;
+  if (ids && cap > 0) {
+    HIPCHK(hipSetDevice(c->p.device));
+    HIPCHK(hipMemcpy(ids, P<int32_t>(c->lid) + c->off_host[b], std::min(n, cap) * sizeof(int32_t),
+                     hipMemcpyDeviceToHost));
+  }
+  return OT_OK;
+}
+
+ot_status ot_export_ewald_table(ot_ctx *c, double *tab) {
+  if (!c) return OT_ERR_INVALID_ARG;
+  if (!c->ewald_ready) return fail(c, OT_ERR_STATE, "no Ewald table");
+  if (!tab) return fail(c, OT_ERR_INVALID_ARG, "null output");
+  HIPCHK(hipSetDevice(c->p.device));
+  const size_t np = (size_t)c->ew_n * c->ew_n * c->ew_n;
+  HIPCHK(hipMemcpy(tab, c->tab64.ptr, np * 10 * sizeof(double), hipMemcpyDeviceToHost));
+  return OT_OK;
+}
+
+const char *ot_last_error(const ot_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+void ot_destroy(ot_ctx *c) {
+  if (!c) return;
+  if (c->dev_bytes || c->ev[0]) (void)hipSetDevice(c->p.device);
+  DevBuf *all[] = {&c->alev, &c->acoord, &c->achild0, &c->aleaf, &c->blev,   &c->bcoord,
+                   &c->bamr, &c->amc,    &c->aS,      &c->btmc,  &c->cm,     &c->flag,
+                   &c->lcount, &c->loff, &c->lrec,    &c->lid,   &c->lscratch, &c->tab64,
+                   &c->tab32};
+  for (DevBuf *b : all) release(c, *b);
+  for (int i = 0; i < 4; ++i)
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  delete c;
+}
+
+}  // extern "C"

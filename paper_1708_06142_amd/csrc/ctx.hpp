@@ -1,0 +1,70 @@
+// Host-side context of libocttree (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/octtree.h"
+#include "common.hpp"
+
+namespace ot {
+
+enum { BC_ISO = 0, BC_3P = 1, BC_2P1I = 2 };
+
+// Device allocation owned by a context; counts bytes against the cap.
+struct DevBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct Topology {
+  int64_t nb = 0, na = 0;
+  int lmax = 0;
+  std::vector<int32_t> blev, bcoord;              // leaf blocks (input order)
+  std::vector<int32_t> alev, acoord;              // amr nodes, (level, key) order
+  std::vector<uint64_t> akey;
+  std::vector<int64_t> aleaf, achild;             // leaf id / 8 children
+  std::vector<int64_t> bamr;                      // leaf block -> amr index
+  std::vector<int64_t> level_begin;               // first amr index per level, [lmax + 2]
+  int64_t nroots = 0;
+};
+
+// Returns an empty string on success, else the reason the grid is invalid.
+std::string build_topology(const int32_t nroot[3], int64_t nb, const int32_t *level,
+                           const int32_t *coord, Topology &t);
+
+}  // namespace ot
+
+struct ot_ctx {
+  ot_params p;
+  int bctype = ot::BC_ISO;
+  double box[3];
+  std::string err;
+  ot::Topology topo;
+  bool have_blocks = false;
+  bool dev_topo = false;
+  bool built = false;
+  size_t dev_bytes = 0;
+  std::vector<ot::DevBuf *> bufs;
+  // topology + moments
+  ot::DevBuf alev, acoord, achild0, aleaf, blev, bcoord, bamr, amc, aS, btmc, cm, flag;
+  // interaction lists
+  ot::DevBuf lcount, loff, lrec, lid, lscratch;
+  int64_t list_cap = 0;
+  int64_t scratch_per_wg = 0;
+  int list_grid = 0;
+  bool lists_valid = false;
+  std::vector<int64_t> off_host;  // list offsets of the last solve
+  // APE limit from the BH pre-pass
+  bool alim_valid = false;
+  double alim = 0.0;
+  // Ewald
+  ot::DevBuf tab64, tab32;
+  bool ewald_ready = false;
+  int ew_n = 0, ew_rcut2 = 0, ew_fcut2 = 0;
+  double ew_alpha = 0, ew_ext[3] = {0, 0, 0}, ew_step[3] = {0, 0, 0};
+  double ms_build = 0.0;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};

@@ -1,0 +1,284 @@
+// Per-cell evaluation of the block interaction lists (Sec. 2.2.1-2.2.4).
+//
+// Phi(r) = -G sum_a M_a phi(r - r_a), a(r) = -G sum_a M_a A(r - r_a) over the
+// accepted nodes (Eqs. 7, 8 and App. A), with phi = 1/r, A = d/r^3 for
+// isolated boundaries, and phi = 1/r + phi_c, A = d/r^3 + A_c for periodic
+// (3P) or mixed (2P1I) ones, the correction taken from the table by a
+// first-order Taylor expansion about the nearest grid point (second approach
+// of Sec. 2.2.4) or, for 2P1I beyond |dz| = 2 Lx, from the analytic limit.
+// The target cell itself is skipped (d = 0 exactly).
+//
+// One workgroup of 256 threads per leaf block; thread t owns cells t and
+// t + 256.  The list is streamed through LDS in tiles of 256 records, which
+// every thread then reads as broadcasts.  The FP32 kernel converts each record
+// to FP32 once per workgroup, accumulates Phi with Kahan compensation and the
+// acceleration in plain FP32.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace ot {
+
+namespace {
+
+constexpr int WG = 256;
+
+// ---------------------------------------------------------------- FP64
+template <int BC>
+__device__ inline void pair64(const EwaldP &E, double cx, double cy, double cz, const double4 r,
+                              double &sp, double &ax, double &ay, double &az) {
+  double dx = cx - r.x, dy = cy - r.y, dz = cz - r.z;
+  if (BC != 0) {
+    dx = dx - E.L[0] * floor(dx / E.L[0] + 0.5);
+    dy = dy - E.L[1] * floor(dy / E.L[1] + 0.5);
+    if (BC == 1) dz = dz - E.L[2] * floor(dz / E.L[2] + 0.5);
+  }
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  if (r2 == 0.0) return;
+  const double inv = 1.0 / sqrt(r2);
+  const double inv3 = inv * inv * inv;
+  if (BC == 0) {
+    sp += r.w * inv;
+    ax += r.w * inv3 * dx;
+    ay += r.w * inv3 * dy;
+    az += r.w * inv3 * dz;
+    return;
+  }
+  double phi, A0, A1, A2;
+  if (BC == 2 && fabs(dz) > E.zfar) {
+    phi = E.far_phi_a * fabs(dz) + E.far_phi_b;
+    A0 = 0.0;
+    A1 = 0.0;
+    A2 = dz < 0 ? -E.far_az : E.far_az;
+  } else {
+    const double u[3] = {fabs(dx), fabs(dy), fabs(dz)};
+    int g[3];
+    double dl[3];
+    for (int k = 0; k < 3; ++k) {
+      int gi = (int)floor(u[k] / E.step[k] + 0.5);
+      gi = gi > E.n - 1 ? E.n - 1 : gi;
+      g[k] = gi;
+      dl[k] = u[k] - gi * E.step[k];
+    }
+    const double *T = E.tab64 + 10 * (((int64_t)g[2] * E.n + g[1]) * E.n + g[0]);
+    const double phic = T[0] - (T[1] * dl[0] + T[2] * dl[1] + T[3] * dl[2]);
+    double a0 = T[1] - (T[4] * dl[0] + T[7] * dl[1] + T[8] * dl[2]);
+    double a1 = T[2] - (T[7] * dl[0] + T[5] * dl[1] + T[9] * dl[2]);
+    double a2 = T[3] - (T[8] * dl[0] + T[9] * dl[1] + T[6] * dl[2]);
+    phi = inv + phic;
+    A0 = dx * inv3 + (dx < 0 ? -a0 : a0);
+    A1 = dy * inv3 + (dy < 0 ? -a1 : a1);
+    A2 = dz * inv3 + (dz < 0 ? -a2 : a2);
+  }
+  sp += r.w * phi;
+  ax += r.w * A0;
+  ay += r.w * A1;
+  az += r.w * A2;
+}
+
+template <int BC>
+__global__ __launch_bounds__(WG) void k_eval64(DevTree T, EwaldP E, const int64_t *__restrict__ off,
+                                               const double4 *__restrict__ rec,
+                                               double *__restrict__ phi, double *__restrict__ acc,
+                                               double negG) {
+  __shared__ double4 tile[WG];
+  const int64_t b = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t ncell = T.nb * 512;
+  const double h = size_at(T.root_size, T.blev[b]) / 8.0;
+  double cx[2], cy[2], cz[2], sp[2] = {0, 0}, ax[2] = {0, 0}, ay[2] = {0, 0}, az[2] = {0, 0};
+  for (int q = 0; q < 2; ++q) {
+    int ci = tid + q * WG;
+    cx[q] = ((double)(ci & 7) - 3.5) * h;
+    cy[q] = ((double)((ci >> 3) & 7) - 3.5) * h;
+    cz[q] = ((double)(ci >> 6) - 3.5) * h;
+  }
+  const int64_t start = off[b], n = off[b + 1] - start;
+  for (int64_t t0 = 0; t0 < n; t0 += WG) {
+    if (t0 + tid < n) tile[tid] = rec[start + t0 + tid];
+    __syncthreads();
+    const int m = (int)(n - t0 < WG ? n - t0 : WG);
+    for (int j = 0; j < m; ++j) {
+      const double4 r = tile[j];
+      pair64<BC>(E, cx[0], cy[0], cz[0], r, sp[0], ax[0], ay[0], az[0]);
+      pair64<BC>(E, cx[1], cy[1], cz[1], r, sp[1], ax[1], ay[1], az[1]);
+    }
+    __syncthreads();
+  }
+  for (int q = 0; q < 2; ++q) {
+    int64_t o = b * 512 + tid + q * WG;
+    phi[o] = negG * sp[q];
+    acc[o] = negG * ax[q];
+    acc[ncell + o] = negG * ay[q];
+    acc[2 * ncell + o] = negG * az[q];
+  }
+}
+
+// ---------------------------------------------------------------- FP32
+struct Acc32 {
+  float s, c;  // Kahan sum of M phi and its compensation
+  float ax, ay, az;
+};
+
+template <int BC>
+__device__ inline void pair32(const EwaldP &E, float cx, float cy, float cz, const float4 r,
+                              Acc32 &a) {
+  float dx = cx - r.x, dy = cy - r.y, dz = cz - r.z;
+  if (BC != 0) {
+    const float Lx = (float)E.L[0], Ly = (float)E.L[1];
+    dx = dx - Lx * floorf(dx / Lx + 0.5f);
+    dy = dy - Ly * floorf(dy / Ly + 0.5f);
+    if (BC == 1) {
+      const float Lz = (float)E.L[2];
+      dz = dz - Lz * floorf(dz / Lz + 0.5f);
+    }
+  }
+  const float r2 = dx * dx + dy * dy + dz * dz;
+  const float inv = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+  const float mi = r.w * inv;
+  float term, fx, fy, fz;
+  if (BC == 0) {
+    const float mi3 = mi * inv * inv;
+    term = mi;
+    fx = mi3 * dx;
+    fy = mi3 * dy;
+    fz = mi3 * dz;
+  } else {
+    const float inv3 = inv * inv * inv;
+    float phi, A0, A1, A2;
+    if (BC == 2 && fabsf(dz) > (float)E.zfar) {
+      phi = (float)E.far_phi_a * fabsf(dz) + (float)E.far_phi_b;
+      A0 = 0.0f;
+      A1 = 0.0f;
+      A2 = dz < 0 ? -(float)E.far_az : (float)E.far_az;
+    } else {
+      const float u0 = fabsf(dx), u1 = fabsf(dy), u2 = fabsf(dz);
+      int g0 = min((int)(u0 * (float)E.inv_step[0] + 0.5f), E.n - 1);
+      int g1 = min((int)(u1 * (float)E.inv_step[1] + 0.5f), E.n - 1);
+      int g2 = min((int)(u2 * (float)E.inv_step[2] + 0.5f), E.n - 1);
+      const float d0 = u0 - g0 * (float)E.step[0];
+      const float d1 = u1 - g1 * (float)E.step[1];
+      const float d2 = u2 - g2 * (float)E.step[2];
+      const float4 *p = E.tab32 + 3 * (((int64_t)g2 * E.n + g1) * E.n + g0);
+      const float4 q0 = p[0], q1 = p[1], q2 = p[2];
+      // q0 = {phi_c, A_c}, q1 = {Hxx, Hyy, Hzz, Hxy}, q2 = {Hxz, Hyz, -, -}
+      const float phic = q0.x - (q0.y * d0 + q0.z * d1 + q0.w * d2);
+      const float a0 = q0.y - (q1.x * d0 + q1.w * d1 + q2.x * d2);
+      const float a1 = q0.z - (q1.w * d0 + q1.y * d1 + q2.y * d2);
+      const float a2 = q0.w - (q2.x * d0 + q2.y * d1 + q1.z * d2);
+      phi = inv + phic;
+      A0 = dx * inv3 + (dx < 0 ? -a0 : a0);
+      A1 = dy * inv3 + (dy < 0 ? -a1 : a1);
+      A2 = dz * inv3 + (dz < 0 ? -a2 : a2);
+    }
+    const bool self = !(r2 > 0.0f);
+    term = self ? 0.0f : r.w * phi;
+    fx = self ? 0.0f : r.w * A0;
+    fy = self ? 0.0f : r.w * A1;
+    fz = self ? 0.0f : r.w * A2;
+  }
+  // Kahan compensated sum of the potential terms
+  const float y = term - a.c;
+  const float t = a.s + y;
+  a.c = (t - a.s) - y;
+  a.s = t;
+  a.ax += fx;
+  a.ay += fy;
+  a.az += fz;
+}
+
+template <int BC>
+__global__ __launch_bounds__(WG) void k_eval32(DevTree T, EwaldP E, const int64_t *__restrict__ off,
+                                               const double4 *__restrict__ rec,
+                                               float *__restrict__ phi, float *__restrict__ acc,
+                                               float negG) {
+  __shared__ float4 tile[WG];
+  const int64_t b = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t ncell = T.nb * 512;
+  const double h = size_at(T.root_size, T.blev[b]) / 8.0;
+  float cx[2], cy[2], cz[2];
+  Acc32 a[2];
+  for (int q = 0; q < 2; ++q) {
+    int ci = tid + q * WG;
+    cx[q] = (float)(((double)(ci & 7) - 3.5) * h);
+    cy[q] = (float)(((double)((ci >> 3) & 7) - 3.5) * h);
+    cz[q] = (float)(((double)(ci >> 6) - 3.5) * h);
+    a[q] = Acc32{0.f, 0.f, 0.f, 0.f, 0.f};
+  }
+  const int64_t start = off[b], n = off[b + 1] - start;
+  for (int64_t t0 = 0; t0 < n; t0 += WG) {
+    if (t0 + tid < n) {
+      const double4 r = rec[start + t0 + tid];
+      tile[tid] = make_float4((float)r.x, (float)r.y, (float)r.z, (float)r.w);
+    }
+    __syncthreads();
+    const int m = (int)(n - t0 < WG ? n - t0 : WG);
+    for (int j = 0; j < m; ++j) {
+      const float4 r = tile[j];
+      pair32<BC>(E, cx[0], cy[0], cz[0], r, a[0]);
+      pair32<BC>(E, cx[1], cy[1], cz[1], r, a[1]);
+    }
+    __syncthreads();
+  }
+  for (int q = 0; q < 2; ++q) {
+    int64_t o = b * 512 + tid + q * WG;
+    phi[o] = negG * (a[q].s - a[q].c);
+    acc[o] = negG * a[q].ax;
+    acc[ncell + o] = negG * a[q].ay;
+    acc[2 * ncell + o] = negG * a[q].az;
+  }
+}
+
+// max |a|^2 over cells (non-negative doubles order like their bit patterns)
+__global__ __launch_bounds__(256) void k_amax(const double *__restrict__ acc, int64_t n,
+                                              unsigned long long *__restrict__ out) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    double x = acc[i], y = acc[n + i], z = acc[2 * n + i];
+    double v = x * x + y * y + z * z;
+    m = v > m ? v : m;
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+}  // namespace
+
+hipError_t launch_eval64(const DevTree &T, const EwaldP &E, const int64_t *off, const double4 *rec,
+                         double *phi, double *acc, double G, hipStream_t st) {
+  dim3 grid((unsigned)T.nb), blk(WG);
+  switch (E.bctype) {
+    case 0: hipLaunchKernelGGL(k_eval64<0>, grid, blk, 0, st, T, E, off, rec, phi, acc, -G); break;
+    case 1: hipLaunchKernelGGL(k_eval64<1>, grid, blk, 0, st, T, E, off, rec, phi, acc, -G); break;
+    default: hipLaunchKernelGGL(k_eval64<2>, grid, blk, 0, st, T, E, off, rec, phi, acc, -G); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_eval32(const DevTree &T, const EwaldP &E, const int64_t *off, const double4 *rec,
+                         float *phi, float *acc, double G, hipStream_t st) {
+  dim3 grid((unsigned)T.nb), blk(WG);
+  float ng = (float)(-G);
+  switch (E.bctype) {
+    case 0: hipLaunchKernelGGL(k_eval32<0>, grid, blk, 0, st, T, E, off, rec, phi, acc, ng); break;
+    case 1: hipLaunchKernelGGL(k_eval32<1>, grid, blk, 0, st, T, E, off, rec, phi, acc, ng); break;
+    default: hipLaunchKernelGGL(k_eval32<2>, grid, blk, 0, st, T, E, off, rec, phi, acc, ng); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_amax(const double *acc, int64_t n, unsigned long long *out, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_amax, dim3((unsigned)blocks), dim3(256), 0, st, acc, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace ot

@@ -1,0 +1,208 @@
+// Ewald correction table, FP64 on the device (Sec. 2.2.2-2.2.4, App. A).
+//
+// For every point u of a uniform grid over the folded domain the kernel sums
+// the series of phi (3P: Eq. 9 with the cut-offs of Eq. 10; 2P1I: Eq. 15 in
+// the code form of its footnote) with the Newtonian 1/r removed from the
+// central image, and their analytic first and second derivatives:
+//   channel 0: phi_c = phi - 1/r
+//   1..3     : A_c = -grad phi_c
+//   4..9     : H = grad grad phi_c (xx, yy, zz, xy, xz, yz)
+// The 2P1I z-integral uses Itilde = pi/(2s) [exp(-g^2/4z - z s^2) erfcx(A+)
+// + exp(-g s) erfc(A-)] with A+- = sqrt(z) s +- g/(2 sqrt(z)), evaluated at
+// |gamma| (even; the first derivative is odd), and the regularised l = 0 term
+// I(0,0) of Eq. 14.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace ot {
+
+namespace {
+
+constexpr double PI = 3.14159265358979323846;
+constexpr double SQRTPI = 1.7724538509055160273;
+
+struct Radial {
+  double f, D1, D2;  // value, f'/r, (f'/r)'/r
+};
+
+// erfc(alpha r)/r
+__device__ inline Radial erfc_term(double a, double r) {
+  const double r2 = r * r;
+  const double ex = (2.0 * a / SQRTPI) * exp(-a * a * r2);
+  const double ec = erfc(a * r);
+  Radial R;
+  R.f = ec / r;
+  R.D1 = -(ex / r2 + ec / (r2 * r));
+  R.D2 = ex * (2.0 * a * a / r2 + 3.0 / (r2 * r2)) + 3.0 * ec / (r2 * r2 * r);
+  return R;
+}
+
+// -erf(alpha r)/r, the central image with 1/r removed; Taylor series of
+// erf(x)/x below x = 0.5 (smooth through r = 0)
+__device__ inline Radial erf_corr_term(double a, double r) {
+  const double x = a * r;
+  Radial R;
+  if (x < 0.5) {
+    const double c = 2.0 * a / SQRTPI;
+    const double x2 = x * x;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    double p0 = 1.0, p1 = 0.0, p2 = 0.0;  // x^(2n), x^(2n-2), x^(2n-4)
+    double inv_fact = 1.0;
+    for (int n = 0; n < 18; ++n) {
+      if (n > 0) inv_fact /= n;
+      const double an = ((n & 1) ? -inv_fact : inv_fact) / (2 * n + 1);
+      s0 += an * p0;
+      if (n >= 1) s1 += 2.0 * n * an * p1;
+      if (n >= 2) s2 += 2.0 * n * (2.0 * n - 2.0) * an * p2;
+      p2 = n >= 1 ? p1 : 0.0;
+      p1 = p0;
+      p0 *= x2;
+    }
+    R.f = -c * s0;
+    R.D1 = -c * a * a * s1;
+    R.D2 = -c * a * a * a * a * s2;
+    return R;
+  }
+  const double r2 = r * r;
+  const double ex = (2.0 * a / SQRTPI) * exp(-a * a * r2);
+  const double ef = erf(x);
+  R.f = -ef / r;
+  R.D1 = -ex / r2 + ef / (r2 * r);
+  R.D2 = ex * (2.0 * a * a / r2 + 3.0 / (r2 * r2)) - 3.0 * ef / (r2 * r2 * r);
+  return R;
+}
+
+struct Acc10 {
+  double v[10];
+};
+
+__device__ inline void add_radial(const Radial &R, double x, double y, double z, Acc10 &o) {
+  o.v[0] += R.f;
+  o.v[1] -= R.D1 * x;
+  o.v[2] -= R.D1 * y;
+  o.v[3] -= R.D1 * z;
+  o.v[4] += R.D2 * x * x + R.D1;
+  o.v[5] += R.D2 * y * y + R.D1;
+  o.v[6] += R.D2 * z * z + R.D1;
+  o.v[7] += R.D2 * x * y;
+  o.v[8] += R.D2 * x * z;
+  o.v[9] += R.D2 * y * z;
+}
+
+__global__ __launch_bounds__(128) void k_ewald_table(EwaldP E, double alpha, int rcut2, int fcut2,
+                                                     double *__restrict__ tab64,
+                                                     float4 *__restrict__ tab32) {
+  const int64_t n = E.n;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n * n * n) return;
+  const int ix = (int)(q % n), iy = (int)((q / n) % n), iz = (int)(q / (n * n));
+  const double u[3] = {ix * E.step[0], iy * E.step[1], iz * E.step[2]};
+  const double Lx = E.L[0], b = E.L[1] / E.L[0], c = E.L[2] / E.L[0];
+  const double zeta = (PI * PI) / ((alpha * Lx) * (alpha * Lx));
+  const bool three = E.bctype == 1;
+  Acc10 o;
+  for (int k = 0; k < 10; ++k) o.v[k] = 0.0;
+
+  const double rr = sqrt((double)rcut2);
+  const int R1 = (int)ceil(rr) + 1, R2 = (int)ceil(rr / b) + 1, R3 = three ? (int)ceil(rr / c) + 1 : 0;
+  for (int i3 = -R3; i3 <= R3; ++i3)
+    for (int i2 = -R2; i2 <= R2; ++i2)
+      for (int i1 = -R1; i1 <= R1; ++i1) {
+        const double qq = (double)(i1 * i1) + (b * i2) * (b * i2) + (c * i3) * (c * i3);
+        if (qq > rcut2) continue;
+        const double x = u[0] - i1 * Lx, y = u[1] - i2 * b * Lx, z = u[2] - i3 * c * Lx;
+        const double r = sqrt(x * x + y * y + z * z);
+        if (i1 == 0 && i2 == 0 && i3 == 0) {
+          add_radial(erf_corr_term(alpha, r), x, y, z, o);
+        } else {
+          add_radial(erfc_term(alpha, r), x, y, z, o);
+        }
+      }
+
+  const double fr = sqrt((double)fcut2);
+  const int F1 = (int)ceil(fr) + 1, F2 = (int)ceil(fr * b) + 1, F3 = (int)ceil(fr * c) + 1;
+  const double kap = 2.0 * PI / Lx;
+  if (three) {
+    const double pre = 1.0 / (PI * b * c * Lx);
+    for (int l3 = -F3; l3 <= F3; ++l3)
+      for (int l2 = -F2; l2 <= F2; ++l2)
+        for (int l1 = -F1; l1 <= F1; ++l1) {
+          if (l1 == 0 && l2 == 0 && l3 == 0) continue;
+          const double q0 = l1, q1 = l2 / b, q2 = l3 / c;
+          const double Q = q0 * q0 + q1 * q1 + q2 * q2;
+          if (Q > fcut2) continue;
+          const double Ew = exp(-zeta * Q) / Q;
+          double sv, cv;
+          sincos(kap * (q0 * u[0] + q1 * u[1] + q2 * u[2]), &sv, &cv);
+          const double hk = -pre * kap * kap * Ew * cv;
+          o.v[0] += pre * Ew * cv;
+          o.v[1] += pre * kap * q0 * Ew * sv;
+          o.v[2] += pre * kap * q1 * Ew * sv;
+          o.v[3] += pre * kap * q2 * Ew * sv;
+          o.v[4] += hk * q0 * q0;
+          o.v[5] += hk * q1 * q1;
+          o.v[6] += hk * q2 * q2;
+          o.v[7] += hk * q0 * q1;
+          o.v[8] += hk * q0 * q2;
+          o.v[9] += hk * q1 * q2;
+        }
+  } else {
+    const double pre = 1.0 / (PI * Lx * b);
+    const double gam = kap * u[2];  // u[2] >= 0 on the folded grid
+    const double sz = sqrt(zeta);
+    for (int l2 = -F2; l2 <= F2; ++l2)
+      for (int l1 = -F1; l1 <= F1; ++l1) {
+        const double q0 = l1, q1 = l2 / b;
+        const double Q = q0 * q0 + q1 * q1;
+        if (Q > fcut2) continue;
+        double I0, I1, I2;
+        if (l1 == 0 && l2 == 0) {
+          const double e = erf(gam / (2.0 * sz));
+          const double gs = exp(-gam * gam / (4.0 * zeta));
+          I0 = -PI * (gam * e + 2.0 * sqrt(zeta / PI) * gs) + 2.0 * sqrt(PI * zeta);
+          I1 = -PI * e;
+          I2 = -(SQRTPI / sz) * gs;
+        } else {
+          const double s = sqrt(Q);
+          const double Ap = sz * s + gam / (2.0 * sz);
+          const double Am = sz * s - gam / (2.0 * sz);
+          const double gauss = exp(-gam * gam / (4.0 * zeta) - zeta * Q);
+          const double E1 = gauss * erfcx(Ap);
+          const double E2 = exp(-gam * s) * erfc(Am);
+          I0 = PI / (2.0 * s) * (E1 + E2);
+          I1 = (PI / 2.0) * (E1 - E2);
+          I2 = (PI / 2.0) * (s * (E1 + E2) - 2.0 / sqrt(PI * zeta) * gauss);
+        }
+        double sv, cv;
+        sincos(kap * (q0 * u[0] + q1 * u[1]), &sv, &cv);
+        const double k2 = pre * kap * kap;
+        o.v[0] += pre * cv * I0;
+        o.v[1] += pre * kap * q0 * sv * I0;
+        o.v[2] += pre * kap * q1 * sv * I0;
+        o.v[3] -= pre * kap * cv * I1;
+        o.v[4] -= k2 * q0 * q0 * cv * I0;
+        o.v[5] -= k2 * q1 * q1 * cv * I0;
+        o.v[6] += k2 * cv * I2;
+        o.v[7] -= k2 * q0 * q1 * cv * I0;
+        o.v[8] -= k2 * q0 * sv * I1;
+        o.v[9] -= k2 * q1 * sv * I1;
+      }
+  }
+  double *t = tab64 + 10 * q;
+  for (int k = 0; k < 10; ++k) t[k] = o.v[k];
+  tab32[3 * q + 0] = make_float4((float)o.v[0], (float)o.v[1], (float)o.v[2], (float)o.v[3]);
+  tab32[3 * q + 1] = make_float4((float)o.v[4], (float)o.v[5], (float)o.v[6], (float)o.v[7]);
+  tab32[3 * q + 2] = make_float4((float)o.v[8], (float)o.v[9], 0.0f, 0.0f);
+}
+
+}  // namespace
+
+hipError_t launch_ewald_table(const EwaldP &E, double alpha, int rcut2, int fcut2, double *tab64,
+                              float4 *tab32, hipStream_t st) {
+  int64_t np = (int64_t)E.n * E.n * E.n;
+  hipLaunchKernelGGL(k_ewald_table, dim3((unsigned)((np + 127) / 128)), dim3(128), 0, st, E, alpha,
+                     rcut2, fcut2, tab64, tab32);
+  return hipGetLastError();
+}
+
+}  // namespace ot

@@ -1,0 +1,303 @@
+// Interaction lists: one per leaf block (group walk), Sec. 2.1 + 2.2.1.
+//
+// The paper walks the tree depth-first per target cell and accepts a node
+// when the MAC suite holds.  Here all 512 cells of a leaf block share one
+// list: a node is accepted for the block when
+//   (i)  the block's cell-centre box lies strictly outside the cuboid of edge
+//        eta_SB h centred on the node (safe box), and
+//   (ii) the MAC holds at the box point closest to the node's centre of mass
+//        (the closest-point distance the paper uses to decide what to export
+//        between processors, Sec. 2.1 figure): BH h^2 < theta^2 d^2, APE
+//        G M h^2 < a_lim d^4; with columns also h^2 < theta_pix^2 d^2.
+// Cells are always accepted.  Compiled with FP contraction off so that the
+// accept/open decisions reproduce exactly.
+//
+// Traversal: a persistent workgroup per target block, level-synchronous over
+// the amr-tree (frontier of amr nodes in global scratch), then over the +1
+// and +2 levels of opened leaf blocks.  Ballot prefix sums give every thread
+// its output slot, so the list order is deterministic.  Pass 1 counts, pass 2
+// writes {r_a - c_T (minimum image), M} in FP64 plus the node ids.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace ot {
+
+namespace {
+
+constexpr int WG = 256;
+constexpr int NW = WG / 64;
+
+struct Target {
+  double c[3];
+  double ext;
+  double h;  // cell size of the target block
+};
+
+__device__ inline bool accept(const DevTree &T, const MacP &P, const Target &tg, double h,
+                              const double g[3], const double4 mc) {
+  const double half = P.half_eta * h;
+  bool outside = false;
+  for (int k = 0; k < 3; ++k) {
+    double d = wrap_axis(tg.c[k] - g[k], T.L[k], T.per[k]);
+    if (fabs(d) - tg.ext > half) outside = true;
+  }
+  if (!outside) return false;
+  const double com[3] = {mc.x, mc.y, mc.z};
+  double d2 = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    double d = wrap_axis(tg.c[k] - com[k], T.L[k], T.per[k]);
+    double e = fabs(d) - tg.ext;
+    if (e > 0.0) d2 = d2 + e * e;
+  }
+  bool ok;
+  if (P.mac == 0) {
+    ok = h * h < P.theta2 * d2;
+  } else {
+    ok = P.G * mc.w * h * h < P.a_lim * d2 * d2;
+  }
+  if (P.use_pix) ok = ok && (h * h < P.tpix2 * d2);
+  return ok;
+}
+
+// Workgroup-wide exclusive prefix of up to three 0/1 flags.
+struct Scan3 {
+  int pre[3];
+  int tot[3];
+};
+
+__device__ inline Scan3 scan3(bool f0, bool f1, bool f2, int (*swave)[NW]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  unsigned long long m[3] = {__ballot(f0), __ballot(f1), __ballot(f2)};
+  Scan3 s;
+  if (lane == 0)
+    for (int f = 0; f < 3; ++f) swave[f][w] = __popcll(m[f]);
+  __syncthreads();
+  for (int f = 0; f < 3; ++f) {
+    int before = 0, tot = 0;
+    for (int q = 0; q < NW; ++q) {
+      int v = swave[f][q];
+      before += q < w ? v : 0;
+      tot += v;
+    }
+    s.pre[f] = before + __popcll(m[f] & lt);
+    s.tot[f] = tot;
+  }
+  __syncthreads();
+  return s;
+}
+
+template <bool FILL>
+__device__ inline void emit(const DevTree &T, const Target &tg, int64_t pos, int32_t id,
+                            const double4 mc, double4 *rec, int32_t *ids) {
+  if (!FILL) return;
+  double4 r;
+  r.x = wrap_axis(mc.x - tg.c[0], T.L[0], T.per[0]);
+  r.y = wrap_axis(mc.y - tg.c[1], T.L[1], T.per[1]);
+  r.z = wrap_axis(mc.z - tg.c[2], T.L[2], T.per[2]);
+  r.w = mc.w;
+  rec[pos] = r;
+  ids[pos] = id;
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__restrict__ count,
+                                              const int64_t *__restrict__ off,
+                                              double4 *__restrict__ rec, int32_t *__restrict__ ids,
+                                              int32_t *__restrict__ scratch, int64_t stride,
+                                              int64_t capA) {
+  __shared__ int swave[3][NW];
+  const int tid = threadIdx.x;
+  int32_t *fa = scratch + (int64_t)blockIdx.x * stride;
+  int32_t *fb = fa + capA;
+  int32_t *olb = fb + capA;
+  int32_t *op1 = olb + T.nb;
+  const int64_t na = T.na, nb = T.nb;
+
+  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    Target tg;
+    const int blev = T.blev[b];
+    const double sb = size_at(T.root_size, blev);
+    for (int k = 0; k < 3; ++k) tg.c[k] = T.org[k] + ((double)T.bcoord[3 * b + k] + 0.5) * sb;
+    tg.ext = 3.5 * (sb / 8.0);
+    tg.h = sb / 8.0;
+    const int64_t base = FILL ? off[b] : 0;
+    int64_t nemit = 0;
+
+    // ---- amr-tree levels
+    int32_t *cur = fa, *nxt = fb;
+    for (int i = tid; i < T.nroots; i += WG) cur[i] = i;
+    __syncthreads();
+    int64_t ncur = T.nroots, nolb = 0;
+    while (ncur > 0) {
+      int64_t nnext = 0;
+      for (int64_t s0 = 0; s0 < ncur; s0 += WG) {
+        int64_t i = s0 + tid;
+        bool acc = false, oi = false, ol = false;
+        int32_t node = -1;
+        double4 mc = make_double4(0, 0, 0, 0);
+        if (i < ncur) {
+          node = cur[i];
+          const int lev = T.alev[node];
+          const double s = size_at(T.root_size, lev);
+          double g[3];
+          for (int k = 0; k < 3; ++k) g[k] = T.org[k] + ((double)T.acoord[3 * node + k] + 0.5) * s;
+          mc = T.amc[node];
+          acc = accept(T, P, tg, s, g, mc);
+          if (!acc) {
+            if (T.aleaf[node] >= 0) ol = true; else oi = true;
+          }
+        }
+        Scan3 sc = scan3(acc, oi, ol, swave);
+        if (acc) emit<FILL>(T, tg, base + nemit + sc.pre[0], node, mc, rec, ids);
+        if (oi) {
+          int32_t c0 = T.achild0[node];
+          for (int o = 0; o < 8; ++o) nxt[nnext + 8 * sc.pre[1] + o] = c0 + o;
+        }
+        if (ol) olb[nolb + sc.pre[2]] = T.aleaf[node];
+        nemit += sc.tot[0];
+        nnext += 8 * sc.tot[1];
+        nolb += sc.tot[2];
+      }
+      __syncthreads();
+      int32_t *t = cur;
+      cur = nxt;
+      nxt = t;
+      ncur = nnext;
+    }
+    __syncthreads();
+
+    // ---- +1 nodes of opened leaf blocks
+    int64_t nop1 = 0;
+    for (int64_t s0 = 0; s0 < 8 * nolb; s0 += WG) {
+      int64_t i = s0 + tid;
+      bool acc = false, op = false;
+      int32_t lb = 0, o1 = 0;
+      double4 mc = make_double4(0, 0, 0, 0);
+      if (i < 8 * nolb) {
+        lb = olb[i >> 3];
+        o1 = (int)(i & 7);
+        const double s = size_at(T.root_size, T.blev[lb]) / 2.0;
+        double g[3];
+        for (int k = 0; k < 3; ++k) {
+          int64_t pos = 2 * (int64_t)T.bcoord[3 * lb + k] + ((o1 >> k) & 1);
+          g[k] = T.org[k] + ((double)pos + 0.5) * s;
+        }
+        mc = T.btmc[(int64_t)lb * 72 + o1];
+        acc = accept(T, P, tg, s, g, mc);
+        op = !acc;
+      }
+      Scan3 sc = scan3(acc, op, false, swave);
+      if (acc) emit<FILL>(T, tg, base + nemit + sc.pre[0], (int32_t)(na + 8 * (int64_t)lb + o1), mc, rec, ids);
+      if (op) op1[nop1 + sc.pre[1]] = lb * 8 + o1;
+      nemit += sc.tot[0];
+      nop1 += sc.tot[1];
+    }
+    __syncthreads();
+
+    // ---- +2 nodes of opened +1 nodes; an opened +2 node emits its 8 cells
+    for (int64_t s0 = 0; s0 < 8 * nop1; s0 += WG) {
+      int64_t i = s0 + tid;
+      bool acc = false, op = false;
+      int32_t lb = 0, o1 = 0, o2 = 0;
+      double4 mc = make_double4(0, 0, 0, 0);
+      if (i < 8 * nop1) {
+        int32_t v = op1[i >> 3];
+        lb = v >> 3;
+        o1 = v & 7;
+        o2 = (int)(i & 7);
+        const double s = size_at(T.root_size, T.blev[lb]) / 4.0;
+        double g[3];
+        for (int k = 0; k < 3; ++k) {
+          int64_t pos = 4 * (int64_t)T.bcoord[3 * lb + k] + 2 * ((o1 >> k) & 1) + ((o2 >> k) & 1);
+          g[k] = T.org[k] + ((double)pos + 0.5) * s;
+        }
+        mc = T.btmc[(int64_t)lb * 72 + 8 + 8 * o1 + o2];
+        acc = accept(T, P, tg, s, g, mc);
+        op = !acc;
+      }
+      Scan3 sc = scan3(acc, op, false, swave);
+      if (acc)
+        emit<FILL>(T, tg, base + nemit + sc.pre[0],
+                   (int32_t)(na + 8 * nb + 64 * (int64_t)lb + 8 * o1 + o2), mc, rec, ids);
+      if (op && FILL) {
+        const int lev = T.blev[lb];
+        const double h = size_at(T.root_size, lev) / 8.0;
+        int64_t p0 = base + nemit + sc.tot[0] + 8 * (int64_t)sc.pre[1];
+        for (int o3 = 0; o3 < 8; ++o3) {
+          int ci = cell_index(o1, o2, o3);
+          int ijk[3] = {ci & 7, (ci >> 3) & 7, ci >> 6};
+          double4 r;
+          if (lb == b) {
+            // own block: the same expression as the evaluation's cell offset,
+            // so the target cell itself gives d = 0 exactly
+            r.x = ((double)ijk[0] - 3.5) * tg.h;
+            r.y = ((double)ijk[1] - 3.5) * tg.h;
+            r.z = ((double)ijk[2] - 3.5) * tg.h;
+          } else {
+            double x[3];
+            for (int k = 0; k < 3; ++k)
+              x[k] = T.org[k] + ((double)(8 * (int64_t)T.bcoord[3 * lb + k] + ijk[k]) + 0.5) * h;
+            r.x = wrap_axis(x[0] - tg.c[0], T.L[0], T.per[0]);
+            r.y = wrap_axis(x[1] - tg.c[1], T.L[1], T.per[1]);
+            r.z = wrap_axis(x[2] - tg.c[2], T.L[2], T.per[2]);
+          }
+          r.w = T.cm[(int64_t)lb * 512 + ci];
+          rec[p0 + o3] = r;
+          ids[p0 + o3] = (int32_t)(na + 72 * nb + 512 * (int64_t)lb + ci);
+        }
+      }
+      nemit += sc.tot[0] + 8 * sc.tot[1];
+    }
+    if (!FILL && tid == 0) count[b] = (int32_t)nemit;
+    __syncthreads();
+  }
+}
+
+// Exclusive scan of the per-block counts (single workgroup, sequential tiles).
+__global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ count, int64_t nb,
+                                               int64_t *__restrict__ off) {
+  __shared__ int64_t part[1024];
+  __shared__ int64_t carry;
+  const int tid = threadIdx.x;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (int64_t s0 = 0; s0 < nb; s0 += 1024) {
+    int64_t i = s0 + tid;
+    int64_t v = i < nb ? count[i] : 0;
+    part[tid] = v;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+      int64_t add = tid >= d ? part[tid - d] : 0;
+      __syncthreads();
+      part[tid] += add;
+      __syncthreads();
+    }
+    if (i < nb) off[i] = carry + part[tid] - v;
+    __syncthreads();
+    if (tid == 1023) carry += part[1023];
+    __syncthreads();
+  }
+  if (tid == 0) off[nb] = carry;
+}
+
+}  // namespace
+
+hipError_t launch_lists(bool fill, const DevTree &T, const MacP &P, int grid, int32_t *count,
+                        const int64_t *off, double4 *rec, int32_t *ids, int32_t *scratch,
+                        int64_t stride, int64_t capA, hipStream_t st) {
+  if (fill)
+    hipLaunchKernelGGL(k_lists<true>, dim3(grid), dim3(WG), 0, st, T, P, count, off, rec, ids,
+                       scratch, stride, capA);
+  else
+    hipLaunchKernelGGL(k_lists<false>, dim3(grid), dim3(WG), 0, st, T, P, count, off, rec, ids,
+                       scratch, stride, capA);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const int32_t *count, int64_t nb, int64_t *off, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, count, nb, off);
+  return hipGetLastError();
+}
+
+}  // namespace ot

@@ -1,0 +1,57 @@
+// Kernel launchers (internal to libocttree).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "common.hpp"
+
+namespace ot {
+
+// MAC suite parameters (Sec. 2.1, 2.2.1).  theta2 = theta*theta and
+// half_eta = 0.5*eta_SB are formed on the host in FP64.
+struct MacP {
+  double theta2;
+  double half_eta;
+  double G;
+  double a_lim;
+  double tpix2;
+  int mac;      // 0 BH, 1 APE
+  int use_pix;  // also require BH at theta_pix
+};
+
+// Ewald look-up description passed to the evaluation kernels.
+struct EwaldP {
+  int bctype;            // 0 iso, 1 3P, 2 2P1I
+  int n;                 // table points per axis
+  double L[3];           // box
+  double step[3];        // table spacing per axis
+  double inv_step[3];
+  double zfar;           // 2P1I: |dz| beyond which the analytic limit is used
+  double far_phi_a;      // phi -> far_phi_a |dz| + far_phi_b
+  double far_phi_b;
+  double far_az;         // A_z -> far_az sign(dz)
+  const double *tab64;   // [n^3][10]
+  const float4 *tab32;   // [n^3][3] (12 floats: 10 used)
+};
+
+hipError_t launch_build(const DevTree &T, const double *rho, int *bad,
+                        const std::vector<int64_t> &level_begin, int lmax, hipStream_t st);
+
+hipError_t launch_lists(bool fill, const DevTree &T, const MacP &P, int grid, int32_t *count,
+                        const int64_t *off, double4 *rec, int32_t *ids, int32_t *scratch,
+                        int64_t scratch_stride, int64_t capA, hipStream_t st);
+
+hipError_t launch_scan(const int32_t *count, int64_t nb, int64_t *off, hipStream_t st);
+
+hipError_t launch_eval64(const DevTree &T, const EwaldP &E, const int64_t *off, const double4 *rec,
+                         double *phi, double *acc, double G, hipStream_t st);
+hipError_t launch_eval32(const DevTree &T, const EwaldP &E, const int64_t *off, const double4 *rec,
+                         float *phi, float *acc, double G, hipStream_t st);
+
+hipError_t launch_amax(const double *acc, int64_t n, unsigned long long *out, hipStream_t st);
+
+hipError_t launch_ewald_table(const EwaldP &E, double alpha, int rcut2, int fcut2, double *tab64,
+                              float4 *tab32, hipStream_t st);
+
+}  // namespace ot
