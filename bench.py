@@ -36,7 +36,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=128, help="cells per axis")
-    ap.add_argument("--cpu-blocks", type=int, default=24, help="oracle sample size (blocks)")
+    ap.add_argument("--cpu-blocks", type=int, default=4096, help="oracle sample size (blocks)")
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="MiB: one fill + one sum of that size before timing (HBM counter calibration)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     return ap.parse_args()
@@ -67,7 +69,8 @@ def cpu_baseline(grid, a_lim, nblk):
     import oracle
     threads = os.cpu_count() or 1
     os.environ.setdefault("OMP_NUM_THREADS", str(threads))
-    sel = np.random.default_rng(7).choice(grid.nb, nblk, replace=False)
+    nblk = min(nblk, grid.nb)
+    sel = np.sort(np.random.default_rng(7).choice(grid.nb, nblk, replace=False))
     t0 = time.perf_counter()
     t = oracle.Tree(grid, mac="ape", a_lim=a_lim)
     tb = time.perf_counter() - t0
@@ -92,6 +95,12 @@ def main():
     import paper_1708_06142_amd as ot
     import workloads
 
+    if args.calib_copy:
+        n = args.calib_copy * (1 << 20) // 4
+        src = torch.ones(n, device="cuda")      # fill kernel: writes exactly n * 4 bytes
+        total = src.sum()                        # reduction: reads exactly n * 4 bytes
+        torch.cuda.synchronize()
+        del src, total
     grid = workloads.c2_lognormal(args.n)
     ncell = grid.ncells
     rho = torch.from_numpy(grid.rho.reshape(-1).copy()).cuda()

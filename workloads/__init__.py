@@ -108,7 +108,7 @@ def gaussian_field_k4(n, seed, box_shape=None):
     nz = k2 > 0
     amp[nz] = 1.0 / k2[nz]
     f *= amp
-    g = np.fft.irfftn(f, s=shape)
+    g = np.fft.irfftn(f, s=shape, axes=(0, 1, 2))
     g -= g.mean()
     g /= g.std()
     return g
