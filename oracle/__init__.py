@@ -14,7 +14,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
-SOURCES = ["octoracle.c", "ewald.c"]
+SOURCES = ["octoracle.c", "ewald.c", "columns.c"]
 
 ERRORS = {1: "bad level/coord", 2: "duplicate block", 3: "overlapping blocks",
           4: "hole in the block tiling", 5: "bad density", 6: "unsupported BCs"}
@@ -39,7 +39,14 @@ class Params(C.Structure):
                 ("eta_sb", C.c_double), ("a_lim", C.c_double), ("theta_pix", C.c_double),
                 ("mac", C.c_int32), ("ewald", C.c_int32), ("ew_n", C.c_int32),
                 ("ew_rcut2", C.c_int32), ("ew_fcut2", C.c_int32), ("pad_", C.c_int32),
-                ("ew_alpha", C.c_double)]
+                ("ew_alpha", C.c_double), ("nside", C.c_int32), ("il_ntheta", C.c_int32),
+                ("il_nphi", C.c_int32), ("il_npsi", C.c_int32), ("il_nr", C.c_int32),
+                ("il_nazi", C.c_int32), ("kappa", C.c_double), ("max_dist", C.c_double),
+                ("psi_max", C.c_double)]
+
+# defaults of the column machinery (App. B: tr_ilNTheta 25, tr_ilNPhi 50,
+# tr_ilNNS 25, tr_ilNR 50; azimuths and psi_max are this build's readings)
+COLUMN_DEFAULTS = dict(il_ntheta=25, il_nphi=50, il_npsi=25, il_nr=50, il_nazi=100, psi_max=0.98)
 
 
 _lib = None
@@ -63,7 +70,13 @@ def lib():
         L.or_block_list.restype = i64
         L.or_block_list.argtypes = [vp, i64, vp, i64]
         L.or_walk_group.argtypes = [vp, vp, vp, vp]
-        L.or_walk_group_blocks.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.or_walk_group_blocks.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
+        L.or_raymarch.argtypes = [vp, vp, i64, i64, i64, vp]
+        L.or_healpix_vec2pix.restype = i64
+        L.or_healpix_vec2pix.argtypes = [i64, C.c_double, C.c_double, C.c_double]
+        L.or_healpix_pix2ang.argtypes = [i64, i64, vp]
+        L.or_raytable_export.restype = i64
+        L.or_raytable_export.argtypes = [C.c_int] * 6 + [C.c_double, vp, vp, vp]
         L.or_walk_percell.argtypes = [vp, i64, vp, vp, vp, vp]
         L.or_direct.argtypes = [vp, i64, vp, vp, vp]
         L.or_morton.restype = C.c_uint64
@@ -95,7 +108,8 @@ def bctype(bc):
 
 
 def make_params(grid, theta=0.5, eta_sb=1.2, mac="bh", a_lim=0.0, theta_pix=0.0, G=1.0,
-                ewald="exact", ew_n=64, ew_alpha=0.0, ew_rcut2=0, ew_fcut2=0, bc=None):
+                ewald="exact", ew_n=64, ew_alpha=0.0, ew_rcut2=0, ew_fcut2=0, bc=None,
+                nside=0, kappa=1.0, max_dist=1e99, **cols):
     p = Params()
     for k in range(3):
         p.nroot[k] = int(grid.nroot[k])
@@ -106,6 +120,12 @@ def make_params(grid, theta=0.5, eta_sb=1.2, mac="bh", a_lim=0.0, theta_pix=0.0,
     p.mac = {"bh": 0, "ape": 1}[mac]
     p.ewald = {"exact": 0, "table": 1}[ewald]
     p.ew_n, p.ew_alpha, p.ew_rcut2, p.ew_fcut2 = ew_n, ew_alpha, ew_rcut2, ew_fcut2
+    p.nside, p.kappa, p.max_dist = nside, kappa, max_dist
+    c = dict(COLUMN_DEFAULTS, **cols)
+    p.il_ntheta, p.il_nphi, p.il_npsi = c["il_ntheta"], c["il_nphi"], c["il_npsi"]
+    p.il_nr, p.il_nazi, p.psi_max = c["il_nr"], c["il_nazi"], c["psi_max"]
+    if nside and theta_pix <= 0:
+        p.theta_pix = 1.0 / nside  # theta_lim ~ sqrt(Omega_pix): 1, 0.5, 0.25 for Nside 1, 2, 4
     return p
 
 
@@ -147,17 +167,30 @@ class Tree:
         lib().or_block_list(self.h, lb, _ptr(ids), n)
         return ids
 
-    def walk_group(self, blocks=None):
-        if blocks is None:
-            nc = 512 * self.nb
-            phi, acc, nint = np.empty(nc), np.empty((3, nc)), np.empty(self.nb, np.int64)
-            lib().or_walk_group(self.h, _ptr(phi), _ptr(acc), _ptr(nint))
-        else:
-            sel = np.ascontiguousarray(blocks, dtype=np.int64)
-            nc = 512 * sel.size
-            phi, acc, nint = np.empty(nc), np.empty((3, nc)), np.empty(sel.size, np.int64)
-            lib().or_walk_group_blocks(self.h, sel.size, _ptr(sel), _ptr(phi), _ptr(acc), _ptr(nint))
+    def walk_group(self, blocks=None, columns=False):
+        """Group walk over all leaf blocks or a subset.  Returns phi [n*512],
+        acc [3, n*512], nint [n]; with columns also npix [n, Npix, 512] and
+        tau [n*512]."""
+        sel = np.arange(self.nb) if blocks is None else np.asarray(blocks)
+        sel = np.ascontiguousarray(sel, dtype=np.int64)
+        nc = 512 * sel.size
+        phi, acc, nint = np.empty(nc), np.empty((3, nc)), np.empty(sel.size, np.int64)
+        npix = tau = None
+        if columns:
+            npx = 12 * self.params.nside ** 2
+            npix, tau = np.empty((sel.size, npx, 512)), np.empty(nc)
+        lib().or_walk_group_blocks(self.h, sel.size, _ptr(sel), _ptr(phi), _ptr(acc), _ptr(npix),
+                                   _ptr(tau), _ptr(nint))
+        if columns:
+            return phi, acc, nint, npix, tau
         return phi, acc, nint
+
+    def raymarch(self, target, nside, nside_f=16):
+        """Reference column map of one cell: mean over the Nside_f pixel-centre
+        rays in each coarse pixel of exact integrals of rho through the cells."""
+        out = np.empty(12 * nside * nside)
+        lib().or_raymarch(self.h, _ptr(self.rho), int(target), int(nside), int(nside_f), _ptr(out))
+        return out
 
     def walk_percell(self, targets):
         tg = np.ascontiguousarray(targets, dtype=np.int64)
@@ -218,3 +251,24 @@ def itilde(s, zeta, gam):
     out = np.empty(3)
     lib().or_itilde(float(s), float(zeta), float(gam), _ptr(out))
     return out
+
+
+def vec2pix(nside, v):
+    v = np.atleast_2d(v)
+    return np.array([lib().or_healpix_vec2pix(int(nside), *map(float, x)) for x in v], np.int64)
+
+
+def pix2ang(nside, p):
+    out = np.empty(2)
+    lib().or_healpix_pix2ang(int(nside), int(p), _ptr(out))
+    return out  # z, phi
+
+
+def raytable(nside, il_ntheta=25, il_nphi=50, il_npsi=25, il_nr=50, il_nazi=100, psi_max=0.98):
+    """Node-ray intersection table (compressed rows): off [ne+1], pix [n], w [n]."""
+    args = [int(nside), il_ntheta, il_nphi, il_npsi, il_nr, il_nazi, float(psi_max)]
+    n = lib().or_raytable_export(*args, None, None, None)
+    ne = il_ntheta * il_nphi * il_npsi
+    off, pix, w = np.empty(ne + 1, np.int64), np.empty(n, np.int32), np.empty(n)
+    lib().or_raytable_export(*args, _ptr(off), _ptr(pix), _ptr(w))
+    return off, pix, w

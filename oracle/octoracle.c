@@ -311,6 +311,9 @@ or_tree *or_tree_new(const or_params *p, int64_t nb, const int32_t *level,
     or_ewald_setup(&t->ew, bct, t->box, p->ew_alpha, rc, fc, p->ew_n > 1 ? p->ew_n : 64,
                    p->ewald == 1);
   }
+  if (p->nside > 0)
+    or_raytable_build(&t->rt, p->nside, p->il_ntheta, p->il_nphi, p->il_npsi, p->il_nr,
+                      p->il_nazi, p->psi_max);
   if (rho) {
     t->rho = rho;
     t->M = (double *)malloc(sizeof(double) * t->nn);
@@ -327,6 +330,7 @@ void or_tree_free(or_tree *t) {
   free(t->blev); free(t->bcoord); free(t->alev); free(t->acoord); free(t->akey);
   free(t->aleaf); free(t->achild); free(t->roots); free(t->M); free(t->S); free(t->com);
   or_ewald_release(&t->ew);
+  if (t->rt.off) or_raytable_free(&t->rt);
   free(t);
 }
 int64_t or_tree_na(const or_tree *t) { return t->na; }
@@ -446,10 +450,18 @@ static void pair_kernel(const or_tree *t, const double d[3], double *phi, double
   or_ewald_total(t, d, phi, A);
 }
 
-/* potential and acceleration at cell (lb, ci) from a list of nodes */
+/* potential and acceleration at a target point x from a list of nodes and,
+ * if cols != NULL, the column density map of the point (Sec. 2.3): every
+ * node adds w M / (Omega_pix d^2) to the pixels its table entry lists. */
 static void sum_list(const or_tree *t, const double x[3], const int64_t *ids, int64_t n,
-                     double *phi_out, double acc_out[3]) {
+                     double *phi_out, double acc_out[3], double *cols) {
   nsum ph = {0, 0}, ac[3] = {{0, 0}, {0, 0}, {0, 0}};
+  const or_raytable *T = &t->rt;
+  double omega = 0.0;
+  if (cols) {
+    omega = 4.0 * M_PI / (double)T->npix;
+    for (int p = 0; p < T->npix; ++p) cols[p] = 0.0;
+  }
   for (int64_t q = 0; q < n; ++q) {
     int64_t id = ids[q];
     double d[3];
@@ -461,9 +473,26 @@ static void sum_list(const or_tree *t, const double x[3], const int64_t *ids, in
     double GM = t->p.G * t->M[id];
     nadd(&ph, -GM * phi);
     for (int k = 0; k < 3; ++k) nadd(&ac[k], -GM * A[k]);
+    if (cols) {
+      double dist = sqrt(r2);
+      if (dist > t->p.max_dist) continue;
+      double h, gc[3];
+      or_node_geom(t, id, &h, gc);
+      double v[3] = {-d[0], -d[1], -d[2]};
+      int64_t e = or_raytable_entry(T, v, dist, h);
+      double base = t->M[id] / (omega * r2);
+      for (int64_t j = T->off[e]; j < T->off[e + 1]; ++j) cols[T->pix[j]] += T->w[j] * base;
+    }
   }
   *phi_out = nval(&ph);
   for (int k = 0; k < 3; ++k) acc_out[k] = nval(&ac[k]);
+}
+
+/* tau_avg = -ln( mean_p exp(-kappa N_p) ), Eq. (A_V) in generic form */
+static double tau_avg(const or_tree *t, const double *cols) {
+  double s = 0.0;
+  for (int p = 0; p < t->rt.npix; ++p) s += exp(-t->p.kappa * cols[p]);
+  return -log(s / (double)t->rt.npix);
 }
 
 void or_cell_centre(const or_tree *t, int64_t lb, int ci, double x[3]) {
@@ -472,43 +501,41 @@ void or_cell_centre(const or_tree *t, int64_t lb, int ci, double x[3]) {
   for (int k = 0; k < 3; ++k) x[k] = gc[k];
 }
 
-/* Group walk (one interaction list per leaf block, closest-point MAC).
- * phi [nb*512], acc [3][nb*512], nint [nb] (list lengths). */
-void or_walk_group(const or_tree *t, double *phi, double *acc, int64_t *nint) {
-  int64_t nb = t->nb, ncell = 512 * nb;
-#pragma omp parallel for schedule(dynamic, 1)
-  for (int64_t lb = 0; lb < nb; ++lb) {
-    idlist l = group_list(t, lb);
-    if (nint) nint[lb] = l.n;
-    for (int ci = 0; ci < 512; ++ci) {
-      double x[3], ph, a[3];
-      or_cell_centre(t, lb, ci, x);
-      sum_list(t, x, l.v, l.n, &ph, a);
-      phi[512 * lb + ci] = ph;
-      for (int k = 0; k < 3; ++k) acc[k * ncell + 512 * lb + ci] = a[k];
-    }
-    free(l.v);
-  }
-}
-
-/* Same, for a subset of leaf blocks; outputs are [nsel*512] / [3][nsel*512]. */
+/* Group walk (one interaction list per leaf block, closest-point MAC) over a
+ * subset of leaf blocks.  Outputs: phi [nsel*512], acc [3][nsel*512], and
+ * with columns on npix [nsel][Npix][512], tau [nsel*512]; nint [nsel]. */
 void or_walk_group_blocks(const or_tree *t, int64_t nsel, const int64_t *sel, double *phi,
-                          double *acc, int64_t *nint) {
+                          double *acc, double *npix, double *tau, int64_t *nint) {
   int64_t ncell = 512 * nsel;
+  int cols = npix && t->rt.off;
+  int np = cols ? t->rt.npix : 0;
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t q = 0; q < nsel; ++q) {
     int64_t lb = sel[q];
     idlist l = group_list(t, lb);
     if (nint) nint[q] = l.n;
+    double *map = cols ? (double *)malloc(sizeof(double) * np) : NULL;
     for (int ci = 0; ci < 512; ++ci) {
       double x[3], ph, a[3];
       or_cell_centre(t, lb, ci, x);
-      sum_list(t, x, l.v, l.n, &ph, a);
+      sum_list(t, x, l.v, l.n, &ph, a, map);
       phi[512 * q + ci] = ph;
       for (int k = 0; k < 3; ++k) acc[k * ncell + 512 * q + ci] = a[k];
+      if (cols) {
+        for (int p = 0; p < np; ++p) npix[(q * np + p) * 512 + ci] = map[p];
+        if (tau) tau[512 * q + ci] = tau_avg(t, map);
+      }
     }
+    free(map);
     free(l.v);
   }
+}
+
+void or_walk_group(const or_tree *t, double *phi, double *acc, int64_t *nint) {
+  int64_t *sel = (int64_t *)malloc(sizeof(int64_t) * t->nb);
+  for (int64_t b = 0; b < t->nb; ++b) sel[b] = b;
+  or_walk_group_blocks(t, t->nb, sel, phi, acc, NULL, NULL, nint);
+  free(sel);
 }
 
 /* Paper-literal walk: one depth-first traversal per target cell (point MAC).
@@ -523,7 +550,7 @@ void or_walk_percell(const or_tree *t, int64_t ntg, const int64_t *tg, double *p
     or_cell_centre(t, lb, ci, x);
     idlist l = {0, 0, 0};
     for (int64_t r = 0; r < t->nroots; ++r) visit(t, t->roots[r], x, 0.0, &l);
-    sum_list(t, x, l.v, l.n, &ph, a);
+    sum_list(t, x, l.v, l.n, &ph, a, NULL);
     phi[q] = ph;
     for (int k = 0; k < 3; ++k) acc[k * ntg + q] = a[k];
     if (nint) nint[q] = l.n;

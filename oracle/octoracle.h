@@ -29,6 +29,15 @@ typedef struct {
   int32_t ew_fcut2;   /* Fourier cut-off |l|^2 (<= 0: 10)                    */
   int32_t pad_;
   double ew_alpha;    /* Ewald splitting alpha (<= 0: 2 / Lx)               */
+  int32_t nside;      /* HEALPix Nside of the column maps; 0 = no columns   */
+  int32_t il_ntheta;  /* intersection table: theta bins                      */
+  int32_t il_nphi;    /*                     phi bins                        */
+  int32_t il_npsi;    /*                     angular-size bins               */
+  int32_t il_nr;      /*                     disc sample radii               */
+  int32_t il_nazi;    /*                     disc sample azimuths            */
+  double kappa;       /* opacity in tau_avg = -ln <exp(-kappa N)>            */
+  double max_dist;    /* columns only from nodes closer than this            */
+  double psi_max;     /* upper edge of the psi bins                          */
 } or_params;
 
 typedef struct or_tree or_tree;

@@ -18,6 +18,20 @@ typedef struct {
   double *tab;          /* [n][n][n][10]: phi_c, A_c (3), H_c (xx,yy,zz,xy,xz,yz) */
 } or_ewald;
 
+/* radius of the sphere with the volume of a unit cube, (3 / (4 pi))^(1/3) */
+#define OR_REQ 0.6203504908994001
+
+/* node-ray intersection table, compressed rows: entry e = (itheta * nphi +
+ * iphi) * npsi + ipsi owns pixels pix[off[e] .. off[e+1]) with weights w */
+typedef struct {
+  int nside, npix, ntheta, nphi, npsi, nr, nazi;
+  double psimax, dtheta, dphi, dpsi;
+  int64_t nentries;
+  int64_t *off;
+  int32_t *pix;
+  double *w;
+} or_raytable;
+
 struct or_tree {
   or_params p;
   int bctype;
@@ -35,6 +49,7 @@ struct or_tree {
   const double *rho; /* only during construction */
   double *M, *S, *com;
   or_ewald ew;
+  or_raytable rt;
 };
 
 uint64_t or_morton(uint64_t x, uint64_t y, uint64_t z);
@@ -58,4 +73,12 @@ void or_ewald_release(or_ewald *e);
 void or_ewald_series(const or_ewald *e, const double d[3], int correction, double *phi,
                      double A[3], double H[6]);
 void or_ewald_total(const or_tree *t, const double d[3], double *phi, double A[3]);
+
+/* columns */
+int64_t or_vec2pix_nest(int64_t nside, double x, double y, double z);
+void or_pix2ang_nest(int64_t nside, int64_t p, double *z, double *phi);
+int or_raytable_build(or_raytable *T, int nside, int ntheta, int nphi, int npsi, int nr,
+                      int nazi, double psimax);
+void or_raytable_free(or_raytable *T);
+int64_t or_raytable_entry(const or_raytable *T, const double v[3], double d, double h);
 #endif
