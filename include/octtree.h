@@ -75,6 +75,19 @@ typedef struct {
   int32_t device;        /* HIP device ordinal                                  [0]    */
   double ewald_alpha;    /* Ewald splitting constant; <= 0: 2 / Lx (Sec. 2.2.2) [0]    */
   uint64_t max_device_bytes; /* cap on library allocations; 0 = none           [0]    */
+  /* column densities (OpticalDepth module, Sec. 2.3; App. B tr_* parameters) */
+  int32_t nside;         /* HEALPix Nside of the per-cell maps: 1, 2 or 4
+                            (N_pix = 12 Nside^2: 12, 48, 192); 0 = no columns  [0]    */
+  int32_t il_ntheta;     /* node-ray table: theta bins (tr_ilNTheta)            [25]   */
+  int32_t il_nphi;       /*                 phi bins (tr_ilNPhi)                [50]   */
+  int32_t il_npsi;       /*                 angular-size bins (tr_ilNNS)        [25]   */
+  int32_t il_nr;         /*                 disc sample radii (tr_ilNR)         [50]   */
+  int32_t il_nazi;       /*                 disc sample azimuths                [100]  */
+  double theta_pix;      /* with columns a node must also pass BH at this angle
+                            (Sec. 2.3: theta_lim ~ sqrt(Omega_pix)); <= 0: 1/Nside [0] */
+  double kappa;          /* opacity in tau_avg = -ln <exp(-kappa N_p)>_p       [1]    */
+  double max_dist;       /* columns only from nodes closer (tr_bhMaxDist)       [1e99] */
+  double psi_max;        /* upper edge of the angular-size bins (rad)          [0.98] */
 } ot_params;
 
 /* Run statistics of the last solve. */
@@ -108,18 +121,23 @@ ot_status ot_set_blocks(ot_ctx *c, int64_t nb, const int32_t *level_host,
  * (OT_ERR_NUMERIC otherwise, checked on the device). */
 ot_status ot_build(ot_ctx *c, const double *rho_dev, void *stream);
 
-/* Tree walk, Sec. 2.1 + 2.2: one interaction list per leaf block (all its
- * cells share it; a node is accepted when the safe box and the MAC hold at
- * the block's closest cell centre), then per cell
+/* Tree walk, Sec. 2.1 + 2.2 + 2.3: one interaction list per leaf block (all
+ * its cells share it; a node is accepted when the safe box and the MAC hold
+ * at the block's closest cell centre, and with columns also BH at
+ * theta_pix), then per cell
  *   Phi = -G sum M phi(d),  a = -G sum M A(d),  d = r - r_a,
- * phi = 1/|d| (isolated) or the Ewald kernel (periodic / mixed).
- * ot_solve: FP32 arithmetic with compensated (Kahan) summation of Phi.
- * ot_solve64: FP64 throughout.  phi_dev [nb*512], acc_dev [3*nb*512].
+ * phi = 1/|d| (isolated) or the Ewald kernel (periodic / mixed), and with
+ * nside > 0 the column map N_p = sum w_p M / (Omega_pix |d|^2) over the
+ * node-ray table's pixels w_p of each node and tau_avg = -ln <exp(-kappa N_p)>.
+ * ot_solve: FP32 arithmetic with compensated (Kahan) summation of Phi;
+ * ot_solve64: FP64 throughout.  Direction bins are decided in FP64 in both.
+ * phi_dev [nb*512], acc_dev [3*nb*512]; npix_dev [nb][N_pix][512] and
+ * tau_dev [nb*512] are required when nside > 0 and ignored otherwise.
  * stats_host may be NULL. */
-ot_status ot_solve(ot_ctx *c, float *phi_dev, float *acc_dev, ot_stats *stats_host,
-                   void *stream);
-ot_status ot_solve64(ot_ctx *c, double *phi_dev, double *acc_dev, ot_stats *stats_host,
-                     void *stream);
+ot_status ot_solve(ot_ctx *c, float *phi_dev, float *acc_dev, float *npix_dev, float *tau_dev,
+                   ot_stats *stats_host, void *stream);
+ot_status ot_solve64(ot_ctx *c, double *phi_dev, double *acc_dev, double *npix_dev,
+                     double *tau_dev, ot_stats *stats_host, void *stream);
 
 /* Ewald correction table, Sec. 2.2.4 (second approach): phi_c = phi - 1/r,
  * A_c = A - d/r^3 and the six second derivatives of phi_c, FP64, on a
@@ -146,6 +164,12 @@ ot_status ot_export_list(ot_ctx *c, int64_t b, int32_t *ids_host, int64_t cap, i
 /* Ewald table (n^3 x 10 doubles, x fastest; channels phi_c, A_c[3],
  * H_xx, H_yy, H_zz, H_xy, H_xz, H_yz) after ot_ewald_prepare. */
 ot_status ot_export_ewald_table(ot_ctx *c, double *tab_host);
+/* Node-ray intersection table (Sec. 2.3), built on the device on first use:
+ * entry e = (itheta * nphi + iphi) * npsi + ipsi owns pixels
+ * pix[off[e] .. off[e+1]) (ascending) with weights w summing to 1.  Call with
+ * NULL arrays to get the sizes: *nentries and *npairs. */
+ot_status ot_export_raytable(ot_ctx *c, int64_t *nentries, int64_t *npairs, int64_t *off_host,
+                             int32_t *pix_host, double *w_host, void *stream);
 
 const char *ot_last_error(const ot_ctx *c); /* owned by ctx; valid until the next call */
 void ot_destroy(ot_ctx *c);

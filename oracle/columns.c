@@ -202,7 +202,10 @@ void or_raytable_free(or_raytable *T) {
 
 /* table entry of a node seen from the target at offset v = r_a - r (|v| = d) */
 int64_t or_raytable_entry(const or_raytable *T, const double v[3], double d, double h) {
-  double th = acos(v[2] / d);
+  double q = v[2] / d; /* |q| <= 1 up to rounding */
+  if (q > 1.0) q = 1.0;
+  if (q < -1.0) q = -1.0;
+  double th = acos(q);
   double ph = atan2(v[1], v[0]);
   if (ph < 0.0) ph += 2.0 * M_PI;
   int it = (int)floor(th / T->dtheta);

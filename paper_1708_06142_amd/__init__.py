@@ -35,7 +35,11 @@ class Params(C.Structure):
                 ("eta_sb", C.c_double), ("mac", C.c_int32), ("ewald", C.c_int32),
                 ("a_lim", C.c_double), ("eps_lim", C.c_double), ("ewald_n", C.c_int32),
                 ("ewald_rcut2", C.c_int32), ("ewald_fcut2", C.c_int32), ("device", C.c_int32),
-                ("ewald_alpha", C.c_double), ("max_device_bytes", C.c_uint64)]
+                ("ewald_alpha", C.c_double), ("max_device_bytes", C.c_uint64),
+                ("nside", C.c_int32), ("il_ntheta", C.c_int32), ("il_nphi", C.c_int32),
+                ("il_npsi", C.c_int32), ("il_nr", C.c_int32), ("il_nazi", C.c_int32),
+                ("theta_pix", C.c_double), ("kappa", C.c_double), ("max_dist", C.c_double),
+                ("psi_max", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -62,8 +66,9 @@ def lib():
         L.ot_create.argtypes = [C.POINTER(Params), C.POINTER(vp)]
         L.ot_set_blocks.argtypes = [vp, i64, vp, vp]
         L.ot_build.argtypes = [vp, vp, vp]
-        L.ot_solve.argtypes = [vp, vp, vp, C.POINTER(Stats), vp]
-        L.ot_solve64.argtypes = [vp, vp, vp, C.POINTER(Stats), vp]
+        L.ot_solve.argtypes = [vp, vp, vp, vp, vp, C.POINTER(Stats), vp]
+        L.ot_solve64.argtypes = [vp, vp, vp, vp, vp, C.POINTER(Stats), vp]
+        L.ot_export_raytable.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), vp, vp, vp, vp]
         L.ot_ewald_prepare.argtypes = [vp, vp]
         L.ot_num_amr_nodes.restype = i64
         L.ot_num_amr_nodes.argtypes = [vp]
@@ -76,7 +81,7 @@ def lib():
         L.ot_destroy.argtypes = [vp]
         for name in ("ot_create", "ot_set_blocks", "ot_build", "ot_solve", "ot_solve64",
                      "ot_ewald_prepare", "ot_export_topology", "ot_export_moments",
-                     "ot_export_list", "ot_export_ewald_table"):
+                     "ot_export_list", "ot_export_ewald_table", "ot_export_raytable"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -113,7 +118,7 @@ MAC = {"bh": 0, "ape": 1}
 def make_params(nroot=(1, 1, 1), root_size=1.0, origin=(0.0, 0.0, 0.0), bc=(0, 0, 0), G=1.0,
                 theta=0.5, eta_sb=1.2, mac="bh", a_lim=0.0, eps_lim=1e-3, ewald="table",
                 ewald_n=64, ewald_rcut2=0, ewald_fcut2=0, ewald_alpha=0.0, device=0,
-                max_device_bytes=0):
+                max_device_bytes=0, nside=0, theta_pix=0.0, kappa=1.0, max_dist=1e99, **table):
     p = Params()
     lib().ot_params_default(C.byref(p))
     for k in range(3):
@@ -124,6 +129,11 @@ def make_params(nroot=(1, 1, 1), root_size=1.0, origin=(0.0, 0.0, 0.0), bc=(0, 0
     p.a_lim, p.eps_lim = float(a_lim), float(eps_lim)
     p.ewald_n, p.ewald_rcut2, p.ewald_fcut2 = int(ewald_n), int(ewald_rcut2), int(ewald_fcut2)
     p.ewald_alpha, p.device, p.max_device_bytes = float(ewald_alpha), int(device), int(max_device_bytes)
+    p.nside, p.theta_pix, p.kappa, p.max_dist = int(nside), float(theta_pix), float(kappa), float(max_dist)
+    for k, v in table.items():
+        if k not in ("il_ntheta", "il_nphi", "il_npsi", "il_nr", "il_nazi", "psi_max"):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(p, k, v)
     return p
 
 
@@ -174,19 +184,30 @@ class Solver:
         import torch
         self._check(lib().ot_build(self.h, _dev_ptr(rho, torch.float64), _stream(stream)))
 
-    def solve(self, phi, acc, stream=None):
+    def solve(self, phi, acc, npix=None, tau=None, stream=None):
         import torch
         st = Stats()
-        self._check(lib().ot_solve(self.h, _dev_ptr(phi, torch.float32), _dev_ptr(acc, torch.float32),
-                                   C.byref(st), _stream(stream)))
+        f = torch.float32
+        self._check(lib().ot_solve(self.h, _dev_ptr(phi, f), _dev_ptr(acc, f), _dev_ptr(npix, f),
+                                   _dev_ptr(tau, f), C.byref(st), _stream(stream)))
         return st
 
-    def solve64(self, phi, acc, stream=None):
+    def solve64(self, phi, acc, npix=None, tau=None, stream=None):
         import torch
         st = Stats()
-        self._check(lib().ot_solve64(self.h, _dev_ptr(phi, torch.float64), _dev_ptr(acc, torch.float64),
-                                     C.byref(st), _stream(stream)))
+        f = torch.float64
+        self._check(lib().ot_solve64(self.h, _dev_ptr(phi, f), _dev_ptr(acc, f), _dev_ptr(npix, f),
+                                     _dev_ptr(tau, f), C.byref(st), _stream(stream)))
         return st
+
+    def export_raytable(self, stream=None):
+        ne, npairs = C.c_int64(0), C.c_int64(0)
+        self._check(lib().ot_export_raytable(self.h, C.byref(ne), C.byref(npairs), None, None, None,
+                                             _stream(stream)))
+        off, pix, w = np.empty(ne.value + 1, np.int64), np.empty(npairs.value, np.int32), np.empty(npairs.value)
+        self._check(lib().ot_export_raytable(self.h, C.byref(ne), C.byref(npairs), _np_ptr(off), _np_ptr(pix),
+                                             _np_ptr(w), _stream(stream)))
+        return off, pix, w
 
     def ewald_prepare(self, stream=None):
         self._check(lib().ot_ewald_prepare(self.h, _stream(stream)))
@@ -221,8 +242,9 @@ class Solver:
         return tab
 
 
-def run(grid, fp64=False, stream=None, **kw):
-    """Convenience: build + solve on cuda:0; returns (phi, acc, stats) as torch tensors."""
+def run(grid, fp64=False, stream=None, columns=False, **kw):
+    """Convenience: build + solve on cuda:0.  Returns (phi, acc [3, n], stats,
+    solver), plus (npix [nb, N_pix, 512], tau) when the solver has nside > 0."""
     import torch
     s = Solver.for_grid(grid, **kw)
     rho = torch.from_numpy(np.ascontiguousarray(grid.rho.reshape(-1))).to("cuda")
@@ -230,5 +252,12 @@ def run(grid, fp64=False, stream=None, **kw):
     dt = torch.float64 if fp64 else torch.float32
     phi = torch.empty(grid.nb * 512, dtype=dt, device="cuda")
     acc = torch.empty(3 * grid.nb * 512, dtype=dt, device="cuda")
-    st = (s.solve64 if fp64 else s.solve)(phi, acc, stream)
+    npix = tau = None
+    if s.params.nside:
+        npx = 12 * s.params.nside ** 2
+        npix = torch.empty(grid.nb * npx * 512, dtype=dt, device="cuda")
+        tau = torch.empty(grid.nb * 512, dtype=dt, device="cuda")
+    st = (s.solve64 if fp64 else s.solve)(phi, acc, npix, tau, stream)
+    if s.params.nside:
+        return phi, acc.view(3, -1), st, s, npix.view(grid.nb, -1, 512), tau
     return phi, acc.view(3, -1), st, s

@@ -20,6 +20,7 @@ SOURCES = {
     "k_list.hip": ["-ffp-contract=off"],
     "k_eval.hip": [],
     "k_ewald.hip": [],
+    "k_columns.hip": [],
 }
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

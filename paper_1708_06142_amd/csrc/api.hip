@@ -174,8 +174,89 @@ ot_status ewald_prepare(ot_ctx *c, hipStream_t st) {
   return OT_OK;
 }
 
+int npix_of(const ot_ctx *c) { return 12 * c->p.nside * c->p.nside; }
+
+ot::RayTableP raytable_desc(const ot_ctx *c) {
+  ot::RayTableP P;
+  P.nside = c->p.nside;
+  P.npix = npix_of(c);
+  P.ntheta = c->p.il_ntheta;
+  P.nphi = c->p.il_nphi;
+  P.npsi = c->p.il_npsi;
+  P.nr = c->p.il_nr;
+  P.nazi = c->p.il_nazi;
+  P.nentries = (int64_t)P.ntheta * P.nphi * P.npsi;
+  P.dtheta = M_PI / (double)P.ntheta;
+  P.dphi = (2.0 * M_PI) / (double)P.nphi;
+  P.dpsi = c->p.psi_max / (double)P.npsi;
+  return P;
+}
+
+ot_status raytable_prepare(ot_ctx *c, hipStream_t st) {
+  if (c->p.nside <= 0) return fail(c, OT_ERR_STATE, "columns are off (nside = 0)");
+  if (c->rt_ready) return OT_OK;
+  HIPCHK(hipSetDevice(c->p.device));
+  const ot::RayTableP RP = raytable_desc(c);
+  DevBuf dense, cnt;
+  ot_status s = dalloc(c, dense, (size_t)RP.nentries * RP.npix * sizeof(double));
+  if (s == OT_OK) s = dalloc(c, cnt, (size_t)RP.nentries * sizeof(int32_t));
+  if (s == OT_OK) s = dalloc(c, c->rt_off, (size_t)(RP.nentries + 1) * sizeof(int64_t));
+  int64_t total = 0;
+  hipError_t e = hipSuccess;
+  if (s == OT_OK)
+    e = ot::launch_raytable(RP, P<double>(dense), P<int32_t>(cnt), P<int64_t>(c->rt_off), nullptr, nullptr,
+                            nullptr, &total, st);
+  if (s == OT_OK && e == hipSuccess) {
+    s = dalloc(c, c->rt_pix, (size_t)total * sizeof(uint16_t));
+    if (s == OT_OK) s = dalloc(c, c->rt_w64, (size_t)total * sizeof(double));
+    if (s == OT_OK) s = dalloc(c, c->rt_w32, (size_t)total * sizeof(float));
+    if (s == OT_OK) {
+      // the row counts were scanned by the sizing pass; fill from the same dense table
+      e = ot::launch_raytable(RP, P<double>(dense), P<int32_t>(cnt), P<int64_t>(c->rt_off),
+                              P<uint16_t>(c->rt_pix), P<double>(c->rt_w64), P<float>(c->rt_w32), &total, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+  }
+  release(c, dense);
+  release(c, cnt);
+  if (s != OT_OK) return s;
+  if (e != hipSuccess) return dev_fail(c, e, "node-ray table");
+  c->rt_pairs = total;
+  c->rt_ready = true;
+  return OT_OK;
+}
+
+ot::ColP col_params(ot_ctx *c) {
+  ot::ColP C;
+  const ot::RayTableP RP = raytable_desc(c);
+  C.npix = RP.npix;
+  C.ntheta = RP.ntheta;
+  C.nphi = RP.nphi;
+  C.npsi = RP.npsi;
+  C.dtheta = RP.dtheta;
+  C.dphi = RP.dphi;
+  C.dpsi = RP.dpsi;
+  C.req = 0.6203504908994001;  // (3 / (4 pi))^(1/3)
+  C.omega = 4.0 * M_PI / (double)RP.npix;
+  C.kappa = c->p.kappa;
+  C.max_dist = c->p.max_dist;
+  C.off = P<int64_t>(c->rt_off);
+  C.pix = P<uint16_t>(c->rt_pix);
+  C.w64 = P<double>(c->rt_w64);
+  C.w32 = P<float>(c->rt_w32);
+  return C;
+}
+
+// cells per workgroup of the column walk: the per-cell maps must fit in LDS
+int cols_cpw(const ot_ctx *c, bool fp64) {
+  for (int cpw : {256, 128, 64})
+    if (ot::cols_smem_bytes(npix_of(c), cpw, fp64) <= 65536) return cpw;
+  if (ot::cols_smem_bytes(npix_of(c), 64, fp64) <= 160 * 1024) return 64;
+  return 0;
+}
+
 // Interaction lists for the given MAC: count, scan, fill.
-ot_status build_lists(ot_ctx *c, const ot::MacP &mp, hipStream_t st) {
+ot_status build_lists(ot_ctx *c, const ot::MacP &mp, bool sizes, hipStream_t st) {
   const ot::Topology &t = c->topo;
   ot::DevTree T = dev_tree(c);
   int64_t capA = 0;
@@ -188,29 +269,31 @@ ot_status build_lists(ot_ctx *c, const ot::MacP &mp, hipStream_t st) {
   OTCHK(dalloc(c, c->lcount, t.nb * sizeof(int32_t)));
   OTCHK(dalloc(c, c->loff, (t.nb + 1) * sizeof(int64_t)));
   HIPCHK(ot::launch_lists(false, T, mp, (int)grid, P<int32_t>(c->lcount), nullptr, nullptr, nullptr,
-                          P<int32_t>(c->lscratch), stride, capA, st));
+                          nullptr, P<int32_t>(c->lscratch), stride, capA, st));
   HIPCHK(ot::launch_scan(P<int32_t>(c->lcount), t.nb, P<int64_t>(c->loff), st));
   int64_t total = 0;
   HIPCHK(hipMemcpyAsync(&total, P<int64_t>(c->loff) + t.nb, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   OTCHK(dalloc(c, c->lrec, (size_t)total * sizeof(double4)));
   OTCHK(dalloc(c, c->lid, (size_t)total * sizeof(int32_t)));
+  if (sizes) OTCHK(dalloc(c, c->lh, (size_t)total * sizeof(double)));
   HIPCHK(ot::launch_lists(true, T, mp, (int)grid, P<int32_t>(c->lcount), P<int64_t>(c->loff),
-                          P<double4>(c->lrec), P<int32_t>(c->lid), P<int32_t>(c->lscratch), stride,
-                          capA, st));
+                          P<double4>(c->lrec), P<int32_t>(c->lid), sizes ? P<double>(c->lh) : nullptr,
+                          P<int32_t>(c->lscratch), stride, capA, st));
   c->list_cap = total;
   return OT_OK;
 }
 
-ot::MacP mac_params(const ot_ctx *c, int mac, double a_lim) {
+ot::MacP mac_params(const ot_ctx *c, int mac, double a_lim, bool cols) {
   ot::MacP m;
   m.theta2 = c->p.theta_lim * c->p.theta_lim;
   m.half_eta = 0.5 * c->p.eta_sb;
   m.G = c->p.G;
   m.a_lim = a_lim;
-  m.tpix2 = 0.0;
+  const double tp = c->p.theta_pix > 0 ? c->p.theta_pix : 1.0 / (double)(c->p.nside > 0 ? c->p.nside : 1);
+  m.tpix2 = tp * tp;
   m.mac = mac;
-  m.use_pix = 0;
+  m.use_pix = cols ? 1 : 0;
   return m;
 }
 
@@ -221,7 +304,7 @@ ot_status ape_limit(ot_ctx *c, hipStream_t st, double *alim) {
     return OT_OK;
   }
   if (!c->alim_valid) {
-    OTCHK(build_lists(c, mac_params(c, OT_MAC_BH, 0.0), st));
+    OTCHK(build_lists(c, mac_params(c, OT_MAC_BH, 0.0, false), false, st));
     const int64_t ncell = c->topo.nb * 512;
     DevBuf phi, acc, mx;
     OTCHK(dalloc(c, phi, ncell * sizeof(double)));
@@ -259,10 +342,13 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
   return ms;
 }
 
-ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, ot_stats *stats, void *stream) {
+ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, void *tau, ot_stats *stats,
+                     void *stream) {
   if (!c) return OT_ERR_INVALID_ARG;
   c->err.clear();
   if (!phi || !acc) return fail(c, OT_ERR_INVALID_ARG, "phi and acc must be device pointers");
+  const bool cols = c->p.nside > 0;
+  if (cols && (!npix || !tau)) return fail(c, OT_ERR_INVALID_ARG, "nside > 0 needs npix and tau outputs");
   if (!c->built) return fail(c, OT_ERR_STATE, "ot_solve before a successful ot_build");
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(c->p.device));
@@ -271,16 +357,22 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, ot_stats *stats
       return fail(c, OT_ERR_UNSUPPORTED, "per-pair exact Ewald series is not built into the walk");
     OTCHK(ewald_prepare(c, st));
   }
+  if (cols) OTCHK(raytable_prepare(c, st));
   double alim = 0.0;
   if (c->p.mac == OT_MAC_APE) OTCHK(ape_limit(c, st, &alim));
   for (int i = 0; i < 4; ++i)
     if (!c->ev[i]) HIPCHK(hipEventCreate(&c->ev[i]));
   HIPCHK(hipEventRecord(c->ev[0], st));
-  OTCHK(build_lists(c, mac_params(c, c->p.mac, alim), st));
+  OTCHK(build_lists(c, mac_params(c, c->p.mac, alim, cols), cols, st));
   HIPCHK(hipEventRecord(c->ev[1], st));
   ot::DevTree T = dev_tree(c);
   ot::EwaldP E = ewald_desc(c);
-  if (fp64)
+  if (cols) {
+    const int cpw = cols_cpw(c, fp64);
+    if (!cpw) return fail(c, OT_ERR_UNSUPPORTED, "column maps do not fit in LDS");
+    HIPCHK(ot::launch_eval_cols(fp64, T, E, col_params(c), P<int64_t>(c->loff), P<double4>(c->lrec),
+                                P<double>(c->lh), phi, acc, npix, tau, c->p.G, cpw, st));
+  } else if (fp64)
     HIPCHK(ot::launch_eval64(T, E, P<int64_t>(c->loff), P<double4>(c->lrec), (double *)phi,
                              (double *)acc, c->p.G, st));
   else
@@ -325,6 +417,16 @@ void ot_params_default(ot_params *p) {
   p->eps_lim = 1e-3;
   p->ewald_n = 64;
   p->device = 0;
+  p->nside = 0;
+  p->il_ntheta = 25;
+  p->il_nphi = 50;
+  p->il_npsi = 25;
+  p->il_nr = 50;
+  p->il_nazi = 100;
+  p->theta_pix = 0.0;
+  p->kappa = 1.0;
+  p->max_dist = 1e99;
+  p->psi_max = 0.98;
 }
 
 ot_status ot_create(const ot_params *p, ot_ctx **out) {
@@ -354,6 +456,14 @@ ot_status ot_create(const ot_params *p, ot_ctx **out) {
   if (p->ewald != OT_EWALD_TABLE && p->ewald != OT_EWALD_EXACT) return bad("unknown Ewald mode");
   if (p->mac == OT_MAC_APE && !(p->a_lim > 0) && !(p->eps_lim > 0)) return bad("APE needs a_lim > 0 or eps_lim > 0");
   if (p->ewald_n < 2 || p->ewald_n > 512) return bad("ewald_n must be in [2, 512]");
+  if (p->nside != 0 && p->nside != 1 && p->nside != 2 && p->nside != 4) return bad("nside must be 0, 1, 2 or 4");
+  if (p->nside) {
+    if (p->il_ntheta < 1 || p->il_nphi < 1 || p->il_npsi < 1 || p->il_nr < 1 || p->il_nazi < 1)
+      return bad("intersection-table sizes must be >= 1");
+    if (p->il_nr > 256 || (int64_t)p->il_nr * p->il_nazi > 8192)
+      return bad("intersection table: il_nr <= 256 and il_nr * il_nazi <= 8192");
+    if (!(p->psi_max > 0) || !(p->kappa >= 0) || !(p->max_dist > 0)) return bad("bad column parameters");
+  }
   const int nper = p->bc[0] + p->bc[1] + p->bc[2];
   if (nper == 0) c->bctype = ot::BC_ISO;
   else if (nper == 3) c->bctype = ot::BC_3P;
@@ -412,12 +522,32 @@ ot_status ot_build(ot_ctx *c, const double *rho, void *stream) {
   return OT_OK;
 }
 
-ot_status ot_solve(ot_ctx *c, float *phi, float *acc, ot_stats *stats, void *stream) {
-  return solve_impl(c, false, phi, acc, stats, stream);
+ot_status ot_solve(ot_ctx *c, float *phi, float *acc, float *npix, float *tau, ot_stats *stats,
+                   void *stream) {
+  return solve_impl(c, false, phi, acc, npix, tau, stats, stream);
 }
 
-ot_status ot_solve64(ot_ctx *c, double *phi, double *acc, ot_stats *stats, void *stream) {
-  return solve_impl(c, true, phi, acc, stats, stream);
+ot_status ot_solve64(ot_ctx *c, double *phi, double *acc, double *npix, double *tau, ot_stats *stats,
+                     void *stream) {
+  return solve_impl(c, true, phi, acc, npix, tau, stats, stream);
+}
+
+ot_status ot_export_raytable(ot_ctx *c, int64_t *nentries, int64_t *npairs, int64_t *off, int32_t *pix,
+                             double *w, void *stream) {
+  if (!c) return OT_ERR_INVALID_ARG;
+  c->err.clear();
+  OTCHK(raytable_prepare(c, (hipStream_t)stream));
+  const ot::RayTableP RP = raytable_desc(c);
+  if (nentries) *nentries = RP.nentries;
+  if (npairs) *npairs = c->rt_pairs;
+  if (off) HIPCHK(hipMemcpy(off, c->rt_off.ptr, (RP.nentries + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+  if (w) HIPCHK(hipMemcpy(w, c->rt_w64.ptr, c->rt_pairs * sizeof(double), hipMemcpyDeviceToHost));
+  if (pix) {
+    std::vector<uint16_t> p16(c->rt_pairs);
+    HIPCHK(hipMemcpy(p16.data(), c->rt_pix.ptr, c->rt_pairs * sizeof(uint16_t), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < c->rt_pairs; ++i) pix[i] = p16[i];
+  }
+  return OT_OK;
 }
 
 ot_status ot_ewald_prepare(ot_ctx *c, void *stream) {
@@ -512,7 +642,7 @@ void ot_destroy(ot_ctx *c) {
   DevBuf *all[] = {&c->alev, &c->acoord, &c->achild0, &c->aleaf, &c->blev,   &c->bcoord,
                    &c->bamr, &c->amc,    &c->aS,      &c->btmc,  &c->cm,     &c->flag,
                    &c->lcount, &c->loff, &c->lrec,    &c->lid,   &c->lscratch, &c->tab64,
-                   &c->tab32};
+                   &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_w32, &c->lh};
   for (DevBuf *b : all) release(c, *b);
   for (int i = 0; i < 4; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);

@@ -1,0 +1,416 @@
+// Column densities (OpticalDepth module, Sec. 2.3) on the device.
+//
+// 1. HEALPix NESTED pixel of a direction (Gorski et al. 2005 construction:
+//    12 base pixels, polar caps above |z| = 2/3, equatorial belt between).
+// 2. Node-ray intersection table: for each (theta, phi, psi) bin centre, a
+//    uniform sphere of angular radius psi is sampled on nr radii x nazi
+//    azimuths (weight sqrt(1 - (b/psi)^2) sin b); each sample is assigned at
+//    Nside_f = 2 Nside (the paper's oversampling) and coarsened to its NESTED
+//    parent; per-pixel weights are normalised to 1 and stored as compressed
+//    rows (pixels ascending).  One wave per entry: lanes fill the sample pixels
+//    into LDS, then each lane sums its own pixels over the samples in order,
+//    so the sums are deterministic.
+// 3. Column walk: like the gravity walk, plus for every (cell, node) pair the
+//    direction bins (FP64), the table row, and N_p += w M / (Omega_pix d^2) in
+//    a per-cell pixel map held in LDS as [pixel][cell] (each thread owns its
+//    cell's column: no atomics, no bank conflicts).  At the end each cell's map
+//    and tau_avg = -ln(mean_p exp(-kappa N_p)) are written out.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace ot {
+
+namespace {
+
+constexpr double PI = 3.14159265358979323846;
+
+__device__ inline int64_t spread2(int64_t v) {
+  int64_t r = 0;
+  for (int b = 0; b < 16; ++b) r |= ((v >> b) & 1) << (2 * b);
+  return r;
+}
+
+// NESTED pixel of direction (x, y, z), any positive length
+__device__ inline int vec2pix_nest(int nside, double x, double y, double z) {
+  const double s2 = x * x + y * y;
+  const double r = sqrt(s2 + z * z);
+  const double zn = z / r;
+  const double za = fabs(zn);
+  double phi = atan2(y, x);
+  if (phi < 0.0) phi += 2.0 * PI;
+  double tt = phi / (0.5 * PI);
+  if (tt >= 4.0) tt = 0.0;
+  int face, ix, iy;
+  if (za <= 2.0 / 3.0) {
+    const double t1 = (double)nside * (0.5 + tt);
+    const double t2 = (double)nside * (zn * 0.75);
+    const int jp = (int)(t1 - t2), jm = (int)(t1 + t2);
+    const int ifp = jp / nside, ifm = jm / nside;
+    face = ifp == ifm ? (ifp & 3) + 4 : (ifp < ifm ? (ifp & 3) : (ifm & 3) + 8);
+    ix = jm & (nside - 1);
+    iy = nside - (jp & (nside - 1)) - 1;
+  } else {
+    int ntt = (int)tt;
+    ntt = ntt > 3 ? 3 : ntt;
+    const double tp = tt - (double)ntt;
+    const double one_minus = s2 / (r * (r + fabs(z)));  // 1 - |z| without cancellation
+    const double tmp = (double)nside * sqrt(3.0 * one_minus);
+    int jp = (int)(tp * tmp), jm = (int)((1.0 - tp) * tmp);
+    jp = jp > nside - 1 ? nside - 1 : jp;
+    jm = jm > nside - 1 ? nside - 1 : jm;
+    if (zn >= 0) {
+      face = ntt;
+      ix = nside - jm - 1;
+      iy = nside - jp - 1;
+    } else {
+      face = ntt + 8;
+      ix = jp;
+      iy = jm;
+    }
+  }
+  return face * nside * nside + (int)(spread2(ix) | (spread2(iy) << 1));
+}
+
+constexpr int RT_MAXS = 8192;  // samples per entry
+constexpr int RT_MAXR = 256;   // radii
+constexpr int RT_MAXP = 768;   // pixels (Nside <= 8)
+
+__global__ __launch_bounds__(64) void k_raytable_dense(RayTableP P, double *__restrict__ dense) {
+  __shared__ short spix[RT_MAXS];
+  __shared__ double swr[RT_MAXR];
+  __shared__ double sw[RT_MAXP];
+  __shared__ double stot;
+  const int e = blockIdx.x, lane = threadIdx.x;
+  const int it = e / (P.nphi * P.npsi), ip = (e / P.npsi) % P.nphi, is = e % P.npsi;
+  const double th = ((double)it + 0.5) * P.dtheta;
+  const double ph = ((double)ip + 0.5) * P.dphi;
+  const double ps = ((double)is + 0.5) * P.dpsi;
+  const double st = sin(th), ct = cos(th), sp = sin(ph), cp = cos(ph);
+  const double c[3] = {st * cp, st * sp, ct};
+  const double et[3] = {ct * cp, ct * sp, -st};
+  const double ep[3] = {-sp, cp, 0.0};
+  const int ns = P.nr * P.nazi;
+  const double dal = (2.0 * PI) / (double)P.nazi;
+  for (int j = lane; j < ns; j += 64) {
+    const int r = j / P.nazi, a = j % P.nazi;
+    const double u = ((double)r + 0.5) / (double)P.nr;
+    const double b = u * ps;
+    const double cb = cos(b), sb = sin(b);
+    const double al = ((double)a + 0.5) * dal;
+    const double ca = cos(al), sa = sin(al);
+    double n[3];
+    for (int k = 0; k < 3; ++k) n[k] = cb * c[k] + sb * (ca * et[k] + sa * ep[k]);
+    spix[j] = (short)(vec2pix_nest(2 * P.nside, n[0], n[1], n[2]) >> 2);
+  }
+  for (int r = lane; r < P.nr; r += 64) {
+    const double u = ((double)r + 0.5) / (double)P.nr;
+    swr[r] = sqrt(1.0 - u * u) * sin(u * ps);
+  }
+  __syncthreads();
+  for (int p = lane; p < P.npix; p += 64) {
+    double acc = 0.0;
+    for (int r = 0; r < P.nr; ++r) {
+      const double w = swr[r];
+      for (int a = 0; a < P.nazi; ++a)
+        if (spix[r * P.nazi + a] == p) acc += w;
+    }
+    sw[p] = acc;
+  }
+  __syncthreads();
+  if (lane == 0) {
+    double tot = 0.0;
+    for (int p = 0; p < P.npix; ++p) tot += sw[p];
+    stot = tot;
+  }
+  __syncthreads();
+  for (int p = lane; p < P.npix; p += 64) dense[(int64_t)e * P.npix + p] = sw[p] / stot;
+}
+
+__global__ void k_raytable_count(RayTableP P, const double *__restrict__ dense, int32_t *__restrict__ cnt) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= P.nentries) return;
+  int n = 0;
+  for (int p = 0; p < P.npix; ++p) n += dense[(int64_t)e * P.npix + p] > 0.0;
+  cnt[e] = n;
+}
+
+__global__ void k_raytable_fill(RayTableP P, const double *__restrict__ dense, const int64_t *__restrict__ off,
+                                uint16_t *__restrict__ pix, double *__restrict__ w64, float *__restrict__ w32) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= P.nentries) return;
+  int64_t o = off[e];
+  for (int p = 0; p < P.npix; ++p) {
+    const double v = dense[(int64_t)e * P.npix + p];
+    if (v > 0.0) {
+      pix[o] = (uint16_t)p;
+      w64[o] = v;
+      w32[o] = (float)v;
+      ++o;
+    }
+  }
+}
+
+// ------------------------------------------------------------- column walk
+constexpr int TILE = 128;
+
+template <typename Real>
+struct ColAcc {
+  Real s, c, ax, ay, az;
+};
+
+// table row of a node at offset v = r_a - r (|v| = d, node size h)
+__device__ inline int clampi(int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); }
+
+__device__ inline int table_row(const ColP &C, double vx, double vy, double vz, double d, double h) {
+  double q = vz / d;
+  q = q > 1.0 ? 1.0 : (q < -1.0 ? -1.0 : q);
+  const double th = acos(q);
+  double ph = atan2(vy, vx);
+  if (ph < 0.0) ph += 2.0 * PI;
+  const int it = clampi((int)floor(th / C.dtheta), C.ntheta - 1);
+  const int ip = clampi((int)floor(ph / C.dphi), C.nphi - 1);
+  const double s = C.req * h / d;
+  const double ps = s >= 1.0 ? 0.5 * PI : asin(s);
+  const int is = clampi((int)floor(ps / C.dpsi), C.npsi - 1);
+  return (it * C.nphi + ip) * C.npsi + is;
+}
+
+template <int BC>
+__device__ inline void wrap3(const EwaldP &E, double &dx, double &dy, double &dz) {
+  if (BC != 0) {
+    dx = dx - E.L[0] * floor(dx / E.L[0] + 0.5);
+    dy = dy - E.L[1] * floor(dy / E.L[1] + 0.5);
+    if (BC == 1) dz = dz - E.L[2] * floor(dz / E.L[2] + 0.5);
+  }
+}
+
+// gravity kernel of one pair in FP64 (isolated or table Ewald); returns false
+// for the target cell itself
+template <int BC>
+__device__ inline bool grav64(const EwaldP &E, double dx, double dy, double dz, double r2, double &phi,
+                              double &A0, double &A1, double &A2) {
+  const double inv = 1.0 / sqrt(r2);
+  const double inv3 = inv * inv * inv;
+  if (BC == 0) {
+    phi = inv;
+    A0 = dx * inv3;
+    A1 = dy * inv3;
+    A2 = dz * inv3;
+    return true;
+  }
+  if (BC == 2 && fabs(dz) > E.zfar) {
+    phi = E.far_phi_a * fabs(dz) + E.far_phi_b;
+    A0 = 0.0;
+    A1 = 0.0;
+    A2 = dz < 0 ? -E.far_az : E.far_az;
+    return true;
+  }
+  const double u[3] = {fabs(dx), fabs(dy), fabs(dz)};
+  int g[3];
+  double dl[3];
+  for (int k = 0; k < 3; ++k) {
+    int gi = (int)floor(u[k] / E.step[k] + 0.5);
+    gi = gi > E.n - 1 ? E.n - 1 : gi;
+    g[k] = gi;
+    dl[k] = u[k] - gi * E.step[k];
+  }
+  const double *T = E.tab64 + 10 * (((int64_t)g[2] * E.n + g[1]) * E.n + g[0]);
+  const double phic = T[0] - (T[1] * dl[0] + T[2] * dl[1] + T[3] * dl[2]);
+  const double a0 = T[1] - (T[4] * dl[0] + T[7] * dl[1] + T[8] * dl[2]);
+  const double a1 = T[2] - (T[7] * dl[0] + T[5] * dl[1] + T[9] * dl[2]);
+  const double a2 = T[3] - (T[8] * dl[0] + T[9] * dl[1] + T[6] * dl[2]);
+  phi = inv + phic;
+  A0 = dx * inv3 + (dx < 0 ? -a0 : a0);
+  A1 = dy * inv3 + (dy < 0 ? -a1 : a1);
+  A2 = dz * inv3 + (dz < 0 ? -a2 : a2);
+  return true;
+}
+
+// FP32 gravity of one pair (same forms as the FP32 walk)
+template <int BC>
+__device__ inline void grav32(const EwaldP &E, float dx, float dy, float dz, float &phi, float &A0, float &A1,
+                              float &A2) {
+  const float r2 = dx * dx + dy * dy + dz * dz;
+  const float inv = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+  const float inv3 = inv * inv * inv;
+  if (BC == 0) {
+    phi = inv;
+    A0 = dx * inv3;
+    A1 = dy * inv3;
+    A2 = dz * inv3;
+    return;
+  }
+  if (BC == 2 && fabsf(dz) > (float)E.zfar) {
+    phi = (float)E.far_phi_a * fabsf(dz) + (float)E.far_phi_b;
+    A0 = 0.0f;
+    A1 = 0.0f;
+    A2 = dz < 0 ? -(float)E.far_az : (float)E.far_az;
+    return;
+  }
+  const float u0 = fabsf(dx), u1 = fabsf(dy), u2 = fabsf(dz);
+  const int g0 = min((int)(u0 * (float)E.inv_step[0] + 0.5f), E.n - 1);
+  const int g1 = min((int)(u1 * (float)E.inv_step[1] + 0.5f), E.n - 1);
+  const int g2 = min((int)(u2 * (float)E.inv_step[2] + 0.5f), E.n - 1);
+  const float d0 = u0 - g0 * (float)E.step[0];
+  const float d1 = u1 - g1 * (float)E.step[1];
+  const float d2 = u2 - g2 * (float)E.step[2];
+  const float4 *p = E.tab32 + 3 * (((int64_t)g2 * E.n + g1) * E.n + g0);
+  const float4 q0 = p[0], q1 = p[1], q2 = p[2];
+  const float phic = q0.x - (q0.y * d0 + q0.z * d1 + q0.w * d2);
+  const float a0 = q0.y - (q1.x * d0 + q1.w * d1 + q2.x * d2);
+  const float a1 = q0.z - (q1.w * d0 + q1.y * d1 + q2.y * d2);
+  const float a2 = q0.w - (q2.x * d0 + q2.y * d1 + q1.z * d2);
+  phi = inv + phic;
+  A0 = dx * inv3 + (dx < 0 ? -a0 : a0);
+  A1 = dy * inv3 + (dy < 0 ? -a1 : a1);
+  A2 = dz * inv3 + (dz < 0 ? -a2 : a2);
+}
+
+// One workgroup handles cpw cells (one per thread) of one leaf block.
+template <typename Real, int BC>
+__global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, const int64_t *__restrict__ off,
+                                                   const double4 *__restrict__ rec, const double *__restrict__ lh,
+                                                   Real *__restrict__ phi, Real *__restrict__ acc,
+                                                   Real *__restrict__ npix, Real *__restrict__ tau, double negG,
+                                                   int cpw) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double4 *tile = reinterpret_cast<double4 *>(smem);
+  double *tileh = reinterpret_cast<double *>(smem + TILE * sizeof(double4));
+  Real *map = reinterpret_cast<Real *>(smem + TILE * (sizeof(double4) + sizeof(double)));
+  const int nchunk = 512 / cpw;
+  const int64_t b = blockIdx.x / nchunk;
+  const int tid = threadIdx.x;
+  const int ci = (int)(blockIdx.x % nchunk) * cpw + tid;
+  const int64_t ncell = T.nb * 512;
+  const double h = size_at(T.root_size, T.blev[b]) / 8.0;
+  const double cx = ((double)(ci & 7) - 3.5) * h;
+  const double cy = ((double)((ci >> 3) & 7) - 3.5) * h;
+  const double cz = ((double)(ci >> 6) - 3.5) * h;
+  const float fx = (float)cx, fy = (float)cy, fz = (float)cz;
+  for (int p = 0; p < C.npix; ++p) map[p * cpw + tid] = (Real)0;
+  // potential: FP64 sum (FP64 walk) or Kahan-compensated FP32 (FP32 walk)
+  Real s = 0, cmp = 0, ax = 0, ay = 0, az = 0;
+  const int64_t start = off[b], n = off[b + 1] - start;
+  for (int64_t t0 = 0; t0 < n; t0 += TILE) {
+    __syncthreads();
+    for (int q = tid; q < TILE && t0 + q < n; q += cpw) {
+      tile[q] = rec[start + t0 + q];
+      tileh[q] = lh[start + t0 + q];
+    }
+    __syncthreads();
+    const int m = (int)(n - t0 < TILE ? n - t0 : TILE);
+    for (int j = 0; j < m; ++j) {
+      const double4 r = tile[j];
+      double dx = cx - r.x, dy = cy - r.y, dz = cz - r.z;
+      wrap3<BC>(E, dx, dy, dz);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 == 0.0) continue;  // the target cell itself
+      // gravity
+      if (sizeof(Real) == 8) {
+        double ph, A0, A1, A2;
+        grav64<BC>(E, dx, dy, dz, r2, ph, A0, A1, A2);
+        s += (Real)(r.w * ph);
+        ax += (Real)(r.w * A0);
+        ay += (Real)(r.w * A1);
+        az += (Real)(r.w * A2);
+      } else {
+        float gx = fx - (float)r.x, gy = fy - (float)r.y, gz = fz - (float)r.z;
+        if (BC != 0) {
+          const float Lx = (float)E.L[0], Ly = (float)E.L[1];
+          gx = gx - Lx * floorf(gx / Lx + 0.5f);
+          gy = gy - Ly * floorf(gy / Ly + 0.5f);
+          if (BC == 1) {
+            const float Lz = (float)E.L[2];
+            gz = gz - Lz * floorf(gz / Lz + 0.5f);
+          }
+        }
+        float ph, A0, A1, A2;
+        grav32<BC>(E, gx, gy, gz, ph, A0, A1, A2);
+        const float m32 = (float)r.w;
+        const float y = m32 * ph - (float)cmp;
+        const float tt = (float)s + y;
+        cmp = (Real)((tt - (float)s) - y);
+        s = (Real)tt;
+        ax += (Real)(m32 * A0);
+        ay += (Real)(m32 * A1);
+        az += (Real)(m32 * A2);
+      }
+      // columns
+      const double d = sqrt(r2);
+      if (d > C.max_dist) continue;
+      const int e = table_row(C, -dx, -dy, -dz, d, tileh[j]);
+      const double base = r.w / (C.omega * r2);
+      const int64_t o0 = C.off[e], o1 = C.off[e + 1];
+      for (int64_t o = o0; o < o1; ++o) {
+        const int p = C.pix[o];
+        if (sizeof(Real) == 8) map[p * cpw + tid] += (Real)(C.w64[o] * base);
+        else map[p * cpw + tid] += (Real)((float)C.w32[o] * (float)base);
+      }
+    }
+  }
+  const int64_t o = b * 512 + ci;
+  phi[o] = (Real)(negG * (double)(s - cmp));
+  acc[o] = (Real)(negG * (double)ax);
+  acc[ncell + o] = (Real)(negG * (double)ay);
+  acc[2 * ncell + o] = (Real)(negG * (double)az);
+  double se = 0.0;
+  for (int p = 0; p < C.npix; ++p) {
+    const Real v = map[p * cpw + tid];
+    npix[(b * C.npix + p) * 512 + ci] = v;
+    se += exp(-C.kappa * (double)v);
+  }
+  tau[o] = (Real)(-log(se / (double)C.npix));
+}
+
+}  // namespace
+
+hipError_t launch_raytable(const RayTableP &P, double *dense, int32_t *cnt, int64_t *off, uint16_t *pix,
+                           double *w64, float *w32, int64_t *total, hipStream_t st) {
+  hipLaunchKernelGGL(k_raytable_dense, dim3((unsigned)P.nentries), dim3(64), 0, st, P, dense);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned nb = (unsigned)((P.nentries + 255) / 256);
+  hipLaunchKernelGGL(k_raytable_count, dim3(nb), dim3(256), 0, st, P, dense, cnt);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_scan(cnt, P.nentries, off, st)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(total, off + P.nentries, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
+    return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  if (!pix) return hipSuccess;  // sizing pass
+  hipLaunchKernelGGL(k_raytable_fill, dim3(nb), dim3(256), 0, st, P, dense, off, pix, w64, w32);
+  return hipGetLastError();
+}
+
+size_t cols_smem_bytes(int npix, int cpw, bool fp64) {
+  return TILE * (sizeof(double4) + sizeof(double)) + (size_t)npix * cpw * (fp64 ? 8 : 4);
+}
+
+hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const ColP &C, const int64_t *off,
+                            const double4 *rec, const double *lh, void *phi, void *acc, void *npix, void *tau,
+                            double G, int cpw, hipStream_t st) {
+  const size_t sm = cols_smem_bytes(C.npix, cpw, fp64);
+  dim3 grid((unsigned)(T.nb * (512 / cpw))), blk(cpw);
+#define OT_LAUNCH(R, B)                                                                                       \
+  do {                                                                                                        \
+    if (sm > 65536) {                                                                                         \
+      hipError_t ea = hipFuncSetAttribute((const void *)k_eval_cols<R, B>,                                   \
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);              \
+      if (ea != hipSuccess) return ea;                                                                        \
+    }                                                                                                         \
+    hipLaunchKernelGGL((k_eval_cols<R, B>), grid, blk, sm, st, T, E, C, off, rec, lh, (R *)phi, (R *)acc,  \
+                       (R *)npix, (R *)tau, -G, cpw);                                                        \
+  } while (0)
+  if (fp64) {
+    if (E.bctype == 0) OT_LAUNCH(double, 0);
+    else if (E.bctype == 1) OT_LAUNCH(double, 1);
+    else OT_LAUNCH(double, 2);
+  } else {
+    if (E.bctype == 0) OT_LAUNCH(float, 0);
+    else if (E.bctype == 1) OT_LAUNCH(float, 1);
+    else OT_LAUNCH(float, 2);
+  }
+#undef OT_LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace ot

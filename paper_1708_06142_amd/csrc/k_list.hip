@@ -89,8 +89,9 @@ __device__ inline Scan3 scan3(bool f0, bool f1, bool f2, int (*swave)[NW]) {
 
 template <bool FILL>
 __device__ inline void emit(const DevTree &T, const Target &tg, int64_t pos, int32_t id,
-                            const double4 mc, double4 *rec, int32_t *ids) {
+                            const double4 mc, double h, double4 *rec, int32_t *ids, double *lh) {
   if (!FILL) return;
+  if (lh) lh[pos] = h;
   double4 r;
   r.x = wrap_axis(mc.x - tg.c[0], T.L[0], T.per[0]);
   r.y = wrap_axis(mc.y - tg.c[1], T.L[1], T.per[1]);
@@ -104,6 +105,7 @@ template <bool FILL>
 __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__restrict__ count,
                                               const int64_t *__restrict__ off,
                                               double4 *__restrict__ rec, int32_t *__restrict__ ids,
+                                              double *__restrict__ lh,
                                               int32_t *__restrict__ scratch, int64_t stride,
                                               int64_t capA) {
   __shared__ int swave[3][NW];
@@ -136,10 +138,11 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
         bool acc = false, oi = false, ol = false;
         int32_t node = -1;
         double4 mc = make_double4(0, 0, 0, 0);
+        double s = 0.0;
         if (i < ncur) {
           node = cur[i];
           const int lev = T.alev[node];
-          const double s = size_at(T.root_size, lev);
+          s = size_at(T.root_size, lev);
           double g[3];
           for (int k = 0; k < 3; ++k) g[k] = T.org[k] + ((double)T.acoord[3 * node + k] + 0.5) * s;
           mc = T.amc[node];
@@ -149,7 +152,7 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
           }
         }
         Scan3 sc = scan3(acc, oi, ol, swave);
-        if (acc) emit<FILL>(T, tg, base + nemit + sc.pre[0], node, mc, rec, ids);
+        if (acc) emit<FILL>(T, tg, base + nemit + sc.pre[0], node, mc, s, rec, ids, lh);
         if (oi) {
           int32_t c0 = T.achild0[node];
           for (int o = 0; o < 8; ++o) nxt[nnext + 8 * sc.pre[1] + o] = c0 + o;
@@ -174,10 +177,11 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
       bool acc = false, op = false;
       int32_t lb = 0, o1 = 0;
       double4 mc = make_double4(0, 0, 0, 0);
+      double s = 0.0;
       if (i < 8 * nolb) {
         lb = olb[i >> 3];
         o1 = (int)(i & 7);
-        const double s = size_at(T.root_size, T.blev[lb]) / 2.0;
+        s = size_at(T.root_size, T.blev[lb]) / 2.0;
         double g[3];
         for (int k = 0; k < 3; ++k) {
           int64_t pos = 2 * (int64_t)T.bcoord[3 * lb + k] + ((o1 >> k) & 1);
@@ -188,7 +192,8 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
         op = !acc;
       }
       Scan3 sc = scan3(acc, op, false, swave);
-      if (acc) emit<FILL>(T, tg, base + nemit + sc.pre[0], (int32_t)(na + 8 * (int64_t)lb + o1), mc, rec, ids);
+      if (acc)
+        emit<FILL>(T, tg, base + nemit + sc.pre[0], (int32_t)(na + 8 * (int64_t)lb + o1), mc, s, rec, ids, lh);
       if (op) op1[nop1 + sc.pre[1]] = lb * 8 + o1;
       nemit += sc.tot[0];
       nop1 += sc.tot[1];
@@ -201,12 +206,13 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
       bool acc = false, op = false;
       int32_t lb = 0, o1 = 0, o2 = 0;
       double4 mc = make_double4(0, 0, 0, 0);
+      double s = 0.0;
       if (i < 8 * nop1) {
         int32_t v = op1[i >> 3];
         lb = v >> 3;
         o1 = v & 7;
         o2 = (int)(i & 7);
-        const double s = size_at(T.root_size, T.blev[lb]) / 4.0;
+        s = size_at(T.root_size, T.blev[lb]) / 4.0;
         double g[3];
         for (int k = 0; k < 3; ++k) {
           int64_t pos = 4 * (int64_t)T.bcoord[3 * lb + k] + 2 * ((o1 >> k) & 1) + ((o2 >> k) & 1);
@@ -219,7 +225,7 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
       Scan3 sc = scan3(acc, op, false, swave);
       if (acc)
         emit<FILL>(T, tg, base + nemit + sc.pre[0],
-                   (int32_t)(na + 8 * nb + 64 * (int64_t)lb + 8 * o1 + o2), mc, rec, ids);
+                   (int32_t)(na + 8 * nb + 64 * (int64_t)lb + 8 * o1 + o2), mc, s, rec, ids, lh);
       if (op && FILL) {
         const int lev = T.blev[lb];
         const double h = size_at(T.root_size, lev) / 8.0;
@@ -245,6 +251,7 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
           r.w = T.cm[(int64_t)lb * 512 + ci];
           rec[p0 + o3] = r;
           ids[p0 + o3] = (int32_t)(na + 72 * nb + 512 * (int64_t)lb + ci);
+          if (lh) lh[p0 + o3] = h;
         }
       }
       nemit += sc.tot[0] + 8 * sc.tot[1];
@@ -284,13 +291,13 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ count
 }  // namespace
 
 hipError_t launch_lists(bool fill, const DevTree &T, const MacP &P, int grid, int32_t *count,
-                        const int64_t *off, double4 *rec, int32_t *ids, int32_t *scratch,
+                        const int64_t *off, double4 *rec, int32_t *ids, double *lh, int32_t *scratch,
                         int64_t stride, int64_t capA, hipStream_t st) {
   if (fill)
-    hipLaunchKernelGGL(k_lists<true>, dim3(grid), dim3(WG), 0, st, T, P, count, off, rec, ids,
+    hipLaunchKernelGGL(k_lists<true>, dim3(grid), dim3(WG), 0, st, T, P, count, off, rec, ids, lh,
                        scratch, stride, capA);
   else
-    hipLaunchKernelGGL(k_lists<false>, dim3(grid), dim3(WG), 0, st, T, P, count, off, rec, ids,
+    hipLaunchKernelGGL(k_lists<false>, dim3(grid), dim3(WG), 0, st, T, P, count, off, rec, ids, lh,
                        scratch, stride, capA);
   return hipGetLastError();
 }

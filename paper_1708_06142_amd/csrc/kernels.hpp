@@ -35,11 +35,39 @@ struct EwaldP {
   const float4 *tab32;   // [n^3][3] (12 floats: 10 used)
 };
 
+// Node-ray intersection table description (Sec. 2.3).
+struct RayTableP {
+  int nside, npix, ntheta, nphi, npsi, nr, nazi;
+  int64_t nentries;
+  double dtheta, dphi, dpsi;
+};
+
+// Column walk parameters: binning, table rows, map normalisation.
+struct ColP {
+  int npix, ntheta, nphi, npsi;
+  double dtheta, dphi, dpsi;
+  double req;       // (3 / (4 pi))^(1/3): equal-volume sphere radius per unit edge
+  double omega;     // 4 pi / N_pix
+  double kappa;     // opacity of tau_avg
+  double max_dist;  // columns only from nodes closer than this
+  const int64_t *off;
+  const uint16_t *pix;
+  const double *w64;
+  const float *w32;
+};
+
+hipError_t launch_raytable(const RayTableP &P, double *dense, int32_t *cnt, int64_t *off, uint16_t *pix,
+                           double *w64, float *w32, int64_t *total, hipStream_t st);
+size_t cols_smem_bytes(int npix, int cpw, bool fp64);
+hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const ColP &C, const int64_t *off,
+                            const double4 *rec, const double *lh, void *phi, void *acc, void *npix, void *tau,
+                            double G, int cpw, hipStream_t st);
+
 hipError_t launch_build(const DevTree &T, const double *rho, int *bad,
                         const std::vector<int64_t> &level_begin, int lmax, hipStream_t st);
 
 hipError_t launch_lists(bool fill, const DevTree &T, const MacP &P, int grid, int32_t *count,
-                        const int64_t *off, double4 *rec, int32_t *ids, int32_t *scratch,
+                        const int64_t *off, double4 *rec, int32_t *ids, double *lh, int32_t *scratch,
                         int64_t scratch_stride, int64_t capA, hipStream_t st);
 
 hipError_t launch_scan(const int32_t *count, int64_t nb, int64_t *off, hipStream_t st);

@@ -50,7 +50,7 @@ def test_call_order_and_grid_errors():
     s.set_blocks(g.level, g.coord)
     # solve before build
     L = ot.lib()
-    st = L.ot_solve(s.h, C.c_void_p(1), C.c_void_p(1), None, None)
+    st = L.ot_solve(s.h, C.c_void_p(1), C.c_void_p(1), None, None, None, None)
     assert st == ot.OT_ERR_STATE
     st = L.ot_export_list(s.h, 0, None, 0, C.byref(C.c_int64()))
     assert st == ot.OT_ERR_STATE
