@@ -4,9 +4,11 @@ Workload: 128^3 cells (4,096 blocks of 8^3) of lognormal density
 exp(1.5 delta - 1.125), delta a seeded P(k) ~ k^-4 Gaussian random field;
 isolated boundaries; APE MAC with a_lim = 1e-3 * max|a| (max|a| from one BH
 theta = 0.5 FP64 walk before timing, as the paper derives a_lim from the
-initial acceleration field).  A step is one pass of the whole path: tree
-build (moments), interaction lists, per-cell potential + acceleration in FP32
-with Kahan-compensated potential.  Inputs are resident in HBM before timing.
+initial acceleration field); with 48-direction column densities (HEALPix
+Nside 2), so a node is also required to pass BH at theta_pix = 0.5.  A step
+is one pass of the whole path: tree build (moments), interaction lists, per-cell
+potential + acceleration in FP32 with Kahan-compensated potential, and the
+per-cell column map + tau_avg.  Inputs are resident in HBM before timing.
 
 Prints one JSON line (see the design doc for the roofline and baseline notes).
 """
@@ -36,11 +38,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=128, help="cells per axis")
-    ap.add_argument("--cpu-blocks", type=int, default=4096, help="oracle sample size (blocks)")
+    ap.add_argument("--cpu-blocks", type=int, default=256, help="oracle sample size (blocks)")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB: one fill + one sum of that size before timing (HBM counter calibration)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--nside", type=int, default=2, help="HEALPix Nside of the column maps (0 = off)")
     return ap.parse_args()
 
 
@@ -64,7 +67,7 @@ def timed_steps(solver, rho, outs, fp64, steps, warmup):
     return dt / steps * 1e3, st, float(np.mean(evals)), float(np.mean(lists)), float(np.mean(builds))
 
 
-def cpu_baseline(grid, a_lim, nblk):
+def cpu_baseline(grid, a_lim, nblk, nside):
     """The FP64 oracle's group walk on a seeded sample of blocks, host cores."""
     import oracle
     threads = os.cpu_count() or 1
@@ -72,18 +75,19 @@ def cpu_baseline(grid, a_lim, nblk):
     nblk = min(nblk, grid.nb)
     sel = np.sort(np.random.default_rng(7).choice(grid.nb, nblk, replace=False))
     t0 = time.perf_counter()
-    t = oracle.Tree(grid, mac="ape", a_lim=a_lim)
+    t = oracle.Tree(grid, mac="ape", a_lim=a_lim, nside=nside)
     tb = time.perf_counter() - t0
     t0 = time.perf_counter()
-    t.walk_group(sel)
+    t.walk_group(sel, columns=nside > 0)
     tw = time.perf_counter() - t0
     cells = 512 * nblk
     # tree build is O(all cells): charge the sample its share
     sec = tw + tb * (nblk / grid.nb)
     return {"value": cells / sec, "unit": "cells/s", "cores": int(os.environ["OMP_NUM_THREADS"]),
             "kind": "oracle",
-            "sample": f"{nblk} seeded blocks ({cells} cells) of the same workload, APE same a_lim; "
-                      f"walk {tw:.2f} s + build share {tb * nblk / grid.nb:.3f} s"}
+            "sample": f"{nblk} seeded blocks ({cells} cells) of the same workload, APE same a_lim, "
+                      f"Nside {nside} columns; walk {tw:.2f} s + build share {tb * nblk / grid.nb:.3f} s "
+                      "(tree build includes the node-ray table)"}
 
 
 def main():
@@ -104,6 +108,7 @@ def main():
     grid = workloads.c2_lognormal(args.n)
     ncell = grid.ncells
     rho = torch.from_numpy(grid.rho.reshape(-1).copy()).cuda()
+    npx = 12 * args.nside ** 2
     s = ot.Solver.for_grid(grid, mac="ape", eps_lim=1e-3, theta=0.5)
     s.build(rho)
     phi = torch.empty(ncell, device="cuda", dtype=torch.float32)
@@ -111,9 +116,12 @@ def main():
     st0 = s.solve(phi, acc)  # derives a_lim from the BH pre-pass (untimed)
     a_lim = st0.a_lim_used
     s.close()
-    s = ot.Solver.for_grid(grid, mac="ape", a_lim=a_lim, theta=0.5)
+    s = ot.Solver.for_grid(grid, mac="ape", a_lim=a_lim, theta=0.5, nside=args.nside)
+    outs = (phi, acc)
+    if args.nside:
+        outs = (phi, acc, torch.empty(ncell * npx, device="cuda"), torch.empty(ncell, device="cuda"))
 
-    ms, st, ms_eval, ms_list, ms_build = timed_steps(s, rho, (phi, acc), False, args.steps, args.warmup)
+    ms, st, ms_eval, ms_list, ms_build = timed_steps(s, rho, outs, False, args.steps, args.warmup)
     value = ncell / (ms * 1e-3)
     flops = st.n_interactions * FLOP_PAIR_ISO
     achieved = flops / (ms_eval * 1e-3) / 1e12
@@ -123,24 +131,27 @@ def main():
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"lognormal {args.n}^3 (sigma_ln 1.5, P(k)~k^-4, seed 2), isolated, "
-                               "APE a_lim=1e-3 a_max, FP32-Kahan walk",
-                   "cells": ncell, "blocks": grid.nb, "a_lim": a_lim, "columns": 0},
+                               f"APE a_lim=1e-3 a_max, {npx}-pixel columns, FP32-Kahan walk",
+                   "cells": ncell, "blocks": grid.nb, "a_lim": a_lim, "columns": npx},
         "phases_ms": {"build": ms_build, "lists": ms_list, "eval": ms_eval},
         "interactions": {"n_int": st.n_interactions, "per_cell": st.n_interactions / ncell,
                          "max_list": st.max_list},
-        "roofline": {"bound": "alu", "kernel": "k_eval32 (isolated)", "achieved": achieved,
+        "roofline": {"bound": "alu", "kernel": "k_eval_cols<float> (isolated, columns)" if args.nside
+                     else "k_eval32 (isolated)", "achieved": achieved,
                      "peak": PEAK_FP32_VALU, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
                      "traffic": None, "flop_per_pair": FLOP_PAIR_ISO},
     }
     if not args.no_fp64:
-        phi64 = torch.empty(ncell, device="cuda", dtype=torch.float64)
-        acc64 = torch.empty(3 * ncell, device="cuda", dtype=torch.float64)
-        ms64, st64, e64, _, _ = timed_steps(s, rho, (phi64, acc64), True, max(2, args.steps // 2), 1)
+        f64 = dict(device="cuda", dtype=torch.float64)
+        outs64 = (torch.empty(ncell, **f64), torch.empty(3 * ncell, **f64))
+        if args.nside:
+            outs64 += (torch.empty(ncell * npx, **f64), torch.empty(ncell, **f64))
+        ms64, st64, e64, _, _ = timed_steps(s, rho, outs64, True, max(2, args.steps // 2), 1)
         a64 = st64.n_interactions * FLOP_PAIR_ISO / (e64 * 1e-3) / 1e12
         out["fp64_walk"] = {"value": ncell / (ms64 * 1e-3), "ms_per_step": ms64, "ms_eval": e64,
                             "achieved_tflops": a64, "frac_fp64_peak": a64 / PEAK_FP64_VALU}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(grid, a_lim, args.cpu_blocks)
+        out["cpu_baseline"] = cpu_baseline(grid, a_lim, args.cpu_blocks, args.nside)
     print(json.dumps(out))
 
 
