@@ -205,15 +205,35 @@ ot_status raytable_prepare(ot_ctx *c, hipStream_t st) {
   hipError_t e = hipSuccess;
   if (s == OT_OK)
     e = ot::launch_raytable(RP, P<double>(dense), P<int32_t>(cnt), P<int64_t>(c->rt_off), nullptr, nullptr,
-                            nullptr, &total, st);
+                            &total, st);
   if (s == OT_OK && e == hipSuccess) {
     s = dalloc(c, c->rt_pix, (size_t)total * sizeof(uint16_t));
     if (s == OT_OK) s = dalloc(c, c->rt_w64, (size_t)total * sizeof(double));
-    if (s == OT_OK) s = dalloc(c, c->rt_w32, (size_t)total * sizeof(float));
+    if (s == OT_OK) s = dalloc(c, c->rt_rows, (size_t)RP.nentries * sizeof(uint32_t));
+    if (s == OT_OK) s = dalloc(c, c->rt_ent, (size_t)total * sizeof(uint32_t));
+    if (s == OT_OK && total >= ((int64_t)1 << 26)) s = fail(c, OT_ERR_UNSUPPORTED, "node-ray table too large");
     if (s == OT_OK) {
-      // the row counts were scanned by the sizing pass; fill from the same dense table
+      // packed rows hold at most 63 pixels per entry
+      std::vector<int64_t> offh(RP.nentries + 1);
+      e = hipMemcpy(offh.data(), c->rt_off.ptr, offh.size() * sizeof(int64_t), hipMemcpyDeviceToHost);
+      for (int64_t q = 0; e == hipSuccess && s == OT_OK && q < RP.nentries; ++q)
+        if (offh[q + 1] - offh[q] > 63) s = fail(c, OT_ERR_UNSUPPORTED, "node-ray table row with > 63 pixels");
+    }
+    if (s == OT_OK) {
+      // the sizing pass is repeated (deterministic) and the rows are filled
       e = ot::launch_raytable(RP, P<double>(dense), P<int32_t>(cnt), P<int64_t>(c->rt_off),
-                              P<uint16_t>(c->rt_pix), P<double>(c->rt_w64), P<float>(c->rt_w32), &total, st);
+                              P<uint16_t>(c->rt_pix), P<double>(c->rt_w64), &total, st);
+      if (e == hipSuccess)
+        e = ot::launch_raytable_pack(RP, P<int64_t>(c->rt_off), P<uint16_t>(c->rt_pix), P<double>(c->rt_w64),
+                                     P<uint32_t>(c->rt_rows), P<uint32_t>(c->rt_ent), st);
+      // direction-bin thresholds: cos(k dtheta), sin(k dpsi), cos(k dphi), sin(k dphi)
+      std::vector<double> thr;
+      for (int k = 0; k < RP.ntheta; ++k) thr.push_back(std::cos(k * RP.dtheta));
+      for (int k = 0; k < RP.npsi; ++k) thr.push_back(std::sin(k * RP.dpsi));
+      for (int k = 0; k <= RP.nphi / 2; ++k) thr.push_back(std::cos(k * RP.dphi));
+      for (int k = 0; k <= RP.nphi / 2; ++k) thr.push_back(std::sin(k * RP.dphi));
+      if (e == hipSuccess && (s = dalloc(c, c->rt_thr, thr.size() * sizeof(double))) == OT_OK)
+        e = hipMemcpyAsync(c->rt_thr.ptr, thr.data(), thr.size() * sizeof(double), hipMemcpyHostToDevice, st);
       if (e == hipSuccess) e = hipStreamSynchronize(st);
     }
   }
@@ -240,18 +260,22 @@ ot::ColP col_params(ot_ctx *c) {
   C.omega = 4.0 * M_PI / (double)RP.npix;
   C.kappa = c->p.kappa;
   C.max_dist = c->p.max_dist;
-  C.off = P<int64_t>(c->rt_off);
+  C.nthr = RP.ntheta + RP.npsi + 2 * (RP.nphi / 2 + 1);
+  C.thr = P<double>(c->rt_thr);
+  C.rows = P<uint32_t>(c->rt_rows);
   C.pix = P<uint16_t>(c->rt_pix);
   C.w64 = P<double>(c->rt_w64);
-  C.w32 = P<float>(c->rt_w32);
+  C.ent = P<uint32_t>(c->rt_ent);
   return C;
 }
 
 // cells per workgroup of the column walk: the per-cell maps must fit in LDS
 int cols_cpw(const ot_ctx *c, bool fp64) {
+  const ot::RayTableP RP = raytable_desc(c);
+  const int nthr = RP.ntheta + RP.npsi + 2 * (RP.nphi / 2 + 1);
   for (int cpw : {256, 128, 64})
-    if (ot::cols_smem_bytes(npix_of(c), cpw, fp64) <= 65536) return cpw;
-  if (ot::cols_smem_bytes(npix_of(c), 64, fp64) <= 160 * 1024) return 64;
+    if (ot::cols_smem_bytes(npix_of(c), cpw, fp64, nthr) <= 65536) return cpw;
+  if (ot::cols_smem_bytes(npix_of(c), 64, fp64, nthr) <= 160 * 1024) return 64;
   return 0;
 }
 
@@ -376,8 +400,8 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
     HIPCHK(ot::launch_eval64(T, E, P<int64_t>(c->loff), P<double4>(c->lrec), (double *)phi,
                              (double *)acc, c->p.G, st));
   else
-    HIPCHK(ot::launch_eval32(T, E, P<int64_t>(c->loff), P<double4>(c->lrec), (float *)phi,
-                             (float *)acc, c->p.G, st));
+    HIPCHK(ot::launch_eval32(T, E, P<int64_t>(c->loff), P<double4>(c->lrec), P<int32_t>(c->lid),
+                             (float *)phi, (float *)acc, c->p.G, st));
   HIPCHK(hipEventRecord(c->ev[2], st));
   c->off_host.resize(c->topo.nb + 1);
   HIPCHK(hipMemcpyAsync(c->off_host.data(), c->loff.ptr, (c->topo.nb + 1) * sizeof(int64_t),
@@ -462,6 +486,8 @@ ot_status ot_create(const ot_params *p, ot_ctx **out) {
       return bad("intersection-table sizes must be >= 1");
     if (p->il_nr > 256 || (int64_t)p->il_nr * p->il_nazi > 8192)
       return bad("intersection table: il_nr <= 256 and il_nr * il_nazi <= 8192");
+    if (p->il_ntheta > 64 || p->il_npsi > 64 || p->il_nphi > 128 || (p->il_nphi & 1))
+      return bad("intersection table: ntheta, npsi <= 64 and an even nphi <= 128");
     if (!(p->psi_max > 0) || !(p->kappa >= 0) || !(p->max_dist > 0)) return bad("bad column parameters");
   }
   const int nper = p->bc[0] + p->bc[1] + p->bc[2];
@@ -642,7 +668,8 @@ void ot_destroy(ot_ctx *c) {
   DevBuf *all[] = {&c->alev, &c->acoord, &c->achild0, &c->aleaf, &c->blev,   &c->bcoord,
                    &c->bamr, &c->amc,    &c->aS,      &c->btmc,  &c->cm,     &c->flag,
                    &c->lcount, &c->loff, &c->lrec,    &c->lid,   &c->lscratch, &c->tab64,
-                   &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_w32, &c->lh};
+                   &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_rows, &c->rt_ent,
+                   &c->rt_thr, &c->lh};
   for (DevBuf *b : all) release(c, *b);
   for (int i = 0; i < 4; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);

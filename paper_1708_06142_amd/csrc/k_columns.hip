@@ -135,7 +135,7 @@ __global__ void k_raytable_count(RayTableP P, const double *__restrict__ dense, 
 }
 
 __global__ void k_raytable_fill(RayTableP P, const double *__restrict__ dense, const int64_t *__restrict__ off,
-                                uint16_t *__restrict__ pix, double *__restrict__ w64, float *__restrict__ w32) {
+                                uint16_t *__restrict__ pix, double *__restrict__ w64) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= P.nentries) return;
   int64_t o = off[e];
@@ -144,7 +144,6 @@ __global__ void k_raytable_fill(RayTableP P, const double *__restrict__ dense, c
     if (v > 0.0) {
       pix[o] = (uint16_t)p;
       w64[o] = v;
-      w32[o] = (float)v;
       ++o;
     }
   }
@@ -158,20 +157,49 @@ struct ColAcc {
   Real s, c, ax, ay, az;
 };
 
-// table row of a node at offset v = r_a - r (|v| = d, node size h)
 __device__ inline int clampi(int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); }
 
-__device__ inline int table_row(const ColP &C, double vx, double vy, double vz, double d, double h) {
-  double q = vz / d;
-  q = q > 1.0 ? 1.0 : (q < -1.0 ? -1.0 : q);
-  const double th = acos(q);
-  double ph = atan2(vy, vx);
-  if (ph < 0.0) ph += 2.0 * PI;
-  const int it = clampi((int)floor(th / C.dtheta), C.ntheta - 1);
-  const int ip = clampi((int)floor(ph / C.dphi), C.nphi - 1);
-  const double s = C.req * h / d;
-  const double ps = s >= 1.0 ? 0.5 * PI : asin(s);
-  const int is = clampi((int)floor(ps / C.dpsi), C.npsi - 1);
+// Largest k in [0, n-1] with pred(k), pred monotone (true up to some k) and
+// pred(0) taken as true; branch-free binary search for n <= 64.
+template <typename Pred>
+__device__ inline int last_true(int n, Pred pred) {
+  int k = 0;
+  for (int step = 32; step > 0; step >>= 1) {
+    const int c = k + step;
+    if (c <= n - 1 && pred(c)) k = c;
+  }
+  return k;
+}
+
+// Table row of a node at offset v = r_a - r from the target (|v| = d, node
+// size h).  The bins are those of floor(theta / dtheta), floor(phi / dphi)
+// and floor(psi / dpsi), decided without inverse trigonometric functions:
+//   theta >= k dtheta  <=>  v_z <= cos(k dtheta) d
+//   psi   >= k dpsi    <=>  R_eq h >= sin(k dpsi) d
+//   phi   >= k dphi    <=>  cos(k dphi) v_y - sin(k dphi) v_x >= 0   (0 < phi < pi)
+// with phi in (pi, 2 pi) mapped to the upper half-plane by v -> -v; v_y = 0
+// (exactly on the x axis) uses atan2 as written.  FP64 throughout.
+__device__ inline int table_row(const ColP &C, const double *thr, double vx, double vy, double vz,
+                                double d, double h) {
+  const double *cth = thr;                       // [ntheta]
+  const double *sps = thr + C.ntheta;            // [npsi]
+  const double *cph = sps + C.npsi;              // [nphi/2 + 1]
+  const double *sph = cph + (C.nphi / 2 + 1);
+  const int it = last_true(C.ntheta, [&](int k) { return vz <= cth[k] * d; });
+  const double rh = C.req * h;
+  const int is = last_true(C.npsi, [&](int k) { return rh >= sps[k] * d; });
+  int ip;
+  if (vy == 0.0) {
+    double ph = atan2(vy, vx);
+    if (ph < 0.0) ph += 2.0 * PI;
+    ip = clampi((int)floor(ph / C.dphi), C.nphi - 1);
+  } else {
+    const bool lower = vy < 0.0;
+    const double ux = lower ? -vx : vx, uy = lower ? -vy : vy;
+    const int half = C.nphi / 2;
+    const int k = last_true(half, [&](int q) { return cph[q] * uy - sph[q] * ux >= 0.0; });
+    ip = clampi((lower ? half : 0) + k, C.nphi - 1);
+  }
   return (it * C.nphi + ip) * C.npsi + is;
 }
 
@@ -276,17 +304,20 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
   extern __shared__ __align__(16) unsigned char smem[];
   double4 *tile = reinterpret_cast<double4 *>(smem);
   double *tileh = reinterpret_cast<double *>(smem + TILE * sizeof(double4));
-  Real *map = reinterpret_cast<Real *>(smem + TILE * (sizeof(double4) + sizeof(double)));
+  double *thr = tileh + TILE;
+  Real *map = reinterpret_cast<Real *>(thr + C.nthr);
   const int nchunk = 512 / cpw;
   const int64_t b = blockIdx.x / nchunk;
   const int tid = threadIdx.x;
   const int ci = (int)(blockIdx.x % nchunk) * cpw + tid;
   const int64_t ncell = T.nb * 512;
   const double h = size_at(T.root_size, T.blev[b]) / 8.0;
-  const double cx = ((double)(ci & 7) - 3.5) * h;
-  const double cy = ((double)((ci >> 3) & 7) - 3.5) * h;
-  const double cz = ((double)(ci >> 6) - 3.5) * h;
-  const float fx = (float)cx, fy = (float)cy, fz = (float)cz;
+  // absolute cell centre, the same expression as the records' cell centres
+  const double cx = T.org[0] + ((double)(8 * (int64_t)T.bcoord[3 * b] + (ci & 7)) + 0.5) * h;
+  const double cy = T.org[1] + ((double)(8 * (int64_t)T.bcoord[3 * b + 1] + ((ci >> 3) & 7)) + 0.5) * h;
+  const double cz = T.org[2] + ((double)(8 * (int64_t)T.bcoord[3 * b + 2] + (ci >> 6)) + 0.5) * h;
+  const float omega32 = (float)C.omega;
+  for (int q = tid; q < C.nthr; q += cpw) thr[q] = C.thr[q];
   for (int p = 0; p < C.npix; ++p) map[p * cpw + tid] = (Real)0;
   // potential: FP64 sum (FP64 walk) or Kahan-compensated FP32 (FP32 walk)
   Real s = 0, cmp = 0, ax = 0, ay = 0, az = 0;
@@ -305,7 +336,11 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
       wrap3<BC>(E, dx, dy, dz);
       const double r2 = dx * dx + dy * dy + dz * dz;
       if (r2 == 0.0) continue;  // the target cell itself
-      // gravity
+      const double d = sqrt(r2);
+      const bool col = d <= C.max_dist;
+      const int e = col ? table_row(C, thr, -dx, -dy, -dz, d, tileh[j]) : 0;
+      const uint32_t rd = C.rows[e];
+      const int o0 = (int)(rd >> 6), cnt = col ? (int)(rd & 63) : 0;
       if (sizeof(Real) == 8) {
         double ph, A0, A1, A2;
         grav64<BC>(E, dx, dy, dz, r2, ph, A0, A1, A2);
@@ -313,19 +348,12 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         ax += (Real)(r.w * A0);
         ay += (Real)(r.w * A1);
         az += (Real)(r.w * A2);
+        const double base = r.w / (C.omega * r2);
+        for (int o = o0; o < o0 + cnt; ++o) map[C.pix[o] * cpw + tid] += (Real)(C.w64[o] * base);
       } else {
-        float gx = fx - (float)r.x, gy = fy - (float)r.y, gz = fz - (float)r.z;
-        if (BC != 0) {
-          const float Lx = (float)E.L[0], Ly = (float)E.L[1];
-          gx = gx - Lx * floorf(gx / Lx + 0.5f);
-          gy = gy - Ly * floorf(gy / Ly + 0.5f);
-          if (BC == 1) {
-            const float Lz = (float)E.L[2];
-            gz = gz - Lz * floorf(gz / Lz + 0.5f);
-          }
-        }
+        // FP32 gravity from the FP64 offset (already the minimum image)
         float ph, A0, A1, A2;
-        grav32<BC>(E, gx, gy, gz, ph, A0, A1, A2);
+        grav32<BC>(E, (float)dx, (float)dy, (float)dz, ph, A0, A1, A2);
         const float m32 = (float)r.w;
         const float y = m32 * ph - (float)cmp;
         const float tt = (float)s + y;
@@ -334,17 +362,11 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         ax += (Real)(m32 * A0);
         ay += (Real)(m32 * A1);
         az += (Real)(m32 * A2);
-      }
-      // columns
-      const double d = sqrt(r2);
-      if (d > C.max_dist) continue;
-      const int e = table_row(C, -dx, -dy, -dz, d, tileh[j]);
-      const double base = r.w / (C.omega * r2);
-      const int64_t o0 = C.off[e], o1 = C.off[e + 1];
-      for (int64_t o = o0; o < o1; ++o) {
-        const int p = C.pix[o];
-        if (sizeof(Real) == 8) map[p * cpw + tid] += (Real)(C.w64[o] * base);
-        else map[p * cpw + tid] += (Real)((float)C.w32[o] * (float)base);
+        const float base = m32 * __builtin_amdgcn_rcpf(omega32 * (float)r2) * (1.0f / 16777216.0f);
+        for (int o = o0; o < o0 + cnt; ++o) {
+          const uint32_t v = C.ent[o];
+          map[(v >> 24) * cpw + tid] += (Real)((float)(v & 0xffffffu) * base);
+        }
       }
     }
   }
@@ -362,10 +384,26 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
   tau[o] = (Real)(-log(se / (double)C.npix));
 }
 
+// packed rows for the walk: row = offset << 6 | count; entry = pixel << 24 |
+// round(w 2^24) (w <= 1, clamped to 2^24 - 1)
+__global__ void k_raytable_pack(RayTableP P, const int64_t *__restrict__ off, const uint16_t *__restrict__ pix,
+                                const double *__restrict__ w, uint32_t *__restrict__ rows,
+                                uint32_t *__restrict__ ent) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= P.nentries) return;
+  const int64_t o0 = off[e], o1 = off[e + 1];
+  rows[e] = (uint32_t)(o0 << 6) | (uint32_t)(o1 - o0);
+  for (int64_t o = o0; o < o1; ++o) {
+    double q = rint(w[o] * 16777216.0);
+    q = q > 16777215.0 ? 16777215.0 : q;
+    ent[o] = ((uint32_t)pix[o] << 24) | (uint32_t)q;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_raytable(const RayTableP &P, double *dense, int32_t *cnt, int64_t *off, uint16_t *pix,
-                           double *w64, float *w32, int64_t *total, hipStream_t st) {
+                           double *w64, int64_t *total, hipStream_t st) {
   hipLaunchKernelGGL(k_raytable_dense, dim3((unsigned)P.nentries), dim3(64), 0, st, P, dense);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -377,18 +415,26 @@ hipError_t launch_raytable(const RayTableP &P, double *dense, int32_t *cnt, int6
     return e;
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
   if (!pix) return hipSuccess;  // sizing pass
-  hipLaunchKernelGGL(k_raytable_fill, dim3(nb), dim3(256), 0, st, P, dense, off, pix, w64, w32);
+  hipLaunchKernelGGL(k_raytable_fill, dim3(nb), dim3(256), 0, st, P, dense, off, pix, w64);
   return hipGetLastError();
 }
 
-size_t cols_smem_bytes(int npix, int cpw, bool fp64) {
-  return TILE * (sizeof(double4) + sizeof(double)) + (size_t)npix * cpw * (fp64 ? 8 : 4);
+size_t cols_smem_bytes(int npix, int cpw, bool fp64, int nthr) {
+  return TILE * (sizeof(double4) + sizeof(double)) + (size_t)nthr * sizeof(double) +
+         (size_t)npix * cpw * (fp64 ? 8 : 4);
+}
+
+hipError_t launch_raytable_pack(const RayTableP &P, const int64_t *off, const uint16_t *pix, const double *w,
+                                uint32_t *rows, uint32_t *ent, hipStream_t st) {
+  hipLaunchKernelGGL(k_raytable_pack, dim3((unsigned)((P.nentries + 255) / 256)), dim3(256), 0, st, P, off,
+                     pix, w, rows, ent);
+  return hipGetLastError();
 }
 
 hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const ColP &C, const int64_t *off,
                             const double4 *rec, const double *lh, void *phi, void *acc, void *npix, void *tau,
                             double G, int cpw, hipStream_t st) {
-  const size_t sm = cols_smem_bytes(C.npix, cpw, fp64);
+  const size_t sm = cols_smem_bytes(C.npix, cpw, fp64, C.nthr);
   dim3 grid((unsigned)(T.nb * (512 / cpw))), blk(cpw);
 #define OT_LAUNCH(R, B)                                                                                       \
   do {                                                                                                        \

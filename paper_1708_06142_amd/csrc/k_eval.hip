@@ -8,11 +8,17 @@
 // of Sec. 2.2.4) or, for 2P1I beyond |dz| = 2 Lx, from the analytic limit.
 // The target cell itself is skipped (d = 0 exactly).
 //
+// List records hold absolute centres of mass in FP64.  The FP64 kernel forms
+// d = r - r_a (minimum image) from absolute cell centres, the same expression
+// for both, so the target cell gives d = 0 exactly.  The FP32 kernel converts
+// each record once per workgroup to an FP32 offset from the block centre; the
+// block's own cells get the same expression as the thread's own offset, so the
+// target cell again gives d = 0.
+//
 // One workgroup of 256 threads per leaf block; thread t owns cells t and
 // t + 256.  The list is streamed through LDS in tiles of 256 records, which
-// every thread then reads as broadcasts.  The FP32 kernel converts each record
-// to FP32 once per workgroup, accumulates Phi with Kahan compensation and the
-// acceleration in plain FP32.
+// every thread then reads as broadcasts.  The FP32 kernel accumulates Phi with
+// Kahan compensation and the acceleration in plain FP32.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -85,12 +91,14 @@ __global__ __launch_bounds__(WG) void k_eval64(DevTree T, EwaldP E, const int64_
   const int tid = threadIdx.x;
   const int64_t ncell = T.nb * 512;
   const double h = size_at(T.root_size, T.blev[b]) / 8.0;
+  const int64_t c0 = 8 * (int64_t)T.bcoord[3 * b], c1 = 8 * (int64_t)T.bcoord[3 * b + 1];
+  const int64_t c2 = 8 * (int64_t)T.bcoord[3 * b + 2];
   double cx[2], cy[2], cz[2], sp[2] = {0, 0}, ax[2] = {0, 0}, ay[2] = {0, 0}, az[2] = {0, 0};
   for (int q = 0; q < 2; ++q) {
     int ci = tid + q * WG;
-    cx[q] = ((double)(ci & 7) - 3.5) * h;
-    cy[q] = ((double)((ci >> 3) & 7) - 3.5) * h;
-    cz[q] = ((double)(ci >> 6) - 3.5) * h;
+    cx[q] = T.org[0] + ((double)(c0 + (ci & 7)) + 0.5) * h;
+    cy[q] = T.org[1] + ((double)(c1 + ((ci >> 3) & 7)) + 0.5) * h;
+    cz[q] = T.org[2] + ((double)(c2 + (ci >> 6)) + 0.5) * h;
   }
   const int64_t start = off[b], n = off[b + 1] - start;
   for (int64_t t0 = 0; t0 < n; t0 += WG) {
@@ -188,14 +196,18 @@ __device__ inline void pair32(const EwaldP &E, float cx, float cy, float cz, con
 
 template <int BC>
 __global__ __launch_bounds__(WG) void k_eval32(DevTree T, EwaldP E, const int64_t *__restrict__ off,
-                                               const double4 *__restrict__ rec,
+                                               const double4 *__restrict__ rec, const int32_t *__restrict__ ids,
                                                float *__restrict__ phi, float *__restrict__ acc,
                                                float negG) {
   __shared__ float4 tile[WG];
   const int64_t b = blockIdx.x;
   const int tid = threadIdx.x;
   const int64_t ncell = T.nb * 512;
-  const double h = size_at(T.root_size, T.blev[b]) / 8.0;
+  const double sb = size_at(T.root_size, T.blev[b]);
+  const double h = sb / 8.0;
+  double cT[3];
+  for (int k = 0; k < 3; ++k) cT[k] = T.org[k] + ((double)T.bcoord[3 * b + k] + 0.5) * sb;
+  const int64_t own0 = T.na + 72 * T.nb + 512 * b;  // id of cell 0 of this block
   float cx[2], cy[2], cz[2];
   Acc32 a[2];
   for (int q = 0; q < 2; ++q) {
@@ -209,7 +221,20 @@ __global__ __launch_bounds__(WG) void k_eval32(DevTree T, EwaldP E, const int64_
   for (int64_t t0 = 0; t0 < n; t0 += WG) {
     if (t0 + tid < n) {
       const double4 r = rec[start + t0 + tid];
-      tile[tid] = make_float4((float)r.x, (float)r.y, (float)r.z, (float)r.w);
+      const int64_t own = (int64_t)ids[start + t0 + tid] - own0;
+      float4 v;
+      if (own >= 0 && own < 512) {
+        // a cell of this block: the same offset expression as the threads' own
+        v.x = (float)(((double)(own & 7) - 3.5) * h);
+        v.y = (float)(((double)((own >> 3) & 7) - 3.5) * h);
+        v.z = (float)(((double)(own >> 6) - 3.5) * h);
+      } else {
+        v.x = (float)wrap_axis(r.x - cT[0], T.L[0], T.per[0]);
+        v.y = (float)wrap_axis(r.y - cT[1], T.L[1], T.per[1]);
+        v.z = (float)wrap_axis(r.z - cT[2], T.L[2], T.per[2]);
+      }
+      v.w = (float)r.w;
+      tile[tid] = v;
     }
     __syncthreads();
     const int m = (int)(n - t0 < WG ? n - t0 : WG);
@@ -262,13 +287,13 @@ hipError_t launch_eval64(const DevTree &T, const EwaldP &E, const int64_t *off, 
 }
 
 hipError_t launch_eval32(const DevTree &T, const EwaldP &E, const int64_t *off, const double4 *rec,
-                         float *phi, float *acc, double G, hipStream_t st) {
+                         const int32_t *ids, float *phi, float *acc, double G, hipStream_t st) {
   dim3 grid((unsigned)T.nb), blk(WG);
   float ng = (float)(-G);
   switch (E.bctype) {
-    case 0: hipLaunchKernelGGL(k_eval32<0>, grid, blk, 0, st, T, E, off, rec, phi, acc, ng); break;
-    case 1: hipLaunchKernelGGL(k_eval32<1>, grid, blk, 0, st, T, E, off, rec, phi, acc, ng); break;
-    default: hipLaunchKernelGGL(k_eval32<2>, grid, blk, 0, st, T, E, off, rec, phi, acc, ng); break;
+    case 0: hipLaunchKernelGGL(k_eval32<0>, grid, blk, 0, st, T, E, off, rec, ids, phi, acc, ng); break;
+    case 1: hipLaunchKernelGGL(k_eval32<1>, grid, blk, 0, st, T, E, off, rec, ids, phi, acc, ng); break;
+    default: hipLaunchKernelGGL(k_eval32<2>, grid, blk, 0, st, T, E, off, rec, ids, phi, acc, ng); break;
   }
   return hipGetLastError();
 }

@@ -16,7 +16,7 @@
 // the amr-tree (frontier of amr nodes in global scratch), then over the +1
 // and +2 levels of opened leaf blocks.  Ballot prefix sums give every thread
 // its output slot, so the list order is deterministic.  Pass 1 counts, pass 2
-// writes {r_a - c_T (minimum image), M} in FP64 plus the node ids.
+// writes {r_a, M} (absolute centre of mass, FP64), the node ids and sizes.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -92,12 +92,7 @@ __device__ inline void emit(const DevTree &T, const Target &tg, int64_t pos, int
                             const double4 mc, double h, double4 *rec, int32_t *ids, double *lh) {
   if (!FILL) return;
   if (lh) lh[pos] = h;
-  double4 r;
-  r.x = wrap_axis(mc.x - tg.c[0], T.L[0], T.per[0]);
-  r.y = wrap_axis(mc.y - tg.c[1], T.L[1], T.per[1]);
-  r.z = wrap_axis(mc.z - tg.c[2], T.L[2], T.per[2]);
-  r.w = mc.w;
-  rec[pos] = r;
+  rec[pos] = mc;
   ids[pos] = id;
 }
 
@@ -234,20 +229,9 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
           int ci = cell_index(o1, o2, o3);
           int ijk[3] = {ci & 7, (ci >> 3) & 7, ci >> 6};
           double4 r;
-          if (lb == b) {
-            // own block: the same expression as the evaluation's cell offset,
-            // so the target cell itself gives d = 0 exactly
-            r.x = ((double)ijk[0] - 3.5) * tg.h;
-            r.y = ((double)ijk[1] - 3.5) * tg.h;
-            r.z = ((double)ijk[2] - 3.5) * tg.h;
-          } else {
-            double x[3];
-            for (int k = 0; k < 3; ++k)
-              x[k] = T.org[k] + ((double)(8 * (int64_t)T.bcoord[3 * lb + k] + ijk[k]) + 0.5) * h;
-            r.x = wrap_axis(x[0] - tg.c[0], T.L[0], T.per[0]);
-            r.y = wrap_axis(x[1] - tg.c[1], T.L[1], T.per[1]);
-            r.z = wrap_axis(x[2] - tg.c[2], T.L[2], T.per[2]);
-          }
+          r.x = T.org[0] + ((double)(8 * (int64_t)T.bcoord[3 * lb + 0] + ijk[0]) + 0.5) * h;
+          r.y = T.org[1] + ((double)(8 * (int64_t)T.bcoord[3 * lb + 1] + ijk[1]) + 0.5) * h;
+          r.z = T.org[2] + ((double)(8 * (int64_t)T.bcoord[3 * lb + 2] + ijk[2]) + 0.5) * h;
           r.w = T.cm[(int64_t)lb * 512 + ci];
           rec[p0 + o3] = r;
           ids[p0 + o3] = (int32_t)(na + 72 * nb + 512 * (int64_t)lb + ci);

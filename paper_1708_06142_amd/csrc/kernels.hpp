@@ -50,15 +50,19 @@ struct ColP {
   double omega;     // 4 pi / N_pix
   double kappa;     // opacity of tau_avg
   double max_dist;  // columns only from nodes closer than this
-  const int64_t *off;
-  const uint16_t *pix;
-  const double *w64;
-  const float *w32;
+  int nthr;         // threshold count: ntheta + npsi + 2 (nphi/2 + 1)
+  const double *thr;       // cos(k dtheta), sin(k dpsi), cos(k dphi), sin(k dphi)
+  const uint32_t *rows;    // [nentries] offset << 6 | count
+  const uint16_t *pix;     // [npairs] FP64 walk
+  const double *w64;       // [npairs]
+  const uint32_t *ent;     // [npairs] FP32 walk: pixel << 24 | unorm24 weight
 };
 
 hipError_t launch_raytable(const RayTableP &P, double *dense, int32_t *cnt, int64_t *off, uint16_t *pix,
-                           double *w64, float *w32, int64_t *total, hipStream_t st);
-size_t cols_smem_bytes(int npix, int cpw, bool fp64);
+                           double *w64, int64_t *total, hipStream_t st);
+hipError_t launch_raytable_pack(const RayTableP &P, const int64_t *off, const uint16_t *pix, const double *w,
+                                uint32_t *rows, uint32_t *ent, hipStream_t st);
+size_t cols_smem_bytes(int npix, int cpw, bool fp64, int nthr);
 hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const ColP &C, const int64_t *off,
                             const double4 *rec, const double *lh, void *phi, void *acc, void *npix, void *tau,
                             double G, int cpw, hipStream_t st);
@@ -75,7 +79,7 @@ hipError_t launch_scan(const int32_t *count, int64_t nb, int64_t *off, hipStream
 hipError_t launch_eval64(const DevTree &T, const EwaldP &E, const int64_t *off, const double4 *rec,
                          double *phi, double *acc, double G, hipStream_t st);
 hipError_t launch_eval32(const DevTree &T, const EwaldP &E, const int64_t *off, const double4 *rec,
-                         float *phi, float *acc, double G, hipStream_t st);
+                         const int32_t *ids, float *phi, float *acc, double G, hipStream_t st);
 
 hipError_t launch_amax(const double *acc, int64_t n, unsigned long long *out, hipStream_t st);
 

@@ -47,7 +47,14 @@ CASES = {
     "amr2p1i_n1": (lambda: workloads.small_amr(bc=(1, 1, 0), nroot=(1, 1, 2)),
                    dict(theta=0.5, nside=1, ewald_n=32)),
     "sphere32_n4": (lambda: workloads.c1_sphere(), dict(theta=0.5, nside=4, kappa=3.0)),
+    # non-dyadic root size and shifted origin: exact zeros of d must survive
+    "forest_offset_n2": (lambda: _forest_offset(), dict(theta=0.5, nside=2)),
 }
+
+
+def _forest_offset():
+    g = workloads.small_amr(nroot=(2, 1, 1), seed=3)
+    return workloads.Grid(g.nroot, 0.3, (0.1, -0.2, 0.05), g.level, g.coord, g.rho, g.bc, "forest")
 
 
 @pytest.mark.parametrize("name", list(CASES))
