@@ -625,7 +625,7 @@ ot_status ot_export_moments(ot_ctx *c, double *M, double *com) {
       double4 v;
       double x[3];
       for (int k = 0; k < 3; ++k)
-        x[k] = c->p.origin[k] + ((double)(8 * (int64_t)t.bcoord[3 * lb + k] + ijk[k]) + 0.5) * h;
+        x[k] = ot::centre_coord(c->p.origin[k], 8 * (int64_t)t.bcoord[3 * lb + k] + ijk[k], h);
       v.x = x[0];
       v.y = x[1];
       v.z = x[2];

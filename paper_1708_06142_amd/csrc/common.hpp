@@ -41,6 +41,15 @@ __host__ __device__ inline double size_at(double root_size, int lev) {
   return root_size / (double)(1LL << (lev - 1));
 }
 
+// Centre of the cell / node at integer position pos (in units of size) along
+// one axis: org + (pos + 1/2) size.  Every kernel and the host use this one
+// expression without FMA contraction, so a cell centre computed in two places
+// is the same double (the target cell then gives d = 0 exactly).
+__host__ __device__ inline double centre_coord(double org, int64_t pos, double size) {
+#pragma clang fp contract(off)
+  return org + ((double)pos + 0.5) * size;
+}
+
 // minimum image in a periodic axis, wrapped to [-L/2, L/2)
 __device__ inline double wrap_axis(double d, double L, int per) {
   return per ? d - L * floor(d / L + 0.5) : d;

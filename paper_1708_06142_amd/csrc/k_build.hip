@@ -42,9 +42,9 @@ __global__ __launch_bounds__(64) void k_block_moments(DevTree T, const double *_
     for (int o3 = 0; o3 < 8; ++o3) {
       int ci = cell_index(o1, o2, o3);
       int ii = ci & 7, jj = (ci >> 3) & 7, kk = ci >> 6;
-      double x = T.org[0] + ((double)(8 * (int64_t)c[0] + ii) + 0.5) * h;
-      double y = T.org[1] + ((double)(8 * (int64_t)c[1] + jj) + 0.5) * h;
-      double z = T.org[2] + ((double)(8 * (int64_t)c[2] + kk) + 0.5) * h;
+      double x = centre_coord(T.org[0], 8 * (int64_t)c[0] + ii, h);
+      double y = centre_coord(T.org[1], 8 * (int64_t)c[1] + jj, h);
+      double z = centre_coord(T.org[2], 8 * (int64_t)c[2] + kk, h);
       double m = sm[ci];
       M = M + m;
       Sx = Sx + m * x;
@@ -55,8 +55,7 @@ __global__ __launch_bounds__(64) void k_block_moments(DevTree T, const double *_
     double s = sblk / 4.0;
     double g[3];
     for (int k = 0; k < 3; ++k) {
-      int64_t pos = 4 * (int64_t)c[k] + 2 * ((o1 >> k) & 1) + ((o2 >> k) & 1);
-      g[k] = T.org[k] + ((double)pos + 0.5) * s;
+      g[k] = centre_coord(T.org[k], 4 * (int64_t)c[k] + 2 * ((o1 >> k) & 1) + ((o2 >> k) & 1), s);
     }
     double4 mc = M > 0.0 ? make_double4(Sx / M, Sy / M, Sz / M, M) : make_double4(g[0], g[1], g[2], M);
     T.btmc[lb * 72 + 8 + t] = mc;
@@ -75,8 +74,7 @@ __global__ __launch_bounds__(64) void k_block_moments(DevTree T, const double *_
     double s = sblk / 2.0;
     double g[3];
     for (int k = 0; k < 3; ++k) {
-      int64_t pos = 2 * (int64_t)c[k] + ((t >> k) & 1);
-      g[k] = T.org[k] + ((double)pos + 0.5) * s;
+      g[k] = centre_coord(T.org[k], 2 * (int64_t)c[k] + ((t >> k) & 1), s);
     }
     T.btmc[lb * 72 + t] = M > 0.0 ? make_double4(Sx / M, Sy / M, Sz / M, M)
                                   : make_double4(g[0], g[1], g[2], M);
@@ -92,7 +90,7 @@ __global__ __launch_bounds__(64) void k_block_moments(DevTree T, const double *_
       Sz = Sz + v.z;
     }
     double g[3];
-    for (int k = 0; k < 3; ++k) g[k] = T.org[k] + ((double)c[k] + 0.5) * sblk;
+    for (int k = 0; k < 3; ++k) g[k] = centre_coord(T.org[k], c[k], sblk);
     int64_t a = T.bamr[lb];
     T.amc[a] = M > 0.0 ? make_double4(Sx / M, Sy / M, Sz / M, M) : make_double4(g[0], g[1], g[2], M);
     T.aS[a] = make_double4(Sx, Sy, Sz, 0.0);
@@ -114,7 +112,7 @@ __global__ __launch_bounds__(256) void k_amr_moments(DevTree T, int64_t begin, i
   }
   double s = size_at(T.root_size, T.alev[i]);
   double g[3];
-  for (int k = 0; k < 3; ++k) g[k] = T.org[k] + ((double)T.acoord[3 * i + k] + 0.5) * s;
+  for (int k = 0; k < 3; ++k) g[k] = centre_coord(T.org[k], T.acoord[3 * i + k], s);
   T.amc[i] = M > 0.0 ? make_double4(Sx / M, Sy / M, Sz / M, M) : make_double4(g[0], g[1], g[2], M);
   T.aS[i] = make_double4(Sx, Sy, Sz, 0.0);
 }

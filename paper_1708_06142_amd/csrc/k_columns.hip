@@ -313,9 +313,9 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
   const int64_t ncell = T.nb * 512;
   const double h = size_at(T.root_size, T.blev[b]) / 8.0;
   // absolute cell centre, the same expression as the records' cell centres
-  const double cx = T.org[0] + ((double)(8 * (int64_t)T.bcoord[3 * b] + (ci & 7)) + 0.5) * h;
-  const double cy = T.org[1] + ((double)(8 * (int64_t)T.bcoord[3 * b + 1] + ((ci >> 3) & 7)) + 0.5) * h;
-  const double cz = T.org[2] + ((double)(8 * (int64_t)T.bcoord[3 * b + 2] + (ci >> 6)) + 0.5) * h;
+  const double cx = centre_coord(T.org[0], 8 * (int64_t)T.bcoord[3 * b] + (ci & 7), h);
+  const double cy = centre_coord(T.org[1], 8 * (int64_t)T.bcoord[3 * b + 1] + ((ci >> 3) & 7), h);
+  const double cz = centre_coord(T.org[2], 8 * (int64_t)T.bcoord[3 * b + 2] + (ci >> 6), h);
   const float omega32 = (float)C.omega;
   for (int q = tid; q < C.nthr; q += cpw) thr[q] = C.thr[q];
   for (int p = 0; p < C.npix; ++p) map[p * cpw + tid] = (Real)0;

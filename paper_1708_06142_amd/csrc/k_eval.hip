@@ -96,9 +96,9 @@ __global__ __launch_bounds__(WG) void k_eval64(DevTree T, EwaldP E, const int64_
   double cx[2], cy[2], cz[2], sp[2] = {0, 0}, ax[2] = {0, 0}, ay[2] = {0, 0}, az[2] = {0, 0};
   for (int q = 0; q < 2; ++q) {
     int ci = tid + q * WG;
-    cx[q] = T.org[0] + ((double)(c0 + (ci & 7)) + 0.5) * h;
-    cy[q] = T.org[1] + ((double)(c1 + ((ci >> 3) & 7)) + 0.5) * h;
-    cz[q] = T.org[2] + ((double)(c2 + (ci >> 6)) + 0.5) * h;
+    cx[q] = centre_coord(T.org[0], c0 + (ci & 7), h);
+    cy[q] = centre_coord(T.org[1], c1 + ((ci >> 3) & 7), h);
+    cz[q] = centre_coord(T.org[2], c2 + (ci >> 6), h);
   }
   const int64_t start = off[b], n = off[b + 1] - start;
   for (int64_t t0 = 0; t0 < n; t0 += WG) {
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(WG) void k_eval32(DevTree T, EwaldP E, const int64_
   const double sb = size_at(T.root_size, T.blev[b]);
   const double h = sb / 8.0;
   double cT[3];
-  for (int k = 0; k < 3; ++k) cT[k] = T.org[k] + ((double)T.bcoord[3 * b + k] + 0.5) * sb;
+  for (int k = 0; k < 3; ++k) cT[k] = centre_coord(T.org[k], T.bcoord[3 * b + k], sb);
   const int64_t own0 = T.na + 72 * T.nb + 512 * b;  // id of cell 0 of this block
   float cx[2], cy[2], cz[2];
   Acc32 a[2];

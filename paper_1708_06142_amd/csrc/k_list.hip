@@ -115,7 +115,7 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
     Target tg;
     const int blev = T.blev[b];
     const double sb = size_at(T.root_size, blev);
-    for (int k = 0; k < 3; ++k) tg.c[k] = T.org[k] + ((double)T.bcoord[3 * b + k] + 0.5) * sb;
+    for (int k = 0; k < 3; ++k) tg.c[k] = centre_coord(T.org[k], T.bcoord[3 * b + k], sb);
     tg.ext = 3.5 * (sb / 8.0);
     tg.h = sb / 8.0;
     const int64_t base = FILL ? off[b] : 0;
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
           const int lev = T.alev[node];
           s = size_at(T.root_size, lev);
           double g[3];
-          for (int k = 0; k < 3; ++k) g[k] = T.org[k] + ((double)T.acoord[3 * node + k] + 0.5) * s;
+          for (int k = 0; k < 3; ++k) g[k] = centre_coord(T.org[k], T.acoord[3 * node + k], s);
           mc = T.amc[node];
           acc = accept(T, P, tg, s, g, mc);
           if (!acc) {
@@ -179,8 +179,7 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
         s = size_at(T.root_size, T.blev[lb]) / 2.0;
         double g[3];
         for (int k = 0; k < 3; ++k) {
-          int64_t pos = 2 * (int64_t)T.bcoord[3 * lb + k] + ((o1 >> k) & 1);
-          g[k] = T.org[k] + ((double)pos + 0.5) * s;
+          g[k] = centre_coord(T.org[k], 2 * (int64_t)T.bcoord[3 * lb + k] + ((o1 >> k) & 1), s);
         }
         mc = T.btmc[(int64_t)lb * 72 + o1];
         acc = accept(T, P, tg, s, g, mc);
@@ -211,7 +210,7 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
         double g[3];
         for (int k = 0; k < 3; ++k) {
           int64_t pos = 4 * (int64_t)T.bcoord[3 * lb + k] + 2 * ((o1 >> k) & 1) + ((o2 >> k) & 1);
-          g[k] = T.org[k] + ((double)pos + 0.5) * s;
+          g[k] = centre_coord(T.org[k], pos, s);
         }
         mc = T.btmc[(int64_t)lb * 72 + 8 + 8 * o1 + o2];
         acc = accept(T, P, tg, s, g, mc);
@@ -229,9 +228,9 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
           int ci = cell_index(o1, o2, o3);
           int ijk[3] = {ci & 7, (ci >> 3) & 7, ci >> 6};
           double4 r;
-          r.x = T.org[0] + ((double)(8 * (int64_t)T.bcoord[3 * lb + 0] + ijk[0]) + 0.5) * h;
-          r.y = T.org[1] + ((double)(8 * (int64_t)T.bcoord[3 * lb + 1] + ijk[1]) + 0.5) * h;
-          r.z = T.org[2] + ((double)(8 * (int64_t)T.bcoord[3 * lb + 2] + ijk[2]) + 0.5) * h;
+          r.x = centre_coord(T.org[0], 8 * (int64_t)T.bcoord[3 * lb + 0] + ijk[0], h);
+          r.y = centre_coord(T.org[1], 8 * (int64_t)T.bcoord[3 * lb + 1] + ijk[1], h);
+          r.z = centre_coord(T.org[2], 8 * (int64_t)T.bcoord[3 * lb + 2] + ijk[2], h);
           r.w = T.cm[(int64_t)lb * 512 + ci];
           rec[p0 + o3] = r;
           ids[p0 + o3] = (int32_t)(na + 72 * nb + 512 * (int64_t)lb + ci);
