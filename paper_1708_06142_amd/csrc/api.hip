@@ -226,12 +226,10 @@ ot_status raytable_prepare(ot_ctx *c, hipStream_t st) {
       if (e == hipSuccess)
         e = ot::launch_raytable_pack(RP, P<int64_t>(c->rt_off), P<uint16_t>(c->rt_pix), P<double>(c->rt_w64),
                                      P<uint32_t>(c->rt_rows), P<uint32_t>(c->rt_ent), st);
-      // direction-bin thresholds: cos(k dtheta), cos^2(k dtheta), sin^2(k dpsi),
-      // cos(k dphi), sin(k dphi)
+      // direction-bin thresholds: cos(k dtheta), sin(k dpsi), cos(k dphi), sin(k dphi)
       std::vector<double> thr;
       for (int k = 0; k < RP.ntheta; ++k) thr.push_back(std::cos(k * RP.dtheta));
-      for (int k = 0; k < RP.ntheta; ++k) thr.push_back(std::cos(k * RP.dtheta) * std::cos(k * RP.dtheta));
-      for (int k = 0; k < RP.npsi; ++k) thr.push_back(std::sin(k * RP.dpsi) * std::sin(k * RP.dpsi));
+      for (int k = 0; k < RP.npsi; ++k) thr.push_back(std::sin(k * RP.dpsi));
       for (int k = 0; k <= RP.nphi / 2; ++k) thr.push_back(std::cos(k * RP.dphi));
       for (int k = 0; k <= RP.nphi / 2; ++k) thr.push_back(std::sin(k * RP.dphi));
       if (e == hipSuccess && (s = dalloc(c, c->rt_thr, thr.size() * sizeof(double))) == OT_OK)
@@ -261,8 +259,8 @@ ot::ColP col_params(ot_ctx *c) {
   C.req = 0.6203504908994001;  // (3 / (4 pi))^(1/3)
   C.omega = 4.0 * M_PI / (double)RP.npix;
   C.kappa = c->p.kappa;
-  C.max_dist2 = c->p.max_dist < 1e150 ? c->p.max_dist * c->p.max_dist : 1e300;
-  C.nthr = 2 * RP.ntheta + RP.npsi + 2 * (RP.nphi / 2 + 1);
+  C.max_dist = c->p.max_dist;
+  C.nthr = RP.ntheta + RP.npsi + 2 * (RP.nphi / 2 + 1);
   C.thr = P<double>(c->rt_thr);
   C.rows = P<uint32_t>(c->rt_rows);
   C.pix = P<uint16_t>(c->rt_pix);
@@ -274,7 +272,7 @@ ot::ColP col_params(ot_ctx *c) {
 // cells per workgroup of the column walk: the per-cell maps must fit in LDS
 int cols_cpw(const ot_ctx *c, bool fp64) {
   const ot::RayTableP RP = raytable_desc(c);
-  const int nthr = 2 * RP.ntheta + RP.npsi + 2 * (RP.nphi / 2 + 1);
+  const int nthr = RP.ntheta + RP.npsi + 2 * (RP.nphi / 2 + 1);
   for (int cpw : {256, 128, 64})
     if (ot::cols_smem_bytes(npix_of(c), cpw, fp64, nthr) <= 65536) return cpw;
   if (ot::cols_smem_bytes(npix_of(c), 64, fp64, nthr) <= 160 * 1024) return 64;

@@ -171,33 +171,23 @@ __device__ inline int last_true(int n, Pred pred) {
   return k;
 }
 
-// Table row of a node at offset v = r_a - r from the target (|v|^2 = r2,
-// node size h).  The bins are those of floor(theta / dtheta), floor(phi /
-// dphi) and floor(psi / dpsi), decided without inverse trigonometric functions
-// or square roots (c_k = cos(k dtheta), s_k = sin(k dpsi)):
-//   theta >= k dtheta  <=>  v_z <= c_k |v|:  c_k >= 0: v_z <= 0 or v_z^2 <= c_k^2 r2,
-//                                             c_k < 0:  v_z < 0 and v_z^2 >= c_k^2 r2
-//   psi   >= k dpsi    <=>  (R_eq h)^2 >= s_k^2 r2
+// Table row of a node at offset v = r_a - r from the target (|v| = d, node
+// size h).  The bins are those of floor(theta / dtheta), floor(phi / dphi)
+// and floor(psi / dpsi), decided without inverse trigonometric functions:
+//   theta >= k dtheta  <=>  v_z <= cos(k dtheta) d
+//   psi   >= k dpsi    <=>  R_eq h >= sin(k dpsi) d
 //   phi   >= k dphi    <=>  cos(k dphi) v_y - sin(k dphi) v_x >= 0   (0 < phi < pi)
 // with phi in (pi, 2 pi) mapped to the upper half-plane by v -> -v; v_y = 0
-// (exactly on the x axis) uses atan2 as written.  FP64 throughout.  The
-// threshold table holds c_k, c_k^2 (ntheta each), s_k^2 (npsi), cos(k dphi),
-// sin(k dphi) (nphi/2 + 1 each).
+// (exactly on the x axis) uses atan2 as written.  FP64 throughout.
 __device__ inline int table_row(const ColP &C, const double *thr, double vx, double vy, double vz,
-                                double r2, double h) {
-  const double *cth = thr;
-  const double *cth2 = thr + C.ntheta;
-  const double *sps2 = cth2 + C.ntheta;
-  const double *cph = sps2 + C.npsi;
+                                double d, double h) {
+  const double *cth = thr;                       // [ntheta]
+  const double *sps = thr + C.ntheta;            // [npsi]
+  const double *cph = sps + C.npsi;              // [nphi/2 + 1]
   const double *sph = cph + (C.nphi / 2 + 1);
-  const double vz2 = vz * vz;
-  const int it = last_true(C.ntheta, [&](int k) {
-    const double c2r2 = cth2[k] * r2;
-    return cth[k] >= 0.0 ? (vz <= 0.0 || vz2 <= c2r2) : (vz < 0.0 && vz2 >= c2r2);
-  });
+  const int it = last_true(C.ntheta, [&](int k) { return vz <= cth[k] * d; });
   const double rh = C.req * h;
-  const double rh2 = rh * rh;
-  const int is = last_true(C.npsi, [&](int k) { return rh2 >= sps2[k] * r2; });
+  const int is = last_true(C.npsi, [&](int k) { return rh >= sps[k] * d; });
   int ip;
   if (vy == 0.0) {
     double ph = atan2(vy, vx);
@@ -346,8 +336,9 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
       wrap3<BC>(E, dx, dy, dz);
       const double r2 = dx * dx + dy * dy + dz * dz;
       if (r2 == 0.0) continue;  // the target cell itself
-      const bool col = r2 <= C.max_dist2;
-      const int e = col ? table_row(C, thr, -dx, -dy, -dz, r2, tileh[j]) : 0;
+      const double d = sqrt(r2);
+      const bool col = d <= C.max_dist;
+      const int e = col ? table_row(C, thr, -dx, -dy, -dz, d, tileh[j]) : 0;
       const uint32_t rd = C.rows[e];
       const int o0 = (int)(rd >> 6), cnt = col ? (int)(rd & 63) : 0;
       if (sizeof(Real) == 8) {

@@ -49,9 +49,9 @@ struct ColP {
   double req;       // (3 / (4 pi))^(1/3): equal-volume sphere radius per unit edge
   double omega;     // 4 pi / N_pix
   double kappa;     // opacity of tau_avg
-  double max_dist2; // columns only from nodes with |d|^2 <= max_dist^2
-  int nthr;         // threshold count: 2 ntheta + npsi + 2 (nphi/2 + 1)
-  const double *thr;       // cos(k dtheta), cos^2, sin^2(k dpsi), cos(k dphi), sin(k dphi)
+  double max_dist;  // columns only from nodes closer than this
+  int nthr;         // threshold count: ntheta + npsi + 2 (nphi/2 + 1)
+  const double *thr;       // cos(k dtheta), sin(k dpsi), cos(k dphi), sin(k dphi)
   const uint32_t *rows;    // [nentries] offset << 6 | count
   const uint16_t *pix;     // [npairs] FP64 walk
   const double *w64;       // [npairs]
