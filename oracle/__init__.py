@@ -14,7 +14,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
-SOURCES = ["octoracle.c", "ewald.c", "columns.c"]
+SOURCES = ["octoracle.c", "ewald.c", "columns.c", "mlp.c"]
 
 ERRORS = {1: "bad level/coord", 2: "duplicate block", 3: "overlapping blocks",
           4: "hole in the block tiling", 5: "bad density", 6: "unsupported BCs"}
@@ -85,6 +85,10 @@ def lib():
         L.or_ewald_table.argtypes = [C.c_int, vp, C.c_double, C.c_int, C.c_int, C.c_int, vp]
         L.or_ewald_table_lookup.argtypes = [C.c_int, vp, C.c_int, vp, i64, vp, vp]
         L.or_itilde.argtypes = [C.c_double, C.c_double, C.c_double, vp]
+        L.or_mlp_nparam.restype = C.c_int
+        L.or_mlp_forward.argtypes = [vp, i64, vp, vp]
+        L.or_mlp_grad.restype = C.c_double
+        L.or_mlp_grad.argtypes = [vp, i64, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -272,3 +276,26 @@ def raytable(nside, il_ntheta=25, il_nphi=50, il_npsi=25, il_nr=50, il_nazi=100,
     off, pix, w = np.empty(ne + 1, np.int64), np.empty(n, np.int32), np.empty(n)
     lib().or_raytable_export(*args, _ptr(off), _ptr(pix), _ptr(w))
     return off, pix, w
+
+
+# ---------------------------------------------------------------- MLP
+MLP_NPARAM = 8836  # 3 -> 64 -> 64 -> 64 -> 4
+
+
+def mlp_forward(params, x):
+    """FP64 forward of the surrogate network: x [B, 3] -> y [B, 4]."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.float64)
+    y = np.empty((x.shape[0], 4))
+    lib().or_mlp_forward(_ptr(p), x.shape[0], _ptr(x), _ptr(y))
+    return y
+
+
+def mlp_grad(params, x, t):
+    """Batch MSE loss and its gradient (FP64 back-propagation)."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.float64)
+    t = np.ascontiguousarray(np.atleast_2d(t), dtype=np.float64)
+    g = np.empty(MLP_NPARAM)
+    loss = lib().or_mlp_grad(_ptr(p), x.shape[0], _ptr(x), _ptr(t), _ptr(g))
+    return loss, g

@@ -1,0 +1,124 @@
+/*
+ * FP64 reference of the learned Ewald surrogate (a small MLP standing in for
+ * the Ewald correction table).  TEST INFRASTRUCTURE ONLY (see octoracle.h).
+ *
+ * Network: 3 -> 64 -> 64 -> 64 -> 4, SiLU after the three hidden layers,
+ * identity output.  Parameter vector layout (8836 values):
+ *   W1[64][3], b1[64], W2[64][64], b2[64], W3[64][64], b3[64], W4[4][64], b4[4]
+ * (row-major, W[out][in]).  Loss over a batch of B samples: mean squared error
+ * over the 4 outputs, L = 1/(4B) sum_s sum_o (y_so - t_so)^2.
+ * Plain loops, no blocking; the gradient is the textbook back-propagation.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { H = 64, NI = 3, NO = 4 };
+enum { OW1 = 0, OB1 = OW1 + H * NI, OW2 = OB1 + H, OB2 = OW2 + H * H, OW3 = OB2 + H,
+       OB3 = OW3 + H * H, OW4 = OB3 + H, OB4 = OW4 + NO * H, NPARAM = OB4 + NO };
+
+static double silu(double z) { return z / (1.0 + exp(-z)); }
+static double dsilu(double z) {
+  double s = 1.0 / (1.0 + exp(-z));
+  return s * (1.0 + z * (1.0 - s));
+}
+
+int or_mlp_nparam(void) { return NPARAM; }
+
+/* forward of one sample; keeps pre-activations for the backward pass */
+static void forward1(const double *p, const double *x, double z1[H], double z2[H], double z3[H],
+                     double y[NO]) {
+  double h1[H], h2[H], h3[H];
+  for (int o = 0; o < H; ++o) {
+    double a = p[OB1 + o];
+    for (int i = 0; i < NI; ++i) a += p[OW1 + o * NI + i] * x[i];
+    z1[o] = a;
+    h1[o] = silu(a);
+  }
+  for (int o = 0; o < H; ++o) {
+    double a = p[OB2 + o];
+    for (int i = 0; i < H; ++i) a += p[OW2 + o * H + i] * h1[i];
+    z2[o] = a;
+    h2[o] = silu(a);
+  }
+  for (int o = 0; o < H; ++o) {
+    double a = p[OB3 + o];
+    for (int i = 0; i < H; ++i) a += p[OW3 + o * H + i] * h2[i];
+    z3[o] = a;
+    h3[o] = silu(a);
+  }
+  for (int o = 0; o < NO; ++o) {
+    double a = p[OB4 + o];
+    for (int i = 0; i < H; ++i) a += p[OW4 + o * H + i] * h3[i];
+    y[o] = a;
+  }
+}
+
+/* y[B][4] = f(x[B][3]) */
+void or_mlp_forward(const double *p, int64_t B, const double *x, double *y) {
+  for (int64_t s = 0; s < B; ++s) {
+    double z1[H], z2[H], z3[H];
+    forward1(p, x + NI * s, z1, z2, z3, y + NO * s);
+  }
+}
+
+/* loss and gradient g[NPARAM] of the batch MSE */
+double or_mlp_grad(const double *p, int64_t B, const double *x, const double *t, double *g) {
+  memset(g, 0, sizeof(double) * NPARAM);
+  double loss = 0.0;
+  const double scale = 1.0 / (double)(NO * B);
+  for (int64_t s = 0; s < B; ++s) {
+    const double *xs = x + NI * s;
+    double z1[H], z2[H], z3[H], y[NO];
+    forward1(p, xs, z1, z2, z3, y);
+    double h1[H], h2[H], h3[H];
+    for (int i = 0; i < H; ++i) {
+      h1[i] = silu(z1[i]);
+      h2[i] = silu(z2[i]);
+      h3[i] = silu(z3[i]);
+    }
+    double dy[NO];
+    for (int o = 0; o < NO; ++o) {
+      double e = y[o] - t[NO * s + o];
+      loss += e * e * scale;
+      dy[o] = 2.0 * e * scale;
+    }
+    /* layer 4 */
+    double dh3[H] = {0};
+    for (int o = 0; o < NO; ++o) {
+      g[OB4 + o] += dy[o];
+      for (int i = 0; i < H; ++i) {
+        g[OW4 + o * H + i] += dy[o] * h3[i];
+        dh3[i] += dy[o] * p[OW4 + o * H + i];
+      }
+    }
+    /* layer 3 */
+    double dh2[H] = {0};
+    for (int o = 0; o < H; ++o) {
+      double dz = dh3[o] * dsilu(z3[o]);
+      g[OB3 + o] += dz;
+      for (int i = 0; i < H; ++i) {
+        g[OW3 + o * H + i] += dz * h2[i];
+        dh2[i] += dz * p[OW3 + o * H + i];
+      }
+    }
+    /* layer 2 */
+    double dh1[H] = {0};
+    for (int o = 0; o < H; ++o) {
+      double dz = dh2[o] * dsilu(z2[o]);
+      g[OB2 + o] += dz;
+      for (int i = 0; i < H; ++i) {
+        g[OW2 + o * H + i] += dz * h1[i];
+        dh1[i] += dz * p[OW2 + o * H + i];
+      }
+    }
+    /* layer 1 */
+    for (int o = 0; o < H; ++o) {
+      double dz = dh1[o] * dsilu(z1[o]);
+      g[OB1 + o] += dz;
+      for (int i = 0; i < NI; ++i) g[OW1 + o * NI + i] += dz * xs[i];
+    }
+  }
+  return loss;
+}
