@@ -2,8 +2,11 @@
  * FP64 reference of the learned Ewald surrogate (a small MLP standing in for
  * the Ewald correction table).  TEST INFRASTRUCTURE ONLY (see octoracle.h).
  *
- * Network: 3 -> 64 -> 64 -> 64 -> 4, SiLU after the three hidden layers,
- * identity output.  Parameter vector layout (8836 values):
+ * Network: 3 -> 64 -> 64 -> 64 -> 4, the gated activation f(z) = z S(z)
+ * after the three hidden layers, identity output.  S is the cubic smoothstep
+ * rising from 0 at z = -3 to 1 at z = 3: S = t^2 (3 - 2t), t = clamp(z/6 + 1/2,
+ * 0, 1).  f is continuously differentiable, close to z sigma(z) (same slope at
+ * 0), and costs no exponential or reciprocal.  Parameter vector layout (8836 values):
  *   W1[64][3], b1[64], W2[64][64], b2[64], W3[64][64], b3[64], W4[4][64], b4[4]
  * (row-major, W[out][in]).  Loss over a batch of B samples: mean squared error
  * over the 4 outputs, L = 1/(4B) sum_s sum_o (y_so - t_so)^2.
@@ -18,10 +21,18 @@ enum { H = 64, NI = 3, NO = 4 };
 enum { OW1 = 0, OB1 = OW1 + H * NI, OW2 = OB1 + H, OB2 = OW2 + H * H, OW3 = OB2 + H,
        OB3 = OW3 + H * H, OW4 = OB3 + H, OB4 = OW4 + NO * H, NPARAM = OB4 + NO };
 
-static double silu(double z) { return z / (1.0 + exp(-z)); }
-static double dsilu(double z) {
-  double s = 1.0 / (1.0 + exp(-z));
-  return s * (1.0 + z * (1.0 - s));
+static double gate_t(double z) {
+  double t = z / 6.0 + 0.5;
+  return t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+}
+static double act(double z) {
+  double t = gate_t(z);
+  return z * t * t * (3.0 - 2.0 * t);
+}
+/* f'(z) = S + z S'(z), S'(z) = t (1 - t) (zero outside [-3, 3]) */
+static double dact(double z) {
+  double t = gate_t(z);
+  return t * t * (3.0 - 2.0 * t) + z * t * (1.0 - t);
 }
 
 int or_mlp_nparam(void) { return NPARAM; }
@@ -34,19 +45,19 @@ static void forward1(const double *p, const double *x, double z1[H], double z2[H
     double a = p[OB1 + o];
     for (int i = 0; i < NI; ++i) a += p[OW1 + o * NI + i] * x[i];
     z1[o] = a;
-    h1[o] = silu(a);
+    h1[o] = act(a);
   }
   for (int o = 0; o < H; ++o) {
     double a = p[OB2 + o];
     for (int i = 0; i < H; ++i) a += p[OW2 + o * H + i] * h1[i];
     z2[o] = a;
-    h2[o] = silu(a);
+    h2[o] = act(a);
   }
   for (int o = 0; o < H; ++o) {
     double a = p[OB3 + o];
     for (int i = 0; i < H; ++i) a += p[OW3 + o * H + i] * h2[i];
     z3[o] = a;
-    h3[o] = silu(a);
+    h3[o] = act(a);
   }
   for (int o = 0; o < NO; ++o) {
     double a = p[OB4 + o];
@@ -74,9 +85,9 @@ double or_mlp_grad(const double *p, int64_t B, const double *x, const double *t,
     forward1(p, xs, z1, z2, z3, y);
     double h1[H], h2[H], h3[H];
     for (int i = 0; i < H; ++i) {
-      h1[i] = silu(z1[i]);
-      h2[i] = silu(z2[i]);
-      h3[i] = silu(z3[i]);
+      h1[i] = act(z1[i]);
+      h2[i] = act(z2[i]);
+      h3[i] = act(z3[i]);
     }
     double dy[NO];
     for (int o = 0; o < NO; ++o) {
@@ -96,7 +107,7 @@ double or_mlp_grad(const double *p, int64_t B, const double *x, const double *t,
     /* layer 3 */
     double dh2[H] = {0};
     for (int o = 0; o < H; ++o) {
-      double dz = dh3[o] * dsilu(z3[o]);
+      double dz = dh3[o] * dact(z3[o]);
       g[OB3 + o] += dz;
       for (int i = 0; i < H; ++i) {
         g[OW3 + o * H + i] += dz * h2[i];
@@ -106,7 +117,7 @@ double or_mlp_grad(const double *p, int64_t B, const double *x, const double *t,
     /* layer 2 */
     double dh1[H] = {0};
     for (int o = 0; o < H; ++o) {
-      double dz = dh2[o] * dsilu(z2[o]);
+      double dz = dh2[o] * dact(z2[o]);
       g[OB2 + o] += dz;
       for (int i = 0; i < H; ++i) {
         g[OW2 + o * H + i] += dz * h1[i];
@@ -115,7 +126,7 @@ double or_mlp_grad(const double *p, int64_t B, const double *x, const double *t,
     }
     /* layer 1 */
     for (int o = 0; o < H; ++o) {
-      double dz = dh1[o] * dsilu(z1[o]);
+      double dz = dh1[o] * dact(z1[o]);
       g[OB1 + o] += dz;
       for (int i = 0; i < NI; ++i) g[OW1 + o * NI + i] += dz * xs[i];
     }

@@ -22,11 +22,24 @@ def _numpy_forward(p, x):
     b3 = p[o:o + 64]; o += 64
     W4 = p[o:o + 256].reshape(4, 64); o += 256
     b4 = p[o:o + 4]
-    silu = lambda z: z / (1 + np.exp(-z))
-    h = silu(x @ W1.T + b1)
-    h = silu(h @ W2.T + b2)
-    h = silu(h @ W3.T + b3)
+    def act(z):
+        t = np.clip(z / 6 + 0.5, 0, 1)
+        return z * t * t * (3 - 2 * t)
+    h = act(x @ W1.T + b1)
+    h = act(h @ W2.T + b2)
+    h = act(h @ W3.T + b3)
     return h @ W4.T + b4
+
+
+def _chain_params():
+    """A network whose output 0 is f(f(f(x0))) for the activation f: one path
+    of unit weights through neuron 0 of every layer, everything else zero."""
+    p = np.zeros(oracle.MLP_NPARAM)
+    p[0] = 1.0                      # W1[0][0]
+    p[256] = 1.0                    # W2[0][0]
+    p[256 + 4096 + 64] = 1.0        # W3[0][0]
+    p[256 + 2 * (4096 + 64)] = 1.0  # W4[0][0]
+    return p
 
 
 def test_forward_matches_layer_formulas():
@@ -53,3 +66,28 @@ def test_gradient_vs_central_differences():
         lm = ((oracle.mlp_forward(q, x) - t) ** 2).mean()
         fd = (lp - lm) / (2 * eps)
         assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(g).max()), i
+
+
+def test_activation_special_values():
+    """f(z) = z for z >= 3, 0 for z <= -3, f(1) = 20/27 (t = 2/3, S = 20/27),
+    f(-1) = -7/27 (t = 1/3, S = 7/27), f(0) = 0; checked through a chain of
+    three activations."""
+    p = _chain_params()
+    x = np.array([[5.0, 0, 0], [3.0, 0, 0], [-4.0, 0, 0], [0.0, 0, 0], [1.0, 0, 0]])
+    y = oracle.mlp_forward(p, x)[:, 0]
+    f1 = 20 / 27
+    t = f1 / 6 + 0.5
+    f2 = f1 * t * t * (3 - 2 * t)
+    t = f2 / 6 + 0.5
+    f3 = f2 * t * t * (3 - 2 * t)
+    np.testing.assert_allclose(y, [5.0, 3.0, 0.0, 0.0, f3], rtol=0, atol=1e-15)
+    # one layer only: W2 and W3 paths replaced by exact pass-through of z >= 3
+    q = _chain_params()
+    q[192] = 10.0                   # b1[0]: pre-activation 10 + x0 stays > 3
+    y = oracle.mlp_forward(q, np.array([[-1.0, 0, 0]]))[0, 0]
+    assert y == 9.0
+    # f(-1) through the first layer, then shifted up by +10 in layer 2
+    q = _chain_params()
+    q[256 + 4096] = 10.0            # b2[0]
+    y = oracle.mlp_forward(q, np.array([[-1.0, 0, 0]]))[0, 0]
+    assert abs(y - (10.0 - 7 / 27)) < 1e-14
