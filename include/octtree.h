@@ -49,7 +49,11 @@ typedef enum {
 
 typedef enum { OT_BC_ISOLATED = 0, OT_BC_PERIODIC = 1 } ot_bc;
 typedef enum { OT_MAC_BH = 0, OT_MAC_APE = 1 } ot_mac;
-typedef enum { OT_EWALD_TABLE = 0, OT_EWALD_EXACT = 1 } ot_ewald;
+/* TABLE: FP64-generated table with the Taylor term (Sec. 2.2.4, second
+ * approach); EXACT: the FP64 series itself (point evaluation only); MLP: the
+ * learned surrogate once ot_mlp_train (or ot_mlp_set) has accepted it, else
+ * the table. */
+typedef enum { OT_EWALD_TABLE = 0, OT_EWALD_EXACT = 1, OT_EWALD_MLP = 2 } ot_ewald;
 
 /* Solver parameters; defaults (ot_params_default) follow App. B where the
  * paper gives one. */
@@ -64,8 +68,9 @@ typedef struct {
   double theta_lim;      /* BH opening angle, Eq. (1), gr_bhTreeLimAngle        [0.5]  */
   double eta_sb;         /* safe-box factor, Sec. 2.1, gr_bhTreeSafeBox         [1.2]  */
   int32_t mac;           /* ot_mac; APE uses Eq. (6) with p = 1, Eq. (4)        [BH]   */
-  int32_t ewald;         /* ot_ewald: correction from the table (Sec. 2.2.4,
-                            second approach) or the exact series per pair      [TABLE] */
+  int32_t ewald;         /* ot_ewald: correction in the walk: TABLE or MLP (the
+                            FP32 walk without columns; every other walk uses the
+                            table); EXACT is rejected by the walk               [TABLE] */
   double a_lim;          /* APE absolute limit, Eq. (4); <= 0: a_lim = eps_lim *
                             a_max from a BH (theta_lim) FP64 pass, Sec. 3      [0]    */
   double eps_lim;        /* relative device of Sec. 3 for a_lim                 [1e-3] */
@@ -99,6 +104,9 @@ typedef struct {
   double ms_build;         /* tree build (moments), device time              */
   double ms_list;          /* interaction-list construction, device time      */
   double ms_eval;          /* per-cell evaluation, device time               */
+  int32_t ewald_used;      /* ot_ewald the evaluation used (TABLE or MLP; TABLE
+                              also for isolated boundaries)                   */
+  int32_t pad_;
 } ot_stats;
 
 void ot_params_default(ot_params *p);
@@ -146,6 +154,73 @@ ot_status ot_solve64(ot_ctx *c, double *phi_dev, double *acc_dev, double *npix_d
  * the first solve that needs it; this call builds it eagerly.  Only for
  * periodic or mixed boundaries (OT_ERR_STATE otherwise). */
 ot_status ot_ewald_prepare(ot_ctx *c, void *stream);
+
+/* ---- learned Ewald surrogate --------------------------------------------
+ * Not part of the paper: a network 3 -> 64 -> 64 -> 64 -> 4 (activation
+ * z S(z), S the cubic smoothstep over [-3, 3]) maps the folded offset to
+ * (phi_c, A_c) in place of the table of Sec. 2.2.4, which stays the fallback
+ * and the judge of its error.  Trained on the device in FP32 (Adam, batch MSE
+ * on standardised outputs) on FP64 series values at offsets drawn uniformly
+ * from the folded domain; evaluated with FP16-input / FP32-accumulate matrix
+ * instructions. */
+typedef struct {
+  int64_t nsamples;  /* training offsets; multiple of 32                    [2097152] */
+  int64_t nval;      /* held-out offsets for validation                     [100000]  */
+  int32_t epochs;    /* passes over the training offsets                    [100]     */
+  int32_t batch;     /* offsets per Adam step; multiple of 32, <= nsamples  [2048]    */
+  double lr_max;     /* Adam step size, cosine decay from lr_max ...        [3e-3]    */
+  double lr_min;     /* ... to lr_min over all steps                        [1e-5]    */
+  uint64_t seed;     /* counter-based streams: init, training and held-out  [4]       */
+  double tol;        /* accepted when every channel's held-out error is at
+                        most tol (max |error| / max |exact value|)         [5e-3]    */
+} ot_mlp_config;
+
+typedef struct {
+  double loss_first;    /* mean batch loss of the first epoch (standardised)  */
+  double loss_last;     /* mean batch loss of the last epoch                  */
+  double err_mlp[4];    /* held-out error per channel (phi_c, A_c x, y, z)    */
+  double err_table[4];  /* the same for this context's FP64 table             */
+  double ms_samples;    /* series evaluation of the training offsets          */
+  double ms_train;      /* all Adam steps                                     */
+  double ms_validate;   /* held-out evaluation                                */
+  int32_t ok;           /* 1: accepted, the walk uses it for OT_EWALD_MLP     */
+  int32_t pad_;
+} ot_mlp_report;
+
+#define OT_MLP_NPARAM 8836 /* W1[64][3] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[4][64] b4[4] */
+#define OT_MLP_NNORM 11    /* ext[3] (x = 2 u / ext - 1), mu[4], sig[4] (y = (out - mu) / sig) */
+
+void ot_mlp_config_default(ot_mlp_config *cfg);
+
+/* Generate the training and held-out offsets, their FP64 series values, train,
+ * validate against the series and the table, and accept or reject the
+ * surrogate.  Periodic or mixed boundaries only (OT_ERR_STATE).  Synchronous;
+ * the training buffers are freed before returning.  report may be NULL. */
+ot_status ot_mlp_train(ot_ctx *c, const ot_mlp_config *cfg, ot_mlp_report *report, void *stream);
+
+/* Current surrogate: params_host [OT_MLP_NPARAM], norm_host [OT_MLP_NNORM]
+ * (either may be NULL).  OT_ERR_STATE before training or ot_mlp_set. */
+ot_status ot_mlp_get(ot_ctx *c, float *params_host, double *norm_host);
+
+/* Install a surrogate (host arrays as in ot_mlp_get); accept != 0 lets the
+ * walk use it.  sig must be > 0 and ext > 0. */
+ot_status ot_mlp_set(ot_ctx *c, const float *params_host, const double *norm_host, int32_t accept,
+                     void *stream);
+
+/* Batch loss and gradient of the training objective at params_dev [NPARAM]
+ * over x_dev [batch][3] (network inputs) and t_dev [batch][4] (standardised
+ * targets): L = 1/(4 batch) sum (y - t)^2.  grad_dev [NPARAM]; *loss_host
+ * gets L.  batch a multiple of 32.  Device pointers are the caller's. */
+ot_status ot_mlp_grad(ot_ctx *c, const float *params_dev, int64_t batch, const float *x_dev,
+                      const float *t_dev, float *grad_dev, float *loss_host, void *stream);
+
+/* The correction (phi_c, A_c) at offsets d_dev [n][3] (any sign; folded and
+ * unfolded inside) into out_dev [n][4], FP64, by method: OT_EWALD_EXACT
+ * (series), OT_EWALD_TABLE (FP64 table with the Taylor term) or OT_EWALD_MLP
+ * (the installed surrogate, accepted or not).  2P1I beyond |dz| = 2 Lx: the
+ * analytic limit for every method, minus 1/r and d/r^3. */
+ot_status ot_ewald_points(ot_ctx *c, int32_t method, int64_t n, const double *d_dev, double *out_dev,
+                          void *stream);
 
 /* ---- inspection (tests, tools) ---- */
 /* Number of amr nodes (all blocks, leaf or not) after ot_set_blocks. */

@@ -45,10 +45,30 @@ class Params(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("n_interactions", C.c_int64), ("max_list", C.c_int64), ("total_list", C.c_int64),
                 ("a_lim_used", C.c_double), ("ms_build", C.c_double), ("ms_list", C.c_double),
-                ("ms_eval", C.c_double)]
+                ("ms_eval", C.c_double), ("ewald_used", C.c_int32), ("pad_", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+
+
+class MlpConfig(C.Structure):
+    _fields_ = [("nsamples", C.c_int64), ("nval", C.c_int64), ("epochs", C.c_int32), ("batch", C.c_int32),
+                ("lr_max", C.c_double), ("lr_min", C.c_double), ("seed", C.c_uint64), ("tol", C.c_double)]
+
+
+class MlpReport(C.Structure):
+    _fields_ = [("loss_first", C.c_double), ("loss_last", C.c_double), ("err_mlp", C.c_double * 4),
+                ("err_table", C.c_double * 4), ("ms_samples", C.c_double), ("ms_train", C.c_double),
+                ("ms_validate", C.c_double), ("ok", C.c_int32), ("pad_", C.c_int32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+        d["err_mlp"], d["err_table"] = list(self.err_mlp), list(self.err_table)
+        return d
+
+
+MLP_NPARAM, MLP_NNORM = 8836, 11
+EWALD = {"table": 0, "exact": 1, "mlp": 2}
 
 
 _lib = None
@@ -58,6 +78,10 @@ def lib():
     """Load libocttree.so (built in-tree by __graft_entry__.build())."""
     global _lib
     if _lib is None:
+        # torch's HIP runtime has the same soname as the system one; loading
+        # torch first makes the library bind to it, so that the streams and
+        # device memory torch hands over belong to the runtime the library uses
+        import torch  # noqa: F401
         if not os.path.exists(LIBPATH):
             raise RuntimeError(f"{LIBPATH} is missing: build it with __graft_entry__.build()")
         L = C.CDLL(LIBPATH)
@@ -76,12 +100,19 @@ def lib():
         L.ot_export_moments.argtypes = [vp, vp, vp]
         L.ot_export_list.argtypes = [vp, i64, vp, i64, C.POINTER(i64)]
         L.ot_export_ewald_table.argtypes = [vp, vp]
+        L.ot_mlp_config_default.argtypes = [C.POINTER(MlpConfig)]
+        L.ot_mlp_train.argtypes = [vp, C.POINTER(MlpConfig), C.POINTER(MlpReport), vp]
+        L.ot_mlp_get.argtypes = [vp, vp, vp]
+        L.ot_mlp_set.argtypes = [vp, vp, vp, C.c_int32, vp]
+        L.ot_mlp_grad.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
+        L.ot_ewald_points.argtypes = [vp, C.c_int32, i64, vp, vp, vp]
         L.ot_last_error.restype = C.c_char_p
         L.ot_last_error.argtypes = [vp]
         L.ot_destroy.argtypes = [vp]
         for name in ("ot_create", "ot_set_blocks", "ot_build", "ot_solve", "ot_solve64",
                      "ot_ewald_prepare", "ot_export_topology", "ot_export_moments",
-                     "ot_export_list", "ot_export_ewald_table", "ot_export_raytable"):
+                     "ot_export_list", "ot_export_ewald_table", "ot_export_raytable", "ot_mlp_train",
+                     "ot_mlp_get", "ot_mlp_set", "ot_mlp_grad", "ot_ewald_points"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -125,7 +156,7 @@ def make_params(nroot=(1, 1, 1), root_size=1.0, origin=(0.0, 0.0, 0.0), bc=(0, 0
         p.nroot[k], p.bc[k], p.origin[k] = int(nroot[k]), int(bc[k]), float(origin[k])
     p.root_size, p.G, p.theta_lim, p.eta_sb = float(root_size), float(G), float(theta), float(eta_sb)
     p.mac = MAC[mac]
-    p.ewald = {"table": 0, "exact": 1}[ewald]
+    p.ewald = EWALD[ewald]
     p.a_lim, p.eps_lim = float(a_lim), float(eps_lim)
     p.ewald_n, p.ewald_rcut2, p.ewald_fcut2 = int(ewald_n), int(ewald_rcut2), int(ewald_fcut2)
     p.ewald_alpha, p.device, p.max_device_bytes = float(ewald_alpha), int(device), int(max_device_bytes)
@@ -211,6 +242,48 @@ class Solver:
 
     def ewald_prepare(self, stream=None):
         self._check(lib().ot_ewald_prepare(self.h, _stream(stream)))
+
+    # ---- learned Ewald surrogate
+    def mlp_train(self, stream=None, **cfg):
+        """Train, validate and accept or reject the surrogate; returns the report
+        as a dict.  Keyword arguments override ot_mlp_config_default."""
+        c = MlpConfig()
+        lib().ot_mlp_config_default(C.byref(c))
+        for k, v in cfg.items():
+            if k not in dict(MlpConfig._fields_):
+                raise TypeError(f"unknown surrogate setting {k}")
+            setattr(c, k, v)
+        r = MlpReport()
+        self._check(lib().ot_mlp_train(self.h, C.byref(c), C.byref(r), _stream(stream)))
+        return r.as_dict()
+
+    def mlp_get(self):
+        p, n = np.empty(MLP_NPARAM, np.float32), np.empty(MLP_NNORM)
+        self._check(lib().ot_mlp_get(self.h, _np_ptr(p), _np_ptr(n)))
+        return p, n
+
+    def mlp_set(self, params, norm, accept=True, stream=None):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        n = np.ascontiguousarray(norm, dtype=np.float64)
+        if p.shape != (MLP_NPARAM,) or n.shape != (MLP_NNORM,):
+            raise ValueError("params [8836] and norm [11] expected")
+        self._check(lib().ot_mlp_set(self.h, _np_ptr(p), _np_ptr(n), int(bool(accept)), _stream(stream)))
+
+    def mlp_grad(self, params, x, t, grad, stream=None):
+        """Batch loss and gradient on the device; returns the loss."""
+        import torch
+        f = torch.float32
+        loss = C.c_float(0.0)
+        self._check(lib().ot_mlp_grad(self.h, _dev_ptr(params, f), int(x.shape[0]), _dev_ptr(x, f),
+                                      _dev_ptr(t, f), _dev_ptr(grad, f), C.byref(loss), _stream(stream)))
+        return loss.value
+
+    def ewald_points(self, method, d, out, stream=None):
+        """Correction (phi_c, A_c) at device offsets d [n, 3] into out [n, 4]."""
+        import torch
+        f = torch.float64
+        self._check(lib().ot_ewald_points(self.h, EWALD[method], int(d.shape[0]), _dev_ptr(d, f),
+                                          _dev_ptr(out, f), _stream(stream)))
 
     # ---- inspection
     def export_topology(self):

@@ -21,6 +21,7 @@ SOURCES = {
     "k_eval.hip": [],
     "k_ewald.hip": [],
     "k_columns.hip": [],
+    "k_mlp.hip": [],
 }
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -1,6 +1,7 @@
 // C ABI of libocttree: parameter validation, device memory, and the order of
 // the solver phases (tree build -> interaction lists -> per-cell evaluation).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -360,6 +361,53 @@ ot_status ape_limit(ot_ctx *c, hipStream_t st, double *alim) {
   return OT_OK;
 }
 
+// ---------------------------------------------------------------- surrogate
+// A device buffer released when it goes out of scope (training scratch).
+struct Scoped {
+  ot_ctx *c;
+  DevBuf b;
+  explicit Scoped(ot_ctx *cc) : c(cc) {}
+  ~Scoped() { release(c, b); }
+  template <typename T>
+  T *p() { return static_cast<T *>(b.ptr); }
+};
+
+ot::MlpNorm mlp_norm_of(const ot_ctx *c) {
+  ot::MlpNorm N;
+  for (int k = 0; k < 3; ++k) N.ext[k] = c->mlp_norm[k];
+  for (int o = 0; o < 4; ++o) {
+    N.mu[o] = c->mlp_norm[3 + o];
+    N.sig[o] = c->mlp_norm[7 + o];
+  }
+  return N;
+}
+
+// pack the current parameters into the inference operands
+ot_status mlp_pack(ot_ctx *c, hipStream_t st) {
+  OTCHK(dalloc(c, c->mlp_pk, (size_t)ot::mlpdef::NPK * 64 * 16));
+  HIPCHK(ot::launch_mlp_pack(P<float>(c->mlp_P), mlp_norm_of(c), c->mlp_pk.ptr, st));
+  return OT_OK;
+}
+
+// correction at n device offsets by one method into out [n][4]
+ot_status ewald_points(ot_ctx *c, int method, int64_t n, const double *d, double *out, hipStream_t st) {
+  const ot::EwaldP E = ewald_desc(c);
+  if (method == OT_EWALD_MLP) {
+    if (!c->mlp_have) return fail(c, OT_ERR_STATE, "no surrogate installed");
+    HIPCHK(ot::launch_mlp_points_eval(c->mlp_pk.ptr, E, n, d, out, st));
+  } else {
+    HIPCHK(ot::launch_ewald_points4(method == OT_EWALD_EXACT ? 1 : 0, E, c->ew_alpha, c->ew_rcut2, c->ew_fcut2,
+                                    n, d, out, st));
+  }
+  return OT_OK;
+}
+
+ot_status mlp_grad_scratch(ot_ctx *c, int64_t batch) {
+  OTCHK(dalloc(c, c->mlp_part, (size_t)(batch / 32) * ot::mlpdef::NP * sizeof(float)));
+  OTCHK(dalloc(c, c->mlp_lossp, (size_t)(batch / 32) * sizeof(float)));
+  return OT_OK;
+}
+
 float elapsed(hipEvent_t a, hipEvent_t b) {
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return -1.f;
@@ -377,10 +425,11 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(c->p.device));
   if (c->bctype != ot::BC_ISO) {
-    if (c->p.ewald != OT_EWALD_TABLE)
+    if (c->p.ewald == OT_EWALD_EXACT)
       return fail(c, OT_ERR_UNSUPPORTED, "per-pair exact Ewald series is not built into the walk");
     OTCHK(ewald_prepare(c, st));
   }
+  const bool use_mlp = c->bctype != ot::BC_ISO && c->p.ewald == OT_EWALD_MLP && c->mlp_ok && !fp64 && !cols;
   if (cols) OTCHK(raytable_prepare(c, st));
   double alim = 0.0;
   if (c->p.mac == OT_MAC_APE) OTCHK(ape_limit(c, st, &alim));
@@ -399,6 +448,9 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
   } else if (fp64)
     HIPCHK(ot::launch_eval64(T, E, P<int64_t>(c->loff), P<double4>(c->lrec), (double *)phi,
                              (double *)acc, c->p.G, st));
+  else if (use_mlp)
+    HIPCHK(ot::launch_eval_mlp(T, E, c->mlp_pk.ptr, P<int64_t>(c->loff), P<double4>(c->lrec),
+                               P<int32_t>(c->lid), (float *)phi, (float *)acc, c->p.G, st));
   else
     HIPCHK(ot::launch_eval32(T, E, P<int64_t>(c->loff), P<double4>(c->lrec), P<int32_t>(c->lid),
                              (float *)phi, (float *)acc, c->p.G, st));
@@ -419,6 +471,7 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
     stats->ms_list = elapsed(c->ev[0], c->ev[1]);
     stats->ms_eval = elapsed(c->ev[1], c->ev[2]);
     stats->ms_build = c->ms_build;
+    stats->ewald_used = use_mlp ? OT_EWALD_MLP : OT_EWALD_TABLE;
   }
   return OT_OK;
 }
@@ -477,7 +530,8 @@ ot_status ot_create(const ot_params *p, ot_ctx **out) {
   if (!(p->theta_lim > 0) || !std::isfinite(p->theta_lim)) return bad("theta_lim must be > 0");
   if (!(p->eta_sb >= 0) || !std::isfinite(p->eta_sb)) return bad("eta_sb must be >= 0");
   if (p->mac != OT_MAC_BH && p->mac != OT_MAC_APE) return bad("unknown MAC");
-  if (p->ewald != OT_EWALD_TABLE && p->ewald != OT_EWALD_EXACT) return bad("unknown Ewald mode");
+  if (p->ewald != OT_EWALD_TABLE && p->ewald != OT_EWALD_EXACT && p->ewald != OT_EWALD_MLP)
+    return bad("unknown Ewald mode");
   if (p->mac == OT_MAC_APE && !(p->a_lim > 0) && !(p->eps_lim > 0)) return bad("APE needs a_lim > 0 or eps_lim > 0");
   if (p->ewald_n < 2 || p->ewald_n > 512) return bad("ewald_n must be in [2, 512]");
   if (p->nside != 0 && p->nside != 1 && p->nside != 2 && p->nside != 4) return bad("nside must be 0, 1, 2 or 4");
@@ -660,6 +714,222 @@ ot_status ot_export_ewald_table(ot_ctx *c, double *tab) {
   return OT_OK;
 }
 
+void ot_mlp_config_default(ot_mlp_config *cfg) {
+  if (!cfg) return;
+  memset(cfg, 0, sizeof(*cfg));
+  cfg->nsamples = 1 << 21;
+  cfg->nval = 100000;
+  cfg->epochs = 100;
+  cfg->batch = 2048;
+  cfg->lr_max = 3e-3;
+  cfg->lr_min = 1e-5;
+  cfg->seed = 4;
+  cfg->tol = 5e-3;
+}
+
+ot_status ot_mlp_train(ot_ctx *c, const ot_mlp_config *cfg, ot_mlp_report *rep, void *stream) {
+  using namespace ot::mlpdef;
+  if (!c) return OT_ERR_INVALID_ARG;
+  c->err.clear();
+  if (!cfg) return fail(c, OT_ERR_INVALID_ARG, "null config");
+  if (cfg->nsamples < 32 || cfg->nsamples % 32 || cfg->batch < 32 || cfg->batch % 32 ||
+      cfg->batch > cfg->nsamples || cfg->epochs < 1 || cfg->nval < 1 || !(cfg->lr_max > 0) ||
+      !(cfg->lr_min >= 0) || !(cfg->tol > 0))
+    return fail(c, OT_ERR_INVALID_ARG,
+                "surrogate training needs nsamples, batch multiples of 32 with batch <= nsamples, "
+                "epochs >= 1, nval >= 1, lr_max > 0, lr_min >= 0, tol > 0");
+  if (cfg->nsamples > ((int64_t)1 << 28) || cfg->nval > ((int64_t)1 << 26))
+    return fail(c, OT_ERR_INVALID_ARG, "nsamples <= 2^28 and nval <= 2^26");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->p.device));
+  OTCHK(ewald_prepare(c, st));
+  c->mlp_ok = false;
+  const int64_t n = cfg->nsamples, nv = cfg->nval;
+  auto now = [] { return std::chrono::steady_clock::now(); };
+  auto ms = [](auto a, auto b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
+  // training offsets and their series values
+  auto t0 = now();
+  Scoped u(c), ser(c), x(c), t(c), grad(c), m(c), v(c), losses(c);
+  OTCHK(dalloc(c, u.b, (size_t)n * 3 * sizeof(double)));
+  OTCHK(dalloc(c, ser.b, (size_t)n * 10 * sizeof(double)));
+  HIPCHK(ot::launch_mlp_points(cfg->seed * 3 + 1, n, c->ew_ext, u.p<double>(), st));
+  const ot::EwaldP E = ewald_desc(c);
+  HIPCHK(ot::launch_ewald_points(E, c->ew_alpha, c->ew_rcut2, c->ew_fcut2, n, u.p<double>(), ser.p<double>(), st));
+  // scaling: inputs to [-1, 1]; outputs standardised on the first offsets
+  const int64_t ns = std::min<int64_t>(n, 65536);
+  std::vector<double> hs((size_t)ns * 10);
+  HIPCHK(hipMemcpyAsync(hs.data(), ser.b.ptr, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int k = 0; k < 3; ++k) c->mlp_norm[k] = c->ew_ext[k];
+  for (int o = 0; o < 4; ++o) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int64_t q = 0; q < ns; ++q) s1 += hs[10 * q + o];
+    const double mu = s1 / (double)ns;
+    for (int64_t q = 0; q < ns; ++q) s2 += (hs[10 * q + o] - mu) * (hs[10 * q + o] - mu);
+    const double sig = std::sqrt(s2 / (double)ns);
+    c->mlp_norm[3 + o] = mu;
+    c->mlp_norm[7 + o] = sig > 0 ? sig : 1.0;
+  }
+  OTCHK(dalloc(c, x.b, (size_t)n * 3 * sizeof(float)));
+  OTCHK(dalloc(c, t.b, (size_t)n * 4 * sizeof(float)));
+  HIPCHK(ot::launch_mlp_prepare(n, u.p<double>(), ser.p<double>(), mlp_norm_of(c), x.p<float>(), t.p<float>(), st));
+  HIPCHK(hipStreamSynchronize(st));
+  release(c, ser.b);
+  release(c, u.b);
+  auto t1 = now();
+  // Adam with a cosine step size; each epoch starts at a different offset
+  const int64_t spe = n / cfg->batch, total = spe * cfg->epochs;
+  OTCHK(dalloc(c, c->mlp_P, NP * sizeof(float)));
+  OTCHK(dalloc(c, grad.b, NP * sizeof(float)));
+  OTCHK(dalloc(c, m.b, NP * sizeof(float)));
+  OTCHK(dalloc(c, v.b, NP * sizeof(float)));
+  OTCHK(dalloc(c, losses.b, (size_t)total * sizeof(float)));
+  OTCHK(mlp_grad_scratch(c, cfg->batch));
+  HIPCHK(hipMemsetAsync(m.b.ptr, 0, NP * sizeof(float), st));
+  HIPCHK(hipMemsetAsync(v.b.ptr, 0, NP * sizeof(float), st));
+  HIPCHK(ot::launch_mlp_init(cfg->seed * 3, P<float>(c->mlp_P), st));
+  c->mlp_have = false;
+  uint64_t rot = cfg->seed * 0x9E3779B97F4A7C15ull + 12345;
+  int64_t step = 0;
+  for (int e = 0; e < cfg->epochs; ++e) {
+    rot ^= rot << 13;
+    rot ^= rot >> 7;
+    rot ^= rot << 17;
+    const int64_t s0 = (int64_t)(rot % (uint64_t)(n / 32)) * 32;
+    for (int64_t k = 0; k < spe; ++k, ++step) {
+      HIPCHK(ot::launch_mlp_grad(P<float>(c->mlp_P), n, (s0 + k * cfg->batch) % n, cfg->batch, x.p<float>(),
+                                 t.p<float>(), P<float>(c->mlp_part), P<float>(c->mlp_lossp), grad.p<float>(),
+                                 losses.p<float>() + step, st));
+      const double lr = cfg->lr_min + 0.5 * (cfg->lr_max - cfg->lr_min) *
+                                          (1.0 + std::cos(M_PI * (double)step / (double)total));
+      HIPCHK(ot::launch_mlp_adam(P<float>(c->mlp_P), grad.p<float>(), m.p<float>(), v.p<float>(), (float)lr,
+                                 (int)std::min<int64_t>(step + 1, 1 << 30), st));
+    }
+  }
+  std::vector<float> hl((size_t)total);
+  HIPCHK(hipMemcpyAsync(hl.data(), losses.b.ptr, hl.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  release(c, x.b);
+  release(c, t.b);
+  c->mlp_have = true;
+  OTCHK(mlp_pack(c, st));
+  auto t2 = now();
+  // held-out validation against the series, with the table alongside
+  Scoped d(c), ex(c), ml(c), tb(c);
+  OTCHK(dalloc(c, d.b, (size_t)nv * 3 * sizeof(double)));
+  OTCHK(dalloc(c, ex.b, (size_t)nv * 4 * sizeof(double)));
+  OTCHK(dalloc(c, ml.b, (size_t)nv * 4 * sizeof(double)));
+  OTCHK(dalloc(c, tb.b, (size_t)nv * 4 * sizeof(double)));
+  HIPCHK(ot::launch_mlp_points(cfg->seed * 3 + 2, nv, c->ew_ext, d.p<double>(), st));
+  OTCHK(ewald_points(c, OT_EWALD_EXACT, nv, d.p<double>(), ex.p<double>(), st));
+  OTCHK(ewald_points(c, OT_EWALD_MLP, nv, d.p<double>(), ml.p<double>(), st));
+  OTCHK(ewald_points(c, OT_EWALD_TABLE, nv, d.p<double>(), tb.p<double>(), st));
+  std::vector<double> hx((size_t)nv * 4), hm((size_t)nv * 4), ht((size_t)nv * 4);
+  HIPCHK(hipMemcpyAsync(hx.data(), ex.b.ptr, hx.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(hm.data(), ml.b.ptr, hm.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(ht.data(), tb.b.ptr, ht.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double em[4], et[4];
+  bool ok = true;
+  for (int o = 0; o < 4; ++o) {
+    double mx = 0.0, dm = 0.0, dt = 0.0;
+    for (int64_t q = 0; q < nv; ++q) {
+      mx = std::max(mx, std::fabs(hx[4 * q + o]));
+      dm = std::max(dm, std::fabs(hm[4 * q + o] - hx[4 * q + o]));
+      dt = std::max(dt, std::fabs(ht[4 * q + o] - hx[4 * q + o]));
+    }
+    em[o] = mx > 0 ? dm / mx : dm;
+    et[o] = mx > 0 ? dt / mx : dt;
+    if (!(em[o] <= cfg->tol)) ok = false;
+  }
+  c->mlp_ok = ok;
+  auto t3 = now();
+  if (rep) {
+    memset(rep, 0, sizeof(*rep));
+    double a = 0.0, b = 0.0;
+    for (int64_t k = 0; k < spe; ++k) {
+      a += hl[k];
+      b += hl[total - spe + k];
+    }
+    rep->loss_first = a / (double)spe;
+    rep->loss_last = b / (double)spe;
+    for (int o = 0; o < 4; ++o) {
+      rep->err_mlp[o] = em[o];
+      rep->err_table[o] = et[o];
+    }
+    rep->ms_samples = ms(t0, t1);
+    rep->ms_train = ms(t1, t2);
+    rep->ms_validate = ms(t2, t3);
+    rep->ok = ok ? 1 : 0;
+  }
+  return OT_OK;
+}
+
+ot_status ot_mlp_get(ot_ctx *c, float *params, double *norm) {
+  if (!c) return OT_ERR_INVALID_ARG;
+  c->err.clear();
+  if (!c->mlp_have) return fail(c, OT_ERR_STATE, "no surrogate: train or set one first");
+  HIPCHK(hipSetDevice(c->p.device));
+  if (params) HIPCHK(hipMemcpy(params, c->mlp_P.ptr, ot::mlpdef::NP * sizeof(float), hipMemcpyDeviceToHost));
+  if (norm) memcpy(norm, c->mlp_norm, sizeof(c->mlp_norm));
+  return OT_OK;
+}
+
+ot_status ot_mlp_set(ot_ctx *c, const float *params, const double *norm, int32_t accept, void *stream) {
+  if (!c) return OT_ERR_INVALID_ARG;
+  c->err.clear();
+  if (!params || !norm) return fail(c, OT_ERR_INVALID_ARG, "null parameters or scaling");
+  for (int k = 0; k < 11; ++k)
+    if (!std::isfinite(norm[k]) || ((k < 3 || k >= 7) && !(norm[k] > 0)))
+      return fail(c, OT_ERR_INVALID_ARG, "scaling must be finite with ext > 0 and sig > 0");
+  for (int i = 0; i < ot::mlpdef::NP; ++i)
+    if (!std::isfinite(params[i])) return fail(c, OT_ERR_INVALID_ARG, "non-finite parameter");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->p.device));
+  OTCHK(dalloc(c, c->mlp_P, ot::mlpdef::NP * sizeof(float)));
+  HIPCHK(hipMemcpyAsync(c->mlp_P.ptr, params, ot::mlpdef::NP * sizeof(float), hipMemcpyHostToDevice, st));
+  memcpy(c->mlp_norm, norm, sizeof(c->mlp_norm));
+  c->mlp_have = true;
+  OTCHK(mlp_pack(c, st));
+  HIPCHK(hipStreamSynchronize(st));
+  c->mlp_ok = accept != 0;
+  return OT_OK;
+}
+
+ot_status ot_mlp_grad(ot_ctx *c, const float *params, int64_t batch, const float *x, const float *t, float *grad,
+                      float *loss, void *stream) {
+  if (!c) return OT_ERR_INVALID_ARG;
+  c->err.clear();
+  if (!params || !x || !t || !grad || !loss) return fail(c, OT_ERR_INVALID_ARG, "null pointer");
+  if (batch < 32 || batch % 32 || batch > ((int64_t)1 << 24))
+    return fail(c, OT_ERR_INVALID_ARG, "batch must be a positive multiple of 32, <= 2^24");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->p.device));
+  OTCHK(mlp_grad_scratch(c, batch));
+  OTCHK(dalloc(c, c->mlp_loss, sizeof(float)));
+  HIPCHK(ot::launch_mlp_grad(params, batch, 0, batch, x, t, P<float>(c->mlp_part), P<float>(c->mlp_lossp), grad,
+                             P<float>(c->mlp_loss), st));
+  HIPCHK(hipMemcpyAsync(loss, c->mlp_loss.ptr, sizeof(float), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return OT_OK;
+}
+
+ot_status ot_ewald_points(ot_ctx *c, int32_t method, int64_t n, const double *d, double *out, void *stream) {
+  if (!c) return OT_ERR_INVALID_ARG;
+  c->err.clear();
+  if (method != OT_EWALD_TABLE && method != OT_EWALD_EXACT && method != OT_EWALD_MLP)
+    return fail(c, OT_ERR_INVALID_ARG, "unknown method");
+  if (n < 0 || (n > 0 && (!d || !out))) return fail(c, OT_ERR_INVALID_ARG, "bad size or null pointer");
+  if (n > ((int64_t)1 << 30)) return fail(c, OT_ERR_INVALID_ARG, "n > 2^30");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->p.device));
+  OTCHK(ewald_prepare(c, st));
+  if (n == 0) return OT_OK;
+  OTCHK(ewald_points(c, method, n, d, out, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return OT_OK;
+}
+
 const char *ot_last_error(const ot_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 void ot_destroy(ot_ctx *c) {
@@ -669,7 +939,8 @@ void ot_destroy(ot_ctx *c) {
                    &c->bamr, &c->amc,    &c->aS,      &c->btmc,  &c->cm,     &c->flag,
                    &c->lcount, &c->loff, &c->lrec,    &c->lid,   &c->lscratch, &c->tab64,
                    &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_rows, &c->rt_ent,
-                   &c->rt_thr, &c->lh};
+                   &c->rt_thr, &c->lh, &c->mlp_P, &c->mlp_pk, &c->mlp_part, &c->mlp_lossp,
+                   &c->mlp_loss};
   for (DevBuf *b : all) release(c, *b);
   for (int i = 0; i < 4; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);

@@ -70,5 +70,10 @@ struct ot_ctx {
   ot::DevBuf rt_off, rt_pix, rt_w64, rt_rows, rt_ent, rt_thr, lh;
   bool rt_ready = false;
   int64_t rt_pairs = 0;
+  // learned Ewald surrogate: FP32 parameters, packed FP16 operands, the
+  // input / output scaling (ext[3], mu[4], sig[4]) and gradient scratch
+  ot::DevBuf mlp_P, mlp_pk, mlp_part, mlp_lossp, mlp_loss;
+  bool mlp_have = false, mlp_ok = false;
+  double mlp_norm[11] = {0};
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };

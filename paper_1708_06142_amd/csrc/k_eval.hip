@@ -20,6 +20,7 @@
 // every thread then reads as broadcasts.  The FP32 kernel accumulates Phi with
 // Kahan compensation and the acceleration in plain FP32.
 #include "common.hpp"
+#include "ewald_lookup.hpp"
 #include "kernels.hpp"
 
 namespace ot {
@@ -57,23 +58,12 @@ __device__ inline void pair64(const EwaldP &E, double cx, double cy, double cz, 
     A2 = dz < 0 ? -E.far_az : E.far_az;
   } else {
     const double u[3] = {fabs(dx), fabs(dy), fabs(dz)};
-    int g[3];
-    double dl[3];
-    for (int k = 0; k < 3; ++k) {
-      int gi = (int)floor(u[k] / E.step[k] + 0.5);
-      gi = gi > E.n - 1 ? E.n - 1 : gi;
-      g[k] = gi;
-      dl[k] = u[k] - gi * E.step[k];
-    }
-    const double *T = E.tab64 + 10 * (((int64_t)g[2] * E.n + g[1]) * E.n + g[0]);
-    const double phic = T[0] - (T[1] * dl[0] + T[2] * dl[1] + T[3] * dl[2]);
-    double a0 = T[1] - (T[4] * dl[0] + T[7] * dl[1] + T[8] * dl[2]);
-    double a1 = T[2] - (T[7] * dl[0] + T[5] * dl[1] + T[9] * dl[2]);
-    double a2 = T[3] - (T[8] * dl[0] + T[9] * dl[1] + T[6] * dl[2]);
+    double phic, a[3];
+    table_taylor64(E, u, phic, a);
     phi = inv + phic;
-    A0 = dx * inv3 + (dx < 0 ? -a0 : a0);
-    A1 = dy * inv3 + (dy < 0 ? -a1 : a1);
-    A2 = dz * inv3 + (dz < 0 ? -a2 : a2);
+    A0 = dx * inv3 + (dx < 0 ? -a[0] : a[0]);
+    A1 = dy * inv3 + (dy < 0 ? -a[1] : a[1]);
+    A2 = dz * inv3 + (dz < 0 ? -a[2] : a[2]);
   }
   sp += r.w * phi;
   ax += r.w * A0;

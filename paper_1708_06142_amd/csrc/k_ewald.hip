@@ -12,6 +12,7 @@
 // |gamma| (even; the first derivative is odd), and the regularised l = 0 term
 // I(0,0) of Eq. 14.
 #include "common.hpp"
+#include "ewald_lookup.hpp"
 #include "kernels.hpp"
 
 namespace ot {
@@ -89,18 +90,12 @@ __device__ inline void add_radial(const Radial &R, double x, double y, double z,
   o.v[9] += R.D2 * y * z;
 }
 
-__global__ __launch_bounds__(128) void k_ewald_table(EwaldP E, double alpha, int rcut2, int fcut2,
-                                                     double *__restrict__ tab64,
-                                                     float4 *__restrict__ tab32) {
-  const int64_t n = E.n;
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n * n * n) return;
-  const int ix = (int)(q % n), iy = (int)((q / n) % n), iz = (int)(q / (n * n));
-  const double u[3] = {ix * E.step[0], iy * E.step[1], iz * E.step[2]};
+// phi_c, A_c and the Hessian of phi_c at folded offset u (all components >= 0)
+__device__ inline void ewald_point(const EwaldP &E, double alpha, int rcut2, int fcut2, const double u[3],
+                                   Acc10 &o) {
   const double Lx = E.L[0], b = E.L[1] / E.L[0], c = E.L[2] / E.L[0];
   const double zeta = (PI * PI) / ((alpha * Lx) * (alpha * Lx));
   const bool three = E.bctype == 1;
-  Acc10 o;
   for (int k = 0; k < 10; ++k) o.v[k] = 0.0;
 
   const double rr = sqrt((double)rcut2);
@@ -188,6 +183,18 @@ __global__ __launch_bounds__(128) void k_ewald_table(EwaldP E, double alpha, int
         o.v[9] -= k2 * q1 * sv * I1;
       }
   }
+}
+
+__global__ __launch_bounds__(128) void k_ewald_table(EwaldP E, double alpha, int rcut2, int fcut2,
+                                                     double *__restrict__ tab64,
+                                                     float4 *__restrict__ tab32) {
+  const int64_t n = E.n;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n * n * n) return;
+  const int ix = (int)(q % n), iy = (int)((q / n) % n), iz = (int)(q / (n * n));
+  const double u[3] = {ix * E.step[0], iy * E.step[1], iz * E.step[2]};
+  Acc10 o;
+  ewald_point(E, alpha, rcut2, fcut2, u, o);
   double *t = tab64 + 10 * q;
   for (int k = 0; k < 10; ++k) t[k] = o.v[k];
   tab32[3 * q + 0] = make_float4((float)o.v[0], (float)o.v[1], (float)o.v[2], (float)o.v[3]);
@@ -195,7 +202,69 @@ __global__ __launch_bounds__(128) void k_ewald_table(EwaldP E, double alpha, int
   tab32[3 * q + 2] = make_float4((float)o.v[8], (float)o.v[9], 0.0f, 0.0f);
 }
 
+// the same series at arbitrary folded offsets u [n][3] -> out [n][10]
+__global__ __launch_bounds__(128) void k_ewald_points(EwaldP E, double alpha, int rcut2, int fcut2, int64_t n,
+                                                      const double *__restrict__ u, double *__restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const double uq[3] = {fabs(u[3 * q]), fabs(u[3 * q + 1]), fabs(u[3 * q + 2])};
+  Acc10 o;
+  ewald_point(E, alpha, rcut2, fcut2, uq, o);
+  for (int k = 0; k < 10; ++k) out[10 * q + k] = o.v[k];
+}
+
+// correction (phi_c, signed A_c) at offsets d [n][3]: method 1 = FP64 series,
+// 0 = FP64 table with the Taylor term; 2P1I beyond |dz| = zfar: the limit
+__global__ __launch_bounds__(128) void k_ewald_points4(int method, EwaldP E, double alpha, int rcut2, int fcut2,
+                                                       int64_t n, const double *__restrict__ d,
+                                                       double *__restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const double dx = d[3 * q], dy = d[3 * q + 1], dz = d[3 * q + 2];
+  double *o = out + 4 * q;
+  if (E.bctype == 2 && fabs(dz) > E.zfar) {
+    // the limit replaces the whole interaction; report it minus 1/r
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    o[0] = E.far_phi_a * fabs(dz) + E.far_phi_b - 1.0 / r;
+    const double r3 = r * r * r;
+    o[1] = -dx / r3;
+    o[2] = -dy / r3;
+    o[3] = (dz < 0 ? -E.far_az : E.far_az) - dz / r3;
+    return;
+  }
+  const double u[3] = {fabs(dx), fabs(dy), fabs(dz)};
+  double phic, a[3];
+  if (method == 1) {
+    Acc10 s;
+    ewald_point(E, alpha, rcut2, fcut2, u, s);
+    phic = s.v[0];
+    a[0] = s.v[1];
+    a[1] = s.v[2];
+    a[2] = s.v[3];
+  } else {
+    table_taylor64(E, u, phic, a);
+  }
+  o[0] = phic;
+  o[1] = dx < 0 ? -a[0] : a[0];
+  o[2] = dy < 0 ? -a[1] : a[1];
+  o[3] = dz < 0 ? -a[2] : a[2];
+}
+
 }  // namespace
+
+hipError_t launch_ewald_points4(int method, const EwaldP &E, double alpha, int rcut2, int fcut2, int64_t n,
+                                const double *d, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_ewald_points4, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, method, E, alpha, rcut2,
+                     fcut2, n, d, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ewald_points(const EwaldP &E, double alpha, int rcut2, int fcut2, int64_t n, const double *u,
+                               double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_ewald_points, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, E, alpha, rcut2, fcut2,
+                     n, u, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_ewald_table(const EwaldP &E, double alpha, int rcut2, int fcut2, double *tab64,
                               float4 *tab32, hipStream_t st) {

@@ -1,0 +1,607 @@
+// Learned surrogate of the Ewald correction.  It is not part of the paper: it
+// stands in for the look-up table of Sec. 2.2.4, which stays the fallback and
+// the judge of its error.
+//
+// Network 3 -> 64 -> 64 -> 64 -> 4 with the activation f(z) = z S(z), S the
+// cubic smoothstep from 0 at z = -3 to 1 at z = 3, after each hidden layer.
+// Input: the folded offset u (all components >= 0) scaled to [-1, 1] per
+// axis; output: (phi_c, A_c) standardised per channel.  Parameters (8836 FP32):
+//   W1[64][3] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[4][64] b4[4].
+//
+// Training (FP32): one workgroup runs forward and backward for 32 samples with
+// all activations in LDS and writes its partial gradient; a second kernel sums
+// the partials in a fixed order (deterministic); Adam updates the parameters.
+// Loss: mean squared error over the 4 outputs of the batch.
+//
+// Inference: every layer runs on the matrix cores in the transposed form
+// h_next = W h, with the weights as the A operand and the 32 pairs of a batch
+// as the columns of B, FP16 inputs and FP32 accumulation
+// (v_mfma_f32_32x32x16_f16).  In that orientation the 32x32 output tile of one
+// layer sits in each lane where the next layer's B operand needs it, up to a
+// fixed permutation of the contraction index that is applied to the packed
+// weights instead.  Biases enter as an extra contraction chunk against a
+// constant (1, 1) input, split into FP16 high and low parts; the input scaling
+// is folded into the first layer and the output de-standardisation into the
+// last.  In the first layer the offset and the weights are both split into
+// FP16 high and low parts (the three products that matter fill the 16-deep
+// contraction), so the inputs lose no precision to FP16; the hidden
+// activations and the other weights are rounded to FP16.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace ot {
+
+namespace {
+
+using namespace mlpdef;
+
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ inline uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+// counter-based uniform in [0, 1): stream `seed`, counter i
+__device__ inline double uniform01(uint64_t seed, uint64_t i) {
+  return (double)(splitmix64(splitmix64(seed) + i) >> 11) * 0x1.0p-53;
+}
+
+__device__ inline float gate_t(float z) { return fminf(fmaxf(fmaf(z, 1.0f / 6.0f, 0.5f), 0.0f), 1.0f); }
+__device__ inline float act(float z) {
+  const float t = gate_t(z);
+  return z * (t * t * fmaf(t, -2.0f, 3.0f));
+}
+// f'(z) = S(z) + z t (1 - t)
+__device__ inline float dact(float z) {
+  const float t = gate_t(z);
+  return t * t * fmaf(t, -2.0f, 3.0f) + z * t * (1.0f - t);
+}
+
+// He-uniform weights, zero biases
+__global__ void k_mlp_init(uint64_t seed, float *__restrict__ P) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NP) return;
+  float a = 0.0f;
+  if (i < OB1) a = sqrtf(6.0f / NI);
+  else if ((i >= OW2 && i < OB2) || (i >= OW3 && i < OB3) || (i >= OW4 && i < OB4)) a = sqrtf(6.0f / H);
+  P[i] = a == 0.0f ? 0.0f : (float)((2.0 * uniform01(seed, i) - 1.0) * a);
+}
+
+// sample offsets uniform in the folded domain [0, ext]^3
+__global__ void k_mlp_points(uint64_t seed, int64_t n, double e0, double e1, double e2, double *__restrict__ u) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  u[3 * q] = e0 * uniform01(seed, 3 * q);
+  u[3 * q + 1] = e1 * uniform01(seed, 3 * q + 1);
+  u[3 * q + 2] = e2 * uniform01(seed, 3 * q + 2);
+}
+
+// network inputs x = 2 u / ext - 1 and standardised targets (phi_c, A_c)
+__global__ void k_mlp_prepare(int64_t n, const double *__restrict__ u, const double *__restrict__ ser,
+                              MlpNorm N, float *__restrict__ x, float *__restrict__ t) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  for (int k = 0; k < 3; ++k) x[3 * q + k] = (float)(2.0 * u[3 * q + k] / N.ext[k] - 1.0);
+  for (int o = 0; o < 4; ++o) t[4 * q + o] = (float)((ser[10 * q + o] - N.mu[o]) / N.sig[o]);
+}
+
+// ------------------------------------------------------------- training
+constexpr int SB = 32;  // samples per workgroup
+constexpr int WP = 65;  // padded LDS row stride of W2, W3
+
+struct TrainLds {
+  float w2[H * WP], w3[H * WP];
+  float z1[SB][H], z2[SB][H], z3[SB][H];
+  float h1[SB][H], h2[SB][H], h3[SB][H];
+  float da[SB][H], db[SB][H];
+  float x[SB][NI], dy[SB][NO];
+  float loss[256];
+};
+
+// Thread t: neuron o = t % 64 of samples s = t / 64 + 4 j in the layer loops.
+__global__ __launch_bounds__(256) void k_mlp_fwdbwd(const float *__restrict__ P, int64_t n, int64_t s0,
+                                                    const float *__restrict__ X, const float *__restrict__ T,
+                                                    float scale, float *__restrict__ partial,
+                                                    float *__restrict__ lossp) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  TrainLds &L = *reinterpret_cast<TrainLds *>(smem_raw);
+  const int t = threadIdx.x;
+  const int64_t base = (s0 + (int64_t)blockIdx.x * SB) % n;  // n and s0 are multiples of SB
+  for (int q = t; q < H * H; q += 256) {
+    L.w2[(q / H) * WP + q % H] = P[OW2 + q];
+    L.w3[(q / H) * WP + q % H] = P[OW3 + q];
+  }
+  for (int q = t; q < SB * NI; q += 256) L.x[q / NI][q % NI] = X[NI * base + q];
+  __syncthreads();
+  const int o = t % H, s4 = t / H;
+  for (int j = 0; j < SB / 4; ++j) {
+    const int s = s4 + 4 * j;
+    float a = P[OB1 + o];
+    for (int i = 0; i < NI; ++i) a += P[OW1 + o * NI + i] * L.x[s][i];
+    L.z1[s][o] = a;
+    L.h1[s][o] = act(a);
+  }
+  __syncthreads();
+  for (int j = 0; j < SB / 4; ++j) {
+    const int s = s4 + 4 * j;
+    float a = P[OB2 + o];
+    for (int i = 0; i < H; ++i) a += L.w2[o * WP + i] * L.h1[s][i];
+    L.z2[s][o] = a;
+    L.h2[s][o] = act(a);
+  }
+  __syncthreads();
+  for (int j = 0; j < SB / 4; ++j) {
+    const int s = s4 + 4 * j;
+    float a = P[OB3 + o];
+    for (int i = 0; i < H; ++i) a += L.w3[o * WP + i] * L.h2[s][i];
+    L.z3[s][o] = a;
+    L.h3[s][o] = act(a);
+  }
+  __syncthreads();
+  float lsum = 0.0f;
+  if (t < SB * NO) {
+    const int s = t / NO, oo = t % NO;
+    float a = P[OB4 + oo];
+    for (int i = 0; i < H; ++i) a += P[OW4 + oo * H + i] * L.h3[s][i];
+    const float e = a - T[NO * (base + s) + oo];
+    lsum = e * e * scale;
+    L.dy[s][oo] = 2.0f * e * scale;
+  }
+  L.loss[t] = lsum;
+  __syncthreads();
+  float *G = partial + (int64_t)blockIdx.x * NP;
+  {  // layer 4: dW4, db4
+    const int oo = t / H, i = t % H;
+    float g = 0.0f;
+    for (int s = 0; s < SB; ++s) g += L.dy[s][oo] * L.h3[s][i];
+    G[OW4 + oo * H + i] = g;
+    if (t < NO) {
+      float gb = 0.0f;
+      for (int s = 0; s < SB; ++s) gb += L.dy[s][t];
+      G[OB4 + t] = gb;
+    }
+  }
+  for (int j = 0; j < SB / 4; ++j) {  // dZ3
+    const int s = s4 + 4 * j;
+    float a = 0.0f;
+    for (int oo = 0; oo < NO; ++oo) a += L.dy[s][oo] * P[OW4 + oo * H + o];
+    L.da[s][o] = a * dact(L.z3[s][o]);
+  }
+  __syncthreads();
+  for (int j = 0; j < H / 4; ++j) {  // dW3
+    const int oo = s4 + 4 * j;
+    float g = 0.0f;
+    for (int s = 0; s < SB; ++s) g += L.da[s][oo] * L.h2[s][o];
+    G[OW3 + oo * H + o] = g;
+  }
+  if (t < H) {
+    float gb = 0.0f;
+    for (int s = 0; s < SB; ++s) gb += L.da[s][t];
+    G[OB3 + t] = gb;
+  }
+  for (int j = 0; j < SB / 4; ++j) {  // dZ2
+    const int s = s4 + 4 * j;
+    float a = 0.0f;
+    for (int oo = 0; oo < H; ++oo) a += L.da[s][oo] * L.w3[oo * WP + o];
+    L.db[s][o] = a * dact(L.z2[s][o]);
+  }
+  __syncthreads();
+  for (int j = 0; j < H / 4; ++j) {  // dW2
+    const int oo = s4 + 4 * j;
+    float g = 0.0f;
+    for (int s = 0; s < SB; ++s) g += L.db[s][oo] * L.h1[s][o];
+    G[OW2 + oo * H + o] = g;
+  }
+  if (t < H) {
+    float gb = 0.0f;
+    for (int s = 0; s < SB; ++s) gb += L.db[s][t];
+    G[OB2 + t] = gb;
+  }
+  __syncthreads();  // da is overwritten next
+  for (int j = 0; j < SB / 4; ++j) {  // dZ1
+    const int s = s4 + 4 * j;
+    float a = 0.0f;
+    for (int oo = 0; oo < H; ++oo) a += L.db[s][oo] * L.w2[oo * WP + o];
+    L.da[s][o] = a * dact(L.z1[s][o]);
+  }
+  __syncthreads();
+  if (t < H * NI) {  // dW1
+    const int oo = t / NI, i = t % NI;
+    float g = 0.0f;
+    for (int s = 0; s < SB; ++s) g += L.da[s][oo] * L.x[s][i];
+    G[OW1 + oo * NI + i] = g;
+  }
+  if (t < H) {
+    float gb = 0.0f;
+    for (int s = 0; s < SB; ++s) gb += L.da[s][t];
+    G[OB1 + t] = gb;
+  }
+  if (t == 0) {
+    float l = 0.0f;
+    for (int q = 0; q < 256; ++q) l += L.loss[q];
+    lossp[blockIdx.x] = l;
+  }
+}
+
+// fixed-order sum of the workgroup partials; thread 0 also sums the loss
+__global__ void k_mlp_reduce(int nwg, const float *__restrict__ partial, const float *__restrict__ lossp,
+                             float *__restrict__ grad, float *__restrict__ loss) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p == 0) {
+    float l = 0.0f;
+    for (int w = 0; w < nwg; ++w) l += lossp[w];
+    *loss = l;
+  }
+  if (p >= NP) return;
+  float g = 0.0f;
+  for (int w = 0; w < nwg; ++w) g += partial[(int64_t)w * NP + p];
+  grad[p] = g;
+}
+
+__global__ void k_mlp_adam(float *__restrict__ P, const float *__restrict__ grad, float *__restrict__ m,
+                           float *__restrict__ v, float lr, float c1, float c2) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NP) return;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float g = grad[p];
+  const float mm = b1 * m[p] + (1.0f - b1) * g;
+  const float vv = b2 * v[p] + (1.0f - b2) * g * g;
+  m[p] = mm;
+  v[p] = vv;
+  P[p] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+// ------------------------------------------------------------- packing
+// Contraction index held by lane group g (= lane / 32) in half j of chunk c:
+// the rows of a 32x32 output tile that lane group g holds, so that the output
+// of one layer is the next layer's B operand without moving data.
+__device__ inline int perm_k(int c, int g, int j) {
+  return 32 * (c >> 1) + 16 * (c & 1) + 8 * (j >> 2) + 4 * g + (j & 3);
+}
+
+__device__ inline void split16(double v, _Float16 &hi, _Float16 &lo) {
+  hi = (_Float16)v;
+  lo = (_Float16)(v - (double)hi);
+}
+
+// one thread per (operand, lane): 27 x 64 threads
+__global__ void k_mlp_pack(const float *__restrict__ P, MlpNorm N, f16x8 *__restrict__ pk) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= NPK * 64) return;
+  const int op = q / 64, l = q % 64, m = l & 31, g = l >> 5;
+  _Float16 a[8];
+  for (int j = 0; j < 8; ++j) a[j] = (_Float16)0.0f;
+  if (op < PK_L2) {  // layer 1 with the input scaling x = 2 u / ext - 1 folded in
+    // lane group 0: (W_hi, b_hi, W_hi, b_lo) against (u_hi, 1, u_lo, 1);
+    // lane group 1: W_lo against u_hi
+    const int i = 32 * op + m;
+    double bs = P[OB1 + i];
+    for (int k = 0; k < 3; ++k) {
+      const double w = (double)P[OW1 + NI * i + k] * (2.0 / N.ext[k]);
+      _Float16 hi, lo;
+      split16(w, hi, lo);
+      if (g == 0) a[k] = a[4 + k] = hi;
+      else a[k] = lo;
+      bs -= (double)P[OW1 + NI * i + k];
+    }
+    if (g == 0) split16(bs, a[3], a[7]);
+  } else if (op < PK_L2B || (op >= PK_L3 && op < PK_L3B)) {  // W2, W3
+    const int r = op < PK_L2B ? op - PK_L2 : op - PK_L3;
+    const int R = r >> 2, c = r & 3, W = op < PK_L2B ? OW2 : OW3;
+    for (int j = 0; j < 8; ++j) a[j] = (_Float16)P[W + H * (32 * R + m) + perm_k(c, g, j)];
+  } else if (op < PK_L3 || op == PK_L3B || op == PK_L3B + 1) {  // b2, b3
+    const int R = op < PK_L3 ? op - PK_L2B : op - PK_L3B;
+    const int B = op < PK_L3 ? OB2 : OB3;
+    if (g == 0) split16(P[B + 32 * R + m], a[0], a[1]);
+  } else if (op < PK_L4B) {  // W4 scaled by sig, rows repeated every 4
+    const int c = op - PK_L4, o = m & 3;
+    for (int j = 0; j < 8; ++j) a[j] = (_Float16)((double)P[OW4 + H * o + perm_k(c, g, j)] * N.sig[o]);
+  } else {  // b4 sig + mu
+    const int o = m & 3;
+    if (g == 0) split16((double)P[OB4 + o] * N.sig[o] + N.mu[o], a[0], a[1]);
+  }
+  f16x8 v;
+  for (int j = 0; j < 8; ++j) v[j] = a[j];
+  pk[q] = v;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- inference
+namespace mlpinf {
+
+__device__ inline f32x16 mma(f16x8 a, f16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+
+struct Ops {
+  f16x8 a[NPK];
+};
+
+__device__ inline void load_ops(const void *pk, Ops &W) {
+  const f16x8 *p = reinterpret_cast<const f16x8 *>(pk);
+  const int l = threadIdx.x & 63;
+  for (int i = 0; i < NPK; ++i) W.a[i] = p[64 * i + l];
+}
+
+// B operand of the first layer: u split into FP16 high and low parts, with
+// the constant inputs for the bias; lane group 1 passes u_hi for the low
+// parts of the weights
+__device__ inline f16x8 input(float u0, float u1, float u2) {
+  f16x8 b;
+  const bool g1 = (threadIdx.x & 63) >= 32;
+  const _Float16 h0 = (_Float16)u0, h1 = (_Float16)u1, h2 = (_Float16)u2;
+  const _Float16 one = (_Float16)(g1 ? 0.0f : 1.0f), zero = (_Float16)0.0f;
+  b[0] = h0;
+  b[1] = h1;
+  b[2] = h2;
+  b[3] = one;
+  b[4] = g1 ? zero : (_Float16)(u0 - (float)h0);
+  b[5] = g1 ? zero : (_Float16)(u1 - (float)h1);
+  b[6] = g1 ? zero : (_Float16)(u2 - (float)h2);
+  b[7] = one;
+  return b;
+}
+
+__device__ inline f16x8 ones() {
+  f16x8 b;
+  const bool g0 = (threadIdx.x & 63) < 32;
+  for (int j = 0; j < 8; ++j) b[j] = (_Float16)((j < 2 && g0) ? 1.0f : 0.0f);
+  return b;
+}
+
+__device__ inline void act_tile(const f32x16 &d, f16x8 &c0, f16x8 &c1) {
+  for (int j = 0; j < 8; ++j) {
+    c0[j] = (_Float16)act(d[j]);
+    c1[j] = (_Float16)act(d[8 + j]);
+  }
+}
+
+// (phi_c, A_c) at the folded offsets of the 32 pairs of this wave: lane l
+// passes the B operand of pair l % 32 and receives its 4 outputs.
+__device__ inline void forward(const Ops &W, const f16x8 &xin, const f16x8 &one, float y[4]) {
+  const f32x16 z = {0};
+  f16x8 h[4];
+  {
+    const f32x16 d0 = mma(W.a[PK_L1], xin, z);
+    const f32x16 d1 = mma(W.a[PK_L1 + 1], xin, z);
+    act_tile(d0, h[0], h[1]);
+    act_tile(d1, h[2], h[3]);
+  }
+#pragma unroll
+  for (int layer = 0; layer < 2; ++layer) {
+    const int A0 = layer == 0 ? PK_L2 : PK_L3, B0 = layer == 0 ? PK_L2B : PK_L3B;
+    f32x16 d0 = mma(W.a[B0], one, z);
+    f32x16 d1 = mma(W.a[B0 + 1], one, z);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      d0 = mma(W.a[A0 + c], h[c], d0);
+      d1 = mma(W.a[A0 + 4 + c], h[c], d1);
+    }
+    act_tile(d0, h[0], h[1]);
+    act_tile(d1, h[2], h[3]);
+  }
+  f32x16 o = mma(W.a[PK_L4B], one, z);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) o = mma(W.a[PK_L4 + c], h[c], o);
+  for (int k = 0; k < 4; ++k) y[k] = o[k];
+}
+
+}  // namespace mlpinf
+
+namespace {
+
+// correction (phi_c, signed A_c) at offsets d [n][3]; 2P1I beyond zfar: the
+// limit minus the Newtonian part, as in the walk.  One wave per 32 offsets.
+__global__ __launch_bounds__(256) void k_mlp_points_eval(const void *__restrict__ pk, EwaldP E, int64_t n,
+                                                         const double *__restrict__ d, double *__restrict__ out) {
+  mlpinf::Ops W;
+  mlpinf::load_ops(pk, W);
+  const f16x8 one = mlpinf::ones();
+  const int l = threadIdx.x & 63;
+  const int64_t q = 32 * (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) + (l & 31);
+  double dx = 0.0, dy = 0.0, dz = 0.0;
+  if (q < n) {
+    dx = d[3 * q];
+    dy = d[3 * q + 1];
+    dz = d[3 * q + 2];
+  }
+  float y[4];
+  mlpinf::forward(W, mlpinf::input((float)fabs(dx), (float)fabs(dy), (float)fabs(dz)), one, y);
+  if (q >= n || l >= 32) return;
+  double *o = out + 4 * q;
+  if (E.bctype == 2 && fabs(dz) > E.zfar) {
+    const double r = sqrt(dx * dx + dy * dy + dz * dz), r3 = r * r * r;
+    o[0] = E.far_phi_a * fabs(dz) + E.far_phi_b - 1.0 / r;
+    o[1] = -dx / r3;
+    o[2] = -dy / r3;
+    o[3] = (dz < 0 ? -E.far_az : E.far_az) - dz / r3;
+    return;
+  }
+  o[0] = y[0];
+  o[1] = dx < 0 ? -y[1] : y[1];
+  o[2] = dy < 0 ? -y[2] : y[2];
+  o[3] = dz < 0 ? -y[3] : y[3];
+}
+
+// ------------------------------------------------------------- walk
+// FP32 evaluation of the block lists with the correction from the surrogate
+// (BC 1 = 3P, 2 = 2P1I).  Layout as the table walk: one workgroup of 256
+// threads per leaf block, thread t owns cells t and t + 256, the list streams
+// through LDS in tiles of offsets from the block centre.  Wave w owns the 128
+// cells {64 w + l, 256 + 64 w + l}; for every list entry it runs 4 batches of
+// 32 pairs through the network, batch b covering the cells of lane group
+// b & 1 in slot b >> 1.  Phi is Kahan-compensated.
+constexpr int WG = 256;
+
+template <int BC>
+__global__ __launch_bounds__(WG) void k_eval_mlp(DevTree T, EwaldP E, const void *__restrict__ pk,
+                                                 const int64_t *__restrict__ off, const double4 *__restrict__ rec,
+                                                 const int32_t *__restrict__ ids, float *__restrict__ phi,
+                                                 float *__restrict__ acc, float negG) {
+  __shared__ float4 tile[WG];
+  const int64_t b = blockIdx.x;
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6, g = l >> 5, m = l & 31;
+  const int64_t ncell = T.nb * 512;
+  const double sb = size_at(T.root_size, T.blev[b]);
+  const double h = sb / 8.0;
+  double cT[3];
+  for (int k = 0; k < 3; ++k) cT[k] = centre_coord(T.org[k], T.bcoord[3 * b + k], sb);
+  const int64_t own0 = T.na + 72 * T.nb + 512 * b;
+  mlpinf::Ops W;
+  mlpinf::load_ops(pk, W);
+  const f16x8 one = mlpinf::ones();
+  // cell of batch bb for this lane (pair 32 bb + m of the wave)
+  float px[4], py[4], pz[4];
+  for (int bb = 0; bb < 4; ++bb) {
+    const int ci = 64 * w + 32 * (bb & 1) + m + 256 * (bb >> 1);
+    px[bb] = (float)(((double)(ci & 7) - 3.5) * h);
+    py[bb] = (float)(((double)((ci >> 3) & 7) - 3.5) * h);
+    pz[bb] = (float)(((double)(ci >> 6) - 3.5) * h);
+  }
+  const float Lx = (float)E.L[0], Ly = (float)E.L[1], Lz = (float)E.L[2];
+  const float zfar = (float)E.zfar, fa = (float)E.far_phi_a, fb = (float)E.far_phi_b, faz = (float)E.far_az;
+  float s[2] = {0.f, 0.f}, cc[2] = {0.f, 0.f}, ax[2] = {0.f, 0.f}, ay[2] = {0.f, 0.f}, az[2] = {0.f, 0.f};
+  const int64_t start = off[b], n = off[b + 1] - start;
+  for (int64_t t0 = 0; t0 < n; t0 += WG) {
+    if (t0 + tid < n) {
+      const double4 r = rec[start + t0 + tid];
+      const int64_t own = (int64_t)ids[start + t0 + tid] - own0;
+      float4 v;
+      if (own >= 0 && own < 512) {
+        v.x = (float)(((double)(own & 7) - 3.5) * h);
+        v.y = (float)(((double)((own >> 3) & 7) - 3.5) * h);
+        v.z = (float)(((double)(own >> 6) - 3.5) * h);
+      } else {
+        v.x = (float)wrap_axis(r.x - cT[0], T.L[0], T.per[0]);
+        v.y = (float)wrap_axis(r.y - cT[1], T.L[1], T.per[1]);
+        v.z = (float)wrap_axis(r.z - cT[2], T.L[2], T.per[2]);
+      }
+      v.w = (float)r.w;
+      tile[tid] = v;
+    }
+    __syncthreads();
+    const int mm = (int)(n - t0 < WG ? n - t0 : WG);
+    for (int j = 0; j < mm; ++j) {
+      const float4 r = tile[j];
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        float dx = px[bb] - r.x, dy = py[bb] - r.y, dz = pz[bb] - r.z;
+        dx = dx - Lx * floorf(dx / Lx + 0.5f);
+        dy = dy - Ly * floorf(dy / Ly + 0.5f);
+        if (BC == 1) dz = dz - Lz * floorf(dz / Lz + 0.5f);
+        float y[4];
+        mlpinf::forward(W, mlpinf::input(fabsf(dx), fabsf(dy), fabsf(dz)), one, y);
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float inv = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+        const float inv3 = inv * inv * inv;
+        float ph = inv + y[0];
+        float A0 = dx * inv3 + (dx < 0 ? -y[1] : y[1]);
+        float A1 = dy * inv3 + (dy < 0 ? -y[2] : y[2]);
+        float A2 = dz * inv3 + (dz < 0 ? -y[3] : y[3]);
+        if (BC == 2 && fabsf(dz) > zfar) {
+          ph = fa * fabsf(dz) + fb;
+          A0 = 0.0f;
+          A1 = 0.0f;
+          A2 = dz < 0 ? -faz : faz;
+        }
+        const bool use = g == (bb & 1) && r2 > 0.0f;
+        const int q = bb >> 1;
+        const float yk = r.w * ph - cc[q];
+        const float tk = s[q] + yk;
+        cc[q] = use ? (tk - s[q]) - yk : cc[q];
+        s[q] = use ? tk : s[q];
+        ax[q] += use ? r.w * A0 : 0.0f;
+        ay[q] += use ? r.w * A1 : 0.0f;
+        az[q] += use ? r.w * A2 : 0.0f;
+      }
+    }
+    __syncthreads();
+  }
+  for (int q = 0; q < 2; ++q) {
+    const int64_t o = b * 512 + tid + q * WG;
+    phi[o] = negG * (s[q] - cc[q]);
+    acc[o] = negG * ax[q];
+    acc[ncell + o] = negG * ay[q];
+    acc[2 * ncell + o] = negG * az[q];
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers
+hipError_t launch_mlp_init(uint64_t seed, float *P, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_init, dim3((NP + 255) / 256), dim3(256), 0, st, seed, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_points(uint64_t seed, int64_t n, const double ext[3], double *u, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, seed, n, ext[0], ext[1],
+                     ext[2], u);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_prepare(int64_t n, const double *u, const double *ser, const MlpNorm &N, float *x, float *t,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_prepare, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, u, ser, N, x, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const float *P, int64_t n, int64_t s0, int64_t batch, const float *X, const float *T,
+                           float *partial, float *lossp, float *grad, float *loss, hipStream_t st) {
+  if (batch <= 0 || batch % SB || n % SB || s0 % SB || batch > n) return hipErrorInvalidValue;
+  const int nwg = (int)(batch / SB);
+  const size_t lds = sizeof(TrainLds);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e =
+        hipFuncSetAttribute((const void *)k_mlp_fwdbwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_mlp_fwdbwd, dim3(nwg), dim3(256), lds, st, P, n, s0, X, T, 1.0f / (4.0f * (float)batch),
+                     partial, lossp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((NP + 255) / 256), dim3(256), 0, st, nwg, partial, lossp, grad, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float *P, const float *grad, float *m, float *v, float lr, int step, hipStream_t st) {
+  const float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);
+  hipLaunchKernelGGL(k_mlp_adam, dim3((NP + 255) / 256), dim3(256), 0, st, P, grad, m, v, lr, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_pack(const float *P, const MlpNorm &N, void *pk, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_pack, dim3((NPK * 64 + 255) / 256), dim3(256), 0, st, P, N,
+                     reinterpret_cast<f16x8 *>(pk));
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_points_eval(const void *pk, const EwaldP &E, int64_t n, const double *d, double *out,
+                                  hipStream_t st) {
+  const int64_t waves = (n + 31) / 32;
+  hipLaunchKernelGGL(k_mlp_points_eval, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, pk, E, n, d, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_mlp(const DevTree &T, const EwaldP &E, const void *pk, const int64_t *off,
+                           const double4 *rec, const int32_t *ids, float *phi, float *acc, double G,
+                           hipStream_t st) {
+  dim3 grid((unsigned)T.nb), blk(WG);
+  const float ng = (float)(-G);
+  if (E.bctype == 1)
+    hipLaunchKernelGGL(k_eval_mlp<1>, grid, blk, 0, st, T, E, pk, off, rec, ids, phi, acc, ng);
+  else if (E.bctype == 2)
+    hipLaunchKernelGGL(k_eval_mlp<2>, grid, blk, 0, st, T, E, pk, off, rec, ids, phi, acc, ng);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace ot

@@ -85,5 +85,49 @@ hipError_t launch_amax(const double *acc, int64_t n, unsigned long long *out, hi
 
 hipError_t launch_ewald_table(const EwaldP &E, double alpha, int rcut2, int fcut2, double *tab64,
                               float4 *tab32, hipStream_t st);
+// FP64 series at arbitrary offsets d [n][3] (folded to |d| inside): out [n][10]
+hipError_t launch_ewald_points(const EwaldP &E, double alpha, int rcut2, int fcut2, int64_t n, const double *u,
+                               double *out, hipStream_t st);
+
+// ---------------------------------------------------------------- surrogate
+// Network 3 -> 64 -> 64 -> 64 -> 4 over the folded offset; parameter layout
+// W1[64][3] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[4][64] b4[4].
+namespace mlpdef {
+constexpr int H = 64, NI = 3, NO = 4;
+constexpr int OW1 = 0, OB1 = OW1 + H * NI, OW2 = OB1 + H, OB2 = OW2 + H * H, OW3 = OB2 + H, OB3 = OW3 + H * H,
+              OW4 = OB3 + H, OB4 = OW4 + NO * H, NP = OB4 + NO;
+// packed matrix-core operands, 8 halves per lane each (see k_mlp.hip)
+constexpr int PK_L1 = 0, PK_L2 = 2, PK_L2B = 10, PK_L3 = 12, PK_L3B = 20, PK_L4 = 22, PK_L4B = 26, NPK = 27;
+}  // namespace mlpdef
+
+// Input / output scaling: x = 2 u / ext - 1, y = (out - mu) / sig.
+struct MlpNorm {
+  double ext[3];
+  double mu[4];
+  double sig[4];
+};
+
+hipError_t launch_mlp_init(uint64_t seed, float *P, hipStream_t st);
+hipError_t launch_mlp_points(uint64_t seed, int64_t n, const double ext[3], double *u, hipStream_t st);
+hipError_t launch_mlp_prepare(int64_t n, const double *u, const double *ser, const MlpNorm &N, float *x, float *t,
+                              hipStream_t st);
+// gradient of the batch MSE at P over samples [s0, s0 + batch) (wrapping at n)
+// of x [n][3], t [n][4]: partial [batch/32][NP] scratch, grad [NP], loss
+// (FP32 sum) into *loss
+hipError_t launch_mlp_grad(const float *P, int64_t n, int64_t s0, int64_t batch, const float *X, const float *T,
+                           float *partial, float *lossp, float *grad, float *loss, hipStream_t st);
+hipError_t launch_mlp_adam(float *P, const float *grad, float *m, float *v, float lr, int step, hipStream_t st);
+// pack (P, N) into the matrix-core operands used by inference
+hipError_t launch_mlp_pack(const float *P, const MlpNorm &N, void *pk, hipStream_t st);
+// correction (phi_c, A_c) at offsets d [n][3] by the surrogate: out [n][4]
+hipError_t launch_mlp_points_eval(const void *pk, const EwaldP &E, int64_t n, const double *d, double *out,
+                                  hipStream_t st);
+// the same offsets by the FP64 series / the FP64 table (Taylor): out [n][4]
+hipError_t launch_ewald_points4(int method, const EwaldP &E, double alpha, int rcut2, int fcut2, int64_t n,
+                                const double *d, double *out, hipStream_t st);
+// FP32 walk with the correction from the surrogate (BC 3P or 2P1I)
+hipError_t launch_eval_mlp(const DevTree &T, const EwaldP &E, const void *pk, const int64_t *off,
+                           const double4 *rec, const int32_t *ids, float *phi, float *acc, double G,
+                           hipStream_t st);
 
 }  // namespace ot

@@ -1,0 +1,369 @@
+"""The learned Ewald surrogate on the GPU, through the C ABI.
+
+* Training gradients (FP32 forward + backward kernels, fixed-order reduction)
+  against the oracle's FP64 back-propagation: max-normalised 1e-5.
+* Matrix-core inference (FP16 inputs, FP32 accumulation) against the oracle's
+  FP64 forward of the same weights, within a first-order bound of that
+  arithmetic propagated through the layers (below).
+* The device FP64 Ewald series and table lookups at arbitrary offsets against
+  the oracle: 1e-12 of each channel's largest value.
+* Training on FP64 series values: the loss falls, training is reproducible bit
+  for bit, and the trained network beats a table of the same memory (9^3
+  points x 10 channels, ~29 KB in FP32, vs 8836 FP32 parameters, ~35 KB).
+* The walk with the surrogate against the table walk on the same lists,
+  within the held-out error carried through the sum over the list and within
+  1e-4 of the largest |Phi| and |a| (the surrogate's accuracy budget); without
+  an accepted surrogate the walk is the table walk, bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1708_06142_amd as ot
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+U16 = 2.0 ** -11        # unit roundoff of FP16
+G32 = 64 * 2.0 ** -24   # FP32 accumulation of a 64-term sum
+LACT = 1.21             # max |f'| of the activation z S(z)
+TINY = 2.0 ** -14       # smallest normal FP16 value
+
+
+def small(W):
+    """|W| where FP16 holds W below its normal range, else 0."""
+    return np.where(np.abs(W) < TINY, np.abs(W), 0.0)
+
+BOXES = {"3p": ((1, 1, 1), 1.0, (1, 1, 1)), "2p1i": ((1, 1, 4), 1.0, (1, 1, 0))}
+
+
+def solver(name, **kw):
+    nroot, rs, bc = BOXES[name]
+    return ot.Solver(nroot=nroot, root_size=rs, bc=bc, **kw)
+
+
+def extent(name):
+    """Folded domain of the correction: half the box in periodic axes, 2 Lx in
+    the isolated axis of 2P1I."""
+    return np.array([0.5, 0.5, 0.5]) if name == "3p" else np.array([0.5, 0.5, 2.0])
+
+
+def unpack(p):
+    o, out = 0, []
+    for shape in ((64, 3), (64,), (64, 64), (64,), (64, 64), (64,), (4, 64), (4,)):
+        k = int(np.prod(shape))
+        out.append(p[o:o + k].reshape(shape))
+        o += k
+    return out
+
+
+def act(z):
+    t = np.clip(z / 6 + 0.5, 0, 1)
+    return z * t * t * (3 - 2 * t)
+
+
+def forward_with_bound(p, norm, d):
+    """FP64 output (phi_c, signed A_c) of the network at offsets d, from the
+    oracle's forward pass, and a first-order bound of the error of evaluating
+    it with FP16 weights and activations and FP32 sums: per layer
+    |dz| <= (U16 + G32) sum |W| (|h| + |dh|) + sum |W| |dh|, and after the
+    activation |dh| <= LACT |dz| + U16 (|h| + LACT |dz|).  Inputs and biases
+    are split into FP16 high and low parts on the device (error O(U16^2)).
+    Values below FP16's smallest normal (2^-14) may lose all precision, which
+    adds their whole product to the bound."""
+    p = np.asarray(p, np.float64)
+    ext, mu, sig = norm[:3], norm[3:7], norm[7:11]
+    u = np.abs(d)
+    y = oracle.mlp_forward(p, 2 * u / ext - 1) * sig + mu
+    W1, b1, W2, b2, W3, b3, W4, b4 = unpack(p)
+    W1s = W1 * (2 / ext)
+    z = u @ W1s.T + (b1 - W1.sum(1))
+    dz = (U16 + G32) * (np.abs(u) @ np.abs(W1s).T) + 4 * U16 ** 2 * (np.abs(b1) + np.abs(W1).sum(1))
+    dz += np.abs(u) @ small(W1s).T
+
+    def layer(h, dh, W, b):
+        a = np.abs(h) + dh
+        return ((U16 + G32) * (a @ np.abs(W).T) + dh @ np.abs(W).T + a @ small(W).T
+                + 4 * U16 ** 2 * np.abs(b))
+
+    for W, b in ((W2, b2), (W3, b3)):
+        h = act(z)
+        dh = LACT * dz + U16 * (np.abs(h) + LACT * dz) + TINY
+        z = h @ W.T + b
+        dz = layer(h, dh, W, b)
+    h = act(z)
+    dh = LACT * dz + U16 * (np.abs(h) + LACT * dz) + TINY
+    bound = layer(h, dh, W4 * sig[:, None], b4 * sig) + 4 * U16 ** 2 * np.abs(mu)
+    sgn = np.where(d < 0, -1.0, 1.0)
+    y[:, 1:] *= sgn
+    return y, bound
+
+
+def random_params(seed):
+    rng = np.random.default_rng(seed)
+    p = np.zeros(ot.MLP_NPARAM, np.float32)
+    W1, b1, W2, b2, W3, b3, W4, b4 = (slice(0, 192), slice(192, 256), slice(256, 4352), slice(4352, 4416),
+                                      slice(4416, 8512), slice(8512, 8576), slice(8576, 8832), slice(8832, 8836))
+    p[W1] = rng.uniform(-1, 1, 192) * np.sqrt(6 / 3)
+    for s in (W2, W3, W4):
+        p[s] = rng.uniform(-1, 1, s.stop - s.start) * np.sqrt(6 / 64)
+    for s in (b1, b2, b3, b4):
+        p[s] = rng.uniform(-0.5, 0.5, s.stop - s.start)
+    return p
+
+
+def offsets(name, n, seed, signed=True):
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(0, 1, (n, 3)) * extent(name)
+    if signed:
+        d *= rng.choice([-1.0, 1.0], (n, 3))
+    d[:3] = 0.0          # offsets on the axes and at the origin of the fold
+    d[0, :] = [0.0, 0.0, 0.3]
+    d[1, :] = [extent(name)[0], 0.0, 0.0]
+    return d
+
+
+def dev(a, dt=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dt)
+
+
+# ------------------------------------------------------------- gradients
+@pytest.mark.parametrize("batch", [32, 96, 512])
+def test_gradient_vs_oracle(batch):
+    s = solver("3p")
+    rng = np.random.default_rng(batch)
+    p = random_params(batch)
+    x = rng.uniform(-1, 1, (batch, 3)).astype(np.float32)
+    t = rng.normal(size=(batch, 4)).astype(np.float32)
+    g = torch.empty(ot.MLP_NPARAM, dtype=torch.float32, device="cuda")
+    loss = s.mlp_grad(dev(p, torch.float32), dev(x, torch.float32), dev(t, torch.float32), g)
+    lr, gr = oracle.mlp_grad(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    gg = g.cpu().numpy().astype(np.float64)
+    err = np.abs(gg - gr).max() / np.abs(gr).max()
+    print(f"batch {batch}: loss {loss:.6g} (oracle {lr:.6g}), gradient error {err:.2e}")
+    assert abs(loss - lr) <= 1e-5 * lr
+    assert err <= 1e-5
+    # every block of the parameter vector is covered
+    for sl in (slice(0, 192), slice(192, 256), slice(4352, 4416), slice(8576, 8832), slice(8832, 8836)):
+        assert np.abs(gg[sl] - gr[sl]).max() <= 1e-5 * np.abs(gr).max()
+
+
+def test_gradient_is_deterministic():
+    s = solver("3p")
+    rng = np.random.default_rng(9)
+    p = dev(random_params(9), torch.float32)
+    x = dev(rng.uniform(-1, 1, (4096, 3)), torch.float32)
+    t = dev(rng.normal(size=(4096, 4)), torch.float32)
+    g1 = torch.empty(ot.MLP_NPARAM, dtype=torch.float32, device="cuda")
+    g2 = torch.empty_like(g1)
+    l1 = s.mlp_grad(p, x, t, g1)
+    l2 = s.mlp_grad(p, x, t, g2)
+    assert l1 == l2 and torch.equal(g1, g2)
+
+
+def test_grad_rejects_bad_batch():
+    s = solver("3p")
+    g = torch.empty(ot.MLP_NPARAM, dtype=torch.float32, device="cuda")
+    x = torch.zeros((40, 3), dtype=torch.float32, device="cuda")
+    t = torch.zeros((40, 4), dtype=torch.float32, device="cuda")
+    with pytest.raises(ot.OTError) as e:
+        s.mlp_grad(g, x, t, g)
+    assert e.value.status == ot.OT_ERR_INVALID_ARG
+
+
+# ------------------------------------------------------------- inference
+@pytest.mark.parametrize("name", list(BOXES))
+def test_inference_vs_oracle_forward(name):
+    s = solver(name, ewald_n=16)
+    p = random_params(3)
+    norm = np.concatenate([extent(name), [0.3, -0.2, 0.1, 1.5], [2.0, 0.7, 1.3, 0.4]])
+    s.mlp_set(p, norm, accept=False)
+    n = 1000  # not a multiple of 32: a ragged last batch
+    d = offsets(name, n, 11)
+    out = torch.empty((n, 4), dtype=torch.float64, device="cuda")
+    s.ewald_points("mlp", dev(d), out)
+    y = out.cpu().numpy()
+    ref, bound = forward_with_bound(p, norm, d)
+    excess = (np.abs(y - ref) - bound).max()
+    rel = np.abs(y - ref).max(0) / np.abs(ref).max(0)
+    print(f"{name}: max error / channel max {rel}, max error / bound {(np.abs(y - ref) / bound).max():.3f}")
+    assert excess <= 0, excess
+    p2, n2 = s.mlp_get()
+    assert np.array_equal(p2, p) and np.array_equal(n2, norm)
+
+
+# ------------------------------------------------------------- series / table points
+@pytest.mark.parametrize("name", list(BOXES))
+def test_points_series_and_table_vs_oracle(name):
+    nroot, rs, bc = BOXES[name]
+    box = np.array(nroot, float) * rs
+    s = solver(name, ewald_n=24)
+    d = offsets(name, 300, 5)
+    d = d[np.abs(d).sum(1) > 0]  # the series' correction is regular at 0 but keep to d != 0
+    out = torch.empty((d.shape[0], 4), dtype=torch.float64, device="cuda")
+    s.ewald_points("exact", dev(d), out)
+    ref = oracle.ewald_eval(bc, box, d, correction=True)[:, :4]
+    got = out.cpu().numpy()
+    for ch in range(4):
+        assert np.abs(got[:, ch] - ref[:, ch]).max() <= 1e-12 * np.abs(ref[:, ch]).max(), ch
+    s.ewald_points("table", dev(d), out)
+    tab = oracle.ewald_table(bc, box, n=24)
+    reft = oracle.ewald_table_lookup(bc, box, tab, d)[:, :4]
+    got = out.cpu().numpy()
+    for ch in range(4):
+        assert np.abs(got[:, ch] - reft[:, ch]).max() <= 1e-12 * np.abs(reft[:, ch]).max(), ch
+
+
+def test_points_need_a_surrogate():
+    s = solver("3p", ewald_n=8)
+    d = dev(np.full((4, 3), 0.1))
+    out = torch.empty((4, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(ot.OTError) as e:
+        s.ewald_points("mlp", d, out)
+    assert e.value.status == ot.OT_ERR_STATE
+
+
+# ------------------------------------------------------------- training
+TRAIN = dict(nval=50000)  # otherwise the library defaults (2^21 offsets, 100 epochs)
+
+
+@pytest.fixture(scope="module")
+def trained():
+    out = {}
+    for name in BOXES:
+        s = solver(name, ewald_n=64, ewald="mlp")
+        rep = s.mlp_train(**TRAIN)
+        print(f"{name}: {rep}")
+        out[name] = (s, rep)
+    return out
+
+
+@pytest.mark.parametrize("name", list(BOXES))
+def test_training_reduces_loss(trained, name):
+    _, rep = trained[name]
+    assert rep["loss_last"] < 0.01 * rep["loss_first"], rep
+
+
+@pytest.mark.parametrize("name", list(BOXES))
+def test_gain_over_equal_memory_table(trained, name):
+    """The surrogate against a table of the same memory (9^3 points) and the
+    default 64^3 table, on the same held-out offsets, all against the series."""
+    s, rep = trained[name]
+    d = offsets(name, 20000, 21)
+    dd = dev(d)
+    out = torch.empty((d.shape[0], 4), dtype=torch.float64, device="cuda")
+    s.ewald_points("exact", dd, out)
+    ex = out.cpu().numpy()
+    scale = np.abs(ex).max(0)
+    s.ewald_points("mlp", dd, out)
+    e_mlp = (np.abs(out.cpu().numpy() - ex).max(0) / scale).max()
+    s.ewald_points("table", dd, out)
+    e_t64 = (np.abs(out.cpu().numpy() - ex).max(0) / scale).max()
+    s9 = solver(name, ewald_n=9)
+    s9.ewald_points("table", dd, out)
+    e_t9 = (np.abs(out.cpu().numpy() - ex).max(0) / scale).max()
+    print(f"{name}: max-normalised error: surrogate {e_mlp:.2e}, table 9^3 {e_t9:.2e}, table 64^3 {e_t64:.2e}")
+    assert e_mlp < e_t9 / 3
+
+
+def test_training_is_reproducible():
+    cfg = dict(nsamples=1 << 14, epochs=3, batch=2048, nval=1000)
+    a = solver("3p", ewald_n=16)
+    b = solver("3p", ewald_n=16)
+    ra, rb = a.mlp_train(**cfg), b.mlp_train(**cfg)
+    pa, na = a.mlp_get()
+    pb, nb = b.mlp_get()
+    assert np.array_equal(pa, pb) and np.array_equal(na, nb)
+    assert ra["loss_last"] == rb["loss_last"]
+    c = solver("3p", ewald_n=16)
+    c.mlp_train(seed=5, **cfg)
+    assert not np.array_equal(c.mlp_get()[0], pa)
+
+
+# ------------------------------------------------------------- walk
+def lognormal32(bc, nroot=(1, 1, 1)):
+    n = 32
+    nb = n // 8
+    level, coord = workloads.uniform_blocks(n)
+    rng = np.random.default_rng(17)
+    rho = rng.lognormal(0.0, 1.0, (nb ** 3, 8, 8, 8))
+    if nroot != (1, 1, 1):
+        level, coord, rho = [], [], []
+        for z in range(nroot[2]):
+            l, c = workloads.uniform_blocks(n)
+            c = np.array(c).copy()
+            c[:, 2] += z * nb
+            level.append(l)
+            coord.append(c)
+            rho.append(rng.lognormal(0.0, 1.0, (nb ** 3, 8, 8, 8)))
+        level, coord, rho = np.concatenate(level), np.concatenate(coord), np.concatenate(rho)
+    return workloads.Grid(nroot, 1.0, (0, 0, 0), level, coord, rho, bc, "lognormal32")
+
+
+@pytest.mark.parametrize("name", list(BOXES))
+def test_walk_with_surrogate(trained, name):
+    """Same lists as the FP32 table walk; the difference is bounded by
+    G M_total (held-out surrogate error + table error) x channel max, with a
+    factor 2 for the held-out maximum not being the global one."""
+    s_tr, rep = trained[name]
+    params, norm = s_tr.mlp_get()
+    nroot, _, bc = BOXES[name]
+    g = lognormal32(bc, nroot)
+    rho = dev(g.rho.reshape(-1))
+    n = g.nb * 512
+    res = {}
+    for mode in ("table", "mlp"):
+        s = ot.Solver.for_grid(g, theta=0.5, ewald_n=64, ewald=mode)
+        if mode == "mlp":
+            s.mlp_set(params, norm, accept=True)
+        s.build(rho)
+        phi = torch.empty(n, dtype=torch.float32, device="cuda")
+        acc = torch.empty(3 * n, dtype=torch.float32, device="cuda")
+        st = s.solve(phi, acc)
+        res[mode] = (phi.cpu().numpy().astype(np.float64), acc.cpu().numpy().reshape(3, -1).astype(np.float64),
+                     st)
+        if mode == "table":
+            ids0 = [s.export_list(b) for b in (0, g.nb - 1)]
+        else:
+            assert all(np.array_equal(a, s.export_list(b)) for a, b in zip(ids0, (0, g.nb - 1)))
+    (pt, at, st_t), (pm, am, st_m) = res["table"], res["mlp"]
+    assert st_t.ewald_used == 0 and st_m.ewald_used == 2
+    # channel maxima of the correction over the folded domain
+    out = torch.empty((20000, 4), dtype=torch.float64, device="cuda")
+    s_tr.ewald_points("exact", dev(offsets(name, 20000, 3)), out)
+    cmax = np.abs(out.cpu().numpy()).max(0)
+    h3 = (1.0 / 32) ** 3
+    mtot = g.rho.sum() * h3
+    e = np.array(rep["err_mlp"]) + np.array(rep["err_table"])
+    dphi = np.abs(pm - pt).max()
+    da = np.abs(am - at).max()
+    # plus FP32 rounding of the two walks (1e-6 of the largest value)
+    bphi = 2 * mtot * e[0] * cmax[0] + 1e-6 * np.abs(pt).max()
+    ba = 2 * mtot * max(e[1:] * cmax[1:]) + 1e-6 * np.abs(at).max()
+    print(f"{name}: |dPhi| {dphi:.3e} (bound {bphi:.3e}, max|Phi| {np.abs(pt).max():.3e}); "
+          f"|da| {da:.3e} (bound {ba:.3e}, max|a| {np.abs(at).max():.3e}); "
+          f"ms_eval table {st_t.ms_eval:.2f}, surrogate {st_m.ms_eval:.2f}")
+    assert dphi <= bphi and da <= ba
+    # the accuracy budget of the surrogate walk against the table walk
+    assert dphi <= 1e-4 * np.abs(pt).max() and da <= 1e-4 * np.abs(at).max()
+
+
+def test_walk_without_accepted_surrogate_is_the_table_walk():
+    g = lognormal32((1, 1, 1))
+    rho = dev(g.rho.reshape(-1))
+    n = g.nb * 512
+    outs = []
+    for mode, accept in (("table", None), ("mlp", None), ("mlp", False)):
+        s = ot.Solver.for_grid(g, theta=0.5, ewald_n=32, ewald=mode)
+        if accept is not None:
+            s.mlp_set(random_params(1), np.concatenate([extent("3p"), np.zeros(4), np.ones(4)]), accept=accept)
+        s.build(rho)
+        phi = torch.empty(n, dtype=torch.float32, device="cuda")
+        acc = torch.empty(3 * n, dtype=torch.float32, device="cuda")
+        st = s.solve(phi, acc)
+        assert st.ewald_used == 0
+        outs.append((phi.cpu(), acc.cpu()))
+    for p, a in outs[1:]:
+        assert torch.equal(p, outs[0][0]) and torch.equal(a, outs[0][1])
