@@ -30,6 +30,10 @@ import numpy as np  # noqa: E402
 FLOP_PAIR_ISO = 22
 PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X vector FP32 (256 CU x 2.4 GHz, packed)
 PEAK_FP64_VALU = 78.6
+# Surrogate network per (cell, node) pair: 2 (3*64 + 64*64 + 64*64 + 64*4)
+# multiply-adds of the four layers, on FP16 matrix instructions.
+FLOP_PAIR_MLP = 2 * (3 * 64 + 64 * 64 + 64 * 64 + 64 * 4)
+PEAK_FP16_MFMA = 2500.0  # TFLOP/s, MI355X dense FP16 matrix
 
 
 def parse():
@@ -44,6 +48,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--nside", type=int, default=2, help="HEALPix Nside of the column maps (0 = off)")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the learned-Ewald leg (same field, 3P boundaries)")
+    ap.add_argument("--surrogate-steps", type=int, default=2)
     return ap.parse_args()
 
 
@@ -65,6 +72,60 @@ def timed_steps(solver, rho, outs, fp64, steps, warmup):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return dt / steps * 1e3, st, float(np.mean(evals)), float(np.mean(lists)), float(np.mean(builds))
+
+
+def surrogate_leg(grid, rho, steps):
+    """Same field with 3P boundaries and the same MAC: the FP32 walk with the
+    learned correction beside the FP32 and FP64 table walks.  Training (on the
+    device, before timing) is reported, not timed as part of a step."""
+    import torch
+    import paper_1708_06142_amd as ot
+    import workloads
+    g = workloads.Grid(grid.nroot, grid.root_size, grid.origin, grid.level, grid.coord, grid.rho, (1, 1, 1),
+                       grid.name + "-3p")
+    n = g.ncells
+    f32 = dict(device="cuda", dtype=torch.float32)
+    f64 = dict(device="cuda", dtype=torch.float64)
+    sm = ot.Solver.for_grid(g, mac="ape", eps_lim=1e-3, theta=0.5, ewald="mlp")
+    t0 = time.perf_counter()
+    rep = sm.mlp_train()
+    train_s = time.perf_counter() - t0
+    sm.build(rho)
+    phi_m, acc_m = torch.empty(n, **f32), torch.empty(3 * n, **f32)
+    a_lim = sm.solve(phi_m, acc_m).a_lim_used  # APE limit from the BH pre-pass (untimed)
+    params, norm = sm.mlp_get()
+    sm.close()
+    res = {}
+    for label, mode, fp64 in (("mlp_fp32", "mlp", False), ("table_fp32", "table", False),
+                              ("table_fp64", "table", True)):
+        s = ot.Solver.for_grid(g, mac="ape", a_lim=a_lim, theta=0.5, ewald=mode)
+        if mode == "mlp":
+            s.mlp_set(params, norm, accept=bool(rep["ok"]))
+        kw = f64 if fp64 else f32
+        outs = (torch.empty(n, **kw), torch.empty(3 * n, **kw))
+        ms, st, ms_eval, _, _ = timed_steps(s, rho, outs, fp64, steps, 1)
+        res[label] = dict(ms=ms, st=st, ms_eval=ms_eval, phi=outs[0].double().cpu().numpy(),
+                          acc=outs[1].double().cpu().numpy().reshape(3, -1))
+        s.close()
+    ref = res["table_fp64"]
+    pmax = np.abs(ref["phi"]).max()
+    amax = np.sqrt((ref["acc"] ** 2).sum(0)).max()
+    out = {"workload": f"{grid.name} field with 3P boundaries, APE a_lim=1e-3 a_max ({a_lim:.4g})",
+           "training": {"seconds": train_s, "report": rep}, "a_lim": a_lim}
+    for label, r in res.items():
+        st = r["st"]
+        e = {"value": n / (r["ms"] * 1e-3), "unit": "cells/s", "ms_per_step": r["ms"], "ms_eval": r["ms_eval"],
+             "ewald_used": ["table", "exact", "mlp"][st.ewald_used], "n_int": st.n_interactions}
+        if label != "table_fp64":
+            e["dphi_maxnorm_vs_fp64_table"] = float(np.abs(r["phi"] - ref["phi"]).max() / pmax)
+            e["da_maxnorm_vs_fp64_table"] = float(np.abs(r["acc"] - ref["acc"]).max() / amax)
+        if label == "mlp_fp32":
+            ach = st.n_interactions * FLOP_PAIR_MLP / (r["ms_eval"] * 1e-3) / 1e12
+            e["roofline"] = {"bound": "mfma", "kernel": "k_eval_mlp<3P>", "achieved": ach,
+                             "peak": PEAK_FP16_MFMA, "unit": "TFLOP/s", "frac": ach / PEAK_FP16_MFMA,
+                             "flop_per_pair": FLOP_PAIR_MLP}
+        out[label] = e
+    return out
 
 
 def cpu_baseline(grid, a_lim, nblk, nside):
@@ -150,6 +211,8 @@ def main():
         a64 = st64.n_interactions * FLOP_PAIR_ISO / (e64 * 1e-3) / 1e12
         out["fp64_walk"] = {"value": ncell / (ms64 * 1e-3), "ms_per_step": ms64, "ms_eval": e64,
                             "achieved_tflops": a64, "frac_fp64_peak": a64 / PEAK_FP64_VALU}
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_leg(grid, rho, args.surrogate_steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(grid, a_lim, args.cpu_blocks, args.nside)
     print(json.dumps(out))

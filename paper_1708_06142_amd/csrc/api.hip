@@ -212,6 +212,7 @@ ot_status raytable_prepare(ot_ctx *c, hipStream_t st) {
     if (s == OT_OK) s = dalloc(c, c->rt_w64, (size_t)total * sizeof(double));
     if (s == OT_OK) s = dalloc(c, c->rt_rows, (size_t)RP.nentries * sizeof(uint32_t));
     if (s == OT_OK) s = dalloc(c, c->rt_ent, (size_t)total * sizeof(uint32_t));
+    if (s == OT_OK) s = dalloc(c, c->rt_rows4, (size_t)RP.nentries * 16);
     if (s == OT_OK && total >= ((int64_t)1 << 26)) s = fail(c, OT_ERR_UNSUPPORTED, "node-ray table too large");
     if (s == OT_OK) {
       // packed rows hold at most 63 pixels per entry
@@ -226,13 +227,24 @@ ot_status raytable_prepare(ot_ctx *c, hipStream_t st) {
                               P<uint16_t>(c->rt_pix), P<double>(c->rt_w64), &total, st);
       if (e == hipSuccess)
         e = ot::launch_raytable_pack(RP, P<int64_t>(c->rt_off), P<uint16_t>(c->rt_pix), P<double>(c->rt_w64),
-                                     P<uint32_t>(c->rt_rows), P<uint32_t>(c->rt_ent), st);
-      // direction-bin thresholds: cos(k dtheta), sin(k dpsi), cos(k dphi), sin(k dphi)
+                                     P<uint32_t>(c->rt_rows), P<uint32_t>(c->rt_ent), P<uint4>(c->rt_rows4), st);
+      // direction-bin thresholds: c |c| with c = cos(k dtheta), sin^2(k dpsi),
+      // cos(k dphi), sin(k dphi); each list ends in a threshold its test
+      // never passes (-inf, +inf, and phi = pi exactly as cos -1, sin 0)
       std::vector<double> thr;
-      for (int k = 0; k < RP.ntheta; ++k) thr.push_back(std::cos(k * RP.dtheta));
-      for (int k = 0; k < RP.npsi; ++k) thr.push_back(std::sin(k * RP.dpsi));
-      for (int k = 0; k <= RP.nphi / 2; ++k) thr.push_back(std::cos(k * RP.dphi));
-      for (int k = 0; k <= RP.nphi / 2; ++k) thr.push_back(std::sin(k * RP.dphi));
+      for (int k = 0; k < RP.ntheta; ++k) {
+        const double c = std::cos(k * RP.dtheta);
+        thr.push_back(c * std::fabs(c));
+      }
+      thr.push_back(-HUGE_VAL);
+      for (int k = 0; k < RP.npsi; ++k) {
+        const double sn = std::sin(k * RP.dpsi);
+        thr.push_back(sn * sn);
+      }
+      thr.push_back(HUGE_VAL);
+      const int half = RP.nphi / 2;
+      for (int k = 0; k <= half; ++k) thr.push_back(k == half ? -1.0 : std::cos(k * RP.dphi));
+      for (int k = 0; k <= half; ++k) thr.push_back(k == half ? 0.0 : std::sin(k * RP.dphi));
       if (e == hipSuccess && (s = dalloc(c, c->rt_thr, thr.size() * sizeof(double))) == OT_OK)
         e = hipMemcpyAsync(c->rt_thr.ptr, thr.data(), thr.size() * sizeof(double), hipMemcpyHostToDevice, st);
       if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -260,10 +272,17 @@ ot::ColP col_params(ot_ctx *c) {
   C.req = 0.6203504908994001;  // (3 / (4 pi))^(1/3)
   C.omega = 4.0 * M_PI / (double)RP.npix;
   C.kappa = c->p.kappa;
-  C.max_dist = c->p.max_dist;
-  C.nthr = RP.ntheta + RP.npsi + 2 * (RP.nphi / 2 + 1);
+  C.max_dist2 = c->p.max_dist * c->p.max_dist;
+  C.ip_pi = std::min((int)std::floor(M_PI / RP.dphi), RP.nphi - 1);
+  C.nthr = (RP.ntheta + 1) + (RP.npsi + 1) + 2 * (RP.nphi / 2 + 1);
+  // the angle estimates are good to ~1e-3 rad (far below 0.01 rad)
+  C.estimate = std::min(RP.dtheta, std::min(RP.dphi, RP.dpsi)) >= 0.01;
+  C.inv_dtheta = (float)(1.0 / RP.dtheta);
+  C.inv_dphi = (float)(1.0 / RP.dphi);
+  C.inv_dpsi = (float)(1.0 / RP.dpsi);
   C.thr = P<double>(c->rt_thr);
   C.rows = P<uint32_t>(c->rt_rows);
+  C.rows4 = P<uint4>(c->rt_rows4);
   C.pix = P<uint16_t>(c->rt_pix);
   C.w64 = P<double>(c->rt_w64);
   C.ent = P<uint32_t>(c->rt_ent);
@@ -273,7 +292,7 @@ ot::ColP col_params(ot_ctx *c) {
 // cells per workgroup of the column walk: the per-cell maps must fit in LDS
 int cols_cpw(const ot_ctx *c, bool fp64) {
   const ot::RayTableP RP = raytable_desc(c);
-  const int nthr = RP.ntheta + RP.npsi + 2 * (RP.nphi / 2 + 1);
+  const int nthr = (RP.ntheta + 1) + (RP.npsi + 1) + 2 * (RP.nphi / 2 + 1);
   for (int cpw : {256, 128, 64})
     if (ot::cols_smem_bytes(npix_of(c), cpw, fp64, nthr) <= 65536) return cpw;
   if (ot::cols_smem_bytes(npix_of(c), 64, fp64, nthr) <= 160 * 1024) return 64;
@@ -938,7 +957,7 @@ void ot_destroy(ot_ctx *c) {
   DevBuf *all[] = {&c->alev, &c->acoord, &c->achild0, &c->aleaf, &c->blev,   &c->bcoord,
                    &c->bamr, &c->amc,    &c->aS,      &c->btmc,  &c->cm,     &c->flag,
                    &c->lcount, &c->loff, &c->lrec,    &c->lid,   &c->lscratch, &c->tab64,
-                   &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_rows, &c->rt_ent,
+                   &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_rows, &c->rt_ent, &c->rt_rows4,
                    &c->rt_thr, &c->lh, &c->mlp_P, &c->mlp_pk, &c->mlp_part, &c->mlp_lossp,
                    &c->mlp_loss};
   for (DevBuf *b : all) release(c, *b);

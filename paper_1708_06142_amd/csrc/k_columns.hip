@@ -13,7 +13,8 @@
 // 3. Column walk: like the gravity walk, plus for every (cell, node) pair the
 //    direction bins (FP64), the table row, and N_p += w M / (Omega_pix d^2) in
 //    a per-cell pixel map held in LDS as [pixel][cell] (each thread owns its
-//    cell's column: no atomics, no bank conflicts).  At the end each cell's map
+//    cell's column: plain read-modify-write in list order, no atomics, no
+//    bank conflicts).  At the end each cell's map
 //    and tau_avg = -ln(mean_p exp(-kappa N_p)) are written out.
 #include "common.hpp"
 #include "kernels.hpp"
@@ -150,7 +151,7 @@ __global__ void k_raytable_fill(RayTableP P, const double *__restrict__ dense, c
 }
 
 // ------------------------------------------------------------- column walk
-constexpr int TILE = 128;
+constexpr int TILE = 64;  // list records per LDS tile (small: the maps need the LDS)
 
 template <typename Real>
 struct ColAcc {
@@ -171,35 +172,73 @@ __device__ inline int last_true(int n, Pred pred) {
   return k;
 }
 
-// Table row of a node at offset v = r_a - r from the target (|v| = d, node
-// size h).  The bins are those of floor(theta / dtheta), floor(phi / dphi)
-// and floor(psi / dpsi), decided without inverse trigonometric functions:
+// The same answer from an estimate k0 that is within one of it: with pred
+// monotone, pred(0) true and a sentinel threshold at n for which pred is
+// false, the answer is k0 - 1 + pred(k0) + pred(k0 + 1) for k0 clamped to
+// [0, n - 1]; the two threshold reads are independent of each other.
+template <typename Pred>
+__device__ inline int near_true(int n, int k0, Pred pred) {
+  k0 = clampi(k0, n - 1);
+  return k0 - 1 + (int)pred(k0) + (int)pred(k0 + 1);
+}
+
+// FP32 estimate of acos(x) on [-1, 1]: the polynomial of Abramowitz & Stegun
+// 4.4.45 (absolute error below 7e-5 rad on [0, 1]), reflected for x < 0.
+__device__ inline float acos_est(float x) {
+  const float a = fminf(fabsf(x), 1.0f);
+  const float p = fmaf(fmaf(fmaf(-0.0187293f, a, 0.0742610f), a, -0.2121144f), a, 1.5707288f);
+  const float r = p * __builtin_sqrtf(1.0f - a);
+  return x < 0.0f ? 3.14159265f - r : r;
+}
+
+// Table row of a node at offset v = r_a - r from the target (|v|^2 = r2,
+// node size h, rh = R_eq h).  The bins are those of floor(theta / dtheta),
+// floor(phi / dphi) and floor(psi / dpsi), decided without inverse
+// trigonometric functions or square roots:
 //   theta >= k dtheta  <=>  v_z <= cos(k dtheta) d
-//   psi   >= k dpsi    <=>  R_eq h >= sin(k dpsi) d
+//                      <=>  v_z |v_z| <= cos(k dtheta) |cos(k dtheta)| r2
+//   psi   >= k dpsi    <=>  (R_eq h)^2 >= sin^2(k dpsi) r2
 //   phi   >= k dphi    <=>  cos(k dphi) v_y - sin(k dphi) v_x >= 0   (0 < phi < pi)
-// with phi in (pi, 2 pi) mapped to the upper half-plane by v -> -v; v_y = 0
-// (exactly on the x axis) uses atan2 as written.  FP64 throughout.
+// (x -> x |x| is increasing, so the squared forms are the same inequalities),
+// with phi in (pi, 2 pi) mapped to the upper half-plane by v -> -v; on the x
+// axis (v_y = +-0) phi is that of atan2: 0, or pi (bin ip_pi) when v_x has its
+// sign bit set.  The comparisons are FP64.
+// Which k to compare: FP32 estimates of the three angles (error ~1e-3 rad at
+// worst, from the rounding of the ratios near the poles) locate the bin to
+// within one when every bin is wider than 0.01 rad, and the comparisons at k0
+// and k0 + 1 then give the same bins as a full binary search over the
+// thresholds, which remains for narrower bins and for offsets too small for
+// FP32.
 __device__ inline int table_row(const ColP &C, const double *thr, double vx, double vy, double vz,
-                                double d, double h) {
-  const double *cth = thr;                       // [ntheta]
-  const double *sps = thr + C.ntheta;            // [npsi]
-  const double *cph = sps + C.npsi;              // [nphi/2 + 1]
-  const double *sph = cph + (C.nphi / 2 + 1);
-  const int it = last_true(C.ntheta, [&](int k) { return vz <= cth[k] * d; });
-  const double rh = C.req * h;
-  const int is = last_true(C.npsi, [&](int k) { return rh >= sps[k] * d; });
-  int ip;
-  if (vy == 0.0) {
-    double ph = atan2(vy, vx);
-    if (ph < 0.0) ph += 2.0 * PI;
-    ip = clampi((int)floor(ph / C.dphi), C.nphi - 1);
+                                double r2, double rh) {
+  const double *cth = thr;                       // [ntheta + 1] c |c|, sentinel -inf
+  const double *sps = cth + C.ntheta + 1;        // [npsi + 1] sin^2, sentinel +inf
+  const double *cph = sps + C.npsi + 1;          // [nphi/2 + 1], the last cos(pi) = -1
+  const double *sph = cph + (C.nphi / 2 + 1);    // [nphi/2 + 1], the last sin(pi) = 0
+  const double rh2 = rh * rh, vzz = vz * fabs(vz);
+  const int half = C.nphi / 2;
+  const bool lower = vy < 0.0;
+  const double ux = lower ? -vx : vx, uy = lower ? -vy : vy;
+  auto pth = [&](int k) { return vzz <= cth[k] * r2; };
+  auto pps = [&](int k) { return rh2 >= sps[k] * r2; };
+  auto pph = [&](int q) { return cph[q] * uy - sph[q] * ux >= 0.0; };
+  const float f2 = (float)r2, fx = (float)ux, fy = (float)uy;
+  const float rho2 = fx * fx + fy * fy;
+  int it, is, k;
+  if (C.estimate && f2 > 1e-30f && rho2 > 1e-30f) {
+    const float rd = __builtin_amdgcn_rsqf(f2);
+    it = near_true(C.ntheta, (int)(acos_est((float)vz * rd) * C.inv_dtheta), pth);
+    const float sn = fminf((float)rh * rd, 1.0f);
+    is = near_true(C.npsi, (int)((1.5707963f - acos_est(sn)) * C.inv_dpsi), pps);
+    k = near_true(half, (int)(acos_est(fx * __builtin_amdgcn_rsqf(rho2)) * C.inv_dphi), pph);
   } else {
-    const bool lower = vy < 0.0;
-    const double ux = lower ? -vx : vx, uy = lower ? -vy : vy;
-    const int half = C.nphi / 2;
-    const int k = last_true(half, [&](int q) { return cph[q] * uy - sph[q] * ux >= 0.0; });
-    ip = clampi((lower ? half : 0) + k, C.nphi - 1);
+    it = last_true(C.ntheta, pth);
+    is = last_true(C.npsi, pps);
+    k = last_true(half, pph);
   }
+  // atan2(+-0, x) is pi (bin ip_pi) whenever the sign bit of x is set, -0
+  // included (a node straight above the cell, v = -d with d_x = +0), else 0
+  const int ip = vy == 0.0 ? (signbit(vx) ? C.ip_pi : 0) : clampi((lower ? half : 0) + k, C.nphi - 1);
   return (it * C.nphi + ip) * C.npsi + is;
 }
 
@@ -326,7 +365,7 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
     __syncthreads();
     for (int q = tid; q < TILE && t0 + q < n; q += cpw) {
       tile[q] = rec[start + t0 + q];
-      tileh[q] = lh[start + t0 + q];
+      tileh[q] = C.req * lh[start + t0 + q];  // radius of the equal-volume sphere
     }
     __syncthreads();
     const int m = (int)(n - t0 < TILE ? n - t0 : TILE);
@@ -335,13 +374,13 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
       double dx = cx - r.x, dy = cy - r.y, dz = cz - r.z;
       wrap3<BC>(E, dx, dy, dz);
       const double r2 = dx * dx + dy * dy + dz * dz;
-      if (r2 == 0.0) continue;  // the target cell itself
-      const double d = sqrt(r2);
-      const bool col = d <= C.max_dist;
-      const int e = col ? table_row(C, thr, -dx, -dy, -dz, d, tileh[j]) : 0;
-      const uint32_t rd = C.rows[e];
-      const int o0 = (int)(rd >> 6), cnt = col ? (int)(rd & 63) : 0;
+      const bool valid = r2 != 0.0;  // the target cell itself contributes nothing
+      const bool col = valid && r2 <= C.max_dist2;
+      const int e = col ? table_row(C, thr, -dx, -dy, -dz, r2, tileh[j]) : 0;
+      const uint4 row = C.rows4[e];
+      const int o0 = (int)(row.x >> 6), cnt = col ? (int)(row.x & 63) : 0;
       if (sizeof(Real) == 8) {
+        if (!valid) continue;
         double ph, A0, A1, A2;
         grav64<BC>(E, dx, dy, dz, r2, ph, A0, A1, A2);
         s += (Real)(r.w * ph);
@@ -354,16 +393,22 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         // FP32 gravity from the FP64 offset (already the minimum image)
         float ph, A0, A1, A2;
         grav32<BC>(E, (float)dx, (float)dy, (float)dz, ph, A0, A1, A2);
-        const float m32 = (float)r.w;
+        const float m32 = valid ? (float)r.w : 0.0f;
         const float y = m32 * ph - (float)cmp;
         const float tt = (float)s + y;
-        cmp = (Real)((tt - (float)s) - y);
-        s = (Real)tt;
+        cmp = valid ? (Real)((tt - (float)s) - y) : cmp;
+        s = valid ? (Real)tt : s;
         ax += (Real)(m32 * A0);
         ay += (Real)(m32 * A1);
         az += (Real)(m32 * A2);
-        const float base = m32 * __builtin_amdgcn_rcpf(omega32 * (float)r2) * (1.0f / 16777216.0f);
-        for (int o = o0; o < o0 + cnt; ++o) {
+        const float base = col ? m32 * __builtin_amdgcn_rcpf(omega32 * (float)r2) * (1.0f / 16777216.0f) : 0.0f;
+        // the first three entries come with the row (zero weight past cnt);
+        // plain read-modify-write: the column is the thread's own, and LDS
+        // atomic adds measured 2.5x slower here
+        map[(row.y >> 24) * cpw + tid] += (Real)((float)(row.y & 0xffffffu) * base);
+        map[(row.z >> 24) * cpw + tid] += cnt > 1 ? (Real)((float)(row.z & 0xffffffu) * base) : (Real)0;
+        map[(row.w >> 24) * cpw + tid] += cnt > 2 ? (Real)((float)(row.w & 0xffffffu) * base) : (Real)0;
+        for (int o = o0 + 3; o < o0 + cnt; ++o) {
           const uint32_t v = C.ent[o];
           map[(v >> 24) * cpw + tid] += (Real)((float)(v & 0xffffffu) * base);
         }
@@ -388,16 +433,21 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
 // round(w 2^24) (w <= 1, clamped to 2^24 - 1)
 __global__ void k_raytable_pack(RayTableP P, const int64_t *__restrict__ off, const uint16_t *__restrict__ pix,
                                 const double *__restrict__ w, uint32_t *__restrict__ rows,
-                                uint32_t *__restrict__ ent) {
+                                uint32_t *__restrict__ ent, uint4 *__restrict__ rows4) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= P.nentries) return;
   const int64_t o0 = off[e], o1 = off[e + 1];
-  rows[e] = (uint32_t)(o0 << 6) | (uint32_t)(o1 - o0);
+  const uint32_t head = (uint32_t)(o0 << 6) | (uint32_t)(o1 - o0);
+  rows[e] = head;
+  uint32_t first[3] = {0u, 0u, 0u};
   for (int64_t o = o0; o < o1; ++o) {
     double q = rint(w[o] * 16777216.0);
     q = q > 16777215.0 ? 16777215.0 : q;
-    ent[o] = ((uint32_t)pix[o] << 24) | (uint32_t)q;
+    const uint32_t v = ((uint32_t)pix[o] << 24) | (uint32_t)q;
+    ent[o] = v;
+    if (o - o0 < 3) first[o - o0] = v;
   }
+  rows4[e] = make_uint4(head, first[0], first[1], first[2]);
 }
 
 }  // namespace
@@ -425,9 +475,9 @@ size_t cols_smem_bytes(int npix, int cpw, bool fp64, int nthr) {
 }
 
 hipError_t launch_raytable_pack(const RayTableP &P, const int64_t *off, const uint16_t *pix, const double *w,
-                                uint32_t *rows, uint32_t *ent, hipStream_t st) {
+                                uint32_t *rows, uint32_t *ent, uint4 *rows4, hipStream_t st) {
   hipLaunchKernelGGL(k_raytable_pack, dim3((unsigned)((P.nentries + 255) / 256)), dim3(256), 0, st, P, off,
-                     pix, w, rows, ent);
+                     pix, w, rows, ent, rows4);
   return hipGetLastError();
 }
 

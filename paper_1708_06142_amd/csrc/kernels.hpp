@@ -49,10 +49,15 @@ struct ColP {
   double req;       // (3 / (4 pi))^(1/3): equal-volume sphere radius per unit edge
   double omega;     // 4 pi / N_pix
   double kappa;     // opacity of tau_avg
-  double max_dist;  // columns only from nodes closer than this
-  int nthr;         // threshold count: ntheta + npsi + 2 (nphi/2 + 1)
-  const double *thr;       // cos(k dtheta), sin(k dpsi), cos(k dphi), sin(k dphi)
+  double max_dist2; // columns only from nodes closer than max_dist (squared)
+  int ip_pi;        // phi bin of phi = pi (offsets on the negative x axis)
+  int nthr;         // threshold count: ntheta + 1 + npsi + 1 + 2 (nphi/2 + 1)
+  int estimate;     // bins from angle estimates checked at two thresholds
+                    // (every bin wider than 0.01 rad), else binary searches
+  float inv_dtheta, inv_dphi, inv_dpsi;
+  const double *thr;       // c|c| (c = cos(k dtheta)), sin^2(k dpsi), cos(k dphi), sin(k dphi)
   const uint32_t *rows;    // [nentries] offset << 6 | count
+  const uint4 *rows4;      // [nentries] {offset << 6 | count, first three entries}
   const uint16_t *pix;     // [npairs] FP64 walk
   const double *w64;       // [npairs]
   const uint32_t *ent;     // [npairs] FP32 walk: pixel << 24 | unorm24 weight
@@ -61,7 +66,7 @@ struct ColP {
 hipError_t launch_raytable(const RayTableP &P, double *dense, int32_t *cnt, int64_t *off, uint16_t *pix,
                            double *w64, int64_t *total, hipStream_t st);
 hipError_t launch_raytable_pack(const RayTableP &P, const int64_t *off, const uint16_t *pix, const double *w,
-                                uint32_t *rows, uint32_t *ent, hipStream_t st);
+                                uint32_t *rows, uint32_t *ent, uint4 *rows4, hipStream_t st);
 size_t cols_smem_bytes(int npix, int cpw, bool fp64, int nthr);
 hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const ColP &C, const int64_t *off,
                             const double4 *rec, const double *lh, void *phi, void *acc, void *npix, void *tau,
