@@ -187,7 +187,7 @@ __device__ inline int near_true(int n, int k0, Pred pred) {
 __device__ inline float acos_est(float x) {
   const float a = fminf(fabsf(x), 1.0f);
   const float p = fmaf(fmaf(fmaf(-0.0187293f, a, 0.0742610f), a, -0.2121144f), a, 1.5707288f);
-  const float r = p * __builtin_sqrtf(1.0f - a);
+  const float r = p * __builtin_amdgcn_sqrtf(1.0f - a);  // hardware sqrt: an estimate needs no rounding fix-up
   return x < 0.0f ? 3.14159265f - r : r;
 }
 
@@ -239,7 +239,7 @@ __device__ inline int table_row(const ColP &C, const double *thr, double vx, dou
   // atan2(+-0, x) is pi (bin ip_pi) whenever the sign bit of x is set, -0
   // included (a node straight above the cell, v = -d with d_x = +0), else 0
   const int ip = vy == 0.0 ? (signbit(vx) ? C.ip_pi : 0) : clampi((lower ? half : 0) + k, C.nphi - 1);
-  return (it * C.nphi + ip) * C.npsi + is;
+  return (int)__umul24(__umul24(it, C.nphi) + ip, C.npsi) + is;  // < 2^24 entries
 }
 
 template <int BC>
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
                                                    const double4 *__restrict__ rec, const double *__restrict__ lh,
                                                    Real *__restrict__ phi, Real *__restrict__ acc,
                                                    Real *__restrict__ npix, Real *__restrict__ tau, double negG,
-                                                   int cpw) {
+                                                   int cpw, int lcpw) {
   extern __shared__ __align__(16) unsigned char smem[];
   double4 *tile = reinterpret_cast<double4 *>(smem);
   double *tileh = reinterpret_cast<double *>(smem + TILE * sizeof(double4));
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         ay += (Real)(r.w * A1);
         az += (Real)(r.w * A2);
         const double base = r.w / (C.omega * r2);
-        for (int o = o0; o < o0 + cnt; ++o) map[C.pix[o] * cpw + tid] += (Real)(C.w64[o] * base);
+        for (int o = o0; o < o0 + cnt; ++o) map[((int)C.pix[o] << lcpw) + tid] += (Real)(C.w64[o] * base);
       } else {
         // FP32 gravity from the FP64 offset (already the minimum image)
         float ph, A0, A1, A2;
@@ -405,12 +405,12 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         // the first three entries come with the row (zero weight past cnt);
         // plain read-modify-write: the column is the thread's own, and LDS
         // atomic adds measured 2.5x slower here
-        map[(row.y >> 24) * cpw + tid] += (Real)((float)(row.y & 0xffffffu) * base);
-        map[(row.z >> 24) * cpw + tid] += cnt > 1 ? (Real)((float)(row.z & 0xffffffu) * base) : (Real)0;
-        map[(row.w >> 24) * cpw + tid] += cnt > 2 ? (Real)((float)(row.w & 0xffffffu) * base) : (Real)0;
+        map[((row.y >> 24) << lcpw) + tid] += (Real)((float)(row.y & 0xffffffu) * base);
+        map[((row.z >> 24) << lcpw) + tid] += cnt > 1 ? (Real)((float)(row.z & 0xffffffu) * base) : (Real)0;
+        map[((row.w >> 24) << lcpw) + tid] += cnt > 2 ? (Real)((float)(row.w & 0xffffffu) * base) : (Real)0;
         for (int o = o0 + 3; o < o0 + cnt; ++o) {
           const uint32_t v = C.ent[o];
-          map[(v >> 24) * cpw + tid] += (Real)((float)(v & 0xffffffu) * base);
+          map[((v >> 24) << lcpw) + tid] += (Real)((float)(v & 0xffffffu) * base);
         }
       }
     }
@@ -485,6 +485,9 @@ hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const 
                             const double4 *rec, const double *lh, void *phi, void *acc, void *npix, void *tau,
                             double G, int cpw, hipStream_t st) {
   const size_t sm = cols_smem_bytes(C.npix, cpw, fp64, C.nthr);
+  int lcpw = 0;
+  while ((1 << lcpw) < cpw) ++lcpw;
+  if ((1 << lcpw) != cpw) return hipErrorInvalidValue;  // cells per workgroup: a power of two
   dim3 grid((unsigned)(T.nb * (512 / cpw))), blk(cpw);
 #define OT_LAUNCH(R, B)                                                                                       \
   do {                                                                                                        \
@@ -494,7 +497,7 @@ hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const 
       if (ea != hipSuccess) return ea;                                                                        \
     }                                                                                                         \
     hipLaunchKernelGGL((k_eval_cols<R, B>), grid, blk, sm, st, T, E, C, off, rec, lh, (R *)phi, (R *)acc,  \
-                       (R *)npix, (R *)tau, -G, cpw);                                                        \
+                       (R *)npix, (R *)tau, -G, cpw, lcpw);                                                  \
   } while (0)
   if (fp64) {
     if (E.bctype == 0) OT_LAUNCH(double, 0);
