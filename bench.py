@@ -30,6 +30,12 @@ import numpy as np  # noqa: E402
 FLOP_PAIR_ISO = 22
 PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X vector FP32 (256 CU x 2.4 GHz, packed)
 PEAK_FP64_VALU = 78.6
+# Column walk per (cell, node) pair: the gravity above plus the column work:
+# FP64 offset and r^2 (8), three direction-bin threshold tests at two
+# thresholds each (12: a product and a comparison per test), N_p weight base
+# m / (Omega r^2) (3) and the map updates (2 per pixel hit, ~2.4 hits -> ~5):
+# 28, rounded to 30.
+FLOP_PAIR_COLS = FLOP_PAIR_ISO + 30
 # Surrogate network per (cell, node) pair: 2 (3*64 + 64*64 + 64*64 + 64*4)
 # multiply-adds of the four layers, on FP16 matrix instructions.
 FLOP_PAIR_MLP = 2 * (3 * 64 + 64 * 64 + 64 * 64 + 64 * 4)
@@ -52,6 +58,23 @@ def parse():
                     help="skip the learned-Ewald leg (same field, 3P boundaries)")
     ap.add_argument("--surrogate-steps", type=int, default=2)
     return ap.parse_args()
+
+
+def measured_traffic(path, source):
+    """HBM bytes of one launch from a committed counter summary, or None when
+    the kernel's source has changed since the counters were taken."""
+    import hashlib
+    try:
+        kv = dict(l.split(": ", 1) for l in open(os.path.join(ROOT, path)).read().splitlines()
+                  if l and not l.startswith("#") and ": " in l)
+        sha = hashlib.sha256(open(os.path.join(ROOT, source), "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if not sha.startswith(kv.get("source_sha256_prefix", "-")):
+        return None
+    return {"bytes": float(kv["traffic_bytes"]), "fetch_kib": float(kv["fetch_size_kib"]),
+            "write_kib": float(kv["write_size_kib"]), "fetch_factor": float(kv["fetch_factor"]),
+            "write_factor": float(kv["write_factor"]), "summary": path}
 
 
 def timed_steps(solver, rho, outs, fp64, steps, warmup):
@@ -184,8 +207,12 @@ def main():
 
     ms, st, ms_eval, ms_list, ms_build = timed_steps(s, rho, outs, False, args.steps, args.warmup)
     value = ncell / (ms * 1e-3)
-    flops = st.n_interactions * FLOP_PAIR_ISO
+    fpair = FLOP_PAIR_COLS if args.nside else FLOP_PAIR_ISO
+    flops = st.n_interactions * fpair
     achieved = flops / (ms_eval * 1e-3) / 1e12
+    traffic = measured_traffic("profiles/eval_cols_lognormal128_nside2_hbm_traffic.txt",
+                               "paper_1708_06142_amd/csrc/k_columns.hip") \
+        if args.nside == 2 and args.n == 128 else None
     out = {
         "metric": "cells/s for potential+accel+N_pix column densities at <=1e-3 rel err",
         "value": value, "unit": "cells/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -200,7 +227,9 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_eval_cols<float> (isolated, columns)" if args.nside
                      else "k_eval32 (isolated)", "achieved": achieved,
                      "peak": PEAK_FP32_VALU, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
-                     "traffic": None, "flop_per_pair": FLOP_PAIR_ISO},
+                     "traffic": traffic["bytes"] if traffic else None,
+                     "traffic_detail": traffic, "flop_per_pair": fpair,
+                     "hbm_gbs_at_traffic": traffic["bytes"] / (ms_eval * 1e-3) / 1e9 if traffic else None},
     }
     if not args.no_fp64:
         f64 = dict(device="cuda", dtype=torch.float64)
@@ -208,7 +237,7 @@ def main():
         if args.nside:
             outs64 += (torch.empty(ncell * npx, **f64), torch.empty(ncell, **f64))
         ms64, st64, e64, _, _ = timed_steps(s, rho, outs64, True, max(2, args.steps // 2), 1)
-        a64 = st64.n_interactions * FLOP_PAIR_ISO / (e64 * 1e-3) / 1e12
+        a64 = st64.n_interactions * fpair / (e64 * 1e-3) / 1e12
         out["fp64_walk"] = {"value": ncell / (ms64 * 1e-3), "ms_per_step": ms64, "ms_eval": e64,
                             "achieved_tflops": a64, "frac_fp64_peak": a64 / PEAK_FP64_VALU}
     if not args.no_surrogate:
