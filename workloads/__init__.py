@@ -241,18 +241,38 @@ def plummer_cores_density(centres, a, rho_c):
     return f
 
 
-def c3_amr(seed=3, rho_c=1e4, a=0.02, base_level=4, levels=3, bc=(1, 1, 0)):
+def c3_amr(seed=3, rho_c=None, a=0.02, base_level=4, levels=3, bc=(1, 1, 0), cells=(2.5e6, 3.5e6)):
     """Four Plummer-like cores in a 1 x 1 x 4 box of four unit root blocks;
     64^3-cell base resolution per root (base_level 4), refined up to
-    ``levels`` more levels where rho > 8 <rho>; mixed BCs by default."""
+    ``levels`` more levels where rho > 8 <rho>; mixed BCs by default.  Unless
+    ``rho_c`` is given, the core density is bisected (in log space, 12 steps
+    from [1e2, 1e4]) until the grid holds a number of cells inside ``cells``;
+    the value used is recorded in ``meta``."""
     rng = np.random.default_rng(seed)
     centres = np.stack([rng.uniform(0.1, 0.9, 4), rng.uniform(0.1, 0.9, 4),
                         rng.uniform(0.5, 3.5, 4)], axis=1)
     nroot = (1, 1, 4)
     vol = 4.0
-    mean = 1.0 + 4 * rho_c * (4.0 * np.pi / 3.0) * a ** 3 / vol
-    dens = plummer_cores_density(centres, a, rho_c)
-    level, coord = amr_blocks(dens, nroot, 1.0, base_level, base_level + levels, 8.0 * mean, bc)
+
+    def blocks(rc):
+        mean = 1.0 + 4 * rc * (4.0 * np.pi / 3.0) * a ** 3 / vol
+        dens = plummer_cores_density(centres, a, rc)
+        return dens, amr_blocks(dens, nroot, 1.0, base_level, base_level + levels, 8.0 * mean, bc)
+
+    if rho_c is None:
+        lo, hi = np.log(1e2), np.log(1e4)
+        for _ in range(12):
+            rho_c = float(np.exp(0.5 * (lo + hi)))
+            dens, (level, coord) = blocks(rho_c)
+            n = 512 * len(level)
+            if n < cells[0]:
+                lo = np.log(rho_c)
+            elif n > cells[1]:
+                hi = np.log(rho_c)
+            else:
+                break
+    else:
+        dens, (level, coord) = blocks(rho_c)
     xc = cell_centres(1.0, (0.0, 0.0, 0.0), level, coord)
     rho = dens(xc[..., 0], xc[..., 1], xc[..., 2])
     return Grid(nroot, 1.0, (0.0, 0.0, 0.0), level, coord, rho, tuple(bc),
