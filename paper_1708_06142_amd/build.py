@@ -21,7 +21,9 @@ SOURCES = {
     "k_eval.hip": [],
     "k_ewald.hip": [],
     "k_columns.hip": [],
-    "k_mlp.hip": [],
+    # matrix products in ordinary vector registers (the activations read them
+    # next; accumulation registers would cost a copy per value)
+    "k_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
 }
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -422,8 +422,9 @@ ot_status ewald_points(ot_ctx *c, int method, int64_t n, const double *d, double
 }
 
 ot_status mlp_grad_scratch(ot_ctx *c, int64_t batch) {
-  OTCHK(dalloc(c, c->mlp_part, (size_t)(batch / 32) * ot::mlpdef::NP * sizeof(float)));
-  OTCHK(dalloc(c, c->mlp_lossp, (size_t)(batch / 32) * sizeof(float)));
+  const int64_t np = ot::mlp_partials(batch);
+  OTCHK(dalloc(c, c->mlp_part, (size_t)np * ot::mlpdef::NP * sizeof(float)));
+  OTCHK(dalloc(c, c->mlp_lossp, (size_t)np * sizeof(float)));
   return OT_OK;
 }
 
@@ -768,7 +769,7 @@ ot_status ot_mlp_train(ot_ctx *c, const ot_mlp_config *cfg, ot_mlp_report *rep, 
   auto ms = [](auto a, auto b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
   // training offsets and their series values
   auto t0 = now();
-  Scoped u(c), ser(c), x(c), t(c), grad(c), m(c), v(c), losses(c);
+  Scoped u(c), ser(c), x(c), t(c), m(c), v(c), losses(c);
   OTCHK(dalloc(c, u.b, (size_t)n * 3 * sizeof(double)));
   OTCHK(dalloc(c, ser.b, (size_t)n * 10 * sizeof(double)));
   HIPCHK(ot::launch_mlp_points(cfg->seed * 3 + 1, n, c->ew_ext, u.p<double>(), st));
@@ -799,7 +800,6 @@ ot_status ot_mlp_train(ot_ctx *c, const ot_mlp_config *cfg, ot_mlp_report *rep, 
   // Adam with a cosine step size; each epoch starts at a different offset
   const int64_t spe = n / cfg->batch, total = spe * cfg->epochs;
   OTCHK(dalloc(c, c->mlp_P, NP * sizeof(float)));
-  OTCHK(dalloc(c, grad.b, NP * sizeof(float)));
   OTCHK(dalloc(c, m.b, NP * sizeof(float)));
   OTCHK(dalloc(c, v.b, NP * sizeof(float)));
   OTCHK(dalloc(c, losses.b, (size_t)total * sizeof(float)));
@@ -816,12 +816,11 @@ ot_status ot_mlp_train(ot_ctx *c, const ot_mlp_config *cfg, ot_mlp_report *rep, 
     rot ^= rot << 17;
     const int64_t s0 = (int64_t)(rot % (uint64_t)(n / 32)) * 32;
     for (int64_t k = 0; k < spe; ++k, ++step) {
-      HIPCHK(ot::launch_mlp_grad(P<float>(c->mlp_P), n, (s0 + k * cfg->batch) % n, cfg->batch, x.p<float>(),
-                                 t.p<float>(), P<float>(c->mlp_part), P<float>(c->mlp_lossp), grad.p<float>(),
-                                 losses.p<float>() + step, st));
       const double lr = cfg->lr_min + 0.5 * (cfg->lr_max - cfg->lr_min) *
                                           (1.0 + std::cos(M_PI * (double)step / (double)total));
-      HIPCHK(ot::launch_mlp_adam(P<float>(c->mlp_P), grad.p<float>(), m.p<float>(), v.p<float>(), (float)lr,
+      HIPCHK(ot::launch_mlp_step(P<float>(c->mlp_P), n, (s0 + k * cfg->batch) % n, cfg->batch, x.p<float>(),
+                                 t.p<float>(), P<float>(c->mlp_part), P<float>(c->mlp_lossp),
+                                 losses.p<float>() + step, m.p<float>(), v.p<float>(), (float)lr,
                                  (int)std::min<int64_t>(step + 1, 1 << 30), st));
     }
   }

@@ -8,9 +8,9 @@
 // axis; output: (phi_c, A_c) standardised per channel.  Parameters (8836 FP32):
 //   W1[64][3] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[4][64] b4[4].
 //
-// Training (FP32): one workgroup runs forward and backward for 32 samples with
+// Training (FP32): one workgroup runs forward and backward for 8 samples with
 // all activations in LDS and writes its partial gradient; a second kernel sums
-// the partials in a fixed order (deterministic); Adam updates the parameters.
+// the partials in a fixed order (deterministic) and applies Adam.
 // Loss: mean squared error over the 4 outputs of the batch.
 //
 // Inference: every layer runs on the matrix cores in the transposed form
@@ -90,7 +90,7 @@ __global__ void k_mlp_prepare(int64_t n, const double *__restrict__ u, const dou
 }
 
 // ------------------------------------------------------------- training
-constexpr int SB = 32;  // samples per workgroup
+constexpr int SB = 8;   // samples per workgroup (batch 2048 -> 256 workgroups)
 constexpr int WP = 65;  // padded LDS row stride of W2, W3
 
 struct TrainLds {
@@ -227,29 +227,45 @@ __global__ __launch_bounds__(256) void k_mlp_fwdbwd(const float *__restrict__ P,
   }
 }
 
-// fixed-order sum of the workgroup partials; thread 0 also sums the loss
-__global__ void k_mlp_reduce(int nwg, const float *__restrict__ partial, const float *__restrict__ lossp,
-                             float *__restrict__ grad, float *__restrict__ loss) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p == 0) {
+// Fixed-order sum of the workgroup partials: 64 parameters per block of four
+// waves, wave w summing partials w, w + 4, ..., the four sums added in wave
+// order; then either the gradient is stored or Adam updates the parameter.
+// The last block sums the per-workgroup losses (strided, then a fixed tree).
+template <bool ADAM>
+__global__ __launch_bounds__(256) void k_mlp_reduce(int nwg, const float *__restrict__ partial,
+                                                    const float *__restrict__ lossp, float *__restrict__ grad,
+                                                    float *__restrict__ loss, float *__restrict__ P,
+                                                    float *__restrict__ m, float *__restrict__ v, float lr, float c1,
+                                                    float c2) {
+  __shared__ float red[256];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (blockIdx.x == gridDim.x - 1) {
     float l = 0.0f;
-    for (int w = 0; w < nwg; ++w) l += lossp[w];
-    *loss = l;
+    for (int q = threadIdx.x; q < nwg; q += 256) l += lossp[q];
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = red[0];
+    return;
   }
-  if (p >= NP) return;
+  const int p = blockIdx.x * 64 + lane;
   float g = 0.0f;
-  for (int w = 0; w < nwg; ++w) g += partial[(int64_t)w * NP + p];
-  grad[p] = g;
-}
-
-__global__ void k_mlp_adam(float *__restrict__ P, const float *__restrict__ grad, float *__restrict__ m,
-                           float *__restrict__ v, float lr, float c1, float c2) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= NP) return;
+  if (p < NP)
+    for (int q = w; q < nwg; q += 4) g += partial[(int64_t)q * NP + p];
+  red[threadIdx.x] = g;
+  __syncthreads();
+  if (w != 0 || p >= NP) return;
+  const float gs = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
+  if (!ADAM) {
+    grad[p] = gs;
+    return;
+  }
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-  const float g = grad[p];
-  const float mm = b1 * m[p] + (1.0f - b1) * g;
-  const float vv = b2 * v[p] + (1.0f - b2) * g * g;
+  const float mm = b1 * m[p] + (1.0f - b1) * gs;
+  const float vv = b2 * v[p] + (1.0f - b2) * gs * gs;
   m[p] = mm;
   v[p] = vv;
   P[p] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
@@ -318,14 +334,21 @@ __device__ inline f32x16 mma(f16x8 a, f16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
 }
 
+// The packed operands live in LDS (27.6 KB per workgroup); each lane reads
+// its 16 bytes of an operand just before the instruction that needs it, which
+// keeps them out of the registers the products and activations need.
 struct Ops {
-  f16x8 a[NPK];
+  const f16x8 *lds;  // [NPK][64]
+  int lane;          // this lane's slot, hidden from the compiler per call (see forward)
+  __device__ f16x8 operator[](int i) const { return lds[64 * i + lane]; }
 };
 
-__device__ inline void load_ops(const void *pk, Ops &W) {
+// all threads of the workgroup copy the operands into lds (then a barrier)
+__device__ inline Ops load_ops(const void *pk, f16x8 *lds) {
   const f16x8 *p = reinterpret_cast<const f16x8 *>(pk);
-  const int l = threadIdx.x & 63;
-  for (int i = 0; i < NPK; ++i) W.a[i] = p[64 * i + l];
+  for (int i = threadIdx.x; i < 64 * NPK; i += blockDim.x) lds[i] = p[i];
+  __syncthreads();
+  return Ops{lds, (int)(threadIdx.x & 63)};
 }
 
 // B operand of the first layer: u split into FP16 high and low parts, with
@@ -363,31 +386,36 @@ __device__ inline void act_tile(const f32x16 &d, f16x8 &c0, f16x8 &c1) {
 
 // (phi_c, A_c) at the folded offsets of the 32 pairs of this wave: lane l
 // passes the B operand of pair l % 32 and receives its 4 outputs.
-__device__ inline void forward(const Ops &W, const f16x8 &xin, const f16x8 &one, float y[4]) {
+__device__ inline void forward(const Ops &W0, const f16x8 &xin, const f16x8 &one, float y[4]) {
+  // An empty asm makes the lane slot opaque, so the operand reads are not
+  // hoisted out of the walk's loops into registers (which would leave the
+  // products in accumulation registers and cut the occupancy).
+  Ops W = W0;
+  asm volatile("" : "+v"(W.lane));
   const f32x16 z = {0};
   f16x8 h[4];
   {
-    const f32x16 d0 = mma(W.a[PK_L1], xin, z);
-    const f32x16 d1 = mma(W.a[PK_L1 + 1], xin, z);
+    const f32x16 d0 = mma(W[PK_L1], xin, z);
+    const f32x16 d1 = mma(W[PK_L1 + 1], xin, z);
     act_tile(d0, h[0], h[1]);
     act_tile(d1, h[2], h[3]);
   }
 #pragma unroll
   for (int layer = 0; layer < 2; ++layer) {
     const int A0 = layer == 0 ? PK_L2 : PK_L3, B0 = layer == 0 ? PK_L2B : PK_L3B;
-    f32x16 d0 = mma(W.a[B0], one, z);
-    f32x16 d1 = mma(W.a[B0 + 1], one, z);
+    f32x16 d0 = mma(W[B0], one, z);
+    f32x16 d1 = mma(W[B0 + 1], one, z);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      d0 = mma(W.a[A0 + c], h[c], d0);
-      d1 = mma(W.a[A0 + 4 + c], h[c], d1);
+      d0 = mma(W[A0 + c], h[c], d0);
+      d1 = mma(W[A0 + 4 + c], h[c], d1);
     }
     act_tile(d0, h[0], h[1]);
     act_tile(d1, h[2], h[3]);
   }
-  f32x16 o = mma(W.a[PK_L4B], one, z);
+  f32x16 o = mma(W[PK_L4B], one, z);
 #pragma unroll
-  for (int c = 0; c < 4; ++c) o = mma(W.a[PK_L4 + c], h[c], o);
+  for (int c = 0; c < 4; ++c) o = mma(W[PK_L4 + c], h[c], o);
   for (int k = 0; k < 4; ++k) y[k] = o[k];
 }
 
@@ -399,8 +427,8 @@ namespace {
 // limit minus the Newtonian part, as in the walk.  One wave per 32 offsets.
 __global__ __launch_bounds__(256) void k_mlp_points_eval(const void *__restrict__ pk, EwaldP E, int64_t n,
                                                          const double *__restrict__ d, double *__restrict__ out) {
-  mlpinf::Ops W;
-  mlpinf::load_ops(pk, W);
+  __shared__ f16x8 wl[64 * NPK];
+  const mlpinf::Ops W = mlpinf::load_ops(pk, wl);
   const f16x8 one = mlpinf::ones();
   const int l = threadIdx.x & 63;
   const int64_t q = 32 * (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) + (l & 31);
@@ -452,17 +480,9 @@ __global__ __launch_bounds__(WG) void k_eval_mlp(DevTree T, EwaldP E, const void
   double cT[3];
   for (int k = 0; k < 3; ++k) cT[k] = centre_coord(T.org[k], T.bcoord[3 * b + k], sb);
   const int64_t own0 = T.na + 72 * T.nb + 512 * b;
-  mlpinf::Ops W;
-  mlpinf::load_ops(pk, W);
+  __shared__ f16x8 wl[64 * NPK];
+  const mlpinf::Ops W = mlpinf::load_ops(pk, wl);
   const f16x8 one = mlpinf::ones();
-  // cell of batch bb for this lane (pair 32 bb + m of the wave)
-  float px[4], py[4], pz[4];
-  for (int bb = 0; bb < 4; ++bb) {
-    const int ci = 64 * w + 32 * (bb & 1) + m + 256 * (bb >> 1);
-    px[bb] = (float)(((double)(ci & 7) - 3.5) * h);
-    py[bb] = (float)(((double)((ci >> 3) & 7) - 3.5) * h);
-    pz[bb] = (float)(((double)(ci >> 6) - 3.5) * h);
-  }
   const float Lx = (float)E.L[0], Ly = (float)E.L[1], Lz = (float)E.L[2];
   const float zfar = (float)E.zfar, fa = (float)E.far_phi_a, fb = (float)E.far_phi_b, faz = (float)E.far_az;
   float s[2] = {0.f, 0.f}, cc[2] = {0.f, 0.f}, ax[2] = {0.f, 0.f}, ay[2] = {0.f, 0.f}, az[2] = {0.f, 0.f};
@@ -488,9 +508,15 @@ __global__ __launch_bounds__(WG) void k_eval_mlp(DevTree T, EwaldP E, const void
     const int mm = (int)(n - t0 < WG ? n - t0 : WG);
     for (int j = 0; j < mm; ++j) {
       const float4 r = tile[j];
-#pragma unroll
+      // one batch of 32 pairs at a time (a loop, not unrolled: fewer live
+      // registers, so the products stay in ordinary vector registers)
+#pragma unroll 1
       for (int bb = 0; bb < 4; ++bb) {
-        float dx = px[bb] - r.x, dy = py[bb] - r.y, dz = pz[bb] - r.z;
+        // cell of pair 32 bb + m of the wave, as the own-cell offsets above
+        const int ci = 64 * w + 32 * (bb & 1) + m + 256 * (bb >> 1);
+        float dx = (float)(((double)(ci & 7) - 3.5) * h) - r.x;
+        float dy = (float)(((double)((ci >> 3) & 7) - 3.5) * h) - r.y;
+        float dz = (float)(((double)(ci >> 6) - 3.5) * h) - r.z;
         dx = dx - Lx * floorf(dx / Lx + 0.5f);
         dy = dy - Ly * floorf(dy / Ly + 0.5f);
         if (BC == 1) dz = dz - Lz * floorf(dz / Lz + 0.5f);
@@ -510,14 +536,22 @@ __global__ __launch_bounds__(WG) void k_eval_mlp(DevTree T, EwaldP E, const void
           A2 = dz < 0 ? -faz : faz;
         }
         const bool use = g == (bb & 1) && r2 > 0.0f;
-        const int q = bb >> 1;
-        const float yk = r.w * ph - cc[q];
-        const float tk = s[q] + yk;
-        cc[q] = use ? (tk - s[q]) - yk : cc[q];
-        s[q] = use ? tk : s[q];
-        ax[q] += use ? r.w * A0 : 0.0f;
-        ay[q] += use ? r.w * A1 : 0.0f;
-        az[q] += use ? r.w * A2 : 0.0f;
+        // slot bb >> 1 is wave-uniform: a uniform branch, no indexed registers
+        if (bb >> 1) {
+          const float yk = r.w * ph - cc[1], tk = s[1] + yk;
+          cc[1] = use ? (tk - s[1]) - yk : cc[1];
+          s[1] = use ? tk : s[1];
+          ax[1] += use ? r.w * A0 : 0.0f;
+          ay[1] += use ? r.w * A1 : 0.0f;
+          az[1] += use ? r.w * A2 : 0.0f;
+        } else {
+          const float yk = r.w * ph - cc[0], tk = s[0] + yk;
+          cc[0] = use ? (tk - s[0]) - yk : cc[0];
+          s[0] = use ? tk : s[0];
+          ax[0] += use ? r.w * A0 : 0.0f;
+          ay[0] += use ? r.w * A1 : 0.0f;
+          az[0] += use ? r.w * A2 : 0.0f;
+        }
       }
     }
     __syncthreads();
@@ -551,29 +585,48 @@ hipError_t launch_mlp_prepare(int64_t n, const double *u, const double *ser, con
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_grad(const float *P, int64_t n, int64_t s0, int64_t batch, const float *X, const float *T,
-                           float *partial, float *lossp, float *grad, float *loss, hipStream_t st) {
+namespace {
+
+// forward + backward of the batch [s0, s0 + batch) into the per-workgroup partials
+hipError_t fwdbwd(const float *P, int64_t n, int64_t s0, int64_t batch, const float *X, const float *T,
+                  float *partial, float *lossp, hipStream_t st) {
   if (batch <= 0 || batch % SB || n % SB || s0 % SB || batch > n) return hipErrorInvalidValue;
-  const int nwg = (int)(batch / SB);
   const size_t lds = sizeof(TrainLds);
   static bool attr = false;
-  if (!attr) {
+  if (!attr && lds > 65536) {
     hipError_t e =
         hipFuncSetAttribute((const void *)k_mlp_fwdbwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(k_mlp_fwdbwd, dim3(nwg), dim3(256), lds, st, P, n, s0, X, T, 1.0f / (4.0f * (float)batch),
-                     partial, lossp);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mlp_reduce, dim3((NP + 255) / 256), dim3(256), 0, st, nwg, partial, lossp, grad, loss);
+  hipLaunchKernelGGL(k_mlp_fwdbwd, dim3((unsigned)(batch / SB)), dim3(256), lds, st, P, n, s0, X, T,
+                     1.0f / (4.0f * (float)batch), partial, lossp);
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_adam(float *P, const float *grad, float *m, float *v, float lr, int step, hipStream_t st) {
+constexpr unsigned reduce_blocks() { return (NP + 63) / 64 + 1; }  // + 1: the loss
+
+}  // namespace
+
+int64_t mlp_partials(int64_t batch) { return batch / SB; }
+
+hipError_t launch_mlp_grad(const float *P, int64_t n, int64_t s0, int64_t batch, const float *X, const float *T,
+                           float *partial, float *lossp, float *grad, float *loss, hipStream_t st) {
+  hipError_t e = fwdbwd(P, n, s0, batch, X, T, partial, lossp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mlp_reduce<false>, dim3(reduce_blocks()), dim3(256), 0, st, (int)(batch / SB), partial,
+                     lossp, grad, loss, (float *)nullptr, (float *)nullptr, (float *)nullptr, 0.0f, 1.0f, 1.0f);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_step(float *P, int64_t n, int64_t s0, int64_t batch, const float *X, const float *T,
+                           float *partial, float *lossp, float *loss, float *m, float *v, float lr, int step,
+                           hipStream_t st) {
+  hipError_t e = fwdbwd(P, n, s0, batch, X, T, partial, lossp, st);
+  if (e != hipSuccess) return e;
   const float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);
-  hipLaunchKernelGGL(k_mlp_adam, dim3((NP + 255) / 256), dim3(256), 0, st, P, grad, m, v, lr, c1, c2);
+  hipLaunchKernelGGL(k_mlp_reduce<true>, dim3(reduce_blocks()), dim3(256), 0, st, (int)(batch / SB), partial,
+                     lossp, (float *)nullptr, loss, P, m, v, lr, c1, c2);
   return hipGetLastError();
 }
 

@@ -117,11 +117,15 @@ hipError_t launch_mlp_points(uint64_t seed, int64_t n, const double ext[3], doub
 hipError_t launch_mlp_prepare(int64_t n, const double *u, const double *ser, const MlpNorm &N, float *x, float *t,
                               hipStream_t st);
 // gradient of the batch MSE at P over samples [s0, s0 + batch) (wrapping at n)
-// of x [n][3], t [n][4]: partial [batch/32][NP] scratch, grad [NP], loss
-// (FP32 sum) into *loss
+// of x [n][3], t [n][4]: partial [mlp_partials(batch)][NP] and lossp
+// [mlp_partials(batch)] scratch, grad [NP], loss (FP32 sum) into *loss
+int64_t mlp_partials(int64_t batch);
 hipError_t launch_mlp_grad(const float *P, int64_t n, int64_t s0, int64_t batch, const float *X, const float *T,
                            float *partial, float *lossp, float *grad, float *loss, hipStream_t st);
-hipError_t launch_mlp_adam(float *P, const float *grad, float *m, float *v, float lr, int step, hipStream_t st);
+// one Adam step (step >= 1, step size lr) on the same batch gradient
+hipError_t launch_mlp_step(float *P, int64_t n, int64_t s0, int64_t batch, const float *X, const float *T,
+                           float *partial, float *lossp, float *loss, float *m, float *v, float lr, int step,
+                           hipStream_t st);
 // pack (P, N) into the matrix-core operands used by inference
 hipError_t launch_mlp_pack(const float *P, const MlpNorm &N, void *pk, hipStream_t st);
 // correction (phi_c, A_c) at offsets d [n][3] by the surrogate: out [n][4]
