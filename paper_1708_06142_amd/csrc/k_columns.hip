@@ -203,33 +203,38 @@ __device__ inline float acos_est(float x) {
 // with phi in (pi, 2 pi) mapped to the upper half-plane by v -> -v; on the x
 // axis (v_y = +-0) phi is that of atan2: 0, or pi (bin ip_pi) when v_x has its
 // sign bit set.  The comparisons are FP64.
-// Which k to compare: FP32 estimates of the three angles (error ~1e-3 rad at
-// worst, from the rounding of the ratios near the poles) locate the bin to
-// within one when every bin is wider than 0.01 rad, and the comparisons at k0
-// and k0 + 1 then give the same bins as a full binary search over the
-// thresholds, which remains for narrower bins and for offsets too small for
-// FP32.
+// Which k to compare: FP32 estimates of the three angles (error ~4e-3 rad at
+// worst) locate the bin to within one when every bin is wider than 0.01 rad,
+// and the comparisons at k0 and k0 + 1 then give the same bins as a full
+// binary search over the thresholds, which remains for narrower bins, for
+// offsets too small for FP32 and for nodes closer than R_eq h / 0.65.
 __device__ inline int table_row(const ColP &C, const double *thr, double vx, double vy, double vz,
-                                double r2, double rh) {
+                                double r2, float f2, double rh2, float rhf) {
   const double *cth = thr;                       // [ntheta + 1] c |c|, sentinel -inf
   const double *sps = cth + C.ntheta + 1;        // [npsi + 1] sin^2, sentinel +inf
   const double *cph = sps + C.npsi + 1;          // [nphi/2 + 1], the last cos(pi) = -1
   const double *sph = cph + (C.nphi / 2 + 1);    // [nphi/2 + 1], the last sin(pi) = 0
-  const double rh2 = rh * rh, vzz = vz * fabs(vz);
+  const double vzz = vz * fabs(vz);
   const int half = C.nphi / 2;
   const bool lower = vy < 0.0;
-  const double ux = lower ? -vx : vx, uy = lower ? -vy : vy;
+  // v -> -v on the lower half-plane: u_y = |v_y|, u_x = v_x with v_y's sign
+  // (they differ from the flip only at v_y = -0, which takes the v_y = 0 rule)
+  const double uy = fabs(vy);
+  const double ux = __longlong_as_double(__double_as_longlong(vx) ^ (__double_as_longlong(vy) & (long long)0x8000000000000000ull));
   auto pth = [&](int k) { return vzz <= cth[k] * r2; };
   auto pps = [&](int k) { return rh2 >= sps[k] * r2; };
   auto pph = [&](int q) { return cph[q] * uy - sph[q] * ux >= 0.0; };
-  const float f2 = (float)r2, fx = (float)ux, fy = (float)uy;
+  const float fx = (float)ux, fy = (float)uy;
   const float rho2 = fx * fx + fy * fy;
+  const float rd = __builtin_amdgcn_rsqf(f2);
+  const float sn = rhf * rd;  // sin psi
   int it, is, k;
-  if (C.estimate && f2 > 1e-30f && rho2 > 1e-30f) {
-    const float rd = __builtin_amdgcn_rsqf(f2);
+  if (C.estimate && f2 > 1e-30f && rho2 > 1e-30f && sn < 0.65f) {
     it = near_true(C.ntheta, (int)(acos_est((float)vz * rd) * C.inv_dtheta), pth);
-    const float sn = fminf((float)rh * rd, 1.0f);
-    is = near_true(C.npsi, (int)((1.5707963f - acos_est(sn)) * C.inv_dpsi), pps);
+    // asin by its series to s^5 (error below 4e-3 rad for s < 0.65; every
+    // accepted node has s <= R_eq / 1 = 0.62)
+    const float s2 = sn * sn;
+    is = near_true(C.npsi, (int)(fmaf(sn * s2, fmaf(0.075f, s2, 0.16666667f), sn) * C.inv_dpsi), pps);
     k = near_true(half, (int)(acos_est(fx * __builtin_amdgcn_rsqf(rho2)) * C.inv_dphi), pph);
   } else {
     it = last_true(C.ntheta, pth);
@@ -295,9 +300,8 @@ __device__ inline bool grav64(const EwaldP &E, double dx, double dy, double dz, 
 
 // FP32 gravity of one pair (same forms as the FP32 walk)
 template <int BC>
-__device__ inline void grav32(const EwaldP &E, float dx, float dy, float dz, float &phi, float &A0, float &A1,
-                              float &A2) {
-  const float r2 = dx * dx + dy * dy + dz * dz;
+__device__ inline void grav32(const EwaldP &E, float dx, float dy, float dz, float r2, float &phi, float &A0,
+                              float &A1, float &A2) {
   const float inv = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
   const float inv3 = inv * inv * inv;
   if (BC == 0) {
@@ -342,8 +346,9 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
                                                    int cpw, int lcpw) {
   extern __shared__ __align__(16) unsigned char smem[];
   double4 *tile = reinterpret_cast<double4 *>(smem);
-  double *tileh = reinterpret_cast<double *>(smem + TILE * sizeof(double4));
-  double *thr = tileh + TILE;
+  double *tileh = reinterpret_cast<double *>(smem + TILE * sizeof(double4));  // (R_eq h)^2
+  float2 *tilef = reinterpret_cast<float2 *>(tileh + TILE);                   // R_eq h, m (FP32)
+  double *thr = reinterpret_cast<double *>(tilef + TILE);
   Real *map = reinterpret_cast<Real *>(thr + C.nthr);
   const int nchunk = 512 / cpw;
   const int64_t b = blockIdx.x / nchunk;
@@ -364,8 +369,11 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
   for (int64_t t0 = 0; t0 < n; t0 += TILE) {
     __syncthreads();
     for (int q = tid; q < TILE && t0 + q < n; q += cpw) {
-      tile[q] = rec[start + t0 + q];
-      tileh[q] = C.req * lh[start + t0 + q];  // radius of the equal-volume sphere
+      const double4 rq = rec[start + t0 + q];
+      const double rh = C.req * lh[start + t0 + q];  // radius of the equal-volume sphere
+      tile[q] = rq;
+      tileh[q] = rh * rh;
+      tilef[q] = make_float2((float)rh, (float)rq.w);
     }
     __syncthreads();
     const int m = (int)(n - t0 < TILE ? n - t0 : TILE);
@@ -376,7 +384,9 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
       const double r2 = dx * dx + dy * dy + dz * dz;
       const bool valid = r2 != 0.0;  // the target cell itself contributes nothing
       const bool col = valid && r2 <= C.max_dist2;
-      const int e = col ? table_row(C, thr, -dx, -dy, -dz, r2, tileh[j]) : 0;
+      const float r2f = (float)r2;
+      const float2 nf = tilef[j];
+      const int e = col ? table_row(C, thr, -dx, -dy, -dz, r2, r2f, tileh[j], nf.x) : 0;
       const uint4 row = C.rows4[e];
       const int o0 = (int)(row.x >> 6), cnt = col ? (int)(row.x & 63) : 0;
       if (sizeof(Real) == 8) {
@@ -392,8 +402,8 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
       } else {
         // FP32 gravity from the FP64 offset (already the minimum image)
         float ph, A0, A1, A2;
-        grav32<BC>(E, (float)dx, (float)dy, (float)dz, ph, A0, A1, A2);
-        const float m32 = valid ? (float)r.w : 0.0f;
+        grav32<BC>(E, (float)dx, (float)dy, (float)dz, r2f, ph, A0, A1, A2);
+        const float m32 = valid ? nf.y : 0.0f;
         const float y = m32 * ph - (float)cmp;
         const float tt = (float)s + y;
         cmp = valid ? (Real)((tt - (float)s) - y) : cmp;
@@ -401,7 +411,7 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         ax += (Real)(m32 * A0);
         ay += (Real)(m32 * A1);
         az += (Real)(m32 * A2);
-        const float base = col ? m32 * __builtin_amdgcn_rcpf(omega32 * (float)r2) * (1.0f / 16777216.0f) : 0.0f;
+        const float base = col ? m32 * __builtin_amdgcn_rcpf(omega32 * r2f) * (1.0f / 16777216.0f) : 0.0f;
         // the first three entries come with the row (zero weight past cnt);
         // plain read-modify-write: the column is the thread's own, and LDS
         // atomic adds measured 2.5x slower here
@@ -470,7 +480,7 @@ hipError_t launch_raytable(const RayTableP &P, double *dense, int32_t *cnt, int6
 }
 
 size_t cols_smem_bytes(int npix, int cpw, bool fp64, int nthr) {
-  return TILE * (sizeof(double4) + sizeof(double)) + (size_t)nthr * sizeof(double) +
+  return TILE * (sizeof(double4) + sizeof(double) + sizeof(float2)) + (size_t)nthr * sizeof(double) +
          (size_t)npix * cpw * (fp64 ? 8 : 4);
 }
 
