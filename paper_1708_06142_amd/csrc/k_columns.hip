@@ -228,18 +228,25 @@ __device__ inline int table_row(const ColP &C, const double *thr, double vx, dou
   const float rho2 = fx * fx + fy * fy;
   const float rd = __builtin_amdgcn_rsqf(f2);
   const float sn = rhf * rd;  // sin psi
-  int it, is, k;
-  if (C.estimate && f2 > 1e-30f && rho2 > 1e-30f && sn < 0.65f) {
-    it = near_true(C.ntheta, (int)(acos_est((float)vz * rd) * C.inv_dtheta), pth);
-    // asin by its series to s^5 (error below 4e-3 rad for s < 0.65; every
-    // accepted node has s <= R_eq / 1 = 0.62)
-    const float s2 = sn * sn;
-    is = near_true(C.npsi, (int)(fmaf(sn * s2, fmaf(0.075f, s2, 0.16666667f), sn) * C.inv_dpsi), pps);
-    k = near_true(half, (int)(acos_est(fx * __builtin_amdgcn_rsqf(rho2)) * C.inv_dphi), pph);
-  } else {
-    it = last_true(C.ntheta, pth);
-    is = last_true(C.npsi, pps);
-    k = last_true(half, pph);
+  // The estimates run on every lane (the probes' indices are clamped, so a
+  // lane outside the estimates' range still reads inside the thresholds);
+  // such lanes are then redone by the binary search under a wave-uniform
+  // branch, which keeps the common path free of divergent control flow.
+  // (on the x axis, v_y = 0, phi comes from the atan2 rule below and its
+  // estimate is not used: a node straight above or below the cell is safe)
+  const bool safe = C.estimate && f2 > 1e-30f && sn < 0.65f && (rho2 > 1e-30f || vy == 0.0);
+  int it = near_true(C.ntheta, (int)(acos_est((float)vz * rd) * C.inv_dtheta), pth);
+  // asin by its series to s^5 (error below 4e-3 rad for s < 0.65; every
+  // node accepted through the BH test at theta_pix <= 1 has s <= R_eq)
+  const float s2 = sn * sn;
+  int is = near_true(C.npsi, (int)(fmaf(sn * s2, fmaf(0.075f, s2, 0.16666667f), sn) * C.inv_dpsi), pps);
+  int k = near_true(half, (int)(acos_est(fx * __builtin_amdgcn_rsqf(rho2)) * C.inv_dphi), pph);
+  if (__ballot(!safe)) {
+    if (!safe) {
+      it = last_true(C.ntheta, pth);
+      is = last_true(C.npsi, pps);
+      k = last_true(half, pph);
+    }
   }
   // atan2(+-0, x) is pi (bin ip_pi) whenever the sign bit of x is set, -0
   // included (a node straight above the cell, v = -d with d_x = +0), else 0
