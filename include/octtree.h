@@ -69,8 +69,8 @@ typedef struct {
   double eta_sb;         /* safe-box factor, Sec. 2.1, gr_bhTreeSafeBox         [1.2]  */
   int32_t mac;           /* ot_mac; APE uses Eq. (6) with p = 1, Eq. (4)        [BH]   */
   int32_t ewald;         /* ot_ewald: correction in the walk: TABLE or MLP (the
-                            FP32 walk without columns; every other walk uses the
-                            table); EXACT is rejected by the walk               [TABLE] */
+                            FP32 walks, with or without columns; the FP64 walks
+                            use the table); EXACT is rejected by the walk     [TABLE] */
   double a_lim;          /* APE absolute limit, Eq. (4); <= 0: a_lim = eps_lim *
                             a_max from a BH (theta_lim) FP64 pass, Sec. 3      [0]    */
   double eps_lim;        /* relative device of Sec. 3 for a_lim                 [1e-3] */

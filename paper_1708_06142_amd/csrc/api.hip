@@ -449,7 +449,7 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
       return fail(c, OT_ERR_UNSUPPORTED, "per-pair exact Ewald series is not built into the walk");
     OTCHK(ewald_prepare(c, st));
   }
-  const bool use_mlp = c->bctype != ot::BC_ISO && c->p.ewald == OT_EWALD_MLP && c->mlp_ok && !fp64 && !cols;
+  const bool use_mlp = c->bctype != ot::BC_ISO && c->p.ewald == OT_EWALD_MLP && c->mlp_ok && !fp64;
   if (cols) OTCHK(raytable_prepare(c, st));
   double alim = 0.0;
   if (c->p.mac == OT_MAC_APE) OTCHK(ape_limit(c, st, &alim));
@@ -464,13 +464,17 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
     const int cpw = cols_cpw(c, fp64);
     if (!cpw) return fail(c, OT_ERR_UNSUPPORTED, "column maps do not fit in LDS");
     HIPCHK(ot::launch_eval_cols(fp64, T, E, col_params(c), P<int64_t>(c->loff), P<double4>(c->lrec),
-                                P<double>(c->lh), phi, acc, npix, tau, c->p.G, cpw, st));
+                                P<double>(c->lh), phi, acc, npix, tau, c->p.G, cpw, use_mlp, st));
+    // with the surrogate: the column walk left the Newtonian part; add the correction
+    if (use_mlp)
+      HIPCHK(ot::launch_eval_mlp(T, E, c->mlp_pk.ptr, P<int64_t>(c->loff), P<double4>(c->lrec),
+                                 P<int32_t>(c->lid), (float *)phi, (float *)acc, c->p.G, true, st));
   } else if (fp64)
     HIPCHK(ot::launch_eval64(T, E, P<int64_t>(c->loff), P<double4>(c->lrec), (double *)phi,
                              (double *)acc, c->p.G, st));
   else if (use_mlp)
     HIPCHK(ot::launch_eval_mlp(T, E, c->mlp_pk.ptr, P<int64_t>(c->loff), P<double4>(c->lrec),
-                               P<int32_t>(c->lid), (float *)phi, (float *)acc, c->p.G, st));
+                               P<int32_t>(c->lid), (float *)phi, (float *)acc, c->p.G, false, st));
   else
     HIPCHK(ot::launch_eval32(T, E, P<int64_t>(c->loff), P<double4>(c->lrec), P<int32_t>(c->lid),
                              (float *)phi, (float *)acc, c->p.G, st));

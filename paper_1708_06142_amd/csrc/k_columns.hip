@@ -305,13 +305,14 @@ __device__ inline bool grav64(const EwaldP &E, double dx, double dy, double dz, 
   return true;
 }
 
-// FP32 gravity of one pair (same forms as the FP32 walk)
-template <int BC>
+// FP32 gravity of one pair (same forms as the FP32 walk); NEWTON: only the
+// minimum-image Newtonian part (the correction is added by another kernel)
+template <int BC, bool NEWTON>
 __device__ inline void grav32(const EwaldP &E, float dx, float dy, float dz, float r2, float &phi, float &A0,
                               float &A1, float &A2) {
   const float inv = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
   const float inv3 = inv * inv * inv;
-  if (BC == 0) {
+  if (BC == 0 || NEWTON) {
     phi = inv;
     A0 = dx * inv3;
     A1 = dy * inv3;
@@ -345,7 +346,7 @@ __device__ inline void grav32(const EwaldP &E, float dx, float dy, float dz, flo
 }
 
 // One workgroup handles cpw cells (one per thread) of one leaf block.
-template <typename Real, int BC>
+template <typename Real, int BC, bool NEWTON>
 __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, const int64_t *__restrict__ off,
                                                    const double4 *__restrict__ rec, const double *__restrict__ lh,
                                                    Real *__restrict__ phi, Real *__restrict__ acc,
@@ -409,7 +410,7 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
       } else {
         // FP32 gravity from the FP64 offset (already the minimum image)
         float ph, A0, A1, A2;
-        grav32<BC>(E, (float)dx, (float)dy, (float)dz, r2f, ph, A0, A1, A2);
+        grav32<BC, NEWTON>(E, (float)dx, (float)dy, (float)dz, r2f, ph, A0, A1, A2);
         const float m32 = valid ? nf.y : 0.0f;
         const float y = m32 * ph - (float)cmp;
         const float tt = (float)s + y;
@@ -500,30 +501,35 @@ hipError_t launch_raytable_pack(const RayTableP &P, const int64_t *off, const ui
 
 hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const ColP &C, const int64_t *off,
                             const double4 *rec, const double *lh, void *phi, void *acc, void *npix, void *tau,
-                            double G, int cpw, hipStream_t st) {
+                            double G, int cpw, bool newton_only, hipStream_t st) {
   const size_t sm = cols_smem_bytes(C.npix, cpw, fp64, C.nthr);
   int lcpw = 0;
   while ((1 << lcpw) < cpw) ++lcpw;
   if ((1 << lcpw) != cpw) return hipErrorInvalidValue;  // cells per workgroup: a power of two
   dim3 grid((unsigned)(T.nb * (512 / cpw))), blk(cpw);
-#define OT_LAUNCH(R, B)                                                                                       \
+#define OT_LAUNCH(R, B, N)                                                                                    \
   do {                                                                                                        \
     if (sm > 65536) {                                                                                         \
-      hipError_t ea = hipFuncSetAttribute((const void *)k_eval_cols<R, B>,                                   \
+      hipError_t ea = hipFuncSetAttribute((const void *)k_eval_cols<R, B, N>,                                \
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);              \
       if (ea != hipSuccess) return ea;                                                                        \
     }                                                                                                         \
-    hipLaunchKernelGGL((k_eval_cols<R, B>), grid, blk, sm, st, T, E, C, off, rec, lh, (R *)phi, (R *)acc,  \
+    hipLaunchKernelGGL((k_eval_cols<R, B, N>), grid, blk, sm, st, T, E, C, off, rec, lh, (R *)phi, (R *)acc, \
                        (R *)npix, (R *)tau, -G, cpw, lcpw);                                                  \
   } while (0)
   if (fp64) {
-    if (E.bctype == 0) OT_LAUNCH(double, 0);
-    else if (E.bctype == 1) OT_LAUNCH(double, 1);
-    else OT_LAUNCH(double, 2);
+    if (newton_only) return hipErrorInvalidValue;
+    if (E.bctype == 0) OT_LAUNCH(double, 0, false);
+    else if (E.bctype == 1) OT_LAUNCH(double, 1, false);
+    else OT_LAUNCH(double, 2, false);
+  } else if (newton_only) {
+    if (E.bctype == 1) OT_LAUNCH(float, 1, true);
+    else if (E.bctype == 2) OT_LAUNCH(float, 2, true);
+    else return hipErrorInvalidValue;
   } else {
-    if (E.bctype == 0) OT_LAUNCH(float, 0);
-    else if (E.bctype == 1) OT_LAUNCH(float, 1);
-    else OT_LAUNCH(float, 2);
+    if (E.bctype == 0) OT_LAUNCH(float, 0, false);
+    else if (E.bctype == 1) OT_LAUNCH(float, 1, false);
+    else OT_LAUNCH(float, 2, false);
   }
 #undef OT_LAUNCH
   return hipGetLastError();

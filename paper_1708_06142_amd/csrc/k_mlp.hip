@@ -466,7 +466,7 @@ __global__ __launch_bounds__(256) void k_mlp_points_eval(const void *__restrict_
 // b & 1 in slot b >> 1.  Phi is Kahan-compensated.
 constexpr int WG = 256;
 
-template <int BC>
+template <int BC, bool ADD>
 __global__ __launch_bounds__(WG) void k_eval_mlp(DevTree T, EwaldP E, const void *__restrict__ pk,
                                                  const int64_t *__restrict__ off, const double4 *__restrict__ rec,
                                                  const int32_t *__restrict__ ids, float *__restrict__ phi,
@@ -525,15 +525,17 @@ __global__ __launch_bounds__(WG) void k_eval_mlp(DevTree T, EwaldP E, const void
         const float r2 = dx * dx + dy * dy + dz * dz;
         const float inv = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
         const float inv3 = inv * inv * inv;
-        float ph = inv + y[0];
-        float A0 = dx * inv3 + (dx < 0 ? -y[1] : y[1]);
-        float A1 = dy * inv3 + (dy < 0 ? -y[2] : y[2]);
-        float A2 = dz * inv3 + (dz < 0 ? -y[3] : y[3]);
+        // ADD: the Newtonian part is already in the outputs
+        const float nw = ADD ? 0.0f : 1.0f;
+        float ph = nw * inv + y[0];
+        float A0 = nw * dx * inv3 + (dx < 0 ? -y[1] : y[1]);
+        float A1 = nw * dy * inv3 + (dy < 0 ? -y[2] : y[2]);
+        float A2 = nw * dz * inv3 + (dz < 0 ? -y[3] : y[3]);
         if (BC == 2 && fabsf(dz) > zfar) {
-          ph = fa * fabsf(dz) + fb;
-          A0 = 0.0f;
-          A1 = 0.0f;
-          A2 = dz < 0 ? -faz : faz;
+          ph = fa * fabsf(dz) + fb - (1.0f - nw) * inv;
+          A0 = -(1.0f - nw) * dx * inv3;
+          A1 = -(1.0f - nw) * dy * inv3;
+          A2 = (dz < 0 ? -faz : faz) - (1.0f - nw) * dz * inv3;
         }
         const bool use = g == (bb & 1) && r2 > 0.0f;
         // slot bb >> 1 is wave-uniform: a uniform branch, no indexed registers
@@ -558,10 +560,10 @@ __global__ __launch_bounds__(WG) void k_eval_mlp(DevTree T, EwaldP E, const void
   }
   for (int q = 0; q < 2; ++q) {
     const int64_t o = b * 512 + tid + q * WG;
-    phi[o] = negG * (s[q] - cc[q]);
-    acc[o] = negG * ax[q];
-    acc[ncell + o] = negG * ay[q];
-    acc[2 * ncell + o] = negG * az[q];
+    phi[o] = (ADD ? phi[o] : 0.0f) + negG * (s[q] - cc[q]);
+    acc[o] = (ADD ? acc[o] : 0.0f) + negG * ax[q];
+    acc[ncell + o] = (ADD ? acc[ncell + o] : 0.0f) + negG * ay[q];
+    acc[2 * ncell + o] = (ADD ? acc[2 * ncell + o] : 0.0f) + negG * az[q];
   }
 }
 
@@ -644,14 +646,18 @@ hipError_t launch_mlp_points_eval(const void *pk, const EwaldP &E, int64_t n, co
 }
 
 hipError_t launch_eval_mlp(const DevTree &T, const EwaldP &E, const void *pk, const int64_t *off,
-                           const double4 *rec, const int32_t *ids, float *phi, float *acc, double G,
+                           const double4 *rec, const int32_t *ids, float *phi, float *acc, double G, bool add,
                            hipStream_t st) {
   dim3 grid((unsigned)T.nb), blk(WG);
   const float ng = (float)(-G);
-  if (E.bctype == 1)
-    hipLaunchKernelGGL(k_eval_mlp<1>, grid, blk, 0, st, T, E, pk, off, rec, ids, phi, acc, ng);
+  if (E.bctype == 1 && !add)
+    hipLaunchKernelGGL((k_eval_mlp<1, false>), grid, blk, 0, st, T, E, pk, off, rec, ids, phi, acc, ng);
+  else if (E.bctype == 2 && !add)
+    hipLaunchKernelGGL((k_eval_mlp<2, false>), grid, blk, 0, st, T, E, pk, off, rec, ids, phi, acc, ng);
+  else if (E.bctype == 1)
+    hipLaunchKernelGGL((k_eval_mlp<1, true>), grid, blk, 0, st, T, E, pk, off, rec, ids, phi, acc, ng);
   else if (E.bctype == 2)
-    hipLaunchKernelGGL(k_eval_mlp<2>, grid, blk, 0, st, T, E, pk, off, rec, ids, phi, acc, ng);
+    hipLaunchKernelGGL((k_eval_mlp<2, true>), grid, blk, 0, st, T, E, pk, off, rec, ids, phi, acc, ng);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

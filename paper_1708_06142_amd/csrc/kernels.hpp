@@ -68,9 +68,11 @@ hipError_t launch_raytable(const RayTableP &P, double *dense, int32_t *cnt, int6
 hipError_t launch_raytable_pack(const RayTableP &P, const int64_t *off, const uint16_t *pix, const double *w,
                                 uint32_t *rows, uint32_t *ent, uint4 *rows4, hipStream_t st);
 size_t cols_smem_bytes(int npix, int cpw, bool fp64, int nthr);
+// newton_only (FP32, 3P / 2P1I): the minimum-image Newtonian part only, for
+// every pair; launch_eval_mlp with add = true then adds the correction
 hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const ColP &C, const int64_t *off,
                             const double4 *rec, const double *lh, void *phi, void *acc, void *npix, void *tau,
-                            double G, int cpw, hipStream_t st);
+                            double G, int cpw, bool newton_only, hipStream_t st);
 
 hipError_t launch_build(const DevTree &T, const double *rho, int *bad,
                         const std::vector<int64_t> &level_begin, int lmax, hipStream_t st);
@@ -134,9 +136,11 @@ hipError_t launch_mlp_points_eval(const void *pk, const EwaldP &E, int64_t n, co
 // the same offsets by the FP64 series / the FP64 table (Taylor): out [n][4]
 hipError_t launch_ewald_points4(int method, const EwaldP &E, double alpha, int rcut2, int fcut2, int64_t n,
                                 const double *d, double *out, hipStream_t st);
-// FP32 walk with the correction from the surrogate (BC 3P or 2P1I)
+// FP32 walk with the correction from the surrogate (BC 3P or 2P1I); add:
+// only the correction (2P1I beyond zfar: the limit minus the Newtonian
+// part), added to phi and acc as the Newtonian column walk left them
 hipError_t launch_eval_mlp(const DevTree &T, const EwaldP &E, const void *pk, const int64_t *off,
-                           const double4 *rec, const int32_t *ids, float *phi, float *acc, double G,
+                           const double4 *rec, const int32_t *ids, float *phi, float *acc, double G, bool add,
                            hipStream_t st);
 
 }  // namespace ot

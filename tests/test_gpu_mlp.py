@@ -367,3 +367,44 @@ def test_walk_without_accepted_surrogate_is_the_table_walk():
         outs.append((phi.cpu(), acc.cpu()))
     for p, a in outs[1:]:
         assert torch.equal(p, outs[0][0]) and torch.equal(a, outs[0][1])
+
+
+@pytest.mark.parametrize("name", list(BOXES))
+def test_column_walk_with_surrogate(trained, name):
+    """Columns (Nside 2) with the surrogate: the column walk computes the
+    Newtonian part and the maps, the surrogate kernel adds the correction.
+    Maps and tau are those of the table walk bit for bit; Phi and a within
+    the same bounds as the gravity walk above."""
+    s_tr, rep = trained[name]
+    params, norm = s_tr.mlp_get()
+    nroot, _, bc = BOXES[name]
+    g = lognormal32(bc, nroot)
+    rho = dev(g.rho.reshape(-1))
+    n = g.nb * 512
+    res = {}
+    for mode in ("table", "mlp"):
+        s = ot.Solver.for_grid(g, theta=0.5, ewald_n=64, ewald=mode, nside=2)
+        if mode == "mlp":
+            s.mlp_set(params, norm, accept=True)
+        s.build(rho)
+        out = [torch.empty(n, dtype=torch.float32, device="cuda"),
+               torch.empty(3 * n, dtype=torch.float32, device="cuda"),
+               torch.empty(n * 48, dtype=torch.float32, device="cuda"),
+               torch.empty(n, dtype=torch.float32, device="cuda")]
+        st = s.solve(*out)
+        res[mode] = [o.cpu().numpy().astype(np.float64) for o in out] + [st]
+    (pt, at, nt, tt, st_t), (pm, am, nm, tm, st_m) = res["table"], res["mlp"]
+    assert st_t.ewald_used == 0 and st_m.ewald_used == 2
+    assert np.array_equal(nt, nm) and np.array_equal(tt, tm)
+    out = torch.empty((20000, 4), dtype=torch.float64, device="cuda")
+    s_tr.ewald_points("exact", dev(offsets(name, 20000, 3)), out)
+    cmax = np.abs(out.cpu().numpy()).max(0)
+    mtot = g.rho.sum() * (1.0 / 32) ** 3
+    e = np.array(rep["err_mlp"]) + np.array(rep["err_table"])
+    at, am = at.reshape(3, -1), am.reshape(3, -1)
+    dphi, da = np.abs(pm - pt).max(), np.abs(am - at).max()
+    print(f"{name} columns: |dPhi| {dphi:.3e} (max|Phi| {np.abs(pt).max():.3e}), |da| {da:.3e} "
+          f"(max|a| {np.abs(at).max():.3e}); ms_eval table {st_t.ms_eval:.2f}, surrogate {st_m.ms_eval:.2f}")
+    assert dphi <= 2 * mtot * e[0] * cmax[0] + 1e-6 * np.abs(pt).max()
+    assert da <= 2 * mtot * max(e[1:] * cmax[1:]) + 1e-6 * np.abs(at).max()
+    assert dphi <= 1e-4 * np.abs(pt).max() and da <= 1e-4 * np.abs(at).max()
