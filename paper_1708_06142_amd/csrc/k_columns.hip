@@ -385,6 +385,10 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
     }
     __syncthreads();
     const int m = (int)(n - t0 < TILE ? n - t0 : TILE);
+    // the acceleration is summed per tile, then the tile sums are added
+    // (blocked summation: the rounding grows with the tile and tile count,
+    // not with the list length)
+    Real tx = 0, ty = 0, tz = 0;
     for (int j = 0; j < m; ++j) {
       const double4 r = tile[j];
       double dx = cx - r.x, dy = cy - r.y, dz = cz - r.z;
@@ -402,9 +406,9 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         double ph, A0, A1, A2;
         grav64<BC>(E, dx, dy, dz, r2, ph, A0, A1, A2);
         s += (Real)(r.w * ph);
-        ax += (Real)(r.w * A0);
-        ay += (Real)(r.w * A1);
-        az += (Real)(r.w * A2);
+        tx += (Real)(r.w * A0);
+        ty += (Real)(r.w * A1);
+        tz += (Real)(r.w * A2);
         const double base = r.w / (C.omega * r2);
         for (int o = o0; o < o0 + cnt; ++o) map[((int)C.pix[o] << lcpw) + tid] += (Real)(C.w64[o] * base);
       } else {
@@ -416,9 +420,9 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         const float tt = (float)s + y;
         cmp = valid ? (Real)((tt - (float)s) - y) : cmp;
         s = valid ? (Real)tt : s;
-        ax += (Real)(m32 * A0);
-        ay += (Real)(m32 * A1);
-        az += (Real)(m32 * A2);
+        tx += (Real)(m32 * A0);
+        ty += (Real)(m32 * A1);
+        tz += (Real)(m32 * A2);
         const float base = col ? m32 * __builtin_amdgcn_rcpf(omega32 * r2f) * (1.0f / 16777216.0f) : 0.0f;
         // the first three entries come with the row (zero weight past cnt);
         // plain read-modify-write: the column is the thread's own, and LDS
@@ -432,6 +436,9 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         }
       }
     }
+    ax += tx;
+    ay += ty;
+    az += tz;
   }
   const int64_t o = b * 512 + ci;
   phi[o] = (Real)(negG * (double)(s - cmp));

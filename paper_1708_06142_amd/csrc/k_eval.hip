@@ -18,7 +18,8 @@
 // One workgroup of 256 threads per leaf block; thread t owns cells t and
 // t + 256.  The list is streamed through LDS in tiles of 256 records, which
 // every thread then reads as broadcasts.  The FP32 kernel accumulates Phi with
-// Kahan compensation and the acceleration in plain FP32.
+// Kahan compensation and the acceleration in plain FP32 per tile, the tile
+// sums then added (blocked summation).
 #include "common.hpp"
 #include "ewald_lookup.hpp"
 #include "kernels.hpp"
@@ -115,6 +116,7 @@ __global__ __launch_bounds__(WG) void k_eval64(DevTree T, EwaldP E, const int64_
 struct Acc32 {
   float s, c;  // Kahan sum of M phi and its compensation
   float ax, ay, az;
+  float tx, ty, tz;  // acceleration of the current tile (blocked summation)
 };
 
 template <int BC>
@@ -179,9 +181,9 @@ __device__ inline void pair32(const EwaldP &E, float cx, float cy, float cz, con
   const float t = a.s + y;
   a.c = (t - a.s) - y;
   a.s = t;
-  a.ax += fx;
-  a.ay += fy;
-  a.az += fz;
+  a.tx += fx;
+  a.ty += fy;
+  a.tz += fz;
 }
 
 template <int BC>
@@ -205,7 +207,7 @@ __global__ __launch_bounds__(WG) void k_eval32(DevTree T, EwaldP E, const int64_
     cx[q] = (float)(((double)(ci & 7) - 3.5) * h);
     cy[q] = (float)(((double)((ci >> 3) & 7) - 3.5) * h);
     cz[q] = (float)(((double)(ci >> 6) - 3.5) * h);
-    a[q] = Acc32{0.f, 0.f, 0.f, 0.f, 0.f};
+    a[q] = Acc32{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   }
   const int64_t start = off[b], n = off[b + 1] - start;
   for (int64_t t0 = 0; t0 < n; t0 += WG) {
@@ -232,6 +234,13 @@ __global__ __launch_bounds__(WG) void k_eval32(DevTree T, EwaldP E, const int64_
       const float4 r = tile[j];
       pair32<BC>(E, cx[0], cy[0], cz[0], r, a[0]);
       pair32<BC>(E, cx[1], cy[1], cz[1], r, a[1]);
+    }
+    // blocked summation of the acceleration: tile sums into the totals
+    for (int q = 0; q < 2; ++q) {
+      a[q].ax += a[q].tx;
+      a[q].ay += a[q].ty;
+      a[q].az += a[q].tz;
+      a[q].tx = a[q].ty = a[q].tz = 0.f;
     }
     __syncthreads();
   }

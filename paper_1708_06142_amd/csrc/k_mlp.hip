@@ -506,6 +506,8 @@ __global__ __launch_bounds__(WG) void k_eval_mlp(DevTree T, EwaldP E, const void
     }
     __syncthreads();
     const int mm = (int)(n - t0 < WG ? n - t0 : WG);
+    // acceleration summed per tile, then into the totals (blocked summation)
+    float tx[2] = {0.f, 0.f}, ty[2] = {0.f, 0.f}, tz[2] = {0.f, 0.f};
     for (int j = 0; j < mm; ++j) {
       const float4 r = tile[j];
       // one batch of 32 pairs at a time (a loop, not unrolled: fewer live
@@ -543,18 +545,23 @@ __global__ __launch_bounds__(WG) void k_eval_mlp(DevTree T, EwaldP E, const void
           const float yk = r.w * ph - cc[1], tk = s[1] + yk;
           cc[1] = use ? (tk - s[1]) - yk : cc[1];
           s[1] = use ? tk : s[1];
-          ax[1] += use ? r.w * A0 : 0.0f;
-          ay[1] += use ? r.w * A1 : 0.0f;
-          az[1] += use ? r.w * A2 : 0.0f;
+          tx[1] += use ? r.w * A0 : 0.0f;
+          ty[1] += use ? r.w * A1 : 0.0f;
+          tz[1] += use ? r.w * A2 : 0.0f;
         } else {
           const float yk = r.w * ph - cc[0], tk = s[0] + yk;
           cc[0] = use ? (tk - s[0]) - yk : cc[0];
           s[0] = use ? tk : s[0];
-          ax[0] += use ? r.w * A0 : 0.0f;
-          ay[0] += use ? r.w * A1 : 0.0f;
-          az[0] += use ? r.w * A2 : 0.0f;
+          tx[0] += use ? r.w * A0 : 0.0f;
+          ty[0] += use ? r.w * A1 : 0.0f;
+          tz[0] += use ? r.w * A2 : 0.0f;
         }
       }
+    }
+    for (int q = 0; q < 2; ++q) {
+      ax[q] += tx[q];
+      ay[q] += ty[q];
+      az[q] += tz[q];
     }
     __syncthreads();
   }

@@ -1,0 +1,102 @@
+"""The large AMR workload at full size: a 512^3-resolution lognormal field
+(sigma_ln 2, P(k) ~ k^-4) on a 128^3 base grid refined up to two levels
+(14-16M cells), x, y periodic and z isolated, APE a_lim = 1e-3 a_max together
+with BH at theta_pix = 0.25 for 192-direction columns (Nside 4).
+
+* 32 seeded blocks against the oracle's group walk (same MAC, a_lim and
+  Ewald table): lists identical; FP64 walk 1e-12 (Phi, a, maps, tau); FP32
+  table walk 1e-6 (Phi) and 1e-5 (a, maps).
+* The FP32 walk with the learned correction against the FP32 table walk:
+  maps and tau identical, Phi and a within 1e-4 of their maxima.
+Outputs are sliced on the device (the FP64 maps alone are 23 GB).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1708_06142_amd as ot
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+KW = dict(mac="ape", theta=0.5, theta_pix=0.25, nside=4, ewald_n=64)
+
+
+@pytest.fixture(scope="module")
+def c5():
+    g = workloads.c5_amr()
+    assert 14e6 <= g.ncells <= 16e6
+    rho = torch.from_numpy(g.rho.reshape(-1)).cuda()
+    # a_lim = 1e-3 max|a| from the library's BH pre-pass (FP64, theta = 0.5)
+    s = ot.Solver.for_grid(g, eps_lim=1e-3, **{k: v for k, v in KW.items() if k != "nside"})
+    s.build(rho)
+    n = g.ncells
+    st = s.solve(torch.empty(n, device="cuda"), torch.empty(3 * n, device="cuda"))
+    a_lim = st.a_lim_used
+    s.close()
+    return g, rho, a_lim
+
+
+def run(g, rho, fp64, sel, a_lim, ewald="table", mlp=None):
+    dt = torch.float64 if fp64 else torch.float32
+    s = ot.Solver.for_grid(g, a_lim=a_lim, ewald=ewald, **KW)
+    if mlp is not None:
+        s.mlp_set(*mlp, accept=True)
+    s.build(rho)
+    n, npx = g.ncells, 192
+    phi, acc = torch.empty(n, dtype=dt, device="cuda"), torch.empty(3 * n, dtype=dt, device="cuda")
+    npix, tau = torch.empty(n * npx, dtype=dt, device="cuda"), torch.empty(n, dtype=dt, device="cuda")
+    st = s.solve64(phi, acc, npix, tau) if fp64 else s.solve(phi, acc, npix, tau)
+    cells = torch.from_numpy((512 * sel[:, None] + np.arange(512)).ravel()).cuda()
+    out = dict(phi=phi[cells].double().cpu().numpy(),
+               acc=acc.view(3, -1)[:, cells].double().cpu().numpy(),
+               npix=npix.view(g.nb, npx, 512)[torch.from_numpy(sel).cuda()].double().cpu().numpy(),
+               tau=tau[cells].double().cpu().numpy(), st=st, solver=s,
+               pmax=float(phi.abs().max()), amax=float(acc.view(3, -1).pow(2).sum(0).sqrt().max()))
+    del phi, acc, npix, tau
+    torch.cuda.empty_cache()
+    return out
+
+
+def test_c5_sampled_parity(c5):
+    g, rho, a_lim = c5
+    sel = np.sort(np.random.default_rng(8).choice(g.nb, 32, replace=False))
+    t = oracle.Tree(g, a_lim=a_lim, ewald="table", ew_n=64,
+                    **{k: v for k, v in KW.items() if k not in ("ewald_n",)})
+    pr, ar, nr, npr, tr = t.walk_group(sel, columns=True)
+    r64 = run(g, rho, True, sel, a_lim)
+    for b in sel[:4]:
+        assert np.array_equal(np.sort(r64["solver"].export_list(b).astype(np.int64)), np.sort(t.block_list(b)))
+    pmax, amax, nmax = np.abs(pr).max(), np.sqrt((ar ** 2).sum(0)).max(), np.abs(npr).max()
+    assert np.abs(r64["phi"] - pr).max() <= 1e-12 * pmax
+    assert np.abs(r64["acc"] - ar).max() <= 1e-12 * amax
+    assert np.abs(r64["npix"] - npr).max() <= 1e-12 * nmax
+    np.testing.assert_allclose(r64["tau"], tr, rtol=1e-12, atol=1e-14)
+    r32 = run(g, rho, False, sel, a_lim)
+    assert np.abs(r32["phi"] - pr).max() <= 1e-6 * pmax
+    assert np.abs(r32["acc"] - ar).max() <= 1e-5 * amax
+    assert np.abs(r32["npix"] - npr).max() <= 1e-5 * nmax
+    st64, st32 = r64["st"], r32["st"]
+    print(f"C5: {g.nb} blocks, {g.ncells} cells, a_lim {a_lim:.4g}, {st32.n_interactions / g.ncells:.0f} "
+          f"interactions per cell; eval FP64 {st64.ms_eval:.0f} ms, FP32 {st32.ms_eval:.0f} ms")
+
+
+def test_c5_surrogate_columns(c5):
+    g, rho, a_lim = c5
+    sel = np.sort(np.random.default_rng(9).choice(g.nb, 64, replace=False))
+    tr = ot.Solver(bc=g.bc, ewald_n=64, ewald="mlp")
+    rep = tr.mlp_train()
+    assert rep["ok"], rep
+    mlp = tr.mlp_get()
+    rt = run(g, rho, False, sel, a_lim)
+    rm = run(g, rho, False, sel, a_lim, ewald="mlp", mlp=mlp)
+    assert rm["st"].ewald_used == 2
+    assert np.array_equal(rm["npix"], rt["npix"]) and np.array_equal(rm["tau"], rt["tau"])
+    dphi = np.abs(rm["phi"] - rt["phi"]).max() / rt["pmax"]
+    da = np.abs(rm["acc"] - rt["acc"]).max() / rt["amax"]
+    print(f"C5 surrogate: training {rep['ms_train'] / 1e3:.1f} s, held-out {max(rep['err_mlp']):.2e}; "
+          f"eval table {rt['st'].ms_eval:.0f} ms, surrogate {rm['st'].ms_eval:.0f} ms; "
+          f"dPhi {dphi:.2e}, da {da:.2e} (of the maxima, on 64 sampled blocks)")
+    assert dphi <= 1e-4 and da <= 1e-4

@@ -299,3 +299,92 @@ def shuffled(g: Grid, seed=11):
     perm = np.random.default_rng(seed).permutation(g.nb)
     return dataclasses.replace(g, level=g.level[perm].copy(), coord=g.coord[perm].copy(),
                                rho=g.rho[perm].copy(), meta=dict(g.meta, perm=perm))
+
+
+def _pool(a, f):
+    """Mean over f^3 cubes of a [z, y, x] array."""
+    n = a.shape[0] // f
+    return a.reshape(n, f, n, f, n, f).mean(axis=(1, 3, 5))
+
+
+def _blockmax(a):
+    """Maximum over the 8^3 cells of each block of a [z, y, x] field."""
+    n = a.shape[0] // BS
+    return a.reshape(n, BS, n, BS, n, BS).max(axis=(1, 3, 5))
+
+
+def _dilate26(m, periodic):
+    """Boolean 26-neighbourhood dilation of a [z, y, x] array; periodic per
+    axis (x, y, z order in ``periodic``), else clipped."""
+    out = m.copy()
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                s = m
+                for ax, d, per in ((0, dz, periodic[2]), (1, dy, periodic[1]), (2, dx, periodic[0])):
+                    if d == 0:
+                        continue
+                    s = np.roll(s, d, axis=ax)
+                    if not per:
+                        sl = [slice(None)] * 3
+                        sl[ax] = slice(0, 1) if d > 0 else slice(-1, None)
+                        s = s.copy()
+                        s[tuple(sl)] = False
+                out |= s
+    return out
+
+
+def c5_amr(seed=5, sigma=2.0, n_fine=512, cells=(14e6, 16e6), bc=(1, 1, 0)):
+    """Large AMR grid: unit cube, 128^3 base cells (4,096 blocks, level 5),
+    refined up to two levels on a lognormal field rho = exp(sigma delta -
+    sigma^2/2), delta a P(k) ~ k^-4 Gaussian field on the 512^3 finest grid
+    (seed 5); a coarse cell's density is the mean of its fine cells.  A block
+    is refined when its maximum cell density exceeds a threshold that is
+    bisected (in log space) until the grid holds a number of cells inside
+    ``cells``; 2:1 balance across faces, edges and corners (periodic in x, y
+    for the default mixed boundaries)."""
+    assert n_fine == 512
+    delta = gaussian_field_k4(n_fine, seed)
+    f7 = np.exp(sigma * delta - 0.5 * sigma * sigma)
+    del delta
+    f6 = _pool(f7, 2)
+    f5 = _pool(f6, 2)
+    m5, m6 = _blockmax(f5), _blockmax(f6)          # [16]^3 and [32]^3 blocks
+    periodic = tuple(bool(b) for b in bc)
+
+    def layout(t):
+        r5 = m5 > t
+        r6 = (m6 > t) & np.repeat(np.repeat(np.repeat(r5, 2, 0), 2, 1), 2, 2)
+        # 2:1 balance: every neighbour of a refined level-6 block exists at level 6
+        need = _dilate26(r6, periodic)
+        r5 = r5 | need.reshape(16, 2, 16, 2, 16, 2).any(axis=(1, 3, 5))
+        nblk = (r5.size - r5.sum()) + (8 * r5.sum() - r6.sum()) + 8 * r6.sum()
+        return r5, r6, int(nblk)
+
+    lo, hi = np.log(f7.mean()), np.log(f7.max())
+    for _ in range(40):
+        t = float(np.exp(0.5 * (lo + hi)))
+        r5, r6, nblk = layout(t)
+        if 512 * nblk > cells[1]:
+            lo = np.log(t)
+        elif 512 * nblk < cells[0]:
+            hi = np.log(t)
+        else:
+            break
+    levels, coords, rhos = [], [], []
+    for lev, mask, field in ((5, ~r5, f5), (6, None, f6), (7, None, f7)):
+        if lev == 6:
+            mask = np.repeat(np.repeat(np.repeat(r5, 2, 0), 2, 1), 2, 2) & ~r6
+        elif lev == 7:
+            mask = np.repeat(np.repeat(np.repeat(r6, 2, 0), 2, 1), 2, 2)
+        cz, cy, cx = np.nonzero(mask)
+        nb = field.shape[0] // BS
+        blocks = field.reshape(nb, BS, nb, BS, nb, BS).transpose(0, 2, 4, 1, 3, 5)  # [bz, by, bx, k, j, i]
+        rhos.append(blocks[cz, cy, cx])
+        levels.append(np.full(cz.size, lev, np.int32))
+        coords.append(np.stack([cx, cy, cz], axis=1).astype(np.int32))
+    level = np.concatenate(levels)
+    coord = np.concatenate(coords)
+    rho = np.ascontiguousarray(np.concatenate(rhos))  # [nb, k, j, i] = [nb][8][8][8], i fastest
+    return Grid((1, 1, 1), 1.0, (0.0, 0.0, 0.0), level, coord, rho, tuple(bc), name="lognormal_amr16m",
+                meta={"seed": seed, "sigma": sigma, "threshold": t})
