@@ -230,6 +230,7 @@ def main():
                                f"APE a_lim=1e-3 a_max, {npx}-pixel columns, FP32-Kahan walk",
                    "cells": ncell, "blocks": grid.nb, "a_lim": a_lim, "columns": npx},
         "phases_ms": {"build": ms_build, "lists": ms_list, "eval": ms_eval},
+        "eval_wg_per_cu": st.eval_wg_per_cu,
         "interactions": {"n_int": st.n_interactions, "per_cell": st.n_interactions / ncell,
                          "max_list": st.max_list},
         "roofline": {"bound": "alu", "kernel": "k_eval_cols<float> (isolated, columns)" if args.nside
@@ -247,7 +248,8 @@ def main():
         ms64, st64, e64, _, _ = timed_steps(s, rho, outs64, True, max(2, args.steps // 2), 1)
         a64 = st64.n_interactions * fpair / (e64 * 1e-3) / 1e12
         out["fp64_walk"] = {"value": ncell / (ms64 * 1e-3), "ms_per_step": ms64, "ms_eval": e64,
-                            "achieved_tflops": a64, "frac_fp64_peak": a64 / PEAK_FP64_VALU}
+                            "achieved_tflops": a64, "frac_fp64_peak": a64 / PEAK_FP64_VALU,
+                            "eval_wg_per_cu": st64.eval_wg_per_cu}
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(grid, rho, args.surrogate_steps, args.nside)
     if not args.no_cpu:

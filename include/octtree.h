@@ -106,7 +106,8 @@ typedef struct {
   double ms_eval;          /* per-cell evaluation, device time               */
   int32_t ewald_used;      /* ot_ewald the evaluation used (TABLE or MLP; TABLE
                               also for isolated boundaries)                   */
-  int32_t pad_;
+  int32_t eval_wg_per_cu;  /* workgroups of the column walk resident per compute
+                              unit (its occupancy); 0 without columns         */
 } ot_stats;
 
 void ot_params_default(ot_params *p);

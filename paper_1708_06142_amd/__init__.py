@@ -45,7 +45,7 @@ class Params(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("n_interactions", C.c_int64), ("max_list", C.c_int64), ("total_list", C.c_int64),
                 ("a_lim_used", C.c_double), ("ms_build", C.c_double), ("ms_list", C.c_double),
-                ("ms_eval", C.c_double), ("ewald_used", C.c_int32), ("pad_", C.c_int32)]
+                ("ms_eval", C.c_double), ("ewald_used", C.c_int32), ("eval_wg_per_cu", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}

@@ -193,6 +193,65 @@ ot::RayTableP raytable_desc(const ot_ctx *c) {
   return P;
 }
 
+// Direction-bin look-up tables of the column walk.  Each angle's bin edges
+// are mapped to a variable that increases or decreases with the angle: cos
+// theta on [-1, 1] for theta, sin psi on [0, 1] for psi (edges above pi/2 are
+// never reached), t = cos phi / (|cos phi| + sin phi) on [-1, 1] for phi in
+// [0, pi] (bins below half).  The cells are at most half as wide as the
+// closest two edges; a cell holds the bin of its centre.
+struct BinLut {
+  int m[3];  // cells: theta, psi, phi
+  bool ok;   // every table fits its share of LUT_BYTES
+};
+
+std::vector<double> lut_edges(const ot::RayTableP &RP, int which) {
+  std::vector<double> x;
+  if (which == 0)
+    for (int k = 1; k < RP.ntheta; ++k) x.push_back(std::cos(k * RP.dtheta));
+  else if (which == 1)
+    for (int k = 1; k < RP.npsi && k * RP.dpsi <= 0.5 * M_PI; ++k) x.push_back(std::sin(k * RP.dpsi));
+  else
+    for (int q = 1; q < RP.nphi / 2; ++q) {
+      const double cq = std::cos(q * RP.dphi), sq = std::sin(q * RP.dphi);
+      x.push_back(cq / (std::fabs(cq) + sq));
+    }
+  return x;
+}
+
+BinLut bin_lut_plan(const ot::RayTableP &RP) {
+  BinLut L;
+  const double range[3] = {2.0, 1.0, 2.0};
+  const int cap[3] = {ot::LUT_TH, ot::LUT_PS, ot::LUT_PH};
+  L.ok = true;
+  for (int w = 0; w < 3; ++w) {
+    const std::vector<double> x = lut_edges(RP, w);
+    double gap = HUGE_VAL;
+    for (size_t i = 1; i < x.size(); ++i) gap = std::min(gap, std::fabs(x[i] - x[i - 1]));
+    const double cells = gap == HUGE_VAL ? 2.0 : std::ceil(range[w] / (0.5 * gap));
+    L.m[w] = cells + 1 <= cap[w] ? (int)cells : 1;
+    L.ok = L.ok && cells + 1 <= cap[w];
+  }
+  return L;
+}
+
+std::vector<uint8_t> bin_luts(const ot::RayTableP &RP) {
+  const BinLut L = bin_lut_plan(RP);
+  std::vector<uint8_t> lut(ot::LUT_BYTES, 0);
+  if (!L.ok) return lut;
+  const int base[3] = {0, ot::LUT_TH, ot::LUT_TH + ot::LUT_PS};
+  for (int w = 0; w < 3; ++w) {
+    const std::vector<double> x = lut_edges(RP, w);
+    for (int j = 0; j <= L.m[w]; ++j) {
+      // cell centre; theta and phi bins grow as their variable falls
+      const double v = w == 1 ? (j + 0.5) / L.m[w] : -1.0 + (j + 0.5) * 2.0 / L.m[w];
+      int bin = 0;
+      for (double xe : x) bin += w == 1 ? v >= xe : v <= xe;
+      lut[base[w] + j] = (uint8_t)bin;
+    }
+  }
+  return lut;
+}
+
 ot_status raytable_prepare(ot_ctx *c, hipStream_t st) {
   if (c->p.nside <= 0) return fail(c, OT_ERR_STATE, "columns are off (nside = 0)");
   if (c->rt_ready) return OT_OK;
@@ -212,7 +271,8 @@ ot_status raytable_prepare(ot_ctx *c, hipStream_t st) {
     if (s == OT_OK) s = dalloc(c, c->rt_w64, (size_t)total * sizeof(double));
     if (s == OT_OK) s = dalloc(c, c->rt_rows, (size_t)RP.nentries * sizeof(uint32_t));
     if (s == OT_OK) s = dalloc(c, c->rt_ent, (size_t)total * sizeof(uint32_t));
-    if (s == OT_OK) s = dalloc(c, c->rt_rows4, (size_t)RP.nentries * 16);
+    if (s == OT_OK) s = dalloc(c, c->rt_rows8, (size_t)RP.nentries * 32);
+    if (s == OT_OK) s = dalloc(c, c->rt_lut, ot::LUT_BYTES);
     if (s == OT_OK && total >= ((int64_t)1 << 26)) s = fail(c, OT_ERR_UNSUPPORTED, "node-ray table too large");
     if (s == OT_OK) {
       // packed rows hold at most 63 pixels per entry
@@ -227,9 +287,9 @@ ot_status raytable_prepare(ot_ctx *c, hipStream_t st) {
                               P<uint16_t>(c->rt_pix), P<double>(c->rt_w64), &total, st);
       if (e == hipSuccess)
         e = ot::launch_raytable_pack(RP, P<int64_t>(c->rt_off), P<uint16_t>(c->rt_pix), P<double>(c->rt_w64),
-                                     P<uint32_t>(c->rt_rows), P<uint32_t>(c->rt_ent), P<uint4>(c->rt_rows4), st);
+                                     P<uint32_t>(c->rt_rows), P<uint32_t>(c->rt_ent), P<uint4>(c->rt_rows8), st);
       // direction-bin thresholds: c |c| with c = cos(k dtheta), sin^2(k dpsi),
-      // cos(k dphi), sin(k dphi); each list ends in a threshold its test
+      // (cos(k dphi), sin(k dphi)) pairs; each list ends in a threshold its test
       // never passes (-inf, +inf, and phi = pi exactly as cos -1, sin 0)
       std::vector<double> thr;
       for (int k = 0; k < RP.ntheta; ++k) {
@@ -238,15 +298,21 @@ ot_status raytable_prepare(ot_ctx *c, hipStream_t st) {
       }
       thr.push_back(-HUGE_VAL);
       for (int k = 0; k < RP.npsi; ++k) {
+        // psi <= pi/2: a bin edge above it is never reached
         const double sn = std::sin(k * RP.dpsi);
-        thr.push_back(sn * sn);
+        thr.push_back(k * RP.dpsi > 0.5 * M_PI ? HUGE_VAL : sn * sn);
       }
       thr.push_back(HUGE_VAL);
       const int half = RP.nphi / 2;
-      for (int k = 0; k <= half; ++k) thr.push_back(k == half ? -1.0 : std::cos(k * RP.dphi));
-      for (int k = 0; k <= half; ++k) thr.push_back(k == half ? 0.0 : std::sin(k * RP.dphi));
+      for (int k = 0; k <= half; ++k) {
+        thr.push_back(k == half ? -1.0 : std::cos(k * RP.dphi));
+        thr.push_back(k == half ? 0.0 : std::sin(k * RP.dphi));
+      }
       if (e == hipSuccess && (s = dalloc(c, c->rt_thr, thr.size() * sizeof(double))) == OT_OK)
         e = hipMemcpyAsync(c->rt_thr.ptr, thr.data(), thr.size() * sizeof(double), hipMemcpyHostToDevice, st);
+      const std::vector<uint8_t> lut = bin_luts(RP);
+      if (e == hipSuccess && s == OT_OK)
+        e = hipMemcpyAsync(c->rt_lut.ptr, lut.data(), lut.size(), hipMemcpyHostToDevice, st);
       if (e == hipSuccess) e = hipStreamSynchronize(st);
     }
   }
@@ -275,14 +341,15 @@ ot::ColP col_params(ot_ctx *c) {
   C.max_dist2 = c->p.max_dist * c->p.max_dist;
   C.ip_pi = std::min((int)std::floor(M_PI / RP.dphi), RP.nphi - 1);
   C.nthr = (RP.ntheta + 1) + (RP.npsi + 1) + 2 * (RP.nphi / 2 + 1);
-  // the angle estimates are good to ~1e-3 rad (far below 0.01 rad)
-  C.estimate = std::min(RP.dtheta, std::min(RP.dphi, RP.dpsi)) >= 0.01;
-  C.inv_dtheta = (float)(1.0 / RP.dtheta);
-  C.inv_dphi = (float)(1.0 / RP.dphi);
-  C.inv_dpsi = (float)(1.0 / RP.dpsi);
+  const BinLut L = bin_lut_plan(RP);
+  C.estimate = L.ok;
+  C.lut_th = (float)(0.5 * L.m[0]);
+  C.lut_ps = (float)L.m[1];
+  C.lut_ph = (float)(0.5 * L.m[2]);
   C.thr = P<double>(c->rt_thr);
+  C.lut = P<uint8_t>(c->rt_lut);
   C.rows = P<uint32_t>(c->rt_rows);
-  C.rows4 = P<uint4>(c->rt_rows4);
+  C.rows8 = P<uint4>(c->rt_rows8);
   C.pix = P<uint16_t>(c->rt_pix);
   C.w64 = P<double>(c->rt_w64);
   C.ent = P<uint32_t>(c->rt_ent);
@@ -460,11 +527,12 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
   HIPCHK(hipEventRecord(c->ev[1], st));
   ot::DevTree T = dev_tree(c);
   ot::EwaldP E = ewald_desc(c);
+  int wg_per_cu = 0;
   if (cols) {
     const int cpw = cols_cpw(c, fp64);
     if (!cpw) return fail(c, OT_ERR_UNSUPPORTED, "column maps do not fit in LDS");
     HIPCHK(ot::launch_eval_cols(fp64, T, E, col_params(c), P<int64_t>(c->loff), P<double4>(c->lrec),
-                                P<double>(c->lh), phi, acc, npix, tau, c->p.G, cpw, use_mlp, st));
+                                P<double>(c->lh), phi, acc, npix, tau, c->p.G, cpw, use_mlp, &wg_per_cu, st));
     // with the surrogate: the column walk left the Newtonian part; add the correction
     if (use_mlp)
       HIPCHK(ot::launch_eval_mlp(T, E, c->mlp_pk.ptr, P<int64_t>(c->loff), P<double4>(c->lrec),
@@ -496,6 +564,7 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
     stats->ms_eval = elapsed(c->ev[1], c->ev[2]);
     stats->ms_build = c->ms_build;
     stats->ewald_used = use_mlp ? OT_EWALD_MLP : OT_EWALD_TABLE;
+    stats->eval_wg_per_cu = wg_per_cu;
   }
   return OT_OK;
 }
@@ -960,7 +1029,7 @@ void ot_destroy(ot_ctx *c) {
   DevBuf *all[] = {&c->alev, &c->acoord, &c->achild0, &c->aleaf, &c->blev,   &c->bcoord,
                    &c->bamr, &c->amc,    &c->aS,      &c->btmc,  &c->cm,     &c->flag,
                    &c->lcount, &c->loff, &c->lrec,    &c->lid,   &c->lscratch, &c->tab64,
-                   &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_rows, &c->rt_ent, &c->rt_rows4,
+                   &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_rows, &c->rt_ent, &c->rt_rows8, &c->rt_lut,
                    &c->rt_thr, &c->lh, &c->mlp_P, &c->mlp_pk, &c->mlp_part, &c->mlp_lossp,
                    &c->mlp_loss};
   for (DevBuf *b : all) release(c, *b);

@@ -151,14 +151,14 @@ __global__ void k_raytable_fill(RayTableP P, const double *__restrict__ dense, c
 }
 
 // ------------------------------------------------------------- column walk
-constexpr int TILE = 64;  // list records per LDS tile (small: the maps need the LDS)
+// list records per LDS tile (small: the maps need the LDS; with 48-pixel
+// FP32 maps of 256 cells three workgroups then fit in a compute unit's LDS)
+constexpr int TILE = 60;
 
 template <typename Real>
 struct ColAcc {
   Real s, c, ax, ay, az;
 };
-
-__device__ inline int clampi(int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); }
 
 // Largest k in [0, n-1] with pred(k), pred monotone (true up to some k) and
 // pred(0) taken as true; branch-free binary search for n <= 64.
@@ -172,23 +172,13 @@ __device__ inline int last_true(int n, Pred pred) {
   return k;
 }
 
-// The same answer from an estimate k0 that is within one of it: with pred
-// monotone, pred(0) true and a sentinel threshold at n for which pred is
-// false, the answer is k0 - 1 + pred(k0) + pred(k0 + 1) for k0 clamped to
-// [0, n - 1]; the two threshold reads are independent of each other.
+// The same answer from an estimate k0 in [0, n - 1] that is within one of
+// it: with pred monotone, pred(0) true and a sentinel threshold at n for
+// which pred is false, the answer is k0 - 1 + pred(k0) + pred(k0 + 1); the
+// two threshold reads are independent of each other.
 template <typename Pred>
-__device__ inline int near_true(int n, int k0, Pred pred) {
-  k0 = clampi(k0, n - 1);
+__device__ inline int near_true(int k0, Pred pred) {
   return k0 - 1 + (int)pred(k0) + (int)pred(k0 + 1);
-}
-
-// FP32 estimate of acos(x) on [-1, 1]: the polynomial of Abramowitz & Stegun
-// 4.4.45 (absolute error below 7e-5 rad on [0, 1]), reflected for x < 0.
-__device__ inline float acos_est(float x) {
-  const float a = fminf(fabsf(x), 1.0f);
-  const float p = fmaf(fmaf(fmaf(-0.0187293f, a, 0.0742610f), a, -0.2121144f), a, 1.5707288f);
-  const float r = p * __builtin_amdgcn_sqrtf(1.0f - a);  // hardware sqrt: an estimate needs no rounding fix-up
-  return x < 0.0f ? 3.14159265f - r : r;
 }
 
 // Table row of a node at offset v = r_a - r from the target (|v|^2 = r2,
@@ -203,17 +193,19 @@ __device__ inline float acos_est(float x) {
 // with phi in (pi, 2 pi) mapped to the upper half-plane by v -> -v; on the x
 // axis (v_y = +-0) phi is that of atan2: 0, or pi (bin ip_pi) when v_x has its
 // sign bit set.  The comparisons are FP64.
-// Which k to compare: FP32 estimates of the three angles (error ~4e-3 rad at
-// worst) locate the bin to within one when every bin is wider than 0.01 rad,
-// and the comparisons at k0 and k0 + 1 then give the same bins as a full
-// binary search over the thresholds, which remains for narrower bins, for
-// offsets too small for FP32 and for nodes closer than R_eq h / 0.65.
-__device__ inline int table_row(const ColP &C, const double *thr, double vx, double vy, double vz,
-                                double r2, float f2, double rh2, float rhf) {
+// Which k to compare: three byte tables in LDS, indexed by FP32 values that
+// are monotone in the angles (cos theta, sin psi, and t = u_x / (|u_x| + u_y)
+// for phi in [0, pi]), give the bin of their cell's centre.  A cell is at
+// most half as wide as the closest two thresholds, so the bin is within one
+// of it and the comparisons at k0 and k0 + 1 then give the same bins as a
+// full binary search over the thresholds.  The searches remain for offsets
+// too small for FP32 and when the tables would not fit (C.estimate = 0).
+// rd = 1 / sqrt(max(f2, 1e-30)) for f2 = r2 in FP32.
+__device__ inline int table_row(const ColP &C, const double *thr, const uint8_t *lut, double vx, double vy,
+                                double vz, double r2, float f2, float rd, double rh2, float rhf) {
   const double *cth = thr;                       // [ntheta + 1] c |c|, sentinel -inf
   const double *sps = cth + C.ntheta + 1;        // [npsi + 1] sin^2, sentinel +inf
-  const double *cph = sps + C.npsi + 1;          // [nphi/2 + 1], the last cos(pi) = -1
-  const double *sph = cph + (C.nphi / 2 + 1);    // [nphi/2 + 1], the last sin(pi) = 0
+  const double *cs = sps + C.npsi + 1;           // [nphi/2 + 1] (cos, sin), the last (-1, 0)
   const double vzz = vz * fabs(vz);
   const int half = C.nphi / 2;
   const bool lower = vy < 0.0;
@@ -223,24 +215,22 @@ __device__ inline int table_row(const ColP &C, const double *thr, double vx, dou
   const double ux = __longlong_as_double(__double_as_longlong(vx) ^ (__double_as_longlong(vy) & (long long)0x8000000000000000ull));
   auto pth = [&](int k) { return vzz <= cth[k] * r2; };
   auto pps = [&](int k) { return rh2 >= sps[k] * r2; };
-  auto pph = [&](int q) { return cph[q] * uy - sph[q] * ux >= 0.0; };
+  auto pph = [&](int q) { return cs[2 * q] * uy - cs[2 * q + 1] * ux >= 0.0; };
   const float fx = (float)ux, fy = (float)uy;
-  const float rho2 = fx * fx + fy * fy;
-  const float rd = __builtin_amdgcn_rsqf(f2);
-  const float sn = rhf * rd;  // sin psi
-  // The estimates run on every lane (the probes' indices are clamped, so a
-  // lane outside the estimates' range still reads inside the thresholds);
-  // such lanes are then redone by the binary search under a wave-uniform
-  // branch, which keeps the common path free of divergent control flow.
-  // (on the x axis, v_y = 0, phi comes from the atan2 rule below and its
-  // estimate is not used: a node straight above or below the cell is safe)
-  const bool safe = C.estimate && f2 > 1e-30f && sn < 0.65f && (rho2 > 1e-30f || vy == 0.0);
-  int it = near_true(C.ntheta, (int)(acos_est((float)vz * rd) * C.inv_dtheta), pth);
-  // asin by its series to s^5 (error below 4e-3 rad for s < 0.65; every
-  // node accepted through the BH test at theta_pix <= 1 has s <= R_eq)
-  const float s2 = sn * sn;
-  int is = near_true(C.npsi, (int)(fmaf(sn * s2, fmaf(0.075f, s2, 0.16666667f), sn) * C.inv_dpsi), pps);
-  int k = near_true(half, (int)(acos_est(fx * __builtin_amdgcn_rsqf(rho2)) * C.inv_dphi), pph);
+  const float den = fabsf(fx) + fy;
+  const float den1 = den + 1e-30f;  // > 0, and den1 = den whenever den > 1e-30
+  // Every index is inside its table: |cos theta| <= 1 and |t| <= 1 up to
+  // rounding, sin psi is clamped to 1, and each table has one cell to spare.
+  // The estimates run on every lane; lanes outside their range are redone by
+  // the binary search under a wave-uniform branch, which keeps the common path
+  // free of divergent control flow.  (On the x axis, v_y = 0, phi comes from
+  // the atan2 rule below and its estimate is not used: a node straight above
+  // or below the cell is safe.)
+  const bool safe = C.estimate && f2 > 1e-30f && (den > 1e-30f || vy == 0.0);
+  int it = near_true(lut[(int)fmaf((float)vz * rd, C.lut_th, C.lut_th)], pth);
+  int is = near_true(lut[LUT_TH + (int)(fminf(rhf * rd, 1.0f) * C.lut_ps)], pps);
+  const float t = fx * __builtin_amdgcn_rcpf(den1);
+  int k = near_true(lut[LUT_TH + LUT_PS + (int)fmaf(t, C.lut_ph, C.lut_ph)], pph);
   if (__ballot(!safe)) {
     if (!safe) {
       it = last_true(C.ntheta, pth);
@@ -249,8 +239,9 @@ __device__ inline int table_row(const ColP &C, const double *thr, double vx, dou
     }
   }
   // atan2(+-0, x) is pi (bin ip_pi) whenever the sign bit of x is set, -0
-  // included (a node straight above the cell, v = -d with d_x = +0), else 0
-  const int ip = vy == 0.0 ? (signbit(vx) ? C.ip_pi : 0) : clampi((lower ? half : 0) + k, C.nphi - 1);
+  // included (a node straight above the cell, v = -d with d_x = +0), else 0;
+  // k <= half - 1, so the lower half-plane stays below nphi
+  const int ip = vy == 0.0 ? (signbit(vx) ? C.ip_pi : 0) : (lower ? half : 0) + k;
   return (int)__umul24(__umul24(it, C.nphi) + ip, C.npsi) + is;  // < 2^24 entries
 }
 
@@ -307,10 +298,10 @@ __device__ inline bool grav64(const EwaldP &E, double dx, double dy, double dz, 
 
 // FP32 gravity of one pair (same forms as the FP32 walk); NEWTON: only the
 // minimum-image Newtonian part (the correction is added by another kernel)
+// (inv = 1 / |d|, 0 for the target cell itself)
 template <int BC, bool NEWTON>
-__device__ inline void grav32(const EwaldP &E, float dx, float dy, float dz, float r2, float &phi, float &A0,
+__device__ inline void grav32(const EwaldP &E, float dx, float dy, float dz, float inv, float &phi, float &A0,
                               float &A1, float &A2) {
-  const float inv = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
   const float inv3 = inv * inv * inv;
   if (BC == 0 || NEWTON) {
     phi = inv;
@@ -346,17 +337,20 @@ __device__ inline void grav32(const EwaldP &E, float dx, float dy, float dz, flo
 }
 
 // One workgroup handles cpw cells (one per thread) of one leaf block.
+// LDS: the bin look-up tables and the list tile at fixed addresses (static),
+// then the thresholds and the maps (dynamic).
 template <typename Real, int BC, bool NEWTON>
 __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, const int64_t *__restrict__ off,
                                                    const double4 *__restrict__ rec, const double *__restrict__ lh,
                                                    Real *__restrict__ phi, Real *__restrict__ acc,
                                                    Real *__restrict__ npix, Real *__restrict__ tau, double negG,
                                                    int cpw, int lcpw) {
+  __shared__ uint8_t lut[LUT_BYTES];
+  __shared__ double4 tile[TILE];
+  __shared__ double tileh[TILE];  // (R_eq h)^2
+  __shared__ float2 tilef[TILE];  // R_eq h, m (FP32)
   extern __shared__ __align__(16) unsigned char smem[];
-  double4 *tile = reinterpret_cast<double4 *>(smem);
-  double *tileh = reinterpret_cast<double *>(smem + TILE * sizeof(double4));  // (R_eq h)^2
-  float2 *tilef = reinterpret_cast<float2 *>(tileh + TILE);                   // R_eq h, m (FP32)
-  double *thr = reinterpret_cast<double *>(tilef + TILE);
+  double *thr = reinterpret_cast<double *>(smem);
   Real *map = reinterpret_cast<Real *>(thr + C.nthr);
   const int nchunk = 512 / cpw;
   const int64_t b = blockIdx.x / nchunk;
@@ -368,9 +362,13 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
   const double cx = centre_coord(T.org[0], 8 * (int64_t)T.bcoord[3 * b] + (ci & 7), h);
   const double cy = centre_coord(T.org[1], 8 * (int64_t)T.bcoord[3 * b + 1] + ((ci >> 3) & 7), h);
   const double cz = centre_coord(T.org[2], 8 * (int64_t)T.bcoord[3 * b + 2] + (ci >> 6), h);
-  const float omega32 = (float)C.omega;
+  for (int q = tid; q < LUT_BYTES; q += cpw) lut[q] = C.lut[q];
   for (int q = tid; q < C.nthr; q += cpw) thr[q] = C.thr[q];
   for (int p = 0; p < C.npix; ++p) map[p * cpw + tid] = (Real)0;
+  // byte address of this cell's entry of pixel 0; pixel p is (p << lmap) on
+  char *const mcell = reinterpret_cast<char *>(map + tid);
+  const int lmap = lcpw + (sizeof(Real) == 8 ? 3 : 2);
+  const float inv_omega = (float)(1.0 / C.omega);
   // potential: FP64 sum (FP64 walk) or Kahan-compensated FP32 (FP32 walk)
   Real s = 0, cmp = 0, ax = 0, ay = 0, az = 0;
   const int64_t start = off[b], n = off[b + 1] - start;
@@ -397,12 +395,13 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
       const bool valid = r2 != 0.0;  // the target cell itself contributes nothing
       const bool col = valid && r2 <= C.max_dist2;
       const float r2f = (float)r2;
+      const float rd = __builtin_amdgcn_rsqf(fmaxf(r2f, 1e-30f));
       const float2 nf = tilef[j];
-      const int e = col ? table_row(C, thr, -dx, -dy, -dz, r2, r2f, tileh[j], nf.x) : 0;
-      const uint4 row = C.rows4[e];
-      const int o0 = (int)(row.x >> 6), cnt = col ? (int)(row.x & 63) : 0;
+      const int e = col ? table_row(C, thr, lut, -dx, -dy, -dz, r2, r2f, rd, tileh[j], nf.x) : 0;
       if (sizeof(Real) == 8) {
         if (!valid) continue;
+        const uint32_t hd = C.rows[e];
+        const int o0 = (int)(hd >> 6), cnt = col ? (int)(hd & 63) : 0;
         double ph, A0, A1, A2;
         grav64<BC>(E, dx, dy, dz, r2, ph, A0, A1, A2);
         s += (Real)(r.w * ph);
@@ -413,8 +412,9 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         for (int o = o0; o < o0 + cnt; ++o) map[((int)C.pix[o] << lcpw) + tid] += (Real)(C.w64[o] * base);
       } else {
         // FP32 gravity from the FP64 offset (already the minimum image)
+        const float inv = valid ? rd : 0.0f;
         float ph, A0, A1, A2;
-        grav32<BC, NEWTON>(E, (float)dx, (float)dy, (float)dz, r2f, ph, A0, A1, A2);
+        grav32<BC, NEWTON>(E, (float)dx, (float)dy, (float)dz, inv, ph, A0, A1, A2);
         const float m32 = valid ? nf.y : 0.0f;
         const float y = m32 * ph - (float)cmp;
         const float tt = (float)s + y;
@@ -423,16 +423,31 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         tx += (Real)(m32 * A0);
         ty += (Real)(m32 * A1);
         tz += (Real)(m32 * A2);
-        const float base = col ? m32 * __builtin_amdgcn_rcpf(omega32 * r2f) * (1.0f / 16777216.0f) : 0.0f;
-        // the first three entries come with the row (zero weight past cnt);
-        // plain read-modify-write: the column is the thread's own, and LDS
-        // atomic adds measured 2.5x slower here
-        map[((row.y >> 24) << lcpw) + tid] += (Real)((float)(row.y & 0xffffffu) * base);
-        map[((row.z >> 24) << lcpw) + tid] += cnt > 1 ? (Real)((float)(row.z & 0xffffffu) * base) : (Real)0;
-        map[((row.w >> 24) << lcpw) + tid] += cnt > 2 ? (Real)((float)(row.w & 0xffffffu) * base) : (Real)0;
-        for (int o = o0 + 3; o < o0 + cnt; ++o) {
-          const uint32_t v = C.ent[o];
-          map[((v >> 24) << lcpw) + tid] += (Real)((float)(v & 0xffffffu) * base);
+        // N_p += w M / (Omega d^2) over the row's pixels: four of them come
+        // with the row (distinct pixels, weight 0 past the count), so the four
+        // read-modify-writes are independent; the column is the thread's own
+        // (plain read-modify-write: LDS atomic adds measured 2.5x slower)
+        const float base = col ? m32 * inv_omega * (rd * rd) : 0.0f;
+        const uint4 pq = C.rows8[2 * e], wq = C.rows8[2 * e + 1];
+        // bit 31 of the first pixel (more than four) is shifted out here
+        float *const q0 = reinterpret_cast<float *>(mcell + (pq.x << lmap));
+        float *const q1 = reinterpret_cast<float *>(mcell + (pq.y << lmap));
+        float *const q2 = reinterpret_cast<float *>(mcell + (pq.z << lmap));
+        float *const q3 = reinterpret_cast<float *>(mcell + (pq.w << lmap));
+        const float v0 = *q0, v1 = *q1, v2 = *q2, v3 = *q3;
+        *q0 = fmaf(__uint_as_float(wq.x), base, v0);
+        *q1 = fmaf(__uint_as_float(wq.y), base, v1);
+        *q2 = fmaf(__uint_as_float(wq.z), base, v2);
+        *q3 = fmaf(__uint_as_float(wq.w), base, v3);
+        if ((int)pq.x < 0 && col) {
+          const uint32_t hd = C.rows[e];
+          const int o0 = (int)(hd >> 6), cnt = (int)(hd & 63);
+          const float base24 = base * (1.0f / 16777216.0f);
+          for (int o = o0 + 4; o < o0 + cnt; ++o) {
+            const uint32_t v = C.ent[o];
+            float *const qv = reinterpret_cast<float *>(mcell + ((v >> 24) << lmap));
+            *qv += (float)(v & 0xffffffu) * base24;
+          }
         }
       }
     }
@@ -454,25 +469,45 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
   tau[o] = (Real)(-log(se / (double)C.npix));
 }
 
-// packed rows for the walk: row = offset << 6 | count; entry = pixel << 24 |
-// round(w 2^24) (w <= 1, clamped to 2^24 - 1)
+// packed rows for the walk: head = offset << 6 | count; entry = pixel << 24 |
+// round(w 2^24) (w <= 1, clamped to 2^24 - 1); rows8 = the first four pixels
+// and their FP32 weights, padded with the lowest pixels the row does not use
+// (weight 0), bit 31 of the first pixel set when the row has more than four
 __global__ void k_raytable_pack(RayTableP P, const int64_t *__restrict__ off, const uint16_t *__restrict__ pix,
                                 const double *__restrict__ w, uint32_t *__restrict__ rows,
-                                uint32_t *__restrict__ ent, uint4 *__restrict__ rows4) {
+                                uint32_t *__restrict__ ent, uint4 *__restrict__ rows8) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= P.nentries) return;
   const int64_t o0 = off[e], o1 = off[e + 1];
   const uint32_t head = (uint32_t)(o0 << 6) | (uint32_t)(o1 - o0);
   rows[e] = head;
-  uint32_t first[3] = {0u, 0u, 0u};
+  uint32_t p4[4], w4[4];
+  int nf = 0;
   for (int64_t o = o0; o < o1; ++o) {
     double q = rint(w[o] * 16777216.0);
     q = q > 16777215.0 ? 16777215.0 : q;
-    const uint32_t v = ((uint32_t)pix[o] << 24) | (uint32_t)q;
-    ent[o] = v;
-    if (o - o0 < 3) first[o - o0] = v;
+    ent[o] = ((uint32_t)pix[o] << 24) | (uint32_t)q;
+    if (nf < 4) {
+      p4[nf] = pix[o];
+      w4[nf] = __float_as_uint((float)w[o]);
+      ++nf;
+    }
   }
-  rows4[e] = make_uint4(head, first[0], first[1], first[2]);
+  // padding (rows of fewer than four): the lowest pixels not in the row
+  uint32_t cand = 0;
+  while (nf < 4) {
+    bool used = false;
+    for (int i = 0; i < nf; ++i) used |= p4[i] == cand;
+    if (!used) {
+      p4[nf] = cand;
+      w4[nf] = 0u;
+      ++nf;
+    }
+    ++cand;
+  }
+  if (o1 - o0 > 4) p4[0] |= 0x80000000u;
+  rows8[2 * e] = make_uint4(p4[0], p4[1], p4[2], p4[3]);
+  rows8[2 * e + 1] = make_uint4(w4[0], w4[1], w4[2], w4[3]);
 }
 
 }  // namespace
@@ -494,33 +529,37 @@ hipError_t launch_raytable(const RayTableP &P, double *dense, int32_t *cnt, int6
   return hipGetLastError();
 }
 
+constexpr size_t COLS_STATIC_LDS = LUT_BYTES + TILE * (sizeof(double4) + sizeof(double) + sizeof(float2));
+
 size_t cols_smem_bytes(int npix, int cpw, bool fp64, int nthr) {
-  return TILE * (sizeof(double4) + sizeof(double) + sizeof(float2)) + (size_t)nthr * sizeof(double) +
-         (size_t)npix * cpw * (fp64 ? 8 : 4);
+  return COLS_STATIC_LDS + (size_t)nthr * sizeof(double) + (size_t)npix * cpw * (fp64 ? 8 : 4);
 }
 
 hipError_t launch_raytable_pack(const RayTableP &P, const int64_t *off, const uint16_t *pix, const double *w,
-                                uint32_t *rows, uint32_t *ent, uint4 *rows4, hipStream_t st) {
+                                uint32_t *rows, uint32_t *ent, uint4 *rows8, hipStream_t st) {
   hipLaunchKernelGGL(k_raytable_pack, dim3((unsigned)((P.nentries + 255) / 256)), dim3(256), 0, st, P, off,
-                     pix, w, rows, ent, rows4);
+                     pix, w, rows, ent, rows8);
   return hipGetLastError();
 }
 
 hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const ColP &C, const int64_t *off,
                             const double4 *rec, const double *lh, void *phi, void *acc, void *npix, void *tau,
-                            double G, int cpw, bool newton_only, hipStream_t st) {
-  const size_t sm = cols_smem_bytes(C.npix, cpw, fp64, C.nthr);
+                            double G, int cpw, bool newton_only, int *wg_per_cu, hipStream_t st) {
+  const size_t sm = cols_smem_bytes(C.npix, cpw, fp64, C.nthr) - COLS_STATIC_LDS;  // dynamic part
   int lcpw = 0;
   while ((1 << lcpw) < cpw) ++lcpw;
   if ((1 << lcpw) != cpw) return hipErrorInvalidValue;  // cells per workgroup: a power of two
   dim3 grid((unsigned)(T.nb * (512 / cpw))), blk(cpw);
 #define OT_LAUNCH(R, B, N)                                                                                    \
   do {                                                                                                        \
-    if (sm > 65536) {                                                                                         \
+    if (sm + COLS_STATIC_LDS > 65536) {                                                                       \
       hipError_t ea = hipFuncSetAttribute((const void *)k_eval_cols<R, B, N>,                                \
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);              \
       if (ea != hipSuccess) return ea;                                                                        \
     }                                                                                                         \
+    if (wg_per_cu &&                                                                                          \
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, k_eval_cols<R, B, N>, cpw, sm) != hipSuccess)  \
+      *wg_per_cu = 0;                                                                                         \
     hipLaunchKernelGGL((k_eval_cols<R, B, N>), grid, blk, sm, st, T, E, C, off, rec, lh, (R *)phi, (R *)acc, \
                        (R *)npix, (R *)tau, -G, cpw, lcpw);                                                  \
   } while (0)

@@ -52,27 +52,36 @@ struct ColP {
   double max_dist2; // columns only from nodes closer than max_dist (squared)
   int ip_pi;        // phi bin of phi = pi (offsets on the negative x axis)
   int nthr;         // threshold count: ntheta + 1 + npsi + 1 + 2 (nphi/2 + 1)
-  int estimate;     // bins from angle estimates checked at two thresholds
-                    // (every bin wider than 0.01 rad), else binary searches
-  float inv_dtheta, inv_dphi, inv_dpsi;
+  int estimate;     // bins from look-up estimates checked at two thresholds,
+                    // else binary searches (look-up tables too large)
+  float lut_th, lut_ps, lut_ph;  // look-up scales: cell of cos theta, sin psi, pseudo-angle
   const double *thr;       // c|c| (c = cos(k dtheta)), sin^2(k dpsi), cos(k dphi), sin(k dphi)
+  const uint8_t *lut;      // [LUT_BYTES] estimated bins (theta, psi, phi tables)
   const uint32_t *rows;    // [nentries] offset << 6 | count
-  const uint4 *rows4;      // [nentries] {offset << 6 | count, first three entries}
+  const uint4 *rows8;      // [nentries][2]: four pixels (bit 31 of the first: more
+                           // than four), their four FP32 weights (zero past count)
   const uint16_t *pix;     // [npairs] FP64 walk
   const double *w64;       // [npairs]
   const uint32_t *ent;     // [npairs] FP32 walk: pixel << 24 | unorm24 weight
 };
 
+// Direction-bin look-up tables of the column walk (one byte per cell, in this
+// order): cos theta over [-1, 1], sin psi over [0, 1], the pseudo-angle
+// t = x / (|x| + y) of the upper half-plane over [-1, 1]; each holds its
+// count of cells plus one.
+constexpr int LUT_TH = 512, LUT_PS = 96, LUT_PH = 80, LUT_BYTES = LUT_TH + LUT_PS + LUT_PH;
+
 hipError_t launch_raytable(const RayTableP &P, double *dense, int32_t *cnt, int64_t *off, uint16_t *pix,
                            double *w64, int64_t *total, hipStream_t st);
 hipError_t launch_raytable_pack(const RayTableP &P, const int64_t *off, const uint16_t *pix, const double *w,
-                                uint32_t *rows, uint32_t *ent, uint4 *rows4, hipStream_t st);
+                                uint32_t *rows, uint32_t *ent, uint4 *rows8, hipStream_t st);
 size_t cols_smem_bytes(int npix, int cpw, bool fp64, int nthr);
 // newton_only (FP32, 3P / 2P1I): the minimum-image Newtonian part only, for
 // every pair; launch_eval_mlp with add = true then adds the correction
+// wg_per_cu (may be null): workgroups of the launched kernel resident per CU
 hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const ColP &C, const int64_t *off,
                             const double4 *rec, const double *lh, void *phi, void *acc, void *npix, void *tau,
-                            double G, int cpw, bool newton_only, hipStream_t st);
+                            double G, int cpw, bool newton_only, int *wg_per_cu, hipStream_t st);
 
 hipError_t launch_build(const DevTree &T, const double *rho, int *bad,
                         const std::vector<int64_t> &level_begin, int lmax, hipStream_t st);
