@@ -356,16 +356,6 @@ ot::ColP col_params(ot_ctx *c) {
   return C;
 }
 
-// cells per workgroup of the column walk: the per-cell maps must fit in LDS
-int cols_cpw(const ot_ctx *c, bool fp64) {
-  const ot::RayTableP RP = raytable_desc(c);
-  const int nthr = (RP.ntheta + 1) + (RP.npsi + 1) + 2 * (RP.nphi / 2 + 1);
-  for (int cpw : {256, 128, 64})
-    if (ot::cols_smem_bytes(npix_of(c), cpw, fp64, nthr) <= 65536) return cpw;
-  if (ot::cols_smem_bytes(npix_of(c), 64, fp64, nthr) <= 160 * 1024) return 64;
-  return 0;
-}
-
 // Interaction lists for the given MAC: count, scan, fill.
 ot_status build_lists(ot_ctx *c, const ot::MacP &mp, bool sizes, hipStream_t st) {
   const ot::Topology &t = c->topo;
@@ -529,10 +519,11 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
   ot::EwaldP E = ewald_desc(c);
   int wg_per_cu = 0;
   if (cols) {
-    const int cpw = cols_cpw(c, fp64);
-    if (!cpw) return fail(c, OT_ERR_UNSUPPORTED, "column maps do not fit in LDS");
-    HIPCHK(ot::launch_eval_cols(fp64, T, E, col_params(c), P<int64_t>(c->loff), P<double4>(c->lrec),
-                                P<double>(c->lh), phi, acc, npix, tau, c->p.G, cpw, use_mlp, &wg_per_cu, st));
+    // maps in LDS when 128 or more cells' maps fit there, else in npix
+    const ot::ColP C = col_params(c);
+    HIPCHK(ot::launch_eval_cols(fp64, T, E, C, P<int64_t>(c->loff), P<double4>(c->lrec), P<double>(c->lh), phi,
+                                acc, npix, tau, c->p.G, ot::cols_lds_cpw(C.npix, fp64, C.nthr), use_mlp,
+                                &wg_per_cu, st));
     // with the surrogate: the column walk left the Newtonian part; add the correction
     if (use_mlp)
       HIPCHK(ot::launch_eval_mlp(T, E, c->mlp_pk.ptr, P<int64_t>(c->loff), P<double4>(c->lrec),

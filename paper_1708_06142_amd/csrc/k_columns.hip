@@ -338,8 +338,11 @@ __device__ inline void grav32(const EwaldP &E, float dx, float dy, float dz, flo
 
 // One workgroup handles cpw cells (one per thread) of one leaf block.
 // LDS: the bin look-up tables and the list tile at fixed addresses (static),
-// then the thresholds and the maps (dynamic).
-template <typename Real, int BC, bool NEWTON>
+// then the thresholds and (GMAP = false) the maps (dynamic).  With GMAP the
+// maps are accumulated in place in npix (each thread owns its cell's column,
+// a wave's 64 cells are adjacent): for maps too large for LDS at a useful
+// occupancy (192 pixels take 768 bytes per cell in FP32).
+template <typename Real, int BC, bool NEWTON, bool GMAP>
 __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, const int64_t *__restrict__ off,
                                                    const double4 *__restrict__ rec, const double *__restrict__ lh,
                                                    Real *__restrict__ phi, Real *__restrict__ acc,
@@ -364,10 +367,11 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
   const double cz = centre_coord(T.org[2], 8 * (int64_t)T.bcoord[3 * b + 2] + (ci >> 6), h);
   for (int q = tid; q < LUT_BYTES; q += cpw) lut[q] = C.lut[q];
   for (int q = tid; q < C.nthr; q += cpw) thr[q] = C.thr[q];
-  for (int p = 0; p < C.npix; ++p) map[p * cpw + tid] = (Real)0;
   // byte address of this cell's entry of pixel 0; pixel p is (p << lmap) on
-  char *const mcell = reinterpret_cast<char *>(map + tid);
-  const int lmap = lcpw + (sizeof(Real) == 8 ? 3 : 2);
+  char *const mcell = GMAP ? reinterpret_cast<char *>(npix + b * C.npix * 512 + ci)
+                           : reinterpret_cast<char *>(map + tid);
+  const int lmap = (GMAP ? 9 : lcpw) + (sizeof(Real) == 8 ? 3 : 2);
+  for (int p = 0; p < C.npix; ++p) *reinterpret_cast<Real *>(mcell + (p << lmap)) = (Real)0;
   const float inv_omega = (float)(1.0 / C.omega);
   // potential: FP64 sum (FP64 walk) or Kahan-compensated FP32 (FP32 walk)
   Real s = 0, cmp = 0, ax = 0, ay = 0, az = 0;
@@ -409,7 +413,8 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         ty += (Real)(r.w * A1);
         tz += (Real)(r.w * A2);
         const double base = r.w / (C.omega * r2);
-        for (int o = o0; o < o0 + cnt; ++o) map[((int)C.pix[o] << lcpw) + tid] += (Real)(C.w64[o] * base);
+        for (int o = o0; o < o0 + cnt; ++o)
+          *reinterpret_cast<Real *>(mcell + ((uint32_t)C.pix[o] << lmap)) += (Real)(C.w64[o] * base);
       } else {
         // FP32 gravity from the FP64 offset (already the minimum image)
         const float inv = valid ? rd : 0.0f;
@@ -434,11 +439,25 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         float *const q1 = reinterpret_cast<float *>(mcell + (pq.y << lmap));
         float *const q2 = reinterpret_cast<float *>(mcell + (pq.z << lmap));
         float *const q3 = reinterpret_cast<float *>(mcell + (pq.w << lmap));
-        const float v0 = *q0, v1 = *q1, v2 = *q2, v3 = *q3;
-        *q0 = fmaf(__uint_as_float(wq.x), base, v0);
-        *q1 = fmaf(__uint_as_float(wq.y), base, v1);
-        *q2 = fmaf(__uint_as_float(wq.z), base, v2);
-        *q3 = fmaf(__uint_as_float(wq.w), base, v3);
+        if (GMAP) {
+          // in memory the padding slots would cost traffic: they are skipped
+          const bool u1 = wq.y != 0u, u2 = wq.z != 0u, u3 = wq.w != 0u;
+          float v1 = 0.0f, v2 = 0.0f, v3 = 0.0f;
+          const float v0 = *q0;
+          if (u1) v1 = *q1;
+          if (u2) v2 = *q2;
+          if (u3) v3 = *q3;
+          *q0 = fmaf(__uint_as_float(wq.x), base, v0);
+          if (u1) *q1 = fmaf(__uint_as_float(wq.y), base, v1);
+          if (u2) *q2 = fmaf(__uint_as_float(wq.z), base, v2);
+          if (u3) *q3 = fmaf(__uint_as_float(wq.w), base, v3);
+        } else {
+          const float v0 = *q0, v1 = *q1, v2 = *q2, v3 = *q3;
+          *q0 = fmaf(__uint_as_float(wq.x), base, v0);
+          *q1 = fmaf(__uint_as_float(wq.y), base, v1);
+          *q2 = fmaf(__uint_as_float(wq.z), base, v2);
+          *q3 = fmaf(__uint_as_float(wq.w), base, v3);
+        }
         if ((int)pq.x < 0 && col) {
           const uint32_t hd = C.rows[e];
           const int o0 = (int)(hd >> 6), cnt = (int)(hd & 63);
@@ -462,8 +481,8 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
   acc[2 * ncell + o] = (Real)(negG * (double)az);
   double se = 0.0;
   for (int p = 0; p < C.npix; ++p) {
-    const Real v = map[p * cpw + tid];
-    npix[(b * C.npix + p) * 512 + ci] = v;
+    const Real v = *reinterpret_cast<const Real *>(mcell + (p << lmap));
+    if (!GMAP) npix[(b * C.npix + p) * 512 + ci] = v;
     se += exp(-C.kappa * (double)v);
   }
   tau[o] = (Real)(-log(se / (double)C.npix));
@@ -535,6 +554,12 @@ size_t cols_smem_bytes(int npix, int cpw, bool fp64, int nthr) {
   return COLS_STATIC_LDS + (size_t)nthr * sizeof(double) + (size_t)npix * cpw * (fp64 ? 8 : 4);
 }
 
+int cols_lds_cpw(int npix, bool fp64, int nthr) {
+  for (int cpw : {256, 128})
+    if (cols_smem_bytes(npix, cpw, fp64, nthr) <= 65536) return cpw;
+  return 0;
+}
+
 hipError_t launch_raytable_pack(const RayTableP &P, const int64_t *off, const uint16_t *pix, const double *w,
                                 uint32_t *rows, uint32_t *ent, uint4 *rows8, hipStream_t st) {
   hipLaunchKernelGGL(k_raytable_pack, dim3((unsigned)((P.nentries + 255) / 256)), dim3(256), 0, st, P, off,
@@ -545,23 +570,34 @@ hipError_t launch_raytable_pack(const RayTableP &P, const int64_t *off, const ui
 hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const ColP &C, const int64_t *off,
                             const double4 *rec, const double *lh, void *phi, void *acc, void *npix, void *tau,
                             double G, int cpw, bool newton_only, int *wg_per_cu, hipStream_t st) {
-  const size_t sm = cols_smem_bytes(C.npix, cpw, fp64, C.nthr) - COLS_STATIC_LDS;  // dynamic part
+  const bool gmap = cpw == 0;
+  if (gmap) cpw = 256;
+  // dynamic LDS: the thresholds, and the maps unless they are in npix
+  const size_t sm = gmap ? (size_t)C.nthr * sizeof(double)
+                         : cols_smem_bytes(C.npix, cpw, fp64, C.nthr) - COLS_STATIC_LDS;
   int lcpw = 0;
   while ((1 << lcpw) < cpw) ++lcpw;
   if ((1 << lcpw) != cpw) return hipErrorInvalidValue;  // cells per workgroup: a power of two
   dim3 grid((unsigned)(T.nb * (512 / cpw))), blk(cpw);
-#define OT_LAUNCH(R, B, N)                                                                                    \
+#define OT_LAUNCH2(R, B, N, M)                                                                                \
   do {                                                                                                        \
     if (sm + COLS_STATIC_LDS > 65536) {                                                                       \
-      hipError_t ea = hipFuncSetAttribute((const void *)k_eval_cols<R, B, N>,                                \
+      hipError_t ea = hipFuncSetAttribute((const void *)k_eval_cols<R, B, N, M>,                             \
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);              \
       if (ea != hipSuccess) return ea;                                                                        \
     }                                                                                                         \
-    if (wg_per_cu &&                                                                                          \
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, k_eval_cols<R, B, N>, cpw, sm) != hipSuccess)  \
+    if (wg_per_cu && hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, k_eval_cols<R, B, N, M>, cpw,   \
+                                                                  sm) != hipSuccess)                          \
       *wg_per_cu = 0;                                                                                         \
-    hipLaunchKernelGGL((k_eval_cols<R, B, N>), grid, blk, sm, st, T, E, C, off, rec, lh, (R *)phi, (R *)acc, \
-                       (R *)npix, (R *)tau, -G, cpw, lcpw);                                                  \
+    hipLaunchKernelGGL((k_eval_cols<R, B, N, M>), grid, blk, sm, st, T, E, C, off, rec, lh, (R *)phi,        \
+                       (R *)acc, (R *)npix, (R *)tau, -G, cpw, lcpw);                                        \
+  } while (0)
+#define OT_LAUNCH(R, B, N)          \
+  do {                              \
+    if (gmap)                       \
+      OT_LAUNCH2(R, B, N, true);    \
+    else                            \
+      OT_LAUNCH2(R, B, N, false);   \
   } while (0)
   if (fp64) {
     if (newton_only) return hipErrorInvalidValue;
@@ -578,6 +614,7 @@ hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const 
     else OT_LAUNCH(float, 2, false);
   }
 #undef OT_LAUNCH
+#undef OT_LAUNCH2
   return hipGetLastError();
 }
 

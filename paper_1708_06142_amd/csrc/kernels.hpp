@@ -76,8 +76,12 @@ hipError_t launch_raytable(const RayTableP &P, double *dense, int32_t *cnt, int6
 hipError_t launch_raytable_pack(const RayTableP &P, const int64_t *off, const uint16_t *pix, const double *w,
                                 uint32_t *rows, uint32_t *ent, uint4 *rows8, hipStream_t st);
 size_t cols_smem_bytes(int npix, int cpw, bool fp64, int nthr);
+// cells per workgroup with the maps in LDS: 256 or 128 when their LDS fits in
+// 64 KB, else 0 (the maps are then accumulated in npix, 256 cells per group)
+int cols_lds_cpw(int npix, bool fp64, int nthr);
 // newton_only (FP32, 3P / 2P1I): the minimum-image Newtonian part only, for
 // every pair; launch_eval_mlp with add = true then adds the correction
+// cpw: cols_lds_cpw (0: maps in npix);
 // wg_per_cu (may be null): workgroups of the launched kernel resident per CU
 hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const ColP &C, const int64_t *off,
                             const double4 *rec, const double *lh, void *phi, void *acc, void *npix, void *tau,
