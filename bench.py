@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the learned-Ewald leg (same field, 3P boundaries)")
     ap.add_argument("--surrogate-steps", type=int, default=2)
+    ap.add_argument("--no-c5", action="store_true",
+                    help="skip the large AMR leg (15.2M cells, 2P1I, 192-pixel columns)")
     return ap.parse_args()
 
 
@@ -159,6 +161,76 @@ def surrogate_leg(grid, rho, steps, nside=0):
     return out
 
 
+def c5_leg():
+    """Large AMR configuration: 512^3-resolution lognormal field (sigma_ln 2,
+    P(k) ~ k^-4, seed 5) on a 128^3 base grid refined up to two levels (15.2M
+    cells), x, y periodic and z isolated, APE a_lim = 1e-3 a_max with BH at
+    theta_pix = 0.25, 192-pixel columns.  The FP32 walk with the learned
+    correction beside the FP32 and FP64 table walks at the same MAC; one
+    untimed step, then one timed step each (a step is several seconds)."""
+    import torch
+    import paper_1708_06142_amd as ot
+    import workloads
+    t0 = time.perf_counter()
+    g = workloads.c5_amr()
+    gen_s = time.perf_counter() - t0
+    n = g.ncells
+    rho = torch.from_numpy(g.rho.reshape(-1)).cuda()
+    kw = dict(mac="ape", theta=0.5, theta_pix=0.25, ewald_n=64)
+    s = ot.Solver.for_grid(g, eps_lim=1e-3, **kw)
+    s.build(rho)
+    a_lim = s.solve(torch.empty(n, device="cuda"), torch.empty(3 * n, device="cuda")).a_lim_used
+    s.close()
+    tr = ot.Solver(bc=g.bc, ewald_n=64, ewald="mlp")
+    t0 = time.perf_counter()
+    rep = tr.mlp_train()
+    train_s = time.perf_counter() - t0
+    params, norm = tr.mlp_get()
+    tr.close()
+    res, out = {}, {"workload": f"AMR lognormal 512^3 effective (sigma_ln 2, seed 5), {g.nb} blocks, {n} cells, "
+                                f"2P1I, APE a_lim=1e-3 a_max ({a_lim:.4g}) + BH theta_pix 0.25, 192-pixel columns",
+                    "generate_s": gen_s, "training": {"seconds": train_s, "err_mlp": rep["err_mlp"],
+                                                     "ok": rep["ok"]}}
+    for label, mode, fp64 in (("mlp_fp32_cols", "mlp", False), ("table_fp32_cols", "table", False),
+                              ("table_fp64_cols", "table", True)):
+        s = ot.Solver.for_grid(g, a_lim=a_lim, ewald=mode, nside=4, **kw)
+        if mode == "mlp":
+            s.mlp_set(params, norm, accept=bool(rep["ok"]))
+        dt = torch.float64 if fp64 else torch.float32
+        outs = (torch.empty(n, dtype=dt, device="cuda"), torch.empty(3 * n, dtype=dt, device="cuda"),
+                torch.empty(n * 192, dtype=dt, device="cuda"), torch.empty(n, dtype=dt, device="cuda"))
+        ms, st, ms_eval, _, _ = timed_steps(s, rho, outs, fp64, 1, 1)
+        s.close()
+        res[label] = outs
+        e = {"value": n / (ms * 1e-3), "unit": "cells/s", "ms_per_step": ms, "ms_eval": ms_eval,
+             "ewald_used": ["table", "exact", "mlp"][st.ewald_used], "n_int": st.n_interactions,
+             "eval_wg_per_cu": st.eval_wg_per_cu}
+        if mode == "mlp":
+            ach = st.n_interactions * FLOP_PAIR_MLP / (ms_eval * 1e-3) / 1e12
+            e["roofline"] = {"bound": "mfma", "kernel": "k_eval_cols<float, newton> + k_eval_mlp<2P1I, add>",
+                             "achieved": ach, "peak": PEAK_FP16_MFMA, "unit": "TFLOP/s",
+                             "frac": ach / PEAK_FP16_MFMA, "flop_per_pair": FLOP_PAIR_MLP,
+                             "note": "matrix work over the time of both kernels"}
+        else:
+            fl = st.n_interactions * FLOP_PAIR_COLS / (ms_eval * 1e-3) / 1e12
+            peak = PEAK_FP64_VALU if fp64 else PEAK_FP32_VALU
+            e["roofline"] = {"bound": "alu", "kernel": f"k_eval_cols<{'double' if fp64 else 'float'}>",
+                             "achieved": fl, "peak": peak, "unit": "TFLOP/s", "frac": fl / peak,
+                             "flop_per_pair": FLOP_PAIR_COLS}
+        out[label] = e
+        torch.cuda.synchronize()
+    ref = res["table_fp64_cols"]
+    names = ("phi", "acc", "npix", "tau")
+    for label in ("mlp_fp32_cols", "table_fp32_cols"):
+        for nm, a, r in zip(names, res[label], ref):
+            out[label][f"d{nm}_maxnorm_vs_fp64_table"] = float((a.double() - r).abs().max() / r.abs().max()) \
+                if nm != "npix" else float(max((a[i:i + (1 << 28)].double() - r[i:i + (1 << 28)]).abs().max()
+                                               for i in range(0, r.numel(), 1 << 28)) / r.abs().max())
+    del res, ref
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(grid, a_lim, nblk, nside):
     """The FP64 oracle's group walk on a seeded sample of blocks, host cores."""
     import oracle
@@ -252,6 +324,8 @@ def main():
                             "eval_wg_per_cu": st64.eval_wg_per_cu}
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(grid, rho, args.surrogate_steps, args.nside)
+    if not args.no_c5:
+        out["c5"] = c5_leg()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(grid, a_lim, args.cpu_blocks, args.nside)
     print(json.dumps(out))
