@@ -198,7 +198,12 @@ ot::RayTableP raytable_desc(const ot_ctx *c) {
 // theta on [-1, 1] for theta, sin psi on [0, 1] for psi (edges above pi/2 are
 // never reached), t = cos phi / (|cos phi| + sin phi) on [-1, 1] for phi in
 // [0, pi] (bins below half).  The cells are at most half as wide as the
-// closest two edges; a cell holds the bin of its centre.
+// closest two edges; a cell holds the lowest bin over the cell widened by
+// LUT_GUARD on both sides (far more than the FP32 rounding of the variable and
+// of the cell index), so a widened cell spans at most one edge and the bin of
+// any value mapped to the cell is its entry or one more.
+constexpr double LUT_GUARD = 1e-5;
+
 struct BinLut {
   int m[3];  // cells: theta, psi, phi
   bool ok;   // every table fits its share of LUT_BYTES
@@ -228,8 +233,9 @@ BinLut bin_lut_plan(const ot::RayTableP &RP) {
     double gap = HUGE_VAL;
     for (size_t i = 1; i < x.size(); ++i) gap = std::min(gap, std::fabs(x[i] - x[i - 1]));
     const double cells = gap == HUGE_VAL ? 2.0 : std::ceil(range[w] / (0.5 * gap));
-    L.m[w] = cells + 1 <= cap[w] ? (int)cells : 1;
-    L.ok = L.ok && cells + 1 <= cap[w];
+    const bool fits = cells + 1 <= cap[w] && (gap == HUGE_VAL || gap > 100.0 * LUT_GUARD);
+    L.m[w] = fits ? (int)cells : 1;
+    L.ok = L.ok && fits;
   }
   return L;
 }
@@ -239,11 +245,14 @@ std::vector<uint8_t> bin_luts(const ot::RayTableP &RP) {
   std::vector<uint8_t> lut(ot::LUT_BYTES, 0);
   if (!L.ok) return lut;
   const int base[3] = {0, ot::LUT_TH, ot::LUT_TH + ot::LUT_PS};
+  const double lo0[3] = {-1.0, 0.0, -1.0}, range[3] = {2.0, 1.0, 2.0};
   for (int w = 0; w < 3; ++w) {
     const std::vector<double> x = lut_edges(RP, w);
+    const double width = range[w] / L.m[w];
     for (int j = 0; j <= L.m[w]; ++j) {
-      // cell centre; theta and phi bins grow as their variable falls
-      const double v = w == 1 ? (j + 0.5) / L.m[w] : -1.0 + (j + 0.5) * 2.0 / L.m[w];
+      // theta and phi bins grow as their variable falls (lowest bin at the
+      // widened cell's top), the psi bin as sin psi rises (at its bottom)
+      const double v = w == 1 ? lo0[w] + j * width - LUT_GUARD : lo0[w] + (j + 1) * width + LUT_GUARD;
       int bin = 0;
       for (double xe : x) bin += w == 1 ? v >= xe : v <= xe;
       lut[base[w] + j] = (uint8_t)bin;

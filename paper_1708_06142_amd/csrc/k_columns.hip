@@ -151,6 +151,14 @@ __global__ void k_raytable_fill(RayTableP P, const double *__restrict__ dense, c
 }
 
 // ------------------------------------------------------------- column walk
+// a list record in the LDS tile: centre of mass and mass, (R_eq h)^2, and
+// R_eq h (times the psi table's scale) and the mass in FP32
+struct __align__(16) ColRec {
+  double x, y, z, w;
+  double rh2;
+  float rhs, m;
+};
+
 // list records per LDS tile (small: the maps need the LDS; with 48-pixel
 // FP32 maps of 256 cells three workgroups then fit in a compute unit's LDS)
 constexpr int TILE = 60;
@@ -172,20 +180,11 @@ __device__ inline int last_true(int n, Pred pred) {
   return k;
 }
 
-// The same answer from an estimate k0 in [0, n - 1] that is within one of
-// it: with pred monotone, pred(0) true and a sentinel threshold at n for
-// which pred is false, the answer is k0 - 1 + pred(k0) + pred(k0 + 1); the
-// two threshold reads are independent of each other.
-template <typename Pred>
-__device__ inline int near_true(int k0, Pred pred) {
-  return k0 - 1 + (int)pred(k0) + (int)pred(k0 + 1);
-}
-
-// Table row of a node at offset v = r_a - r from the target (|v|^2 = r2,
-// node size h, rh = R_eq h).  The bins are those of floor(theta / dtheta),
-// floor(phi / dphi) and floor(psi / dpsi), decided without inverse
-// trigonometric functions or square roots:
-//   theta >= k dtheta  <=>  v_z <= cos(k dtheta) d
+// Table row of a node at offset d = r - r_a from the target cell (the node
+// seen from the cell along v = -d; |d|^2 = r2, node size h, R_eq h).  The bins
+// are those of floor(theta / dtheta), floor(phi / dphi) and floor(psi / dpsi)
+// of v, decided without inverse trigonometric functions or square roots:
+//   theta >= k dtheta  <=>  v_z <= cos(k dtheta) |v|
 //                      <=>  v_z |v_z| <= cos(k dtheta) |cos(k dtheta)| r2
 //   psi   >= k dpsi    <=>  (R_eq h)^2 >= sin^2(k dpsi) r2
 //   phi   >= k dphi    <=>  cos(k dphi) v_y - sin(k dphi) v_x >= 0   (0 < phi < pi)
@@ -195,30 +194,30 @@ __device__ inline int near_true(int k0, Pred pred) {
 // sign bit set.  The comparisons are FP64.
 // Which k to compare: three byte tables in LDS, indexed by FP32 values that
 // are monotone in the angles (cos theta, sin psi, and t = u_x / (|u_x| + u_y)
-// for phi in [0, pi]), give the bin of their cell's centre.  A cell is at
-// most half as wide as the closest two thresholds, so the bin is within one
-// of it and the comparisons at k0 and k0 + 1 then give the same bins as a
-// full binary search over the thresholds.  The searches remain for offsets
-// too small for FP32 and when the tables would not fit (C.estimate = 0).
-// rd = 1 / sqrt(max(f2, 1e-30)) for f2 = r2 in FP32.
-__device__ inline int table_row(const ColP &C, const double *thr, const uint8_t *lut, double vx, double vy,
-                                double vz, double r2, float f2, float rd, double rh2, float rhf) {
+// for phi in [0, pi]), hold for each cell the lowest bin over the cell
+// widened by a guard band larger than the FP32 rounding.  A widened cell
+// spans at most one threshold (cells are at most half as wide as the closest
+// two), so the bin is k0 or k0 + 1: one FP64 comparison at k0 + 1 decides
+// (each threshold list ends in a sentinel its test never passes).  Binary
+// searches remain for offsets too small for FP32 and when the tables would
+// not fit (C.estimate = 0).
+// dxf, dyf, dzf: d in FP32; rd = 1 / sqrt(max(f2, 1e-30)) for f2 = r2 in FP32;
+// rhs = R_eq h times the psi table's scale.
+__device__ inline int table_row(const ColP &C, const double *thr, const uint8_t *lut, double dx, double dy,
+                                double dz, float dxf, float dyf, float dzf, double r2, float f2, float rd,
+                                double rh2, float rhs) {
   const double *cth = thr;                       // [ntheta + 1] c |c|, sentinel -inf
   const double *sps = cth + C.ntheta + 1;        // [npsi + 1] sin^2, sentinel +inf
   const double *cs = sps + C.npsi + 1;           // [nphi/2 + 1] (cos, sin), the last (-1, 0)
-  const double vzz = vz * fabs(vz);
+  const double vzz = -dz * fabs(dz);             // v_z |v_z|
   const int half = C.nphi / 2;
-  const bool lower = vy < 0.0;
-  // v -> -v on the lower half-plane: u_y = |v_y|, u_x = v_x with v_y's sign
-  // (they differ from the flip only at v_y = -0, which takes the v_y = 0 rule)
-  const double uy = fabs(vy);
-  const double ux = __longlong_as_double(__double_as_longlong(vx) ^ (__double_as_longlong(vy) & (long long)0x8000000000000000ull));
+  const bool lower = dy > 0.0;                   // v_y < 0
+  // v -> -v on the lower half-plane: u = (v_x or -v_x, |v_y|)
+  const double ux = dx * (lower ? 1.0 : -1.0);
   auto pth = [&](int k) { return vzz <= cth[k] * r2; };
   auto pps = [&](int k) { return rh2 >= sps[k] * r2; };
-  auto pph = [&](int q) { return cs[2 * q] * uy - cs[2 * q + 1] * ux >= 0.0; };
-  const float fx = (float)ux, fy = (float)uy;
-  const float den = fabsf(fx) + fy;
-  const float den1 = den + 1e-30f;  // > 0, and den1 = den whenever den > 1e-30
+  auto pph = [&](int q) { return cs[2 * q] * fabs(dy) - cs[2 * q + 1] * ux >= 0.0; };
+  const float den = fabsf(dxf) + fabsf(dyf);     // |u_x| + u_y
   // Every index is inside its table: |cos theta| <= 1 and |t| <= 1 up to
   // rounding, sin psi is clamped to 1, and each table has one cell to spare.
   // The estimates run on every lane; lanes outside their range are redone by
@@ -226,11 +225,14 @@ __device__ inline int table_row(const ColP &C, const double *thr, const uint8_t 
   // free of divergent control flow.  (On the x axis, v_y = 0, phi comes from
   // the atan2 rule below and its estimate is not used: a node straight above
   // or below the cell is safe.)
-  const bool safe = C.estimate && f2 > 1e-30f && (den > 1e-30f || vy == 0.0);
-  int it = near_true(lut[(int)fmaf((float)vz * rd, C.lut_th, C.lut_th)], pth);
-  int is = near_true(lut[LUT_TH + (int)(fminf(rhf * rd, 1.0f) * C.lut_ps)], pps);
-  const float t = fx * __builtin_amdgcn_rcpf(den1);
-  int k = near_true(lut[LUT_TH + LUT_PS + (int)fmaf(t, C.lut_ph, C.lut_ph)], pph);
+  const bool safe = C.estimate && f2 > 1e-30f && (den > 1e-30f || dy == 0.0);
+  const int k0t = lut[(int)fmaf(-dzf * rd, C.lut_th, C.lut_th)];
+  const int k0s = lut[LUT_TH + (int)fminf(rhs * rd, C.lut_ps)];
+  const float t = (float)ux * __builtin_amdgcn_rcpf(den + 1e-30f);
+  const int k0p = lut[LUT_TH + LUT_PS + (int)fmaf(t, C.lut_ph, C.lut_ph)];
+  int it = k0t + (int)pth(k0t + 1);
+  int is = k0s + (int)pps(k0s + 1);
+  int k = k0p + (int)pph(k0p + 1);
   if (__ballot(!safe)) {
     if (!safe) {
       it = last_true(C.ntheta, pth);
@@ -238,10 +240,10 @@ __device__ inline int table_row(const ColP &C, const double *thr, const uint8_t 
       k = last_true(half, pph);
     }
   }
-  // atan2(+-0, x) is pi (bin ip_pi) whenever the sign bit of x is set, -0
-  // included (a node straight above the cell, v = -d with d_x = +0), else 0;
+  // atan2(+-0, x) is pi (bin ip_pi) whenever the sign bit of v_x = -d_x is
+  // set, -0 included (a node straight above the cell, d_x = +0), else 0;
   // k <= half - 1, so the lower half-plane stays below nphi
-  const int ip = vy == 0.0 ? (signbit(vx) ? C.ip_pi : 0) : (lower ? half : 0) + k;
+  const int ip = dy == 0.0 ? (signbit(dx) ? 0 : C.ip_pi) : (lower ? half : 0) + k;
   return (int)__umul24(__umul24(it, C.nphi) + ip, C.npsi) + is;  // < 2^24 entries
 }
 
@@ -349,9 +351,7 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
                                                    Real *__restrict__ npix, Real *__restrict__ tau, double negG,
                                                    int cpw, int lcpw) {
   __shared__ uint8_t lut[LUT_BYTES];
-  __shared__ double4 tile[TILE];
-  __shared__ double tileh[TILE];  // (R_eq h)^2
-  __shared__ float2 tilef[TILE];  // R_eq h, m (FP32)
+  __shared__ ColRec tile[TILE];
   extern __shared__ __align__(16) unsigned char smem[];
   double *thr = reinterpret_cast<double *>(smem);
   Real *map = reinterpret_cast<Real *>(thr + C.nthr);
@@ -381,9 +381,13 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
     for (int q = tid; q < TILE && t0 + q < n; q += cpw) {
       const double4 rq = rec[start + t0 + q];
       const double rh = C.req * lh[start + t0 + q];  // radius of the equal-volume sphere
-      tile[q] = rq;
-      tileh[q] = rh * rh;
-      tilef[q] = make_float2((float)rh, (float)rq.w);
+      tile[q].x = rq.x;
+      tile[q].y = rq.y;
+      tile[q].z = rq.z;
+      tile[q].w = rq.w;
+      tile[q].rh2 = rh * rh;
+      tile[q].rhs = (float)rh * C.lut_ps;
+      tile[q].m = (float)rq.w;
     }
     __syncthreads();
     const int m = (int)(n - t0 < TILE ? n - t0 : TILE);
@@ -392,7 +396,7 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
     // not with the list length)
     Real tx = 0, ty = 0, tz = 0;
     for (int j = 0; j < m; ++j) {
-      const double4 r = tile[j];
+      const ColRec r = tile[j];
       double dx = cx - r.x, dy = cy - r.y, dz = cz - r.z;
       wrap3<BC>(E, dx, dy, dz);
       const double r2 = dx * dx + dy * dy + dz * dz;
@@ -400,8 +404,8 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
       const bool col = valid && r2 <= C.max_dist2;
       const float r2f = (float)r2;
       const float rd = __builtin_amdgcn_rsqf(fmaxf(r2f, 1e-30f));
-      const float2 nf = tilef[j];
-      const int e = col ? table_row(C, thr, lut, -dx, -dy, -dz, r2, r2f, rd, tileh[j], nf.x) : 0;
+      const float dxf = (float)dx, dyf = (float)dy, dzf = (float)dz;
+      const int e = col ? table_row(C, thr, lut, dx, dy, dz, dxf, dyf, dzf, r2, r2f, rd, r.rh2, r.rhs) : 0;
       if (sizeof(Real) == 8) {
         if (!valid) continue;
         const uint32_t hd = C.rows[e];
@@ -419,12 +423,14 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         // FP32 gravity from the FP64 offset (already the minimum image)
         const float inv = valid ? rd : 0.0f;
         float ph, A0, A1, A2;
-        grav32<BC, NEWTON>(E, (float)dx, (float)dy, (float)dz, inv, ph, A0, A1, A2);
-        const float m32 = valid ? nf.y : 0.0f;
+        grav32<BC, NEWTON>(E, dxf, dyf, dzf, inv, ph, A0, A1, A2);
+        // the target cell's term is an exact zero (a Kahan step with it only
+        // moves the compensation into the sum)
+        const float m32 = valid ? r.m : 0.0f;
         const float y = m32 * ph - (float)cmp;
         const float tt = (float)s + y;
-        cmp = valid ? (Real)((tt - (float)s) - y) : cmp;
-        s = valid ? (Real)tt : s;
+        cmp = (Real)((tt - (float)s) - y);
+        s = (Real)tt;
         tx += (Real)(m32 * A0);
         ty += (Real)(m32 * A1);
         tz += (Real)(m32 * A2);
@@ -433,7 +439,8 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         // read-modify-writes are independent; the column is the thread's own
         // (plain read-modify-write: LDS atomic adds measured 2.5x slower)
         const float base = col ? m32 * inv_omega * (rd * rd) : 0.0f;
-        const uint4 pq = C.rows8[2 * e], wq = C.rows8[2 * e + 1];
+        const char *const rp = reinterpret_cast<const char *>(C.rows8) + (uint32_t)e * 32u;
+        const uint4 pq = *reinterpret_cast<const uint4 *>(rp), wq = *reinterpret_cast<const uint4 *>(rp + 16);
         // bit 31 of the first pixel (more than four) is shifted out here
         float *const q0 = reinterpret_cast<float *>(mcell + (pq.x << lmap));
         float *const q1 = reinterpret_cast<float *>(mcell + (pq.y << lmap));
@@ -548,7 +555,8 @@ hipError_t launch_raytable(const RayTableP &P, double *dense, int32_t *cnt, int6
   return hipGetLastError();
 }
 
-constexpr size_t COLS_STATIC_LDS = LUT_BYTES + TILE * (sizeof(double4) + sizeof(double) + sizeof(float2));
+constexpr size_t COLS_STATIC_LDS = LUT_BYTES + TILE * sizeof(ColRec);
+static_assert(sizeof(ColRec) == 48, "list record of the column walk");
 
 size_t cols_smem_bytes(int npix, int cpw, bool fp64, int nthr) {
   return COLS_STATIC_LDS + (size_t)nthr * sizeof(double) + (size_t)npix * cpw * (fp64 ? 8 : 4);
