@@ -90,6 +90,7 @@ ot::DevTree dev_tree(ot_ctx *c) {
     T.per[k] = c->p.bc[k];
     T.org[k] = c->p.origin[k];
     T.L[k] = c->box[k];
+    T.inv_L[k] = ot::exact_inverse(c->box[k]);
   }
   T.root_size = c->p.root_size;
   return T;
@@ -134,6 +135,7 @@ ot::EwaldP ewald_desc(const ot_ctx *c) {
   E.n = c->ew_n;
   for (int k = 0; k < 3; ++k) {
     E.L[k] = c->box[k];
+    E.inv_L[k] = ot::exact_inverse(c->box[k]);
     E.step[k] = c->ew_step[k];
     E.inv_step[k] = c->ew_step[k] > 0 ? 1.0 / c->ew_step[k] : 0.0;
   }

@@ -35,6 +35,7 @@ struct DevTree {
   double root_size;
   double org[3];
   double L[3];            // domain edge per axis
+  double inv_L[3];        // exact_inverse(L)
 };
 
 __host__ __device__ inline double size_at(double root_size, int lev) {
@@ -50,9 +51,19 @@ __host__ __device__ inline double centre_coord(double org, int64_t pos, double s
   return org + ((double)pos + 0.5) * size;
 }
 
-// minimum image in a periodic axis, wrapped to [-L/2, L/2)
-__device__ inline double wrap_axis(double d, double L, int per) {
-  return per ? d - L * floor(d / L + 0.5) : d;
+// minimum image in a periodic axis, wrapped to [-L/2, L/2): d - L floor(d / L
+// + 1/2).  inv_L = 1 / L when L is a power of two (then d inv_L is d / L
+// exactly), else 0 and the quotient is a division.
+__device__ inline double wrap_axis(double d, double L, double inv_L, int per) {
+  if (!per) return d;
+  const double q = inv_L != 0.0 ? d * inv_L : d / L;
+  return d - L * floor(q + 0.5);
+}
+
+// 1 / L if that is exact (L a power of two), else 0
+__host__ inline double exact_inverse(double L) {
+  int e = 0;
+  return L > 0.0 && frexp(L, &e) == 0.5 ? 1.0 / L : 0.0;
 }
 
 __device__ inline int cell_index(int o1, int o2, int o3) {

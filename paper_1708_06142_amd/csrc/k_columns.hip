@@ -250,9 +250,9 @@ __device__ inline int table_row(const ColP &C, const double *thr, const uint8_t 
 template <int BC>
 __device__ inline void wrap3(const EwaldP &E, double &dx, double &dy, double &dz) {
   if (BC != 0) {
-    dx = dx - E.L[0] * floor(dx / E.L[0] + 0.5);
-    dy = dy - E.L[1] * floor(dy / E.L[1] + 0.5);
-    if (BC == 1) dz = dz - E.L[2] * floor(dz / E.L[2] + 0.5);
+    dx = wrap_axis(dx, E.L[0], E.inv_L[0], 1);
+    dy = wrap_axis(dy, E.L[1], E.inv_L[1], 1);
+    if (BC == 1) dz = wrap_axis(dz, E.L[2], E.inv_L[2], 1);
   }
 }
 

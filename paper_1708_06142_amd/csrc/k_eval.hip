@@ -36,9 +36,9 @@ __device__ inline void pair64(const EwaldP &E, double cx, double cy, double cz, 
                               double &sp, double &ax, double &ay, double &az) {
   double dx = cx - r.x, dy = cy - r.y, dz = cz - r.z;
   if (BC != 0) {
-    dx = dx - E.L[0] * floor(dx / E.L[0] + 0.5);
-    dy = dy - E.L[1] * floor(dy / E.L[1] + 0.5);
-    if (BC == 1) dz = dz - E.L[2] * floor(dz / E.L[2] + 0.5);
+    dx = wrap_axis(dx, E.L[0], E.inv_L[0], 1);
+    dy = wrap_axis(dy, E.L[1], E.inv_L[1], 1);
+    if (BC == 1) dz = wrap_axis(dz, E.L[2], E.inv_L[2], 1);
   }
   const double r2 = dx * dx + dy * dy + dz * dz;
   if (r2 == 0.0) return;
@@ -221,9 +221,9 @@ __global__ __launch_bounds__(WG) void k_eval32(DevTree T, EwaldP E, const int64_
         v.y = (float)(((double)((own >> 3) & 7) - 3.5) * h);
         v.z = (float)(((double)(own >> 6) - 3.5) * h);
       } else {
-        v.x = (float)wrap_axis(r.x - cT[0], T.L[0], T.per[0]);
-        v.y = (float)wrap_axis(r.y - cT[1], T.L[1], T.per[1]);
-        v.z = (float)wrap_axis(r.z - cT[2], T.L[2], T.per[2]);
+        v.x = (float)wrap_axis(r.x - cT[0], T.L[0], T.inv_L[0], T.per[0]);
+        v.y = (float)wrap_axis(r.y - cT[1], T.L[1], T.inv_L[1], T.per[1]);
+        v.z = (float)wrap_axis(r.z - cT[2], T.L[2], T.inv_L[2], T.per[2]);
       }
       v.w = (float)r.w;
       tile[tid] = v;

@@ -38,14 +38,14 @@ __device__ inline bool accept(const DevTree &T, const MacP &P, const Target &tg,
   const double half = P.half_eta * h;
   bool outside = false;
   for (int k = 0; k < 3; ++k) {
-    double d = wrap_axis(tg.c[k] - g[k], T.L[k], T.per[k]);
+    double d = wrap_axis(tg.c[k] - g[k], T.L[k], T.inv_L[k], T.per[k]);
     if (fabs(d) - tg.ext > half) outside = true;
   }
   if (!outside) return false;
   const double com[3] = {mc.x, mc.y, mc.z};
   double d2 = 0.0;
   for (int k = 0; k < 3; ++k) {
-    double d = wrap_axis(tg.c[k] - com[k], T.L[k], T.per[k]);
+    double d = wrap_axis(tg.c[k] - com[k], T.L[k], T.inv_L[k], T.per[k]);
     double e = fabs(d) - tg.ext;
     if (e > 0.0) d2 = d2 + e * e;
   }

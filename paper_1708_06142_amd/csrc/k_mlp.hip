@@ -497,9 +497,9 @@ __global__ __launch_bounds__(WG) void k_eval_mlp(DevTree T, EwaldP E, const void
         v.y = (float)(((double)((own >> 3) & 7) - 3.5) * h);
         v.z = (float)(((double)(own >> 6) - 3.5) * h);
       } else {
-        v.x = (float)wrap_axis(r.x - cT[0], T.L[0], T.per[0]);
-        v.y = (float)wrap_axis(r.y - cT[1], T.L[1], T.per[1]);
-        v.z = (float)wrap_axis(r.z - cT[2], T.L[2], T.per[2]);
+        v.x = (float)wrap_axis(r.x - cT[0], T.L[0], T.inv_L[0], T.per[0]);
+        v.y = (float)wrap_axis(r.y - cT[1], T.L[1], T.inv_L[1], T.per[1]);
+        v.z = (float)wrap_axis(r.z - cT[2], T.L[2], T.inv_L[2], T.per[2]);
       }
       v.w = (float)r.w;
       tile[tid] = v;

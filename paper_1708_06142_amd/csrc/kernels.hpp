@@ -25,6 +25,7 @@ struct EwaldP {
   int bctype;            // 0 iso, 1 3P, 2 2P1I
   int n;                 // table points per axis
   double L[3];           // box
+  double inv_L[3];       // exact_inverse(L)
   double step[3];        // table spacing per axis
   double inv_step[3];
   double zfar;           // 2P1I: |dz| beyond which the analytic limit is used
