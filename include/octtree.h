@@ -224,6 +224,17 @@ ot_status ot_ewald_points(ot_ctx *c, int32_t method, int64_t n, const double *d_
                           void *stream);
 
 /* ---- inspection (tests, tools) ---- */
+/* Node-ray table entry (Sec. 2.3: the (theta, phi, psi) bin of a node seen
+ * from a cell) that the column walk uses for nodes of size h_dev [n] at
+ * offsets d_dev [n][3] = cell centre minus node centre of mass (FP64, any
+ * sign; the periodic wrap is the caller's), into row_dev [n]: entry
+ * (itheta * il_nphi + iphi) * il_npsi + ipsi, or -1 for d = 0.  Runs the walk's
+ * own device function (look-up estimate, FP64 threshold tests, exact
+ * fallback).  Needs nside > 0; builds the node-ray table on first use.
+ * Device pointers are the caller's; n <= 2^30. */
+ot_status ot_column_bins(ot_ctx *c, int64_t n, const double *d_dev, const double *h_dev, int32_t *row_dev,
+                         void *stream);
+
 /* Number of amr nodes (all blocks, leaf or not) after ot_set_blocks. */
 int64_t ot_num_amr_nodes(const ot_ctx *c);
 /* amr-tree topology as built on the host: level [na], coord [na*3], leaf

@@ -75,6 +75,7 @@ def lib():
         L.or_healpix_vec2pix.restype = i64
         L.or_healpix_vec2pix.argtypes = [i64, C.c_double, C.c_double, C.c_double]
         L.or_healpix_pix2ang.argtypes = [i64, i64, vp]
+        L.or_raytable_entries.argtypes = [C.c_int] * 3 + [C.c_double, i64, vp, vp, vp]
         L.or_raytable_export.restype = i64
         L.or_raytable_export.argtypes = [C.c_int] * 6 + [C.c_double, vp, vp, vp]
         L.or_walk_percell.argtypes = [vp, i64, vp, vp, vp, vp]
@@ -266,6 +267,17 @@ def pix2ang(nside, p):
     out = np.empty(2)
     lib().or_healpix_pix2ang(int(nside), int(p), _ptr(out))
     return out  # z, phi
+
+
+def raytable_entries(d, h, il_ntheta=25, il_nphi=50, il_npsi=25, psi_max=0.98):
+    """Node-ray table entry (theta, phi, psi bin) the walk uses for nodes of
+    size h [n] at offsets d [n, 3] = target cell minus node; -1 for d = 0."""
+    d = np.ascontiguousarray(d, np.float64)
+    h = np.ascontiguousarray(h, np.float64)
+    out = np.empty(d.shape[0], np.int64)
+    lib().or_raytable_entries(int(il_ntheta), int(il_nphi), int(il_npsi), float(psi_max), d.shape[0],
+                              _ptr(d), _ptr(h), _ptr(out))
+    return out
 
 
 def raytable(nside, il_ntheta=25, il_nphi=50, il_npsi=25, il_nr=50, il_nazi=100, psi_max=0.98):

@@ -220,6 +220,32 @@ int64_t or_raytable_entry(const or_raytable *T, const double v[3], double d, dou
 }
 
 /* ---------------------------------------------------------- test exports */
+/* table entries of nodes of size h[i] at offsets d[i] = r - r_a (target cell
+ * minus node), as the walk bins them (v = -d, |v| = sqrt of the plain sum of
+ * squares); -1 for d = 0 */
+void or_raytable_entries(int ntheta, int nphi, int npsi, double psimax, int64_t n, const double *d,
+                         const double *h, int64_t *out) {
+  or_raytable T;
+  memset(&T, 0, sizeof(T));
+  T.ntheta = ntheta;
+  T.nphi = nphi;
+  T.npsi = npsi;
+  T.psimax = psimax;
+  T.dtheta = M_PI / (double)ntheta;
+  T.dphi = (2.0 * M_PI) / (double)nphi;
+  T.dpsi = psimax / (double)npsi;
+  for (int64_t i = 0; i < n; ++i) {
+    const double *di = d + 3 * i;
+    double r2 = di[0] * di[0] + di[1] * di[1] + di[2] * di[2];
+    if (r2 == 0.0) {
+      out[i] = -1;
+      continue;
+    }
+    double v[3] = {-di[0], -di[1], -di[2]};
+    out[i] = or_raytable_entry(&T, v, sqrt(r2), h[i]);
+  }
+}
+
 int64_t or_healpix_vec2pix(int64_t nside, double x, double y, double z) {
   return or_vec2pix_nest(nside, x, y, z);
 }

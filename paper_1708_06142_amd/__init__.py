@@ -106,13 +106,14 @@ def lib():
         L.ot_mlp_set.argtypes = [vp, vp, vp, C.c_int32, vp]
         L.ot_mlp_grad.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
         L.ot_ewald_points.argtypes = [vp, C.c_int32, i64, vp, vp, vp]
+        L.ot_column_bins.argtypes = [vp, i64, vp, vp, vp, vp]
         L.ot_last_error.restype = C.c_char_p
         L.ot_last_error.argtypes = [vp]
         L.ot_destroy.argtypes = [vp]
         for name in ("ot_create", "ot_set_blocks", "ot_build", "ot_solve", "ot_solve64",
                      "ot_ewald_prepare", "ot_export_topology", "ot_export_moments",
                      "ot_export_list", "ot_export_ewald_table", "ot_export_raytable", "ot_mlp_train",
-                     "ot_mlp_get", "ot_mlp_set", "ot_mlp_grad", "ot_ewald_points"):
+                     "ot_mlp_get", "ot_mlp_set", "ot_mlp_grad", "ot_ewald_points", "ot_column_bins"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -286,6 +287,13 @@ class Solver:
                                           _dev_ptr(out, f), _stream(stream)))
 
     # ---- inspection
+    def column_bins(self, d, h, row, stream=None):
+        """Node-ray table rows the column walk uses for nodes of size h [n]
+        at device offsets d [n, 3] (cell minus node) into row [n] (int32)."""
+        import torch
+        self._check(lib().ot_column_bins(self.h, int(d.shape[0]), _dev_ptr(d, torch.float64),
+                                         _dev_ptr(h, torch.float64), _dev_ptr(row, torch.int32), _stream(stream)))
+
     def export_topology(self):
         na = self.na
         out = dict(alev=np.empty(na, np.int32), acoord=np.empty((na, 3), np.int32),

@@ -1023,6 +1023,19 @@ ot_status ot_ewald_points(ot_ctx *c, int32_t method, int64_t n, const double *d,
   return OT_OK;
 }
 
+ot_status ot_column_bins(ot_ctx *c, int64_t n, const double *d, const double *h, int32_t *row, void *stream) {
+  if (!c) return OT_ERR_INVALID_ARG;
+  c->err.clear();
+  if (n < 0 || (n > 0 && (!d || !h || !row))) return fail(c, OT_ERR_INVALID_ARG, "bad size or null pointer");
+  if (n > ((int64_t)1 << 30)) return fail(c, OT_ERR_INVALID_ARG, "n > 2^30");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->p.device));
+  OTCHK(raytable_prepare(c, st));
+  HIPCHK(ot::launch_column_bins(col_params(c), n, d, h, row, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return OT_OK;
+}
+
 const char *ot_last_error(const ot_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 void ot_destroy(ot_ctx *c) {

@@ -225,7 +225,9 @@ __device__ inline int table_row(const ColP &C, const double *thr, const uint8_t 
   // free of divergent control flow.  (On the x axis, v_y = 0, phi comes from
   // the atan2 rule below and its estimate is not used: a node straight above
   // or below the cell is safe.)
-  const bool safe = C.estimate && f2 > 1e-30f && (den > 1e-30f || dy == 0.0);
+  // (den + 1e-30 below keeps the reciprocal finite; it is den to ten digits
+  // only for den > 1e-20, so smaller den take the exact path)
+  const bool safe = C.estimate && f2 > 1e-30f && (den > 1e-20f || dy == 0.0);
   const int k0t = lut[(int)fmaf(-dzf * rd, C.lut_th, C.lut_th)];
   const int k0s = lut[LUT_TH + (int)fminf(rhs * rd, C.lut_ps)];
   const float t = (float)ux * __builtin_amdgcn_rcpf(den + 1e-30f);
@@ -495,6 +497,31 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
   tau[o] = (Real)(-log(se / (double)C.npix));
 }
 
+// table rows of arbitrary offsets d = cell - node with the walk's binning
+// (thresholds and look-up tables in LDS as in the walk); -1 for d = 0
+__global__ __launch_bounds__(256) void k_column_bins(ColP C, int64_t n, const double *__restrict__ d,
+                                                     const double *__restrict__ hn, int32_t *__restrict__ row) {
+  __shared__ uint8_t lut[LUT_BYTES];
+  extern __shared__ __align__(16) unsigned char smem[];
+  double *thr = reinterpret_cast<double *>(smem);
+  for (int q = threadIdx.x; q < LUT_BYTES; q += 256) lut[q] = C.lut[q];
+  for (int q = threadIdx.x; q < C.nthr; q += 256) thr[q] = C.thr[q];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool in = i < n;
+  // every lane runs the binning (its fallback is decided by a wave vote)
+  const double dx = in ? d[3 * i] : 1.0, dy = in ? d[3 * i + 1] : 0.0, dz = in ? d[3 * i + 2] : 0.0;
+  const double h = in ? hn[i] : 0.0;
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const float r2f = (float)r2;
+  const float rd = __builtin_amdgcn_rsqf(fmaxf(r2f, 1e-30f));
+  const double rh = C.req * h;
+  const int e = r2 != 0.0 ? table_row(C, thr, lut, dx, dy, dz, (float)dx, (float)dy, (float)dz, r2, r2f, rd,
+                                      rh * rh, (float)rh * C.lut_ps)
+                          : -1;
+  if (in) row[i] = e;
+}
+
 // packed rows for the walk: head = offset << 6 | count; entry = pixel << 24 |
 // round(w 2^24) (w <= 1, clamped to 2^24 - 1); rows8 = the first four pixels
 // and their FP32 weights, padded with the lowest pixels the row does not use
@@ -537,6 +564,14 @@ __global__ void k_raytable_pack(RayTableP P, const int64_t *__restrict__ off, co
 }
 
 }  // namespace
+
+hipError_t launch_column_bins(const ColP &C, int64_t n, const double *d, const double *h, int32_t *row,
+                              hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_column_bins, dim3((unsigned)((n + 255) / 256)), dim3(256), C.nthr * sizeof(double), st, C,
+                     n, d, h, row);
+  return hipGetLastError();
+}
 
 hipError_t launch_raytable(const RayTableP &P, double *dense, int32_t *cnt, int64_t *off, uint16_t *pix,
                            double *w64, int64_t *total, hipStream_t st) {

@@ -82,6 +82,9 @@ size_t cols_smem_bytes(int npix, int cpw, bool fp64, int nthr);
 int cols_lds_cpw(int npix, bool fp64, int nthr);
 // newton_only (FP32, 3P / 2P1I): the minimum-image Newtonian part only, for
 // every pair; launch_eval_mlp with add = true then adds the correction
+// table rows of offsets d [n][3] (cell - node) of nodes of size h [n]; -1 for d = 0
+hipError_t launch_column_bins(const ColP &C, int64_t n, const double *d, const double *h, int32_t *row,
+                              hipStream_t st);
 // cpw: cols_lds_cpw (0: maps in npix);
 // wg_per_cu (may be null): workgroups of the launched kernel resident per CU
 hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const ColP &C, const int64_t *off,
