@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=128, help="cells per axis")
-    ap.add_argument("--cpu-blocks", type=int, default=256, help="oracle sample size (blocks)")
+    ap.add_argument("--cpu-blocks", type=int, default=1024, help="oracle sample size (blocks, ~10 s on 16 threads)")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB: one fill + one sum of that size before timing (HBM counter calibration)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--surrogate-steps", type=int, default=2)
     ap.add_argument("--no-c5", action="store_true",
                     help="skip the large AMR leg (15.2M cells, 2P1I, 192-pixel columns)")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the Plummer AMR leg (2.6M cells, box 1x1x4, 2P1I, 64^3 Ewald table)")
     return ap.parse_args()
 
 
@@ -231,6 +233,40 @@ def c5_leg():
     return out
 
 
+def c3_leg(steps):
+    """Plummer AMR configuration: box 1 x 1 x 4 (four root blocks), 64^3 base,
+    up to three levels around four Plummer cores (5,100 blocks, 2.61M cells),
+    x, y periodic and z isolated, BH theta = 0.5, FP64-generated 64^3 Ewald
+    table: the FP32-Kahan table walk beside the FP64 table walk."""
+    import torch
+    import paper_1708_06142_amd as ot
+    import workloads
+    g = workloads.c3_amr()
+    n = g.ncells
+    rho = torch.from_numpy(g.rho.reshape(-1)).cuda()
+    s = ot.Solver.for_grid(g, mac="bh", theta=0.5, ewald_n=64)
+    out = {"workload": f"Plummer AMR, box 1x1x4, {g.nb} blocks, {n} cells, 2P1I, BH theta 0.5, 64^3 Ewald table"}
+    res = {}
+    for label, fp64 in (("table_fp32", False), ("table_fp64", True)):
+        dt = torch.float64 if fp64 else torch.float32
+        outs = (torch.empty(n, dtype=dt, device="cuda"), torch.empty(3 * n, dtype=dt, device="cuda"))
+        ms, st, ms_eval, ms_list, _ = timed_steps(s, rho, outs, fp64, steps, 1)
+        res[label] = outs
+        flop = st.n_interactions * (FLOP_PAIR_ISO + 46) / (ms_eval * 1e-3) / 1e12
+        peak = PEAK_FP64_VALU if fp64 else PEAK_FP32_VALU
+        out[label] = {"value": n / (ms * 1e-3), "unit": "cells/s", "ms_per_step": ms, "ms_eval": ms_eval,
+                      "ms_lists": ms_list, "n_int": st.n_interactions,
+                      "roofline": {"bound": "alu", "kernel": f"k_eval{'64' if fp64 else '32'}<2P1I>",
+                                   "achieved": flop, "peak": peak, "unit": "TFLOP/s", "frac": flop / peak,
+                                   "flop_per_pair": FLOP_PAIR_ISO + 46}}
+    s.close()
+    (p32, a32), (p64, a64) = res["table_fp32"], res["table_fp64"]
+    out["table_fp32"]["dphi_rel_vs_fp64"] = float(((p32.double() - p64).abs() / p64.abs()).max())
+    a64n = a64.view(3, -1).pow(2).sum(0).sqrt().max()
+    out["table_fp32"]["da_maxnorm_vs_fp64"] = float((a32.double() - a64).abs().max() / a64n)
+    return out
+
+
 def cpu_baseline(grid, a_lim, nblk, nside):
     """The FP64 oracle's group walk on a seeded sample of blocks, host cores."""
     import oracle
@@ -324,6 +360,8 @@ def main():
                             "eval_wg_per_cu": st64.eval_wg_per_cu}
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(grid, rho, args.surrogate_steps, args.nside)
+    if not args.no_c3:
+        out["c3"] = c3_leg(max(2, args.steps // 2))
     if not args.no_c5:
         out["c5"] = c5_leg()
     if not args.no_cpu:
