@@ -537,14 +537,14 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
                                 &wg_per_cu, st));
     // with the surrogate: the column walk left the Newtonian part; add the correction
     if (use_mlp)
-      HIPCHK(ot::launch_eval_mlp(T, E, c->mlp_pk.ptr, P<int64_t>(c->loff), P<double4>(c->lrec),
-                                 P<int32_t>(c->lid), (float *)phi, (float *)acc, c->p.G, true, st));
+      HIPCHK(ot::launch_eval_mlp(T, E, c->mlp_pk.ptr, P<int64_t>(c->loff), P<double4>(c->lrec), (float *)phi,
+                                 (float *)acc, c->p.G, true, st));
   } else if (fp64)
     HIPCHK(ot::launch_eval64(T, E, P<int64_t>(c->loff), P<double4>(c->lrec), (double *)phi,
                              (double *)acc, c->p.G, st));
   else if (use_mlp)
-    HIPCHK(ot::launch_eval_mlp(T, E, c->mlp_pk.ptr, P<int64_t>(c->loff), P<double4>(c->lrec),
-                               P<int32_t>(c->lid), (float *)phi, (float *)acc, c->p.G, false, st));
+    HIPCHK(ot::launch_eval_mlp(T, E, c->mlp_pk.ptr, P<int64_t>(c->loff), P<double4>(c->lrec), (float *)phi,
+                               (float *)acc, c->p.G, false, st));
   else
     HIPCHK(ot::launch_eval32(T, E, P<int64_t>(c->loff), P<double4>(c->lrec), P<int32_t>(c->lid),
                              (float *)phi, (float *)acc, c->p.G, st));

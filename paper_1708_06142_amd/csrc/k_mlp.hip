@@ -462,99 +462,88 @@ __global__ __launch_bounds__(256) void k_mlp_points_eval(const void *__restrict_
 // threads per leaf block, thread t owns cells t and t + 256, the list streams
 // through LDS in tiles of offsets from the block centre.  Wave w owns the 128
 // cells {64 w + l, 256 + 64 w + l}; for every list entry it runs 4 batches of
-// 32 pairs through the network, batch b covering the cells of lane group
-// b & 1 in slot b >> 1.  Phi is Kahan-compensated.
+// 32 pairs through the network: batch (sl, gg) covers cells 64 w + 32 gg + m +
+// 256 sl (m = l % 32, both lane groups hold halves of each pair's operand),
+// and lane group g keeps the batches gg = g, in slot sl.  Phi is
+// Kahan-compensated.
 constexpr int WG = 256;
 
 template <int BC, bool ADD>
 __global__ __launch_bounds__(WG) void k_eval_mlp(DevTree T, EwaldP E, const void *__restrict__ pk,
                                                  const int64_t *__restrict__ off, const double4 *__restrict__ rec,
-                                                 const int32_t *__restrict__ ids, float *__restrict__ phi,
+                                                 float *__restrict__ phi,
                                                  float *__restrict__ acc, float negG) {
-  __shared__ float4 tile[WG];
+  __shared__ double4 tile[WG];
   const int64_t b = blockIdx.x;
   const int tid = threadIdx.x, l = tid & 63, w = tid >> 6, g = l >> 5, m = l & 31;
   const int64_t ncell = T.nb * 512;
-  const double sb = size_at(T.root_size, T.blev[b]);
-  const double h = sb / 8.0;
-  double cT[3];
-  for (int k = 0; k < 3; ++k) cT[k] = centre_coord(T.org[k], T.bcoord[3 * b + k], sb);
-  const int64_t own0 = T.na + 72 * T.nb + 512 * b;
+  const double h = size_at(T.root_size, T.blev[b]) / 8.0;
   __shared__ f16x8 wl[64 * NPK];
   const mlpinf::Ops W = mlpinf::load_ops(pk, wl);
   const f16x8 one = mlpinf::ones();
-  const float Lx = (float)E.L[0], Ly = (float)E.L[1], Lz = (float)E.L[2];
   const float zfar = (float)E.zfar, fa = (float)E.far_phi_a, fb = (float)E.far_phi_b, faz = (float)E.far_az;
   float s[2] = {0.f, 0.f}, cc[2] = {0.f, 0.f}, ax[2] = {0.f, 0.f}, ay[2] = {0.f, 0.f}, az[2] = {0.f, 0.f};
+  // absolute centres of this lane's cells (cell 64 w + 32 gg + m + 256 sl of
+  // batch (sl, gg); x is the same for all four), by the expression of the
+  // records' cell centres: each offset is then formed and wrapped in FP64
+  // exactly as the column walk does (its Newtonian part and this correction
+  // refer to the same image, and the target cell gives d = 0 exactly)
+  const int c0 = 64 * w + m;
+  const int64_t bx = 8 * (int64_t)T.bcoord[3 * b], by = 8 * (int64_t)T.bcoord[3 * b + 1],
+                bz = 8 * (int64_t)T.bcoord[3 * b + 2];
+  const double cx = centre_coord(T.org[0], bx + (c0 & 7), h);
+  const double cy0 = centre_coord(T.org[1], by + ((c0 >> 3) & 7), h);
+  const double cy1 = centre_coord(T.org[1], by + (((c0 + 32) >> 3) & 7), h);
+  const double cz0 = centre_coord(T.org[2], bz + (c0 >> 6), h);
+  const double cz1 = centre_coord(T.org[2], bz + ((c0 + 256) >> 6), h);
   const int64_t start = off[b], n = off[b + 1] - start;
   for (int64_t t0 = 0; t0 < n; t0 += WG) {
-    if (t0 + tid < n) {
-      const double4 r = rec[start + t0 + tid];
-      const int64_t own = (int64_t)ids[start + t0 + tid] - own0;
-      float4 v;
-      if (own >= 0 && own < 512) {
-        v.x = (float)(((double)(own & 7) - 3.5) * h);
-        v.y = (float)(((double)((own >> 3) & 7) - 3.5) * h);
-        v.z = (float)(((double)(own >> 6) - 3.5) * h);
-      } else {
-        v.x = (float)wrap_axis(r.x - cT[0], T.L[0], T.inv_L[0], T.per[0]);
-        v.y = (float)wrap_axis(r.y - cT[1], T.L[1], T.inv_L[1], T.per[1]);
-        v.z = (float)wrap_axis(r.z - cT[2], T.L[2], T.inv_L[2], T.per[2]);
-      }
-      v.w = (float)r.w;
-      tile[tid] = v;
-    }
+    if (t0 + tid < n) tile[tid] = rec[start + t0 + tid];
     __syncthreads();
     const int mm = (int)(n - t0 < WG ? n - t0 : WG);
     // acceleration summed per tile, then into the totals (blocked summation)
     float tx[2] = {0.f, 0.f}, ty[2] = {0.f, 0.f}, tz[2] = {0.f, 0.f};
     for (int j = 0; j < mm; ++j) {
-      const float4 r = tile[j];
-      // one batch of 32 pairs at a time (a loop, not unrolled: fewer live
+      const double4 r = tile[j];
+      const float m32 = (float)r.w;
+      // slot sl (unrolled: its accumulators are fixed registers), then one
+      // batch of 32 pairs per lane group (a loop, not unrolled: fewer live
       // registers, so the products stay in ordinary vector registers)
+#pragma unroll
+      for (int sl = 0; sl < 2; ++sl) {
 #pragma unroll 1
-      for (int bb = 0; bb < 4; ++bb) {
-        // cell of pair 32 bb + m of the wave, as the own-cell offsets above
-        const int ci = 64 * w + 32 * (bb & 1) + m + 256 * (bb >> 1);
-        float dx = (float)(((double)(ci & 7) - 3.5) * h) - r.x;
-        float dy = (float)(((double)((ci >> 3) & 7) - 3.5) * h) - r.y;
-        float dz = (float)(((double)(ci >> 6) - 3.5) * h) - r.z;
-        dx = dx - Lx * floorf(dx / Lx + 0.5f);
-        dy = dy - Ly * floorf(dy / Ly + 0.5f);
-        if (BC == 1) dz = dz - Lz * floorf(dz / Lz + 0.5f);
-        float y[4];
-        mlpinf::forward(W, mlpinf::input(fabsf(dx), fabsf(dy), fabsf(dz)), one, y);
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        const float inv = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
-        const float inv3 = inv * inv * inv;
-        // ADD: the Newtonian part is already in the outputs
-        const float nw = ADD ? 0.0f : 1.0f;
-        float ph = nw * inv + y[0];
-        float A0 = nw * dx * inv3 + (dx < 0 ? -y[1] : y[1]);
-        float A1 = nw * dy * inv3 + (dy < 0 ? -y[2] : y[2]);
-        float A2 = nw * dz * inv3 + (dz < 0 ? -y[3] : y[3]);
-        if (BC == 2 && fabsf(dz) > zfar) {
-          ph = fa * fabsf(dz) + fb - (1.0f - nw) * inv;
-          A0 = -(1.0f - nw) * dx * inv3;
-          A1 = -(1.0f - nw) * dy * inv3;
-          A2 = (dz < 0 ? -faz : faz) - (1.0f - nw) * dz * inv3;
-        }
-        const bool use = g == (bb & 1) && r2 > 0.0f;
-        // slot bb >> 1 is wave-uniform: a uniform branch, no indexed registers
-        if (bb >> 1) {
-          const float yk = r.w * ph - cc[1], tk = s[1] + yk;
-          cc[1] = use ? (tk - s[1]) - yk : cc[1];
-          s[1] = use ? tk : s[1];
-          tx[1] += use ? r.w * A0 : 0.0f;
-          ty[1] += use ? r.w * A1 : 0.0f;
-          tz[1] += use ? r.w * A2 : 0.0f;
-        } else {
-          const float yk = r.w * ph - cc[0], tk = s[0] + yk;
-          cc[0] = use ? (tk - s[0]) - yk : cc[0];
-          s[0] = use ? tk : s[0];
-          tx[0] += use ? r.w * A0 : 0.0f;
-          ty[0] += use ? r.w * A1 : 0.0f;
-          tz[0] += use ? r.w * A2 : 0.0f;
+        for (int gg = 0; gg < 2; ++gg) {
+          const double ex = wrap_axis(cx - r.x, E.L[0], E.inv_L[0], 1);
+          const double ey = wrap_axis((gg ? cy1 : cy0) - r.y, E.L[1], E.inv_L[1], 1);
+          const double ez = wrap_axis((sl ? cz1 : cz0) - r.z, E.L[2], E.inv_L[2], BC == 1);
+          const double e2 = ex * ex + ey * ey + ez * ez;
+          const float dx = (float)ex, dy = (float)ey, dz = (float)ez;
+          float y[4];
+          mlpinf::forward(W, mlpinf::input(fabsf(dx), fabsf(dy), fabsf(dz)), one, y);
+          const bool valid = e2 != 0.0;  // the target cell itself contributes nothing
+          const float inv = valid ? __builtin_amdgcn_rsqf(fmaxf((float)e2, 1e-30f)) : 0.0f;
+          const float inv3 = inv * inv * inv;
+          // ADD: the Newtonian part is already in the outputs
+          const float nw = ADD ? 0.0f : 1.0f;
+          float ph = nw * inv + y[0];
+          float A0 = nw * dx * inv3 + (dx < 0 ? -y[1] : y[1]);
+          float A1 = nw * dy * inv3 + (dy < 0 ? -y[2] : y[2]);
+          float A2 = nw * dz * inv3 + (dz < 0 ? -y[3] : y[3]);
+          if (BC == 2 && fabsf(dz) > zfar) {
+            ph = fa * fabsf(dz) + fb - (1.0f - nw) * inv;
+            A0 = -(1.0f - nw) * dx * inv3;
+            A1 = -(1.0f - nw) * dy * inv3;
+            A2 = (dz < 0 ? -faz : faz) - (1.0f - nw) * dz * inv3;
+          }
+          // lane group g owns the batch gg == g; a zero mass makes the other
+          // group's term (and the target cell's) an exact zero
+          const float mw = (g == gg && valid) ? m32 : 0.0f;
+          const float yk = mw * ph - cc[sl], tk = s[sl] + yk;
+          cc[sl] = (tk - s[sl]) - yk;
+          s[sl] = tk;
+          tx[sl] += mw * A0;
+          ty[sl] += mw * A1;
+          tz[sl] += mw * A2;
         }
       }
     }
@@ -653,18 +642,18 @@ hipError_t launch_mlp_points_eval(const void *pk, const EwaldP &E, int64_t n, co
 }
 
 hipError_t launch_eval_mlp(const DevTree &T, const EwaldP &E, const void *pk, const int64_t *off,
-                           const double4 *rec, const int32_t *ids, float *phi, float *acc, double G, bool add,
+                           const double4 *rec, float *phi, float *acc, double G, bool add,
                            hipStream_t st) {
   dim3 grid((unsigned)T.nb), blk(WG);
   const float ng = (float)(-G);
   if (E.bctype == 1 && !add)
-    hipLaunchKernelGGL((k_eval_mlp<1, false>), grid, blk, 0, st, T, E, pk, off, rec, ids, phi, acc, ng);
+    hipLaunchKernelGGL((k_eval_mlp<1, false>), grid, blk, 0, st, T, E, pk, off, rec, phi, acc, ng);
   else if (E.bctype == 2 && !add)
-    hipLaunchKernelGGL((k_eval_mlp<2, false>), grid, blk, 0, st, T, E, pk, off, rec, ids, phi, acc, ng);
+    hipLaunchKernelGGL((k_eval_mlp<2, false>), grid, blk, 0, st, T, E, pk, off, rec, phi, acc, ng);
   else if (E.bctype == 1)
-    hipLaunchKernelGGL((k_eval_mlp<1, true>), grid, blk, 0, st, T, E, pk, off, rec, ids, phi, acc, ng);
+    hipLaunchKernelGGL((k_eval_mlp<1, true>), grid, blk, 0, st, T, E, pk, off, rec, phi, acc, ng);
   else if (E.bctype == 2)
-    hipLaunchKernelGGL((k_eval_mlp<2, true>), grid, blk, 0, st, T, E, pk, off, rec, ids, phi, acc, ng);
+    hipLaunchKernelGGL((k_eval_mlp<2, true>), grid, blk, 0, st, T, E, pk, off, rec, phi, acc, ng);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -157,7 +157,6 @@ hipError_t launch_ewald_points4(int method, const EwaldP &E, double alpha, int r
 // only the correction (2P1I beyond zfar: the limit minus the Newtonian
 // part), added to phi and acc as the Newtonian column walk left them
 hipError_t launch_eval_mlp(const DevTree &T, const EwaldP &E, const void *pk, const int64_t *off,
-                           const double4 *rec, const int32_t *ids, float *phi, float *acc, double G, bool add,
-                           hipStream_t st);
+                           const double4 *rec, float *phi, float *acc, double G, bool add, hipStream_t st);
 
 }  // namespace ot
