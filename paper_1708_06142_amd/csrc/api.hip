@@ -136,6 +136,7 @@ ot::EwaldP ewald_desc(const ot_ctx *c) {
   for (int k = 0; k < 3; ++k) {
     E.L[k] = c->box[k];
     E.inv_L[k] = ot::exact_inverse(c->box[k]);
+    E.rcp_Lf[k] = (float)(1.0 / c->box[k]);
     E.step[k] = c->ew_step[k];
     E.inv_step[k] = c->ew_step[k] > 0 ? 1.0 / c->ew_step[k] : 0.0;
   }

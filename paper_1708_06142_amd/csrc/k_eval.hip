@@ -124,12 +124,15 @@ __device__ inline void pair32(const EwaldP &E, float cx, float cy, float cz, con
                               Acc32 &a) {
   float dx = cx - r.x, dy = cy - r.y, dz = cz - r.z;
   if (BC != 0) {
+    // minimum image by the FP32 reciprocal: where rounding picks the other
+    // image of a pair at |d| = L/2, the Newtonian part and the correction
+    // below both refer to it, and their sum is periodic
     const float Lx = (float)E.L[0], Ly = (float)E.L[1];
-    dx = dx - Lx * floorf(dx / Lx + 0.5f);
-    dy = dy - Ly * floorf(dy / Ly + 0.5f);
+    dx = dx - Lx * floorf(fmaf(dx, E.rcp_Lf[0], 0.5f));
+    dy = dy - Ly * floorf(fmaf(dy, E.rcp_Lf[1], 0.5f));
     if (BC == 1) {
       const float Lz = (float)E.L[2];
-      dz = dz - Lz * floorf(dz / Lz + 0.5f);
+      dz = dz - Lz * floorf(fmaf(dz, E.rcp_Lf[2], 0.5f));
     }
   }
   const float r2 = dx * dx + dy * dy + dz * dz;

@@ -26,6 +26,7 @@ struct EwaldP {
   int n;                 // table points per axis
   double L[3];           // box
   double inv_L[3];       // exact_inverse(L)
+  float rcp_Lf[3];       // 1 / L rounded to FP32 (the FP32 walks' wrap)
   double step[3];        // table spacing per axis
   double inv_step[3];
   double zfar;           // 2P1I: |dz| beyond which the analytic limit is used
