@@ -264,6 +264,12 @@ std::vector<uint8_t> bin_luts(const ot::RayTableP &RP) {
   return lut;
 }
 
+// Half-width of the lattice table (cells of a block's own size within LAT_R
+// cell sizes per axis).
+constexpr int LAT_R = 15;
+
+ot::ColP col_params(ot_ctx *c);
+
 ot_status raytable_prepare(ot_ctx *c, hipStream_t st) {
   if (c->p.nside <= 0) return fail(c, OT_ERR_STATE, "columns are off (nside = 0)");
   if (c->rt_ready) return OT_OK;
@@ -325,6 +331,11 @@ ot_status raytable_prepare(ot_ctx *c, hipStream_t st) {
       const std::vector<uint8_t> lut = bin_luts(RP);
       if (e == hipSuccess && s == OT_OK)
         e = hipMemcpyAsync(c->rt_lut.ptr, lut.data(), lut.size(), hipMemcpyHostToDevice, st);
+      // rows of the cells at lattice offsets, by the walk's own binning
+      const int64_t nlat = (2 * LAT_R + 1) * (2 * LAT_R + 1) * (2 * LAT_R + 1);
+      if (e == hipSuccess && s == OT_OK && (s = dalloc(c, c->rt_lat, nlat * sizeof(int16_t))) == OT_OK &&
+          (s = dalloc(c, c->rt_lat8, nlat * 32)) == OT_OK)
+        e = ot::launch_lattice_rows(col_params(c), LAT_R, P<int16_t>(c->rt_lat), P<uint4>(c->rt_lat8), st);
       if (e == hipSuccess) e = hipStreamSynchronize(st);
     }
   }
@@ -335,6 +346,22 @@ ot_status raytable_prepare(ot_ctx *c, hipStream_t st) {
   c->rt_pairs = total;
   c->rt_ready = true;
   return OT_OK;
+}
+
+// Every cell centre org + (i + 1/2) h is an exact double: the root size is a
+// power of two and the origin a multiple of half the finest cell size, within
+// 2^40 of them (so same-size cells lie exact multiples of h apart).
+bool dyadic_grid(const ot_ctx *c) {
+  if (!c->have_blocks) return false;
+  int ex = 0;
+  if (!(c->p.root_size > 0) || std::frexp(c->p.root_size, &ex) != 0.5) return false;
+  const double half = ot::size_at(c->p.root_size, c->topo.lmax) / 16.0;
+  for (int k = 0; k < 3; ++k) {
+    const double q = c->p.origin[k] / half;
+    if (q != std::floor(q) || std::fabs(q) > 0x1p40 || q * half != c->p.origin[k]) return false;
+    if ((double)c->p.nroot[k] * c->p.root_size / half > 0x1p40) return false;
+  }
+  return true;
 }
 
 ot::ColP col_params(ot_ctx *c) {
@@ -362,6 +389,9 @@ ot::ColP col_params(ot_ctx *c) {
   C.lut = P<uint8_t>(c->rt_lut);
   C.rows = P<uint32_t>(c->rt_rows);
   C.rows8 = P<uint4>(c->rt_rows8);
+  C.lat = P<int16_t>(c->rt_lat);
+  C.lat8 = P<uint4>(c->rt_lat8);
+  C.lat_r = c->rt_lat.ptr && dyadic_grid(c) ? LAT_R : 0;
   C.pix = P<uint16_t>(c->rt_pix);
   C.w64 = P<double>(c->rt_w64);
   C.ent = P<uint32_t>(c->rt_ent);
@@ -533,9 +563,9 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
   if (cols) {
     // maps in LDS when 128 or more cells' maps fit there, else in npix
     const ot::ColP C = col_params(c);
-    HIPCHK(ot::launch_eval_cols(fp64, T, E, C, P<int64_t>(c->loff), P<double4>(c->lrec), P<double>(c->lh), phi,
-                                acc, npix, tau, c->p.G, ot::cols_lds_cpw(C.npix, fp64, C.nthr), use_mlp,
-                                &wg_per_cu, st));
+    HIPCHK(ot::launch_eval_cols(fp64, T, E, C, P<int64_t>(c->loff), P<double4>(c->lrec), P<int32_t>(c->lid),
+                                P<double>(c->lh), phi, acc, npix, tau, c->p.G,
+                                ot::cols_lds_cpw(C.npix, fp64, C.nthr), use_mlp, &wg_per_cu, st));
     // with the surrogate: the column walk left the Newtonian part; add the correction
     if (use_mlp)
       HIPCHK(ot::launch_eval_mlp(T, E, c->mlp_pk.ptr, P<int64_t>(c->loff), P<double4>(c->lrec), (float *)phi,
@@ -1045,7 +1075,7 @@ void ot_destroy(ot_ctx *c) {
   DevBuf *all[] = {&c->alev, &c->acoord, &c->achild0, &c->aleaf, &c->blev,   &c->bcoord,
                    &c->bamr, &c->amc,    &c->aS,      &c->btmc,  &c->cm,     &c->flag,
                    &c->lcount, &c->loff, &c->lrec,    &c->lid,   &c->lscratch, &c->tab64,
-                   &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_rows, &c->rt_ent, &c->rt_rows8, &c->rt_lut,
+                   &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_rows, &c->rt_ent, &c->rt_rows8, &c->rt_lut, &c->rt_lat, &c->rt_lat8,
                    &c->rt_thr, &c->lh, &c->mlp_P, &c->mlp_pk, &c->mlp_part, &c->mlp_lossp,
                    &c->mlp_loss};
   for (DevBuf *b : all) release(c, *b);

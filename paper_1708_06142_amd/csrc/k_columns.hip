@@ -346,9 +346,10 @@ __device__ inline void grav32(const EwaldP &E, float dx, float dy, float dz, flo
 // maps are accumulated in place in npix (each thread owns its cell's column,
 // a wave's 64 cells are adjacent): for maps too large for LDS at a useful
 // occupancy (192 pixels take 768 bytes per cell in FP32).
-template <typename Real, int BC, bool NEWTON, bool GMAP>
+template <typename Real, int BC, bool NEWTON, bool GMAP, bool LATTICE = sizeof(Real) == 4 && !GMAP>
 __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, const int64_t *__restrict__ off,
-                                                   const double4 *__restrict__ rec, const double *__restrict__ lh,
+                                                   const double4 *__restrict__ rec,
+                                                   const int32_t *__restrict__ ids, const double *__restrict__ lh,
                                                    Real *__restrict__ phi, Real *__restrict__ acc,
                                                    Real *__restrict__ npix, Real *__restrict__ tau, double negG,
                                                    int cpw, int lcpw) {
@@ -375,6 +376,13 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
   const int lmap = (GMAP ? 9 : lcpw) + (sizeof(Real) == 8 ? 3 : 2);
   for (int p = 0; p < C.npix; ++p) *reinterpret_cast<Real *>(mcell + (p << lmap)) = (Real)0;
   const float inv_omega = (float)(1.0 / C.omega);
+  // cells of this block's size at lattice offsets take their table row from
+  // the lattice table (exact: the grid is dyadic when lat_r > 0, so such
+  // offsets are exact multiples of h, and the bins do not change under
+  // power-of-two scaling)
+  const int64_t cell0 = T.na + 72 * T.nb;
+  const float inv_hf = (float)(1.0 / h);
+  const int lat_w = 2 * C.lat_r + 1;
   // potential: FP64 sum (FP64 walk) or Kahan-compensated FP32 (FP32 walk)
   Real s = 0, cmp = 0, ax = 0, ay = 0, az = 0;
   const int64_t start = off[b], n = off[b + 1] - start;
@@ -388,7 +396,9 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
       tile[q].z = rq.z;
       tile[q].w = rq.w;
       tile[q].rh2 = rh * rh;
-      tile[q].rhs = (float)rh * C.lut_ps;
+      // rhs carries the lattice flag in its sign
+      const bool lat = LATTICE && C.lat_r > 0 && ids[start + t0 + q] >= cell0 && lh[start + t0 + q] == h;
+      tile[q].rhs = (lat ? -1.0f : 1.0f) * ((float)rh * C.lut_ps);
       tile[q].m = (float)rq.w;
     }
     __syncthreads();
@@ -407,10 +417,30 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
       const float r2f = (float)r2;
       const float rd = __builtin_amdgcn_rsqf(fmaxf(r2f, 1e-30f));
       const float dxf = (float)dx, dyf = (float)dy, dzf = (float)dz;
-      const int e = col ? table_row(C, thr, lut, dx, dy, dz, dxf, dyf, dzf, r2, r2f, rd, r.rh2, r.rhs) : 0;
+      // the table row e of the pair and its record (four pixels and their
+      // weights); il >= 0: e is that of lattice entry il
+      int e = 0, il = -1;
+      const char *rp;
+      if (LATTICE && r.rhs < 0.0f) {
+        // a cell of this block's size (the record is the same for the whole
+        // wave): its offset in cell sizes indexes the lattice table
+        const int li = (int)(dxf * inv_hf) + C.lat_r, lj = (int)(dyf * inv_hf) + C.lat_r,
+                  lk = (int)(dzf * inv_hf) + C.lat_r;
+        const bool in = (unsigned)li < (unsigned)lat_w && (unsigned)lj < (unsigned)lat_w &&
+                        (unsigned)lk < (unsigned)lat_w;
+        il = in && col ? (lk * lat_w + lj) * lat_w + li : -1;
+        if (__ballot(col && !in)) {
+          if (col && !in) e = table_row(C, thr, lut, dx, dy, dz, dxf, dyf, dzf, r2, r2f, rd, r.rh2, -r.rhs);
+        }
+        rp = il >= 0 ? reinterpret_cast<const char *>(C.lat8) + (uint32_t)il * 32u
+                     : reinterpret_cast<const char *>(C.rows8) + (uint32_t)e * 32u;
+      } else {
+        if (col) e = table_row(C, thr, lut, dx, dy, dz, dxf, dyf, dzf, r2, r2f, rd, r.rh2, fabsf(r.rhs));
+        rp = reinterpret_cast<const char *>(C.rows8) + (uint32_t)e * 32u;
+      }
       if (sizeof(Real) == 8) {
         if (!valid) continue;
-        const uint32_t hd = C.rows[e];
+        const uint32_t hd = C.rows[il >= 0 ? (int)C.lat[il] : e];
         const int o0 = (int)(hd >> 6), cnt = col ? (int)(hd & 63) : 0;
         double ph, A0, A1, A2;
         grav64<BC>(E, dx, dy, dz, r2, ph, A0, A1, A2);
@@ -441,7 +471,6 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         // read-modify-writes are independent; the column is the thread's own
         // (plain read-modify-write: LDS atomic adds measured 2.5x slower)
         const float base = col ? m32 * inv_omega * (rd * rd) : 0.0f;
-        const char *const rp = reinterpret_cast<const char *>(C.rows8) + (uint32_t)e * 32u;
         const uint4 pq = *reinterpret_cast<const uint4 *>(rp), wq = *reinterpret_cast<const uint4 *>(rp + 16);
         // bit 31 of the first pixel (more than four) is shifted out here
         float *const q0 = reinterpret_cast<float *>(mcell + (pq.x << lmap));
@@ -468,7 +497,7 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
           *q3 = fmaf(__uint_as_float(wq.w), base, v3);
         }
         if ((int)pq.x < 0 && col) {
-          const uint32_t hd = C.rows[e];
+          const uint32_t hd = C.rows[il >= 0 ? (int)C.lat[il] : e];
           const int o0 = (int)(hd >> 6), cnt = (int)(hd & 63);
           const float base24 = base * (1.0f / 16777216.0f);
           for (int o = o0 + 4; o < o0 + cnt; ++o) {
@@ -522,6 +551,35 @@ __global__ __launch_bounds__(256) void k_column_bins(ColP C, int64_t n, const do
   if (in) row[i] = e;
 }
 
+// table rows of the lattice offsets d = (i, j, k) (in cell sizes, node size
+// 1): the walk's own binning; -1 at the origin
+__global__ __launch_bounds__(256) void k_lattice_rows(ColP C, int R, int16_t *__restrict__ out,
+                                                      uint4 *__restrict__ out8) {
+  __shared__ uint8_t lut[LUT_BYTES];
+  extern __shared__ __align__(16) unsigned char smem[];
+  double *thr = reinterpret_cast<double *>(smem);
+  for (int q = threadIdx.x; q < LUT_BYTES; q += 256) lut[q] = C.lut[q];
+  for (int q = threadIdx.x; q < C.nthr; q += 256) thr[q] = C.thr[q];
+  __syncthreads();
+  const int W = 2 * R + 1;
+  const int n = W * W * W;
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int tt = t < n ? t : 0;
+  const double dz = (double)(tt / (W * W) - R), dy = (double)((tt / W) % W - R), dx = (double)(tt % W - R);
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const float r2f = (float)r2;
+  const float rd = __builtin_amdgcn_rsqf(fmaxf(r2f, 1e-30f));
+  const double rh = C.req;
+  const int e = r2 != 0.0 ? table_row(C, thr, lut, dx, dy, dz, (float)dx, (float)dy, (float)dz, r2, r2f, rd,
+                                      rh * rh, (float)rh * C.lut_ps)
+                          : -1;
+  if (t < n) {
+    out[t] = (int16_t)e;
+    out8[2 * t] = e >= 0 ? C.rows8[2 * e] : make_uint4(0, 1, 2, 3);
+    out8[2 * t + 1] = e >= 0 ? C.rows8[2 * e + 1] : make_uint4(0, 0, 0, 0);
+  }
+}
+
 // packed rows for the walk: head = offset << 6 | count; entry = pixel << 24 |
 // round(w 2^24) (w <= 1, clamped to 2^24 - 1); rows8 = the first four pixels
 // and their FP32 weights, padded with the lowest pixels the row does not use
@@ -573,6 +631,13 @@ hipError_t launch_column_bins(const ColP &C, int64_t n, const double *d, const d
   return hipGetLastError();
 }
 
+hipError_t launch_lattice_rows(const ColP &C, int R, int16_t *lat, uint4 *lat8, hipStream_t st) {
+  const int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
+  hipLaunchKernelGGL(k_lattice_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), C.nthr * sizeof(double), st, C,
+                     R, lat, lat8);
+  return hipGetLastError();
+}
+
 hipError_t launch_raytable(const RayTableP &P, double *dense, int32_t *cnt, int64_t *off, uint16_t *pix,
                            double *w64, int64_t *total, hipStream_t st) {
   hipLaunchKernelGGL(k_raytable_dense, dim3((unsigned)P.nentries), dim3(64), 0, st, P, dense);
@@ -611,8 +676,9 @@ hipError_t launch_raytable_pack(const RayTableP &P, const int64_t *off, const ui
 }
 
 hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const ColP &C, const int64_t *off,
-                            const double4 *rec, const double *lh, void *phi, void *acc, void *npix, void *tau,
-                            double G, int cpw, bool newton_only, int *wg_per_cu, hipStream_t st) {
+                            const double4 *rec, const int32_t *ids, const double *lh, void *phi, void *acc,
+                            void *npix, void *tau, double G, int cpw, bool newton_only, int *wg_per_cu,
+                            hipStream_t st) {
   const bool gmap = cpw == 0;
   if (gmap) cpw = 256;
   // dynamic LDS: the thresholds, and the maps unless they are in npix
@@ -632,7 +698,7 @@ hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const 
     if (wg_per_cu && hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, k_eval_cols<R, B, N, M>, cpw,   \
                                                                   sm) != hipSuccess)                          \
       *wg_per_cu = 0;                                                                                         \
-    hipLaunchKernelGGL((k_eval_cols<R, B, N, M>), grid, blk, sm, st, T, E, C, off, rec, lh, (R *)phi,        \
+    hipLaunchKernelGGL((k_eval_cols<R, B, N, M>), grid, blk, sm, st, T, E, C, off, rec, ids, lh, (R *)phi,   \
                        (R *)acc, (R *)npix, (R *)tau, -G, cpw, lcpw);                                        \
   } while (0)
 #define OT_LAUNCH(R, B, N)          \

@@ -62,6 +62,9 @@ struct ColP {
   const uint32_t *rows;    // [nentries] offset << 6 | count
   const uint4 *rows8;      // [nentries][2]: four pixels (bit 31 of the first: more
                            // than four), their four FP32 weights (zero past count)
+  const int16_t *lat;      // [(2 lat_r + 1)^3] table row of a cell at a lattice offset
+  const uint4 *lat8;       // [(2 lat_r + 1)^3][2] its rows8 record
+  int lat_r;               // half-width of the lattice table; 0: not used (grid not dyadic)
   const uint16_t *pix;     // [npairs] FP64 walk
   const double *w64;       // [npairs]
   const uint32_t *ent;     // [npairs] FP32 walk: pixel << 24 | unorm24 weight
@@ -89,8 +92,13 @@ hipError_t launch_column_bins(const ColP &C, int64_t n, const double *d, const d
 // cpw: cols_lds_cpw (0: maps in npix);
 // wg_per_cu (may be null): workgroups of the launched kernel resident per CU
 hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const ColP &C, const int64_t *off,
-                            const double4 *rec, const double *lh, void *phi, void *acc, void *npix, void *tau,
-                            double G, int cpw, bool newton_only, int *wg_per_cu, hipStream_t st);
+                            const double4 *rec, const int32_t *ids, const double *lh, void *phi, void *acc,
+                            void *npix, void *tau, double G, int cpw, bool newton_only, int *wg_per_cu,
+                            hipStream_t st);
+// table rows of the offsets (i, j, k) cell sizes between two cells of one size,
+// |i|, |j|, |k| <= R, into lat [(2R + 1)^3] (k slowest, i fastest; -1 at the
+// origin) and their rows8 records into lat8 [(2R + 1)^3][2] (zero at the origin)
+hipError_t launch_lattice_rows(const ColP &C, int R, int16_t *lat, uint4 *lat8, hipStream_t st);
 
 hipError_t launch_build(const DevTree &T, const double *rho, int *bad,
                         const std::vector<int64_t> &level_begin, int lmax, hipStream_t st);
