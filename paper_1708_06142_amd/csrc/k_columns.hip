@@ -407,58 +407,97 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
     // (blocked summation: the rounding grows with the tile and tile count,
     // not with the list length)
     Real tx = 0, ty = 0, tz = 0;
-    for (int j = 0; j < m; ++j) {
-      const ColRec r = tile[j];
-      double dx = cx - r.x, dy = cy - r.y, dz = cz - r.z;
-      wrap3<BC>(E, dx, dy, dz);
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      const bool valid = r2 != 0.0;  // the target cell itself contributes nothing
-      const bool col = valid && r2 <= C.max_dist2;
-      const float r2f = (float)r2;
-      const float rd = __builtin_amdgcn_rsqf(fmaxf(r2f, 1e-30f));
-      const float dxf = (float)dx, dyf = (float)dy, dzf = (float)dz;
-      // the table row e of the pair and its record (four pixels and their
-      // weights); il >= 0: e is that of lattice entry il
-      int e = 0, il = -1;
-      const char *rp;
+    // offsets of a pair (minimum image, FP64) and their FP32 copies
+    struct Geo {
+      double dx, dy, dz, r2;
+      float r2f, rd, dxf, dyf, dzf;
+      bool valid, col;
+    };
+    auto geometry = [&](const ColRec &r) {
+      Geo q;
+      q.dx = cx - r.x;
+      q.dy = cy - r.y;
+      q.dz = cz - r.z;
+      wrap3<BC>(E, q.dx, q.dy, q.dz);
+      q.r2 = q.dx * q.dx + q.dy * q.dy + q.dz * q.dz;
+      q.valid = q.r2 != 0.0;  // the target cell itself contributes nothing
+      q.col = q.valid && q.r2 <= C.max_dist2;
+      q.r2f = (float)q.r2;
+      q.rd = __builtin_amdgcn_rsqf(fmaxf(q.r2f, 1e-30f));
+      q.dxf = (float)q.dx;
+      q.dyf = (float)q.dy;
+      q.dzf = (float)q.dz;
+      return q;
+    };
+    // the table row e of a pair and the address of its record (four pixels
+    // and their weights); il >= 0: e is that of lattice entry il
+    auto row_of = [&](const ColRec &r, const Geo &q, int &e, int &il) {
+      e = 0;
+      il = -1;
       if (LATTICE && r.rhs < 0.0f) {
         // a cell of this block's size (the record is the same for the whole
         // wave): its offset in cell sizes indexes the lattice table
-        const int li = (int)(dxf * inv_hf) + C.lat_r, lj = (int)(dyf * inv_hf) + C.lat_r,
-                  lk = (int)(dzf * inv_hf) + C.lat_r;
+        const int li = (int)(q.dxf * inv_hf) + C.lat_r, lj = (int)(q.dyf * inv_hf) + C.lat_r,
+                  lk = (int)(q.dzf * inv_hf) + C.lat_r;
         const bool in = (unsigned)li < (unsigned)lat_w && (unsigned)lj < (unsigned)lat_w &&
                         (unsigned)lk < (unsigned)lat_w;
-        il = in && col ? (lk * lat_w + lj) * lat_w + li : -1;
-        if (__ballot(col && !in)) {
-          if (col && !in) e = table_row(C, thr, lut, dx, dy, dz, dxf, dyf, dzf, r2, r2f, rd, r.rh2, -r.rhs);
+        il = in && q.col ? (lk * lat_w + lj) * lat_w + li : -1;
+        if (__ballot(q.col && !in)) {
+          if (q.col && !in)
+            e = table_row(C, thr, lut, q.dx, q.dy, q.dz, q.dxf, q.dyf, q.dzf, q.r2, q.r2f, q.rd, r.rh2, -r.rhs);
         }
-        rp = il >= 0 ? reinterpret_cast<const char *>(C.lat8) + (uint32_t)il * 32u
-                     : reinterpret_cast<const char *>(C.rows8) + (uint32_t)e * 32u;
-      } else {
-        if (col) e = table_row(C, thr, lut, dx, dy, dz, dxf, dyf, dzf, r2, r2f, rd, r.rh2, fabsf(r.rhs));
-        rp = reinterpret_cast<const char *>(C.rows8) + (uint32_t)e * 32u;
+        return il >= 0 ? reinterpret_cast<const char *>(C.lat8) + (uint32_t)il * 32u
+                       : reinterpret_cast<const char *>(C.rows8) + (uint32_t)e * 32u;
       }
-      if (sizeof(Real) == 8) {
-        if (!valid) continue;
+      if (q.col)
+        e = table_row(C, thr, lut, q.dx, q.dy, q.dz, q.dxf, q.dyf, q.dzf, q.r2, q.r2f, q.rd, r.rh2, fabsf(r.rhs));
+      return reinterpret_cast<const char *>(C.rows8) + (uint32_t)e * 32u;
+    };
+    if (sizeof(Real) == 8) {
+      for (int j = 0; j < m; ++j) {
+        const ColRec r = tile[j];
+        const Geo q = geometry(r);
+        int e, il;
+        (void)row_of(r, q, e, il);
+        if (!q.valid) continue;
         const uint32_t hd = C.rows[il >= 0 ? (int)C.lat[il] : e];
-        const int o0 = (int)(hd >> 6), cnt = col ? (int)(hd & 63) : 0;
+        const int o0 = (int)(hd >> 6), cnt = q.col ? (int)(hd & 63) : 0;
         double ph, A0, A1, A2;
-        grav64<BC>(E, dx, dy, dz, r2, ph, A0, A1, A2);
+        grav64<BC>(E, q.dx, q.dy, q.dz, q.r2, ph, A0, A1, A2);
         s += (Real)(r.w * ph);
         tx += (Real)(r.w * A0);
         ty += (Real)(r.w * A1);
         tz += (Real)(r.w * A2);
-        const double base = r.w / (C.omega * r2);
+        const double base = r.w / (C.omega * q.r2);
         for (int o = o0; o < o0 + cnt; ++o)
           *reinterpret_cast<Real *>(mcell + ((uint32_t)C.pix[o] << lmap)) += (Real)(C.w64[o] * base);
-      } else {
+      }
+    } else {
+      // With LDS maps, a two-stage pipeline over the tile: stage A of pair
+      // j + 1 (offsets, gravity, bins, and the load of its row record) runs
+      // before stage B of pair j (the map update), so each record load is in
+      // flight while the next pair's bins are computed.  Both stages keep
+      // list order, so the sums are those of the plain loop.
+      struct Pend {
+        uint4 pq, wq;
+        float base;
+        int e, il;
+        bool col;
+      };
+      auto stage_a = [&](int jj) {
+        const ColRec r = tile[jj];
+        const Geo q = geometry(r);
+        Pend p;
+        const char *rp = row_of(r, q, p.e, p.il);
+        p.pq = *reinterpret_cast<const uint4 *>(rp);
+        p.wq = *reinterpret_cast<const uint4 *>(rp + 16);
         // FP32 gravity from the FP64 offset (already the minimum image)
-        const float inv = valid ? rd : 0.0f;
+        const float inv = q.valid ? q.rd : 0.0f;
         float ph, A0, A1, A2;
-        grav32<BC, NEWTON>(E, dxf, dyf, dzf, inv, ph, A0, A1, A2);
+        grav32<BC, NEWTON>(E, q.dxf, q.dyf, q.dzf, inv, ph, A0, A1, A2);
         // the target cell's term is an exact zero (a Kahan step with it only
         // moves the compensation into the sum)
-        const float m32 = valid ? r.m : 0.0f;
+        const float m32 = q.valid ? r.m : 0.0f;
         const float y = m32 * ph - (float)cmp;
         const float tt = (float)s + y;
         cmp = (Real)((tt - (float)s) - y);
@@ -466,12 +505,18 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         tx += (Real)(m32 * A0);
         ty += (Real)(m32 * A1);
         tz += (Real)(m32 * A2);
-        // N_p += w M / (Omega d^2) over the row's pixels: four of them come
-        // with the row (distinct pixels, weight 0 past the count), so the four
-        // read-modify-writes are independent; the column is the thread's own
-        // (plain read-modify-write: LDS atomic adds measured 2.5x slower)
-        const float base = col ? m32 * inv_omega * (rd * rd) : 0.0f;
-        const uint4 pq = *reinterpret_cast<const uint4 *>(rp), wq = *reinterpret_cast<const uint4 *>(rp + 16);
+        // N_p += w M / (Omega d^2): the weight base of the pair
+        p.base = q.col ? m32 * inv_omega * (q.rd * q.rd) : 0.0f;
+        p.col = q.col;
+        return p;
+      };
+      // four of the row's pixels come with its record (distinct pixels,
+      // weight 0 past the count), so the four read-modify-writes are
+      // independent; the column is the thread's own (plain read-modify-write:
+      // LDS atomic adds measured 2.5x slower)
+      auto stage_b = [&](const Pend &p) {
+        const float base = p.base;
+        const uint4 pq = p.pq, wq = p.wq;
         // bit 31 of the first pixel (more than four) is shifted out here
         float *const q0 = reinterpret_cast<float *>(mcell + (pq.x << lmap));
         float *const q1 = reinterpret_cast<float *>(mcell + (pq.y << lmap));
@@ -496,8 +541,8 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
           *q2 = fmaf(__uint_as_float(wq.z), base, v2);
           *q3 = fmaf(__uint_as_float(wq.w), base, v3);
         }
-        if ((int)pq.x < 0 && col) {
-          const uint32_t hd = C.rows[il >= 0 ? (int)C.lat[il] : e];
+        if ((int)pq.x < 0 && p.col) {
+          const uint32_t hd = C.rows[p.il >= 0 ? (int)C.lat[p.il] : p.e];
           const int o0 = (int)(hd >> 6), cnt = (int)(hd & 63);
           const float base24 = base * (1.0f / 16777216.0f);
           for (int o = o0 + 4; o < o0 + cnt; ++o) {
@@ -505,6 +550,19 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
             float *const qv = reinterpret_cast<float *>(mcell + ((v >> 24) << lmap));
             *qv += (float)(v & 0xffffffu) * base24;
           }
+        }
+      };
+      if (GMAP) {
+        // maps in memory: no pipeline (its registers would cost occupancy,
+        // and this walk waits on the map traffic rather than on the records)
+        for (int j = 0; j < m; ++j) stage_b(stage_a(j));
+      } else {
+        Pend cur = stage_a(0);
+        for (int j = 0; j < m; ++j) {
+          Pend nxt = cur;
+          if (j + 1 < m) nxt = stage_a(j + 1);
+          stage_b(cur);
+          cur = nxt;
         }
       }
     }
