@@ -557,12 +557,16 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         // and this walk waits on the map traffic rather than on the records)
         for (int j = 0; j < m; ++j) stage_b(stage_a(j));
       } else {
-        Pend cur = stage_a(0);
-        for (int j = 0; j < m; ++j) {
-          Pend nxt = cur;
-          if (j + 1 < m) nxt = stage_a(j + 1);
-          stage_b(cur);
-          cur = nxt;
+        // unrolled by two with the pending state in alternating registers
+        // (no copy of the state between iterations)
+        Pend p0 = stage_a(0), p1;
+        for (int j = 0; j < m; j += 2) {
+          if (j + 1 < m) p1 = stage_a(j + 1);
+          stage_b(p0);
+          if (j + 1 < m) {
+            if (j + 2 < m) p0 = stage_a(j + 2);
+            stage_b(p1);
+          }
         }
       }
     }
