@@ -152,21 +152,21 @@ __global__ void k_raytable_fill(RayTableP P, const double *__restrict__ dense, c
 
 // ------------------------------------------------------------- column walk
 // a list record in the LDS tile: centre of mass and mass, (R_eq h)^2, and
-// R_eq h (times the psi table's scale) and the mass in FP32
+// R_eq h (times the psi table's scale) and the mass in FP32.  A record of the
+// lattice table (negative rhs) holds, in place of (R_eq h)^2, its entry for
+// the block's first cell; a cell's entry adds the cell's own lattice index.
 struct __align__(16) ColRec {
   double x, y, z, w;
-  double rh2;
+  union {
+    double rh2;
+    int lat;
+  };
   float rhs, m;
 };
 
 // list records per LDS tile (small: the maps need the LDS; with 48-pixel
 // FP32 maps of 256 cells three workgroups then fit in a compute unit's LDS)
 constexpr int TILE = 60;
-
-template <typename Real>
-struct ColAcc {
-  Real s, c, ax, ay, az;
-};
 
 // Largest k in [0, n-1] with pred(k), pred monotone (true up to some k) and
 // pred(0) taken as true; branch-free binary search for n <= 64.
@@ -376,13 +376,29 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
   const int lmap = (GMAP ? 9 : lcpw) + (sizeof(Real) == 8 ? 3 : 2);
   for (int p = 0; p < C.npix; ++p) *reinterpret_cast<Real *>(mcell + (p << lmap)) = (Real)0;
   const float inv_omega = (float)(1.0 / C.omega);
-  // cells of this block's size at lattice offsets take their table row from
+  // Cells of this block's size at lattice offsets take their table row from
   // the lattice table (exact: the grid is dyadic when lat_r > 0, so such
   // offsets are exact multiples of h, and the bins do not change under
-  // power-of-two scaling)
+  // power-of-two scaling).  A record qualifies when the offsets of all 512
+  // cells of the block lie in the table and no periodic image is involved;
+  // the entry of cell (i, j, k) is then the record's entry for cell 0 plus
+  // (k W + j) W + i.
   const int64_t cell0 = T.na + 72 * T.nb;
-  const float inv_hf = (float)(1.0 / h);
   const int lat_w = 2 * C.lat_r + 1;
+  const int lat_lane = ((ci >> 6) * lat_w + ((ci >> 3) & 7)) * lat_w + (ci & 7);
+  const double inv_h = 1.0 / h;  // exact: h is a power of two on a dyadic grid
+  const double bx0 = centre_coord(T.org[0], 8 * (int64_t)T.bcoord[3 * b], h);
+  const double by0 = centre_coord(T.org[1], 8 * (int64_t)T.bcoord[3 * b + 1], h);
+  const double bz0 = centre_coord(T.org[2], 8 * (int64_t)T.bcoord[3 * b + 2], h);
+  // lattice offset (in cells) of a node from the block's first cell, or a
+  // value outside [-lat_r, lat_r - 7] if the block's offsets leave the table
+  // or may wrap on a periodic axis
+  auto lat_axis = [&](double d0, int ax) {
+    const bool per = BC == 1 || (BC == 2 && ax < 2);
+    if (per && !(d0 > -0.5 * E.L[ax] + h && d0 + 8.0 * h < 0.5 * E.L[ax])) return 1 << 20;
+    const double n0 = d0 * inv_h;
+    return fabs(n0) < (double)(1 << 20) && n0 == rint(n0) ? (int)n0 : 1 << 20;
+  };
   // potential: FP64 sum (FP64 walk) or Kahan-compensated FP32 (FP32 walk)
   Real s = 0, cmp = 0, ax = 0, ay = 0, az = 0;
   const int64_t start = off[b], n = off[b + 1] - start;
@@ -395,9 +411,15 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
       tile[q].y = rq.y;
       tile[q].z = rq.z;
       tile[q].w = rq.w;
-      tile[q].rh2 = rh * rh;
       // rhs carries the lattice flag in its sign
-      const bool lat = LATTICE && C.lat_r > 0 && ids[start + t0 + q] >= cell0 && lh[start + t0 + q] == h;
+      bool lat = LATTICE && C.lat_r > 0 && ids[start + t0 + q] >= cell0 && lh[start + t0 + q] == h;
+      if (lat) {
+        const int nx = lat_axis(bx0 - rq.x, 0), ny = lat_axis(by0 - rq.y, 1), nz = lat_axis(bz0 - rq.z, 2);
+        const int lo = -C.lat_r, hi = C.lat_r - 7;
+        lat = nx >= lo && nx <= hi && ny >= lo && ny <= hi && nz >= lo && nz <= hi;
+        if (lat) tile[q].lat = ((nz + C.lat_r) * lat_w + (ny + C.lat_r)) * lat_w + (nx + C.lat_r);
+      }
+      if (!lat) tile[q].rh2 = rh * rh;
       tile[q].rhs = (lat ? -1.0f : 1.0f) * ((float)rh * C.lut_ps);
       tile[q].m = (float)rq.w;
     }
@@ -435,19 +457,11 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
       e = 0;
       il = -1;
       if (LATTICE && r.rhs < 0.0f) {
-        // a cell of this block's size (the record is the same for the whole
-        // wave): its offset in cell sizes indexes the lattice table
-        const int li = (int)(q.dxf * inv_hf) + C.lat_r, lj = (int)(q.dyf * inv_hf) + C.lat_r,
-                  lk = (int)(q.dzf * inv_hf) + C.lat_r;
-        const bool in = (unsigned)li < (unsigned)lat_w && (unsigned)lj < (unsigned)lat_w &&
-                        (unsigned)lk < (unsigned)lat_w;
-        il = in && q.col ? (lk * lat_w + lj) * lat_w + li : -1;
-        if (__ballot(q.col && !in)) {
-          if (q.col && !in)
-            e = table_row(C, thr, lut, q.dx, q.dy, q.dz, q.dxf, q.dyf, q.dzf, q.r2, q.r2f, q.rd, r.rh2, -r.rhs);
-        }
-        return il >= 0 ? reinterpret_cast<const char *>(C.lat8) + (uint32_t)il * 32u
-                       : reinterpret_cast<const char *>(C.rows8) + (uint32_t)e * 32u;
+        // a cell of this block's size, in the lattice table for every cell of
+        // the block (the record is the same for the whole wave); outside the
+        // column radius and at the origin the pair's weight base is zero
+        il = r.lat + lat_lane;
+        return reinterpret_cast<const char *>(C.lat8) + (uint32_t)il * 32u;
       }
       if (q.col)
         e = table_row(C, thr, lut, q.dx, q.dy, q.dz, q.dxf, q.dyf, q.dzf, q.r2, q.r2f, q.rd, r.rh2, fabsf(r.rhs));
@@ -460,7 +474,7 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         int e, il;
         (void)row_of(r, q, e, il);
         if (!q.valid) continue;
-        const uint32_t hd = C.rows[il >= 0 ? (int)C.lat[il] : e];
+        const uint32_t hd = C.rows[il >= 0 && q.col ? (int)C.lat[il] : e];
         const int o0 = (int)(hd >> 6), cnt = q.col ? (int)(hd & 63) : 0;
         double ph, A0, A1, A2;
         grav64<BC>(E, q.dx, q.dy, q.dz, q.r2, ph, A0, A1, A2);
