@@ -290,9 +290,11 @@ ot_status raytable_prepare(ot_ctx *c, hipStream_t st) {
   if (s == OT_OK && e == hipSuccess) {
     s = dalloc(c, c->rt_pix, (size_t)total * sizeof(uint16_t));
     if (s == OT_OK) s = dalloc(c, c->rt_w64, (size_t)total * sizeof(double));
-    if (s == OT_OK) s = dalloc(c, c->rt_rows, (size_t)RP.nentries * sizeof(uint32_t));
+    // the rows of the cells at lattice offsets follow the table's own rows
+    const int64_t nlat = (2 * LAT_R + 1) * (2 * LAT_R + 1) * (2 * LAT_R + 1);
+    if (s == OT_OK) s = dalloc(c, c->rt_rows, (size_t)(RP.nentries + nlat) * sizeof(uint32_t));
     if (s == OT_OK) s = dalloc(c, c->rt_ent, (size_t)total * sizeof(uint32_t));
-    if (s == OT_OK) s = dalloc(c, c->rt_rows8, (size_t)RP.nentries * 32);
+    if (s == OT_OK) s = dalloc(c, c->rt_rows8, (size_t)(RP.nentries + nlat) * 32);
     if (s == OT_OK) s = dalloc(c, c->rt_lut, ot::LUT_BYTES);
     if (s == OT_OK && total >= ((int64_t)1 << 26)) s = fail(c, OT_ERR_UNSUPPORTED, "node-ray table too large");
     if (s == OT_OK) {
@@ -335,10 +337,8 @@ ot_status raytable_prepare(ot_ctx *c, hipStream_t st) {
       if (e == hipSuccess && s == OT_OK)
         e = hipMemcpyAsync(c->rt_lut.ptr, lut.data(), lut.size(), hipMemcpyHostToDevice, st);
       // rows of the cells at lattice offsets, by the walk's own binning
-      const int64_t nlat = (2 * LAT_R + 1) * (2 * LAT_R + 1) * (2 * LAT_R + 1);
-      if (e == hipSuccess && s == OT_OK && (s = dalloc(c, c->rt_lat, nlat * sizeof(int16_t))) == OT_OK &&
-          (s = dalloc(c, c->rt_lat8, nlat * 32)) == OT_OK)
-        e = ot::launch_lattice_rows(col_params(c), LAT_R, P<int16_t>(c->rt_lat), P<uint4>(c->rt_lat8), st);
+      if (e == hipSuccess && s == OT_OK)
+        e = ot::launch_lattice_rows(col_params(c), LAT_R, P<uint32_t>(c->rt_rows), P<uint4>(c->rt_rows8), st);
       if (e == hipSuccess) e = hipStreamSynchronize(st);
     }
   }
@@ -392,9 +392,8 @@ ot::ColP col_params(ot_ctx *c) {
   C.lut = P<uint8_t>(c->rt_lut);
   C.rows = P<uint32_t>(c->rt_rows);
   C.rows8 = P<uint4>(c->rt_rows8);
-  C.lat = P<int16_t>(c->rt_lat);
-  C.lat8 = P<uint4>(c->rt_lat8);
-  C.lat_r = c->rt_lat.ptr && dyadic_grid(c) ? LAT_R : 0;
+  C.lat0 = (int)RP.nentries;
+  C.lat_r = c->rt_ready && dyadic_grid(c) ? LAT_R : 0;
   C.pix = P<uint16_t>(c->rt_pix);
   C.w64 = P<double>(c->rt_w64);
   C.ent = P<uint32_t>(c->rt_ent);
@@ -1078,7 +1077,7 @@ void ot_destroy(ot_ctx *c) {
   DevBuf *all[] = {&c->alev, &c->acoord, &c->achild0, &c->aleaf, &c->blev,   &c->bcoord,
                    &c->bamr, &c->amc,    &c->aS,      &c->btmc,  &c->cm,     &c->flag,
                    &c->lcount, &c->loff, &c->lrec,    &c->lid,   &c->lscratch, &c->tab64,
-                   &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_rows, &c->rt_ent, &c->rt_rows8, &c->rt_lut, &c->rt_lat, &c->rt_lat8,
+                   &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_rows, &c->rt_ent, &c->rt_rows8, &c->rt_lut,
                    &c->rt_thr, &c->lh, &c->mlp_P, &c->mlp_pk, &c->mlp_part, &c->mlp_lossp,
                    &c->mlp_loss};
   for (DevBuf *b : all) release(c, *b);

@@ -417,7 +417,7 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         const int nx = lat_axis(bx0 - rq.x, 0), ny = lat_axis(by0 - rq.y, 1), nz = lat_axis(bz0 - rq.z, 2);
         const int lo = -C.lat_r, hi = C.lat_r - 7;
         lat = nx >= lo && nx <= hi && ny >= lo && ny <= hi && nz >= lo && nz <= hi;
-        if (lat) tile[q].lat = ((nz + C.lat_r) * lat_w + (ny + C.lat_r)) * lat_w + (nx + C.lat_r);
+        if (lat) tile[q].lat = C.lat0 + ((nz + C.lat_r) * lat_w + (ny + C.lat_r)) * lat_w + (nx + C.lat_r);
       }
       if (!lat) tile[q].rh2 = rh * rh;
       tile[q].rhs = (lat ? -1.0f : 1.0f) * ((float)rh * C.lut_ps);
@@ -451,30 +451,23 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
       q.dzf = (float)q.dz;
       return q;
     };
-    // the table row e of a pair and the address of its record (four pixels
-    // and their weights); il >= 0: e is that of lattice entry il
-    auto row_of = [&](const ColRec &r, const Geo &q, int &e, int &il) {
-      e = 0;
-      il = -1;
-      if (LATTICE && r.rhs < 0.0f) {
-        // a cell of this block's size, in the lattice table for every cell of
-        // the block (the record is the same for the whole wave); outside the
-        // column radius and at the origin the pair's weight base is zero
-        il = r.lat + lat_lane;
-        return reinterpret_cast<const char *>(C.lat8) + (uint32_t)il * 32u;
-      }
-      if (q.col)
-        e = table_row(C, thr, lut, q.dx, q.dy, q.dz, q.dxf, q.dyf, q.dzf, q.r2, q.r2f, q.rd, r.rh2, fabsf(r.rhs));
-      return reinterpret_cast<const char *>(C.rows8) + (uint32_t)e * 32u;
+    // the row of a pair in the node-ray table (0 outside the column radius,
+    // where the pair's weight base is zero)
+    auto row_of = [&](const ColRec &r, const Geo &q) {
+      // a cell of this block's size, in the lattice rows for every cell of
+      // the block (the record is the same for the whole wave)
+      if (LATTICE && r.rhs < 0.0f) return r.lat + lat_lane;
+      return q.col ? table_row(C, thr, lut, q.dx, q.dy, q.dz, q.dxf, q.dyf, q.dzf, q.r2, q.r2f, q.rd, r.rh2,
+                               fabsf(r.rhs))
+                   : 0;
     };
     if (sizeof(Real) == 8) {
       for (int j = 0; j < m; ++j) {
         const ColRec r = tile[j];
         const Geo q = geometry(r);
-        int e, il;
-        (void)row_of(r, q, e, il);
+        const int e = row_of(r, q);
         if (!q.valid) continue;
-        const uint32_t hd = C.rows[il >= 0 && q.col ? (int)C.lat[il] : e];
+        const uint32_t hd = C.rows[e];
         const int o0 = (int)(hd >> 6), cnt = q.col ? (int)(hd & 63) : 0;
         double ph, A0, A1, A2;
         grav64<BC>(E, q.dx, q.dy, q.dz, q.r2, ph, A0, A1, A2);
@@ -495,16 +488,16 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
       struct Pend {
         uint4 pq, wq;
         float base;
-        int e, il;
+        int e;
         bool col;
       };
       auto stage_a = [&](int jj) {
         const ColRec r = tile[jj];
         const Geo q = geometry(r);
         Pend p;
-        const char *rp = row_of(r, q, p.e, p.il);
-        p.pq = *reinterpret_cast<const uint4 *>(rp);
-        p.wq = *reinterpret_cast<const uint4 *>(rp + 16);
+        p.e = row_of(r, q);
+        p.pq = C.rows8[2 * (uint32_t)p.e];
+        p.wq = C.rows8[2 * (uint32_t)p.e + 1];
         // FP32 gravity from the FP64 offset (already the minimum image)
         const float inv = q.valid ? q.rd : 0.0f;
         float ph, A0, A1, A2;
@@ -556,7 +549,7 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
           *q3 = fmaf(__uint_as_float(wq.w), base, v3);
         }
         if ((int)pq.x < 0 && p.col) {
-          const uint32_t hd = C.rows[p.il >= 0 ? (int)C.lat[p.il] : p.e];
+          const uint32_t hd = C.rows[p.e];
           const int o0 = (int)(hd >> 6), cnt = (int)(hd & 63);
           const float base24 = base * (1.0f / 16777216.0f);
           for (int o = o0 + 4; o < o0 + cnt; ++o) {
@@ -627,9 +620,10 @@ __global__ __launch_bounds__(256) void k_column_bins(ColP C, int64_t n, const do
   if (in) row[i] = e;
 }
 
-// table rows of the lattice offsets d = (i, j, k) (in cell sizes, node size
-// 1): the walk's own binning; -1 at the origin
-__global__ __launch_bounds__(256) void k_lattice_rows(ColP C, int R, int16_t *__restrict__ out,
+// rows of the lattice offsets d = (i, j, k) (in cell sizes, node size 1),
+// copied from the table row that the walk's own binning gives (head and
+// packed record); the origin gets an empty row
+__global__ __launch_bounds__(256) void k_lattice_rows(ColP C, int R, uint32_t *__restrict__ out,
                                                       uint4 *__restrict__ out8) {
   __shared__ uint8_t lut[LUT_BYTES];
   extern __shared__ __align__(16) unsigned char smem[];
@@ -650,7 +644,7 @@ __global__ __launch_bounds__(256) void k_lattice_rows(ColP C, int R, int16_t *__
                                       rh * rh, (float)rh * C.lut_ps)
                           : -1;
   if (t < n) {
-    out[t] = (int16_t)e;
+    out[t] = e >= 0 ? C.rows[e] : 0u;
     out8[2 * t] = e >= 0 ? C.rows8[2 * e] : make_uint4(0, 1, 2, 3);
     out8[2 * t + 1] = e >= 0 ? C.rows8[2 * e + 1] : make_uint4(0, 0, 0, 0);
   }
@@ -707,10 +701,10 @@ hipError_t launch_column_bins(const ColP &C, int64_t n, const double *d, const d
   return hipGetLastError();
 }
 
-hipError_t launch_lattice_rows(const ColP &C, int R, int16_t *lat, uint4 *lat8, hipStream_t st) {
+hipError_t launch_lattice_rows(const ColP &C, int R, uint32_t *rows, uint4 *rows8, hipStream_t st) {
   const int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
   hipLaunchKernelGGL(k_lattice_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), C.nthr * sizeof(double), st, C,
-                     R, lat, lat8);
+                     R, rows + C.lat0, rows8 + 2 * (int64_t)C.lat0);
   return hipGetLastError();
 }
 

@@ -59,11 +59,12 @@ struct ColP {
   float lut_th, lut_ps, lut_ph;  // look-up scales: cell of cos theta, sin psi, pseudo-angle
   const double *thr;       // c|c| (c = cos(k dtheta)), sin^2(k dpsi), cos(k dphi), sin(k dphi)
   const uint8_t *lut;      // [LUT_BYTES] estimated bins (theta, psi, phi tables)
-  const uint32_t *rows;    // [nentries] offset << 6 | count
-  const uint4 *rows8;      // [nentries][2]: four pixels (bit 31 of the first: more
-                           // than four), their four FP32 weights (zero past count)
-  const int16_t *lat;      // [(2 lat_r + 1)^3] table row of a cell at a lattice offset
-  const uint4 *lat8;       // [(2 lat_r + 1)^3][2] its rows8 record
+  const uint32_t *rows;    // [nentries + nlat] offset << 6 | count
+  const uint4 *rows8;      // [nentries + nlat][2]: four pixels (bit 31 of the first:
+                           // more than four), their four FP32 weights (zero past count)
+  int lat0;                // row lat0 + (k W + j) W + i (W = 2 lat_r + 1): copy of the
+                           // row of a cell at lattice offset (i, j, k) - lat_r (node
+                           // size 1); the origin's has no pixels
   int lat_r;               // half-width of the lattice table; 0: not used (grid not dyadic)
   const uint16_t *pix;     // [npairs] FP64 walk
   const double *w64;       // [npairs]
@@ -98,7 +99,7 @@ hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const 
 // table rows of the offsets (i, j, k) cell sizes between two cells of one size,
 // |i|, |j|, |k| <= R, into lat [(2R + 1)^3] (k slowest, i fastest; -1 at the
 // origin) and their rows8 records into lat8 [(2R + 1)^3][2] (zero at the origin)
-hipError_t launch_lattice_rows(const ColP &C, int R, int16_t *lat, uint4 *lat8, hipStream_t st);
+hipError_t launch_lattice_rows(const ColP &C, int R, uint32_t *rows, uint4 *rows8, hipStream_t st);
 
 hipError_t launch_build(const DevTree &T, const double *rho, int *bad,
                         const std::vector<int64_t> &level_begin, int lmax, hipStream_t st);
