@@ -399,8 +399,9 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
     const double n0 = d0 * inv_h;
     return fabs(n0) < (double)(1 << 20) && n0 == rint(n0) ? (int)n0 : 1 << 20;
   };
-  // potential: FP64 sum (FP64 walk) or Kahan-compensated FP32 (FP32 walk)
-  Real s = 0, cmp = 0, ax = 0, ay = 0, az = 0;
+  // potential: FP64 sum (of FP32 pair terms in the FP32 walk)
+  double s = 0.0;
+  Real ax = 0, ay = 0, az = 0;
   const int64_t start = off[b], n = off[b + 1] - start;
   for (int64_t t0 = 0; t0 < n; t0 += TILE) {
     __syncthreads();
@@ -471,7 +472,7 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         const int o0 = (int)(hd >> 6), cnt = q.col ? (int)(hd & 63) : 0;
         double ph, A0, A1, A2;
         grav64<BC>(E, q.dx, q.dy, q.dz, q.r2, ph, A0, A1, A2);
-        s += (Real)(r.w * ph);
+        s += r.w * ph;
         tx += (Real)(r.w * A0);
         ty += (Real)(r.w * A1);
         tz += (Real)(r.w * A2);
@@ -496,24 +497,30 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         const Geo q = geometry(r);
         Pend p;
         p.e = row_of(r, q);
-        p.pq = C.rows8[2 * (uint32_t)p.e];
-        p.wq = C.rows8[2 * (uint32_t)p.e + 1];
-        // FP32 gravity from the FP64 offset (already the minimum image)
-        const float inv = q.valid ? q.rd : 0.0f;
-        float ph, A0, A1, A2;
-        grav32<BC, NEWTON>(E, q.dxf, q.dyf, q.dzf, inv, ph, A0, A1, A2);
-        // the target cell's term is an exact zero (a Kahan step with it only
-        // moves the compensation into the sum)
+        // both halves at one 32-bit byte offset from the uniform base
+        const char *const rq = reinterpret_cast<const char *>(C.rows8) + ((uint32_t)p.e << 5);
+        p.pq = *reinterpret_cast<const uint4 *>(rq);
+        p.wq = *reinterpret_cast<const uint4 *>(rq + 16);
+        // FP32 gravity from the FP64 offset (already the minimum image); the
+        // target cell's terms are exact zeros (zero mass; 1/r stays finite)
         const float m32 = q.valid ? r.m : 0.0f;
-        const float y = m32 * ph - (float)cmp;
-        const float tt = (float)s + y;
-        cmp = (Real)((tt - (float)s) - y);
-        s = (Real)tt;
-        tx += (Real)(m32 * A0);
-        ty += (Real)(m32 * A1);
-        tz += (Real)(m32 * A2);
+        const float mr = m32 * q.rd, mr2 = mr * q.rd;  // M / r, M / r^2
+        if (BC == 0 || NEWTON) {
+          const float mr3 = mr2 * q.rd;
+          s += (double)mr;
+          tx = fmaf(q.dxf, mr3, (float)tx);
+          ty = fmaf(q.dyf, mr3, (float)ty);
+          tz = fmaf(q.dzf, mr3, (float)tz);
+        } else {
+          float ph, A0, A1, A2;
+          grav32<BC, NEWTON>(E, q.dxf, q.dyf, q.dzf, q.valid ? q.rd : 0.0f, ph, A0, A1, A2);
+          s += (double)(m32 * ph);
+          tx += (Real)(m32 * A0);
+          ty += (Real)(m32 * A1);
+          tz += (Real)(m32 * A2);
+        }
         // N_p += w M / (Omega d^2): the weight base of the pair
-        p.base = q.col ? m32 * inv_omega * (q.rd * q.rd) : 0.0f;
+        p.base = q.col ? mr2 * inv_omega : 0.0f;
         p.col = q.col;
         return p;
       };
@@ -582,7 +589,7 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
     az += tz;
   }
   const int64_t o = b * 512 + ci;
-  phi[o] = (Real)(negG * (double)(s - cmp));
+  phi[o] = (Real)(negG * s);
   acc[o] = (Real)(negG * (double)ax);
   acc[ncell + o] = (Real)(negG * (double)ay);
   acc[2 * ncell + o] = (Real)(negG * (double)az);
