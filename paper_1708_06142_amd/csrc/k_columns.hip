@@ -482,9 +482,9 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
       }
     } else {
       // With LDS maps, a two-stage pipeline over the tile: stage A of pair
-      // j + 1 (offsets, gravity, bins, and the load of its row record) runs
+      // j + 2 (offsets, gravity, bins, and the load of its row record) runs
       // before stage B of pair j (the map update), so each record load is in
-      // flight while the next pair's bins are computed.  Both stages keep
+      // flight while the next two pairs' bins are computed.  Both stages keep
       // list order, so the sums are those of the plain loop.
       struct Pend {
         uint4 pq, wq;
@@ -492,8 +492,13 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         int e;
         bool col;
       };
+      // stage A of a pair past the tile's end (jj >= m: the pipeline issues
+      // its loads unconditionally, so that the waits for each record can
+      // count the loads issued after it) repeats the last record with zero
+      // mass and no columns: it adds exact zeros
       auto stage_a = [&](int jj) {
-        const ColRec r = tile[jj];
+        const bool live = jj < m;
+        const ColRec r = tile[live ? jj : m - 1];
         const Geo q = geometry(r);
         Pend p;
         p.e = row_of(r, q);
@@ -503,7 +508,7 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         p.wq = *reinterpret_cast<const uint4 *>(rq + 16);
         // FP32 gravity from the FP64 offset (already the minimum image); the
         // target cell's terms are exact zeros (zero mass; 1/r stays finite)
-        const float m32 = q.valid ? r.m : 0.0f;
+        const float m32 = q.valid && live ? r.m : 0.0f;
         const float mr = m32 * q.rd, mr2 = mr * q.rd;  // M / r, M / r^2
         if (BC == 0 || NEWTON) {
           const float mr3 = mr2 * q.rd;
@@ -520,8 +525,8 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
           tz += (Real)(m32 * A2);
         }
         // N_p += w M / (Omega d^2): the weight base of the pair
-        p.base = q.col ? mr2 * inv_omega : 0.0f;
-        p.col = q.col;
+        p.col = q.col && live;
+        p.base = p.col ? mr2 * inv_omega : 0.0f;
         return p;
       };
       // four of the row's pixels come with its record (distinct pixels,
@@ -571,16 +576,17 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         // and this walk waits on the map traffic rather than on the records)
         for (int j = 0; j < m; ++j) stage_b(stage_a(j));
       } else {
-        // unrolled by two with the pending state in alternating registers
-        // (no copy of the state between iterations)
-        Pend p0 = stage_a(0), p1;
-        for (int j = 0; j < m; j += 2) {
-          if (j + 1 < m) p1 = stage_a(j + 1);
+        // two pairs ahead (stage A of pair j + 2 before stage B of pair j),
+        // unrolled by three with the pending state in rotating registers (no
+        // copy of the state between iterations)
+        Pend p0 = stage_a(0), p1 = stage_a(1), p2;
+        for (int j = 0; j < m; j += 3) {
+          p2 = stage_a(j + 2);
           stage_b(p0);
-          if (j + 1 < m) {
-            if (j + 2 < m) p0 = stage_a(j + 2);
-            stage_b(p1);
-          }
+          p0 = stage_a(j + 3);
+          if (j + 1 < m) stage_b(p1);
+          p1 = stage_a(j + 4);
+          if (j + 2 < m) stage_b(p2);
         }
       }
     }
