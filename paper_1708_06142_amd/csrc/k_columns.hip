@@ -561,13 +561,19 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
           *q3 = fmaf(__uint_as_float(wq.w), base, v3);
         }
         if ((int)pq.x < 0 && p.col) {
-          const uint32_t hd = C.rows[p.e];
-          const int o0 = (int)(hd >> 6), cnt = (int)(hd & 63);
+          // the row's count and offset ride in the pixels' high bits (shifted
+          // out of the addresses above); the rest of the row two at a time (a
+          // zero entry adds zero to pixel 0)
+          const int cnt = (int)((pq.x >> 23) & 63u);
+          const int o0 = (int)((pq.y >> 23) | ((pq.z >> 23) << 9) | ((pq.w >> 23) << 18));
+          const int o1 = o0 + cnt;
           const float base24 = base * (1.0f / 16777216.0f);
-          for (int o = o0 + 4; o < o0 + cnt; ++o) {
-            const uint32_t v = C.ent[o];
+          for (int o = o0 + 4; o < o1; o += 2) {
+            const uint32_t v = C.ent[o], u = o + 1 < o1 ? C.ent[o + 1] : 0u;
             float *const qv = reinterpret_cast<float *>(mcell + ((v >> 24) << lmap));
             *qv += (float)(v & 0xffffffu) * base24;
+            float *const qu = reinterpret_cast<float *>(mcell + ((u >> 24) << lmap));
+            *qu += (float)(u & 0xffffffu) * base24;
           }
         }
       };
@@ -666,7 +672,8 @@ __global__ __launch_bounds__(256) void k_lattice_rows(ColP C, int R, uint32_t *_
 // packed rows for the walk: head = offset << 6 | count; entry = pixel << 24 |
 // round(w 2^24) (w <= 1, clamped to 2^24 - 1); rows8 = the first four pixels
 // and their FP32 weights, padded with the lowest pixels the row does not use
-// (weight 0), bit 31 of the first pixel set when the row has more than four
+// (weight 0); a row of more than four has bit 31 of the first pixel set and
+// its count and offset in the pixels' bits 23..30 / 23..31
 __global__ void k_raytable_pack(RayTableP P, const int64_t *__restrict__ off, const uint16_t *__restrict__ pix,
                                 const double *__restrict__ w, uint32_t *__restrict__ rows,
                                 uint32_t *__restrict__ ent, uint4 *__restrict__ rows8) {
@@ -699,7 +706,15 @@ __global__ void k_raytable_pack(RayTableP P, const int64_t *__restrict__ off, co
     }
     ++cand;
   }
-  if (o1 - o0 > 4) p4[0] |= 0x80000000u;
+  if (o1 - o0 > 4) {
+    // more than four: flag, count and offset (< 2^26) in bits 23..31 of the
+    // pixels (the walks shift the pixels by at least 9 bits into 32-bit
+    // addresses, which drops these bits)
+    p4[0] |= 0x80000000u | ((uint32_t)(o1 - o0) << 23);
+    p4[1] |= (uint32_t)(o0 & 511) << 23;
+    p4[2] |= (uint32_t)((o0 >> 9) & 511) << 23;
+    p4[3] |= (uint32_t)((o0 >> 18) & 511) << 23;
+  }
   rows8[2 * e] = make_uint4(p4[0], p4[1], p4[2], p4[3]);
   rows8[2 * e + 1] = make_uint4(w4[0], w4[1], w4[2], w4[3]);
 }
@@ -770,6 +785,9 @@ hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const 
   int lcpw = 0;
   while ((1 << lcpw) < cpw) ++lcpw;
   if ((1 << lcpw) != cpw) return hipErrorInvalidValue;  // cells per workgroup: a power of two
+  // FP32 map addresses shift the packed pixels by lcpw + 2 >= 9 bits (the
+  // bits above 22 hold a long row's count and offset)
+  if (!fp64 && !gmap && lcpw < 7) return hipErrorInvalidValue;
   dim3 grid((unsigned)(T.nb * (512 / cpw))), blk(cpw);
 #define OT_LAUNCH2(R, B, N, M)                                                                                \
   do {                                                                                                        \

@@ -61,7 +61,9 @@ struct ColP {
   const uint8_t *lut;      // [LUT_BYTES] estimated bins (theta, psi, phi tables)
   const uint32_t *rows;    // [nentries + nlat] offset << 6 | count
   const uint4 *rows8;      // [nentries + nlat][2]: four pixels (bit 31 of the first:
-                           // more than four), their four FP32 weights (zero past count)
+                           // more than four, whose count (first) and offset (next
+                           // three) are in bits 23 and up), their four FP32 weights
+                           // (zero past count)
   int lat0;                // row lat0 + (k W + j) W + i (W = 2 lat_r + 1): copy of the
                            // row of a cell at lattice offset (i, j, k) - lat_r (node
                            // size 1); the origin's has no pixels
