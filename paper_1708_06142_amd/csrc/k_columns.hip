@@ -485,7 +485,7 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
       // j + 2 (offsets, gravity, bins, and the load of its row record) runs
       // before stage B of pair j (the map update), so each record load is in
       // flight while the next two pairs' bins are computed.  Both stages keep
-      // list order, so the sums are those of the plain loop.
+      // list order (the remainders of long rows follow at the tile's end).
       struct Pend {
         uint4 pq, wq;
         float base;
@@ -529,6 +529,26 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         p.base = p.col ? mr2 * inv_omega : 0.0f;
         return p;
       };
+      // Rows of more than four pixels: the rest of the row (entries of the
+      // packed table, further loads that would stall the pipeline) is added
+      // at the tile's end, from a per-thread queue of up to DQ rows; a thread
+      // whose queue is full adds its oldest row at once.
+      constexpr int DQ = 4;
+      uint32_t dq_code[DQ] = {};  // count << 26 | offset
+      float dq_base[DQ] = {};
+      int dq_n = 0;
+      auto long_row = [&](uint32_t code, float base) {
+        const int o0 = (int)(code & 0x3ffffffu), o1 = o0 + (int)(code >> 26);
+        const float base24 = base * (1.0f / 16777216.0f);
+        // two entries at a time (a zero entry adds zero to pixel 0)
+        for (int o = o0 + 4; o < o1; o += 2) {
+          const uint32_t v = C.ent[o], u = o + 1 < o1 ? C.ent[o + 1] : 0u;
+          float *const qv = reinterpret_cast<float *>(mcell + ((v >> 24) << lmap));
+          *qv += (float)(v & 0xffffffu) * base24;
+          float *const qu = reinterpret_cast<float *>(mcell + ((u >> 24) << lmap));
+          *qu += (float)(u & 0xffffffu) * base24;
+        }
+      };
       // four of the row's pixels come with its record (distinct pixels,
       // weight 0 past the count), so the four read-modify-writes are
       // independent; the column is the thread's own (plain read-modify-write:
@@ -562,19 +582,20 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         }
         if ((int)pq.x < 0 && p.col) {
           // the row's count and offset ride in the pixels' high bits (shifted
-          // out of the addresses above); the rest of the row two at a time (a
-          // zero entry adds zero to pixel 0)
-          const int cnt = (int)((pq.x >> 23) & 63u);
-          const int o0 = (int)((pq.y >> 23) | ((pq.z >> 23) << 9) | ((pq.w >> 23) << 18));
-          const int o1 = o0 + cnt;
-          const float base24 = base * (1.0f / 16777216.0f);
-          for (int o = o0 + 4; o < o1; o += 2) {
-            const uint32_t v = C.ent[o], u = o + 1 < o1 ? C.ent[o + 1] : 0u;
-            float *const qv = reinterpret_cast<float *>(mcell + ((v >> 24) << lmap));
-            *qv += (float)(v & 0xffffffu) * base24;
-            float *const qu = reinterpret_cast<float *>(mcell + ((u >> 24) << lmap));
-            *qu += (float)(u & 0xffffffu) * base24;
+          // out of the addresses above); the row joins the queue
+          const uint32_t cnt = (pq.x >> 23) & 63u;
+          const uint32_t o0 = (pq.y >> 23) | ((pq.z >> 23) << 9) | ((pq.w >> 23) << 18);
+          if (dq_n == DQ) {
+            long_row(dq_code[DQ - 1], dq_base[DQ - 1]);
+            --dq_n;
           }
+          for (int k = DQ - 1; k > 0; --k) {
+            dq_code[k] = dq_code[k - 1];
+            dq_base[k] = dq_base[k - 1];
+          }
+          dq_code[0] = (cnt << 26) | o0;
+          dq_base[0] = base;
+          ++dq_n;
         }
       };
       if (GMAP) {
@@ -595,6 +616,8 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
           if (j + 2 < m) stage_b(p2);
         }
       }
+      for (int k = 0; k < DQ; ++k)
+        if (k < dq_n) long_row(dq_code[k], dq_base[k]);
     }
     ax += tx;
     ay += ty;
