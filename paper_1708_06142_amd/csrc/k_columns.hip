@@ -533,7 +533,7 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
       // packed table, further loads that would stall the pipeline) is added
       // at the tile's end, from a per-thread queue of up to DQ rows; a thread
       // whose queue is full adds its oldest row at once.
-      constexpr int DQ = 4;
+      constexpr int DQ = GMAP ? 4 : 8;
       uint32_t dq_code[DQ] = {};  // count << 26 | offset
       float dq_base[DQ] = {};
       int dq_n = 0;
