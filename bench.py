@@ -7,7 +7,7 @@ theta = 0.5 FP64 walk before timing, as the paper derives a_lim from the
 initial acceleration field); with 48-direction column densities (HEALPix
 Nside 2), so a node is also required to pass BH at theta_pix = 0.5.  A step
 is one pass of the whole path: tree build (moments), interaction lists, per-cell
-potential + acceleration from FP32 pair terms (potential summed in FP64), and the
+potential + acceleration in FP32 with Kahan-compensated potential, and the
 per-cell column map + tau_avg.  Inputs are resident in HBM before timing.
 
 Prints one JSON line (see the design doc for the roofline and baseline notes).
@@ -26,8 +26,8 @@ import numpy as np  # noqa: E402
 
 # Algorithmic FP32 work of one (cell, node) interaction of the isolated walk:
 # 3 sub (d), 5 (r^2: 3 mul + 2 add), rsqrt (1), m/r (1), m/r^3 (2 mul),
-# 3 FMA for the acceleration (6), one add for the potential sum (1).
-FLOP_PAIR_ISO = 19
+# 3 FMA for the acceleration (6), Kahan update of the potential (4).
+FLOP_PAIR_ISO = 22
 PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X vector FP32 (256 CU x 2.4 GHz, packed)
 PEAK_FP64_VALU = 78.6
 # Column walk per (cell, node) pair: the gravity above (its offset and r^2
@@ -237,7 +237,7 @@ def c3_leg(steps):
     """Plummer AMR configuration: box 1 x 1 x 4 (four root blocks), 64^3 base,
     up to three levels around four Plummer cores (5,100 blocks, 2.61M cells),
     x, y periodic and z isolated, BH theta = 0.5, FP64-generated 64^3 Ewald
-    table: the FP32 table walk beside the FP64 table walk."""
+    table: the FP32-Kahan table walk beside the FP64 table walk."""
     import torch
     import paper_1708_06142_amd as ot
     import workloads
@@ -335,7 +335,7 @@ def main():
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"lognormal {args.n}^3 (sigma_ln 1.5, P(k)~k^-4, seed 2), isolated, "
-                               f"APE a_lim=1e-3 a_max, {npx}-pixel columns, FP32 walk (FP64 potential sum)",
+                               f"APE a_lim=1e-3 a_max, {npx}-pixel columns, FP32-Kahan walk",
                    "cells": ncell, "blocks": grid.nb, "a_lim": a_lim, "columns": npx},
         "phases_ms": {"build": ms_build, "lists": ms_list, "eval": ms_eval},
         "eval_wg_per_cu": st.eval_wg_per_cu,

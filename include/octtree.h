@@ -138,8 +138,7 @@ ot_status ot_build(ot_ctx *c, const double *rho_dev, void *stream);
  * phi = 1/|d| (isolated) or the Ewald kernel (periodic / mixed), and with
  * nside > 0 the column map N_p = sum w_p M / (Omega_pix |d|^2) over the
  * node-ray table's pixels w_p of each node and tau_avg = -ln <exp(-kappa N_p)>.
- * ot_solve: FP32 pair terms, the terms of Phi summed in FP64 (with the
- * learned correction: Kahan-compensated FP32 sum);
+ * ot_solve: FP32 arithmetic with compensated (Kahan) summation of Phi;
  * ot_solve64: FP64 throughout.  Direction bins are decided in FP64 in both.
  * phi_dev [nb*512], acc_dev [3*nb*512]; npix_dev [nb][N_pix][512] and
  * tau_dev [nb*512] are required when nside > 0 and ignored otherwise.

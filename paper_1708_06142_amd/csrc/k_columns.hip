@@ -399,8 +399,16 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
     const double n0 = d0 * inv_h;
     return fabs(n0) < (double)(1 << 20) && n0 == rint(n0) ? (int)n0 : 1 << 20;
   };
-  // potential: FP64 sum (of FP32 pair terms in the FP32 walk)
+  // potential: FP64 sum (FP64 walk) or Kahan-compensated FP32 sum and its
+  // compensation (FP32 walk)
   double s = 0.0;
+  float ks = 0.0f, kc = 0.0f;
+  auto kahan = [&](float x) {
+    const float y = x - kc;
+    const float t = ks + y;
+    kc = (t - ks) - y;
+    ks = t;
+  };
   Real ax = 0, ay = 0, az = 0;
   const int64_t start = off[b], n = off[b + 1] - start;
   for (int64_t t0 = 0; t0 < n; t0 += TILE) {
@@ -507,19 +515,20 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
         p.pq = *reinterpret_cast<const uint4 *>(rq);
         p.wq = *reinterpret_cast<const uint4 *>(rq + 16);
         // FP32 gravity from the FP64 offset (already the minimum image); the
-        // target cell's terms are exact zeros (zero mass; 1/r stays finite)
+        // target cell's terms are exact zeros (zero mass; 1/r stays finite; a
+        // Kahan step with a zero only moves the compensation into the sum)
         const float m32 = q.valid && live ? r.m : 0.0f;
         const float mr = m32 * q.rd, mr2 = mr * q.rd;  // M / r, M / r^2
         if (BC == 0 || NEWTON) {
           const float mr3 = mr2 * q.rd;
-          s += (double)mr;
+          kahan(mr);
           tx = fmaf(q.dxf, mr3, (float)tx);
           ty = fmaf(q.dyf, mr3, (float)ty);
           tz = fmaf(q.dzf, mr3, (float)tz);
         } else {
           float ph, A0, A1, A2;
           grav32<BC, NEWTON>(E, q.dxf, q.dyf, q.dzf, q.valid ? q.rd : 0.0f, ph, A0, A1, A2);
-          s += (double)(m32 * ph);
+          kahan(m32 * ph);
           tx += (Real)(m32 * A0);
           ty += (Real)(m32 * A1);
           tz += (Real)(m32 * A2);
@@ -624,7 +633,7 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
     az += tz;
   }
   const int64_t o = b * 512 + ci;
-  phi[o] = (Real)(negG * s);
+  phi[o] = (Real)(negG * (sizeof(Real) == 8 ? s : (double)(ks - kc)));
   acc[o] = (Real)(negG * (double)ax);
   acc[ncell + o] = (Real)(negG * (double)ay);
   acc[2 * ncell + o] = (Real)(negG * (double)az);

@@ -17,8 +17,8 @@
 //
 // One workgroup of 256 threads per leaf block; thread t owns cells t and
 // t + 256.  The list is streamed through LDS in tiles of 256 records, which
-// every thread then reads as broadcasts.  The FP32 kernel accumulates the FP32
-// potential terms in FP64 and the acceleration in plain FP32 per tile, the tile
+// every thread then reads as broadcasts.  The FP32 kernel accumulates Phi with
+// Kahan compensation and the acceleration in plain FP32 per tile, the tile
 // sums then added (blocked summation).
 #include "common.hpp"
 #include "ewald_lookup.hpp"
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(WG) void k_eval64(DevTree T, EwaldP E, const int64_
 
 // ---------------------------------------------------------------- FP32
 struct Acc32 {
-  double s;  // sum of the FP32 terms M phi
+  float s, c;  // Kahan sum of M phi and its compensation
   float ax, ay, az;
   float tx, ty, tz;  // acceleration of the current tile (blocked summation)
 };
@@ -179,7 +179,11 @@ __device__ inline void pair32(const EwaldP &E, float cx, float cy, float cz, con
     fy = self ? 0.0f : r.w * A1;
     fz = self ? 0.0f : r.w * A2;
   }
-  a.s += (double)term;
+  // Kahan compensated sum of the potential terms
+  const float y = term - a.c;
+  const float t = a.s + y;
+  a.c = (t - a.s) - y;
+  a.s = t;
   a.tx += fx;
   a.ty += fy;
   a.tz += fz;
@@ -206,7 +210,7 @@ __global__ __launch_bounds__(WG) void k_eval32(DevTree T, EwaldP E, const int64_
     cx[q] = (float)(((double)(ci & 7) - 3.5) * h);
     cy[q] = (float)(((double)((ci >> 3) & 7) - 3.5) * h);
     cz[q] = (float)(((double)(ci >> 6) - 3.5) * h);
-    a[q] = Acc32{0.0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    a[q] = Acc32{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   }
   const int64_t start = off[b], n = off[b + 1] - start;
   for (int64_t t0 = 0; t0 < n; t0 += WG) {
@@ -245,7 +249,7 @@ __global__ __launch_bounds__(WG) void k_eval32(DevTree T, EwaldP E, const int64_
   }
   for (int q = 0; q < 2; ++q) {
     int64_t o = b * 512 + tid + q * WG;
-    phi[o] = (float)((double)negG * a[q].s);
+    phi[o] = negG * (a[q].s - a[q].c);
     acc[o] = negG * a[q].ax;
     acc[ncell + o] = negG * a[q].ay;
     acc[2 * ncell + o] = negG * a[q].az;
