@@ -295,6 +295,7 @@ ot_status raytable_prepare(ot_ctx *c, hipStream_t st) {
     if (s == OT_OK) s = dalloc(c, c->rt_rows, (size_t)(RP.nentries + nlat) * sizeof(uint32_t));
     if (s == OT_OK) s = dalloc(c, c->rt_ent, (size_t)total * sizeof(uint32_t));
     if (s == OT_OK) s = dalloc(c, c->rt_rows8, (size_t)(RP.nentries + nlat) * 32);
+    if (s == OT_OK) s = dalloc(c, c->rt_quad64, (size_t)(RP.nentries + nlat) * 32);
     if (s == OT_OK) s = dalloc(c, c->rt_lut, ot::LUT_BYTES);
     if (s == OT_OK && total >= ((int64_t)1 << 26)) s = fail(c, OT_ERR_UNSUPPORTED, "node-ray table too large");
     if (s == OT_OK) {
@@ -310,7 +311,8 @@ ot_status raytable_prepare(ot_ctx *c, hipStream_t st) {
                               P<uint16_t>(c->rt_pix), P<double>(c->rt_w64), &total, st);
       if (e == hipSuccess)
         e = ot::launch_raytable_pack(RP, P<int64_t>(c->rt_off), P<uint16_t>(c->rt_pix), P<double>(c->rt_w64),
-                                     P<uint32_t>(c->rt_rows), P<uint32_t>(c->rt_ent), P<uint4>(c->rt_rows8), st);
+                                     P<uint32_t>(c->rt_rows), P<uint32_t>(c->rt_ent), P<uint4>(c->rt_rows8),
+                                     P<double>(c->rt_quad64), st);
       // direction-bin thresholds: c |c| with c = cos(k dtheta), sin^2(k dpsi),
       // (cos(k dphi), sin(k dphi)) pairs; each list ends in a threshold its test
       // never passes (-inf, +inf, and phi = pi exactly as cos -1, sin 0)
@@ -338,7 +340,8 @@ ot_status raytable_prepare(ot_ctx *c, hipStream_t st) {
         e = hipMemcpyAsync(c->rt_lut.ptr, lut.data(), lut.size(), hipMemcpyHostToDevice, st);
       // rows of the cells at lattice offsets, by the walk's own binning
       if (e == hipSuccess && s == OT_OK)
-        e = ot::launch_lattice_rows(col_params(c), LAT_R, P<uint32_t>(c->rt_rows), P<uint4>(c->rt_rows8), st);
+        e = ot::launch_lattice_rows(col_params(c), LAT_R, P<uint32_t>(c->rt_rows), P<uint4>(c->rt_rows8),
+                                    P<double>(c->rt_quad64), st);
       if (e == hipSuccess) e = hipStreamSynchronize(st);
     }
   }
@@ -392,6 +395,7 @@ ot::ColP col_params(ot_ctx *c) {
   C.lut = P<uint8_t>(c->rt_lut);
   C.rows = P<uint32_t>(c->rt_rows);
   C.rows8 = P<uint4>(c->rt_rows8);
+  C.quad_w64 = P<double>(c->rt_quad64);
   C.lat0 = (int)RP.nentries;
   C.lat_r = c->rt_ready && dyadic_grid(c) ? LAT_R : 0;
   C.pix = P<uint16_t>(c->rt_pix);
@@ -1077,7 +1081,7 @@ void ot_destroy(ot_ctx *c) {
   DevBuf *all[] = {&c->alev, &c->acoord, &c->achild0, &c->aleaf, &c->blev,   &c->bcoord,
                    &c->bamr, &c->amc,    &c->aS,      &c->btmc,  &c->cm,     &c->flag,
                    &c->lcount, &c->loff, &c->lrec,    &c->lid,   &c->lscratch, &c->tab64,
-                   &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_rows, &c->rt_ent, &c->rt_rows8, &c->rt_lut,
+                   &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_rows, &c->rt_ent, &c->rt_rows8, &c->rt_quad64, &c->rt_lut,
                    &c->rt_thr, &c->lh, &c->mlp_P, &c->mlp_pk, &c->mlp_part, &c->mlp_lossp,
                    &c->mlp_loss};
   for (DevBuf *b : all) release(c, *b);

@@ -67,7 +67,7 @@ struct ot_ctx {
   double ew_alpha = 0, ew_ext[3] = {0, 0, 0}, ew_step[3] = {0, 0, 0};
   double ms_build = 0.0;
   // columns
-  ot::DevBuf rt_off, rt_pix, rt_w64, rt_rows, rt_ent, rt_rows8, rt_lut, rt_thr, lh;
+  ot::DevBuf rt_off, rt_pix, rt_w64, rt_rows, rt_ent, rt_rows8, rt_quad64, rt_lut, rt_thr, lh;
   bool rt_ready = false;
   int64_t rt_pairs = 0;
   // learned Ewald surrogate: FP32 parameters, packed FP16 operands, the

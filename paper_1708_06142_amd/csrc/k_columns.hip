@@ -16,6 +16,8 @@
 //    cell's column: plain read-modify-write in list order, no atomics, no
 //    bank conflicts).  At the end each cell's map
 //    and tau_avg = -ln(mean_p exp(-kappa N_p)) are written out.
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -346,7 +348,7 @@ __device__ inline void grav32(const EwaldP &E, float dx, float dy, float dz, flo
 // maps are accumulated in place in npix (each thread owns its cell's column,
 // a wave's 64 cells are adjacent): for maps too large for LDS at a useful
 // occupancy (192 pixels take 768 bytes per cell in FP32).
-template <typename Real, int BC, bool NEWTON, bool GMAP, bool LATTICE = sizeof(Real) == 4 && !GMAP>
+template <typename Real, int BC, bool NEWTON, bool GMAP, bool LATTICE = !GMAP>
 __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, const int64_t *__restrict__ off,
                                                    const double4 *__restrict__ rec,
                                                    const int32_t *__restrict__ ids, const double *__restrict__ lh,
@@ -470,49 +472,54 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
                                fabsf(r.rhs))
                    : 0;
     };
-    if (sizeof(Real) == 8) {
-      for (int j = 0; j < m; ++j) {
-        const ColRec r = tile[j];
-        const Geo q = geometry(r);
-        const int e = row_of(r, q);
-        if (!q.valid) continue;
-        const uint32_t hd = C.rows[e];
-        const int o0 = (int)(hd >> 6), cnt = q.col ? (int)(hd & 63) : 0;
+    // A two-stage pipeline over the tile: stage A of pair j + 2 (offsets,
+    // gravity, bins, and the load of its row record) runs before stage B of
+    // pair j (the map update), so each record load is in flight while the
+    // next two pairs' bins are computed (with the maps in memory one stage
+    // follows the other).  Both stages keep list order (the remainders of
+    // long rows follow at the tile's end).  The record: four pixels, and their
+    // weights in FP32 (the FP32 walk) or FP64.
+    struct W64 {
+      double2 a, b;
+    };
+    using WQ = typename std::conditional<sizeof(Real) == 8, W64, uint4>::type;
+    struct Pend {
+      uint4 pq;
+      WQ wq;
+      Real base;
+      int e;
+      bool col;
+    };
+    // stage A of a pair past the tile's end (jj >= m: the pipeline issues its
+    // loads unconditionally, so that the waits for each record can count the
+    // loads issued after it) repeats the last record with zero mass and no
+    // columns: it adds exact zeros
+    auto stage_a = [&](int jj) {
+      const bool live = jj < m;
+      const ColRec r = tile[live ? jj : m - 1];
+      const Geo q = geometry(r);
+      Pend p;
+      p.e = row_of(r, q);
+      // pixels and weights at one 32-bit byte offset from uniform bases
+      const uint32_t ro = (uint32_t)p.e << 5;
+      const char *const rq = reinterpret_cast<const char *>(C.rows8) + ro;
+      p.pq = *reinterpret_cast<const uint4 *>(rq);
+      p.col = q.col && live;
+      if constexpr (sizeof(Real) == 8) {
+        const char *const wq = reinterpret_cast<const char *>(C.quad_w64) + ro;
+        p.wq.a = *reinterpret_cast<const double2 *>(wq);
+        p.wq.b = *reinterpret_cast<const double2 *>(wq + 16);
+        // FP64 gravity; the target cell (and a repeat) adds exact zeros
+        const double m64 = q.valid && live ? r.w : 0.0;
         double ph, A0, A1, A2;
-        grav64<BC>(E, q.dx, q.dy, q.dz, q.r2, ph, A0, A1, A2);
-        s += r.w * ph;
-        tx += (Real)(r.w * A0);
-        ty += (Real)(r.w * A1);
-        tz += (Real)(r.w * A2);
-        const double base = r.w / (C.omega * q.r2);
-        for (int o = o0; o < o0 + cnt; ++o)
-          *reinterpret_cast<Real *>(mcell + ((uint32_t)C.pix[o] << lmap)) += (Real)(C.w64[o] * base);
-      }
-    } else {
-      // With LDS maps, a two-stage pipeline over the tile: stage A of pair
-      // j + 2 (offsets, gravity, bins, and the load of its row record) runs
-      // before stage B of pair j (the map update), so each record load is in
-      // flight while the next two pairs' bins are computed.  Both stages keep
-      // list order (the remainders of long rows follow at the tile's end).
-      struct Pend {
-        uint4 pq, wq;
-        float base;
-        int e;
-        bool col;
-      };
-      // stage A of a pair past the tile's end (jj >= m: the pipeline issues
-      // its loads unconditionally, so that the waits for each record can
-      // count the loads issued after it) repeats the last record with zero
-      // mass and no columns: it adds exact zeros
-      auto stage_a = [&](int jj) {
-        const bool live = jj < m;
-        const ColRec r = tile[live ? jj : m - 1];
-        const Geo q = geometry(r);
-        Pend p;
-        p.e = row_of(r, q);
-        // both halves at one 32-bit byte offset from the uniform base
-        const char *const rq = reinterpret_cast<const char *>(C.rows8) + ((uint32_t)p.e << 5);
-        p.pq = *reinterpret_cast<const uint4 *>(rq);
+        grav64<BC>(E, q.dx, q.dy, q.dz, q.valid ? q.r2 : 1.0, ph, A0, A1, A2);
+        s += m64 * ph;
+        tx += m64 * A0;
+        ty += m64 * A1;
+        tz += m64 * A2;
+        // N_p += w M / (Omega d^2): the weight base of the pair
+        p.base = p.col ? r.w / (C.omega * q.r2) : 0.0;
+      } else {
         p.wq = *reinterpret_cast<const uint4 *>(rq + 16);
         // FP32 gravity from the FP64 offset (already the minimum image); the
         // target cell's terms are exact zeros (zero mass; 1/r stays finite; a
@@ -534,22 +541,26 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
           tz += (Real)(m32 * A2);
         }
         // N_p += w M / (Omega d^2): the weight base of the pair
-        p.col = q.col && live;
-        p.base = p.col ? mr2 * inv_omega : 0.0f;
-        return p;
-      };
-      // Rows of more than four pixels: the rest of the row (entries of the
-      // packed table, further loads that would stall the pipeline) is added
-      // at the tile's end, from a per-thread queue of up to DQ rows; a thread
-      // whose queue is full adds its oldest row at once.
-      constexpr int DQ = GMAP ? 4 : 8;
-      uint32_t dq_code[DQ] = {};  // count << 26 | offset
-      float dq_base[DQ] = {};
-      int dq_n = 0;
-      auto long_row = [&](uint32_t code, float base) {
-        const int o0 = (int)(code & 0x3ffffffu), o1 = o0 + (int)(code >> 26);
+        p.base = p.col ? (Real)(mr2 * inv_omega) : (Real)0;
+      }
+      return p;
+    };
+    // Rows of more than four pixels: the rest of the row (further loads that
+    // would stall the pipeline) is added at the tile's end, from a per-thread
+    // queue of up to DQ rows; a thread whose queue is full adds its oldest row
+    // at once.
+    constexpr int DQ = GMAP ? 4 : 8;
+    uint32_t dq_code[DQ] = {};  // count << 26 | offset
+    Real dq_base[DQ] = {};
+    int dq_n = 0;
+    auto long_row = [&](uint32_t code, Real base) {
+      const int o0 = (int)(code & 0x3ffffffu), o1 = o0 + (int)(code >> 26);
+      if constexpr (sizeof(Real) == 8) {
+        for (int o = o0 + 4; o < o1; ++o)
+          *reinterpret_cast<double *>(mcell + ((uint32_t)C.pix[o] << lmap)) += C.w64[o] * base;
+      } else {
         const float base24 = base * (1.0f / 16777216.0f);
-        // two entries at a time (a zero entry adds zero to pixel 0)
+        // two packed entries at a time (a zero entry adds zero to pixel 0)
         for (int o = o0 + 4; o < o1; o += 2) {
           const uint32_t v = C.ent[o], u = o + 1 < o1 ? C.ent[o + 1] : 0u;
           float *const qv = reinterpret_cast<float *>(mcell + ((v >> 24) << lmap));
@@ -557,77 +568,89 @@ __global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, 
           float *const qu = reinterpret_cast<float *>(mcell + ((u >> 24) << lmap));
           *qu += (float)(u & 0xffffffu) * base24;
         }
-      };
-      // four of the row's pixels come with its record (distinct pixels,
-      // weight 0 past the count), so the four read-modify-writes are
-      // independent; the column is the thread's own (plain read-modify-write:
-      // LDS atomic adds measured 2.5x slower)
-      auto stage_b = [&](const Pend &p) {
-        const float base = p.base;
-        const uint4 pq = p.pq, wq = p.wq;
-        // bit 31 of the first pixel (more than four) is shifted out here
-        float *const q0 = reinterpret_cast<float *>(mcell + (pq.x << lmap));
-        float *const q1 = reinterpret_cast<float *>(mcell + (pq.y << lmap));
-        float *const q2 = reinterpret_cast<float *>(mcell + (pq.z << lmap));
-        float *const q3 = reinterpret_cast<float *>(mcell + (pq.w << lmap));
-        if (GMAP) {
-          // in memory the padding slots would cost traffic: they are skipped
-          const bool u1 = wq.y != 0u, u2 = wq.z != 0u, u3 = wq.w != 0u;
-          float v1 = 0.0f, v2 = 0.0f, v3 = 0.0f;
-          const float v0 = *q0;
-          if (u1) v1 = *q1;
-          if (u2) v2 = *q2;
-          if (u3) v3 = *q3;
-          *q0 = fmaf(__uint_as_float(wq.x), base, v0);
-          if (u1) *q1 = fmaf(__uint_as_float(wq.y), base, v1);
-          if (u2) *q2 = fmaf(__uint_as_float(wq.z), base, v2);
-          if (u3) *q3 = fmaf(__uint_as_float(wq.w), base, v3);
-        } else {
-          const float v0 = *q0, v1 = *q1, v2 = *q2, v3 = *q3;
-          *q0 = fmaf(__uint_as_float(wq.x), base, v0);
-          *q1 = fmaf(__uint_as_float(wq.y), base, v1);
-          *q2 = fmaf(__uint_as_float(wq.z), base, v2);
-          *q3 = fmaf(__uint_as_float(wq.w), base, v3);
-        }
-        if ((int)pq.x < 0 && p.col) {
-          // the row's count and offset ride in the pixels' high bits (shifted
-          // out of the addresses above); the row joins the queue
-          const uint32_t cnt = (pq.x >> 23) & 63u;
-          const uint32_t o0 = (pq.y >> 23) | ((pq.z >> 23) << 9) | ((pq.w >> 23) << 18);
-          if (dq_n == DQ) {
-            long_row(dq_code[DQ - 1], dq_base[DQ - 1]);
-            --dq_n;
-          }
-          for (int k = DQ - 1; k > 0; --k) {
-            dq_code[k] = dq_code[k - 1];
-            dq_base[k] = dq_base[k - 1];
-          }
-          dq_code[0] = (cnt << 26) | o0;
-          dq_base[0] = base;
-          ++dq_n;
-        }
-      };
-      if (GMAP) {
-        // maps in memory: no pipeline (its registers would cost occupancy,
-        // and this walk waits on the map traffic rather than on the records)
-        for (int j = 0; j < m; ++j) stage_b(stage_a(j));
-      } else {
-        // two pairs ahead (stage A of pair j + 2 before stage B of pair j),
-        // unrolled by three with the pending state in rotating registers (no
-        // copy of the state between iterations)
-        Pend p0 = stage_a(0), p1 = stage_a(1), p2;
-        for (int j = 0; j < m; j += 3) {
-          p2 = stage_a(j + 2);
-          stage_b(p0);
-          p0 = stage_a(j + 3);
-          if (j + 1 < m) stage_b(p1);
-          p1 = stage_a(j + 4);
-          if (j + 2 < m) stage_b(p2);
-        }
       }
-      for (int k = 0; k < DQ; ++k)
-        if (k < dq_n) long_row(dq_code[k], dq_base[k]);
+    };
+    // four of the row's pixels come with its record (distinct pixels, weight
+    // 0 past the count), so the four read-modify-writes are independent; the
+    // column is the thread's own (plain read-modify-write: LDS atomic adds
+    // measured 2.5x slower)
+    auto stage_b = [&](const Pend &p) {
+      const Real base = p.base;
+      const uint4 pq = p.pq;
+      Real w[4];
+      if constexpr (sizeof(Real) == 8) {
+        w[0] = p.wq.a.x;
+        w[1] = p.wq.a.y;
+        w[2] = p.wq.b.x;
+        w[3] = p.wq.b.y;
+      } else {
+        w[0] = __uint_as_float(p.wq.x);
+        w[1] = __uint_as_float(p.wq.y);
+        w[2] = __uint_as_float(p.wq.z);
+        w[3] = __uint_as_float(p.wq.w);
+      }
+      // bit 31 of the first pixel (more than four) and the bits from 23 up
+      // are shifted out here
+      Real *const q0 = reinterpret_cast<Real *>(mcell + (pq.x << lmap));
+      Real *const q1 = reinterpret_cast<Real *>(mcell + (pq.y << lmap));
+      Real *const q2 = reinterpret_cast<Real *>(mcell + (pq.z << lmap));
+      Real *const q3 = reinterpret_cast<Real *>(mcell + (pq.w << lmap));
+      if (GMAP) {
+        // in memory the padding slots would cost traffic: they are skipped
+        const bool u1 = w[1] != (Real)0, u2 = w[2] != (Real)0, u3 = w[3] != (Real)0;
+        Real v1 = 0, v2 = 0, v3 = 0;
+        const Real v0 = *q0;
+        if (u1) v1 = *q1;
+        if (u2) v2 = *q2;
+        if (u3) v3 = *q3;
+        *q0 = fma(w[0], base, v0);
+        if (u1) *q1 = fma(w[1], base, v1);
+        if (u2) *q2 = fma(w[2], base, v2);
+        if (u3) *q3 = fma(w[3], base, v3);
+      } else {
+        const Real v0 = *q0, v1 = *q1, v2 = *q2, v3 = *q3;
+        *q0 = fma(w[0], base, v0);
+        *q1 = fma(w[1], base, v1);
+        *q2 = fma(w[2], base, v2);
+        *q3 = fma(w[3], base, v3);
+      }
+      if ((int)pq.x < 0 && p.col) {
+        // the row's count and offset ride in the pixels' high bits; the row
+        // joins the queue
+        const uint32_t cnt = (pq.x >> 23) & 63u;
+        const uint32_t o0 = (pq.y >> 23) | ((pq.z >> 23) << 9) | ((pq.w >> 23) << 18);
+        if (dq_n == DQ) {
+          long_row(dq_code[DQ - 1], dq_base[DQ - 1]);
+          --dq_n;
+        }
+        for (int k = DQ - 1; k > 0; --k) {
+          dq_code[k] = dq_code[k - 1];
+          dq_base[k] = dq_base[k - 1];
+        }
+        dq_code[0] = (cnt << 26) | o0;
+        dq_base[0] = base;
+        ++dq_n;
+      }
+    };
+    if (GMAP) {
+      // maps in memory: no pipeline (its registers would cost occupancy, and
+      // this walk waits on the map traffic rather than on the records)
+      for (int j = 0; j < m; ++j) stage_b(stage_a(j));
+    } else {
+      // two pairs ahead, unrolled by three with the pending state in rotating
+      // registers (no copy of the state between iterations)
+      Pend p0 = stage_a(0), p1 = stage_a(1), p2;
+      for (int j = 0; j < m; j += 3) {
+        p2 = stage_a(j + 2);
+        stage_b(p0);
+        p0 = stage_a(j + 3);
+        if (j + 1 < m) stage_b(p1);
+        p1 = stage_a(j + 4);
+        if (j + 2 < m) stage_b(p2);
+      }
     }
+    for (int k = 0; k < DQ; ++k)
+      if (k < dq_n) long_row(dq_code[k], dq_base[k]);
     ax += tx;
     ay += ty;
     az += tz;
@@ -675,7 +698,7 @@ __global__ __launch_bounds__(256) void k_column_bins(ColP C, int64_t n, const do
 // copied from the table row that the walk's own binning gives (head and
 // packed record); the origin gets an empty row
 __global__ __launch_bounds__(256) void k_lattice_rows(ColP C, int R, uint32_t *__restrict__ out,
-                                                      uint4 *__restrict__ out8) {
+                                                      uint4 *__restrict__ out8, double *__restrict__ out_w64) {
   __shared__ uint8_t lut[LUT_BYTES];
   extern __shared__ __align__(16) unsigned char smem[];
   double *thr = reinterpret_cast<double *>(smem);
@@ -698,6 +721,7 @@ __global__ __launch_bounds__(256) void k_lattice_rows(ColP C, int R, uint32_t *_
     out[t] = e >= 0 ? C.rows[e] : 0u;
     out8[2 * t] = e >= 0 ? C.rows8[2 * e] : make_uint4(0, 1, 2, 3);
     out8[2 * t + 1] = e >= 0 ? C.rows8[2 * e + 1] : make_uint4(0, 0, 0, 0);
+    for (int k = 0; k < 4; ++k) out_w64[4 * (int64_t)t + k] = e >= 0 ? C.quad_w64[4 * (int64_t)e + k] : 0.0;
   }
 }
 
@@ -708,13 +732,15 @@ __global__ __launch_bounds__(256) void k_lattice_rows(ColP C, int R, uint32_t *_
 // its count and offset in the pixels' bits 23..30 / 23..31
 __global__ void k_raytable_pack(RayTableP P, const int64_t *__restrict__ off, const uint16_t *__restrict__ pix,
                                 const double *__restrict__ w, uint32_t *__restrict__ rows,
-                                uint32_t *__restrict__ ent, uint4 *__restrict__ rows8) {
+                                uint32_t *__restrict__ ent, uint4 *__restrict__ rows8,
+                                double *__restrict__ quad_w64) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= P.nentries) return;
   const int64_t o0 = off[e], o1 = off[e + 1];
   const uint32_t head = (uint32_t)(o0 << 6) | (uint32_t)(o1 - o0);
   rows[e] = head;
   uint32_t p4[4], w4[4];
+  double d4[4];
   int nf = 0;
   for (int64_t o = o0; o < o1; ++o) {
     double q = rint(w[o] * 16777216.0);
@@ -723,6 +749,7 @@ __global__ void k_raytable_pack(RayTableP P, const int64_t *__restrict__ off, co
     if (nf < 4) {
       p4[nf] = pix[o];
       w4[nf] = __float_as_uint((float)w[o]);
+      d4[nf] = w[o];
       ++nf;
     }
   }
@@ -734,6 +761,7 @@ __global__ void k_raytable_pack(RayTableP P, const int64_t *__restrict__ off, co
     if (!used) {
       p4[nf] = cand;
       w4[nf] = 0u;
+      d4[nf] = 0.0;
       ++nf;
     }
     ++cand;
@@ -749,6 +777,7 @@ __global__ void k_raytable_pack(RayTableP P, const int64_t *__restrict__ off, co
   }
   rows8[2 * e] = make_uint4(p4[0], p4[1], p4[2], p4[3]);
   rows8[2 * e + 1] = make_uint4(w4[0], w4[1], w4[2], w4[3]);
+  for (int k = 0; k < 4; ++k) quad_w64[4 * (int64_t)e + k] = d4[k];
 }
 
 }  // namespace
@@ -761,10 +790,11 @@ hipError_t launch_column_bins(const ColP &C, int64_t n, const double *d, const d
   return hipGetLastError();
 }
 
-hipError_t launch_lattice_rows(const ColP &C, int R, uint32_t *rows, uint4 *rows8, hipStream_t st) {
+hipError_t launch_lattice_rows(const ColP &C, int R, uint32_t *rows, uint4 *rows8, double *quad_w64,
+                               hipStream_t st) {
   const int n = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
   hipLaunchKernelGGL(k_lattice_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), C.nthr * sizeof(double), st, C,
-                     R, rows + C.lat0, rows8 + 2 * (int64_t)C.lat0);
+                     R, rows + C.lat0, rows8 + 2 * (int64_t)C.lat0, quad_w64 + 4 * (int64_t)C.lat0);
   return hipGetLastError();
 }
 
@@ -799,9 +829,9 @@ int cols_lds_cpw(int npix, bool fp64, int nthr) {
 }
 
 hipError_t launch_raytable_pack(const RayTableP &P, const int64_t *off, const uint16_t *pix, const double *w,
-                                uint32_t *rows, uint32_t *ent, uint4 *rows8, hipStream_t st) {
+                                uint32_t *rows, uint32_t *ent, uint4 *rows8, double *quad_w64, hipStream_t st) {
   hipLaunchKernelGGL(k_raytable_pack, dim3((unsigned)((P.nentries + 255) / 256)), dim3(256), 0, st, P, off,
-                     pix, w, rows, ent, rows8);
+                     pix, w, rows, ent, rows8, quad_w64);
   return hipGetLastError();
 }
 
@@ -817,9 +847,9 @@ hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const 
   int lcpw = 0;
   while ((1 << lcpw) < cpw) ++lcpw;
   if ((1 << lcpw) != cpw) return hipErrorInvalidValue;  // cells per workgroup: a power of two
-  // FP32 map addresses shift the packed pixels by lcpw + 2 >= 9 bits (the
-  // bits above 22 hold a long row's count and offset)
-  if (!fp64 && !gmap && lcpw < 7) return hipErrorInvalidValue;
+  // map addresses shift the packed pixels by lcpw + 2 (FP32) or + 3 (FP64),
+  // at least 9 bits (the bits above 22 hold a long row's count and offset)
+  if (lcpw + (fp64 ? 3 : 2) < 9) return hipErrorInvalidValue;
   dim3 grid((unsigned)(T.nb * (512 / cpw))), blk(cpw);
 #define OT_LAUNCH2(R, B, N, M)                                                                                \
   do {                                                                                                        \

@@ -64,6 +64,7 @@ struct ColP {
                            // more than four, whose count (first) and offset (next
                            // three) are in bits 23 and up), their four FP32 weights
                            // (zero past count)
+  const double *quad_w64;  // [nentries + nlat][4]: the four weights in FP64 (FP64 walk)
   int lat0;                // row lat0 + (k W + j) W + i (W = 2 lat_r + 1): copy of the
                            // row of a cell at lattice offset (i, j, k) - lat_r (node
                            // size 1); the origin's has no pixels
@@ -82,7 +83,7 @@ constexpr int LUT_TH = 512, LUT_PS = 96, LUT_PH = 80, LUT_BYTES = LUT_TH + LUT_P
 hipError_t launch_raytable(const RayTableP &P, double *dense, int32_t *cnt, int64_t *off, uint16_t *pix,
                            double *w64, int64_t *total, hipStream_t st);
 hipError_t launch_raytable_pack(const RayTableP &P, const int64_t *off, const uint16_t *pix, const double *w,
-                                uint32_t *rows, uint32_t *ent, uint4 *rows8, hipStream_t st);
+                                uint32_t *rows, uint32_t *ent, uint4 *rows8, double *quad_w64, hipStream_t st);
 size_t cols_smem_bytes(int npix, int cpw, bool fp64, int nthr);
 // cells per workgroup with the maps in LDS: 256 or 128 when their LDS fits in
 // 64 KB, else 0 (the maps are then accumulated in npix, 256 cells per group)
@@ -98,10 +99,12 @@ hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const 
                             const double4 *rec, const int32_t *ids, const double *lh, void *phi, void *acc,
                             void *npix, void *tau, double G, int cpw, bool newton_only, int *wg_per_cu,
                             hipStream_t st);
-// table rows of the offsets (i, j, k) cell sizes between two cells of one size,
-// |i|, |j|, |k| <= R, into lat [(2R + 1)^3] (k slowest, i fastest; -1 at the
-// origin) and their rows8 records into lat8 [(2R + 1)^3][2] (zero at the origin)
-hipError_t launch_lattice_rows(const ColP &C, int R, uint32_t *rows, uint4 *rows8, hipStream_t st);
+// rows of the offsets (i, j, k) cell sizes between two cells of one size,
+// |i|, |j|, |k| <= R (k slowest, i fastest), written at rows C.lat0 + ... of
+// rows, rows8 and quad_w64: copies of the table rows that the walk's binning
+// gives them (an empty row at the origin)
+hipError_t launch_lattice_rows(const ColP &C, int R, uint32_t *rows, uint4 *rows8, double *quad_w64,
+                               hipStream_t st);
 
 hipError_t launch_build(const DevTree &T, const double *rho, int *bad,
                         const std::vector<int64_t> &level_begin, int lmax, hipStream_t st);
