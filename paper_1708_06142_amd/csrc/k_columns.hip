@@ -349,7 +349,7 @@ __device__ inline void grav32(const EwaldP &E, float dx, float dy, float dz, flo
 // a wave's 64 cells are adjacent): for maps too large for LDS at a useful
 // occupancy (192 pixels take 768 bytes per cell in FP32).
 template <typename Real, int BC, bool NEWTON, bool GMAP, bool LATTICE = !GMAP>
-__global__ __launch_bounds__(256) void k_eval_cols(DevTree T, EwaldP E, ColP C, const int64_t *__restrict__ off,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_eval_cols(DevTree T, EwaldP E, ColP C, const int64_t *__restrict__ off,
                                                    const double4 *__restrict__ rec,
                                                    const int32_t *__restrict__ ids, const double *__restrict__ lh,
                                                    Real *__restrict__ phi, Real *__restrict__ acc,
