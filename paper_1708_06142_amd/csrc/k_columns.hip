@@ -11,11 +11,15 @@
 //    into LDS, then each lane sums its own pixels over the samples in order,
 //    so the sums are deterministic.
 // 3. Column walk: like the gravity walk, plus for every (cell, node) pair the
-//    direction bins (FP64), the table row, and N_p += w M / (Omega_pix d^2) in
-//    a per-cell pixel map held in LDS as [pixel][cell] (each thread owns its
-//    cell's column: plain read-modify-write in list order, no atomics, no
-//    bank conflicts).  At the end each cell's map
-//    and tau_avg = -ln(mean_p exp(-kappa N_p)) are written out.
+//    direction bins (FP64; for cells of the block's own size on a dyadic grid
+//    a precomputed lattice row), the table row's four-slot record, and
+//    N_p += w M / (Omega_pix d^2) in a per-cell pixel map held in LDS as
+//    [pixel][cell] (each thread owns its cell's column: plain
+//    read-modify-write, no atomics, no bank conflicts), or in place in the
+//    output when the maps are too large for LDS.  The record loads run two
+//    pairs ahead of the map updates; rows of more than four pixels finish
+//    from a per-thread queue at the end of each list tile.  At the end each
+//    cell's map and tau_avg = -ln(mean_p exp(-kappa N_p)) are written out.
 #include <type_traits>
 
 #include "common.hpp"
