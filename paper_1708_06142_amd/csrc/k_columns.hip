@@ -235,8 +235,10 @@ __device__ inline int table_row(const ColP &C, const double *thr, const uint8_t 
   // only for den > 1e-20, so smaller den take the exact path)
   const bool safe = C.estimate && f2 > 1e-30f && (den > 1e-20f || dy == 0.0);
   const int k0t = lut[(int)fmaf(-dzf * rd, C.lut_th, C.lut_th)];
-  const int k0s = lut[LUT_TH + (int)fminf(rhs * rd, C.lut_ps)];
-  const float t = (float)ux * __builtin_amdgcn_rcpf(den + 1e-30f);
+  // (rhs rd >= 0: the median with 0 and the table size is the clamp; (float)ux
+  // is +-dxf exactly)
+  const int k0s = lut[LUT_TH + (int)__builtin_amdgcn_fmed3f(rhs * rd, 0.0f, C.lut_ps)];
+  const float t = (lower ? dxf : -dxf) * __builtin_amdgcn_rcpf(den + 1e-30f);
   const int k0p = lut[LUT_TH + LUT_PS + (int)fmaf(t, C.lut_ph, C.lut_ph)];
   int it = k0t + (int)pth(k0t + 1);
   int is = k0s + (int)pps(k0s + 1);
