@@ -266,9 +266,10 @@ std::vector<uint8_t> bin_luts(const ot::RayTableP &RP) {
 
 // Half-width of the lattice table (cells of a block's own size within LAT_R
 // cell sizes per axis): the walk takes a record to the table when all 512
-// cells of the block see it within the table, i.e. from up to LAT_R - 7 cells
-// before the block to LAT_R cells past its first cell (a block's near-field
-// cells reach one block before and two after it).  47^3 entries, 3.5 MB.
+// cells of the block see it within the table, i.e. from LAT_R - 7 cells before
+// the block's first cell to LAT_R cells after it.  In the lists of a 128^3
+// lognormal field under APE every cell of the block's own size lies inside.
+// 47^3 rows of 68 bytes (head, four-slot record, FP64 weights).
 constexpr int LAT_R = 23;
 
 ot::ColP col_params(ot_ctx *c);
