@@ -67,6 +67,7 @@ def lib():
         L.or_tree_nn.restype = i64
         L.or_tree_nn.argtypes = [vp]
         L.or_tree_export.argtypes = [vp] + [vp] * 7
+        L.or_tree_mpe_export.argtypes = [vp, vp, vp]
         L.or_block_list.restype = i64
         L.or_block_list.argtypes = [vp, i64, vp, i64]
         L.or_walk_group.argtypes = [vp, vp, vp, vp]
@@ -122,7 +123,7 @@ def make_params(grid, theta=0.5, eta_sb=1.2, mac="bh", a_lim=0.0, theta_pix=0.0,
         p.origin[k] = float(grid.origin[k])
     p.root_size = float(grid.root_size)
     p.G, p.theta, p.eta_sb, p.a_lim, p.theta_pix = G, theta, eta_sb, a_lim, theta_pix
-    p.mac = {"bh": 0, "ape": 1}[mac]
+    p.mac = {"bh": 0, "ape": 1, "mpe": 2}[mac]
     p.ewald = {"exact": 0, "table": 1}[ewald]
     p.ew_n, p.ew_alpha, p.ew_rcut2, p.ew_fcut2 = ew_n, ew_alpha, ew_rcut2, ew_fcut2
     p.nside, p.kappa, p.max_dist = nside, kappa, max_dist
@@ -165,6 +166,13 @@ class Tree:
         lib().or_tree_export(self.h, *(_ptr(out[k]) for k in
                                        ("alev", "acoord", "aleaf", "achild", "akey", "M", "com")))
         return out
+
+    def mpe_moments(self):
+        """B_2, B_3 of the na + 72 nb non-cell nodes (mac="mpe" only)."""
+        n = self.na + 72 * self.nb
+        B2, B3 = np.empty(n), np.empty(n)
+        lib().or_tree_mpe_export(self.h, _ptr(B2), _ptr(B3))
+        return B2, B3
 
     def block_list(self, lb):
         n = lib().or_block_list(self.h, lb, None, 0)

@@ -8,6 +8,8 @@
  *   - depth-first walk from the roots; a node is accepted by the MAC suite or
  *     opened (Sec. 2.1); geometric BH MAC, Eq. (1), with the safe box;
  *   - APE MAC, Eq. (6) with p = 1, against an absolute limit, Eq. (4);
+ *   - MPE MAC, Eq. (2) with p = 1 (B_2, B_3 of Eq. (3), summed over the
+ *     node's cells), against an absolute limit, Eq. (4);
  *   - monopole potential and acceleration, Eqs. (7) and (8);
  *   - reference solution by direct summation over all other cells (Sec. 3).
  *
@@ -19,7 +21,13 @@
  *   - the safe box is a cuboid of edge eta_SB h centred on the node's
  *     geometric centre; the target (point or box) must lie strictly outside;
  *   - the MAC distance is from the node's COM to the closest target point;
- *     BH accepts if h^2 < theta^2 d^2, APE if G M h^2 < a_lim d^4;
+ *     BH accepts if h^2 < theta^2 d^2, APE if G M h^2 < a_lim d^4, MPE if
+ *     d > b_max and G (3 B_2 d - 2 B_3) < a_lim d^3 (d - b_max)^2 (Eq. (2)
+ *     multiplied out), b_max the distance from the COM to the farthest corner;
+ *   - B_p = sum of m |r_i - r_a|^p over the node's cells: per leaf block a
+ *     partial sum over its cells in octant order (the walk's +1, +2, cell
+ *     nesting), the partials added in the amr-tree's depth-first octant order;
+ *     |d|^3 = d^2 sqrt(d^2);
  *   - leaf nodes (cells) are always accepted; the target cell itself is
  *     skipped by r^2 = 0 (the direct sum runs over "all the other cells");
  *   - periodic axes use the minimum image, wrapped to [-L/2, L/2).
@@ -206,6 +214,59 @@ static void moments(or_tree *t, int64_t id) {
   }
 }
 
+/* MPE moments, Eq. (3): B_2 and B_3 of node `id` about its own COM, as the
+ * sum of m |r_i - r_a|^2 and m |r_i - r_a|^3 over its cells.  The cells of a
+ * leaf-block subtree are visited in octant order (+1, +2, cell) and summed
+ * from zero into one partial per leaf block; an amr node adds its blocks'
+ * partials in depth-first octant order. */
+static void cells_partial(const or_tree *t, int64_t id, const double ra[3], double *s2, double *s3) {
+  int64_t ch[8];
+  if (id >= t->na + 72 * t->nb) {
+    double d2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      double d = t->com[3 * id + k] - ra[k];
+      d2 = d2 + d * d;
+    }
+    *s2 = *s2 + t->M[id] * d2;
+    *s3 = *s3 + t->M[id] * (d2 * sqrt(d2));
+    return;
+  }
+  or_children(t, id, ch);
+  for (int o = 0; o < 8; ++o) cells_partial(t, ch[o], ra, s2, s3);
+}
+
+static void amr_partials(const or_tree *t, int64_t id, const double ra[3], double *B2, double *B3) {
+  if (t->aleaf[id] >= 0) {
+    double s2 = 0.0, s3 = 0.0;
+    cells_partial(t, id, ra, &s2, &s3);
+    *B2 = *B2 + s2;
+    *B3 = *B3 + s3;
+    return;
+  }
+  for (int o = 0; o < 8; ++o) amr_partials(t, t->achild[8 * id + o], ra, B2, B3);
+}
+
+static void mpe_moments(or_tree *t) {
+  const int64_t nnode = t->na + 72 * t->nb;
+  t->B2 = (double *)calloc(nnode, sizeof(double));
+  t->B3 = (double *)calloc(nnode, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t id = 0; id < nnode; ++id) {
+    const double *ra = t->com + 3 * id;
+    double B2 = 0.0, B3 = 0.0;
+    if (id < t->na) amr_partials(t, id, ra, &B2, &B3);
+    else cells_partial(t, id, ra, &B2, &B3);
+    t->B2[id] = B2;
+    t->B3[id] = B3;
+  }
+}
+
+void or_tree_mpe_export(const or_tree *t, double *B2, double *B3) {
+  const int64_t nnode = t->na + 72 * t->nb;
+  if (t->B2 && B2) memcpy(B2, t->B2, sizeof(double) * nnode);
+  if (t->B3 && B3) memcpy(B3, t->B3, sizeof(double) * nnode);
+}
+
 or_tree *or_tree_new(const or_params *p, int64_t nb, const int32_t *level,
                      const int32_t *coord, const double *rho, int *err) {
   *err = 0;
@@ -321,6 +382,7 @@ or_tree *or_tree_new(const or_params *p, int64_t nb, const int32_t *level,
     t->com = (double *)malloc(sizeof(double) * 3 * t->nn);
     for (int64_t r = 0; r < t->nroots; ++r) moments(t, t->roots[r]);
     t->rho = NULL;
+    if (p->mac == 2) mpe_moments(t);
   }
   return t;
 }
@@ -329,6 +391,7 @@ void or_tree_free(or_tree *t) {
   if (!t) return;
   free(t->blev); free(t->bcoord); free(t->alev); free(t->acoord); free(t->akey);
   free(t->aleaf); free(t->achild); free(t->roots); free(t->M); free(t->S); free(t->com);
+  free(t->B2); free(t->B3);
   or_ewald_release(&t->ew);
   if (t->rt.off) or_raytable_free(&t->rt);
   free(t);
@@ -373,8 +436,17 @@ int or_accept(const or_tree *t, int64_t id, const double cT[3], double ext) {
   int ok;
   if (p->mac == 0) {
     ok = h * h < p->theta * p->theta * d2;
-  } else {
+  } else if (p->mac == 1) {
     ok = p->G * t->M[id] * h * h < p->a_lim * d2 * d2;
+  } else {
+    /* Eq. (2), p = 1: G / d^2 (1 - b/d)^-2 (3 B_2 / d^2 - 2 B_3 / d^3) < a_lim */
+    double b2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      double e = fabs(t->com[3 * id + k] - gc[k]) + 0.5 * h;
+      b2 = b2 + e * e;
+    }
+    double d = sqrt(d2), bmax = sqrt(b2), q = d - bmax;
+    ok = d > bmax && p->G * (3.0 * t->B2[id] * d - 2.0 * t->B3[id]) < p->a_lim * (d2 * d) * (q * q);
   }
   if (p->theta_pix > 0.0) ok = ok && (h * h < p->theta_pix * p->theta_pix * d2);
   return ok;

@@ -22,7 +22,7 @@ typedef struct {
   double eta_sb;      /* safe-box factor eta_SB (Sec. 2.1)                  */
   double a_lim;       /* APE absolute acceleration limit, Eqs. (4), (6)     */
   double theta_pix;   /* extra BH angle when columns are on; <= 0: off      */
-  int32_t mac;        /* 0 = BH, 1 = APE                                    */
+  int32_t mac;        /* 0 = BH, 1 = APE, 2 = MPE                           */
   int32_t ewald;      /* 0 = exact series, 1 = table (periodic/mixed only)  */
   int32_t ew_n;       /* table points per axis                              */
   int32_t ew_rcut2;   /* real-space cut-off |i|^2 (<= 0: 15 for 3P, 10 2P1I) */
@@ -48,6 +48,8 @@ typedef struct or_tree or_tree;
 or_tree *or_tree_new(const or_params *p, int64_t nb, const int32_t *level,
                      const int32_t *coord, const double *rho, int *err);
 void or_tree_free(or_tree *t);
+/* MPE moments B_2, B_3 [na + 72 nb] (node ids below the cells); mac = 2 only */
+void or_tree_mpe_export(const or_tree *t, double *B2, double *B3);
 int64_t or_tree_na(const or_tree *t);
 int64_t or_tree_nn(const or_tree *t);
 #endif

@@ -48,6 +48,7 @@ struct or_tree {
   int64_t nn;
   const double *rho; /* only during construction */
   double *M, *S, *com;
+  double *B2, *B3; /* MPE moments of the na + 72 nb non-cell nodes (MPE MAC only) */
   or_ewald ew;
   or_raytable rt;
 };
