@@ -48,7 +48,7 @@ typedef enum {
 } ot_status;
 
 typedef enum { OT_BC_ISOLATED = 0, OT_BC_PERIODIC = 1 } ot_bc;
-typedef enum { OT_MAC_BH = 0, OT_MAC_APE = 1 } ot_mac;
+typedef enum { OT_MAC_BH = 0, OT_MAC_APE = 1, OT_MAC_MPE = 2 } ot_mac;
 /* TABLE: FP64-generated table with the Taylor term (Sec. 2.2.4, second
  * approach); EXACT: the FP64 series itself (point evaluation only); MLP: the
  * learned surrogate once ot_mlp_train (or ot_mlp_set) has accepted it, else
@@ -67,11 +67,12 @@ typedef struct {
   double G;              /* gravitational constant, App. B grv_bhNewton         [1.0]  */
   double theta_lim;      /* BH opening angle, Eq. (1), gr_bhTreeLimAngle        [0.5]  */
   double eta_sb;         /* safe-box factor, Sec. 2.1, gr_bhTreeSafeBox         [1.2]  */
-  int32_t mac;           /* ot_mac; APE uses Eq. (6) with p = 1, Eq. (4)        [BH]   */
+  int32_t mac;           /* ot_mac; APE uses Eq. (6) with p = 1, Eq. (4); MPE uses    */
+                         /* Eq. (2) with p = 1 (B_2, B_3 of Eq. (3)), Eq. (4)  [BH]   */
   int32_t ewald;         /* ot_ewald: correction in the walk: TABLE or MLP (the
                             FP32 walks, with or without columns; the FP64 walks
                             use the table); EXACT is rejected by the walk     [TABLE] */
-  double a_lim;          /* APE absolute limit, Eq. (4); <= 0: a_lim = eps_lim *
+  double a_lim;          /* APE/MPE absolute limit, Eq. (4); <= 0: a_lim = eps_lim *
                             a_max from a BH (theta_lim) FP64 pass, Sec. 3      [0]    */
   double eps_lim;        /* relative device of Sec. 3 for a_lim                 [1e-3] */
   int32_t ewald_n;       /* table points per axis (grv_bhEwaldNPer)             [64]   */

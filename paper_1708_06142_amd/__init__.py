@@ -144,7 +144,7 @@ def _stream(stream):
     return C.c_void_p(s.cuda_stream)
 
 
-MAC = {"bh": 0, "ape": 1}
+MAC = {"bh": 0, "ape": 1, "mpe": 2}
 
 
 def make_params(nroot=(1, 1, 1), root_size=1.0, origin=(0.0, 0.0, 0.0), bc=(0, 0, 0), G=1.0,

@@ -83,6 +83,8 @@ ot::DevTree dev_tree(ot_ctx *c) {
   T.aS = P<double4>(c->aS);
   T.btmc = P<double4>(c->btmc);
   T.cm = P<double>(c->cm);
+  T.abq = P<double2>(c->mpe_a);
+  T.bbq = P<double2>(c->mpe_b);
   T.na = c->topo.na;
   T.nb = c->topo.nb;
   T.nroots = (int32_t)c->topo.nroots;
@@ -123,6 +125,35 @@ ot_status upload_topology(ot_ctx *c, hipStream_t st) {
   OTCHK(dalloc(c, c->btmc, t.nb * 72 * sizeof(double4)));
   OTCHK(dalloc(c, c->cm, t.nb * 512 * sizeof(double)));
   OTCHK(dalloc(c, c->flag, 64));
+  if (c->p.mac == OT_MAC_MPE) {
+    // the leaf blocks under each amr node in depth-first octant order
+    std::vector<int32_t> pnode, pblock;
+    std::vector<int64_t> poff(t.na + 1, 0);
+    std::vector<int64_t> stack;
+    for (int64_t i = 0; i < t.na; ++i) {
+      poff[i] = (int64_t)pblock.size();
+      stack.assign(1, i);
+      while (!stack.empty()) {
+        const int64_t a = stack.back();
+        stack.pop_back();
+        if (t.aleaf[a] >= 0) {
+          pnode.push_back((int32_t)i);
+          pblock.push_back((int32_t)t.aleaf[a]);
+        } else {
+          for (int o = 7; o >= 0; --o) stack.push_back(t.achild[8 * a + o]);
+        }
+      }
+    }
+    poff[t.na] = (int64_t)pblock.size();
+    c->mpe_npairs = (int64_t)pblock.size();
+    OTCHK(upload(c, c->mpe_pnode, pnode, st));
+    OTCHK(upload(c, c->mpe_pblock, pblock, st));
+    OTCHK(upload(c, c->mpe_poff, poff, st));
+    OTCHK(dalloc(c, c->mpe_part, std::max<int64_t>(c->mpe_npairs, 1) * sizeof(double2)));
+    OTCHK(dalloc(c, c->mpe_a, t.na * sizeof(double2)));
+    OTCHK(dalloc(c, c->mpe_b, t.nb * 72 * sizeof(double2)));
+    HIPCHK(hipStreamSynchronize(st));  // the host vectors end here
+  }
   HIPCHK(hipStreamSynchronize(st));
   c->dev_topo = true;
   return OT_OK;
@@ -558,7 +589,7 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
   const bool use_mlp = c->bctype != ot::BC_ISO && c->p.ewald == OT_EWALD_MLP && c->mlp_ok && !fp64;
   if (cols) OTCHK(raytable_prepare(c, st));
   double alim = 0.0;
-  if (c->p.mac == OT_MAC_APE) OTCHK(ape_limit(c, st, &alim));
+  if (c->p.mac == OT_MAC_APE || c->p.mac == OT_MAC_MPE) OTCHK(ape_limit(c, st, &alim));
   for (int i = 0; i < 4; ++i)
     if (!c->ev[i]) HIPCHK(hipEventCreate(&c->ev[i]));
   HIPCHK(hipEventRecord(c->ev[0], st));
@@ -662,10 +693,10 @@ ot_status ot_create(const ot_params *p, ot_ctx **out) {
   if (!(p->G > 0) || !std::isfinite(p->G)) return bad("G must be > 0");
   if (!(p->theta_lim > 0) || !std::isfinite(p->theta_lim)) return bad("theta_lim must be > 0");
   if (!(p->eta_sb >= 0) || !std::isfinite(p->eta_sb)) return bad("eta_sb must be >= 0");
-  if (p->mac != OT_MAC_BH && p->mac != OT_MAC_APE) return bad("unknown MAC");
+  if (p->mac != OT_MAC_BH && p->mac != OT_MAC_APE && p->mac != OT_MAC_MPE) return bad("unknown MAC");
   if (p->ewald != OT_EWALD_TABLE && p->ewald != OT_EWALD_EXACT && p->ewald != OT_EWALD_MLP)
     return bad("unknown Ewald mode");
-  if (p->mac == OT_MAC_APE && !(p->a_lim > 0) && !(p->eps_lim > 0)) return bad("APE needs a_lim > 0 or eps_lim > 0");
+  if (p->mac != OT_MAC_BH && !(p->a_lim > 0) && !(p->eps_lim > 0)) return bad("APE/MPE need a_lim > 0 or eps_lim > 0");
   if (p->ewald_n < 2 || p->ewald_n > 512) return bad("ewald_n must be in [2, 512]");
   if (p->nside != 0 && p->nside != 1 && p->nside != 2 && p->nside != 4) return bad("nside must be 0, 1, 2 or 4");
   if (p->nside) {
@@ -726,6 +757,9 @@ ot_status ot_build(ot_ctx *c, const double *rho, void *stream) {
   HIPCHK(hipEventRecord(c->ev[0], st));
   ot::DevTree T = dev_tree(c);
   HIPCHK(ot::launch_build(T, rho, P<int>(c->flag), c->topo.level_begin, c->topo.lmax, st));
+  if (c->p.mac == OT_MAC_MPE)
+    HIPCHK(ot::launch_mpe(T, c->mpe_npairs, P<int32_t>(c->mpe_pnode), P<int32_t>(c->mpe_pblock),
+                          P<int64_t>(c->mpe_poff), P<double2>(c->mpe_part), st));
   HIPCHK(hipEventRecord(c->ev[3], st));
   HIPCHK(hipMemcpyAsync(&bad, c->flag.ptr, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1082,7 +1116,7 @@ void ot_destroy(ot_ctx *c) {
   DevBuf *all[] = {&c->alev, &c->acoord, &c->achild0, &c->aleaf, &c->blev,   &c->bcoord,
                    &c->bamr, &c->amc,    &c->aS,      &c->btmc,  &c->cm,     &c->flag,
                    &c->lcount, &c->loff, &c->lrec,    &c->lid,   &c->lscratch, &c->tab64,
-                   &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_rows, &c->rt_ent, &c->rt_rows8, &c->rt_quad64, &c->rt_lut,
+                   &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_rows, &c->rt_ent, &c->rt_rows8, &c->rt_quad64, &c->mpe_a, &c->mpe_b, &c->mpe_pnode, &c->mpe_pblock, &c->mpe_poff, &c->mpe_part, &c->rt_lut,
                    &c->rt_thr, &c->lh, &c->mlp_P, &c->mlp_pk, &c->mlp_part, &c->mlp_lossp,
                    &c->mlp_loss};
   for (DevBuf *b : all) release(c, *b);

@@ -29,6 +29,8 @@ struct DevTree {
   double4 *aS;            // [na] {S.x, S.y, S.z, 0}: sum of m x (build only)
   double4 *btmc;          // [nb*72] +1 nodes (8) then +2 nodes (64)
   double *cm;             // [nb*512] cell masses
+  double2 *abq;           // [na] MPE moments {B_2, B_3} (MPE MAC only, else null)
+  double2 *bbq;           // [nb*72] the same for the +1 and +2 nodes
   int64_t na, nb;
   int32_t nroots;
   int32_t per[3];         // periodic axis flags

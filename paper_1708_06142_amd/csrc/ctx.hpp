@@ -50,6 +50,10 @@ struct ot_ctx {
   std::vector<ot::DevBuf *> bufs;
   // topology + moments
   ot::DevBuf alev, acoord, achild0, aleaf, blev, bcoord, bamr, amc, aS, btmc, cm, flag;
+  // MPE moments: {B_2, B_3} of the amr and +1/+2 nodes, and the (amr node,
+  // leaf block) pairs of their per-block partial sums, grouped by node
+  ot::DevBuf mpe_a, mpe_b, mpe_pnode, mpe_pblock, mpe_poff, mpe_part;
+  int64_t mpe_npairs = 0;
   // interaction lists
   ot::DevBuf lcount, loff, lrec, lid, lscratch;
   int64_t list_cap = 0;

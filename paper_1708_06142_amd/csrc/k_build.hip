@@ -117,6 +117,88 @@ __global__ __launch_bounds__(256) void k_amr_moments(DevTree T, int64_t begin, i
   T.aS[i] = make_double4(Sx, Sy, Sz, 0.0);
 }
 
+// MPE moments (Eqs. (2), (3)): B_2 and B_3 of a node about its own COM, the
+// sums of m |r_i - r_a|^2 and m |r_i - r_a|^3 over its cells, |d|^3 =
+// d^2 sqrt(d^2).  The cells of a leaf block are visited in octant order (+1,
+// +2, cell) into one partial sum per (node, block); an amr node adds its
+// blocks' partials in depth-first octant order.
+
+// m |x - ra|^2 and m |x - ra|^3 of cell ci of leaf block lb, added to s
+__device__ inline void mpe_cell(const DevTree &T, int64_t lb, int ci, double h, const double ra[3], double2 &s) {
+  const int ijk[3] = {ci & 7, (ci >> 3) & 7, ci >> 6};
+  double d2 = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const double d = centre_coord(T.org[k], 8 * (int64_t)T.bcoord[3 * lb + k] + ijk[k], h) - ra[k];
+    d2 = d2 + d * d;
+  }
+  const double m = T.cm[512 * lb + ci];
+  s.x = s.x + m * d2;
+  s.y = s.y + m * (d2 * sqrt(d2));
+}
+
+// +1 (threads 0..7) and +2 (8..71) nodes of one leaf block per workgroup
+__global__ __launch_bounds__(128) void k_mpe_block(DevTree T) {
+  const int64_t lb = blockIdx.x;
+  const int t = threadIdx.x;
+  if (t >= 72) return;
+  const double h = size_at(T.root_size, T.blev[lb]) / 8.0;
+  const double4 mc = T.btmc[lb * 72 + t];
+  const double ra[3] = {mc.x, mc.y, mc.z};
+  double2 s = make_double2(0.0, 0.0);
+  if (t < 8) {
+    for (int o2 = 0; o2 < 8; ++o2)
+      for (int o3 = 0; o3 < 8; ++o3) mpe_cell(T, lb, cell_index(t, o2, o3), h, ra, s);
+  } else {
+    const int o1 = (t - 8) >> 3, o2 = (t - 8) & 7;
+    for (int o3 = 0; o3 < 8; ++o3) mpe_cell(T, lb, cell_index(o1, o2, o3), h, ra, s);
+  }
+  T.bbq[lb * 72 + t] = s;
+}
+
+// one (amr node, leaf block under it) pair per thread: the block's partial
+__global__ __launch_bounds__(256) void k_mpe_pairs(DevTree T, int64_t npairs, const int32_t *__restrict__ pnode,
+                                                   const int32_t *__restrict__ pblock, double2 *__restrict__ part) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  const int64_t lb = pblock[p];
+  const double4 mc = T.amc[pnode[p]];
+  const double ra[3] = {mc.x, mc.y, mc.z};
+  const double h = size_at(T.root_size, T.blev[lb]) / 8.0;
+  double2 s = make_double2(0.0, 0.0);
+  for (int o1 = 0; o1 < 8; ++o1)
+    for (int o2 = 0; o2 < 8; ++o2)
+      for (int o3 = 0; o3 < 8; ++o3) mpe_cell(T, lb, cell_index(o1, o2, o3), h, ra, s);
+  part[p] = s;
+}
+
+// amr node i: its blocks' partials [poff[i], poff[i + 1]) in depth-first order
+__global__ __launch_bounds__(256) void k_mpe_amr(DevTree T, const int64_t *__restrict__ poff,
+                                                 const double2 *__restrict__ part) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= T.na) return;
+  double2 B = make_double2(0.0, 0.0);
+  for (int64_t p = poff[i]; p < poff[i + 1]; ++p) {
+    B.x = B.x + part[p].x;
+    B.y = B.y + part[p].y;
+  }
+  T.abq[i] = B;
+}
+
+hipError_t launch_mpe(const DevTree &T, int64_t npairs, const int32_t *pnode, const int32_t *pblock,
+                      const int64_t *poff, double2 *part, hipStream_t st) {
+  hipLaunchKernelGGL(k_mpe_block, dim3((unsigned)T.nb), dim3(128), 0, st, T);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (npairs > 0) {
+    hipLaunchKernelGGL(k_mpe_pairs, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, st, T, npairs, pnode,
+                       pblock, part);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_mpe_amr, dim3((unsigned)((T.na + 255) / 256)), dim3(256), 0, st, T, poff, part);
+  return hipGetLastError();
+}
+
 hipError_t launch_build(const DevTree &T, const double *rho, int *bad,
                         const std::vector<int64_t> &level_begin, int lmax, hipStream_t st) {
   hipLaunchKernelGGL(k_block_moments, dim3((unsigned)T.nb), dim3(64), 0, st, T, rho, bad);

@@ -8,7 +8,9 @@
 //   (ii) the MAC holds at the box point closest to the node's centre of mass
 //        (the closest-point distance the paper uses to decide what to export
 //        between processors, Sec. 2.1 figure): BH h^2 < theta^2 d^2, APE
-//        G M h^2 < a_lim d^4; with columns also h^2 < theta_pix^2 d^2.
+//        G M h^2 < a_lim d^4, MPE Eq. (2) with p = 1 (the moments B_2, B_3
+//        of Eq. (3)); with columns also h^2 < theta_pix^2 d^2.  The MPE
+//        bound falls with d, so the closest point is its largest value.
 // Cells are always accepted.  Compiled with FP contraction off so that the
 // accept/open decisions reproduce exactly.
 //
@@ -34,7 +36,7 @@ struct Target {
 };
 
 __device__ inline bool accept(const DevTree &T, const MacP &P, const Target &tg, double h,
-                              const double g[3], const double4 mc) {
+                              const double g[3], const double4 mc, const double2 bq) {
   const double half = P.half_eta * h;
   bool outside = false;
   for (int k = 0; k < 3; ++k) {
@@ -52,8 +54,19 @@ __device__ inline bool accept(const DevTree &T, const MacP &P, const Target &tg,
   bool ok;
   if (P.mac == 0) {
     ok = h * h < P.theta2 * d2;
-  } else {
+  } else if (P.mac == 1) {
     ok = P.G * mc.w * h * h < P.a_lim * d2 * d2;
+  } else {
+    // MPE, Eq. (2) with p = 1 multiplied out: d > b_max and
+    // G (3 B_2 d - 2 B_3) < a_lim d^3 (d - b_max)^2, b_max the distance from
+    // the COM to the node's farthest corner
+    double b2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double e = fabs(com[k] - g[k]) + 0.5 * h;
+      b2 = b2 + e * e;
+    }
+    const double d = sqrt(d2), bmax = sqrt(b2), q = d - bmax;
+    ok = d > bmax && P.G * (3.0 * bq.x * d - 2.0 * bq.y) < P.a_lim * (d2 * d) * (q * q);
   }
   if (P.use_pix) ok = ok && (h * h < P.tpix2 * d2);
   return ok;
@@ -141,7 +154,7 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
           double g[3];
           for (int k = 0; k < 3; ++k) g[k] = centre_coord(T.org[k], T.acoord[3 * node + k], s);
           mc = T.amc[node];
-          acc = accept(T, P, tg, s, g, mc);
+          acc = accept(T, P, tg, s, g, mc, P.mac == 2 ? T.abq[node] : make_double2(0.0, 0.0));
           if (!acc) {
             if (T.aleaf[node] >= 0) ol = true; else oi = true;
           }
@@ -182,7 +195,7 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
           g[k] = centre_coord(T.org[k], 2 * (int64_t)T.bcoord[3 * lb + k] + ((o1 >> k) & 1), s);
         }
         mc = T.btmc[(int64_t)lb * 72 + o1];
-        acc = accept(T, P, tg, s, g, mc);
+        acc = accept(T, P, tg, s, g, mc, P.mac == 2 ? T.bbq[(int64_t)lb * 72 + o1] : make_double2(0.0, 0.0));
         op = !acc;
       }
       Scan3 sc = scan3(acc, op, false, swave);
@@ -213,7 +226,8 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
           g[k] = centre_coord(T.org[k], pos, s);
         }
         mc = T.btmc[(int64_t)lb * 72 + 8 + 8 * o1 + o2];
-        acc = accept(T, P, tg, s, g, mc);
+        acc = accept(T, P, tg, s, g, mc,
+                     P.mac == 2 ? T.bbq[(int64_t)lb * 72 + 8 + 8 * o1 + o2] : make_double2(0.0, 0.0));
         op = !acc;
       }
       Scan3 sc = scan3(acc, op, false, swave);

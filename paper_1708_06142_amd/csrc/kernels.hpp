@@ -16,7 +16,7 @@ struct MacP {
   double G;
   double a_lim;
   double tpix2;
-  int mac;      // 0 BH, 1 APE
+  int mac;      // 0 BH, 1 APE, 2 MPE
   int use_pix;  // also require BH at theta_pix
 };
 
@@ -106,6 +106,11 @@ hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const 
 hipError_t launch_lattice_rows(const ColP &C, int R, uint32_t *rows, uint4 *rows8, double *quad_w64,
                                hipStream_t st);
 
+// MPE moments of every non-cell node (after launch_build): pairs p of (amr
+// node pnode[p], leaf block pblock[p]) grouped by node, poff [na + 1]; part
+// [npairs] scratch for the per-block partials
+hipError_t launch_mpe(const DevTree &T, int64_t npairs, const int32_t *pnode, const int32_t *pblock,
+                      const int64_t *poff, double2 *part, hipStream_t st);
 hipError_t launch_build(const DevTree &T, const double *rho, int *bad,
                         const std::vector<int64_t> &level_begin, int lmax, hipStream_t st);
 

@@ -71,15 +71,15 @@ def test_moments_bit_exact(name):
 
 
 @pytest.mark.parametrize("name", ["sphere32", "amr", "forest_offset"])
-@pytest.mark.parametrize("mac", ["bh", "ape"])
+@pytest.mark.parametrize("mac", ["bh", "ape", "mpe"])
 def test_lists_and_fp64_walk(name, mac):
     g = GRIDS[name]()
     kw = dict(theta=0.5)
-    if mac == "ape":
+    if mac != "bh":
         # a_lim chosen here (from the oracle's own BH walk), passed to both sides
         t0 = oracle.Tree(g, theta=0.5)
         _, a0, _ = t0.walk_group()
-        kw = dict(mac="ape", a_lim=1e-3 * np.sqrt((a0 ** 2).sum(0)).max())
+        kw = dict(mac=mac, a_lim=1e-3 * np.sqrt((a0 ** 2).sum(0)).max())
     t = oracle.Tree(g, **kw)
     pr, ar, nr = t.walk_group()
     p, a, st, s = gpu(g, fp64=True, **kw)
@@ -198,12 +198,12 @@ def lognormal128():
     return workloads.c2_lognormal(128)
 
 
-@pytest.mark.parametrize("mac", ["bh", "ape"])
+@pytest.mark.parametrize("mac", ["bh", "ape", "mpe"])
 def test_lognormal128_sampled(lognormal128, mac):
     """The 128^3 lognormal workload in the benchmark's launch configuration,
     checked on 24 sampled blocks against the oracle's group walk."""
     g = lognormal128
-    kw = dict(theta=0.5) if mac == "bh" else dict(mac="ape", a_lim=2.0e-3)
+    kw = dict(theta=0.5) if mac == "bh" else dict(mac=mac, a_lim=2.0e-3)
     sel = np.random.default_rng(1).choice(g.nb, 24, replace=False)
     t = oracle.Tree(g, **kw)
     pr, ar, nr = t.walk_group(sel)
