@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--surrogate-steps", type=int, default=2)
     ap.add_argument("--no-c5", action="store_true",
                     help="skip the large AMR leg (15.2M cells, 2P1I, 192-pixel columns)")
+    ap.add_argument("--no-mpe", action="store_true", help="skip the MPE MAC leg")
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the Plummer AMR leg (2.6M cells, box 1x1x4, 2P1I, 64^3 Ewald table)")
     return ap.parse_args()
@@ -267,6 +268,41 @@ def c3_leg(steps):
     return out
 
 
+def mpe_leg(grid, rho, a_lim, steps, nside):
+    """The benchmark field with the MPE MAC (Eq. (2) with p = 1) at the same
+    absolute limit: the whole path (tree build with the B_2, B_3 moments,
+    lists, FP32-Kahan and FP64 column walks)."""
+    import torch
+    import paper_1708_06142_amd as ot
+    n = grid.ncells
+    npx = 12 * nside ** 2
+    s = ot.Solver.for_grid(grid, mac="mpe", a_lim=a_lim, theta=0.5, nside=nside)
+    out = {"workload": f"lognormal {round(n ** (1 / 3))}^3, isolated, MPE a_lim={a_lim:.5g} (1e-3 a_max), "
+                       f"{npx}-pixel columns"}
+    res = {}
+    for label, fp64 in (("fp32", False), ("fp64", True)):
+        dt = torch.float64 if fp64 else torch.float32
+        outs = (torch.empty(n, dtype=dt, device="cuda"), torch.empty(3 * n, dtype=dt, device="cuda"))
+        if nside:
+            outs += (torch.empty(n * npx, dtype=dt, device="cuda"), torch.empty(n, dtype=dt, device="cuda"))
+        ms, st, ms_eval, ms_list, ms_build = timed_steps(s, rho, outs, fp64, steps, 1)
+        res[label] = outs
+        fpair = FLOP_PAIR_COLS if nside else FLOP_PAIR_ISO
+        fl = st.n_interactions * fpair / (ms_eval * 1e-3) / 1e12
+        peak = PEAK_FP64_VALU if fp64 else PEAK_FP32_VALU
+        out[label] = {"value": n / (ms * 1e-3), "unit": "cells/s", "ms_per_step": ms,
+                      "phases_ms": {"build": ms_build, "lists": ms_list, "eval": ms_eval},
+                      "n_int": st.n_interactions, "per_cell": st.n_interactions / n, "max_list": st.max_list,
+                      "roofline": {"bound": "alu", "achieved": fl, "peak": peak, "unit": "TFLOP/s",
+                                   "frac": fl / peak, "flop_per_pair": fpair}}
+    s.close()
+    (p32, a32) = res["fp32"][:2]
+    (p64, a64) = res["fp64"][:2]
+    out["fp32"]["dphi_rel_vs_fp64"] = float(((p32.double() - p64).abs() / p64.abs()).max())
+    out["fp32"]["da_maxnorm_vs_fp64"] = float((a32.double() - a64).abs().max() / a64.view(3, -1).pow(2).sum(0).sqrt().max())
+    return out
+
+
 def cpu_baseline(grid, a_lim, nblk, nside):
     """The FP64 oracle's group walk on a seeded sample of blocks, host cores."""
     import oracle
@@ -360,6 +396,8 @@ def main():
                             "eval_wg_per_cu": st64.eval_wg_per_cu}
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(grid, rho, args.surrogate_steps, args.nside)
+    if not args.no_mpe:
+        out["mpe"] = mpe_leg(grid, rho, a_lim, max(2, args.steps // 2), args.nside)
     if not args.no_c3:
         out["c3"] = c3_leg(max(2, args.steps // 2))
     if not args.no_c5:
