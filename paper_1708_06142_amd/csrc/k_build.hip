@@ -177,7 +177,18 @@ __global__ __launch_bounds__(256) void k_mpe_amr(DevTree T, const int64_t *__res
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= T.na) return;
   double2 B = make_double2(0.0, 0.0);
-  for (int64_t p = poff[i]; p < poff[i + 1]; ++p) {
+  const int64_t p1 = poff[i + 1];
+  int64_t p = poff[i];
+  // sixteen loads in flight, then the adds in order
+  for (; p + 16 <= p1; p += 16) {
+    double2 v[16];
+    for (int k = 0; k < 16; ++k) v[k] = part[p + k];
+    for (int k = 0; k < 16; ++k) {
+      B.x = B.x + v[k].x;
+      B.y = B.y + v[k].y;
+    }
+  }
+  for (; p < p1; ++p) {
     B.x = B.x + part[p].x;
     B.y = B.y + part[p].y;
   }
