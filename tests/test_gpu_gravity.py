@@ -223,13 +223,15 @@ def test_lognormal128_sampled(lognormal128, mac):
     check32(p32[cells], a32[:, cells], pr, ar)
 
 
-def test_lognormal128_tree_vs_direct(lognormal128):
+@pytest.mark.parametrize("mac", ["ape", "mpe"])
+def test_lognormal128_tree_vs_direct(lognormal128, mac):
     """The benchmark's accuracy claim: the FP32 walk at its MAC (APE with
-    a_lim = 1e-3 a_max, plus BH at theta_pix for the 48-pixel columns) against
-    the oracle's direct sum, on 128 seeded cells and the 64 cells of largest
-    |a|.  e_a = |a - a_dir| / max |a_dir|, e_phi = |Phi / Phi_dir - 1|."""
+    a_lim = 1e-3 a_max, plus BH at theta_pix for the 48-pixel columns; and
+    the MPE MAC at the same limit) against the oracle's direct sum, on 128
+    seeded cells and the 64 cells of largest |a|.  e_a = |a - a_dir| / max
+    |a_dir|, e_phi = |Phi / Phi_dir - 1|."""
     g = lognormal128
-    phi, acc, st, s, npix, tau = ot.run(g, fp64=False, mac="ape", eps_lim=1e-3, theta=0.5, nside=2)
+    phi, acc, st, s, npix, tau = ot.run(g, fp64=False, mac=mac, eps_lim=1e-3, theta=0.5, nside=2)
     p, a = phi.cpu().numpy().astype(np.float64), acc.cpu().numpy().astype(np.float64)
     amag = np.sqrt((a ** 2).sum(0))
     tg = np.unique(np.concatenate([np.random.default_rng(4).choice(g.ncells, 128, replace=False),
@@ -238,6 +240,6 @@ def test_lognormal128_tree_vs_direct(lognormal128):
     amax = np.sqrt((ad ** 2).sum(0)).max()
     ea = np.sqrt(((a[:, tg] - ad) ** 2).sum(0)) / amax
     ep = np.abs(p[tg] / pd - 1)
-    print(f"lognormal128 APE 1e-3 + columns MAC: e_a max {ea.max():.3e}, e_phi max {ep.max():.3e}, "
+    print(f"lognormal128 {mac} 1e-3 + columns MAC: e_a max {ea.max():.3e}, e_phi max {ep.max():.3e}, "
           f"a_lim {st.a_lim_used:.4g}")
     assert ea.max() <= 1e-3 and ep.max() <= 1e-3
