@@ -101,7 +101,7 @@ typedef struct {
   int64_t n_interactions;  /* sum over cells of accepted list entries (N_int) */
   int64_t max_list;        /* longest block interaction list                 */
   int64_t total_list;      /* sum of block list lengths                      */
-  double a_lim_used;       /* APE limit actually used (0 for BH)             */
+  double a_lim_used;       /* APE/MPE limit actually used (0 for BH)         */
   double ms_build;         /* tree build (moments), device time              */
   double ms_list;          /* interaction-list construction, device time      */
   double ms_eval;          /* per-cell evaluation, device time               */
@@ -127,8 +127,11 @@ ot_status ot_set_blocks(ot_ctx *c, int64_t nb, const int32_t *level_host,
 
 /* Tree build, Sec. 2.1: cell masses m = rho h^3 and, bottom-up, each node's
  * mass and centre of mass in FP64 (children summed in octant order; leaf
- * COM = cell centre).  rho_dev: [nb*512] FP64 device array, finite, >= 0
- * (OT_ERR_NUMERIC otherwise, checked on the device). */
+ * COM = cell centre); with the MPE MAC also each node's B_2 and B_3 of
+ * Eq. (3) about its COM (per leaf block a partial over its cells in octant
+ * order, an amr node adding its blocks' partials depth first).  rho_dev:
+ * [nb*512] FP64 device array, finite, >= 0 (OT_ERR_NUMERIC otherwise,
+ * checked on the device). */
 ot_status ot_build(ot_ctx *c, const double *rho_dev, void *stream);
 
 /* Tree walk, Sec. 2.1 + 2.2 + 2.3: one interaction list per leaf block (all
