@@ -68,6 +68,7 @@ def lib():
         L.or_tree_nn.argtypes = [vp]
         L.or_tree_export.argtypes = [vp] + [vp] * 7
         L.or_tree_mpe_export.argtypes = [vp, vp, vp]
+        L.or_walk_group_abu.argtypes = [vp, vp, vp, C.c_double, vp, vp, vp]
         L.or_block_list.restype = i64
         L.or_block_list.argtypes = [vp, i64, vp, i64]
         L.or_walk_group.argtypes = [vp, vp, vp, vp]
@@ -173,6 +174,16 @@ class Tree:
         B2, B3 = np.empty(n), np.empty(n)
         lib().or_tree_mpe_export(self.h, _ptr(B2), _ptr(B3))
         return B2, B3
+
+    def walk_abu(self, prev_phi, prev_acc, tol):
+        """Adaptive block update (gravity only): returns phi [nb*512], acc [3, nb*512]
+        and updated [nb] (1 where the block was evaluated)."""
+        n = 512 * self.nb
+        pp = np.ascontiguousarray(prev_phi, dtype=np.float64).reshape(n)
+        pa = np.ascontiguousarray(prev_acc, dtype=np.float64).reshape(3, n)
+        phi, acc, upd = np.empty(n), np.empty((3, n)), np.empty(self.nb, np.int32)
+        lib().or_walk_group_abu(self.h, _ptr(pp), _ptr(pa), float(tol), _ptr(phi), _ptr(acc), _ptr(upd))
+        return phi, acc, upd
 
     def block_list(self, lb):
         n = lib().or_block_list(self.h, lb, None, 0)

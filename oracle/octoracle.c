@@ -11,6 +11,7 @@
  *   - MPE MAC, Eq. (2) with p = 1 (B_2, B_3 of Eq. (3), summed over the
  *     node's cells), against an absolute limit, Eq. (4);
  *   - monopole potential and acceleration, Eqs. (7) and (8);
+ *   - adaptive block update (Sec. 2.2.5) from the eight corner cells;
  *   - reference solution by direct summation over all other cells (Sec. 3).
  *
  * Readings of the paper taken here (they bind the GPU library as well):
@@ -599,6 +600,50 @@ void or_walk_group_blocks(const or_tree *t, int64_t nsel, const int64_t *sel, do
       }
     }
     free(map);
+    free(l.v);
+  }
+}
+
+/* Adaptive block update (Sec. 2.2.5): per leaf block the group walk first
+ * evaluates the eight corner cells (i, j, k in {0, 7}); when at each of them
+ * the acceleration differs from the previous step's by less than tol (the
+ * Euclidean norm of the difference, an absolute accuracy as in Eq. (4)), the
+ * block keeps the previous values of all its cells, else all 512 cells are
+ * evaluated.  prev_* and the outputs are full-size ([nb*512], acc
+ * [3][nb*512]); updated[lb] = 1 where the block was evaluated. */
+void or_walk_group_abu(const or_tree *t, const double *prev_phi, const double *prev_acc, double tol,
+                       double *phi, double *acc, int32_t *updated) {
+  const int64_t ncell = 512 * t->nb;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t lb = 0; lb < t->nb; ++lb) {
+    idlist l = group_list(t, lb);
+    int changed = 0;
+    for (int k = 0; k < 8; ++k) {
+      const int ci = 7 * (k & 1) + 56 * ((k >> 1) & 1) + 448 * ((k >> 2) & 1);
+      double x[3], ph, a[3];
+      or_cell_centre(t, lb, ci, x);
+      sum_list(t, x, l.v, l.n, &ph, a, NULL);
+      double d2 = 0.0;
+      for (int q = 0; q < 3; ++q) {
+        const double d = a[q] - prev_acc[q * ncell + 512 * lb + ci];
+        d2 = d2 + d * d;
+      }
+      if (!(sqrt(d2) < tol)) changed = 1;
+    }
+    updated[lb] = changed;
+    for (int ci = 0; ci < 512; ++ci) {
+      const int64_t o = 512 * lb + ci;
+      if (changed) {
+        double x[3], ph, a[3];
+        or_cell_centre(t, lb, ci, x);
+        sum_list(t, x, l.v, l.n, &ph, a, NULL);
+        phi[o] = ph;
+        for (int q = 0; q < 3; ++q) acc[q * ncell + o] = a[q];
+      } else {
+        phi[o] = prev_phi[o];
+        for (int q = 0; q < 3; ++q) acc[q * ncell + o] = prev_acc[q * ncell + o];
+      }
+    }
     free(l.v);
   }
 }

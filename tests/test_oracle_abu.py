@@ -1,0 +1,50 @@
+"""Pins of the oracle's adaptive block update (Sec. 2.2.5): with a zero
+tolerance it is the plain group walk; on an unchanged density it keeps every
+block; on a locally perturbed density its block decisions are those of the
+corner criterion applied to an independent full walk, and each block holds
+either the full walk's values or the previous ones."""
+import numpy as np
+
+import oracle
+import workloads
+
+CORNERS = np.array([7 * (k & 1) + 56 * ((k >> 1) & 1) + 448 * ((k >> 2) & 1) for k in range(8)])
+
+
+def _perturbed(g, amp=0.5, centre=(0.2, 0.2, 0.2), width=0.08):
+    x = workloads.cell_centres(g.root_size, g.origin, g.level, g.coord)
+    r2 = ((x - np.array(centre)) ** 2).sum(-1)
+    rho = g.rho * (1.0 + amp * np.exp(-r2 / (2 * width ** 2)))
+    return workloads.Grid(g.nroot, g.root_size, g.origin, g.level, g.coord, rho, g.bc, g.name)
+
+
+def test_zero_tolerance_is_the_plain_walk_and_unchanged_density_keeps_all():
+    g = workloads.small_amr()
+    t = oracle.Tree(g, theta=0.5)
+    p0, a0, _ = t.walk_group()
+    p, a, upd = t.walk_abu(np.zeros_like(p0), np.zeros_like(a0), 0.0)
+    assert upd.all()
+    assert np.array_equal(p, p0) and np.array_equal(a, a0)
+    p, a, upd = t.walk_abu(p0, a0, 1e-12)
+    assert not upd.any()
+    assert np.array_equal(p, p0) and np.array_equal(a, a0)
+
+
+def test_local_perturbation_follows_the_corner_criterion():
+    g = workloads.small_amr()
+    p0, a0, _ = oracle.Tree(g, theta=0.5).walk_group()
+    g1 = _perturbed(g)
+    t1 = oracle.Tree(g1, theta=0.5)
+    p1, a1, _ = t1.walk_group()
+    amax = np.sqrt((a1 ** 2).sum(0)).max()
+    tol = 1e-3 * amax
+    p, a, upd = t1.walk_abu(p0, a0, tol)
+    da = np.sqrt(((a1 - a0) ** 2).sum(0)).reshape(g.nb, 512)[:, CORNERS].max(1)
+    assert np.array_equal(upd.astype(bool), ~(da < tol))
+    assert 0 < upd.sum() < g.nb
+    pb, ab = p.reshape(g.nb, 512), a.reshape(3, g.nb, 512)
+    for arr, new, old in ((pb, p1.reshape(g.nb, 512), p0.reshape(g.nb, 512)),
+                          (ab, a1.reshape(3, g.nb, 512), a0.reshape(3, g.nb, 512))):
+        sel = upd.astype(bool)
+        assert np.array_equal(arr[..., sel, :], new[..., sel, :])
+        assert np.array_equal(arr[..., ~sel, :], old[..., ~sel, :])
