@@ -640,9 +640,96 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
   return OT_OK;
 }
 
+// Adaptive block update (Sec. 2.2.5), gravity only: the eight corner cells of
+// every block first (FP64, against the previous acceleration in acc), then the
+// full evaluation of the blocks where one of them moved by tol or more; the
+// other blocks keep phi and acc.
+ot_status abu_impl(ot_ctx *c, bool fp64, void *phi, void *acc, double tol, int32_t *updated, ot_stats *stats,
+                   void *stream) {
+  if (!c) return OT_ERR_INVALID_ARG;
+  c->err.clear();
+  if (!phi || !acc) return fail(c, OT_ERR_INVALID_ARG, "phi and acc must be device pointers");
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(c, OT_ERR_INVALID_ARG, "tol must be finite and >= 0");
+  if (c->p.nside > 0) return fail(c, OT_ERR_UNSUPPORTED, "the adaptive block update covers gravity only (nside 0)");
+  if (!c->built) return fail(c, OT_ERR_STATE, "ot_solve_abu before a successful ot_build");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->p.device));
+  if (c->bctype != ot::BC_ISO) {
+    if (c->p.ewald == OT_EWALD_EXACT)
+      return fail(c, OT_ERR_UNSUPPORTED, "per-pair exact Ewald series is not built into the walk");
+    if (c->p.ewald == OT_EWALD_MLP && !fp64)
+      return fail(c, OT_ERR_UNSUPPORTED, "the adaptive block update uses the Ewald table");
+    OTCHK(ewald_prepare(c, st));
+  }
+  double alim = 0.0;
+  if (c->p.mac == OT_MAC_APE || c->p.mac == OT_MAC_MPE) OTCHK(ape_limit(c, st, &alim));
+  for (int i = 0; i < 4; ++i)
+    if (!c->ev[i]) HIPCHK(hipEventCreate(&c->ev[i]));
+  const int64_t nb = c->topo.nb;
+  if (!c->abu_flag.ptr) {
+    OTCHK(dalloc(c, c->abu_flag, nb * sizeof(int32_t)));
+    OTCHK(dalloc(c, c->abu_blist, nb * sizeof(int32_t)));
+  }
+  HIPCHK(hipEventRecord(c->ev[0], st));
+  OTCHK(build_lists(c, mac_params(c, c->p.mac, alim, false), false, st));
+  HIPCHK(hipEventRecord(c->ev[1], st));
+  ot::DevTree T = dev_tree(c);
+  ot::EwaldP E = ewald_desc(c);
+  HIPCHK(hipMemsetAsync(c->abu_flag.ptr, 0, nb * sizeof(int32_t), st));
+  HIPCHK(ot::launch_abu_corners(fp64, T, E, P<int64_t>(c->loff), P<double4>(c->lrec), acc, c->p.G, tol,
+                                P<int32_t>(c->abu_flag), st));
+  std::vector<int32_t> flag(nb), blist;
+  HIPCHK(hipMemcpyAsync(flag.data(), c->abu_flag.ptr, nb * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int64_t b = 0; b < nb; ++b)
+    if (flag[b]) blist.push_back((int32_t)b);
+  if (updated) memcpy(updated, flag.data(), nb * sizeof(int32_t));
+  const int64_t nup = (int64_t)blist.size();
+  if (nup > 0)
+    HIPCHK(hipMemcpyAsync(c->abu_blist.ptr, blist.data(), nup * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  if (fp64)
+    HIPCHK(ot::launch_eval64(T, E, P<int64_t>(c->loff), P<double4>(c->lrec), (double *)phi, (double *)acc, c->p.G,
+                             st, P<int32_t>(c->abu_blist), nup));
+  else
+    HIPCHK(ot::launch_eval32(T, E, P<int64_t>(c->loff), P<double4>(c->lrec), P<int32_t>(c->lid), (float *)phi,
+                             (float *)acc, c->p.G, st, P<int32_t>(c->abu_blist), nup));
+  HIPCHK(hipEventRecord(c->ev[2], st));
+  c->off_host.resize(nb + 1);
+  HIPCHK(hipMemcpyAsync(c->off_host.data(), c->loff.ptr, (nb + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));  // also keeps blist alive until its copy is done
+  c->lists_valid = true;
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    int64_t mx = 0, tot_up = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+      mx = std::max(mx, c->off_host[b + 1] - c->off_host[b]);
+      if (flag[b]) tot_up += c->off_host[b + 1] - c->off_host[b] - 1;
+    }
+    stats->total_list = c->off_host[nb];
+    stats->max_list = mx;
+    stats->n_interactions = 512 * tot_up;  // pairs of the blocks evaluated in full
+    stats->a_lim_used = alim;
+    stats->ms_list = elapsed(c->ev[0], c->ev[1]);
+    stats->ms_eval = elapsed(c->ev[1], c->ev[2]);
+    stats->ms_build = c->ms_build;
+    stats->ewald_used = OT_EWALD_TABLE;
+  }
+  return OT_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+ot_status ot_solve_abu(ot_ctx *c, float *phi, float *acc, double tol, int32_t *updated_host, ot_stats *stats,
+                       void *stream) {
+  return abu_impl(c, false, phi, acc, tol, updated_host, stats, stream);
+}
+
+ot_status ot_solve_abu64(ot_ctx *c, double *phi, double *acc, double tol, int32_t *updated_host,
+                         ot_stats *stats, void *stream) {
+  return abu_impl(c, true, phi, acc, tol, updated_host, stats, stream);
+}
 
 void ot_params_default(ot_params *p) {
   if (!p) return;
@@ -1116,7 +1203,7 @@ void ot_destroy(ot_ctx *c) {
   DevBuf *all[] = {&c->alev, &c->acoord, &c->achild0, &c->aleaf, &c->blev,   &c->bcoord,
                    &c->bamr, &c->amc,    &c->aS,      &c->btmc,  &c->cm,     &c->flag,
                    &c->lcount, &c->loff, &c->lrec,    &c->lid,   &c->lscratch, &c->tab64,
-                   &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_rows, &c->rt_ent, &c->rt_rows8, &c->rt_quad64, &c->mpe_a, &c->mpe_b, &c->mpe_pnode, &c->mpe_pblock, &c->mpe_poff, &c->mpe_part, &c->rt_lut,
+                   &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_rows, &c->rt_ent, &c->rt_rows8, &c->rt_quad64, &c->mpe_a, &c->mpe_b, &c->mpe_pnode, &c->mpe_pblock, &c->mpe_poff, &c->mpe_part, &c->abu_flag, &c->abu_blist, &c->rt_lut,
                    &c->rt_thr, &c->lh, &c->mlp_P, &c->mlp_pk, &c->mlp_part, &c->mlp_lossp,
                    &c->mlp_loss};
   for (DevBuf *b : all) release(c, *b);

@@ -54,6 +54,7 @@ struct ot_ctx {
   // leaf block) pairs of their per-block partial sums, grouped by node
   ot::DevBuf mpe_a, mpe_b, mpe_pnode, mpe_pblock, mpe_poff, mpe_part;
   int64_t mpe_npairs = 0;
+  ot::DevBuf abu_flag, abu_blist;  // adaptive block update: per-block flags, updated blocks
   // interaction lists
   ot::DevBuf lcount, loff, lrec, lid, lscratch;
   int64_t list_cap = 0;

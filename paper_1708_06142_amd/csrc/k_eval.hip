@@ -76,9 +76,9 @@ template <int BC>
 __global__ __launch_bounds__(WG) void k_eval64(DevTree T, EwaldP E, const int64_t *__restrict__ off,
                                                const double4 *__restrict__ rec,
                                                double *__restrict__ phi, double *__restrict__ acc,
-                                               double negG) {
+                                               double negG, const int32_t *__restrict__ blist) {
   __shared__ double4 tile[WG];
-  const int64_t b = blockIdx.x;
+  const int64_t b = blist ? (int64_t)blist[blockIdx.x] : (int64_t)blockIdx.x;
   const int tid = threadIdx.x;
   const int64_t ncell = T.nb * 512;
   const double h = size_at(T.root_size, T.blev[b]) / 8.0;
@@ -193,9 +193,9 @@ template <int BC>
 __global__ __launch_bounds__(WG) void k_eval32(DevTree T, EwaldP E, const int64_t *__restrict__ off,
                                                const double4 *__restrict__ rec, const int32_t *__restrict__ ids,
                                                float *__restrict__ phi, float *__restrict__ acc,
-                                               float negG) {
+                                               float negG, const int32_t *__restrict__ blist) {
   __shared__ float4 tile[WG];
-  const int64_t b = blockIdx.x;
+  const int64_t b = blist ? (int64_t)blist[blockIdx.x] : (int64_t)blockIdx.x;
   const int tid = threadIdx.x;
   const int64_t ncell = T.nb * 512;
   const double sb = size_at(T.root_size, T.blev[b]);
@@ -278,24 +278,77 @@ __global__ __launch_bounds__(256) void k_amax(const double *__restrict__ acc, in
 }  // namespace
 
 hipError_t launch_eval64(const DevTree &T, const EwaldP &E, const int64_t *off, const double4 *rec,
-                         double *phi, double *acc, double G, hipStream_t st) {
-  dim3 grid((unsigned)T.nb), blk(WG);
+                         double *phi, double *acc, double G, hipStream_t st, const int32_t *blist,
+                         int64_t nblist) {
+  if (blist && nblist <= 0) return hipSuccess;
+  dim3 grid((unsigned)(blist ? nblist : T.nb)), blk(WG);
   switch (E.bctype) {
-    case 0: hipLaunchKernelGGL(k_eval64<0>, grid, blk, 0, st, T, E, off, rec, phi, acc, -G); break;
-    case 1: hipLaunchKernelGGL(k_eval64<1>, grid, blk, 0, st, T, E, off, rec, phi, acc, -G); break;
-    default: hipLaunchKernelGGL(k_eval64<2>, grid, blk, 0, st, T, E, off, rec, phi, acc, -G); break;
+    case 0: hipLaunchKernelGGL(k_eval64<0>, grid, blk, 0, st, T, E, off, rec, phi, acc, -G, blist); break;
+    case 1: hipLaunchKernelGGL(k_eval64<1>, grid, blk, 0, st, T, E, off, rec, phi, acc, -G, blist); break;
+    default: hipLaunchKernelGGL(k_eval64<2>, grid, blk, 0, st, T, E, off, rec, phi, acc, -G, blist); break;
   }
   return hipGetLastError();
 }
 
+// Adaptive block update (Sec. 2.2.5): the eight corner cells (i, j, k in
+// {0, 7}) of every leaf block, walked in FP64 over the block's list (one
+// thread per corner); flags[b] = 1 when at one of them |a_new - a_prev| >=
+// tol.  flags must be zero on entry.
+template <int BC, typename Real>
+__global__ __launch_bounds__(256) void k_abu_corners(DevTree T, EwaldP E, const int64_t *__restrict__ off,
+                                                     const double4 *__restrict__ rec,
+                                                     const Real *__restrict__ prev_acc, double negG, double tol,
+                                                     int32_t *__restrict__ flags) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T.nb * 8) return;
+  const int64_t b = t >> 3;
+  const int k = (int)(t & 7);
+  const int ci = 7 * (k & 1) + 56 * ((k >> 1) & 1) + 448 * ((k >> 2) & 1);
+  const double h = size_at(T.root_size, T.blev[b]) / 8.0;
+  const double cx = centre_coord(T.org[0], 8 * (int64_t)T.bcoord[3 * b] + (ci & 7), h);
+  const double cy = centre_coord(T.org[1], 8 * (int64_t)T.bcoord[3 * b + 1] + ((ci >> 3) & 7), h);
+  const double cz = centre_coord(T.org[2], 8 * (int64_t)T.bcoord[3 * b + 2] + (ci >> 6), h);
+  double sp = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
+  for (int64_t j = off[b]; j < off[b + 1]; ++j) pair64<BC>(E, cx, cy, cz, rec[j], sp, ax, ay, az);
+  const int64_t ncell = T.nb * 512, o = b * 512 + ci;
+  const double dx = negG * ax - (double)prev_acc[o], dy = negG * ay - (double)prev_acc[ncell + o];
+  const double dz = negG * az - (double)prev_acc[2 * ncell + o];
+  if (!(sqrt(dx * dx + dy * dy + dz * dz) < tol)) flags[b] = 1;
+}
+
+hipError_t launch_abu_corners(bool fp64, const DevTree &T, const EwaldP &E, const int64_t *off,
+                              const double4 *rec, const void *prev_acc, double G, double tol, int32_t *flags,
+                              hipStream_t st) {
+  dim3 grid((unsigned)((T.nb * 8 + 255) / 256)), blk(256);
+#define OT_ABU(B, R) \
+  hipLaunchKernelGGL((k_abu_corners<B, R>), grid, blk, 0, st, T, E, off, rec, (const R *)prev_acc, -G, tol, flags)
+  if (fp64) {
+    switch (E.bctype) {
+      case 0: OT_ABU(0, double); break;
+      case 1: OT_ABU(1, double); break;
+      default: OT_ABU(2, double); break;
+    }
+  } else {
+    switch (E.bctype) {
+      case 0: OT_ABU(0, float); break;
+      case 1: OT_ABU(1, float); break;
+      default: OT_ABU(2, float); break;
+    }
+  }
+#undef OT_ABU
+  return hipGetLastError();
+}
+
 hipError_t launch_eval32(const DevTree &T, const EwaldP &E, const int64_t *off, const double4 *rec,
-                         const int32_t *ids, float *phi, float *acc, double G, hipStream_t st) {
-  dim3 grid((unsigned)T.nb), blk(WG);
+                         const int32_t *ids, float *phi, float *acc, double G, hipStream_t st,
+                         const int32_t *blist, int64_t nblist) {
+  if (blist && nblist <= 0) return hipSuccess;
+  dim3 grid((unsigned)(blist ? nblist : T.nb)), blk(WG);
   float ng = (float)(-G);
   switch (E.bctype) {
-    case 0: hipLaunchKernelGGL(k_eval32<0>, grid, blk, 0, st, T, E, off, rec, ids, phi, acc, ng); break;
-    case 1: hipLaunchKernelGGL(k_eval32<1>, grid, blk, 0, st, T, E, off, rec, ids, phi, acc, ng); break;
-    default: hipLaunchKernelGGL(k_eval32<2>, grid, blk, 0, st, T, E, off, rec, ids, phi, acc, ng); break;
+    case 0: hipLaunchKernelGGL(k_eval32<0>, grid, blk, 0, st, T, E, off, rec, ids, phi, acc, ng, blist); break;
+    case 1: hipLaunchKernelGGL(k_eval32<1>, grid, blk, 0, st, T, E, off, rec, ids, phi, acc, ng, blist); break;
+    default: hipLaunchKernelGGL(k_eval32<2>, grid, blk, 0, st, T, E, off, rec, ids, phi, acc, ng, blist); break;
   }
   return hipGetLastError();
 }

@@ -120,10 +120,19 @@ hipError_t launch_lists(bool fill, const DevTree &T, const MacP &P, int grid, in
 
 hipError_t launch_scan(const int32_t *count, int64_t nb, int64_t *off, hipStream_t st);
 
+// blist (optional): evaluate only the nblist leaf blocks listed there
 hipError_t launch_eval64(const DevTree &T, const EwaldP &E, const int64_t *off, const double4 *rec,
-                         double *phi, double *acc, double G, hipStream_t st);
+                         double *phi, double *acc, double G, hipStream_t st, const int32_t *blist = nullptr,
+                         int64_t nblist = 0);
 hipError_t launch_eval32(const DevTree &T, const EwaldP &E, const int64_t *off, const double4 *rec,
-                         const int32_t *ids, float *phi, float *acc, double G, hipStream_t st);
+                         const int32_t *ids, float *phi, float *acc, double G, hipStream_t st,
+                         const int32_t *blist = nullptr, int64_t nblist = 0);
+// adaptive block update: flags[b] = 1 for every leaf block with a corner cell
+// whose FP64 acceleration differs from prev_acc (FP64 or FP32, [3][nb*512]) by
+// at least tol; flags [nb] zero on entry
+hipError_t launch_abu_corners(bool fp64, const DevTree &T, const EwaldP &E, const int64_t *off,
+                              const double4 *rec, const void *prev_acc, double G, double tol, int32_t *flags,
+                              hipStream_t st);
 
 hipError_t launch_amax(const double *acc, int64_t n, unsigned long long *out, hipStream_t st);
 

@@ -1,0 +1,79 @@
+"""GPU parity of the adaptive block update (Sec. 2.2.5) with the oracle's:
+the zero-tolerance and unchanged-density limits, and a locally perturbed
+field whose previous solution is the oracle's walk on the unperturbed one."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1708_06142_amd as ot
+import workloads
+from test_oracle_abu import CORNERS, _perturbed
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _solver(g):
+    s = ot.Solver.for_grid(g, theta=0.5)
+    s.build(torch.from_numpy(g.rho.reshape(-1)).cuda())
+    return s
+
+
+def test_abu_limits():
+    g = workloads.small_amr()
+    s = _solver(g)
+    n = 512 * g.nb
+    phi = torch.empty(n, dtype=torch.float64, device="cuda")
+    acc = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+    s.solve64(phi, acc)
+    p_ref, a_ref = phi.cpu().numpy(), acc.cpu().numpy()
+    # tol 0: every block evaluated, the same values as the plain solve
+    phi.zero_()
+    acc.zero_()
+    st, upd = s.solve_abu(phi, acc, 0.0, fp64=True)
+    assert upd.all() and st.n_interactions > 0
+    assert np.array_equal(phi.cpu().numpy(), p_ref) and np.array_equal(acc.cpu().numpy(), a_ref)
+    # unchanged density: the corners reproduce the previous values, nothing is evaluated
+    st, upd = s.solve_abu(phi, acc, 1e-12, fp64=True)
+    assert not upd.any() and st.n_interactions == 0
+    assert np.array_equal(phi.cpu().numpy(), p_ref) and np.array_equal(acc.cpu().numpy(), a_ref)
+    with pytest.raises(ot.OTError, match="INVALID_ARG"):
+        s.solve_abu(phi, acc, -1.0, fp64=True)
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_abu_perturbed_matches_oracle(fp64):
+    g = workloads.small_amr()
+    p0, a0, _ = oracle.Tree(g, theta=0.5).walk_group()
+    dt = torch.float64 if fp64 else torch.float32
+    if not fp64:  # both sides start from the same FP32 previous solution
+        p0, a0 = p0.astype(np.float32).astype(np.float64), a0.astype(np.float32).astype(np.float64)
+    g1 = _perturbed(g)
+    t1 = oracle.Tree(g1, theta=0.5)
+    p1, a1, _ = t1.walk_group()
+    tol = 1e-3 * np.sqrt((a1 ** 2).sum(0)).max()
+    pr, ar, upd_r = t1.walk_abu(p0, a0, tol)
+    s = _solver(g1)
+    phi = torch.from_numpy(p0.copy()).to(dt).cuda()
+    acc = torch.from_numpy(a0.reshape(-1).copy()).to(dt).cuda()
+    st, upd = s.solve_abu(phi, acc, tol, fp64=fp64)
+    p, a = phi.cpu().numpy().astype(np.float64), acc.cpu().numpy().astype(np.float64).reshape(3, -1)
+    assert 0 < upd_r.sum() < g.nb
+    # a block may only be decided differently where its corners sit at the tolerance
+    da = np.sqrt(((a1 - a0) ** 2).sum(0)).reshape(g.nb, 512)[:, CORNERS].max(1)
+    differ = upd != upd_r
+    assert np.all(np.abs(da[differ] - tol) <= 1e-9 * tol), (np.nonzero(differ), da[differ] / tol)
+    same = ~differ
+    pb, ab = p.reshape(g.nb, 512), a.reshape(3, g.nb, 512)
+    prb, arb = pr.reshape(g.nb, 512), ar.reshape(3, g.nb, 512)
+    keep = same & (upd == 0)
+    assert np.array_equal(pb[keep], p0.reshape(g.nb, 512)[keep])
+    assert np.array_equal(ab[:, keep], a0.reshape(3, g.nb, 512)[:, keep])
+    ev = same & (upd == 1)
+    amax = np.sqrt((ar ** 2).sum(0)).max()
+    if fp64:
+        np.testing.assert_allclose(pb[ev], prb[ev], rtol=1e-12)
+        assert np.abs(ab[:, ev] - arb[:, ev]).max() <= 1e-12 * amax
+    else:
+        assert (np.abs(pb[ev] / prb[ev] - 1)).max() <= 1e-6
+        assert np.abs(ab[:, ev] - arb[:, ev]).max() <= 1e-5 * amax
