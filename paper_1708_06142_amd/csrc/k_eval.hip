@@ -291,25 +291,31 @@ hipError_t launch_eval64(const DevTree &T, const EwaldP &E, const int64_t *off, 
 }
 
 // Adaptive block update (Sec. 2.2.5): the eight corner cells (i, j, k in
-// {0, 7}) of every leaf block, walked in FP64 over the block's list (one
-// thread per corner); flags[b] = 1 when at one of them |a_new - a_prev| >=
-// tol.  flags must be zero on entry.
+// {0, 7}) of every leaf block, walked in FP64 over the block's list; one wave
+// per block, lane l takes corner l % 8 and every eighth list entry from
+// l / 8, and the eight slices are added in a fixed butterfly.  flags[b] = 1
+// when at one corner |a_new - a_prev| >= tol.  flags must be zero on entry.
 template <int BC, typename Real>
 __global__ __launch_bounds__(256) void k_abu_corners(DevTree T, EwaldP E, const int64_t *__restrict__ off,
                                                      const double4 *__restrict__ rec,
                                                      const Real *__restrict__ prev_acc, double negG, double tol,
                                                      int32_t *__restrict__ flags) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= T.nb * 8) return;
-  const int64_t b = t >> 3;
-  const int k = (int)(t & 7);
+  const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (b >= T.nb) return;  // whole waves leave together
+  const int lane = threadIdx.x & 63, k = lane & 7, sl = lane >> 3;
   const int ci = 7 * (k & 1) + 56 * ((k >> 1) & 1) + 448 * ((k >> 2) & 1);
   const double h = size_at(T.root_size, T.blev[b]) / 8.0;
   const double cx = centre_coord(T.org[0], 8 * (int64_t)T.bcoord[3 * b] + (ci & 7), h);
   const double cy = centre_coord(T.org[1], 8 * (int64_t)T.bcoord[3 * b + 1] + ((ci >> 3) & 7), h);
   const double cz = centre_coord(T.org[2], 8 * (int64_t)T.bcoord[3 * b + 2] + (ci >> 6), h);
   double sp = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
-  for (int64_t j = off[b]; j < off[b + 1]; ++j) pair64<BC>(E, cx, cy, cz, rec[j], sp, ax, ay, az);
+  for (int64_t j = off[b] + sl; j < off[b + 1]; j += 8) pair64<BC>(E, cx, cy, cz, rec[j], sp, ax, ay, az);
+  for (int m = 32; m >= 8; m >>= 1) {
+    ax += __shfl_xor(ax, m);
+    ay += __shfl_xor(ay, m);
+    az += __shfl_xor(az, m);
+  }
+  if (sl != 0) return;
   const int64_t ncell = T.nb * 512, o = b * 512 + ci;
   const double dx = negG * ax - (double)prev_acc[o], dy = negG * ay - (double)prev_acc[ncell + o];
   const double dz = negG * az - (double)prev_acc[2 * ncell + o];
@@ -319,7 +325,7 @@ __global__ __launch_bounds__(256) void k_abu_corners(DevTree T, EwaldP E, const 
 hipError_t launch_abu_corners(bool fp64, const DevTree &T, const EwaldP &E, const int64_t *off,
                               const double4 *rec, const void *prev_acc, double G, double tol, int32_t *flags,
                               hipStream_t st) {
-  dim3 grid((unsigned)((T.nb * 8 + 255) / 256)), blk(256);
+  dim3 grid((unsigned)((T.nb + 3) / 4)), blk(256);
 #define OT_ABU(B, R) \
   hipLaunchKernelGGL((k_abu_corners<B, R>), grid, blk, 0, st, T, E, off, rec, (const R *)prev_acc, -G, tol, flags)
   if (fp64) {
