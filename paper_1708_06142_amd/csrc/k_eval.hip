@@ -16,7 +16,9 @@
 // target cell again gives d = 0.
 //
 // One workgroup of 256 threads per leaf block; thread t owns cells t and
-// t + 256.  The list is streamed through LDS in tiles of 256 records, which
+// t + 256 (NQ = 2).  When only a few blocks are evaluated (the adaptive block
+// update), two workgroups share a block, one cell per thread (NQ = 1): the
+// same arithmetic per cell in the same order, half the latency.  The list is streamed through LDS in tiles of 256 records, which
 // every thread then reads as broadcasts.  The FP32 kernel accumulates Phi with
 // Kahan compensation and the acceleration in plain FP32 per tile, the tile
 // sums then added (blocked summation).
@@ -29,6 +31,9 @@ namespace ot {
 namespace {
 
 constexpr int WG = 256;
+// below this many blocks two workgroups share a block (four resident
+// workgroups per CU at one per block)
+constexpr int64_t FEW_BLOCKS = 1024;
 
 // ---------------------------------------------------------------- FP64
 template <int BC>
@@ -72,21 +77,24 @@ __device__ inline void pair64(const EwaldP &E, double cx, double cy, double cz, 
   az += r.w * A2;
 }
 
-template <int BC>
+template <int BC, int NQ>
 __global__ __launch_bounds__(WG) void k_eval64(DevTree T, EwaldP E, const int64_t *__restrict__ off,
                                                const double4 *__restrict__ rec,
                                                double *__restrict__ phi, double *__restrict__ acc,
                                                double negG, const int32_t *__restrict__ blist) {
   __shared__ double4 tile[WG];
-  const int64_t b = blist ? (int64_t)blist[blockIdx.x] : (int64_t)blockIdx.x;
+  const int64_t g = NQ == 2 ? (int64_t)blockIdx.x : (int64_t)(blockIdx.x >> 1);
+  const int part = NQ == 2 ? 0 : (int)(blockIdx.x & 1);
+  const int64_t b = blist ? (int64_t)blist[g] : g;
   const int tid = threadIdx.x;
   const int64_t ncell = T.nb * 512;
   const double h = size_at(T.root_size, T.blev[b]) / 8.0;
   const int64_t c0 = 8 * (int64_t)T.bcoord[3 * b], c1 = 8 * (int64_t)T.bcoord[3 * b + 1];
   const int64_t c2 = 8 * (int64_t)T.bcoord[3 * b + 2];
-  double cx[2], cy[2], cz[2], sp[2] = {0, 0}, ax[2] = {0, 0}, ay[2] = {0, 0}, az[2] = {0, 0};
-  for (int q = 0; q < 2; ++q) {
-    int ci = tid + q * WG;
+  double cx[NQ], cy[NQ], cz[NQ], sp[NQ], ax[NQ], ay[NQ], az[NQ];
+  for (int q = 0; q < NQ; ++q) {
+    int ci = tid + (q + part) * WG;
+    sp[q] = ax[q] = ay[q] = az[q] = 0.0;
     cx[q] = centre_coord(T.org[0], c0 + (ci & 7), h);
     cy[q] = centre_coord(T.org[1], c1 + ((ci >> 3) & 7), h);
     cz[q] = centre_coord(T.org[2], c2 + (ci >> 6), h);
@@ -98,13 +106,13 @@ __global__ __launch_bounds__(WG) void k_eval64(DevTree T, EwaldP E, const int64_
     const int m = (int)(n - t0 < WG ? n - t0 : WG);
     for (int j = 0; j < m; ++j) {
       const double4 r = tile[j];
-      pair64<BC>(E, cx[0], cy[0], cz[0], r, sp[0], ax[0], ay[0], az[0]);
-      pair64<BC>(E, cx[1], cy[1], cz[1], r, sp[1], ax[1], ay[1], az[1]);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) pair64<BC>(E, cx[q], cy[q], cz[q], r, sp[q], ax[q], ay[q], az[q]);
     }
     __syncthreads();
   }
-  for (int q = 0; q < 2; ++q) {
-    int64_t o = b * 512 + tid + q * WG;
+  for (int q = 0; q < NQ; ++q) {
+    int64_t o = b * 512 + tid + (q + part) * WG;
     phi[o] = negG * sp[q];
     acc[o] = negG * ax[q];
     acc[ncell + o] = negG * ay[q];
@@ -189,13 +197,15 @@ __device__ inline void pair32(const EwaldP &E, float cx, float cy, float cz, con
   a.tz += fz;
 }
 
-template <int BC>
+template <int BC, int NQ>
 __global__ __launch_bounds__(WG) void k_eval32(DevTree T, EwaldP E, const int64_t *__restrict__ off,
                                                const double4 *__restrict__ rec, const int32_t *__restrict__ ids,
                                                float *__restrict__ phi, float *__restrict__ acc,
                                                float negG, const int32_t *__restrict__ blist) {
   __shared__ float4 tile[WG];
-  const int64_t b = blist ? (int64_t)blist[blockIdx.x] : (int64_t)blockIdx.x;
+  const int64_t g = NQ == 2 ? (int64_t)blockIdx.x : (int64_t)(blockIdx.x >> 1);
+  const int part = NQ == 2 ? 0 : (int)(blockIdx.x & 1);
+  const int64_t b = blist ? (int64_t)blist[g] : g;
   const int tid = threadIdx.x;
   const int64_t ncell = T.nb * 512;
   const double sb = size_at(T.root_size, T.blev[b]);
@@ -203,10 +213,10 @@ __global__ __launch_bounds__(WG) void k_eval32(DevTree T, EwaldP E, const int64_
   double cT[3];
   for (int k = 0; k < 3; ++k) cT[k] = centre_coord(T.org[k], T.bcoord[3 * b + k], sb);
   const int64_t own0 = T.na + 72 * T.nb + 512 * b;  // id of cell 0 of this block
-  float cx[2], cy[2], cz[2];
-  Acc32 a[2];
-  for (int q = 0; q < 2; ++q) {
-    int ci = tid + q * WG;
+  float cx[NQ], cy[NQ], cz[NQ];
+  Acc32 a[NQ];
+  for (int q = 0; q < NQ; ++q) {
+    int ci = tid + (q + part) * WG;
     cx[q] = (float)(((double)(ci & 7) - 3.5) * h);
     cy[q] = (float)(((double)((ci >> 3) & 7) - 3.5) * h);
     cz[q] = (float)(((double)(ci >> 6) - 3.5) * h);
@@ -235,11 +245,11 @@ __global__ __launch_bounds__(WG) void k_eval32(DevTree T, EwaldP E, const int64_
     const int m = (int)(n - t0 < WG ? n - t0 : WG);
     for (int j = 0; j < m; ++j) {
       const float4 r = tile[j];
-      pair32<BC>(E, cx[0], cy[0], cz[0], r, a[0]);
-      pair32<BC>(E, cx[1], cy[1], cz[1], r, a[1]);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) pair32<BC>(E, cx[q], cy[q], cz[q], r, a[q]);
     }
     // blocked summation of the acceleration: tile sums into the totals
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       a[q].ax += a[q].tx;
       a[q].ay += a[q].ty;
       a[q].az += a[q].tz;
@@ -247,8 +257,8 @@ __global__ __launch_bounds__(WG) void k_eval32(DevTree T, EwaldP E, const int64_
     }
     __syncthreads();
   }
-  for (int q = 0; q < 2; ++q) {
-    int64_t o = b * 512 + tid + q * WG;
+  for (int q = 0; q < NQ; ++q) {
+    int64_t o = b * 512 + tid + (q + part) * WG;
     phi[o] = negG * (a[q].s - a[q].c);
     acc[o] = negG * a[q].ax;
     acc[ncell + o] = negG * a[q].ay;
@@ -281,51 +291,65 @@ hipError_t launch_eval64(const DevTree &T, const EwaldP &E, const int64_t *off, 
                          double *phi, double *acc, double G, hipStream_t st, const int32_t *blist,
                          int64_t nblist) {
   if (blist && nblist <= 0) return hipSuccess;
-  dim3 grid((unsigned)(blist ? nblist : T.nb)), blk(WG);
+  const int64_t nwg = blist ? nblist : T.nb;
+  const bool split = nwg < FEW_BLOCKS;
+  dim3 grid((unsigned)(split ? 2 * nwg : nwg)), blk(WG);
+#define OT_E64(B, Q) hipLaunchKernelGGL((k_eval64<B, Q>), grid, blk, 0, st, T, E, off, rec, phi, acc, -G, blist)
   switch (E.bctype) {
-    case 0: hipLaunchKernelGGL(k_eval64<0>, grid, blk, 0, st, T, E, off, rec, phi, acc, -G, blist); break;
-    case 1: hipLaunchKernelGGL(k_eval64<1>, grid, blk, 0, st, T, E, off, rec, phi, acc, -G, blist); break;
-    default: hipLaunchKernelGGL(k_eval64<2>, grid, blk, 0, st, T, E, off, rec, phi, acc, -G, blist); break;
+    case 0: if (split) OT_E64(0, 1); else OT_E64(0, 2); break;
+    case 1: if (split) OT_E64(1, 1); else OT_E64(1, 2); break;
+    default: if (split) OT_E64(2, 1); else OT_E64(2, 2); break;
   }
+#undef OT_E64
   return hipGetLastError();
 }
 
 // Adaptive block update (Sec. 2.2.5): the eight corner cells (i, j, k in
-// {0, 7}) of every leaf block, walked in FP64 over the block's list; one wave
-// per block, lane l takes corner l % 8 and every eighth list entry from
-// l / 8, and the eight slices are added in a fixed butterfly.  flags[b] = 1
-// when at one corner |a_new - a_prev| >= tol.  flags must be zero on entry.
+// {0, 7}) of every leaf block, walked in FP64 over the block's list; one
+// workgroup per block, thread t takes corner t % 8 and every 32nd list entry
+// from t / 8, and the 32 slices are added in a fixed order (a butterfly in
+// each wave, then the four waves in sequence).  flags[b] = 1 when at one
+// corner |a_new - a_prev| >= tol.  flags must be zero on entry.
 template <int BC, typename Real>
 __global__ __launch_bounds__(256) void k_abu_corners(DevTree T, EwaldP E, const int64_t *__restrict__ off,
                                                      const double4 *__restrict__ rec,
                                                      const Real *__restrict__ prev_acc, double negG, double tol,
                                                      int32_t *__restrict__ flags) {
-  const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (b >= T.nb) return;  // whole waves leave together
-  const int lane = threadIdx.x & 63, k = lane & 7, sl = lane >> 3;
+  __shared__ double red[4][3][8];
+  const int64_t b = blockIdx.x;
+  const int tid = threadIdx.x, k = tid & 7, sl = tid >> 3;
   const int ci = 7 * (k & 1) + 56 * ((k >> 1) & 1) + 448 * ((k >> 2) & 1);
   const double h = size_at(T.root_size, T.blev[b]) / 8.0;
   const double cx = centre_coord(T.org[0], 8 * (int64_t)T.bcoord[3 * b] + (ci & 7), h);
   const double cy = centre_coord(T.org[1], 8 * (int64_t)T.bcoord[3 * b + 1] + ((ci >> 3) & 7), h);
   const double cz = centre_coord(T.org[2], 8 * (int64_t)T.bcoord[3 * b + 2] + (ci >> 6), h);
   double sp = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
-  for (int64_t j = off[b] + sl; j < off[b + 1]; j += 8) pair64<BC>(E, cx, cy, cz, rec[j], sp, ax, ay, az);
+  for (int64_t j = off[b] + sl; j < off[b + 1]; j += 32) pair64<BC>(E, cx, cy, cz, rec[j], sp, ax, ay, az);
   for (int m = 32; m >= 8; m >>= 1) {
     ax += __shfl_xor(ax, m);
     ay += __shfl_xor(ay, m);
     az += __shfl_xor(az, m);
   }
-  if (sl != 0) return;
+  const int w = tid >> 6;
+  if ((tid & 63) < 8) {
+    red[w][0][k] = ax;
+    red[w][1][k] = ay;
+    red[w][2][k] = az;
+  }
+  __syncthreads();
+  if (tid >= 8) return;
+  double v[3];
+  for (int c = 0; c < 3; ++c) v[c] = ((red[0][c][k] + red[1][c][k]) + red[2][c][k]) + red[3][c][k];
   const int64_t ncell = T.nb * 512, o = b * 512 + ci;
-  const double dx = negG * ax - (double)prev_acc[o], dy = negG * ay - (double)prev_acc[ncell + o];
-  const double dz = negG * az - (double)prev_acc[2 * ncell + o];
+  const double dx = negG * v[0] - (double)prev_acc[o], dy = negG * v[1] - (double)prev_acc[ncell + o];
+  const double dz = negG * v[2] - (double)prev_acc[2 * ncell + o];
   if (!(sqrt(dx * dx + dy * dy + dz * dz) < tol)) flags[b] = 1;
 }
 
 hipError_t launch_abu_corners(bool fp64, const DevTree &T, const EwaldP &E, const int64_t *off,
                               const double4 *rec, const void *prev_acc, double G, double tol, int32_t *flags,
                               hipStream_t st) {
-  dim3 grid((unsigned)((T.nb + 3) / 4)), blk(256);
+  dim3 grid((unsigned)T.nb), blk(256);
 #define OT_ABU(B, R) \
   hipLaunchKernelGGL((k_abu_corners<B, R>), grid, blk, 0, st, T, E, off, rec, (const R *)prev_acc, -G, tol, flags)
   if (fp64) {
@@ -349,13 +373,18 @@ hipError_t launch_eval32(const DevTree &T, const EwaldP &E, const int64_t *off, 
                          const int32_t *ids, float *phi, float *acc, double G, hipStream_t st,
                          const int32_t *blist, int64_t nblist) {
   if (blist && nblist <= 0) return hipSuccess;
-  dim3 grid((unsigned)(blist ? nblist : T.nb)), blk(WG);
+  const int64_t nwg = blist ? nblist : T.nb;
+  const bool split = nwg < FEW_BLOCKS;
+  dim3 grid((unsigned)(split ? 2 * nwg : nwg)), blk(WG);
   float ng = (float)(-G);
+#define OT_E32(B, Q) \
+  hipLaunchKernelGGL((k_eval32<B, Q>), grid, blk, 0, st, T, E, off, rec, ids, phi, acc, ng, blist)
   switch (E.bctype) {
-    case 0: hipLaunchKernelGGL(k_eval32<0>, grid, blk, 0, st, T, E, off, rec, ids, phi, acc, ng, blist); break;
-    case 1: hipLaunchKernelGGL(k_eval32<1>, grid, blk, 0, st, T, E, off, rec, ids, phi, acc, ng, blist); break;
-    default: hipLaunchKernelGGL(k_eval32<2>, grid, blk, 0, st, T, E, off, rec, ids, phi, acc, ng, blist); break;
+    case 0: if (split) OT_E32(0, 1); else OT_E32(0, 2); break;
+    case 1: if (split) OT_E32(1, 1); else OT_E32(1, 2); break;
+    default: if (split) OT_E32(2, 1); else OT_E32(2, 2); break;
   }
+#undef OT_E32
   return hipGetLastError();
 }
 
