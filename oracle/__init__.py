@@ -88,6 +88,7 @@ def lib():
         L.or_ewald_table.argtypes = [C.c_int, vp, C.c_double, C.c_int, C.c_int, C.c_int, vp]
         L.or_ewald_table_lookup.argtypes = [C.c_int, vp, C.c_int, vp, i64, vp, vp]
         L.or_itilde.argtypes = [C.c_double, C.c_double, C.c_double, vp]
+        L.or_kfuncs.argtypes = [C.c_int, C.c_double, C.c_double, vp]
         L.or_mlp_nparam.restype = C.c_int
         L.or_mlp_forward.argtypes = [vp, i64, vp, vp]
         L.or_mlp_grad.restype = C.c_double
@@ -100,7 +101,7 @@ def _ptr(a):
     return a.ctypes.data_as(C.c_void_p) if a is not None else None
 
 
-BC_ISO, BC_3P, BC_2P1I = 0, 1, 2
+BC_ISO, BC_3P, BC_2P1I, BC_1P2I = 0, 1, 2, 3
 
 
 def bctype(bc):
@@ -111,6 +112,8 @@ def bctype(bc):
         return BC_3P
     if bc == (1, 1, 0):
         return BC_2P1I
+    if bc == (1, 0, 0):
+        return BC_1P2I
     raise ValueError("unsupported boundary combination")
 
 
@@ -266,6 +269,14 @@ def ewald_table_lookup(bc, box, table, d):
     d = np.ascontiguousarray(np.atleast_2d(d), dtype=np.float64)
     out = np.empty((d.shape[0], 4))
     lib().or_ewald_table_lookup(bt, _ptr(box), table.shape[0], _ptr(table), d.shape[0], _ptr(d), _ptr(out))
+    return out
+
+
+def kfuncs(l, eta, zeta):
+    """1P2I integrals K(l, eta), M(l, eta) = -dK/deta, dM/deta and M/eta
+    (its limit dM/deta at eta = 0); l = 0: the regularised closed forms."""
+    out = np.empty(4)
+    lib().or_kfuncs(int(l), float(eta), float(zeta), _ptr(out))
     return out
 
 

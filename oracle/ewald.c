@@ -13,6 +13,20 @@
  *            + 1/(pi Lx b) sum_{l1,l2} cos(v_l) Itilde(l1, l2, dz).
  * Itilde is evaluated at |gamma| (it is even in gamma, its derivative odd).
  * The l = 0 term uses I(0,0) of Eq. (14); its derivative is -pi erf(gamma/2 sqrt(zeta)).
+ *   1P2I (Sec. 2.2.3, the 1P2I potential; App. A.3), periodic along x:
+ *        phi = sum_{i1} erfc(alpha|d - i1 Lx e_x|)/|d - i1 Lx e_x|
+ *            + 2/Lx sum_{l1} exp(-zeta l1^2) cos(2 pi l1 dx / Lx) K(l1, eta),
+ *        eta = 2 pi rho / Lx, rho = sqrt(dy^2 + dz^2),
+ *        K(l, eta) = int_0^inf J0(eta q) exp(-zeta q^2) q / (l^2 + q^2) dq,
+ *        M = -dK/deta = int_0^inf J1(eta q) exp(-zeta q^2) q^2 / (l^2 + q^2) dq,
+ *        dM/deta = int_0^inf (J0(eta q) - J1(eta q)/(eta q)) exp(-zeta q^2) q^3 / (l^2 + q^2) dq,
+ *        by composite Gauss-Legendre quadrature (J0, J1 from the C library) for
+ *        l != 0.  The l = 0 integral of K diverges at q = 0; its regularised
+ *        form, the divergent constant dropped, is K(0, eta) = -Ein(s)/2 with
+ *        s = eta^2/(4 zeta) and Ein(s) = E1(s) + ln s + gamma_E, whose
+ *        derivative gives M(0, eta) = (1 - exp(-s))/eta (equal to the
+ *        convergent integral above).  Beyond rho = 4 Lx the analytic
+ *        line-mass limit phi -> -(2 ln(alpha rho) + gamma_E)/Lx is used.
  *
  * Readings: the printed 3P potential has no k = 0 constant and it is kept
  * that way; real-space cut-off |i|^2 <= 15 (3P) and <= 10 (2P1I), Fourier
@@ -125,6 +139,98 @@ static void i00(long double zeta, long double gam, long double *I0, long double 
   *I2 = -(SQRTPI_L / sz) * gauss;
 }
 
+/* ---- 1P2I: K, M = -dK/deta, dM/deta and M/eta ------------------------- */
+#define EULER_GAMMA_L 0.577215664901532860606512090082402431L
+
+/* Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on P_n) */
+#define GL_N 16
+static long double gl_x[GL_N], gl_w[GL_N];
+static void gl_init(void) {
+  static int done = 0;
+  if (done) return;
+#pragma omp critical(or_gl_init)
+  if (!done) {
+    for (int i = 0; i < GL_N; ++i) {
+      long double x = cosl(PI_L * (i + 0.75L) / (GL_N + 0.5L)), dp = 0;
+      for (int it = 0; it < 100; ++it) {
+        long double p0 = 1, p1 = x;
+        for (int k = 2; k <= GL_N; ++k) {
+          long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        dp = GL_N * (x * p1 - p0) / (x * x - 1);
+        long double dx = p1 / dp;
+        x -= dx;
+        if (fabsl(dx) < 1e-19L) break;
+      }
+      gl_x[i] = x;
+      gl_w[i] = 2.0L / ((1 - x * x) * dp * dp);
+    }
+    done = 1;
+  }
+}
+
+/* Ein(s) = int_0^s (1 - exp(-t))/t dt = E1(s) + ln s + gamma_E: its power
+ * series for s <= 4, else E1 by its continued fraction (modified Lentz). */
+static long double ein(long double s) {
+  if (s <= 4.0L) {
+    long double term = 1, sum = 0;
+    for (int k = 1; k < 80; ++k) {
+      term *= s / k; /* s^k / k! */
+      long double t = ((k & 1) ? term : -term) / k;
+      sum += t;
+      if (fabsl(t) < 1e-22L * fabsl(sum)) break;
+    }
+    return sum;
+  }
+  long double b = s + 1, c = 1.0L / 1e-300L, d = 1.0L / b, h = d;
+  for (int i = 1; i < 500; ++i) {
+    long double an = -(long double)i * i;
+    b += 2;
+    d = 1.0L / (an * d + b);
+    c = b + an / c;
+    long double del = c * d;
+    h *= del;
+    if (fabsl(del - 1) < 1e-20L) break;
+  }
+  return h * expl(-s) + logl(s) + EULER_GAMMA_L;
+}
+
+static void kfuncs(int l, long double eta, long double zeta, long double *K, long double *M,
+                   long double *Mp, long double *Mq) {
+  if (l == 0) {
+    long double s = eta * eta / (4 * zeta);
+    long double om = -expm1l(-s); /* 1 - exp(-s) */
+    *K = -0.5L * ein(s);
+    *M = eta > 0 ? om / eta : 0.0L;
+    *Mq = s > 0 ? om / s / (4 * zeta) : 1.0L / (4 * zeta);
+    *Mp = expl(-s) / (2 * zeta) - *Mq;
+    return;
+  }
+  gl_init();
+  /* the Gaussian factor is below 1e-19 beyond qmax */
+  const long double qmax = sqrtl(44.0L / zeta);
+  const int npanel = 48;
+  const long double hp = qmax / npanel, l2 = (long double)l * l;
+  long double sk = 0, sm = 0, sp = 0;
+  for (int p = 0; p < npanel; ++p)
+    for (int i = 0; i < GL_N; ++i) {
+      long double q = hp * (p + 0.5L + 0.5L * gl_x[i]);
+      long double w = 0.5L * hp * gl_w[i] * expl(-zeta * q * q) / (l2 + q * q);
+      double t = (double)(eta * q);
+      long double j0v = j0(t), j1v = j1(t);
+      long double j1t = t < 1e-6 ? 0.5L - (long double)t * t / 16 : j1v / t;
+      sk += w * j0v * q;
+      sm += w * j1v * q * q;
+      sp += w * (j0v - j1t) * q * q * q;
+    }
+  *K = sk;
+  *M = sm;
+  *Mp = sp;
+  *Mq = eta > 0 ? sm / eta : sp;
+}
+
 void or_ewald_series(const or_ewald *e, const double dd[3], int correction, double *phi_out,
                      double A_out[3], double H_out[6]) {
   long double d[3] = {dd[0], dd[1], dd[2]};
@@ -134,7 +240,9 @@ void or_ewald_series(const or_ewald *e, const double dd[3], int correction, doub
   int three = e->bctype == OR_BC_3P;
   /* loop bounds that cover the cut-off ellipsoids */
   double rr = sqrt((double)e->rcut2), fr = sqrt((double)e->fcut2);
-  int R1 = (int)ceil(rr) + 1, R2 = (int)ceil(rr / e->b) + 1, R3 = three ? (int)ceil(rr / e->c) + 1 : 0;
+  int onep = e->bctype == OR_BC_1P2I;
+  int R1 = (int)ceil(rr) + 1, R2 = onep ? 0 : (int)ceil(rr / e->b) + 1;
+  int R3 = three ? (int)ceil(rr / e->c) + 1 : 0;
   int F1 = (int)ceil(fr) + 1, F2 = (int)ceil(fr * e->b) + 1, F3 = (int)ceil(fr * e->c) + 1;
   /* real space */
   for (int i3 = -R3; i3 <= R3; ++i3)
@@ -178,6 +286,33 @@ void or_ewald_series(const or_ewald *e, const double dd[3], int correction, doub
             H[5] += hk * qv[1] * qv[2];
           }
         }
+  } else if (onep) {
+    long double pre = 2.0L / Lx;
+    long double rho = sqrtl(d[1] * d[1] + d[2] * d[2]);
+    long double uy = rho > 0 ? d[1] / rho : 0.0L, uz = rho > 0 ? d[2] / rho : 0.0L;
+    long double eta = kap * rho;
+    for (int l = -F1; l <= F1; ++l) {
+      if ((long double)l * l > e->fcut2) continue;
+      long double K, M, Mp, Mq;
+      kfuncs(l < 0 ? -l : l, eta, zeta, &K, &M, &Mp, &Mq);
+      long double E = expl(-zeta * (long double)l * l);
+      long double v = kap * l * d[0];
+      long double cv = cosl(v), sv = sinl(v);
+      phi += pre * E * cv * K;
+      A[0] += pre * E * kap * l * sv * K;
+      long double ar = pre * E * kap * cv * M; /* radial component of A */
+      A[1] += ar * uy;
+      A[2] += ar * uz;
+      if (H) {
+        long double k2 = pre * E * kap * kap;
+        H[0] -= k2 * (long double)l * l * cv * K;
+        H[1] -= k2 * cv * (Mp * uy * uy + Mq * (1.0L - uy * uy));
+        H[2] -= k2 * cv * (Mp * uz * uz + Mq * (1.0L - uz * uz));
+        H[3] += k2 * l * sv * M * uy;
+        H[4] += k2 * l * sv * M * uz;
+        H[5] -= k2 * cv * (Mp - Mq) * uy * uz;
+      }
+    }
   } else {
     long double pre = 1.0L / (PI_L * Lx * b);
     long double gam = kap * d[2];
@@ -227,7 +362,12 @@ int or_ewald_setup(or_ewald *e, int bctype, const double box[3], double alpha, i
   e->ext[0] = 0.5 * box[0];
   e->ext[1] = 0.5 * box[1];
   if (bctype == OR_BC_3P) e->ext[2] = 0.5 * box[2];
-  else e->ext[2] = box[2] < 2.0 * box[0] ? box[2] : 2.0 * box[0];
+  else if (bctype == OR_BC_2P1I) e->ext[2] = box[2] < 2.0 * box[0] ? box[2] : 2.0 * box[0];
+  if (bctype == OR_BC_1P2I) {
+    const double rf = OR_1P2I_RFAR * box[0];
+    e->ext[1] = box[1] < rf ? box[1] : rf;
+    e->ext[2] = box[2] < rf ? box[2] : rf;
+  }
   for (int k = 0; k < 3; ++k) e->step[k] = e->ext[k] / (double)(n - 1);
   if (!with_table) return 0;
   int64_t np = (int64_t)n * n * n;
@@ -290,6 +430,17 @@ void or_ewald_total(const or_tree *t, const double d[3], double *phi, double A[3
     A[2] = (d[2] < 0 ? -2.0 : 2.0) * M_PI / bL2;
     return;
   }
+  if (e->bctype == OR_BC_1P2I) {
+    const double rho2 = d[1] * d[1] + d[2] * d[2], rf = OR_1P2I_RFAR * e->Lx;
+    if (rho2 > rf * rf) {
+      /* line mass 1/Lx: phi = -(2 ln(alpha rho) + gamma_E)/Lx, A = 2 (0, dy, dz)/(Lx rho^2) */
+      *phi = -(log(e->alpha * e->alpha * rho2) + (double)EULER_GAMMA_L) / e->Lx;
+      A[0] = 0.0;
+      A[1] = 2.0 * d[1] / (e->Lx * rho2);
+      A[2] = 2.0 * d[2] / (e->Lx * rho2);
+      return;
+    }
+  }
   double phic, Ac[3];
   table_lookup(e, d, &phic, Ac);
   *phi = 1.0 / r + phic;
@@ -345,4 +496,14 @@ void or_itilde(double s, double zeta, double gam, double *out) {
   out[0] = (double)I0;
   out[1] = (double)I1;
   out[2] = (double)I2;
+}
+
+/* 1P2I integrals for tests: out = {K, M, dM/deta, M/eta} at (l, eta). */
+void or_kfuncs(int l, double eta, double zeta, double *out) {
+  long double K, M, Mp, Mq;
+  kfuncs(l < 0 ? -l : l, eta, zeta, &K, &M, &Mp, &Mq);
+  out[0] = (double)K;
+  out[1] = (double)M;
+  out[2] = (double)Mp;
+  out[3] = (double)Mq;
 }

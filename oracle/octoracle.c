@@ -289,6 +289,7 @@ or_tree *or_tree_new(const or_params *p, int64_t nb, const int32_t *level,
   if (!p->bc[0] && !p->bc[1] && !p->bc[2]) bct = OR_BC_ISO;
   else if (p->bc[0] && p->bc[1] && p->bc[2]) bct = OR_BC_3P;
   else if (p->bc[0] && p->bc[1] && !p->bc[2]) bct = OR_BC_2P1I;
+  else if (p->bc[0] && !p->bc[1] && !p->bc[2]) bct = OR_BC_1P2I;
   else { *err = 6; return NULL; }
   or_tree *t = (or_tree *)calloc(1, sizeof(or_tree));
   t->p = *p;
