@@ -60,8 +60,9 @@ typedef enum { OT_EWALD_TABLE = 0, OT_EWALD_EXACT = 1, OT_EWALD_MLP = 2 } ot_ewa
 typedef struct {
   int32_t nroot[3];      /* root blocks per axis (a forest, Sec. 2)            [1,1,1] */
   int32_t bc[3];         /* per-axis boundary, App. B grav_boundary_type_*     [iso]   */
-                         /* supported: all isolated, all periodic (3P), and
-                            x, y periodic with z isolated (2P1I, Sec. 2.2.3)           */
+                         /* supported: all isolated, all periodic (3P), x, y
+                            periodic with z isolated (2P1I, Sec. 2.2.3), and x
+                            periodic with y, z isolated (1P2I, Sec. 2.2.3)             */
   double root_size;      /* edge of a cubic root block                          [1.0]  */
   double origin[3];      /* domain corner                                       [0,0,0]*/
   double G;              /* gravitational constant, App. B grv_bhNewton         [1.0]  */
@@ -76,7 +77,7 @@ typedef struct {
                             a_max from a BH (theta_lim) FP64 pass, Sec. 3      [0]    */
   double eps_lim;        /* relative device of Sec. 3 for a_lim                 [1e-3] */
   int32_t ewald_n;       /* table points per axis (grv_bhEwaldNPer)             [64]   */
-  int32_t ewald_rcut2;   /* real-space cut-off |i|^2, Eq. (10); <=0: 15 (3P), 10 (2P1I) */
+  int32_t ewald_rcut2;   /* real-space cut-off |i|^2, Eq. (10); <=0: 15 (3P), 10 (2P1I, 1P2I) */
   int32_t ewald_fcut2;   /* Fourier cut-off |l|^2, Eq. (10); <= 0: 10                  */
   int32_t device;        /* HIP device ordinal                                  [0]    */
   double ewald_alpha;    /* Ewald splitting constant; <= 0: 2 / Lx (Sec. 2.2.2) [0]    */
@@ -172,7 +173,8 @@ ot_status ot_solve_abu64(ot_ctx *c, double *phi_dev, double *acc_dev, double tol
 /* Ewald correction table, Sec. 2.2.4 (second approach): phi_c = phi - 1/r,
  * A_c = A - d/r^3 and the six second derivatives of phi_c, FP64, on a
  * uniform n^3 grid over the folded domain [0, Lx/2] x [0, Ly/2] x
- * [0, Lz/2] (3P) or [0, min(Lz, 2 Lx)] in z (2P1I).  Built on the device by
+ * [0, Lz/2] (3P), [0, min(Lz, 2 Lx)] in z (2P1I), or [0, Lx/2] x
+ * [0, min(Ly, 4 Lx)] x [0, min(Lz, 4 Lx)] (1P2I).  Built on the device by
  * the first solve that needs it; this call builds it eagerly.  Only for
  * periodic or mixed boundaries (OT_ERR_STATE otherwise). */
 ot_status ot_ewald_prepare(ot_ctx *c, void *stream);
@@ -216,7 +218,8 @@ void ot_mlp_config_default(ot_mlp_config *cfg);
 
 /* Generate the training and held-out offsets, their FP64 series values, train,
  * validate against the series and the table, and accept or reject the
- * surrogate.  Periodic or mixed boundaries only (OT_ERR_STATE).  Synchronous;
+ * surrogate.  3P and 2P1I only (OT_ERR_STATE when isolated, OT_ERR_UNSUPPORTED
+ * for 1P2I, whose walks use the table).  Synchronous;
  * the training buffers are freed before returning.  report may be NULL. */
 ot_status ot_mlp_train(ot_ctx *c, const ot_mlp_config *cfg, ot_mlp_report *report, void *stream);
 
@@ -239,8 +242,10 @@ ot_status ot_mlp_grad(ot_ctx *c, const float *params_dev, int64_t batch, const f
 /* The correction (phi_c, A_c) at offsets d_dev [n][3] (any sign; folded and
  * unfolded inside) into out_dev [n][4], FP64, by method: OT_EWALD_EXACT
  * (series), OT_EWALD_TABLE (FP64 table with the Taylor term) or OT_EWALD_MLP
- * (the installed surrogate, accepted or not).  2P1I beyond |dz| = 2 Lx: the
- * analytic limit for every method, minus 1/r and d/r^3. */
+ * (the installed surrogate, accepted or not; 3P and 2P1I only).  2P1I beyond
+ * |dz| = 2 Lx and 1P2I beyond sqrt(dy^2 + dz^2) = 4 Lx (a line of mass 1/Lx:
+ * phi = -(ln(alpha^2 rho^2) + gamma_E)/Lx): the analytic limit for every
+ * method, minus 1/r and d/r^3. */
 ot_status ot_ewald_points(ot_ctx *c, int32_t method, int64_t n, const double *d_dev, double *out_dev,
                           void *stream);
 

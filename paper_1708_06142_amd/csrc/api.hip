@@ -179,6 +179,14 @@ ot::EwaldP ewald_desc(const ot_ctx *c) {
     E.far_phi_b = std::sqrt(M_PI) / (b * Lx);
     E.far_az = 2.0 * M_PI / bL2;
   }
+  if (c->bctype == ot::BC_1P2I) {
+    // a line of mass 1/Lx: phi = -(ln(alpha^2 rho^2) + gamma_E)/Lx
+    const double Lx = c->box[0], al = c->ew_alpha > 0 ? c->ew_alpha : 2.0 / Lx;
+    E.zfar = ot::RFAR_1P2I * Lx;
+    E.far_phi_a = -1.0 / Lx;
+    E.far_phi_b = -(std::log(al * al) + 0.57721566490153286061) / Lx;
+    E.far_az = 2.0 / Lx;
+  }
   E.tab64 = static_cast<const double *>(c->tab64.ptr);
   E.tab32 = static_cast<const float4 *>(c->tab32.ptr);
   return E;
@@ -197,6 +205,11 @@ ot_status ewald_prepare(ot_ctx *c, hipStream_t st) {
   c->ew_ext[1] = 0.5 * c->box[1];
   c->ew_ext[2] = c->bctype == ot::BC_3P ? 0.5 * c->box[2]
                                         : (c->box[2] < 2.0 * c->box[0] ? c->box[2] : 2.0 * c->box[0]);
+  if (c->bctype == ot::BC_1P2I) {
+    const double rf = ot::RFAR_1P2I * c->box[0];
+    c->ew_ext[1] = std::min(c->box[1], rf);
+    c->ew_ext[2] = std::min(c->box[2], rf);
+  }
   for (int k = 0; k < 3; ++k) c->ew_step[k] = c->ew_ext[k] / (double)(n - 1);
   const size_t np = (size_t)n * n * n;
   OTCHK(dalloc(c, c->tab64, np * 10 * sizeof(double)));
@@ -586,7 +599,8 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
       return fail(c, OT_ERR_UNSUPPORTED, "per-pair exact Ewald series is not built into the walk");
     OTCHK(ewald_prepare(c, st));
   }
-  const bool use_mlp = c->bctype != ot::BC_ISO && c->p.ewald == OT_EWALD_MLP && c->mlp_ok && !fp64;
+  const bool use_mlp = (c->bctype == ot::BC_3P || c->bctype == ot::BC_2P1I) && c->p.ewald == OT_EWALD_MLP &&
+                       c->mlp_ok && !fp64;
   if (cols) OTCHK(raytable_prepare(c, st));
   double alim = 0.0;
   if (c->p.mac == OT_MAC_APE || c->p.mac == OT_MAC_MPE) OTCHK(ape_limit(c, st, &alim));
@@ -799,8 +813,9 @@ ot_status ot_create(const ot_params *p, ot_ctx **out) {
   if (nper == 0) c->bctype = ot::BC_ISO;
   else if (nper == 3) c->bctype = ot::BC_3P;
   else if (p->bc[0] && p->bc[1] && !p->bc[2]) c->bctype = ot::BC_2P1I;
+  else if (p->bc[0] && !p->bc[1] && !p->bc[2]) c->bctype = ot::BC_1P2I;
   else {
-    c->err = "boundary combination not supported (isolated, 3P and x,y-periodic 2P1I are)";
+    c->err = "boundary combination not supported (isolated, 3P, x,y-periodic 2P1I and x-periodic 1P2I are)";
     *out = c;
     return OT_ERR_UNSUPPORTED;
   }
@@ -986,6 +1001,8 @@ ot_status ot_mlp_train(ot_ctx *c, const ot_mlp_config *cfg, ot_mlp_report *rep, 
   if (!c) return OT_ERR_INVALID_ARG;
   c->err.clear();
   if (!cfg) return fail(c, OT_ERR_INVALID_ARG, "null config");
+  if (c->bctype == ot::BC_1P2I)
+    return fail(c, OT_ERR_UNSUPPORTED, "the learned surrogate covers 3P and 2P1I (1P2I uses the table)");
   if (cfg->nsamples < 32 || cfg->nsamples % 32 || cfg->batch < 32 || cfg->batch % 32 ||
       cfg->batch > cfg->nsamples || cfg->epochs < 1 || cfg->nval < 1 || !(cfg->lr_max > 0) ||
       !(cfg->lr_min >= 0) || !(cfg->tol > 0))
@@ -1131,6 +1148,8 @@ ot_status ot_mlp_set(ot_ctx *c, const float *params, const double *norm, int32_t
   if (!c) return OT_ERR_INVALID_ARG;
   c->err.clear();
   if (!params || !norm) return fail(c, OT_ERR_INVALID_ARG, "null parameters or scaling");
+  if (c->bctype == ot::BC_1P2I)
+    return fail(c, OT_ERR_UNSUPPORTED, "the learned surrogate covers 3P and 2P1I (1P2I uses the table)");
   for (int k = 0; k < 11; ++k)
     if (!std::isfinite(norm[k]) || ((k < 3 || k >= 7) && !(norm[k] > 0)))
       return fail(c, OT_ERR_INVALID_ARG, "scaling must be finite with ext > 0 and sig > 0");

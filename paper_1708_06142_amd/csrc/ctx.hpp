@@ -11,7 +11,9 @@
 
 namespace ot {
 
-enum { BC_ISO = 0, BC_3P = 1, BC_2P1I = 2 };
+enum { BC_ISO = 0, BC_3P = 1, BC_2P1I = 2, BC_1P2I = 3 };
+// 1P2I: the analytic line-mass limit beyond this many Lx from the periodic axis
+constexpr double RFAR_1P2I = 4.0;
 
 // Device allocation owned by a context; counts bytes against the cap.
 struct DevBuf {

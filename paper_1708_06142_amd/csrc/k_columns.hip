@@ -261,7 +261,7 @@ template <int BC>
 __device__ inline void wrap3(const EwaldP &E, double &dx, double &dy, double &dz) {
   if (BC != 0) {
     dx = wrap_axis(dx, E.L[0], E.inv_L[0], 1);
-    dy = wrap_axis(dy, E.L[1], E.inv_L[1], 1);
+    if (BC != 3) dy = wrap_axis(dy, E.L[1], E.inv_L[1], 1);
     if (BC == 1) dz = wrap_axis(dz, E.L[2], E.inv_L[2], 1);
   }
 }
@@ -285,6 +285,14 @@ __device__ inline bool grav64(const EwaldP &E, double dx, double dy, double dz, 
     A0 = 0.0;
     A1 = 0.0;
     A2 = dz < 0 ? -E.far_az : E.far_az;
+    return true;
+  }
+  if (BC == 3 && dy * dy + dz * dz > E.zfar * E.zfar) {
+    const double rho2 = dy * dy + dz * dz;
+    phi = E.far_phi_a * log(rho2) + E.far_phi_b;
+    A0 = 0.0;
+    A1 = E.far_az * dy / rho2;
+    A2 = E.far_az * dz / rho2;
     return true;
   }
   const double u[3] = {fabs(dx), fabs(dy), fabs(dz)};
@@ -327,6 +335,14 @@ __device__ inline void grav32(const EwaldP &E, float dx, float dy, float dz, flo
     A0 = 0.0f;
     A1 = 0.0f;
     A2 = dz < 0 ? -(float)E.far_az : (float)E.far_az;
+    return;
+  }
+  if (BC == 3 && dy * dy + dz * dz > (float)(E.zfar * E.zfar)) {
+    const float rho2 = dy * dy + dz * dz, fa = (float)E.far_az / rho2;
+    phi = (float)E.far_phi_a * logf(rho2) + (float)E.far_phi_b;
+    A0 = 0.0f;
+    A1 = fa * dy;
+    A2 = fa * dz;
     return;
   }
   const float u0 = fabsf(dx), u1 = fabsf(dy), u2 = fabsf(dz);
@@ -402,7 +418,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // value outside [-lat_r, lat_r - 7] if the block's offsets leave the table
   // or may wrap on a periodic axis
   auto lat_axis = [&](double d0, int ax) {
-    const bool per = BC == 1 || (BC == 2 && ax < 2);
+    const bool per = BC == 1 || (BC == 2 && ax < 2) || (BC == 3 && ax == 0);
     if (per && !(d0 > -0.5 * E.L[ax] + h && d0 + 8.0 * h < 0.5 * E.L[ax])) return 1 << 20;
     const double n0 = d0 * inv_h;
     return fabs(n0) < (double)(1 << 20) && n0 == rint(n0) ? (int)n0 : 1 << 20;
@@ -881,7 +897,8 @@ hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const 
     if (newton_only) return hipErrorInvalidValue;
     if (E.bctype == 0) OT_LAUNCH(double, 0, false);
     else if (E.bctype == 1) OT_LAUNCH(double, 1, false);
-    else OT_LAUNCH(double, 2, false);
+    else if (E.bctype == 2) OT_LAUNCH(double, 2, false);
+    else OT_LAUNCH(double, 3, false);
   } else if (newton_only) {
     if (E.bctype == 1) OT_LAUNCH(float, 1, true);
     else if (E.bctype == 2) OT_LAUNCH(float, 2, true);
@@ -889,7 +906,8 @@ hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const 
   } else {
     if (E.bctype == 0) OT_LAUNCH(float, 0, false);
     else if (E.bctype == 1) OT_LAUNCH(float, 1, false);
-    else OT_LAUNCH(float, 2, false);
+    else if (E.bctype == 2) OT_LAUNCH(float, 2, false);
+    else OT_LAUNCH(float, 3, false);
   }
 #undef OT_LAUNCH
 #undef OT_LAUNCH2

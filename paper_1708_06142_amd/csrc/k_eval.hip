@@ -3,9 +3,10 @@
 // Phi(r) = -G sum_a M_a phi(r - r_a), a(r) = -G sum_a M_a A(r - r_a) over the
 // accepted nodes (Eqs. 7, 8 and App. A), with phi = 1/r, A = d/r^3 for
 // isolated boundaries, and phi = 1/r + phi_c, A = d/r^3 + A_c for periodic
-// (3P) or mixed (2P1I) ones, the correction taken from the table by a
+// (3P) or mixed (2P1I, 1P2I) ones, the correction taken from the table by a
 // first-order Taylor expansion about the nearest grid point (second approach
-// of Sec. 2.2.4) or, for 2P1I beyond |dz| = 2 Lx, from the analytic limit.
+// of Sec. 2.2.4) or, for 2P1I beyond |dz| = 2 Lx and for 1P2I beyond 4 Lx
+// from the periodic axis, from the analytic limit.
 // The target cell itself is skipped (d = 0 exactly).
 //
 // List records hold absolute centres of mass in FP64.  The FP64 kernel forms
@@ -42,7 +43,7 @@ __device__ inline void pair64(const EwaldP &E, double cx, double cy, double cz, 
   double dx = cx - r.x, dy = cy - r.y, dz = cz - r.z;
   if (BC != 0) {
     dx = wrap_axis(dx, E.L[0], E.inv_L[0], 1);
-    dy = wrap_axis(dy, E.L[1], E.inv_L[1], 1);
+    if (BC != 3) dy = wrap_axis(dy, E.L[1], E.inv_L[1], 1);
     if (BC == 1) dz = wrap_axis(dz, E.L[2], E.inv_L[2], 1);
   }
   const double r2 = dx * dx + dy * dy + dz * dz;
@@ -62,6 +63,12 @@ __device__ inline void pair64(const EwaldP &E, double cx, double cy, double cz, 
     A0 = 0.0;
     A1 = 0.0;
     A2 = dz < 0 ? -E.far_az : E.far_az;
+  } else if (BC == 3 && dy * dy + dz * dz > E.zfar * E.zfar) {
+    const double rho2 = dy * dy + dz * dz;
+    phi = E.far_phi_a * log(rho2) + E.far_phi_b;
+    A0 = 0.0;
+    A1 = E.far_az * dy / rho2;
+    A2 = E.far_az * dz / rho2;
   } else {
     const double u[3] = {fabs(dx), fabs(dy), fabs(dz)};
     double phic, a[3];
@@ -137,7 +144,7 @@ __device__ inline void pair32(const EwaldP &E, float cx, float cy, float cz, con
     // below both refer to it, and their sum is periodic
     const float Lx = (float)E.L[0], Ly = (float)E.L[1];
     dx = dx - Lx * floorf(fmaf(dx, E.rcp_Lf[0], 0.5f));
-    dy = dy - Ly * floorf(fmaf(dy, E.rcp_Lf[1], 0.5f));
+    if (BC != 3) dy = dy - Ly * floorf(fmaf(dy, E.rcp_Lf[1], 0.5f));
     if (BC == 1) {
       const float Lz = (float)E.L[2];
       dz = dz - Lz * floorf(fmaf(dz, E.rcp_Lf[2], 0.5f));
@@ -161,6 +168,12 @@ __device__ inline void pair32(const EwaldP &E, float cx, float cy, float cz, con
       A0 = 0.0f;
       A1 = 0.0f;
       A2 = dz < 0 ? -(float)E.far_az : (float)E.far_az;
+    } else if (BC == 3 && dy * dy + dz * dz > (float)(E.zfar * E.zfar)) {
+      const float rho2 = dy * dy + dz * dz, fa = (float)E.far_az / rho2;
+      phi = (float)E.far_phi_a * logf(rho2) + (float)E.far_phi_b;
+      A0 = 0.0f;
+      A1 = fa * dy;
+      A2 = fa * dz;
     } else {
       const float u0 = fabsf(dx), u1 = fabsf(dy), u2 = fabsf(dz);
       int g0 = min((int)(u0 * (float)E.inv_step[0] + 0.5f), E.n - 1);
@@ -298,7 +311,8 @@ hipError_t launch_eval64(const DevTree &T, const EwaldP &E, const int64_t *off, 
   switch (E.bctype) {
     case 0: if (split) OT_E64(0, 1); else OT_E64(0, 2); break;
     case 1: if (split) OT_E64(1, 1); else OT_E64(1, 2); break;
-    default: if (split) OT_E64(2, 1); else OT_E64(2, 2); break;
+    case 2: if (split) OT_E64(2, 1); else OT_E64(2, 2); break;
+    default: if (split) OT_E64(3, 1); else OT_E64(3, 2); break;
   }
 #undef OT_E64
   return hipGetLastError();
@@ -356,13 +370,15 @@ hipError_t launch_abu_corners(bool fp64, const DevTree &T, const EwaldP &E, cons
     switch (E.bctype) {
       case 0: OT_ABU(0, double); break;
       case 1: OT_ABU(1, double); break;
-      default: OT_ABU(2, double); break;
+      case 2: OT_ABU(2, double); break;
+      default: OT_ABU(3, double); break;
     }
   } else {
     switch (E.bctype) {
       case 0: OT_ABU(0, float); break;
       case 1: OT_ABU(1, float); break;
-      default: OT_ABU(2, float); break;
+      case 2: OT_ABU(2, float); break;
+      default: OT_ABU(3, float); break;
     }
   }
 #undef OT_ABU
@@ -382,7 +398,8 @@ hipError_t launch_eval32(const DevTree &T, const EwaldP &E, const int64_t *off, 
   switch (E.bctype) {
     case 0: if (split) OT_E32(0, 1); else OT_E32(0, 2); break;
     case 1: if (split) OT_E32(1, 1); else OT_E32(1, 2); break;
-    default: if (split) OT_E32(2, 1); else OT_E32(2, 2); break;
+    case 2: if (split) OT_E32(2, 1); else OT_E32(2, 2); break;
+    default: if (split) OT_E32(3, 1); else OT_E32(3, 2); break;
   }
 #undef OT_E32
   return hipGetLastError();

@@ -11,6 +11,9 @@
 // + exp(-g s) erfc(A-)] with A+- = sqrt(z) s +- g/(2 sqrt(z)), evaluated at
 // |gamma| (even; the first derivative is odd), and the regularised l = 0 term
 // I(0,0) of Eq. 14.
+// 1P2I (periodic along x): the images along x in real space and, in Fourier
+// space, 2/Lx sum_l exp(-zeta l^2) cos(kappa l dx) K(l, eta), eta = kappa rho,
+// rho = sqrt(dy^2 + dz^2) (Sec. 2.2.3; App. A for the acceleration).
 #include "common.hpp"
 #include "ewald_lookup.hpp"
 #include "kernels.hpp"
@@ -73,6 +76,71 @@ __device__ inline Radial erf_corr_term(double a, double r) {
   return R;
 }
 
+// 1P2I: K(l, eta), M = -dK/deta, dM/deta and M/eta (dM/deta at eta = 0).
+// For l != 0, writing 1/(l^2 + q^2) as int_0^inf exp(-t (l^2 + q^2)) dt and
+// using int_0^inf J0(eta q) exp(-p q^2) q dq = exp(-eta^2/(4p))/(2p) turns
+// the Bessel integral into
+//   K = 1/2 int_0^inf exp(-zeta l^2 (e^s - 1) - b e^-s) ds,  b = eta^2/(4 zeta),
+// with M and dM/deta by differentiation under the integral.  The integral is
+// taken by the trapezoidal rule after s = e^t, t in [-45, 3] with step 1/32:
+// the transformed integrand decays at both ends and is analytic in a strip,
+// so the rule converges geometrically.  For l = 0 the regularised closed
+// forms: K = -Ein(b)/2, M = (1 - e^-b)/eta, with Ein(b) = E1(b) + ln b + gamma
+// (its series below b = 1; above, E1(b) = int_0^inf exp(-b e^w) dw by the same
+// rule after w = e^t).
+struct KFun {
+  double K, M, Mp, Mq;
+};
+
+constexpr double EULER_GAMMA = 0.57721566490153286061;
+constexpr double DE_T0 = -45.0, DE_H = 1.0 / 32.0;
+constexpr int DE_N = 1537;  // t = -45 ... 3
+
+__device__ inline double ein(double b) {
+  if (b < 1.0) {
+    double term = 1.0, sum = 0.0;
+    for (int k = 1; k <= 30; ++k) {
+      term *= b / k;
+      sum += ((k & 1) ? term : -term) / k;
+    }
+    return sum;
+  }
+  double e1 = 0.0;
+  for (int i = 0; i < DE_N; ++i) {
+    const double w = exp(DE_T0 + i * DE_H);
+    e1 += exp(-b * exp(w)) * w;
+  }
+  return DE_H * e1 + log(b) + EULER_GAMMA;
+}
+
+__device__ inline KFun kfun(int l, double eta, double zeta) {
+  KFun F;
+  const double b = eta * eta / (4.0 * zeta);
+  if (l == 0) {
+    const double om = -expm1(-b);
+    F.K = -0.5 * ein(b);
+    F.M = eta > 0.0 ? om / eta : 0.0;
+    F.Mq = b > 0.0 ? om / b / (4.0 * zeta) : 1.0 / (4.0 * zeta);
+    F.Mp = exp(-b) / (2.0 * zeta) - F.Mq;
+    return F;
+  }
+  const double a = zeta * l * l, c = eta / (2.0 * zeta), c0 = 1.0 / (2.0 * zeta);
+  double sk = 0.0, sm = 0.0, sp = 0.0;
+  for (int i = 0; i < DE_N; ++i) {
+    const double sg = exp(DE_T0 + i * DE_H);
+    const double em = exp(-sg);
+    const double f = exp(-a * expm1(sg) - b * em) * sg;
+    sk += f;
+    sm += f * em;
+    sp += f * em * (c0 - c * c * em);
+  }
+  F.K = 0.5 * DE_H * sk;
+  F.M = 0.5 * DE_H * c * sm;
+  F.Mp = 0.5 * DE_H * sp;
+  F.Mq = eta > 0.0 ? F.M / eta : F.Mp;
+  return F;
+}
+
 struct Acc10 {
   double v[10];
 };
@@ -95,11 +163,11 @@ __device__ inline void ewald_point(const EwaldP &E, double alpha, int rcut2, int
                                    Acc10 &o) {
   const double Lx = E.L[0], b = E.L[1] / E.L[0], c = E.L[2] / E.L[0];
   const double zeta = (PI * PI) / ((alpha * Lx) * (alpha * Lx));
-  const bool three = E.bctype == 1;
+  const bool three = E.bctype == 1, onep = E.bctype == 3;
   for (int k = 0; k < 10; ++k) o.v[k] = 0.0;
 
   const double rr = sqrt((double)rcut2);
-  const int R1 = (int)ceil(rr) + 1, R2 = (int)ceil(rr / b) + 1, R3 = three ? (int)ceil(rr / c) + 1 : 0;
+  const int R1 = (int)ceil(rr) + 1, R2 = onep ? 0 : (int)ceil(rr / b) + 1, R3 = three ? (int)ceil(rr / c) + 1 : 0;
   for (int i3 = -R3; i3 <= R3; ++i3)
     for (int i2 = -R2; i2 <= R2; ++i2)
       for (int i1 = -R1; i1 <= R1; ++i1) {
@@ -141,6 +209,30 @@ __device__ inline void ewald_point(const EwaldP &E, double alpha, int rcut2, int
           o.v[8] += hk * q0 * q2;
           o.v[9] += hk * q1 * q2;
         }
+  } else if (onep) {
+    const double pre = 2.0 / Lx;
+    const double rho = sqrt(u[1] * u[1] + u[2] * u[2]);
+    const double uy = rho > 0.0 ? u[1] / rho : 0.0, uz = rho > 0.0 ? u[2] / rho : 0.0;
+    const double eta = kap * rho;
+    for (int l = 0; l * l <= fcut2; ++l) {
+      const KFun F = kfun(l, eta, zeta);
+      // the terms of l and -l: cos doubles, sin l cancels with the sign of l
+      const double w = (l == 0 ? 1.0 : 2.0) * pre * exp(-zeta * l * l);
+      double sv, cv;
+      sincos(kap * l * u[0], &sv, &cv);
+      const double k2 = w * kap * kap;
+      const double ar = w * kap * cv * F.M;  // radial component of A
+      o.v[0] += w * cv * F.K;
+      o.v[1] += w * kap * l * sv * F.K;
+      o.v[2] += ar * uy;
+      o.v[3] += ar * uz;
+      o.v[4] -= k2 * l * l * cv * F.K;
+      o.v[5] -= k2 * cv * (F.Mp * uy * uy + F.Mq * (1.0 - uy * uy));
+      o.v[6] -= k2 * cv * (F.Mp * uz * uz + F.Mq * (1.0 - uz * uz));
+      o.v[7] += k2 * l * sv * F.M * uy;
+      o.v[8] += k2 * l * sv * F.M * uz;
+      o.v[9] -= k2 * cv * (F.Mp - F.Mq) * uy * uz;
+    }
   } else {
     const double pre = 1.0 / (PI * Lx * b);
     const double gam = kap * u[2];  // u[2] >= 0 on the folded grid
@@ -230,6 +322,15 @@ __global__ __launch_bounds__(128) void k_ewald_points4(int method, EwaldP E, dou
     o[1] = -dx / r3;
     o[2] = -dy / r3;
     o[3] = (dz < 0 ? -E.far_az : E.far_az) - dz / r3;
+    return;
+  }
+  if (E.bctype == 3 && dy * dy + dz * dz > E.zfar * E.zfar) {
+    const double r = sqrt(dx * dx + dy * dy + dz * dz), rho2 = dy * dy + dz * dz;
+    o[0] = E.far_phi_a * log(rho2) + E.far_phi_b - 1.0 / r;
+    const double r3 = r * r * r;
+    o[1] = -dx / r3;
+    o[2] = E.far_az * dy / rho2 - dy / r3;
+    o[3] = E.far_az * dz / rho2 - dz / r3;
     return;
   }
   const double u[3] = {fabs(dx), fabs(dy), fabs(dz)};

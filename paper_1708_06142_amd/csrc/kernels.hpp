@@ -22,15 +22,16 @@ struct MacP {
 
 // Ewald look-up description passed to the evaluation kernels.
 struct EwaldP {
-  int bctype;            // 0 iso, 1 3P, 2 2P1I
+  int bctype;            // 0 iso, 1 3P, 2 2P1I, 3 1P2I
   int n;                 // table points per axis
   double L[3];           // box
   double inv_L[3];       // exact_inverse(L)
   float rcp_Lf[3];       // 1 / L rounded to FP32 (the FP32 walks' wrap)
   double step[3];        // table spacing per axis
   double inv_step[3];
-  double zfar;           // 2P1I: |dz| beyond which the analytic limit is used
-  double far_phi_a;      // phi -> far_phi_a |dz| + far_phi_b
+  double zfar;           // 2P1I: |dz|, 1P2I: sqrt(dy^2 + dz^2) beyond which the analytic limit is used
+  double far_phi_a;      // 2P1I: phi -> far_phi_a |dz| + far_phi_b; 1P2I: far_phi_a ln(rho^2) + far_phi_b,
+                         // A -> far_az (0, dy, dz) / rho^2
   double far_phi_b;
   double far_az;         // A_z -> far_az sign(dz)
   const double *tab64;   // [n^3][10]

@@ -1,0 +1,117 @@
+"""GPU parity of the 1P2I path (periodic along x, isolated in y and z) against
+the FP64 oracle, through the C ABI.
+
+The device builds its table from a different representation of the same
+integrals (a non-oscillatory form of K and M by the trapezoidal rule) than
+the oracle (Gauss-Legendre quadrature of the Bessel integrals), so agreement
+to 1e-12 checks both.  Bars as for the other boundary types: table and series
+1e-12 of each channel's largest value; lists bit-exact; FP64 walk 1e-12; FP32
+walk 1e-6 of max |Phi| (the potential changes sign) and 1e-5 of max |a|;
+column maps 1e-12 (FP64) and 1e-5 (FP32) of the largest column.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1708_06142_amd as ot
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+BC = (1, 0, 0)
+
+
+def grid():
+    return workloads.small_amr(bc=BC, nroot=(1, 2, 2))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", torch.float64)
+
+
+def test_table_parity():
+    g = grid()
+    s = ot.Solver.for_grid(g, ewald_n=24)
+    s.ewald_prepare()
+    tab = s.export_ewald_table()
+    ref = oracle.ewald_table(BC, g.box(), n=24)
+    for ch in range(10):
+        scale = np.abs(ref[..., ch]).max()
+        assert np.abs(tab[..., ch] - ref[..., ch]).max() <= 1e-12 * scale, ch
+
+
+def test_points_series_table_and_far_limit():
+    g = grid()
+    box = g.box()
+    s = ot.Solver.for_grid(g, ewald_n=24)
+    rng = np.random.default_rng(5)
+    d = rng.uniform(-1, 1, (300, 3)) * [0.5, 2.0, 2.0]
+    d[0] = [0.25, 0.0, 0.0]  # on the periodic axis
+    d[1] = [0.5, 0.0, 1e-3]
+    out = torch.empty((d.shape[0], 4), dtype=torch.float64, device="cuda")
+    s.ewald_points("exact", dev(d), out)
+    ref = oracle.ewald_eval(BC, box, d, correction=True)[:, :4]
+    got = out.cpu().numpy()
+    for ch in range(4):
+        assert np.abs(got[:, ch] - ref[:, ch]).max() <= 1e-12 * np.abs(ref[:, ch]).max(), ch
+    s.ewald_points("table", dev(d), out)
+    tab = oracle.ewald_table(BC, box, n=24)
+    reft = oracle.ewald_table_lookup(BC, box, tab, d)[:, :4]
+    got = out.cpu().numpy()
+    for ch in range(4):
+        assert np.abs(got[:, ch] - reft[:, ch]).max() <= 1e-12 * np.abs(reft[:, ch]).max(), ch
+    # beyond 4 Lx from the axis both methods give the line-mass limit, which
+    # differs from the series by less than 1e-10
+    far = np.array([[0.1, 4.2, 0.3], [-0.4, -3.0, 3.1], [0.3, 0.2, -6.0]])
+    big = (1.0, 14.0, 14.0)
+    sf = ot.Solver(nroot=(1, 14, 14), root_size=1.0, bc=BC, ewald_n=8)
+    of = torch.empty((3, 4), dtype=torch.float64, device="cuda")
+    reff = oracle.ewald_eval(BC, big, far, correction=True)[:, :4]
+    for m in ("exact", "table"):
+        sf.ewald_points(m, dev(far), of)
+        assert np.abs(of.cpu().numpy() - reff).max() < 1e-10, m
+
+
+@pytest.mark.parametrize("mac", ["bh", "ape", "mpe"])
+def test_walk_parity(mac):
+    g = grid()
+    kw = dict(theta=0.5, ewald_n=32) if mac == "bh" else dict(mac=mac, a_lim=1e-2, ewald_n=32)
+    okw = {k: v for k, v in kw.items() if k != "ewald_n"}
+    t = oracle.Tree(g, ew_n=32, ewald="table", **okw)
+    pr, ar, _ = t.walk_group()
+    phi, acc, _, s = ot.run(g, fp64=True, **kw)
+    for b in range(0, g.nb, 5):
+        assert np.array_equal(np.sort(s.export_list(b).astype(np.int64)), np.sort(t.block_list(b))), b
+    p, a = phi.cpu().numpy(), acc.cpu().numpy()
+    np.testing.assert_allclose(p, pr, rtol=1e-12, atol=0)
+    assert np.abs(a - ar).max() <= 1e-12 * np.abs(ar).max()
+    phi, acc, _, _ = ot.run(g, fp64=False, **kw)
+    p32, a32 = phi.cpu().numpy().astype(np.float64), acc.cpu().numpy().astype(np.float64)
+    assert np.abs(p32 - pr).max() <= 1e-6 * np.abs(pr).max()
+    assert np.abs(a32 - ar).max() <= 1e-5 * np.sqrt((ar ** 2).sum(0)).max()
+
+
+def test_column_walk_parity():
+    g = grid()
+    kw = dict(theta=0.5, nside=1, ewald_n=32)
+    t = oracle.Tree(g, theta=0.5, nside=1, ew_n=32, ewald="table")
+    sel = np.arange(0, g.nb, 3)
+    pr, ar, _, npr, taur = t.walk_group(sel, columns=True)
+    cells = (512 * sel[:, None] + np.arange(512)).ravel()
+    for fp64, tol in ((True, 1e-12), (False, 1e-5)):
+        phi, acc, _, _, npix, _ = ot.run(g, fp64=fp64, **kw)
+        p = phi.cpu().numpy().astype(np.float64)[cells]
+        a = acc.cpu().numpy().astype(np.float64)[:, cells]
+        n = npix.cpu().numpy().astype(np.float64)[sel]
+        assert np.abs(p - pr).max() <= (1e-12 if fp64 else 1e-6) * np.abs(pr).max()
+        assert np.abs(a - ar).max() <= (1e-12 if fp64 else 1e-5) * np.abs(ar).max()
+        assert np.abs(n - npr).max() <= tol * np.abs(npr).max()
+
+
+def test_surrogate_is_rejected():
+    s = ot.Solver.for_grid(grid(), ewald_n=8)
+    with pytest.raises(ot.OTError) as e:
+        s.mlp_train(nsamples=1024, batch=256, epochs=1, nval=256)
+    assert e.value.status == ot.OT_ERR_UNSUPPORTED
