@@ -24,8 +24,11 @@ def test_param_validation():
         ot.Solver(theta=-1.0)
     with pytest.raises(ot.OTError, match="INVALID_ARG"):
         ot.Solver(root_size=0.0)
-    with pytest.raises(ot.OTError, match="UNSUPPORTED"):
-        ot.Solver(bc=(1, 0, 0))
+    # x-periodic 1P2I and x, y-periodic 2P1I are the mixed cases; others are not
+    for bc in ((0, 1, 0), (0, 0, 1), (1, 0, 1), (0, 1, 1)):
+        with pytest.raises(ot.OTError, match="UNSUPPORTED"):
+            ot.Solver(bc=bc)
+    ot.Solver(bc=(1, 0, 0)).close()
     with pytest.raises(ot.OTError, match="INVALID_ARG"):
         ot.Solver(ewald_n=1)
     s = ot.Solver(bc=(1, 1, 0), nroot=(1, 1, 4))
