@@ -61,6 +61,7 @@ def parse():
                     help="skip the large AMR leg (15.2M cells, 2P1I, 192-pixel columns)")
     ap.add_argument("--no-mpe", action="store_true", help="skip the MPE MAC leg")
     ap.add_argument("--no-abu", action="store_true", help="skip the adaptive block update leg")
+    ap.add_argument("--no-p1", action="store_true", help="skip the 1P2I filament leg")
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the Plummer AMR leg (2.6M cells, box 1x1x4, 2P1I, 64^3 Ewald table)")
     return ap.parse_args()
@@ -269,6 +270,45 @@ def c3_leg(steps):
     return out
 
 
+def p1_leg(steps):
+    """1P2I configuration: a filament along the periodic x axis of a 1 x 2 x 2
+    box (isothermal-cylinder profile, H = 0.1, modulated along x, lognormal
+    noise), 64 x 128 x 128 cells, APE a_lim = 1e-3 a_max, FP64-generated 64^3
+    Ewald table: the FP32-Kahan table walk beside the FP64 table walk."""
+    import torch
+    import paper_1708_06142_amd as ot
+    import workloads
+    g = workloads.filament_1p2i(64)
+    n = g.ncells
+    rho = torch.from_numpy(g.rho.reshape(-1)).cuda()
+    s0 = ot.Solver.for_grid(g, mac="ape", eps_lim=1e-3, theta=0.5, ewald_n=64)
+    s0.build(rho)
+    a_lim = s0.solve(torch.empty(n, device="cuda"), torch.empty(3 * n, device="cuda")).a_lim_used
+    s0.close()
+    s = ot.Solver.for_grid(g, mac="ape", a_lim=a_lim, theta=0.5, ewald_n=64)
+    out = {"workload": f"filament 1x2x2 box, 64x128x128 cells ({g.nb} blocks), 1P2I, APE a_lim 1e-3 a_max, "
+                       "64^3 Ewald table", "a_lim": a_lim}
+    res = {}
+    for label, fp64 in (("table_fp32", False), ("table_fp64", True)):
+        dt = torch.float64 if fp64 else torch.float32
+        outs = (torch.empty(n, dtype=dt, device="cuda"), torch.empty(3 * n, dtype=dt, device="cuda"))
+        ms, st, ms_eval, ms_list, _ = timed_steps(s, rho, outs, fp64, steps, 1)
+        res[label] = outs
+        flop = st.n_interactions * (FLOP_PAIR_ISO + 46) / (ms_eval * 1e-3) / 1e12
+        peak = PEAK_FP64_VALU if fp64 else PEAK_FP32_VALU
+        out[label] = {"value": n / (ms * 1e-3), "unit": "cells/s", "ms_per_step": ms, "ms_eval": ms_eval,
+                      "ms_lists": ms_list, "n_int": st.n_interactions,
+                      "roofline": {"bound": "alu", "kernel": f"k_eval{'64' if fp64 else '32'}<1P2I>",
+                                   "achieved": flop, "peak": peak, "unit": "TFLOP/s", "frac": flop / peak,
+                                   "flop_per_pair": FLOP_PAIR_ISO + 46}}
+    s.close()
+    (p32, a32), (p64, a64) = res["table_fp32"], res["table_fp64"]
+    out["table_fp32"]["dphi_maxnorm_vs_fp64"] = float((p32.double() - p64).abs().max() / p64.abs().max())
+    a64n = a64.view(3, -1).pow(2).sum(0).sqrt().max()
+    out["table_fp32"]["da_maxnorm_vs_fp64"] = float((a32.double() - a64).abs().max() / a64n)
+    return out
+
+
 def mpe_leg(grid, rho, a_lim, steps, nside):
     """The benchmark field with the MPE MAC (Eq. (2) with p = 1) at the same
     absolute limit: the whole path (tree build with the B_2, B_3 moments,
@@ -458,6 +498,8 @@ def main():
         out["mpe"] = mpe_leg(grid, rho, a_lim, max(2, args.steps // 2), args.nside)
     if not args.no_c3:
         out["c3"] = c3_leg(max(2, args.steps // 2))
+    if not args.no_p1:
+        out["p1"] = p1_leg(max(2, args.steps // 2))
     if not args.no_c5:
         out["c5"] = c5_leg()
     if not args.no_cpu:

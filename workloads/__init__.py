@@ -143,6 +143,22 @@ def c2_lognormal(n=128, seed=2, sigma=1.5, bc=(0, 0, 0)):
                 name=f"lognormal{n}", meta={"seed": seed, "sigma": sigma})
 
 
+def filament_1p2i(n=64, seed=13, H=0.1, amp=0.3, noise=0.5):
+    """A filament along the periodic x axis of a 1 x 2 x 2 box (1P2I): the
+    isothermal-cylinder profile rho = 1/(1 + r^2/(8 H^2))^2 about the line
+    y = z = 1, modulated by 1 + amp cos(2 pi x) and seeded lognormal cell noise
+    (sigma ``noise``), n cells per root edge (n x 2n x 2n cells)."""
+    nroot = (1, 2, 2)
+    level, coord = uniform_blocks(n, nroot)
+    xc = cell_centres(1.0, (0.0, 0.0, 0.0), level, coord)
+    r2 = (xc[..., 1] - 1.0) ** 2 + (xc[..., 2] - 1.0) ** 2
+    rho = (1.0 + amp * np.cos(2 * np.pi * xc[..., 0])) / (1.0 + r2 / (8 * H * H)) ** 2
+    rng = np.random.default_rng(seed)
+    rho = rho * rng.lognormal(-0.5 * noise * noise, noise, rho.shape)
+    return Grid(nroot, 1.0, (0.0, 0.0, 0.0), level, coord, rho, (1, 0, 0),
+                name=f"filament{n}", meta={"seed": seed, "H": H})
+
+
 # ---------------------------------------------------------------- AMR
 def _key(l, c):
     return (int(l), int(c[0]), int(c[1]), int(c[2]))
