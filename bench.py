@@ -344,7 +344,7 @@ def mpe_leg(grid, rho, a_lim, steps, nside):
     return out
 
 
-def abu_leg(grid, a_lim, nsnap=6, seed=12):
+def abu_leg(grid, a_lim, nsnap=6, seed=12, nside=0):
     """Adaptive block update (gravity only) on a seeded sequence of snapshots of
     the benchmark field: each snapshot multiplies the density by 1 + 0.3 G(x - c),
     G a Gaussian bump of width 0.05 whose centre c moves by 0.02 per snapshot
@@ -359,11 +359,14 @@ def abu_leg(grid, a_lim, nsnap=6, seed=12):
     step = rng.normal(size=3)
     step *= 0.02 / np.linalg.norm(step)
     n = grid.ncells
-    s = ot.Solver.for_grid(grid, mac="ape", a_lim=a_lim, theta=0.5)
+    s = ot.Solver.for_grid(grid, mac="ape", a_lim=a_lim, theta=0.5, nside=nside)
     phi = torch.empty(n, device="cuda")
     acc = torch.empty(3 * n, device="cuda")
     phi_f = torch.empty(n, device="cuda")
     acc_f = torch.empty(3 * n, device="cuda")
+    npx = 12 * nside * nside
+    npix, tau, npix_f, tau_f = ((torch.empty(m, device="cuda") for m in (n * npx, n, n * npx, n)) if nside
+                                else (None,) * 4)
     rows = []
     for k in range(nsnap):
         ck = c + k * step
@@ -372,27 +375,33 @@ def abu_leg(grid, a_lim, nsnap=6, seed=12):
         s.build(rho)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        stf = s.solve(phi_f, acc_f)
+        stf = s.solve(phi_f, acc_f, npix_f, tau_f)
         torch.cuda.synchronize()
         ms_full = (time.perf_counter() - t0) * 1e3
         if k == 0:
             phi.copy_(phi_f)
             acc.copy_(acc_f)
+            if nside:
+                npix.copy_(npix_f)
+                tau.copy_(tau_f)
             tol = 1e-3 * float(acc_f.view(3, -1).double().pow(2).sum(0).sqrt().max())
             continue
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st, upd = s.solve_abu(phi, acc, tol)
+        st, upd = s.solve_abu(phi, acc, tol, npix=npix, tau=tau)
         torch.cuda.synchronize()
         ms_abu = (time.perf_counter() - t0) * 1e3
         amax = acc_f.view(3, -1).double().pow(2).sum(0).sqrt().max()
         ea = float((acc.double() - acc_f.double()).view(3, -1).pow(2).sum(0).sqrt().max() / amax)
-        rows.append({"updated_frac": float(upd.mean()), "ms_abu": ms_abu, "ms_full": ms_full,
-                     "ms_eval_abu": st.ms_eval, "ms_eval_full": stf.ms_eval, "e_a_max_vs_full": ea})
+        row = {"updated_frac": float(upd.mean()), "ms_abu": ms_abu, "ms_full": ms_full,
+               "ms_eval_abu": st.ms_eval, "ms_eval_full": stf.ms_eval, "e_a_max_vs_full": ea}
+        if nside:
+            row["e_npix_max_vs_full"] = float((npix - npix_f).abs().max() / npix_f.abs().max())
+        rows.append(row)
     s.close()
     return {"workload": f"lognormal 128^3 x {nsnap} snapshots with a moving Gaussian bump (amplitude 0.3, "
                         f"width 0.05, 0.02 per snapshot, seed {seed}), APE a_lim 1e-3 a_max, FP32-Kahan walk, "
-                        "ABU tolerance 1e-3 a_max",
+                        f"{npx if nside else 'no'} columns, ABU tolerance 1e-3 a_max",
             "snapshots": rows,
             "mean_updated_frac": float(np.mean([r["updated_frac"] for r in rows])),
             "ms_abu_mean": float(np.mean([r["ms_abu"] for r in rows])),
@@ -494,6 +503,8 @@ def main():
         out["surrogate"] = surrogate_leg(grid, rho, args.surrogate_steps, args.nside)
     if not args.no_abu:
         out["abu"] = abu_leg(grid, a_lim)
+        if args.nside:
+            out["abu_columns"] = abu_leg(grid, a_lim, nside=args.nside)
     if not args.no_mpe:
         out["mpe"] = mpe_leg(grid, rho, a_lim, max(2, args.steps // 2), args.nside)
     if not args.no_c3:

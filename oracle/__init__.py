@@ -178,15 +178,27 @@ class Tree:
         lib().or_tree_mpe_export(self.h, _ptr(B2), _ptr(B3))
         return B2, B3
 
-    def walk_abu(self, prev_phi, prev_acc, tol):
-        """Adaptive block update (gravity only): returns phi [nb*512], acc [3, nb*512]
-        and updated [nb] (1 where the block was evaluated)."""
+    def walk_abu(self, prev_phi, prev_acc, tol, prev_npix=None, prev_tau=None):
+        """Adaptive block update (Sec. 2.2.5): returns phi [nb*512], acc [3, nb*512]
+        and updated [nb] (1 where the block was evaluated).  With prev_npix
+        [nb, Npix, 512] and prev_tau [nb*512] (trees with nside > 0) also npix and
+        tau: the group walk's columns for the updated blocks, the previous ones
+        for the others (the decision is the gravity corner test either way)."""
         n = 512 * self.nb
         pp = np.ascontiguousarray(prev_phi, dtype=np.float64).reshape(n)
         pa = np.ascontiguousarray(prev_acc, dtype=np.float64).reshape(3, n)
         phi, acc, upd = np.empty(n), np.empty((3, n)), np.empty(self.nb, np.int32)
         lib().or_walk_group_abu(self.h, _ptr(pp), _ptr(pa), float(tol), _ptr(phi), _ptr(acc), _ptr(upd))
-        return phi, acc, upd
+        if prev_npix is None:
+            return phi, acc, upd
+        npix = np.array(prev_npix, dtype=np.float64).reshape(self.nb, -1, 512)
+        tau = np.array(prev_tau, dtype=np.float64).reshape(self.nb, 512)
+        sel = np.nonzero(upd)[0]
+        if sel.size:
+            _, _, _, nps, ts = self.walk_group(sel, columns=True)
+            npix[sel] = nps
+            tau[sel] = ts.reshape(sel.size, 512)
+        return phi, acc, upd, npix, tau.reshape(n)
 
     def block_list(self, lb):
         n = lib().or_block_list(self.h, lb, None, 0)

@@ -92,8 +92,8 @@ def lib():
         L.ot_build.argtypes = [vp, vp, vp]
         L.ot_solve.argtypes = [vp, vp, vp, vp, vp, C.POINTER(Stats), vp]
         L.ot_solve64.argtypes = [vp, vp, vp, vp, vp, C.POINTER(Stats), vp]
-        L.ot_solve_abu.argtypes = [vp, vp, vp, C.c_double, vp, C.POINTER(Stats), vp]
-        L.ot_solve_abu64.argtypes = [vp, vp, vp, C.c_double, vp, C.POINTER(Stats), vp]
+        L.ot_solve_abu.argtypes = [vp, vp, vp, vp, vp, C.c_double, vp, C.POINTER(Stats), vp]
+        L.ot_solve_abu64.argtypes = [vp, vp, vp, vp, vp, C.c_double, vp, C.POINTER(Stats), vp]
         L.ot_export_raytable.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), vp, vp, vp, vp]
         L.ot_ewald_prepare.argtypes = [vp, vp]
         L.ot_num_amr_nodes.restype = i64
@@ -235,17 +235,17 @@ class Solver:
                                      _dev_ptr(tau, f), C.byref(st), _stream(stream)))
         return st
 
-    def solve_abu(self, phi, acc, tol, fp64=False, stream=None):
-        """Adaptive block update (gravity only): phi, acc hold the previous
-        step's solution and are updated in place where a block's corner cells
-        moved by tol or more.  Returns (stats, updated [nb] int32)."""
+    def solve_abu(self, phi, acc, tol, fp64=False, npix=None, tau=None, stream=None):
+        """Adaptive block update: phi, acc (and npix, tau when nside > 0) hold
+        the previous step's solution and are updated in place where a block's
+        corner cells moved by tol or more.  Returns (stats, updated [nb] int32)."""
         import torch
         st = Stats()
         f = torch.float64 if fp64 else torch.float32
         upd = np.empty(self.nb, np.int32)
         fn = lib().ot_solve_abu64 if fp64 else lib().ot_solve_abu
-        self._check(fn(self.h, _dev_ptr(phi, f), _dev_ptr(acc, f), float(tol), _np_ptr(upd), C.byref(st),
-                       _stream(stream)))
+        self._check(fn(self.h, _dev_ptr(phi, f), _dev_ptr(acc, f), _dev_ptr(npix, f), _dev_ptr(tau, f),
+                       float(tol), _np_ptr(upd), C.byref(st), _stream(stream)))
         return st, upd
 
     def export_raytable(self, stream=None):

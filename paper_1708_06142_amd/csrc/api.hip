@@ -654,17 +654,18 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
   return OT_OK;
 }
 
-// Adaptive block update (Sec. 2.2.5), gravity only: the eight corner cells of
-// every block first (FP64, against the previous acceleration in acc), then the
-// full evaluation of the blocks where one of them moved by tol or more; the
-// other blocks keep phi and acc.
-ot_status abu_impl(ot_ctx *c, bool fp64, void *phi, void *acc, double tol, int32_t *updated, ot_stats *stats,
-                   void *stream) {
+// Adaptive block update (Sec. 2.2.5): the eight corner cells of every block
+// first (FP64 gravity, against the previous acceleration in acc), then the
+// full evaluation (with the columns when nside > 0) of the blocks where one of
+// them moved by tol or more; the other blocks keep phi, acc, npix and tau.
+ot_status abu_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, void *tau, double tol,
+                   int32_t *updated, ot_stats *stats, void *stream) {
   if (!c) return OT_ERR_INVALID_ARG;
   c->err.clear();
   if (!phi || !acc) return fail(c, OT_ERR_INVALID_ARG, "phi and acc must be device pointers");
   if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(c, OT_ERR_INVALID_ARG, "tol must be finite and >= 0");
-  if (c->p.nside > 0) return fail(c, OT_ERR_UNSUPPORTED, "the adaptive block update covers gravity only (nside 0)");
+  const bool cols = c->p.nside > 0;
+  if (cols && (!npix || !tau)) return fail(c, OT_ERR_INVALID_ARG, "nside > 0 needs npix and tau");
   if (!c->built) return fail(c, OT_ERR_STATE, "ot_solve_abu before a successful ot_build");
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(c->p.device));
@@ -675,6 +676,7 @@ ot_status abu_impl(ot_ctx *c, bool fp64, void *phi, void *acc, double tol, int32
       return fail(c, OT_ERR_UNSUPPORTED, "the adaptive block update uses the Ewald table");
     OTCHK(ewald_prepare(c, st));
   }
+  if (cols) OTCHK(raytable_prepare(c, st));
   double alim = 0.0;
   if (c->p.mac == OT_MAC_APE || c->p.mac == OT_MAC_MPE) OTCHK(ape_limit(c, st, &alim));
   for (int i = 0; i < 4; ++i)
@@ -685,7 +687,7 @@ ot_status abu_impl(ot_ctx *c, bool fp64, void *phi, void *acc, double tol, int32
     OTCHK(dalloc(c, c->abu_blist, nb * sizeof(int32_t)));
   }
   HIPCHK(hipEventRecord(c->ev[0], st));
-  OTCHK(build_lists(c, mac_params(c, c->p.mac, alim, false), false, st));
+  OTCHK(build_lists(c, mac_params(c, c->p.mac, alim, cols), cols, st));
   HIPCHK(hipEventRecord(c->ev[1], st));
   ot::DevTree T = dev_tree(c);
   ot::EwaldP E = ewald_desc(c);
@@ -701,7 +703,13 @@ ot_status abu_impl(ot_ctx *c, bool fp64, void *phi, void *acc, double tol, int32
   const int64_t nup = (int64_t)blist.size();
   if (nup > 0)
     HIPCHK(hipMemcpyAsync(c->abu_blist.ptr, blist.data(), nup * sizeof(int32_t), hipMemcpyHostToDevice, st));
-  if (fp64)
+  if (cols) {
+    const ot::ColP C = col_params(c);
+    HIPCHK(ot::launch_eval_cols(fp64, T, E, C, P<int64_t>(c->loff), P<double4>(c->lrec), P<int32_t>(c->lid),
+                                P<double>(c->lh), phi, acc, npix, tau, c->p.G,
+                                ot::cols_lds_cpw(C.npix, fp64, C.nthr), false, nullptr, st,
+                                P<int32_t>(c->abu_blist), nup));
+  } else if (fp64)
     HIPCHK(ot::launch_eval64(T, E, P<int64_t>(c->loff), P<double4>(c->lrec), (double *)phi, (double *)acc, c->p.G,
                              st, P<int32_t>(c->abu_blist), nup));
   else
@@ -735,14 +743,14 @@ ot_status abu_impl(ot_ctx *c, bool fp64, void *phi, void *acc, double tol, int32
 
 extern "C" {
 
-ot_status ot_solve_abu(ot_ctx *c, float *phi, float *acc, double tol, int32_t *updated_host, ot_stats *stats,
-                       void *stream) {
-  return abu_impl(c, false, phi, acc, tol, updated_host, stats, stream);
+ot_status ot_solve_abu(ot_ctx *c, float *phi, float *acc, float *npix, float *tau, double tol,
+                       int32_t *updated_host, ot_stats *stats, void *stream) {
+  return abu_impl(c, false, phi, acc, npix, tau, tol, updated_host, stats, stream);
 }
 
-ot_status ot_solve_abu64(ot_ctx *c, double *phi, double *acc, double tol, int32_t *updated_host,
-                         ot_stats *stats, void *stream) {
-  return abu_impl(c, true, phi, acc, tol, updated_host, stats, stream);
+ot_status ot_solve_abu64(ot_ctx *c, double *phi, double *acc, double *npix, double *tau, double tol,
+                         int32_t *updated_host, ot_stats *stats, void *stream) {
+  return abu_impl(c, true, phi, acc, npix, tau, tol, updated_host, stats, stream);
 }
 
 void ot_params_default(ot_params *p) {

@@ -376,14 +376,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                    const int32_t *__restrict__ ids, const double *__restrict__ lh,
                                                    Real *__restrict__ phi, Real *__restrict__ acc,
                                                    Real *__restrict__ npix, Real *__restrict__ tau, double negG,
-                                                   int cpw, int lcpw) {
+                                                   int cpw, int lcpw, const int32_t *__restrict__ blist) {
   __shared__ uint8_t lut[LUT_BYTES];
   __shared__ ColRec tile[TILE];
   extern __shared__ __align__(16) unsigned char smem[];
   double *thr = reinterpret_cast<double *>(smem);
   Real *map = reinterpret_cast<Real *>(thr + C.nthr);
   const int nchunk = 512 / cpw;
-  const int64_t b = blockIdx.x / nchunk;
+  // blist (optional): the leaf blocks to evaluate, else all of them in order
+  const int64_t b = blist ? (int64_t)blist[blockIdx.x / nchunk] : (int64_t)(blockIdx.x / nchunk);
   const int tid = threadIdx.x;
   const int ci = (int)(blockIdx.x % nchunk) * cpw + tid;
   const int64_t ncell = T.nb * 512;
@@ -860,7 +861,8 @@ hipError_t launch_raytable_pack(const RayTableP &P, const int64_t *off, const ui
 hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const ColP &C, const int64_t *off,
                             const double4 *rec, const int32_t *ids, const double *lh, void *phi, void *acc,
                             void *npix, void *tau, double G, int cpw, bool newton_only, int *wg_per_cu,
-                            hipStream_t st) {
+                            hipStream_t st, const int32_t *blist, int64_t nblist) {
+  if (blist && nblist <= 0) return hipSuccess;
   const bool gmap = cpw == 0;
   if (gmap) cpw = 256;
   // dynamic LDS: the thresholds, and the maps unless they are in npix
@@ -872,7 +874,7 @@ hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const 
   // map addresses shift the packed pixels by lcpw + 2 (FP32) or + 3 (FP64),
   // at least 9 bits (the bits above 22 hold a long row's count and offset)
   if (lcpw + (fp64 ? 3 : 2) < 9) return hipErrorInvalidValue;
-  dim3 grid((unsigned)(T.nb * (512 / cpw))), blk(cpw);
+  dim3 grid((unsigned)((blist ? nblist : T.nb) * (512 / cpw))), blk(cpw);
 #define OT_LAUNCH2(R, B, N, M)                                                                                \
   do {                                                                                                        \
     if (sm + COLS_STATIC_LDS > 65536) {                                                                       \
@@ -884,7 +886,7 @@ hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const 
                                                                   sm) != hipSuccess)                          \
       *wg_per_cu = 0;                                                                                         \
     hipLaunchKernelGGL((k_eval_cols<R, B, N, M>), grid, blk, sm, st, T, E, C, off, rec, ids, lh, (R *)phi,   \
-                       (R *)acc, (R *)npix, (R *)tau, -G, cpw, lcpw);                                        \
+                       (R *)acc, (R *)npix, (R *)tau, -G, cpw, lcpw, blist);                                 \
   } while (0)
 #define OT_LAUNCH(R, B, N)          \
   do {                              \

@@ -95,11 +95,12 @@ int cols_lds_cpw(int npix, bool fp64, int nthr);
 hipError_t launch_column_bins(const ColP &C, int64_t n, const double *d, const double *h, int32_t *row,
                               hipStream_t st);
 // cpw: cols_lds_cpw (0: maps in npix);
-// wg_per_cu (may be null): workgroups of the launched kernel resident per CU
+// wg_per_cu (may be null): workgroups of the launched kernel resident per CU;
+// blist (optional): evaluate only the nblist leaf blocks listed there
 hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const ColP &C, const int64_t *off,
                             const double4 *rec, const int32_t *ids, const double *lh, void *phi, void *acc,
                             void *npix, void *tau, double G, int cpw, bool newton_only, int *wg_per_cu,
-                            hipStream_t st);
+                            hipStream_t st, const int32_t *blist = nullptr, int64_t nblist = 0);
 // rows of the offsets (i, j, k) cell sizes between two cells of one size,
 // |i|, |j|, |k| <= R (k slowest, i fastest), written at rows C.lat0 + ... of
 // rows, rows8 and quad_w64: copies of the table rows that the walk's binning

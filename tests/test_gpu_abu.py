@@ -85,3 +85,41 @@ def test_abu_perturbed_matches_oracle(fp64, bc):
         else:
             assert (np.abs(pb[ev] / prb[ev] - 1)).max() <= 1e-6
         assert np.abs(ab[:, ev] - arb[:, ev]).max() <= 1e-5 * amax
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_abu_columns_matches_oracle(fp64):
+    """With 12-pixel columns: kept blocks keep phi, acc, the maps and tau bit
+    for bit; updated blocks match the oracle's walk with columns at the walk's
+    bar (1e-12 FP64, 1e-6 / 1e-5 FP32; maps relative to the largest column)."""
+    g = workloads.small_amr()
+    kw = dict(theta=0.5, nside=1)
+    p0, a0, _, n0, t0 = oracle.Tree(g, **kw).walk_group(columns=True)
+    if not fp64:
+        p0, a0, n0, t0 = (x.astype(np.float32).astype(np.float64) for x in (p0, a0, n0, t0))
+    g1 = _perturbed(g)
+    t1 = oracle.Tree(g1, **kw)
+    a1 = t1.walk_group()[1]
+    tol = 1e-3 * np.sqrt((a1 ** 2).sum(0)).max()
+    pr, ar, upd_r, nr, tr = t1.walk_abu(p0, a0, tol, n0, t0)
+    s = _solver(g1, nside=1)
+    dt = torch.float64 if fp64 else torch.float32
+    phi, acc = (torch.from_numpy(x.reshape(-1).copy()).to(dt).cuda() for x in (p0, a0))
+    npix, tau = (torch.from_numpy(x.reshape(-1).copy()).to(dt).cuda() for x in (n0, t0))
+    st, upd = s.solve_abu(phi, acc, tol, fp64=fp64, npix=npix, tau=tau)
+    assert 0 < upd_r.sum() < g.nb
+    da = np.sqrt(((a1 - a0) ** 2).sum(0)).reshape(g.nb, 512)[:, CORNERS].max(1)
+    differ = upd != upd_r
+    assert np.all(np.abs(da[differ] - tol) <= 1e-9 * tol)
+    keep, ev = ~differ & (upd == 0), ~differ & (upd == 1)
+    got = [x.cpu().numpy().astype(np.float64) for x in (phi, acc, npix, tau)]
+    shapes = [(g.nb, 512), (3, g.nb, 512), (g.nb, -1, 512), (g.nb, 512)]
+    for x, x0, xr, shp in zip(got, (p0, a0, n0, t0), (pr, ar, nr, tr), shapes):
+        xb, x0b, xrb = x.reshape(shp), x0.reshape(shp), xr.reshape(shp)
+        if xb.ndim == 3 and shp[0] == 3:
+            assert np.array_equal(xb[:, keep], x0b[:, keep])
+            e = np.abs(xb[:, ev] - xrb[:, ev]).max() / np.abs(xrb).max()
+        else:
+            assert np.array_equal(xb[keep], x0b[keep])
+            e = np.abs(xb[ev] - xrb[ev]).max() / np.abs(xrb).max()
+        assert e <= (1e-12 if fp64 else 1e-5), e

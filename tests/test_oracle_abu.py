@@ -48,3 +48,24 @@ def test_local_perturbation_follows_the_corner_criterion():
         sel = upd.astype(bool)
         assert np.array_equal(arr[..., sel, :], new[..., sel, :])
         assert np.array_equal(arr[..., ~sel, :], old[..., ~sel, :])
+
+
+def test_columns_follow_the_gravity_decision():
+    """With columns: tolerance 0 gives the plain walk's maps and tau bit for bit;
+    on the perturbed density the updated blocks hold the new walk's maps, the
+    others the previous ones."""
+    g = workloads.small_amr()
+    kw = dict(theta=0.5, nside=1)
+    p0, a0, _, n0, t0 = oracle.Tree(g, **kw).walk_group(columns=True)
+    g1 = _perturbed(g)
+    t1 = oracle.Tree(g1, **kw)
+    p1, a1, _, n1, ta1 = t1.walk_group(columns=True)
+    p, a, upd, npx, tau = t1.walk_abu(p0, a0, 0.0, n0, t0)
+    assert upd.all() and np.array_equal(npx, n1) and np.array_equal(tau, ta1)
+    tol = 1e-3 * np.sqrt((a1 ** 2).sum(0)).max()
+    p, a, upd, npx, tau = t1.walk_abu(p0, a0, tol, n0, t0)
+    sel = upd.astype(bool)
+    assert 0 < sel.sum() < g.nb
+    assert np.array_equal(npx[sel], n1[sel]) and np.array_equal(npx[~sel], n0[~sel])
+    tb, t1b, t0b = tau.reshape(g.nb, 512), ta1.reshape(g.nb, 512), t0.reshape(g.nb, 512)
+    assert np.array_equal(tb[sel], t1b[sel]) and np.array_equal(tb[~sel], t0b[~sel])
