@@ -10,7 +10,7 @@ is one pass of the whole path: tree build (moments), interaction lists, per-cell
 potential + acceleration in FP32 with Kahan-compensated potential, and the
 per-cell column map + tau_avg.  Inputs are resident in HBM before timing.
 
-Prints one JSON line (see the design doc for the roofline and baseline notes).
+Prints one JSON line, with the roofline of the dominant kernel and the oracle's CPU baseline.
 """
 import argparse
 import json
