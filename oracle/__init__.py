@@ -6,6 +6,7 @@ slow and independent of the GPU library (no shared code, headers or tables).
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -20,17 +21,18 @@ ERRORS = {1: "bad level/coord", 2: "duplicate block", 3: "overlapping blocks",
           4: "hole in the block tiling", 5: "bad density", 6: "unsupported BCs"}
 
 
-def build(force=True):
-    """Compile liboracle.so with gcc (FP64, no FMA contraction, OpenMP)."""
-    if not force and os.path.exists(LIB):
-        return LIB
-    srcs = [os.path.join(HERE, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
+def build(force=True, src_dir=HERE, out=LIB, extra=()):
+    """Compile liboracle.so with gcc (FP64, no FMA contraction, OpenMP).
+    src_dir / out / extra flags serve tests that build a copy of the sources."""
+    if not force and os.path.exists(out):
+        return out
+    srcs = [os.path.join(src_dir, s) for s in SOURCES]
+    tmp = out + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-fopenmp",
-           "-ffp-contract=off", "-fno-fast-math", "-o", tmp] + srcs + ["-lm"]
+           "-ffp-contract=off", "-fno-fast-math", *extra, "-o", tmp] + srcs + ["-lm"]
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 class Params(C.Structure):
@@ -57,44 +59,64 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB):
             build()
-        L = C.CDLL(LIB)
-        vp, i64, dp = C.c_void_p, C.c_int64, C.POINTER(C.c_double)
-        L.or_tree_new.restype = vp
-        L.or_tree_new.argtypes = [C.POINTER(Params), i64, vp, vp, vp, C.POINTER(C.c_int)]
-        L.or_tree_free.argtypes = [vp]
-        L.or_tree_na.restype = i64
-        L.or_tree_na.argtypes = [vp]
-        L.or_tree_nn.restype = i64
-        L.or_tree_nn.argtypes = [vp]
-        L.or_tree_export.argtypes = [vp] + [vp] * 7
-        L.or_tree_mpe_export.argtypes = [vp, vp, vp]
-        L.or_walk_group_abu.argtypes = [vp, vp, vp, C.c_double, vp, vp, vp]
-        L.or_block_list.restype = i64
-        L.or_block_list.argtypes = [vp, i64, vp, i64]
-        L.or_walk_group.argtypes = [vp, vp, vp, vp]
-        L.or_walk_group_blocks.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
-        L.or_raymarch.argtypes = [vp, vp, i64, i64, i64, vp]
-        L.or_healpix_vec2pix.restype = i64
-        L.or_healpix_vec2pix.argtypes = [i64, C.c_double, C.c_double, C.c_double]
-        L.or_healpix_pix2ang.argtypes = [i64, i64, vp]
-        L.or_raytable_entries.argtypes = [C.c_int] * 3 + [C.c_double, i64, vp, vp, vp]
-        L.or_raytable_export.restype = i64
-        L.or_raytable_export.argtypes = [C.c_int] * 6 + [C.c_double, vp, vp, vp]
-        L.or_walk_percell.argtypes = [vp, i64, vp, vp, vp, vp]
-        L.or_direct.argtypes = [vp, i64, vp, vp, vp]
-        L.or_morton.restype = C.c_uint64
-        L.or_morton.argtypes = [C.c_uint64] * 3
-        L.or_ewald_eval.argtypes = [C.c_int, vp, C.c_double, C.c_int, C.c_int, C.c_int, i64, vp, vp]
-        L.or_ewald_table.argtypes = [C.c_int, vp, C.c_double, C.c_int, C.c_int, C.c_int, vp]
-        L.or_ewald_table_lookup.argtypes = [C.c_int, vp, C.c_int, vp, i64, vp, vp]
-        L.or_itilde.argtypes = [C.c_double, C.c_double, C.c_double, vp]
-        L.or_kfuncs.argtypes = [C.c_int, C.c_double, C.c_double, vp]
-        L.or_mlp_nparam.restype = C.c_int
-        L.or_mlp_forward.argtypes = [vp, i64, vp, vp]
-        L.or_mlp_grad.restype = C.c_double
-        L.or_mlp_grad.argtypes = [vp, i64, vp, vp, vp]
-        _lib = L
+        _lib = _load(LIB)
     return _lib
+
+
+@contextlib.contextmanager
+def using_library(path):
+    """Run the oracle from another build of its sources (tests that plant a
+    mistake in a copy of them and check that a pin catches it)."""
+    global _lib
+    old = lib()
+    _lib = _load(path)
+    try:
+        yield
+    finally:
+        _lib = old
+
+
+def _load(path):
+    L = C.CDLL(path)
+    vp, i64, dp = C.c_void_p, C.c_int64, C.POINTER(C.c_double)
+    L.or_tree_new.restype = vp
+    L.or_tree_new.argtypes = [C.POINTER(Params), i64, vp, vp, vp, C.POINTER(C.c_int)]
+    L.or_tree_free.argtypes = [vp]
+    L.or_tree_na.restype = i64
+    L.or_tree_na.argtypes = [vp]
+    L.or_tree_nn.restype = i64
+    L.or_tree_nn.argtypes = [vp]
+    L.or_tree_export.argtypes = [vp] + [vp] * 7
+    L.or_tree_mpe_export.argtypes = [vp, vp, vp]
+    L.or_walk_group_abu.argtypes = [vp, vp, vp, C.c_double, vp, vp, vp]
+    L.or_block_list.restype = i64
+    L.or_block_list.argtypes = [vp, i64, vp, i64]
+    L.or_walk_group.argtypes = [vp, vp, vp, vp]
+    L.or_walk_group_blocks.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
+    L.or_raymarch.argtypes = [vp, vp, i64, i64, i64, vp]
+    L.or_healpix_vec2pix.restype = i64
+    L.or_healpix_vec2pix.argtypes = [i64, C.c_double, C.c_double, C.c_double]
+    L.or_healpix_pix2ang.argtypes = [i64, i64, vp]
+    L.or_raytable_entries.argtypes = [C.c_int] * 3 + [C.c_double, i64, vp, vp, vp]
+    L.or_raytable_export.restype = i64
+    L.or_raytable_export.argtypes = [C.c_int] * 6 + [C.c_double, vp, vp, vp]
+    L.or_walk_percell.argtypes = [vp, i64, vp, vp, vp, vp]
+    L.or_direct.argtypes = [vp, i64, vp, vp, vp]
+    L.or_morton.restype = C.c_uint64
+    L.or_morton.argtypes = [C.c_uint64] * 3
+    L.or_ewald_eval.argtypes = [C.c_int, vp, C.c_double, C.c_int, C.c_int, C.c_int, i64, vp, vp]
+    L.or_ewald_table.argtypes = [C.c_int, vp, C.c_double, C.c_int, C.c_int, C.c_int, vp]
+    L.or_ewald_table_lookup.argtypes = [C.c_int, vp, C.c_int, vp, i64, vp, vp]
+    L.or_itilde.argtypes = [C.c_double, C.c_double, C.c_double, vp]
+    L.or_kfuncs.argtypes = [C.c_int, C.c_double, C.c_double, vp]
+    L.or_mlp_nparam.restype = C.c_int
+    L.or_mlp_forward.argtypes = [vp, i64, vp, vp]
+    L.or_mlp_grad.restype = C.c_double
+    L.or_mlp_grad.argtypes = [vp, i64, vp, vp, vp]
+    L.or_adam_update.argtypes = [vp, vp, vp, vp, i64, C.c_double, i64]
+    L.or_mlp_adam.restype = C.c_double
+    L.or_mlp_adam.argtypes = [vp, vp, vp, i64, vp, vp, C.c_double, i64]
+    return L
 
 
 def _ptr(a):
@@ -333,7 +355,7 @@ def raytable(nside, il_ntheta=25, il_nphi=50, il_npsi=25, il_nr=50, il_nazi=100,
 
 
 # ---------------------------------------------------------------- MLP
-MLP_NPARAM = 8836  # 3 -> 64 -> 64 -> 64 -> 4
+MLP_NPARAM, MLP_NOUT = 8836, 4  # 3 -> 64 -> 64 -> 64 -> 4
 
 
 def mlp_forward(params, x):
@@ -353,3 +375,20 @@ def mlp_grad(params, x, t):
     g = np.empty(MLP_NPARAM)
     loss = lib().or_mlp_grad(_ptr(p), x.shape[0], _ptr(x), _ptr(t), _ptr(g))
     return loss, g
+
+
+def adam_update(p, g, m, v, lr, step):
+    """One Adam step on copies of p, m, v with gradient g: returns (p, m, v)."""
+    p, m, v = (np.array(a, dtype=np.float64) for a in (p, m, v))
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    lib().or_adam_update(_ptr(p), _ptr(g), _ptr(m), _ptr(v), p.size, float(lr), int(step))
+    return p, m, v
+
+
+def mlp_adam(params, m, v, x, t, lr, step):
+    """Batch gradient + one Adam step (FP64): returns (loss, params, m, v)."""
+    p, m, v = (np.array(a, dtype=np.float64) for a in (params, m, v))
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.float64)
+    t = np.ascontiguousarray(np.atleast_2d(t), dtype=np.float64)
+    loss = lib().or_mlp_adam(_ptr(p), _ptr(m), _ptr(v), x.shape[0], _ptr(x), _ptr(t), float(lr), int(step))
+    return loss, p, m, v

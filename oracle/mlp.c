@@ -133,3 +133,30 @@ double or_mlp_grad(const double *p, int64_t B, const double *x, const double *t,
   }
   return loss;
 }
+
+/* One step of Adam (Kingma & Ba 2015, Algorithm 1) on n parameters p with the
+ * gradient g: first and second moment estimates m, v with decay rates
+ * beta1 = 0.9, beta2 = 0.999, bias corrections 1 - beta^step (step >= 1),
+ * step size lr and eps = 1e-8 added to the root of the corrected second
+ * moment.  m and v are updated in place. */
+void or_adam_update(double *p, const double *g, double *m, double *v, int64_t n, double lr, int64_t step) {
+  const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+  const double c1 = 1.0 - pow(b1, (double)step), c2 = 1.0 - pow(b2, (double)step);
+  for (int64_t i = 0; i < n; ++i) {
+    m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+    v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+    const double mhat = m[i] / c1, vhat = v[i] / c2;
+    p[i] = p[i] - lr * mhat / (sqrt(vhat) + eps);
+  }
+}
+
+/* The training step: the batch gradient of the MSE, then one Adam step;
+ * returns the batch loss before the step. */
+double or_mlp_adam(double *p, double *m, double *v, int64_t B, const double *x, const double *t, double lr,
+                   int64_t step) {
+  double *g = (double *)malloc(sizeof(double) * NPARAM);
+  const double loss = or_mlp_grad(p, B, x, t, g);
+  or_adam_update(p, g, m, v, NPARAM, lr, step);
+  free(g);
+  return loss;
+}

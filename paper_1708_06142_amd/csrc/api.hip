@@ -682,10 +682,11 @@ ot_status abu_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, void 
   for (int i = 0; i < 4; ++i)
     if (!c->ev[i]) HIPCHK(hipEventCreate(&c->ev[i]));
   const int64_t nb = c->topo.nb;
-  if (!c->abu_flag.ptr) {
-    OTCHK(dalloc(c, c->abu_flag, nb * sizeof(int32_t)));
-    OTCHK(dalloc(c, c->abu_blist, nb * sizeof(int32_t)));
-  }
+  // grow-only: a later ot_set_blocks may have brought more blocks
+  OTCHK(dalloc(c, c->abu_flag, nb * sizeof(int32_t)));
+  OTCHK(dalloc(c, c->abu_blist, nb * sizeof(int32_t)));
+  if (c->abu_flag.bytes < (size_t)nb * sizeof(int32_t) || c->abu_blist.bytes < (size_t)nb * sizeof(int32_t))
+    return fail(c, OT_ERR_STATE, "adaptive block update buffers smaller than the block count");
   HIPCHK(hipEventRecord(c->ev[0], st));
   OTCHK(build_lists(c, mac_params(c, c->p.mac, alim, cols), cols, st));
   HIPCHK(hipEventRecord(c->ev[1], st));

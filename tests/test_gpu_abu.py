@@ -123,3 +123,31 @@ def test_abu_columns_matches_oracle(fp64):
             assert np.array_equal(xb[keep], x0b[keep])
             e = np.abs(xb[ev] - xrb[ev]).max() / np.abs(xrb).max()
         assert e <= (1e-12 if fp64 else 1e-5), e
+
+
+def test_abu_after_regrid_to_more_blocks():
+    """The update's per-block buffers follow the grid: a first update on a
+    small grid, then a larger grid on the same context, where the update with
+    tolerance 0 must equal the plain solve bit for bit."""
+    small, big = workloads.c1_sphere(n=16), workloads.small_amr()
+    assert big.nb > small.nb
+    s = _solver(small)
+    n = 512 * small.nb
+    phi = torch.zeros(n, dtype=torch.float64, device="cuda")
+    acc = torch.zeros(3 * n, dtype=torch.float64, device="cuda")
+    st, upd = s.solve_abu(phi, acc, 0.0, fp64=True)
+    assert upd.all()
+    s.set_blocks(big.level, big.coord)
+    s.build(torch.from_numpy(big.rho.reshape(-1)).cuda())
+    n = 512 * big.nb
+    for fp64 in (True, False):
+        dt = torch.float64 if fp64 else torch.float32
+        phi = torch.empty(n, dtype=dt, device="cuda")
+        acc = torch.empty(3 * n, dtype=dt, device="cuda")
+        (s.solve64 if fp64 else s.solve)(phi, acc)
+        p_ref, a_ref = phi.cpu().numpy(), acc.cpu().numpy()
+        phi.zero_()
+        acc.zero_()
+        st, upd = s.solve_abu(phi, acc, 0.0, fp64=fp64)
+        assert upd.shape == (big.nb,) and upd.all()
+        assert np.array_equal(phi.cpu().numpy(), p_ref) and np.array_equal(acc.cpu().numpy(), a_ref)

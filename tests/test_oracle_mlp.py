@@ -91,3 +91,61 @@ def test_activation_special_values():
     q[256 + 4096] = 10.0            # b2[0]
     y = oracle.mlp_forward(q, np.array([[-1.0, 0, 0]]))[0, 0]
     assert abs(y - (10.0 - 7 / 27)) < 1e-14
+
+
+# ------------------------------------------------------------------ Adam
+def test_adam_first_step_closed_form():
+    """From zero moments the bias-corrected moments are g and g^2, so the
+    first step is -lr g / (|g| + eps) (eps = 1e-8 outside the root)."""
+    rng = np.random.default_rng(3)
+    g = rng.normal(size=1000) * np.logspace(-9, 1, 1000)
+    lr = 3e-3
+    p, m, v = oracle.adam_update(np.zeros(1000), g, np.zeros(1000), np.zeros(1000), lr, 1)
+    np.testing.assert_allclose(p, -lr * g / (np.abs(g) + 1e-8), rtol=1e-13)
+    np.testing.assert_allclose(m, 0.1 * g, rtol=1e-14)
+    np.testing.assert_allclose(v, 0.001 * g * g, rtol=1e-14)
+    # |g| = eps: exactly half a step
+    p, _, _ = oracle.adam_update([0.0], [1e-8], [0.0], [0.0], lr, 1)
+    np.testing.assert_allclose(p, [-lr / 2], rtol=1e-12)
+
+
+def test_adam_constant_gradient():
+    """With a constant gradient the corrected moments stay g and g^2 at every
+    step (m_t = (1 - beta1^t) g, v_t = (1 - beta2^t) g^2), so each step moves
+    by -lr g / (|g| + eps)."""
+    g = np.array([2.0, -0.5, 1e-3, -7.0])
+    p0 = np.array([0.1, 0.2, 0.3, 0.4])
+    p, m, v = p0.copy(), np.zeros(4), np.zeros(4)
+    lr = 1e-2
+    for step in range(1, 51):
+        p, m, v = oracle.adam_update(p, g, m, v, lr, step)
+        np.testing.assert_allclose(m, (1 - 0.9 ** step) * g, rtol=1e-13)
+        np.testing.assert_allclose(v, (1 - 0.999 ** step) * g * g, rtol=1e-12)
+    np.testing.assert_allclose(p - p0, -50 * lr * g / (np.abs(g) + 1e-8), rtol=1e-11)
+
+
+def test_adam_two_steps_by_hand():
+    """g = 1 then g = -1: m_2 = 0.9 * 0.1 - 0.1 = -0.01, v_2 = 0.999 * 0.001
+    + 0.001 = 0.001999; corrections 1 - 0.81 = 0.19 and 1 - 0.998001 =
+    0.001999, so the second step is +lr (0.01 / 0.19) / (1 + eps)."""
+    lr = 1e-3
+    p, m, v = oracle.adam_update([0.0], [1.0], [0.0], [0.0], lr, 1)
+    np.testing.assert_allclose(p, [-lr / (1 + 1e-8)], rtol=1e-14)
+    p2, m2, v2 = oracle.adam_update(p, [-1.0], m, v, lr, 2)
+    np.testing.assert_allclose(m2, [-0.01], rtol=1e-13)
+    np.testing.assert_allclose(v2, [0.001999], rtol=1e-13)
+    np.testing.assert_allclose(p2 - p, [lr * (0.01 / 0.19) / (1 + 1e-8)], rtol=1e-12)
+
+
+def test_training_step_is_gradient_then_adam():
+    rng = np.random.default_rng(8)
+    p = _params(8)
+    x = rng.uniform(-1, 1, (48, 3))
+    t = rng.normal(size=(48, oracle.MLP_NOUT))
+    m = rng.normal(size=p.size) * 1e-2
+    v = rng.uniform(0, 1e-3, p.size)
+    loss, p1, m1, v1 = oracle.mlp_adam(p, m, v, x, t, 2e-3, 7)
+    l0, g = oracle.mlp_grad(p, x, t)
+    pe, me, ve = oracle.adam_update(p, g, m, v, 2e-3, 7)
+    assert loss == l0
+    assert np.array_equal(p1, pe) and np.array_equal(m1, me) and np.array_equal(v1, ve)
