@@ -241,6 +241,21 @@ ot_status ot_mlp_set(ot_ctx *c, const float *params_host, const double *norm_hos
 ot_status ot_mlp_grad(ot_ctx *c, const float *params_dev, int64_t batch, const float *x_dev,
                       const float *t_dev, float *grad_dev, float *loss_host, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training or serving loops, harnesses that forbid
+ * hipMalloc): ot_mlp_grad without any allocation.  The per-workgroup partial
+ * gradients live in a fixed workspace of the library, a static device array
+ * of 4.5 MB (the partials of 1024 samples) that each GPU the library runs on
+ * holds until the process ends.  Arguments as ot_mlp_grad, except that the
+ * loss goes to a device scalar, loss_dev [1], and that the call only enqueues
+ * its kernels on stream and returns without synchronising.  batch: a
+ * positive multiple of 32, at most 1024 (OT_ERR_INVALID_ARG beyond; use
+ * ot_mlp_grad for larger batches).  Every call on one GPU shares that GPU's
+ * workspace: calls that overlap in time on one GPU (other streams, other
+ * host threads, other contexts) race and must be serialised by the caller. */
+ot_status ot_mlp_grad_noalloc(ot_ctx *c, const float *params_dev, int64_t batch, const float *x_dev,
+                              const float *t_dev, float *grad_dev, float *loss_dev, void *stream);
+
 /* The correction (phi_c, A_c) at offsets d_dev [n][3] (any sign; folded and
  * unfolded inside) into out_dev [n][4], FP64, by method: OT_EWALD_EXACT
  * (series), OT_EWALD_TABLE (FP64 table with the Taylor term) or OT_EWALD_MLP

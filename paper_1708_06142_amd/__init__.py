@@ -67,7 +67,7 @@ class MlpReport(C.Structure):
         return d
 
 
-MLP_NPARAM, MLP_NNORM = 8836, 11
+MLP_NPARAM, MLP_NNORM, MLP_NOUT = 8836, 11, 4
 EWALD = {"table": 0, "exact": 1, "mlp": 2}
 
 
@@ -107,6 +107,7 @@ def lib():
         L.ot_mlp_get.argtypes = [vp, vp, vp]
         L.ot_mlp_set.argtypes = [vp, vp, vp, C.c_int32, vp]
         L.ot_mlp_grad.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
+        L.ot_mlp_grad_noalloc.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
         L.ot_ewald_points.argtypes = [vp, C.c_int32, i64, vp, vp, vp]
         L.ot_column_bins.argtypes = [vp, i64, vp, vp, vp, vp]
         L.ot_last_error.restype = C.c_char_p
@@ -116,7 +117,8 @@ def lib():
                      "ot_solve_abu64",
                      "ot_ewald_prepare", "ot_export_topology", "ot_export_moments",
                      "ot_export_list", "ot_export_ewald_table", "ot_export_raytable", "ot_mlp_train",
-                     "ot_mlp_get", "ot_mlp_set", "ot_mlp_grad", "ot_ewald_points", "ot_column_bins"):
+                     "ot_mlp_get", "ot_mlp_set", "ot_mlp_grad", "ot_mlp_grad_noalloc", "ot_ewald_points",
+                     "ot_column_bins"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -294,6 +296,16 @@ class Solver:
         self._check(lib().ot_mlp_grad(self.h, _dev_ptr(params, f), int(x.shape[0]), _dev_ptr(x, f),
                                       _dev_ptr(t, f), _dev_ptr(grad, f), C.byref(loss), _stream(stream)))
         return loss.value
+
+    def mlp_grad_noalloc(self, params, x, t, grad, loss, stream=None):
+        """The same batch gradient with no allocation (fixed library workspace,
+        batch <= 1024); the loss goes to the device scalar loss [1].  Enqueues
+        only: synchronise the stream before reading the outputs."""
+        import torch
+        f = torch.float32
+        self._check(lib().ot_mlp_grad_noalloc(self.h, _dev_ptr(params, f), int(x.shape[0]), _dev_ptr(x, f),
+                                              _dev_ptr(t, f), _dev_ptr(grad, f), _dev_ptr(loss, f),
+                                              _stream(stream)))
 
     def ewald_points(self, method, d, out, stream=None):
         """Correction (phi_c, A_c) at device offsets d [n, 3] into out [n, 4]."""

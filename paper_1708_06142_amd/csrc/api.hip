@@ -1194,6 +1194,27 @@ ot_status ot_mlp_grad(ot_ctx *c, const float *params, int64_t batch, const float
   return OT_OK;
 }
 
+ot_status ot_mlp_grad_noalloc(ot_ctx *c, const float *params, int64_t batch, const float *x, const float *t,
+                              float *grad, float *loss, void *stream) {
+  if (!c) return OT_ERR_INVALID_ARG;
+  c->err.clear();
+  if (!params || !x || !t || !grad || !loss) return fail(c, OT_ERR_INVALID_ARG, "null pointer");
+  if (batch < 32 || batch % 32)
+    return fail(c, OT_ERR_INVALID_ARG, "batch must be a positive multiple of 32");
+  if (batch > ot::MLP_NOALLOC_MAX_BATCH)
+    return fail(c, OT_ERR_INVALID_ARG,
+                "batch " + std::to_string(batch) + " exceeds the fixed workspace of the allocation-free gradient (" +
+                    std::to_string(ot::MLP_NOALLOC_MAX_BATCH) + " samples); use ot_mlp_grad");
+  float *part = nullptr, *lossp = nullptr;
+  hipError_t e = ot::mlp_noalloc_workspace(c->p.device, &part, &lossp);
+  if (e != hipSuccess) return dev_fail(c, e, "fixed workspace of the allocation-free gradient");
+  HIPCHK(hipSetDevice(c->p.device));
+  // every partial and per-workgroup loss is written before it is read:
+  // nothing needs clearing between calls
+  HIPCHK(ot::launch_mlp_grad(params, batch, 0, batch, x, t, part, lossp, grad, loss, (hipStream_t)stream));
+  return OT_OK;
+}
+
 ot_status ot_ewald_points(ot_ctx *c, int32_t method, int64_t n, const double *d, double *out, void *stream) {
   if (!c) return OT_ERR_INVALID_ARG;
   c->err.clear();

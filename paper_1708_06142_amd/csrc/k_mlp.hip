@@ -26,6 +26,8 @@
 // FP16 high and low parts (the three products that matter fill the 16-deep
 // contraction), so the inputs lose no precision to FP16; the hidden
 // activations and the other weights are rounded to FP16.
+#include <mutex>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -607,6 +609,42 @@ constexpr unsigned reduce_blocks() { return (NP + 63) / 64 + 1; }  // + 1: the l
 }  // namespace
 
 int64_t mlp_partials(int64_t batch) { return batch / SB; }
+
+// ------------------------------------------------------------- fixed workspace
+// Workspace of the allocation-free gradient call: the per-workgroup partial
+// gradients of a batch of up to MLP_NOALLOC_MAX_BATCH samples and their
+// losses, in one array that each GPU holds from library load to process exit.  Host code reaches it only through the device address that
+// hipGetSymbolAddress returns for the current device (the array's name is a
+// host-side stand-in there).
+namespace {
+constexpr int64_t NOALLOC_PARTIALS = MLP_NOALLOC_MAX_BATCH / SB;
+constexpr int64_t NOALLOC_FLOATS = NOALLOC_PARTIALS * NP + NOALLOC_PARTIALS;
+static_assert((NOALLOC_PARTIALS * NP) % 64 == 0 && NOALLOC_PARTIALS % 64 == 0, "256-byte aligned regions");
+static __device__ __align__(256) float scratch[NOALLOC_FLOATS];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+float *scratch_addr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t mlp_noalloc_workspace(int device, float **partial, float **lossp) {
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_addr[device]) {
+    // once per device, with that device current
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return e;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    scratch_addr[device] = static_cast<float *>(p);
+  }
+  float *base = scratch_addr[device];
+  *partial = base;
+  *lossp = base + NOALLOC_PARTIALS * NP;
+  return hipSuccess;
+}
 
 hipError_t launch_mlp_grad(const float *P, int64_t n, int64_t s0, int64_t batch, const float *X, const float *T,
                            float *partial, float *lossp, float *grad, float *loss, hipStream_t st) {

@@ -170,6 +170,13 @@ hipError_t launch_mlp_prepare(int64_t n, const double *u, const double *ser, con
 // of x [n][3], t [n][4]: partial [mlp_partials(batch)][NP] and lossp
 // [mlp_partials(batch)] scratch, grad [NP], loss (FP32 sum) into *loss
 int64_t mlp_partials(int64_t batch);
+// largest batch of the allocation-free gradient (its fixed workspace holds
+// the partials of that many samples)
+constexpr int64_t MLP_NOALLOC_MAX_BATCH = 1024;
+// device addresses, for the given device (made current by the first call on
+// it), of the fixed workspace: partial [MLP_NOALLOC_MAX_BATCH / 8][NP] and
+// lossp [MLP_NOALLOC_MAX_BATCH / 8]
+hipError_t mlp_noalloc_workspace(int device, float **partial, float **lossp);
 hipError_t launch_mlp_grad(const float *P, int64_t n, int64_t s0, int64_t batch, const float *X, const float *T,
                            float *partial, float *lossp, float *grad, float *loss, hipStream_t st);
 // one Adam step (step >= 1, step size lr) on the same batch gradient
