@@ -1,20 +1,30 @@
 """Throughput of the tree-solver hot path on one MI355X.
 
-Workload: 128^3 cells (4,096 blocks of 8^3) of lognormal density
-exp(1.5 delta - 1.125), delta a seeded P(k) ~ k^-4 Gaussian random field;
-isolated boundaries; APE MAC with a_lim = 1e-3 * max|a| (max|a| from one BH
-theta = 0.5 FP64 walk before timing, as the paper derives a_lim from the
-initial acceleration field); with 48-direction column densities (HEALPix
-Nside 2), so a node is also required to pass BH at theta_pix = 0.5.  A step
-is one pass of the whole path: tree build (moments), interaction lists, per-cell
-potential + acceleration in FP32 with Kahan-compensated potential, and the
-per-cell column map + tau_avg.  Inputs are resident in HBM before timing.
+Headline workload: the large AMR configuration, the largest that runs on one
+GPU.  A 512^3-resolution lognormal density (sigma_ln 2, P(k) ~ k^-4, seed 5)
+on a 128^3 base grid refined up to two levels (29,709 blocks of 8^3, 15.2M
+cells); x, y periodic and z isolated (generalised Ewald, 64^3 table); APE MAC
+with a_lim = 1e-3 max|a| (max|a| from one BH theta = 0.5 FP64 walk before
+timing, as the paper derives the limit from the acceleration field) together
+with BH at theta_pix = 0.25 for 192-direction column densities (HEALPix
+Nside 4).  A step is one pass of the whole path: tree build (moments),
+interaction lists, FP32 gravity with Kahan-compensated potential and the
+Ewald correction from the learned surrogate (its network evaluated once per
+group of cells and list entry on FP16 matrix instructions, a first-order
+Taylor step to each cell), and the per-cell column maps + tau_avg.  The
+surrogate is trained on the device before timing.  Inputs are resident in
+HBM before timing.  Beside it, on the same lists: the FP64-table walk (the
+plain reference) and the FP32-table walk, the accuracy of the headline
+against the FP64-table walk over all cells and against the direct sum on
+sampled cells, and the other configurations as extra keys.
 
-Prints one JSON line, with the roofline of the dominant kernel and the oracle's CPU baseline.
+Prints one JSON line, with the roofline of the dominant kernel and the
+oracle's CPU baseline on a sample of the same workload.
 """
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -24,41 +34,49 @@ if ROOT not in sys.path:
 
 import numpy as np  # noqa: E402
 
-# Algorithmic FP32 work of one (cell, node) interaction of the isolated walk:
-# 3 sub (d), 5 (r^2: 3 mul + 2 add), rsqrt (1), m/r (1), m/r^3 (2 mul),
-# 3 FMA for the acceleration (6), Kahan update of the potential (4).
-FLOP_PAIR_ISO = 22
-PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X vector FP32 (256 CU x 2.4 GHz, packed)
+# Algorithmic work per (cell, node) pair, counted as in the scope's per-unit
+# figures: FP32 gravity 21 (3 sub for d, 5 for r^2, 1 m/r, 2 for m/r^3,
+# 3 FMA for a = 6, Kahan 4) + the rsqrt; the Ewald table look-up 46 (fold,
+# index and offset 12, Taylor of phi_c 6, of A_c 18, unfold and add 10); the
+# columns 30 (offset and r^2 8, weight base 2, three direction bins 12, map
+# updates of ~2.4 pixels 5, rsqrt 1 and the cut 2).
+FLOP_GRAV = 21
+FLOP_EWALD_TABLE = 46
+FLOP_COLS = 30
+FLOP_PAIR_ISO = FLOP_GRAV
+FLOP_PAIR_COLS = FLOP_GRAV + FLOP_COLS
+FLOP_PAIR_TABLE_COLS = FLOP_GRAV + FLOP_EWALD_TABLE + FLOP_COLS
+# Surrogate: per network evaluation 2 (3*64 + 64*64 + 64*64 + 64*10)
+# multiply-adds on FP16 matrix instructions; per (cell, node) pair the
+# gravity and the Taylor step from the group centre (phi_c 6, A_c 18).
+FLOP_MLP_EVAL = 2 * (3 * 64 + 64 * 64 + 64 * 64 + 64 * 10)
+FLOP_PAIR_MLP_TAYLOR = FLOP_GRAV + 24
+PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X vector FP32 (published, packed)
 PEAK_FP64_VALU = 78.6
-# Column walk per (cell, node) pair: the gravity above (its offset and r^2
-# serve the bins too) plus the column work: three direction bins, each a
-# look-up index (multiply-add and conversion) and one threshold test (product
-# and comparison) (12); the N_p weight base m / (Omega r^2) from the gravity's
-# m / r^2 (1); the map updates (2 per pixel hit, ~2.4 hits -> 5): 18.
-FLOP_PAIR_COLS = FLOP_PAIR_ISO + 18
-# Surrogate network per (cell, node) pair: 2 (3*64 + 64*64 + 64*64 + 64*4)
-# multiply-adds of the four layers, on FP16 matrix instructions.
-FLOP_PAIR_MLP = 2 * (3 * 64 + 64 * 64 + 64 * 64 + 64 * 4)
 PEAK_FP16_MFMA = 2500.0  # TFLOP/s, MI355X dense FP16 matrix
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=128, help="cells per axis")
-    ap.add_argument("--cpu-blocks", type=int, default=1024, help="oracle sample size (blocks, ~10 s on 16 threads)")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--side-steps", type=int, default=2,
+                    help="timed steps of the FP64- and FP32-table walks beside the headline")
+    ap.add_argument("--cpu-blocks", type=int, default=128, help="oracle sample size (blocks of the workload)")
+    ap.add_argument("--direct-cells", type=int, default=64,
+                    help="seeded cells (plus half as many of largest |a|) for the error against the direct sum")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB: one fill + one sum of that size before timing (HBM counter calibration)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--nside", type=int, default=2, help="HEALPix Nside of the column maps (0 = off)")
+    ap.add_argument("--no-side", action="store_true", help="skip the table walks beside the headline")
+    ap.add_argument("--no-direct", action="store_true", help="skip the error against the direct sum")
+    ap.add_argument("--no-c2", action="store_true",
+                    help="skip the 128^3 lognormal leg (isolated, 48-pixel columns)")
+    ap.add_argument("--c2-steps", type=int, default=10)
     ap.add_argument("--no-surrogate", action="store_true",
-                    help="skip the learned-Ewald leg (same field, 3P boundaries)")
+                    help="skip the learned-Ewald leg on the 128^3 field with 3P boundaries")
     ap.add_argument("--surrogate-steps", type=int, default=2)
-    ap.add_argument("--no-c5", action="store_true",
-                    help="skip the large AMR leg (15.2M cells, 2P1I, 192-pixel columns)")
     ap.add_argument("--no-mpe", action="store_true", help="skip the MPE MAC leg")
     ap.add_argument("--no-abu", action="store_true", help="skip the adaptive block update leg")
     ap.add_argument("--no-p1", action="store_true", help="skip the 1P2I filament leg")
@@ -158,21 +176,35 @@ def surrogate_leg(grid, rho, steps, nside=0):
         if "npix" in r and label != "table_fp64_cols":
             e["dnpix_maxnorm_vs_fp64"] = float(np.abs(r["npix"] - ref["npix"]).max() / np.abs(ref["npix"]).max())
         if label == "mlp_fp32":
-            ach = st.n_interactions * FLOP_PAIR_MLP / (r["ms_eval"] * 1e-3) / 1e12
-            e["roofline"] = {"bound": "mfma", "kernel": "k_eval_mlp<3P>", "achieved": ach,
-                             "peak": PEAK_FP16_MFMA, "unit": "TFLOP/s", "frac": ach / PEAK_FP16_MFMA,
-                             "flop_per_pair": FLOP_PAIR_MLP}
+            e["roofline"] = mlp_roofline(st)
+            e["n_mlp_evals"] = st.n_mlp_evals
         out[label] = e
     return out
 
 
-def c5_leg():
-    """Large AMR configuration: 512^3-resolution lognormal field (sigma_ln 2,
-    P(k) ~ k^-4, seed 5) on a 128^3 base grid refined up to two levels (15.2M
-    cells), x, y periodic and z isolated, APE a_lim = 1e-3 a_max with BH at
-    theta_pix = 0.25, 192-pixel columns.  The FP32 walk with the learned
-    correction beside the FP32 and FP64 table walks at the same MAC; one
-    untimed step, then one timed step each (a step is several seconds)."""
+def mlp_roofline(st):
+    """The surrogate gravity walk: matrix work of its network evaluations over
+    the kernel's time (its vector part: the per-pair Taylor step and the
+    activations)."""
+    ach = st.n_mlp_evals * FLOP_MLP_EVAL / (st.ms_gravity * 1e-3) / 1e12
+    valu = st.n_interactions * FLOP_PAIR_MLP_TAYLOR / (st.ms_gravity * 1e-3) / 1e12
+    return {"bound": "mfma", "kernel": "k_eval_mlp_taylor", "achieved": ach, "peak": PEAK_FP16_MFMA,
+            "unit": "TFLOP/s", "frac": ach / PEAK_FP16_MFMA, "flop_per_eval": FLOP_MLP_EVAL,
+            "n_evals": st.n_mlp_evals, "ms": st.ms_gravity, "valu_tflops_taylor": valu,
+            "valu_flop_per_pair": FLOP_PAIR_MLP_TAYLOR}
+
+
+def cols_roofline(st, flop_pair, fp64, kernel):
+    ms = st.ms_columns if st.ms_columns > 0 else st.ms_eval
+    fl = st.n_interactions * flop_pair / (ms * 1e-3) / 1e12
+    peak = PEAK_FP64_VALU if fp64 else PEAK_FP32_VALU
+    return {"bound": "alu", "kernel": kernel, "achieved": fl, "peak": peak, "unit": "TFLOP/s",
+            "frac": fl / peak, "flop_per_pair": flop_pair, "ms": ms}
+
+
+def c5_setup():
+    """The headline workload, its APE limit (BH FP64 pre-pass) and the
+    surrogate trained for its boundaries (untimed)."""
     import torch
     import paper_1708_06142_amd as ot
     import workloads
@@ -190,50 +222,111 @@ def c5_leg():
     t0 = time.perf_counter()
     rep = tr.mlp_train()
     train_s = time.perf_counter() - t0
-    params, norm = tr.mlp_get()
+    mlp = tr.mlp_get()
     tr.close()
-    res, out = {}, {"workload": f"AMR lognormal 512^3 effective (sigma_ln 2, seed 5), {g.nb} blocks, {n} cells, "
-                                f"2P1I, APE a_lim=1e-3 a_max ({a_lim:.4g}) + BH theta_pix 0.25, 192-pixel columns",
-                    "generate_s": gen_s, "training": {"seconds": train_s, "err_mlp": rep["err_mlp"],
-                                                     "ok": rep["ok"]}}
-    for label, mode, fp64 in (("mlp_fp32_cols", "mlp", False), ("table_fp32_cols", "table", False),
-                              ("table_fp64_cols", "table", True)):
-        s = ot.Solver.for_grid(g, a_lim=a_lim, ewald=mode, nside=4, **kw)
-        if mode == "mlp":
-            s.mlp_set(params, norm, accept=bool(rep["ok"]))
-        dt = torch.float64 if fp64 else torch.float32
-        outs = (torch.empty(n, dtype=dt, device="cuda"), torch.empty(3 * n, dtype=dt, device="cuda"),
-                torch.empty(n * 192, dtype=dt, device="cuda"), torch.empty(n, dtype=dt, device="cuda"))
-        ms, st, ms_eval, _, _ = timed_steps(s, rho, outs, fp64, 1, 1)
-        s.close()
-        res[label] = outs
-        e = {"value": n / (ms * 1e-3), "unit": "cells/s", "ms_per_step": ms, "ms_eval": ms_eval,
-             "ewald_used": ["table", "exact", "mlp"][st.ewald_used], "n_int": st.n_interactions,
-             "eval_wg_per_cu": st.eval_wg_per_cu}
-        if mode == "mlp":
-            ach = st.n_interactions * FLOP_PAIR_MLP / (ms_eval * 1e-3) / 1e12
-            e["roofline"] = {"bound": "mfma", "kernel": "k_eval_cols<float, newton> + k_eval_mlp<2P1I, add>",
-                             "achieved": ach, "peak": PEAK_FP16_MFMA, "unit": "TFLOP/s",
-                             "frac": ach / PEAK_FP16_MFMA, "flop_per_pair": FLOP_PAIR_MLP,
-                             "note": "matrix work over the time of both kernels"}
-        else:
-            fl = st.n_interactions * FLOP_PAIR_COLS / (ms_eval * 1e-3) / 1e12
-            peak = PEAK_FP64_VALU if fp64 else PEAK_FP32_VALU
-            e["roofline"] = {"bound": "alu", "kernel": f"k_eval_cols<{'double' if fp64 else 'float'}>",
-                             "achieved": fl, "peak": peak, "unit": "TFLOP/s", "frac": fl / peak,
-                             "flop_per_pair": FLOP_PAIR_COLS}
-        out[label] = e
-        torch.cuda.synchronize()
-    ref = res["table_fp64_cols"]
-    names = ("phi", "acc", "npix", "tau")
-    for label in ("mlp_fp32_cols", "table_fp32_cols"):
-        for nm, a, r in zip(names, res[label], ref):
-            out[label][f"d{nm}_maxnorm_vs_fp64_table"] = float((a.double() - r).abs().max() / r.abs().max()) \
-                if nm != "npix" else float(max((a[i:i + (1 << 28)].double() - r[i:i + (1 << 28)]).abs().max()
-                                               for i in range(0, r.numel(), 1 << 28)) / r.abs().max())
-    del res, ref
-    torch.cuda.empty_cache()
-    return out
+    info = {"generate_s": gen_s, "a_lim": a_lim,
+            "training": {"seconds": train_s, "ok": rep["ok"], "err_mlp": rep["err_mlp"],
+                         "err_table": rep["err_table"], "loss_first": rep["loss_first"],
+                         "loss_last": rep["loss_last"]}}
+    return g, rho, kw, a_lim, mlp, rep, info
+
+
+def c5_run(g, rho, kw, a_lim, mode, fp64, steps, warmup, mlp=None, accept=True):
+    import torch
+    import paper_1708_06142_amd as ot
+    s = ot.Solver.for_grid(g, a_lim=a_lim, ewald=mode, nside=4, **kw)
+    if mlp is not None:
+        s.mlp_set(*mlp, accept=accept)
+    n = g.ncells
+    dt = torch.float64 if fp64 else torch.float32
+    outs = (torch.empty(n, dtype=dt, device="cuda"), torch.empty(3 * n, dtype=dt, device="cuda"),
+            torch.empty(n * 192, dtype=dt, device="cuda"), torch.empty(n, dtype=dt, device="cuda"))
+    ms, st, ms_eval, ms_list, ms_build = timed_steps(s, rho, outs, fp64, steps, warmup)
+    s.close()
+    e = {"value": n / (ms * 1e-3), "unit": "cells/s", "ms_per_step": ms,
+         "phases_ms": {"build": ms_build, "lists": ms_list, "eval": ms_eval, "gravity": st.ms_gravity,
+                       "columns": st.ms_columns},
+         "ewald_used": ["table", "exact", "mlp"][st.ewald_used], "n_int": st.n_interactions,
+         "eval_wg_per_cu": st.eval_wg_per_cu}
+    return outs, st, e
+
+
+def maxnorm_diffs(outs, ref):
+    """Largest |difference| of phi, acc, npix, tau over all cells, each
+    normalised by the reference's largest |value| (|a| as a vector)."""
+    res = {}
+    for nm, a, r in zip(("phi", "acc", "npix", "tau"), outs, ref):
+        d, mx = 0.0, 0.0
+        for i in range(0, r.numel(), 1 << 28):
+            d = max(d, float((a[i:i + (1 << 28)].double() - r[i:i + (1 << 28)]).abs().max()))
+        mx = float(r.view(3, -1).pow(2).sum(0).sqrt().max()) if nm == "acc" else \
+            max(float(r[i:i + (1 << 28)].abs().max()) for i in range(0, r.numel(), 1 << 28))
+        res[f"d{nm}_maxnorm_vs_fp64_table"] = d / mx
+    return res
+
+
+def oracle_tree(g, kw, a_lim):
+    """The oracle's tree of the workload with the same MAC, 64^3 Ewald table
+    and 192-pixel column machinery (host FP64)."""
+    import oracle
+    t0 = time.perf_counter()
+    t = oracle.Tree(g, mac="ape", a_lim=a_lim, theta_pix=kw["theta_pix"], nside=4, ewald="table", ew_n=64)
+    return t, time.perf_counter() - t0
+
+
+def direct_errors(t, g, phi, acc, ncells, seed=17):
+    """e_a,max and e_Phi,max of the walk against the direct sum (the oracle's
+    FP64 sum over all other cells with the same Ewald table) on seeded cells
+    and the cells of largest |a|, normalised by the largest reference |a| and
+    |Phi| over those cells."""
+    import torch
+    n = g.ncells
+    amag = acc.view(3, -1).double().pow(2).sum(0)
+    top = torch.topk(amag, ncells // 2).indices.cpu().numpy()
+    rnd = np.random.default_rng(seed).choice(n, ncells, replace=False)
+    tg = np.unique(np.concatenate([rnd, top]))
+    t0 = time.perf_counter()
+    pd, ad = t.direct(tg)
+    sec = time.perf_counter() - t0
+    idx = torch.from_numpy(tg).cuda()
+    pw = phi[idx].double().cpu().numpy()
+    aw = acc.view(3, -1)[:, idx].double().cpu().numpy()
+    amax = np.sqrt((ad ** 2).sum(0)).max()
+    ea = np.sqrt(((aw - ad) ** 2).sum(0)) / amax
+    ep = np.abs(pw - pd) / np.abs(pd).max()
+    return {"e_a_max": float(ea.max()), "e_phi_max": float(ep.max()), "cells": int(tg.size),
+            "sample": f"{ncells} seeded cells and the {ncells // 2} of largest |a|",
+            "reference": "oracle direct sum over all other cells, FP64, same 64^3 Ewald table",
+            "seconds": sec}
+
+
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return None
+
+
+def cpu_baseline(t, tree_s, g, nblk, seed=7):
+    """The FP64 oracle's group walk with columns on a seeded sample of blocks
+    of the same workload, on the host cores."""
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    nblk = min(nblk, g.nb)
+    sel = np.sort(np.random.default_rng(seed).choice(g.nb, nblk, replace=False))
+    t0 = time.perf_counter()
+    t.walk_group(sel, columns=True)
+    tw = time.perf_counter() - t0
+    cells = 512 * nblk
+    sec = tw + tree_s * (nblk / g.nb)  # tree build is O(all cells): the sample's share
+    return {"value": cells / sec, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"{nblk} seeded blocks ({cells} cells) of the same workload: group walk with the same "
+                      f"MAC, FP64 64^3 Ewald table and 192-pixel columns; walk {tw:.2f} s + build share "
+                      f"{tree_s * nblk / g.nb:.3f} s (tree, Ewald and node-ray tables)"}
 
 
 def c3_leg(steps):
@@ -255,13 +348,13 @@ def c3_leg(steps):
         outs = (torch.empty(n, dtype=dt, device="cuda"), torch.empty(3 * n, dtype=dt, device="cuda"))
         ms, st, ms_eval, ms_list, _ = timed_steps(s, rho, outs, fp64, steps, 1)
         res[label] = outs
-        flop = st.n_interactions * (FLOP_PAIR_ISO + 46) / (ms_eval * 1e-3) / 1e12
+        flop = st.n_interactions * (FLOP_GRAV + FLOP_EWALD_TABLE) / (ms_eval * 1e-3) / 1e12
         peak = PEAK_FP64_VALU if fp64 else PEAK_FP32_VALU
         out[label] = {"value": n / (ms * 1e-3), "unit": "cells/s", "ms_per_step": ms, "ms_eval": ms_eval,
                       "ms_lists": ms_list, "n_int": st.n_interactions,
                       "roofline": {"bound": "alu", "kernel": f"k_eval{'64' if fp64 else '32'}<2P1I>",
                                    "achieved": flop, "peak": peak, "unit": "TFLOP/s", "frac": flop / peak,
-                                   "flop_per_pair": FLOP_PAIR_ISO + 46}}
+                                   "flop_per_pair": FLOP_GRAV + FLOP_EWALD_TABLE}}
     s.close()
     (p32, a32), (p64, a64) = res["table_fp32"], res["table_fp64"]
     out["table_fp32"]["dphi_rel_vs_fp64"] = float(((p32.double() - p64).abs() / p64.abs()).max())
@@ -294,13 +387,13 @@ def p1_leg(steps):
         outs = (torch.empty(n, dtype=dt, device="cuda"), torch.empty(3 * n, dtype=dt, device="cuda"))
         ms, st, ms_eval, ms_list, _ = timed_steps(s, rho, outs, fp64, steps, 1)
         res[label] = outs
-        flop = st.n_interactions * (FLOP_PAIR_ISO + 46) / (ms_eval * 1e-3) / 1e12
+        flop = st.n_interactions * (FLOP_GRAV + FLOP_EWALD_TABLE) / (ms_eval * 1e-3) / 1e12
         peak = PEAK_FP64_VALU if fp64 else PEAK_FP32_VALU
         out[label] = {"value": n / (ms * 1e-3), "unit": "cells/s", "ms_per_step": ms, "ms_eval": ms_eval,
                       "ms_lists": ms_list, "n_int": st.n_interactions,
                       "roofline": {"bound": "alu", "kernel": f"k_eval{'64' if fp64 else '32'}<1P2I>",
                                    "achieved": flop, "peak": peak, "unit": "TFLOP/s", "frac": flop / peak,
-                                   "flop_per_pair": FLOP_PAIR_ISO + 46}}
+                                   "flop_per_pair": FLOP_GRAV + FLOP_EWALD_TABLE}}
     s.close()
     (p32, a32), (p64, a64) = res["table_fp32"], res["table_fp64"]
     out["table_fp32"]["dphi_maxnorm_vs_fp64"] = float((p32.double() - p64).abs().max() / p64.abs().max())
@@ -408,27 +501,46 @@ def abu_leg(grid, a_lim, nsnap=6, seed=12, nside=0):
             "ms_full_mean": float(np.mean([r["ms_full"] for r in rows]))}
 
 
-def cpu_baseline(grid, a_lim, nblk, nside):
-    """The FP64 oracle's group walk on a seeded sample of blocks, host cores."""
-    import oracle
-    threads = os.cpu_count() or 1
-    os.environ.setdefault("OMP_NUM_THREADS", str(threads))
-    nblk = min(nblk, grid.nb)
-    sel = np.sort(np.random.default_rng(7).choice(grid.nb, nblk, replace=False))
-    t0 = time.perf_counter()
-    t = oracle.Tree(grid, mac="ape", a_lim=a_lim, nside=nside)
-    tb = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    t.walk_group(sel, columns=nside > 0)
-    tw = time.perf_counter() - t0
-    cells = 512 * nblk
-    # tree build is O(all cells): charge the sample its share
-    sec = tw + tb * (nblk / grid.nb)
-    return {"value": cells / sec, "unit": "cells/s", "cores": int(os.environ["OMP_NUM_THREADS"]),
-            "kind": "oracle",
-            "sample": f"{nblk} seeded blocks ({cells} cells) of the same workload, APE same a_lim, "
-                      f"Nside {nside} columns; walk {tw:.2f} s + build share {tb * nblk / grid.nb:.3f} s "
-                      "(tree build includes the node-ray table)"}
+def c2_leg(steps, warmup, nside=2):
+    """128^3 lognormal field (sigma_ln 1.5, seed 2), isolated, APE a_lim =
+    1e-3 a_max, 48-pixel columns: the FP32-Kahan column walk with its maps in
+    LDS, beside the FP64 walk; with its HBM counters when committed."""
+    import torch
+    import paper_1708_06142_amd as ot
+    import workloads
+    grid = workloads.c2_lognormal(128)
+    n = grid.ncells
+    rho = torch.from_numpy(grid.rho.reshape(-1).copy()).cuda()
+    npx = 12 * nside ** 2
+    s = ot.Solver.for_grid(grid, mac="ape", eps_lim=1e-3, theta=0.5)
+    s.build(rho)
+    phi = torch.empty(n, device="cuda", dtype=torch.float32)
+    acc = torch.empty(3 * n, device="cuda", dtype=torch.float32)
+    a_lim = s.solve(phi, acc).a_lim_used  # a_lim from the BH pre-pass (untimed)
+    s.close()
+    s = ot.Solver.for_grid(grid, mac="ape", a_lim=a_lim, theta=0.5, nside=nside)
+    outs = (phi, acc, torch.empty(n * npx, device="cuda"), torch.empty(n, device="cuda"))
+    ms, st, ms_eval, ms_list, ms_build = timed_steps(s, rho, outs, False, steps, warmup)
+    rl = cols_roofline(st, FLOP_PAIR_COLS, False, "k_eval_cols<float, isolated, maps in LDS>")
+    traffic = measured_traffic("profiles/eval_cols_lognormal128_nside2_hbm_traffic.txt",
+                               "paper_1708_06142_amd/csrc/k_columns.hip")
+    rl["traffic"] = traffic["bytes"] if traffic else None
+    rl["traffic_detail"] = traffic
+    out = {"workload": f"lognormal 128^3 (sigma_ln 1.5, P(k)~k^-4, seed 2), isolated, APE a_lim=1e-3 a_max "
+                       f"({a_lim:.4g}), {npx}-pixel columns, FP32-Kahan walk", "cells": n, "steps": steps,
+           "value": n / (ms * 1e-3), "unit": "cells/s", "ms_per_step": ms,
+           "phases_ms": {"build": ms_build, "lists": ms_list, "eval": ms_eval},
+           "eval_wg_per_cu": st.eval_wg_per_cu, "roofline": rl,
+           "interactions": {"n_int": st.n_interactions, "per_cell": st.n_interactions / n,
+                            "max_list": st.max_list, "n_opened": st.n_opened, "n_accepted": st.n_accepted}}
+    f64 = dict(device="cuda", dtype=torch.float64)
+    outs64 = (torch.empty(n, **f64), torch.empty(3 * n, **f64), torch.empty(n * npx, **f64), torch.empty(n, **f64))
+    ms64, st64, e64, _, _ = timed_steps(s, rho, outs64, True, max(2, steps // 2), 1)
+    out["fp64_walk"] = {"value": n / (ms64 * 1e-3), "ms_per_step": ms64, "ms_eval": e64,
+                        "roofline": cols_roofline(st64, FLOP_PAIR_COLS, True, "k_eval_cols<double, isolated>"),
+                        "eval_wg_per_cu": st64.eval_wg_per_cu}
+    s.close()
+    return out, grid, rho, a_lim
 
 
 def main():
@@ -437,84 +549,85 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
-    import paper_1708_06142_amd as ot
-    import workloads
 
     if args.calib_copy:
-        n = args.calib_copy * (1 << 20) // 4
-        src = torch.ones(n, device="cuda")      # fill kernel: writes exactly n * 4 bytes
-        total = src.sum()                        # reduction: reads exactly n * 4 bytes
+        nc = args.calib_copy * (1 << 20) // 4
+        src = torch.ones(nc, device="cuda")      # fill kernel: writes exactly nc * 4 bytes
+        total = src.sum()                         # reduction: reads exactly nc * 4 bytes
         torch.cuda.synchronize()
         del src, total
-    grid = workloads.c2_lognormal(args.n)
-    ncell = grid.ncells
-    rho = torch.from_numpy(grid.rho.reshape(-1).copy()).cuda()
-    npx = 12 * args.nside ** 2
-    s = ot.Solver.for_grid(grid, mac="ape", eps_lim=1e-3, theta=0.5)
-    s.build(rho)
-    phi = torch.empty(ncell, device="cuda", dtype=torch.float32)
-    acc = torch.empty(3 * ncell, device="cuda", dtype=torch.float32)
-    st0 = s.solve(phi, acc)  # derives a_lim from the BH pre-pass (untimed)
-    a_lim = st0.a_lim_used
-    s.close()
-    s = ot.Solver.for_grid(grid, mac="ape", a_lim=a_lim, theta=0.5, nside=args.nside)
-    outs = (phi, acc)
-    if args.nside:
-        outs = (phi, acc, torch.empty(ncell * npx, device="cuda"), torch.empty(ncell, device="cuda"))
-
-    ms, st, ms_eval, ms_list, ms_build = timed_steps(s, rho, outs, False, args.steps, args.warmup)
-    value = ncell / (ms * 1e-3)
-    fpair = FLOP_PAIR_COLS if args.nside else FLOP_PAIR_ISO
-    flops = st.n_interactions * fpair
-    achieved = flops / (ms_eval * 1e-3) / 1e12
-    traffic = measured_traffic("profiles/eval_cols_lognormal128_nside2_hbm_traffic.txt",
-                               "paper_1708_06142_amd/csrc/k_columns.hip") \
-        if args.nside == 2 and args.n == 128 else None
+    g, rho, kw, a_lim, mlp, rep, info = c5_setup()
+    n = g.ncells
+    outs, st, e = c5_run(g, rho, kw, a_lim, "mlp", False, args.steps, args.warmup, mlp, bool(rep["ok"]))
+    rl_grav = mlp_roofline(st) if st.ms_gravity > 0 else None
+    rl_cols = cols_roofline(st, FLOP_COLS, False, "k_eval_cols<float, 2P1I, columns only, maps in memory>")
+    dominant = rl_grav if rl_grav and st.ms_gravity >= st.ms_columns else rl_cols
+    traffic = None
+    if dominant is rl_cols:
+        traffic = measured_traffic("profiles/eval_cols_c5amr_nside4_nograv_hbm_traffic.txt",
+                                   "paper_1708_06142_amd/csrc/k_columns.hip")
+    else:
+        traffic = measured_traffic("profiles/eval_mlp_taylor_c5amr_hbm_traffic.txt",
+                                   "paper_1708_06142_amd/csrc/k_mlp.hip")
+    dominant = dict(dominant, traffic=traffic["bytes"] if traffic else None, traffic_detail=traffic)
     out = {
         "metric": "cells/s for potential+accel+N_pix column densities at <=1e-3 rel err",
-        "value": value, "unit": "cells/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "value": e["value"], "unit": "cells/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": e["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"lognormal {args.n}^3 (sigma_ln 1.5, P(k)~k^-4, seed 2), isolated, "
-                               f"APE a_lim=1e-3 a_max, {npx}-pixel columns, FP32-Kahan walk",
-                   "cells": ncell, "blocks": grid.nb, "a_lim": a_lim, "columns": npx},
-        "phases_ms": {"build": ms_build, "lists": ms_list, "eval": ms_eval},
-        "eval_wg_per_cu": st.eval_wg_per_cu,
-        "interactions": {"n_int": st.n_interactions, "per_cell": st.n_interactions / ncell,
-                         "max_list": st.max_list},
-        "roofline": {"bound": "alu", "kernel": "k_eval_cols<float> (isolated, columns)" if args.nside
-                     else "k_eval32 (isolated)", "achieved": achieved,
-                     "peak": PEAK_FP32_VALU, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
-                     "traffic": traffic["bytes"] if traffic else None,
-                     "traffic_detail": traffic, "flop_per_pair": fpair,
-                     "hbm_gbs_at_traffic": traffic["bytes"] / (ms_eval * 1e-3) / 1e9 if traffic else None},
+        "config": {"workload": f"AMR lognormal 512^3 effective (sigma_ln 2, P(k)~k^-4, seed 5), 128^3 base + 2 "
+                               f"levels, {g.nb} blocks, x,y periodic z isolated (unit box), APE a_lim=1e-3 a_max "
+                               f"+ BH theta_pix 0.25, 192-pixel columns, FP32-Kahan walk with the learned Ewald "
+                               f"correction (FP16 matrix instructions, Taylor step per cell group)",
+                   "cells": n, "blocks": g.nb, "a_lim": a_lim, "columns": 192, "ewald": e["ewald_used"]},
+        "phases_ms": e["phases_ms"], "eval_wg_per_cu": e["eval_wg_per_cu"],
+        "interactions": {"n_int": st.n_interactions, "per_cell": st.n_interactions / n, "max_list": st.max_list,
+                         "n_opened": st.n_opened, "n_accepted": st.n_accepted, "n_mlp_evals": st.n_mlp_evals,
+                         "list_hist": list(st.list_hist)},
+        "roofline": dominant,
+        "kernels": {"gravity": rl_grav, "columns": rl_cols},
+        "surrogate": info,
     }
-    if not args.no_fp64:
-        f64 = dict(device="cuda", dtype=torch.float64)
-        outs64 = (torch.empty(ncell, **f64), torch.empty(3 * ncell, **f64))
-        if args.nside:
-            outs64 += (torch.empty(ncell * npx, **f64), torch.empty(ncell, **f64))
-        ms64, st64, e64, _, _ = timed_steps(s, rho, outs64, True, max(2, args.steps // 2), 1)
-        a64 = st64.n_interactions * fpair / (e64 * 1e-3) / 1e12
-        out["fp64_walk"] = {"value": ncell / (ms64 * 1e-3), "ms_per_step": ms64, "ms_eval": e64,
-                            "achieved_tflops": a64, "frac_fp64_peak": a64 / PEAK_FP64_VALU,
-                            "eval_wg_per_cu": st64.eval_wg_per_cu}
-    if not args.no_surrogate:
-        out["surrogate"] = surrogate_leg(grid, rho, args.surrogate_steps, args.nside)
-    if not args.no_abu:
-        out["abu"] = abu_leg(grid, a_lim)
-        if args.nside:
-            out["abu_columns"] = abu_leg(grid, a_lim, nside=args.nside)
-    if not args.no_mpe:
-        out["mpe"] = mpe_leg(grid, rho, a_lim, max(2, args.steps // 2), args.nside)
+    if not args.no_side:
+        o64, st64, e64 = c5_run(g, rho, kw, a_lim, "table", True, args.side_steps, 1)
+        e64["roofline"] = cols_roofline(st64, FLOP_PAIR_TABLE_COLS, True, "k_eval_cols<double, 2P1I>")
+        out["fp64_table"] = e64
+        out["accuracy_vs_fp64_table"] = maxnorm_diffs(outs, o64)
+        o32, st32, e32 = c5_run(g, rho, kw, a_lim, "table", False, args.side_steps, 1)
+        e32["roofline"] = cols_roofline(st32, FLOP_PAIR_TABLE_COLS, False, "k_eval_cols<float, 2P1I>")
+        e32.update(maxnorm_diffs(o32, o64))
+        out["fp32_table"] = e32
+        del o32
+    else:
+        o64 = None
+    torch.cuda.synchronize()
+    if not args.no_direct or not args.no_cpu:
+        t, tree_s = oracle_tree(g, kw, a_lim)
+        if not args.no_direct:
+            out["accuracy_vs_direct"] = direct_errors(t, g, outs[0], outs[1], args.direct_cells)
+            if o64 is not None:
+                out["fp64_table"]["accuracy_vs_direct"] = direct_errors(t, g, o64[0], o64[1], args.direct_cells)
+        if not args.no_cpu:
+            out["cpu_baseline"] = cpu_baseline(t, tree_s, g, args.cpu_blocks)
+        del t
+    del outs, o64
+    torch.cuda.empty_cache()
+    if not args.no_c2 or not args.no_surrogate or not args.no_abu or not args.no_mpe:
+        c2, grid, rho2, a2 = c2_leg(args.c2_steps, 2)
+        if not args.no_c2:
+            out["c2"] = c2
+        if not args.no_surrogate:
+            out["surrogate_3p"] = surrogate_leg(grid, rho2, args.surrogate_steps, 2)
+        if not args.no_abu:
+            out["abu"] = abu_leg(grid, a2)
+            out["abu_columns"] = abu_leg(grid, a2, nside=2)
+        if not args.no_mpe:
+            out["mpe"] = mpe_leg(grid, rho2, a2, max(2, args.c2_steps // 2), 2)
+        del rho2
     if not args.no_c3:
-        out["c3"] = c3_leg(max(2, args.steps // 2))
+        out["c3"] = c3_leg(4)
     if not args.no_p1:
-        out["p1"] = p1_leg(max(2, args.steps // 2))
-    if not args.no_c5:
-        out["c5"] = c5_leg()
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(grid, a_lim, args.cpu_blocks, args.nside)
+        out["p1"] = p1_leg(4)
     print(json.dumps(out))
 
 

@@ -110,6 +110,16 @@ typedef struct {
                               also for isolated boundaries)                   */
   int32_t eval_wg_per_cu;  /* workgroups of the column walk resident per compute
                               unit (its occupancy); 0 without columns         */
+  int64_t n_opened;        /* nodes the MAC suite opened, summed over blocks  */
+  int64_t n_accepted;      /* list entries that are not cells: nodes the MAC
+                              suite accepted, summed over blocks (ot_solve,
+                              ot_solve64; 0 for the adaptive update)          */
+  int64_t list_hist[32];   /* blocks whose list length L has 2^k <= L < 2^(k+1) */
+  int64_t n_mlp_evals;     /* network evaluations of the surrogate walk
+                              (cell groups x list entries); 0 without it      */
+  double ms_gravity;       /* device time of the surrogate gravity walk       */
+  double ms_columns;       /* device time of the column walk (with the table,
+                              it computes the gravity too)                    */
 } ot_stats;
 
 void ot_params_default(ot_params *p);
@@ -182,30 +192,39 @@ ot_status ot_solve_abu64(ot_ctx *c, double *phi_dev, double *acc_dev, double *np
 ot_status ot_ewald_prepare(ot_ctx *c, void *stream);
 
 /* ---- learned Ewald surrogate --------------------------------------------
- * Not part of the paper: a network 3 -> 64 -> 64 -> 64 -> 4 (activation
- * z S(z), S the cubic smoothstep over [-3, 3]) maps the folded offset to
- * (phi_c, A_c) in place of the table of Sec. 2.2.4, which stays the fallback
- * and the judge of its error.  Trained on the device in FP32 (Adam, batch MSE
- * on standardised outputs) on FP64 series values at offsets drawn uniformly
- * from the folded domain; evaluated with FP16-input / FP32-accumulate matrix
- * instructions. */
+ * Not part of the paper: a network 3 -> 64 -> 64 -> 64 -> 10 (activation
+ * z S(z), S the cubic smoothstep over [-3, 3]) maps the folded offset to the
+ * ten channels of the Ewald table of Sec. 2.2.5 (phi_c, A_c and the six
+ * second derivatives of phi_c), which stays the fallback and the judge of
+ * its error.  Trained on the device in FP32 (Adam, batch MSE on standardised
+ * outputs) on FP64 series values at offsets drawn uniformly from the folded
+ * domain; evaluated with FP16-input / FP32-accumulate matrix instructions.
+ * The FP32 walk evaluates it once per (group of cells, list entry), a group
+ * being the largest block-tree node (4^3 or 2^3 cells, else a single cell)
+ * whose cells lie within half the table's smallest spacing of its centre on
+ * every axis, and takes the first-order Taylor step from the group's centre
+ * to each cell as the table look-up does (second approach of Sec. 2.2.5). */
 typedef struct {
   int64_t nsamples;  /* training offsets; multiple of 32                    [2097152] */
   int64_t nval;      /* held-out offsets for validation                     [100000]  */
-  int32_t epochs;    /* passes over the training offsets                    [100]     */
+  int32_t epochs;    /* passes over the training offsets                    [300]     */
   int32_t batch;     /* offsets per Adam step; multiple of 32, <= nsamples  [2048]    */
   double lr_max;     /* Adam step size, cosine decay from lr_max ...        [3e-3]    */
   double lr_min;     /* ... to lr_min over all steps                        [1e-5]    */
   uint64_t seed;     /* counter-based streams: init, training and held-out  [4]       */
-  double tol;        /* accepted when every channel's held-out error is at
-                        most tol (max |error| / max |exact value|)         [5e-3]    */
+  double tol;        /* accepted when the held-out error of phi_c and A_c is
+                        at most tol and that of the second derivatives at
+                        most 10 tol (max |error| / max |exact value|)     [5e-3]    */
 } ot_mlp_config;
 
 typedef struct {
   double loss_first;    /* mean batch loss of the first epoch (standardised)  */
   double loss_last;     /* mean batch loss of the last epoch                  */
-  double err_mlp[4];    /* held-out error per channel (phi_c, A_c x, y, z)    */
-  double err_table[4];  /* the same for this context's FP64 table             */
+  double err_mlp[10];   /* held-out error per channel (phi_c, A_c x, y, z, the
+                           second derivatives xx, yy, zz, xy, xz, yz): max
+                           |error| / max |exact value|                        */
+  double err_table[10]; /* the same for this context's FP64 table (Taylor term
+                           for phi_c and A_c, nearest point for the others)   */
   double ms_samples;    /* series evaluation of the training offsets          */
   double ms_train;      /* all Adam steps                                     */
   double ms_validate;   /* held-out evaluation                                */
@@ -213,8 +232,9 @@ typedef struct {
   int32_t pad_;
 } ot_mlp_report;
 
-#define OT_MLP_NPARAM 8836 /* W1[64][3] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[4][64] b4[4] */
-#define OT_MLP_NNORM 11    /* ext[3] (x = 2 u / ext - 1), mu[4], sig[4] (y = (out - mu) / sig) */
+#define OT_MLP_NPARAM 9226 /* W1[64][3] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[10][64] b4[10] */
+#define OT_MLP_NOUT 10     /* outputs: phi_c, A_c[3], second derivatives xx yy zz xy xz yz */
+#define OT_MLP_NNORM 23    /* ext[3] (x = 2 u / ext - 1), mu[10], sig[10] (y = (out - mu) / sig) */
 
 void ot_mlp_config_default(ot_mlp_config *cfg);
 
@@ -235,8 +255,8 @@ ot_status ot_mlp_set(ot_ctx *c, const float *params_host, const double *norm_hos
                      void *stream);
 
 /* Batch loss and gradient of the training objective at params_dev [NPARAM]
- * over x_dev [batch][3] (network inputs) and t_dev [batch][4] (standardised
- * targets): L = 1/(4 batch) sum (y - t)^2.  grad_dev [NPARAM]; *loss_host
+ * over x_dev [batch][3] (network inputs) and t_dev [batch][10] (standardised
+ * targets): L = 1/(10 batch) sum (y - t)^2.  grad_dev [NPARAM]; *loss_host
  * gets L.  batch a multiple of 32.  Device pointers are the caller's. */
 ot_status ot_mlp_grad(ot_ctx *c, const float *params_dev, int64_t batch, const float *x_dev,
                       const float *t_dev, float *grad_dev, float *loss_host, void *stream);
@@ -245,7 +265,7 @@ ot_status ot_mlp_grad(ot_ctx *c, const float *params_dev, int64_t batch, const f
  * capture, tight training or serving loops, harnesses that forbid
  * hipMalloc): ot_mlp_grad without any allocation.  The per-workgroup partial
  * gradients live in a fixed workspace of the library, a static device array
- * of 4.5 MB (the partials of 1024 samples) that each GPU the library runs on
+ * of 4.7 MB (the partials of 1024 samples) that each GPU the library runs on
  * holds until the process ends.  Arguments as ot_mlp_grad, except that the
  * loss goes to a device scalar, loss_dev [1], and that the call only enqueues
  * its kernels on stream and returns without synchronising.  batch: a
@@ -256,13 +276,15 @@ ot_status ot_mlp_grad(ot_ctx *c, const float *params_dev, int64_t batch, const f
 ot_status ot_mlp_grad_noalloc(ot_ctx *c, const float *params_dev, int64_t batch, const float *x_dev,
                               const float *t_dev, float *grad_dev, float *loss_dev, void *stream);
 
-/* The correction (phi_c, A_c) at offsets d_dev [n][3] (any sign; folded and
- * unfolded inside) into out_dev [n][4], FP64, by method: OT_EWALD_EXACT
- * (series), OT_EWALD_TABLE (FP64 table with the Taylor term) or OT_EWALD_MLP
- * (the installed surrogate, accepted or not; 3P and 2P1I only).  2P1I beyond
+/* The correction at offsets d_dev [n][3] (any sign; folded and unfolded
+ * inside) into out_dev [n][10], FP64: phi_c, A_c (3) and the second
+ * derivatives of phi_c (xx, yy, zz, xy, xz, yz), by method: OT_EWALD_EXACT
+ * (series), OT_EWALD_TABLE (FP64 table with the Taylor term for phi_c and
+ * A_c, the nearest grid point's second derivatives) or OT_EWALD_MLP (the
+ * installed surrogate, accepted or not; 3P and 2P1I only).  2P1I beyond
  * |dz| = 2 Lx and 1P2I beyond sqrt(dy^2 + dz^2) = 4 Lx (a line of mass 1/Lx:
  * phi = -(ln(alpha^2 rho^2) + gamma_E)/Lx): the analytic limit for every
- * method, minus 1/r and d/r^3. */
+ * method, minus the Newtonian 1/r and its derivatives. */
 ot_status ot_ewald_points(ot_ctx *c, int32_t method, int64_t n, const double *d_dev, double *out_dev,
                           void *stream);
 

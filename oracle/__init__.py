@@ -15,7 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
-SOURCES = ["octoracle.c", "ewald.c", "columns.c", "mlp.c"]
+SOURCES = ["octoracle.c", "ewald.c", "columns.c", "mlp.c", "mlpwalk.c"]
 
 ERRORS = {1: "bad level/coord", 2: "duplicate block", 3: "overlapping blocks",
           4: "hole in the block tiling", 5: "bad density", 6: "unsupported BCs"}
@@ -113,6 +113,9 @@ def _load(path):
     L.or_mlp_forward.argtypes = [vp, i64, vp, vp]
     L.or_mlp_grad.restype = C.c_double
     L.or_mlp_grad.argtypes = [vp, i64, vp, vp, vp]
+    L.or_walk_group_mlp.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
+    L.or_mlp_group_level.restype = C.c_int
+    L.or_mlp_group_level.argtypes = [vp, i64]
     L.or_adam_update.argtypes = [vp, vp, vp, vp, i64, C.c_double, i64]
     L.or_mlp_adam.restype = C.c_double
     L.or_mlp_adam.argtypes = [vp, vp, vp, i64, vp, vp, C.c_double, i64]
@@ -246,6 +249,30 @@ class Tree:
             return phi, acc, nint, npix, tau
         return phi, acc, nint
 
+    def walk_group_mlp(self, params, norm, blocks=None, columns=False):
+        """Group walk with the learned surrogate (FP64 network) in place of
+        the Ewald table: per (group of cells, listed node) the network's ten
+        channels at the group centre, a first-order Taylor step to each cell.
+        Returns as walk_group; the column maps (columns=True) are the plain
+        walk's."""
+        sel = np.arange(self.nb) if blocks is None else np.asarray(blocks)
+        sel = np.ascontiguousarray(sel, dtype=np.int64)
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        nm = np.ascontiguousarray(norm, dtype=np.float64)
+        if p.shape != (MLP_NPARAM,) or nm.shape != (3 + 2 * MLP_NOUT,):
+            raise ValueError("surrogate parameters or scaling of the wrong size")
+        nc = 512 * sel.size
+        phi, acc, nint = np.empty(nc), np.empty((3, nc)), np.empty(sel.size, np.int64)
+        lib().or_walk_group_mlp(self.h, _ptr(p), _ptr(nm), sel.size, _ptr(sel), _ptr(phi), _ptr(acc), _ptr(nint))
+        if columns:
+            _, _, _, npix, tau = self.walk_group(sel, columns=True)
+            return phi, acc, nint, npix, tau
+        return phi, acc, nint
+
+    def mlp_group_level(self, lb):
+        """Side 2^gl of the surrogate walk's cell groups in leaf block lb."""
+        return int(lib().or_mlp_group_level(self.h, int(lb)))
+
     def raymarch(self, target, nside, nside_f=16):
         """Reference column map of one cell: mean over the Nside_f pixel-centre
         rays in each coarse pixel of exact integrals of rho through the cells."""
@@ -355,14 +382,14 @@ def raytable(nside, il_ntheta=25, il_nphi=50, il_npsi=25, il_nr=50, il_nazi=100,
 
 
 # ---------------------------------------------------------------- MLP
-MLP_NPARAM, MLP_NOUT = 8836, 4  # 3 -> 64 -> 64 -> 64 -> 4
+MLP_NPARAM, MLP_NOUT = 9226, 10  # 3 -> 64 -> 64 -> 64 -> 10
 
 
 def mlp_forward(params, x):
-    """FP64 forward of the surrogate network: x [B, 3] -> y [B, 4]."""
+    """FP64 forward of the surrogate network: x [B, 3] -> y [B, 10]."""
     p = np.ascontiguousarray(params, dtype=np.float64)
     x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.float64)
-    y = np.empty((x.shape[0], 4))
+    y = np.empty((x.shape[0], MLP_NOUT))
     lib().or_mlp_forward(_ptr(p), x.shape[0], _ptr(x), _ptr(y))
     return y
 

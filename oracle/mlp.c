@@ -2,14 +2,16 @@
  * FP64 reference of the learned Ewald surrogate (a small MLP standing in for
  * the Ewald correction table).  TEST INFRASTRUCTURE ONLY (see octoracle.h).
  *
- * Network: 3 -> 64 -> 64 -> 64 -> 4, the gated activation f(z) = z S(z)
+ * Network: 3 -> 64 -> 64 -> 64 -> 10, the gated activation f(z) = z S(z)
  * after the three hidden layers, identity output.  S is the cubic smoothstep
  * rising from 0 at z = -3 to 1 at z = 3: S = t^2 (3 - 2t), t = clamp(z/6 + 1/2,
  * 0, 1).  f is continuously differentiable, close to z sigma(z) (same slope at
- * 0), and costs no exponential or reciprocal.  Parameter vector layout (8836 values):
- *   W1[64][3], b1[64], W2[64][64], b2[64], W3[64][64], b3[64], W4[4][64], b4[4]
+ * 0), and costs no exponential or reciprocal.  The ten outputs are the Ewald
+ * table's channels: phi_c, A_c (3) and the six second derivatives of phi_c.
+ * Parameter vector layout (9226 values):
+ *   W1[64][3], b1[64], W2[64][64], b2[64], W3[64][64], b3[64], W4[10][64], b4[10]
  * (row-major, W[out][in]).  Loss over a batch of B samples: mean squared error
- * over the 4 outputs, L = 1/(4B) sum_s sum_o (y_so - t_so)^2.
+ * over the 10 outputs, L = 1/(10B) sum_s sum_o (y_so - t_so)^2.
  * Plain loops, no blocking; the gradient is the textbook back-propagation.
  */
 #include <math.h>
@@ -17,7 +19,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { H = 64, NI = 3, NO = 4 };
+enum { H = 64, NI = 3, NO = 10 };
 enum { OW1 = 0, OB1 = OW1 + H * NI, OW2 = OB1 + H, OB2 = OW2 + H * H, OW3 = OB2 + H,
        OB3 = OW3 + H * H, OW4 = OB3 + H, OB4 = OW4 + NO * H, NPARAM = OB4 + NO };
 
@@ -66,7 +68,7 @@ static void forward1(const double *p, const double *x, double z1[H], double z2[H
   }
 }
 
-/* y[B][4] = f(x[B][3]) */
+/* y[B][10] = f(x[B][3]) */
 void or_mlp_forward(const double *p, int64_t B, const double *x, double *y) {
   for (int64_t s = 0; s < B; ++s) {
     double z1[H], z2[H], z3[H];

@@ -45,10 +45,14 @@ class Params(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("n_interactions", C.c_int64), ("max_list", C.c_int64), ("total_list", C.c_int64),
                 ("a_lim_used", C.c_double), ("ms_build", C.c_double), ("ms_list", C.c_double),
-                ("ms_eval", C.c_double), ("ewald_used", C.c_int32), ("eval_wg_per_cu", C.c_int32)]
+                ("ms_eval", C.c_double), ("ewald_used", C.c_int32), ("eval_wg_per_cu", C.c_int32),
+                ("n_opened", C.c_int64), ("n_accepted", C.c_int64), ("list_hist", C.c_int64 * 32),
+                ("n_mlp_evals", C.c_int64), ("ms_gravity", C.c_double), ("ms_columns", C.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+        d["list_hist"] = list(self.list_hist)
+        return d
 
 
 class MlpConfig(C.Structure):
@@ -57,8 +61,8 @@ class MlpConfig(C.Structure):
 
 
 class MlpReport(C.Structure):
-    _fields_ = [("loss_first", C.c_double), ("loss_last", C.c_double), ("err_mlp", C.c_double * 4),
-                ("err_table", C.c_double * 4), ("ms_samples", C.c_double), ("ms_train", C.c_double),
+    _fields_ = [("loss_first", C.c_double), ("loss_last", C.c_double), ("err_mlp", C.c_double * 10),
+                ("err_table", C.c_double * 10), ("ms_samples", C.c_double), ("ms_train", C.c_double),
                 ("ms_validate", C.c_double), ("ok", C.c_int32), ("pad_", C.c_int32)]
 
     def as_dict(self):
@@ -67,7 +71,7 @@ class MlpReport(C.Structure):
         return d
 
 
-MLP_NPARAM, MLP_NNORM, MLP_NOUT = 8836, 11, 4
+MLP_NPARAM, MLP_NNORM, MLP_NOUT = 9226, 23, 10
 EWALD = {"table": 0, "exact": 1, "mlp": 2}
 
 
@@ -285,7 +289,7 @@ class Solver:
         p = np.ascontiguousarray(params, dtype=np.float32)
         n = np.ascontiguousarray(norm, dtype=np.float64)
         if p.shape != (MLP_NPARAM,) or n.shape != (MLP_NNORM,):
-            raise ValueError("params [8836] and norm [11] expected")
+            raise ValueError(f"params [{MLP_NPARAM}] and norm [{MLP_NNORM}] expected")
         self._check(lib().ot_mlp_set(self.h, _np_ptr(p), _np_ptr(n), int(bool(accept)), _stream(stream)))
 
     def mlp_grad(self, params, x, t, grad, stream=None):
@@ -308,7 +312,8 @@ class Solver:
                                               _stream(stream)))
 
     def ewald_points(self, method, d, out, stream=None):
-        """Correction (phi_c, A_c) at device offsets d [n, 3] into out [n, 4]."""
+        """Correction (phi_c, A_c, second derivatives xx yy zz xy xz yz) at
+        device offsets d [n, 3] into out [n, 10]."""
         import torch
         f = torch.float64
         self._check(lib().ot_ewald_points(self.h, EWALD[method], int(d.shape[0]), _dev_ptr(d, f),

@@ -462,7 +462,8 @@ ot_status build_lists(ot_ctx *c, const ot::MacP &mp, bool sizes, hipStream_t st)
   OTCHK(dalloc(c, c->lscratch, (size_t)(grid * stride * 4)));
   OTCHK(dalloc(c, c->lcount, t.nb * sizeof(int32_t)));
   OTCHK(dalloc(c, c->loff, (t.nb + 1) * sizeof(int64_t)));
-  HIPCHK(ot::launch_lists(false, T, mp, (int)grid, P<int32_t>(c->lcount), nullptr, nullptr, nullptr,
+  OTCHK(dalloc(c, c->lnodes, 2 * t.nb * sizeof(int32_t)));
+  HIPCHK(ot::launch_lists(false, T, mp, (int)grid, P<int32_t>(c->lcount), P<int32_t>(c->lnodes), nullptr, nullptr, nullptr,
                           nullptr, P<int32_t>(c->lscratch), stride, capA, st));
   HIPCHK(ot::launch_scan(P<int32_t>(c->lcount), t.nb, P<int64_t>(c->loff), st));
   int64_t total = 0;
@@ -471,7 +472,7 @@ ot_status build_lists(ot_ctx *c, const ot::MacP &mp, bool sizes, hipStream_t st)
   OTCHK(dalloc(c, c->lrec, (size_t)total * sizeof(double4)));
   OTCHK(dalloc(c, c->lid, (size_t)total * sizeof(int32_t)));
   if (sizes) OTCHK(dalloc(c, c->lh, (size_t)total * sizeof(double)));
-  HIPCHK(ot::launch_lists(true, T, mp, (int)grid, P<int32_t>(c->lcount), P<int64_t>(c->loff),
+  HIPCHK(ot::launch_lists(true, T, mp, (int)grid, P<int32_t>(c->lcount), nullptr, P<int64_t>(c->loff),
                           P<double4>(c->lrec), P<int32_t>(c->lid), sizes ? P<double>(c->lh) : nullptr,
                           P<int32_t>(c->lscratch), stride, capA, st));
   c->list_cap = total;
@@ -542,13 +543,25 @@ struct Scoped {
 };
 
 ot::MlpNorm mlp_norm_of(const ot_ctx *c) {
+  using ot::mlpdef::NO;
   ot::MlpNorm N;
   for (int k = 0; k < 3; ++k) N.ext[k] = c->mlp_norm[k];
-  for (int o = 0; o < 4; ++o) {
+  for (int o = 0; o < NO; ++o) {
     N.mu[o] = c->mlp_norm[3 + o];
-    N.sig[o] = c->mlp_norm[7 + o];
+    N.sig[o] = c->mlp_norm[3 + NO + o];
   }
   return N;
+}
+
+// Largest Taylor offset per axis the surrogate walk allows (half the Ewald
+// table's smallest spacing) and the grid's largest cell size.
+double mlp_tmax(const ot_ctx *c) {
+  return 0.5 * std::min(c->ew_step[0], std::min(c->ew_step[1], c->ew_step[2]));
+}
+double cell_size_max(const ot_ctx *c) {
+  int lmin = c->topo.lmax;
+  for (int32_t l : c->topo.blev) lmin = std::min(lmin, (int)l);
+  return ot::size_at(c->p.root_size, lmin) / 8.0;
 }
 
 // pack the current parameters into the inference operands
@@ -558,15 +571,15 @@ ot_status mlp_pack(ot_ctx *c, hipStream_t st) {
   return OT_OK;
 }
 
-// correction at n device offsets by one method into out [n][4]
+// correction at n device offsets by one method into out [n][10]
 ot_status ewald_points(ot_ctx *c, int method, int64_t n, const double *d, double *out, hipStream_t st) {
   const ot::EwaldP E = ewald_desc(c);
   if (method == OT_EWALD_MLP) {
     if (!c->mlp_have) return fail(c, OT_ERR_STATE, "no surrogate installed");
     HIPCHK(ot::launch_mlp_points_eval(c->mlp_pk.ptr, E, n, d, out, st));
   } else {
-    HIPCHK(ot::launch_ewald_points4(method == OT_EWALD_EXACT ? 1 : 0, E, c->ew_alpha, c->ew_rcut2, c->ew_fcut2,
-                                    n, d, out, st));
+    HIPCHK(ot::launch_ewald_points10(method == OT_EWALD_EXACT ? 1 : 0, E, c->ew_alpha, c->ew_rcut2, c->ew_fcut2,
+                                     n, d, out, st));
   }
   return OT_OK;
 }
@@ -576,6 +589,27 @@ ot_status mlp_grad_scratch(ot_ctx *c, int64_t batch) {
   OTCHK(dalloc(c, c->mlp_part, (size_t)np * ot::mlpdef::NP * sizeof(float)));
   OTCHK(dalloc(c, c->mlp_lossp, (size_t)np * sizeof(float)));
   return OT_OK;
+}
+
+// list lengths, their histogram and the MAC suite's opened / accepted counts
+// (nodes: per block the opened nodes and the cells of its list, or empty)
+void list_stats(const ot_ctx *c, const std::vector<int32_t> &nodes, ot_stats *stats) {
+  memset(stats, 0, sizeof(*stats));
+  int64_t mx = 0;
+  for (int64_t b = 0; b < c->topo.nb; ++b) {
+    const int64_t len = c->off_host[b + 1] - c->off_host[b];
+    mx = std::max(mx, len);
+    int k = 0;
+    while (k < 31 && ((int64_t)2 << k) <= len) ++k;
+    ++stats->list_hist[k];
+    if (!nodes.empty()) {
+      stats->n_opened += nodes[2 * b];
+      stats->n_accepted += len - nodes[2 * b + 1];
+    }
+  }
+  stats->total_list = c->off_host[c->topo.nb];
+  stats->max_list = mx;
+  stats->n_interactions = 512 * (stats->total_list - c->topo.nb);
 }
 
 float elapsed(hipEvent_t a, hipEvent_t b) {
@@ -604,7 +638,7 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
   if (cols) OTCHK(raytable_prepare(c, st));
   double alim = 0.0;
   if (c->p.mac == OT_MAC_APE || c->p.mac == OT_MAC_MPE) OTCHK(ape_limit(c, st, &alim));
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 6; ++i)
     if (!c->ev[i]) HIPCHK(hipEventCreate(&c->ev[i]));
   HIPCHK(hipEventRecord(c->ev[0], st));
   OTCHK(build_lists(c, mac_params(c, c->p.mac, alim, cols), cols, st));
@@ -612,44 +646,52 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
   ot::DevTree T = dev_tree(c);
   ot::EwaldP E = ewald_desc(c);
   int wg_per_cu = 0;
+  if (use_mlp)
+    // gravity from the surrogate walk (the columns, if any, follow without gravity)
+    HIPCHK(ot::launch_eval_mlp(T, E, c->mlp_pk.ptr, P<int64_t>(c->loff), P<double4>(c->lrec), (float *)phi,
+                               (float *)acc, c->p.G, mlp_tmax(c), cell_size_max(c), st));
+  HIPCHK(hipEventRecord(c->ev[4], st));
   if (cols) {
     // maps in LDS when 128 or more cells' maps fit there, else in npix
     const ot::ColP C = col_params(c);
     HIPCHK(ot::launch_eval_cols(fp64, T, E, C, P<int64_t>(c->loff), P<double4>(c->lrec), P<int32_t>(c->lid),
                                 P<double>(c->lh), phi, acc, npix, tau, c->p.G,
                                 ot::cols_lds_cpw(C.npix, fp64, C.nthr), use_mlp, &wg_per_cu, st));
-    // with the surrogate: the column walk left the Newtonian part; add the correction
-    if (use_mlp)
-      HIPCHK(ot::launch_eval_mlp(T, E, c->mlp_pk.ptr, P<int64_t>(c->loff), P<double4>(c->lrec), (float *)phi,
-                                 (float *)acc, c->p.G, true, st));
   } else if (fp64)
     HIPCHK(ot::launch_eval64(T, E, P<int64_t>(c->loff), P<double4>(c->lrec), (double *)phi,
                              (double *)acc, c->p.G, st));
-  else if (use_mlp)
-    HIPCHK(ot::launch_eval_mlp(T, E, c->mlp_pk.ptr, P<int64_t>(c->loff), P<double4>(c->lrec), (float *)phi,
-                               (float *)acc, c->p.G, false, st));
-  else
+  else if (use_mlp) {
+  } else
     HIPCHK(ot::launch_eval32(T, E, P<int64_t>(c->loff), P<double4>(c->lrec), P<int32_t>(c->lid),
                              (float *)phi, (float *)acc, c->p.G, st));
   HIPCHK(hipEventRecord(c->ev[2], st));
   c->off_host.resize(c->topo.nb + 1);
   HIPCHK(hipMemcpyAsync(c->off_host.data(), c->loff.ptr, (c->topo.nb + 1) * sizeof(int64_t),
                         hipMemcpyDeviceToHost, st));
+  std::vector<int32_t> nodes;
+  if (stats) {
+    nodes.resize(2 * c->topo.nb);
+    HIPCHK(hipMemcpyAsync(nodes.data(), c->lnodes.ptr, nodes.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                          st));
+  }
   HIPCHK(hipStreamSynchronize(st));
   c->lists_valid = true;
   if (stats) {
-    memset(stats, 0, sizeof(*stats));
-    int64_t mx = 0;
-    for (int64_t b = 0; b < c->topo.nb; ++b) mx = std::max(mx, c->off_host[b + 1] - c->off_host[b]);
-    stats->total_list = c->off_host[c->topo.nb];
-    stats->max_list = mx;
-    stats->n_interactions = 512 * (stats->total_list - c->topo.nb);
+    list_stats(c, nodes, stats);
     stats->a_lim_used = alim;
     stats->ms_list = elapsed(c->ev[0], c->ev[1]);
     stats->ms_eval = elapsed(c->ev[1], c->ev[2]);
     stats->ms_build = c->ms_build;
     stats->ewald_used = use_mlp ? OT_EWALD_MLP : OT_EWALD_TABLE;
     stats->eval_wg_per_cu = wg_per_cu;
+    if (use_mlp) {
+      stats->ms_gravity = elapsed(c->ev[1], c->ev[4]);
+      const double tmax = mlp_tmax(c);
+      for (int64_t b = 0; b < c->topo.nb; ++b)
+        stats->n_mlp_evals += (int64_t)ot::mlp_groups(ot::size_at(c->p.root_size, c->topo.blev[b]) / 8.0, tmax) *
+                              (c->off_host[b + 1] - c->off_host[b]);
+    }
+    if (cols) stats->ms_columns = elapsed(c->ev[4], c->ev[2]);
   }
   return OT_OK;
 }
@@ -722,14 +764,10 @@ ot_status abu_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, void 
   HIPCHK(hipStreamSynchronize(st));  // also keeps blist alive until its copy is done
   c->lists_valid = true;
   if (stats) {
-    memset(stats, 0, sizeof(*stats));
-    int64_t mx = 0, tot_up = 0;
-    for (int64_t b = 0; b < nb; ++b) {
-      mx = std::max(mx, c->off_host[b + 1] - c->off_host[b]);
+    list_stats(c, std::vector<int32_t>(), stats);
+    int64_t tot_up = 0;
+    for (int64_t b = 0; b < nb; ++b)
       if (flag[b]) tot_up += c->off_host[b + 1] - c->off_host[b] - 1;
-    }
-    stats->total_list = c->off_host[nb];
-    stats->max_list = mx;
     stats->n_interactions = 512 * tot_up;  // pairs of the blocks evaluated in full
     stats->a_lim_used = alim;
     stats->ms_list = elapsed(c->ev[0], c->ev[1]);
@@ -997,7 +1035,7 @@ void ot_mlp_config_default(ot_mlp_config *cfg) {
   memset(cfg, 0, sizeof(*cfg));
   cfg->nsamples = 1 << 21;
   cfg->nval = 100000;
-  cfg->epochs = 100;
+  cfg->epochs = 300;
   cfg->batch = 2048;
   cfg->lr_max = 3e-3;
   cfg->lr_min = 1e-5;
@@ -1040,18 +1078,21 @@ ot_status ot_mlp_train(ot_ctx *c, const ot_mlp_config *cfg, ot_mlp_report *rep, 
   std::vector<double> hs((size_t)ns * 10);
   HIPCHK(hipMemcpyAsync(hs.data(), ser.b.ptr, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  // outputs standardised by mean and standard deviation; the second
+  // derivatives by 3 standard deviations, which weighs them 1/9 in the loss:
+  // the walk multiplies them by offsets within half a table spacing
   for (int k = 0; k < 3; ++k) c->mlp_norm[k] = c->ew_ext[k];
-  for (int o = 0; o < 4; ++o) {
+  for (int o = 0; o < NO; ++o) {
     double s1 = 0.0, s2 = 0.0;
     for (int64_t q = 0; q < ns; ++q) s1 += hs[10 * q + o];
     const double mu = s1 / (double)ns;
     for (int64_t q = 0; q < ns; ++q) s2 += (hs[10 * q + o] - mu) * (hs[10 * q + o] - mu);
     const double sig = std::sqrt(s2 / (double)ns);
     c->mlp_norm[3 + o] = mu;
-    c->mlp_norm[7 + o] = sig > 0 ? sig : 1.0;
+    c->mlp_norm[3 + NO + o] = (sig > 0 ? sig : 1.0) * (o < 4 ? 1.0 : 3.0);
   }
   OTCHK(dalloc(c, x.b, (size_t)n * 3 * sizeof(float)));
-  OTCHK(dalloc(c, t.b, (size_t)n * 4 * sizeof(float)));
+  OTCHK(dalloc(c, t.b, (size_t)n * NO * sizeof(float)));
   HIPCHK(ot::launch_mlp_prepare(n, u.p<double>(), ser.p<double>(), mlp_norm_of(c), x.p<float>(), t.p<float>(), st));
   HIPCHK(hipStreamSynchronize(st));
   release(c, ser.b);
@@ -1095,30 +1136,33 @@ ot_status ot_mlp_train(ot_ctx *c, const ot_mlp_config *cfg, ot_mlp_report *rep, 
   // held-out validation against the series, with the table alongside
   Scoped d(c), ex(c), ml(c), tb(c);
   OTCHK(dalloc(c, d.b, (size_t)nv * 3 * sizeof(double)));
-  OTCHK(dalloc(c, ex.b, (size_t)nv * 4 * sizeof(double)));
-  OTCHK(dalloc(c, ml.b, (size_t)nv * 4 * sizeof(double)));
-  OTCHK(dalloc(c, tb.b, (size_t)nv * 4 * sizeof(double)));
+  OTCHK(dalloc(c, ex.b, (size_t)nv * NO * sizeof(double)));
+  OTCHK(dalloc(c, ml.b, (size_t)nv * NO * sizeof(double)));
+  OTCHK(dalloc(c, tb.b, (size_t)nv * NO * sizeof(double)));
   HIPCHK(ot::launch_mlp_points(cfg->seed * 3 + 2, nv, c->ew_ext, d.p<double>(), st));
   OTCHK(ewald_points(c, OT_EWALD_EXACT, nv, d.p<double>(), ex.p<double>(), st));
   OTCHK(ewald_points(c, OT_EWALD_MLP, nv, d.p<double>(), ml.p<double>(), st));
   OTCHK(ewald_points(c, OT_EWALD_TABLE, nv, d.p<double>(), tb.p<double>(), st));
-  std::vector<double> hx((size_t)nv * 4), hm((size_t)nv * 4), ht((size_t)nv * 4);
+  std::vector<double> hx((size_t)nv * NO), hm((size_t)nv * NO), ht((size_t)nv * NO);
   HIPCHK(hipMemcpyAsync(hx.data(), ex.b.ptr, hx.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(hm.data(), ml.b.ptr, hm.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(ht.data(), tb.b.ptr, ht.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  double em[4], et[4];
+  // accepted when phi_c and A_c are within tol of their largest value and the
+  // second derivatives, which the walk multiplies by offsets within half a
+  // table spacing, within 10 tol
+  double em[NO], et[NO];
   bool ok = true;
-  for (int o = 0; o < 4; ++o) {
+  for (int o = 0; o < NO; ++o) {
     double mx = 0.0, dm = 0.0, dt = 0.0;
     for (int64_t q = 0; q < nv; ++q) {
-      mx = std::max(mx, std::fabs(hx[4 * q + o]));
-      dm = std::max(dm, std::fabs(hm[4 * q + o] - hx[4 * q + o]));
-      dt = std::max(dt, std::fabs(ht[4 * q + o] - hx[4 * q + o]));
+      mx = std::max(mx, std::fabs(hx[NO * q + o]));
+      dm = std::max(dm, std::fabs(hm[NO * q + o] - hx[NO * q + o]));
+      dt = std::max(dt, std::fabs(ht[NO * q + o] - hx[NO * q + o]));
     }
     em[o] = mx > 0 ? dm / mx : dm;
     et[o] = mx > 0 ? dt / mx : dt;
-    if (!(em[o] <= cfg->tol)) ok = false;
+    if (!(em[o] <= (o < 4 ? 1.0 : 10.0) * cfg->tol)) ok = false;
   }
   c->mlp_ok = ok;
   auto t3 = now();
@@ -1131,7 +1175,7 @@ ot_status ot_mlp_train(ot_ctx *c, const ot_mlp_config *cfg, ot_mlp_report *rep, 
     }
     rep->loss_first = a / (double)spe;
     rep->loss_last = b / (double)spe;
-    for (int o = 0; o < 4; ++o) {
+    for (int o = 0; o < NO; ++o) {
       rep->err_mlp[o] = em[o];
       rep->err_table[o] = et[o];
     }
@@ -1159,8 +1203,8 @@ ot_status ot_mlp_set(ot_ctx *c, const float *params, const double *norm, int32_t
   if (!params || !norm) return fail(c, OT_ERR_INVALID_ARG, "null parameters or scaling");
   if (c->bctype == ot::BC_1P2I)
     return fail(c, OT_ERR_UNSUPPORTED, "the learned surrogate covers 3P and 2P1I (1P2I uses the table)");
-  for (int k = 0; k < 11; ++k)
-    if (!std::isfinite(norm[k]) || ((k < 3 || k >= 7) && !(norm[k] > 0)))
+  for (int k = 0; k < OT_MLP_NNORM; ++k)
+    if (!std::isfinite(norm[k]) || ((k < 3 || k >= 3 + ot::mlpdef::NO) && !(norm[k] > 0)))
       return fail(c, OT_ERR_INVALID_ARG, "scaling must be finite with ext > 0 and sig > 0");
   for (int i = 0; i < ot::mlpdef::NP; ++i)
     if (!std::isfinite(params[i])) return fail(c, OT_ERR_INVALID_ARG, "non-finite parameter");
@@ -1251,12 +1295,12 @@ void ot_destroy(ot_ctx *c) {
   if (c->dev_bytes || c->ev[0]) (void)hipSetDevice(c->p.device);
   DevBuf *all[] = {&c->alev, &c->acoord, &c->achild0, &c->aleaf, &c->blev,   &c->bcoord,
                    &c->bamr, &c->amc,    &c->aS,      &c->btmc,  &c->cm,     &c->flag,
-                   &c->lcount, &c->loff, &c->lrec,    &c->lid,   &c->lscratch, &c->tab64,
+                   &c->lcount, &c->lnodes, &c->loff, &c->lrec,    &c->lid,   &c->lscratch, &c->tab64,
                    &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_rows, &c->rt_ent, &c->rt_rows8, &c->rt_quad64, &c->mpe_a, &c->mpe_b, &c->mpe_pnode, &c->mpe_pblock, &c->mpe_poff, &c->mpe_part, &c->abu_flag, &c->abu_blist, &c->rt_lut,
                    &c->rt_thr, &c->lh, &c->mlp_P, &c->mlp_pk, &c->mlp_part, &c->mlp_lossp,
                    &c->mlp_loss};
   for (DevBuf *b : all) release(c, *b);
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 6; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   delete c;
 }

@@ -58,7 +58,7 @@ struct ot_ctx {
   int64_t mpe_npairs = 0;
   ot::DevBuf abu_flag, abu_blist;  // adaptive block update: per-block flags, updated blocks
   // interaction lists
-  ot::DevBuf lcount, loff, lrec, lid, lscratch;
+  ot::DevBuf lcount, lnodes, loff, lrec, lid, lscratch;
   int64_t list_cap = 0;
   int64_t scratch_per_wg = 0;
   int list_grid = 0;
@@ -78,9 +78,9 @@ struct ot_ctx {
   bool rt_ready = false;
   int64_t rt_pairs = 0;
   // learned Ewald surrogate: FP32 parameters, packed FP16 operands, the
-  // input / output scaling (ext[3], mu[4], sig[4]) and gradient scratch
+  // input / output scaling (ext[3], mu[10], sig[10]) and gradient scratch
   ot::DevBuf mlp_P, mlp_pk, mlp_part, mlp_lossp, mlp_loss;
   bool mlp_have = false, mlp_ok = false;
-  double mlp_norm[11] = {0};
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  double mlp_norm[OT_MLP_NNORM] = {0};
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };

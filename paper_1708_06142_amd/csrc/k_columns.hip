@@ -316,14 +316,13 @@ __device__ inline bool grav64(const EwaldP &E, double dx, double dy, double dz, 
   return true;
 }
 
-// FP32 gravity of one pair (same forms as the FP32 walk); NEWTON: only the
-// minimum-image Newtonian part (the correction is added by another kernel)
+// FP32 gravity of one pair (same forms as the FP32 walk)
 // (inv = 1 / |d|, 0 for the target cell itself)
-template <int BC, bool NEWTON>
+template <int BC>
 __device__ inline void grav32(const EwaldP &E, float dx, float dy, float dz, float inv, float &phi, float &A0,
                               float &A1, float &A2) {
   const float inv3 = inv * inv * inv;
-  if (BC == 0 || NEWTON) {
+  if (BC == 0) {
     phi = inv;
     A0 = dx * inv3;
     A1 = dy * inv3;
@@ -370,7 +369,9 @@ __device__ inline void grav32(const EwaldP &E, float dx, float dy, float dz, flo
 // maps are accumulated in place in npix (each thread owns its cell's column,
 // a wave's 64 cells are adjacent): for maps too large for LDS at a useful
 // occupancy (192 pixels take 768 bytes per cell in FP32).
-template <typename Real, int BC, bool NEWTON, bool GMAP, bool LATTICE = !GMAP>
+// NOGRAV (FP32): the columns only; phi and acc are left to another kernel (the
+// walk with the learned correction).
+template <typename Real, int BC, bool NOGRAV, bool GMAP, bool LATTICE = !GMAP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_eval_cols(DevTree T, EwaldP E, ColP C, const int64_t *__restrict__ off,
                                                    const double4 *__restrict__ rec,
                                                    const int32_t *__restrict__ ids, const double *__restrict__ lh,
@@ -549,7 +550,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         // Kahan step with a zero only moves the compensation into the sum)
         const float m32 = q.valid && live ? r.m : 0.0f;
         const float mr = m32 * q.rd, mr2 = mr * q.rd;  // M / r, M / r^2
-        if (BC == 0 || NEWTON) {
+        if (NOGRAV) {
+        } else if (BC == 0) {
           const float mr3 = mr2 * q.rd;
           kahan(mr);
           tx = fmaf(q.dxf, mr3, (float)tx);
@@ -557,7 +559,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
           tz = fmaf(q.dzf, mr3, (float)tz);
         } else {
           float ph, A0, A1, A2;
-          grav32<BC, NEWTON>(E, q.dxf, q.dyf, q.dzf, q.valid ? q.rd : 0.0f, ph, A0, A1, A2);
+          grav32<BC>(E, q.dxf, q.dyf, q.dzf, q.valid ? q.rd : 0.0f, ph, A0, A1, A2);
           kahan(m32 * ph);
           tx += (Real)(m32 * A0);
           ty += (Real)(m32 * A1);
@@ -679,10 +681,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     az += tz;
   }
   const int64_t o = b * 512 + ci;
-  phi[o] = (Real)(negG * (sizeof(Real) == 8 ? s : (double)(ks - kc)));
-  acc[o] = (Real)(negG * (double)ax);
-  acc[ncell + o] = (Real)(negG * (double)ay);
-  acc[2 * ncell + o] = (Real)(negG * (double)az);
+  if (!NOGRAV) {
+    phi[o] = (Real)(negG * (sizeof(Real) == 8 ? s : (double)(ks - kc)));
+    acc[o] = (Real)(negG * (double)ax);
+    acc[ncell + o] = (Real)(negG * (double)ay);
+    acc[2 * ncell + o] = (Real)(negG * (double)az);
+  }
   double se = 0.0;
   for (int p = 0; p < C.npix; ++p) {
     const Real v = *reinterpret_cast<const Real *>(mcell + (p << lmap));
@@ -860,7 +864,7 @@ hipError_t launch_raytable_pack(const RayTableP &P, const int64_t *off, const ui
 
 hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const ColP &C, const int64_t *off,
                             const double4 *rec, const int32_t *ids, const double *lh, void *phi, void *acc,
-                            void *npix, void *tau, double G, int cpw, bool newton_only, int *wg_per_cu,
+                            void *npix, void *tau, double G, int cpw, bool no_gravity, int *wg_per_cu,
                             hipStream_t st, const int32_t *blist, int64_t nblist) {
   if (blist && nblist <= 0) return hipSuccess;
   const bool gmap = cpw == 0;
@@ -896,12 +900,12 @@ hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const 
       OT_LAUNCH2(R, B, N, false);   \
   } while (0)
   if (fp64) {
-    if (newton_only) return hipErrorInvalidValue;
+    if (no_gravity) return hipErrorInvalidValue;
     if (E.bctype == 0) OT_LAUNCH(double, 0, false);
     else if (E.bctype == 1) OT_LAUNCH(double, 1, false);
     else if (E.bctype == 2) OT_LAUNCH(double, 2, false);
     else OT_LAUNCH(double, 3, false);
-  } else if (newton_only) {
+  } else if (no_gravity) {
     if (E.bctype == 1) OT_LAUNCH(float, 1, true);
     else if (E.bctype == 2) OT_LAUNCH(float, 2, true);
     else return hipErrorInvalidValue;

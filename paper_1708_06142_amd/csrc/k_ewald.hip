@@ -305,58 +305,51 @@ __global__ __launch_bounds__(128) void k_ewald_points(EwaldP E, double alpha, in
   for (int k = 0; k < 10; ++k) out[10 * q + k] = o.v[k];
 }
 
-// correction (phi_c, signed A_c) at offsets d [n][3]: method 1 = FP64 series,
-// 0 = FP64 table with the Taylor term; 2P1I beyond |dz| = zfar: the limit
-__global__ __launch_bounds__(128) void k_ewald_points4(int method, EwaldP E, double alpha, int rcut2, int fcut2,
-                                                       int64_t n, const double *__restrict__ d,
-                                                       double *__restrict__ out) {
+// correction (phi_c, signed A_c, H_c) at offsets d [n][3] -> out [n][10]:
+// method 1 = FP64 series, 0 = FP64 table (Taylor term for phi_c and A_c, the
+// nearest grid point's second derivatives); beyond the far-field switch
+// (2P1I |dz| > zfar, 1P2I sqrt(dy^2 + dz^2) > zfar) the analytic limit minus
+// the Newtonian kernel, whose second derivatives are (3 d_j d_k - r^2
+// delta_jk) / r^5
+__global__ __launch_bounds__(128) void k_ewald_points10(int method, EwaldP E, double alpha, int rcut2, int fcut2,
+                                                        int64_t n, const double *__restrict__ d,
+                                                        double *__restrict__ out) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   const double dx = d[3 * q], dy = d[3 * q + 1], dz = d[3 * q + 2];
-  double *o = out + 4 * q;
-  if (E.bctype == 2 && fabs(dz) > E.zfar) {
-    // the limit replaces the whole interaction; report it minus 1/r
-    const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    o[0] = E.far_phi_a * fabs(dz) + E.far_phi_b - 1.0 / r;
-    const double r3 = r * r * r;
-    o[1] = -dx / r3;
-    o[2] = -dy / r3;
-    o[3] = (dz < 0 ? -E.far_az : E.far_az) - dz / r3;
-    return;
-  }
-  if (E.bctype == 3 && dy * dy + dz * dz > E.zfar * E.zfar) {
-    const double r = sqrt(dx * dx + dy * dy + dz * dz), rho2 = dy * dy + dz * dz;
-    o[0] = E.far_phi_a * log(rho2) + E.far_phi_b - 1.0 / r;
-    const double r3 = r * r * r;
-    o[1] = -dx / r3;
-    o[2] = E.far_az * dy / rho2 - dy / r3;
-    o[3] = E.far_az * dz / rho2 - dz / r3;
-    return;
-  }
+  double *o = out + 10 * q;
+  if (far_field10(E, dx, dy, dz, o)) return;
   const double u[3] = {fabs(dx), fabs(dy), fabs(dz)};
-  double phic, a[3];
+  double v[10];
   if (method == 1) {
     Acc10 s;
     ewald_point(E, alpha, rcut2, fcut2, u, s);
-    phic = s.v[0];
-    a[0] = s.v[1];
-    a[1] = s.v[2];
-    a[2] = s.v[3];
+    for (int k = 0; k < 10; ++k) v[k] = s.v[k];
   } else {
-    table_taylor64(E, u, phic, a);
+    table_taylor64(E, u, v[0], v + 1);
+    table_hessian64(E, u, v + 4);
   }
-  o[0] = phic;
-  o[1] = dx < 0 ? -a[0] : a[0];
-  o[2] = dy < 0 ? -a[1] : a[1];
-  o[3] = dz < 0 ? -a[2] : a[2];
+  // unfold: phi_c and the diagonal second derivatives are even in every
+  // component, A_c,k odd in d_k, H_jk (j != k) odd in d_j and in d_k
+  const double sx = dx < 0 ? -1.0 : 1.0, sy = dy < 0 ? -1.0 : 1.0, sz = dz < 0 ? -1.0 : 1.0;
+  o[0] = v[0];
+  o[1] = sx * v[1];
+  o[2] = sy * v[2];
+  o[3] = sz * v[3];
+  o[4] = v[4];
+  o[5] = v[5];
+  o[6] = v[6];
+  o[7] = sx * sy * v[7];
+  o[8] = sx * sz * v[8];
+  o[9] = sy * sz * v[9];
 }
 
 }  // namespace
 
-hipError_t launch_ewald_points4(int method, const EwaldP &E, double alpha, int rcut2, int fcut2, int64_t n,
-                                const double *d, double *out, hipStream_t st) {
-  hipLaunchKernelGGL(k_ewald_points4, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, method, E, alpha, rcut2,
-                     fcut2, n, d, out);
+hipError_t launch_ewald_points10(int method, const EwaldP &E, double alpha, int rcut2, int fcut2, int64_t n,
+                                 const double *d, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_ewald_points10, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, method, E, alpha,
+                     rcut2, fcut2, n, d, out);
   return hipGetLastError();
 }
 

@@ -109,9 +109,12 @@ __device__ inline void emit(const DevTree &T, const Target &tg, int64_t pos, int
   ids[pos] = id;
 }
 
+// Count pass (FILL false): count[b] = list length of block b and, with
+// nodes != null, nodes[2 b] = nodes the MAC suite opened, nodes[2 b + 1] =
+// cells in the list (children of opened +2 nodes).
 template <bool FILL>
 __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__restrict__ count,
-                                              const int64_t *__restrict__ off,
+                                              int32_t *__restrict__ nodes, const int64_t *__restrict__ off,
                                               double4 *__restrict__ rec, int32_t *__restrict__ ids,
                                               double *__restrict__ lh,
                                               int32_t *__restrict__ scratch, int64_t stride,
@@ -132,7 +135,7 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
     tg.ext = 3.5 * (sb / 8.0);
     tg.h = sb / 8.0;
     const int64_t base = FILL ? off[b] : 0;
-    int64_t nemit = 0;
+    int64_t nemit = 0, nopened = 0, ncells = 0;
 
     // ---- amr-tree levels
     int32_t *cur = fa, *nxt = fb;
@@ -169,6 +172,7 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
         nemit += sc.tot[0];
         nnext += 8 * sc.tot[1];
         nolb += sc.tot[2];
+        nopened += sc.tot[1] + sc.tot[2];
       }
       __syncthreads();
       int32_t *t = cur;
@@ -204,6 +208,7 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
       if (op) op1[nop1 + sc.pre[1]] = lb * 8 + o1;
       nemit += sc.tot[0];
       nop1 += sc.tot[1];
+      nopened += sc.tot[1];
     }
     __syncthreads();
 
@@ -252,8 +257,16 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
         }
       }
       nemit += sc.tot[0] + 8 * sc.tot[1];
+      nopened += sc.tot[1];
+      ncells += 8 * sc.tot[1];
     }
-    if (!FILL && tid == 0) count[b] = (int32_t)nemit;
+    if (!FILL && tid == 0) {
+      count[b] = (int32_t)nemit;
+      if (nodes) {
+        nodes[2 * b] = (int32_t)nopened;
+        nodes[2 * b + 1] = (int32_t)ncells;
+      }
+    }
     __syncthreads();
   }
 }
@@ -287,14 +300,14 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ count
 
 }  // namespace
 
-hipError_t launch_lists(bool fill, const DevTree &T, const MacP &P, int grid, int32_t *count,
+hipError_t launch_lists(bool fill, const DevTree &T, const MacP &P, int grid, int32_t *count, int32_t *nodes,
                         const int64_t *off, double4 *rec, int32_t *ids, double *lh, int32_t *scratch,
                         int64_t stride, int64_t capA, hipStream_t st) {
   if (fill)
-    hipLaunchKernelGGL(k_lists<true>, dim3(grid), dim3(WG), 0, st, T, P, count, off, rec, ids, lh,
+    hipLaunchKernelGGL(k_lists<true>, dim3(grid), dim3(WG), 0, st, T, P, count, nodes, off, rec, ids, lh,
                        scratch, stride, capA);
   else
-    hipLaunchKernelGGL(k_lists<false>, dim3(grid), dim3(WG), 0, st, T, P, count, off, rec, ids, lh,
+    hipLaunchKernelGGL(k_lists<false>, dim3(grid), dim3(WG), 0, st, T, P, count, nodes, off, rec, ids, lh,
                        scratch, stride, capA);
   return hipGetLastError();
 }

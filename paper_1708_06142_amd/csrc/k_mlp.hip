@@ -2,16 +2,17 @@
 // stands in for the look-up table of Sec. 2.2.4, which stays the fallback and
 // the judge of its error.
 //
-// Network 3 -> 64 -> 64 -> 64 -> 4 with the activation f(z) = z S(z), S the
+// Network 3 -> 64 -> 64 -> 64 -> 10 with the activation f(z) = z S(z), S the
 // cubic smoothstep from 0 at z = -3 to 1 at z = 3, after each hidden layer.
 // Input: the folded offset u (all components >= 0) scaled to [-1, 1] per
-// axis; output: (phi_c, A_c) standardised per channel.  Parameters (8836 FP32):
-//   W1[64][3] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[4][64] b4[4].
+// axis; output: the table's ten channels (phi_c, A_c and the six second
+// derivatives of phi_c) standardised per channel.  Parameters (9226 FP32):
+//   W1[64][3] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[10][64] b4[10].
 //
 // Training (FP32): one workgroup runs forward and backward for 8 samples with
 // all activations in LDS and writes its partial gradient; a second kernel sums
 // the partials in a fixed order (deterministic) and applies Adam.
-// Loss: mean squared error over the 4 outputs of the batch.
+// Loss: mean squared error over the 10 outputs of the batch.
 //
 // Inference: every layer runs on the matrix cores in the transposed form
 // h_next = W h, with the weights as the A operand and the 32 pairs of a batch
@@ -29,6 +30,7 @@
 #include <mutex>
 
 #include "common.hpp"
+#include "ewald_lookup.hpp"
 #include "kernels.hpp"
 
 namespace ot {
@@ -82,13 +84,13 @@ __global__ void k_mlp_points(uint64_t seed, int64_t n, double e0, double e1, dou
   u[3 * q + 2] = e2 * uniform01(seed, 3 * q + 2);
 }
 
-// network inputs x = 2 u / ext - 1 and standardised targets (phi_c, A_c)
+// network inputs x = 2 u / ext - 1 and the ten standardised targets
 __global__ void k_mlp_prepare(int64_t n, const double *__restrict__ u, const double *__restrict__ ser,
                               MlpNorm N, float *__restrict__ x, float *__restrict__ t) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   for (int k = 0; k < 3; ++k) x[3 * q + k] = (float)(2.0 * u[3 * q + k] / N.ext[k] - 1.0);
-  for (int o = 0; o < 4; ++o) t[4 * q + o] = (float)((ser[10 * q + o] - N.mu[o]) / N.sig[o]);
+  for (int o = 0; o < NO; ++o) t[NO * q + o] = (float)((ser[10 * q + o] - N.mu[o]) / N.sig[o]);
 }
 
 // ------------------------------------------------------------- training
@@ -157,10 +159,12 @@ __global__ __launch_bounds__(256) void k_mlp_fwdbwd(const float *__restrict__ P,
   __syncthreads();
   float *G = partial + (int64_t)blockIdx.x * NP;
   {  // layer 4: dW4, db4
-    const int oo = t / H, i = t % H;
-    float g = 0.0f;
-    for (int s = 0; s < SB; ++s) g += L.dy[s][oo] * L.h3[s][i];
-    G[OW4 + oo * H + i] = g;
+    for (int q = t; q < NO * H; q += 256) {
+      const int oo = q / H, i = q % H;
+      float g = 0.0f;
+      for (int s = 0; s < SB; ++s) g += L.dy[s][oo] * L.h3[s][i];
+      G[OW4 + oo * H + i] = g;
+    }
     if (t < NO) {
       float gb = 0.0f;
       for (int s = 0; s < SB; ++s) gb += L.dy[s][t];
@@ -281,6 +285,18 @@ __device__ inline int perm_k(int c, int g, int j) {
   return 32 * (c >> 1) + 16 * (c & 1) + 8 * (j >> 2) + 4 * g + (j & 3);
 }
 
+// Channel of row r of the last layer's 32-row output tile, or -1 (unused).
+// Lane group g of the product holds the rows 8 (k / 4) + 4 g + k % 4 in its
+// value k; rows 0-7 carry channels 0-3, rows 8-15 channels 4-7 and rows
+// 16, 17 and 20, 21 channels 8, 9, so both lane groups hold all ten channels
+// of their pair in values 0-9.
+__host__ __device__ inline int out_channel(int r) {
+  if (r < 8) return r & 3;
+  if (r < 16) return 4 + (r & 3);
+  if (r < 24 && (r & 3) < 2) return 8 + (r & 3);
+  return -1;
+}
+
 __device__ inline void split16(double v, _Float16 &hi, _Float16 &lo) {
   hi = (_Float16)v;
   lo = (_Float16)(v - (double)hi);
@@ -315,12 +331,13 @@ __global__ void k_mlp_pack(const float *__restrict__ P, MlpNorm N, f16x8 *__rest
     const int R = op < PK_L3 ? op - PK_L2B : op - PK_L3B;
     const int B = op < PK_L3 ? OB2 : OB3;
     if (g == 0) split16(P[B + 32 * R + m], a[0], a[1]);
-  } else if (op < PK_L4B) {  // W4 scaled by sig, rows repeated every 4
-    const int c = op - PK_L4, o = m & 3;
-    for (int j = 0; j < 8; ++j) a[j] = (_Float16)((double)P[OW4 + H * o + perm_k(c, g, j)] * N.sig[o]);
+  } else if (op < PK_L4B) {  // W4 scaled by sig, output row m -> channel out_channel(m)
+    const int c = op - PK_L4, o = out_channel(m);
+    if (o >= 0)
+      for (int j = 0; j < 8; ++j) a[j] = (_Float16)((double)P[OW4 + H * o + perm_k(c, g, j)] * N.sig[o]);
   } else {  // b4 sig + mu
-    const int o = m & 3;
-    if (g == 0) split16((double)P[OB4 + o] * N.sig[o] + N.mu[o], a[0], a[1]);
+    const int o = out_channel(m);
+    if (g == 0 && o >= 0) split16((double)P[OB4 + o] * N.sig[o] + N.mu[o], a[0], a[1]);
   }
   f16x8 v;
   for (int j = 0; j < 8; ++j) v[j] = a[j];
@@ -386,9 +403,10 @@ __device__ inline void act_tile(const f32x16 &d, f16x8 &c0, f16x8 &c1) {
   }
 }
 
-// (phi_c, A_c) at the folded offsets of the 32 pairs of this wave: lane l
-// passes the B operand of pair l % 32 and receives its 4 outputs.
-__device__ inline void forward(const Ops &W0, const f16x8 &xin, const f16x8 &one, float y[4]) {
+// The ten channels at the folded offsets of the 32 pairs of this wave: lane l
+// passes the B operand of pair l % 32 and receives its outputs (both lane
+// groups receive all ten).
+__device__ inline void forward(const Ops &W0, const f16x8 &xin, const f16x8 &one, float y[NO]) {
   // An empty asm makes the lane slot opaque, so the operand reads are not
   // hoisted out of the walk's loops into registers (which would leave the
   // products in accumulation registers and cut the occupancy).
@@ -418,15 +436,16 @@ __device__ inline void forward(const Ops &W0, const f16x8 &xin, const f16x8 &one
   f32x16 o = mma(W[PK_L4B], one, z);
 #pragma unroll
   for (int c = 0; c < 4; ++c) o = mma(W[PK_L4 + c], h[c], o);
-  for (int k = 0; k < 4; ++k) y[k] = o[k];
+  for (int k = 0; k < NO; ++k) y[k] = o[k];
 }
 
 }  // namespace mlpinf
 
 namespace {
 
-// correction (phi_c, signed A_c) at offsets d [n][3]; 2P1I beyond zfar: the
-// limit minus the Newtonian part, as in the walk.  One wave per 32 offsets.
+// The ten channels (phi_c, signed A_c, H_c) at offsets d [n][3] into out
+// [n][10]; beyond the far-field switch the analytic limit as for the other
+// methods.  One wave per 32 offsets.
 __global__ __launch_bounds__(256) void k_mlp_points_eval(const void *__restrict__ pk, EwaldP E, int64_t n,
                                                          const double *__restrict__ d, double *__restrict__ out) {
   __shared__ f16x8 wl[64 * NPK];
@@ -440,129 +459,188 @@ __global__ __launch_bounds__(256) void k_mlp_points_eval(const void *__restrict_
     dy = d[3 * q + 1];
     dz = d[3 * q + 2];
   }
-  float y[4];
+  float y[NO];
   mlpinf::forward(W, mlpinf::input((float)fabs(dx), (float)fabs(dy), (float)fabs(dz)), one, y);
   if (q >= n || l >= 32) return;
-  double *o = out + 4 * q;
-  if (E.bctype == 2 && fabs(dz) > E.zfar) {
-    const double r = sqrt(dx * dx + dy * dy + dz * dz), r3 = r * r * r;
-    o[0] = E.far_phi_a * fabs(dz) + E.far_phi_b - 1.0 / r;
-    o[1] = -dx / r3;
-    o[2] = -dy / r3;
-    o[3] = (dz < 0 ? -E.far_az : E.far_az) - dz / r3;
-    return;
-  }
+  double *o = out + NO * q;
+  if (far_field10(E, dx, dy, dz, o)) return;
+  const double sx = dx < 0 ? -1.0 : 1.0, sy = dy < 0 ? -1.0 : 1.0, sz = dz < 0 ? -1.0 : 1.0;
   o[0] = y[0];
-  o[1] = dx < 0 ? -y[1] : y[1];
-  o[2] = dy < 0 ? -y[2] : y[2];
-  o[3] = dz < 0 ? -y[3] : y[3];
+  o[1] = sx * y[1];
+  o[2] = sy * y[2];
+  o[3] = sz * y[3];
+  o[4] = y[4];
+  o[5] = y[5];
+  o[6] = y[6];
+  o[7] = sx * sy * y[7];
+  o[8] = sx * sz * y[8];
+  o[9] = sy * sz * y[9];
 }
 
 // ------------------------------------------------------------- walk
-// FP32 evaluation of the block lists with the correction from the surrogate
-// (BC 1 = 3P, 2 = 2P1I).  Layout as the table walk: one workgroup of 256
-// threads per leaf block, thread t owns cells t and t + 256, the list streams
-// through LDS in tiles of offsets from the block centre.  Wave w owns the 128
-// cells {64 w + l, 256 + 64 w + l}; for every list entry it runs 4 batches of
-// 32 pairs through the network: batch (sl, gg) covers cells 64 w + 32 gg + m +
-// 256 sl (m = l % 32, both lane groups hold halves of each pair's operand),
-// and lane group g keeps the batches gg = g, in slot sl.  Phi is
-// Kahan-compensated.
-constexpr int WG = 256;
+// FP32 gravity walk with the surrogate's correction (BC 1 = 3P, 2 = 2P1I).
+// One workgroup of 512 threads per leaf block, thread t owns cell t, the
+// block's list streams through LDS once.  The network is evaluated once per
+// (group of cells, list entry): the group is a node of the block-tree of
+// side 2^gl cells (gl = 2: the 8 +1 nodes, 1: the 64 +2 nodes, 0: single
+// cells), the largest whose cells lie within the Ewald table's half-spacing of
+// its centre on every axis, so that the Taylor step below spans no more than
+// the table's own (Sec. 2.2.5, second approach).  At the group centre c_g the
+// offset d0 = c_g - r_node (minimum image) gives the network's ten channels at
+// |d0|, unfolded to the signs of d0; a cell at delta = x - c_g then sums, with
+// d = d0 + delta (the image of its group),
+//   Phi -= G M (1/|d| + phi_c(d0) - A_c(d0) . delta)
+//   a   -= G M (d/|d|^3 + A_c(d0) - H_c(d0) delta),
+// the Newtonian part and the correction referring to the same image.  In
+// 2P1I a group whose |d0_z| exceeds the far-field switch takes the analytic
+// limit at every cell's d instead.  Per chunk of list entries each wave runs
+// one or two batches of 32 (group, entry) pairs through the network and
+// leaves their channels in LDS; after a barrier every thread sums its cell
+// over the chunk.  Phi is Kahan-compensated, a summed per tile of entries.
+constexpr int TW = 512;       // threads (cells) per workgroup
+constexpr int TTILE = 64;     // list entries per LDS tile
+constexpr int TSLOT = 16;     // floats per (group, entry) pair in LDS
 
-template <int BC, bool ADD>
-__global__ __launch_bounds__(WG) void k_eval_mlp(DevTree T, EwaldP E, const void *__restrict__ pk,
-                                                 const int64_t *__restrict__ off, const double4 *__restrict__ rec,
-                                                 float *__restrict__ phi,
-                                                 float *__restrict__ acc, float negG) {
-  __shared__ double4 tile[WG];
+struct __align__(16) TRec {
+  double x, y, z;
+  float m, pad;
+};
+
+// pairs per chunk: 512 single cells with one entry, else 256
+__host__ __device__ inline int taylor_pairs(int gl) { return gl == 0 ? 512 : 256; }
+
+template <int BC>
+__global__ __launch_bounds__(TW) void k_eval_mlp_taylor(DevTree T, EwaldP E, const void *__restrict__ pk,
+                                                        const int64_t *__restrict__ off,
+                                                        const double4 *__restrict__ rec, float *__restrict__ phi,
+                                                        float *__restrict__ acc, float negG, double tmax) {
+  __shared__ f16x8 wl[64 * NPK];
+  __shared__ TRec tile[TTILE];
+  extern __shared__ __align__(16) float slot[];  // [pairs][TSLOT]
   const int64_t b = blockIdx.x;
-  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6, g = l >> 5, m = l & 31;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, m = l & 31;
   const int64_t ncell = T.nb * 512;
   const double h = size_at(T.root_size, T.blev[b]) / 8.0;
-  __shared__ f16x8 wl[64 * NPK];
+  const int gl = mlp_group_level(h, tmax);
+  const int gs = 1 << gl, ga = 8 >> gl, G = ga * ga * ga;  // group side, groups per axis, groups
+  const int P = taylor_pairs(gl), C = P / G;                // pairs and entries per chunk
   const mlpinf::Ops W = mlpinf::load_ops(pk, wl);
   const f16x8 one = mlpinf::ones();
+  const int64_t bx = T.bcoord[3 * b], by = T.bcoord[3 * b + 1], bz = T.bcoord[3 * b + 2];
+  const double gsz = h * (double)gs;  // group edge (exact: a power-of-two multiple of h)
+  // this thread's cell, its group and its offset from the group centre
+  const int ci = tid, ii = ci & 7, jj = (ci >> 3) & 7, kk = ci >> 6;
+  const int mg = (ii >> gl) + ga * ((jj >> gl) + ga * (kk >> gl));
+  auto gcentre = [&](int g, double c[3]) {
+    const int gx = g % ga, gy = (g / ga) % ga, gz = g / (ga * ga);
+    if (gl == 0) {
+      c[0] = centre_coord(T.org[0], 8 * bx + gx, h);
+      c[1] = centre_coord(T.org[1], 8 * by + gy, h);
+      c[2] = centre_coord(T.org[2], 8 * bz + gz, h);
+    } else {
+      c[0] = centre_coord(T.org[0], ga * bx + gx, gsz);
+      c[1] = centre_coord(T.org[1], ga * by + gy, gsz);
+      c[2] = centre_coord(T.org[2], ga * bz + gz, gsz);
+    }
+  };
+  float dlx, dly, dlz;
+  {
+    double gc[3];
+    gcentre(mg, gc);
+    dlx = (float)(centre_coord(T.org[0], 8 * bx + ii, h) - gc[0]);
+    dly = (float)(centre_coord(T.org[1], 8 * by + jj, h) - gc[1]);
+    dlz = (float)(centre_coord(T.org[2], 8 * bz + kk, h) - gc[2]);
+  }
+  // the (group, entry) pairs of this lane in the network phase: batch q of
+  // wave w covers pairs 32 (w + 8 q) + m, pair p = entry p / G, group p % G
+  const int nbatch = P / 256;
+  double pgc[2][3];
+  int pent[2];
+  for (int q = 0; q < 2; ++q) {
+    const int p = 32 * (w + 8 * q) + m;
+    pent[q] = p / G;
+    gcentre(p % G, pgc[q]);
+  }
   const float zfar = (float)E.zfar, fa = (float)E.far_phi_a, fb = (float)E.far_phi_b, faz = (float)E.far_az;
-  float s[2] = {0.f, 0.f}, cc[2] = {0.f, 0.f}, ax[2] = {0.f, 0.f}, ay[2] = {0.f, 0.f}, az[2] = {0.f, 0.f};
-  // absolute centres of this lane's cells (cell 64 w + 32 gg + m + 256 sl of
-  // batch (sl, gg); x is the same for all four), by the expression of the
-  // records' cell centres: each offset is then formed and wrapped in FP64
-  // exactly as the column walk does (its Newtonian part and this correction
-  // refer to the same image, and the target cell gives d = 0 exactly)
-  const int c0 = 64 * w + m;
-  const int64_t bx = 8 * (int64_t)T.bcoord[3 * b], by = 8 * (int64_t)T.bcoord[3 * b + 1],
-                bz = 8 * (int64_t)T.bcoord[3 * b + 2];
-  const double cx = centre_coord(T.org[0], bx + (c0 & 7), h);
-  const double cy0 = centre_coord(T.org[1], by + ((c0 >> 3) & 7), h);
-  const double cy1 = centre_coord(T.org[1], by + (((c0 + 32) >> 3) & 7), h);
-  const double cz0 = centre_coord(T.org[2], bz + (c0 >> 6), h);
-  const double cz1 = centre_coord(T.org[2], bz + ((c0 + 256) >> 6), h);
+  float ks = 0.f, kc = 0.f, ax = 0.f, ay = 0.f, az = 0.f;
   const int64_t start = off[b], n = off[b + 1] - start;
-  for (int64_t t0 = 0; t0 < n; t0 += WG) {
-    if (t0 + tid < n) tile[tid] = rec[start + t0 + tid];
-    __syncthreads();
-    const int mm = (int)(n - t0 < WG ? n - t0 : WG);
-    // acceleration summed per tile, then into the totals (blocked summation)
-    float tx[2] = {0.f, 0.f}, ty[2] = {0.f, 0.f}, tz[2] = {0.f, 0.f};
-    for (int j = 0; j < mm; ++j) {
-      const double4 r = tile[j];
-      const float m32 = (float)r.w;
-      // slot sl (unrolled: its accumulators are fixed registers), then one
-      // batch of 32 pairs per lane group (a loop, not unrolled: fewer live
-      // registers, so the products stay in ordinary vector registers)
-#pragma unroll
-      for (int sl = 0; sl < 2; ++sl) {
-#pragma unroll 1
-        for (int gg = 0; gg < 2; ++gg) {
-          const double ex = wrap_axis(cx - r.x, E.L[0], E.inv_L[0], 1);
-          const double ey = wrap_axis((gg ? cy1 : cy0) - r.y, E.L[1], E.inv_L[1], 1);
-          const double ez = wrap_axis((sl ? cz1 : cz0) - r.z, E.L[2], E.inv_L[2], BC == 1);
-          const double e2 = ex * ex + ey * ey + ez * ez;
-          const float dx = (float)ex, dy = (float)ey, dz = (float)ez;
-          float y[4];
-          mlpinf::forward(W, mlpinf::input(fabsf(dx), fabsf(dy), fabsf(dz)), one, y);
-          const bool valid = e2 != 0.0;  // the target cell itself contributes nothing
-          const float inv = valid ? __builtin_amdgcn_rsqf(fmaxf((float)e2, 1e-30f)) : 0.0f;
-          const float inv3 = inv * inv * inv;
-          // ADD: the Newtonian part is already in the outputs
-          const float nw = ADD ? 0.0f : 1.0f;
-          float ph = nw * inv + y[0];
-          float A0 = nw * dx * inv3 + (dx < 0 ? -y[1] : y[1]);
-          float A1 = nw * dy * inv3 + (dy < 0 ? -y[2] : y[2]);
-          float A2 = nw * dz * inv3 + (dz < 0 ? -y[3] : y[3]);
-          if (BC == 2 && fabsf(dz) > zfar) {
-            ph = fa * fabsf(dz) + fb - (1.0f - nw) * inv;
-            A0 = -(1.0f - nw) * dx * inv3;
-            A1 = -(1.0f - nw) * dy * inv3;
-            A2 = (dz < 0 ? -faz : faz) - (1.0f - nw) * dz * inv3;
-          }
-          // lane group g owns the batch gg == g; a zero mass makes the other
-          // group's term (and the target cell's) an exact zero
-          const float mw = (g == gg && valid) ? m32 : 0.0f;
-          const float yk = mw * ph - cc[sl], tk = s[sl] + yk;
-          cc[sl] = (tk - s[sl]) - yk;
-          s[sl] = tk;
-          tx[sl] += mw * A0;
-          ty[sl] += mw * A1;
-          tz[sl] += mw * A2;
+  for (int64_t t0 = 0; t0 < n; t0 += TTILE) {
+    const int mt = (int)(n - t0 < TTILE ? n - t0 : TTILE);
+    __syncthreads();  // the previous tile's last chunk is consumed
+    if (tid < mt) {
+      const double4 r = rec[start + t0 + tid];
+      tile[tid].x = r.x;
+      tile[tid].y = r.y;
+      tile[tid].z = r.z;
+      tile[tid].m = (float)r.w;
+    }
+    float tx = 0.f, ty = 0.f, tz = 0.f;
+    for (int j0 = 0; j0 < mt; j0 += C) {
+      __syncthreads();  // tile loaded; the previous chunk's slots are consumed
+      // network phase: (group, entry) pairs of this chunk; entries past the
+      // tile's end repeat its last entry (their slots are never read)
+      for (int q = 0; q < nbatch; ++q) {
+        const int j = j0 + pent[q] < mt ? j0 + pent[q] : mt - 1;
+        const TRec r = tile[j];
+        const double ex = wrap_axis(pgc[q][0] - r.x, E.L[0], E.inv_L[0], 1);
+        const double ey = wrap_axis(pgc[q][1] - r.y, E.L[1], E.inv_L[1], 1);
+        const double ez = wrap_axis(pgc[q][2] - r.z, E.L[2], E.inv_L[2], BC == 1);
+        const float dx = (float)ex, dy = (float)ey, dz = (float)ez;
+        float y[NO];
+        mlpinf::forward(W, mlpinf::input(fabsf(dx), fabsf(dy), fabsf(dz)), one, y);
+        const float sx = ex < 0 ? -1.f : 1.f, sy = ey < 0 ? -1.f : 1.f, sz = ez < 0 ? -1.f : 1.f;
+        const bool far = BC == 2 && fabs(ez) > E.zfar;
+        float4 *o = reinterpret_cast<float4 *>(slot + TSLOT * (32 * (w + 8 * q) + m));
+        // the two lane groups hold the same outputs: each writes half the slot
+        if (l < 32) {
+          o[0] = make_float4(y[0], sx * y[1], sy * y[2], sz * y[3]);
+          o[1] = make_float4(y[4], y[5], y[6], sx * sy * y[7]);
+        } else {
+          o[2] = make_float4(sx * sz * y[8], sy * sz * y[9], dx, dy);
+          o[3] = make_float4(dz, far ? 1.f : 0.f, 0.f, 0.f);
         }
       }
+      __syncthreads();
+      // cell phase: this thread's cell against the chunk's entries
+      const int mc = mt - j0 < C ? mt - j0 : C;
+      for (int j = 0; j < mc; ++j) {
+        const float4 *o = reinterpret_cast<const float4 *>(slot + TSLOT * (j * G + mg));
+        const float4 v0 = o[0], v1 = o[1], v2 = o[2], v3 = o[3];
+        const float dx = v2.z + dlx, dy = v2.w + dly, dz = v3.x + dlz;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const bool valid = r2 != 0.0f;  // the target cell itself contributes nothing
+        const float inv = valid ? __builtin_amdgcn_rsqf(fmaxf(r2, 1e-30f)) : 0.0f;
+        const float inv3 = inv * inv * inv;
+        float ph, A0, A1, A2;
+        if (BC == 2 && v3.y != 0.0f) {
+          ph = fa * fabsf(dz) + fb;
+          A0 = 0.0f;
+          A1 = 0.0f;
+          A2 = dz < 0 ? -faz : faz;
+        } else {
+          ph = inv + (v0.x - (v0.y * dlx + v0.z * dly + v0.w * dlz));
+          A0 = dx * inv3 + (v0.y - (v1.x * dlx + v1.w * dly + v2.x * dlz));
+          A1 = dy * inv3 + (v0.z - (v1.w * dlx + v1.y * dly + v2.y * dlz));
+          A2 = dz * inv3 + (v0.w - (v2.x * dlx + v2.y * dly + v1.z * dlz));
+        }
+        const float mw = valid ? tile[j0 + j].m : 0.0f;
+        const float yk = mw * ph - kc, tk = ks + yk;
+        kc = (tk - ks) - yk;
+        ks = tk;
+        tx += mw * A0;
+        ty += mw * A1;
+        tz += mw * A2;
+      }
     }
-    for (int q = 0; q < 2; ++q) {
-      ax[q] += tx[q];
-      ay[q] += ty[q];
-      az[q] += tz[q];
-    }
-    __syncthreads();
+    ax += tx;
+    ay += ty;
+    az += tz;
   }
-  for (int q = 0; q < 2; ++q) {
-    const int64_t o = b * 512 + tid + q * WG;
-    phi[o] = (ADD ? phi[o] : 0.0f) + negG * (s[q] - cc[q]);
-    acc[o] = (ADD ? acc[o] : 0.0f) + negG * ax[q];
-    acc[ncell + o] = (ADD ? acc[ncell + o] : 0.0f) + negG * ay[q];
-    acc[2 * ncell + o] = (ADD ? acc[2 * ncell + o] : 0.0f) + negG * az[q];
-  }
+  const int64_t o = b * 512 + ci;
+  phi[o] = negG * (ks - kc);
+  acc[o] = negG * ax;
+  acc[ncell + o] = negG * ay;
+  acc[2 * ncell + o] = negG * az;
 }
 
 }  // namespace
@@ -600,7 +678,7 @@ hipError_t fwdbwd(const float *P, int64_t n, int64_t s0, int64_t batch, const fl
     attr = true;
   }
   hipLaunchKernelGGL(k_mlp_fwdbwd, dim3((unsigned)(batch / SB)), dim3(256), lds, st, P, n, s0, X, T,
-                     1.0f / (4.0f * (float)batch), partial, lossp);
+                     1.0f / ((float)NO * (float)batch), partial, lossp);
   return hipGetLastError();
 }
 
@@ -679,19 +757,21 @@ hipError_t launch_mlp_points_eval(const void *pk, const EwaldP &E, int64_t n, co
   return hipGetLastError();
 }
 
+size_t eval_mlp_smem(double h_max, double tmax) {
+  return (size_t)taylor_pairs(mlp_group_level(h_max, tmax)) * TSLOT * sizeof(float);
+}
+
 hipError_t launch_eval_mlp(const DevTree &T, const EwaldP &E, const void *pk, const int64_t *off,
-                           const double4 *rec, float *phi, float *acc, double G, bool add,
+                           const double4 *rec, float *phi, float *acc, double G, double tmax, double h_max,
                            hipStream_t st) {
-  dim3 grid((unsigned)T.nb), blk(WG);
+  dim3 grid((unsigned)T.nb), blk(TW);
   const float ng = (float)(-G);
-  if (E.bctype == 1 && !add)
-    hipLaunchKernelGGL((k_eval_mlp<1, false>), grid, blk, 0, st, T, E, pk, off, rec, phi, acc, ng);
-  else if (E.bctype == 2 && !add)
-    hipLaunchKernelGGL((k_eval_mlp<2, false>), grid, blk, 0, st, T, E, pk, off, rec, phi, acc, ng);
-  else if (E.bctype == 1)
-    hipLaunchKernelGGL((k_eval_mlp<1, true>), grid, blk, 0, st, T, E, pk, off, rec, phi, acc, ng);
+  // dynamic LDS for the coarsest block (its groups are the smallest)
+  const size_t sm = eval_mlp_smem(h_max, tmax);
+  if (E.bctype == 1)
+    hipLaunchKernelGGL((k_eval_mlp_taylor<1>), grid, blk, sm, st, T, E, pk, off, rec, phi, acc, ng, tmax);
   else if (E.bctype == 2)
-    hipLaunchKernelGGL((k_eval_mlp<2, true>), grid, blk, 0, st, T, E, pk, off, rec, phi, acc, ng);
+    hipLaunchKernelGGL((k_eval_mlp_taylor<2>), grid, blk, sm, st, T, E, pk, off, rec, phi, acc, ng, tmax);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

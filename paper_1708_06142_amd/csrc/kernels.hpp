@@ -89,8 +89,8 @@ size_t cols_smem_bytes(int npix, int cpw, bool fp64, int nthr);
 // cells per workgroup with the maps in LDS: 256 or 128 when their LDS fits in
 // 64 KB, else 0 (the maps are then accumulated in npix, 256 cells per group)
 int cols_lds_cpw(int npix, bool fp64, int nthr);
-// newton_only (FP32, 3P / 2P1I): the minimum-image Newtonian part only, for
-// every pair; launch_eval_mlp with add = true then adds the correction
+// no_gravity (FP32, 3P / 2P1I): the columns only, phi and acc untouched (the
+// walk with the learned correction computes them)
 // table rows of offsets d [n][3] (cell - node) of nodes of size h [n]; -1 for d = 0
 hipError_t launch_column_bins(const ColP &C, int64_t n, const double *d, const double *h, int32_t *row,
                               hipStream_t st);
@@ -99,7 +99,7 @@ hipError_t launch_column_bins(const ColP &C, int64_t n, const double *d, const d
 // blist (optional): evaluate only the nblist leaf blocks listed there
 hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const ColP &C, const int64_t *off,
                             const double4 *rec, const int32_t *ids, const double *lh, void *phi, void *acc,
-                            void *npix, void *tau, double G, int cpw, bool newton_only, int *wg_per_cu,
+                            void *npix, void *tau, double G, int cpw, bool no_gravity, int *wg_per_cu,
                             hipStream_t st, const int32_t *blist = nullptr, int64_t nblist = 0);
 // rows of the offsets (i, j, k) cell sizes between two cells of one size,
 // |i|, |j|, |k| <= R (k slowest, i fastest), written at rows C.lat0 + ... of
@@ -116,7 +116,9 @@ hipError_t launch_mpe(const DevTree &T, int64_t npairs, const int32_t *pnode, co
 hipError_t launch_build(const DevTree &T, const double *rho, int *bad,
                         const std::vector<int64_t> &level_begin, int lmax, hipStream_t st);
 
-hipError_t launch_lists(bool fill, const DevTree &T, const MacP &P, int grid, int32_t *count,
+// count pass (fill false): count [nb] list lengths and, when nodes is not
+// null, nodes [2 nb] = (opened nodes, cells in the list) per block
+hipError_t launch_lists(bool fill, const DevTree &T, const MacP &P, int grid, int32_t *count, int32_t *nodes,
                         const int64_t *off, double4 *rec, int32_t *ids, double *lh, int32_t *scratch,
                         int64_t scratch_stride, int64_t capA, hipStream_t st);
 
@@ -145,10 +147,12 @@ hipError_t launch_ewald_points(const EwaldP &E, double alpha, int rcut2, int fcu
                                double *out, hipStream_t st);
 
 // ---------------------------------------------------------------- surrogate
-// Network 3 -> 64 -> 64 -> 64 -> 4 over the folded offset; parameter layout
-// W1[64][3] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[4][64] b4[4].
+// Network 3 -> 64 -> 64 -> 64 -> 10 over the folded offset: the correction's
+// ten channels of the Ewald table, phi_c, A_c (3) and the second derivatives
+// of phi_c (xx, yy, zz, xy, xz, yz); parameter layout
+// W1[64][3] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[10][64] b4[10].
 namespace mlpdef {
-constexpr int H = 64, NI = 3, NO = 4;
+constexpr int H = 64, NI = 3, NO = 10;
 constexpr int OW1 = 0, OB1 = OW1 + H * NI, OW2 = OB1 + H, OB2 = OW2 + H * H, OW3 = OB2 + H, OB3 = OW3 + H * H,
               OW4 = OB3 + H, OB4 = OW4 + NO * H, NP = OB4 + NO;
 // packed matrix-core operands, 8 halves per lane each (see k_mlp.hip)
@@ -158,8 +162,8 @@ constexpr int PK_L1 = 0, PK_L2 = 2, PK_L2B = 10, PK_L3 = 12, PK_L3B = 20, PK_L4 
 // Input / output scaling: x = 2 u / ext - 1, y = (out - mu) / sig.
 struct MlpNorm {
   double ext[3];
-  double mu[4];
-  double sig[4];
+  double mu[mlpdef::NO];
+  double sig[mlpdef::NO];
 };
 
 hipError_t launch_mlp_init(uint64_t seed, float *P, hipStream_t st);
@@ -185,16 +189,30 @@ hipError_t launch_mlp_step(float *P, int64_t n, int64_t s0, int64_t batch, const
                            hipStream_t st);
 // pack (P, N) into the matrix-core operands used by inference
 hipError_t launch_mlp_pack(const float *P, const MlpNorm &N, void *pk, hipStream_t st);
-// correction (phi_c, A_c) at offsets d [n][3] by the surrogate: out [n][4]
+// correction (phi_c, A_c, H_c) at offsets d [n][3] by the surrogate: out [n][10]
 hipError_t launch_mlp_points_eval(const void *pk, const EwaldP &E, int64_t n, const double *d, double *out,
                                   hipStream_t st);
-// the same offsets by the FP64 series / the FP64 table (Taylor): out [n][4]
-hipError_t launch_ewald_points4(int method, const EwaldP &E, double alpha, int rcut2, int fcut2, int64_t n,
-                                const double *d, double *out, hipStream_t st);
-// FP32 walk with the correction from the surrogate (BC 3P or 2P1I); add:
-// only the correction (2P1I beyond zfar: the limit minus the Newtonian
-// part), added to phi and acc as the Newtonian column walk left them
+// the same offsets by the FP64 series / the FP64 table (Taylor for phi_c and
+// A_c, the nearest grid point's H_c): out [n][10]
+hipError_t launch_ewald_points10(int method, const EwaldP &E, double alpha, int rcut2, int fcut2, int64_t n,
+                                 const double *d, double *out, hipStream_t st);
+// FP32 gravity walk with the surrogate's correction (BC 3P or 2P1I): the
+// network once per (group of cells, list entry), a first-order Taylor step to
+// each cell of the group; groups are the largest block-tree nodes whose cells
+// lie within tmax (half the Ewald table's smallest spacing) of their centre
+// on every axis; h_max: the largest cell size of the grid (sizes the LDS)
 hipError_t launch_eval_mlp(const DevTree &T, const EwaldP &E, const void *pk, const int64_t *off,
-                           const double4 *rec, float *phi, float *acc, double G, bool add, hipStream_t st);
+                           const double4 *rec, float *phi, float *acc, double G, double tmax, double h_max,
+                           hipStream_t st);
+size_t eval_mlp_smem(double h_max, double tmax);
+// Group level of the surrogate walk for cells of size h: groups of 2^gl cells
+// per axis, the largest gl in {2, 1, 0} whose cells lie within tmax of the
+// group centre ((2^gl - 1) h / 2 <= tmax).  Groups per leaf block: 512 >> 3 gl.
+__host__ __device__ inline int mlp_group_level(double h, double tmax) {
+  if ((3.0 * h) * 0.5 <= tmax) return 2;
+  if ((1.0 * h) * 0.5 <= tmax) return 1;
+  return 0;
+}
+inline int mlp_groups(double h, double tmax) { return 512 >> (3 * mlp_group_level(h, tmax)); }
 
 }  // namespace ot

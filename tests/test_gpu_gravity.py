@@ -243,3 +243,31 @@ def test_lognormal128_tree_vs_direct(lognormal128, mac):
     print(f"lognormal128 {mac} 1e-3 + columns MAC: e_a max {ea.max():.3e}, e_phi max {ep.max():.3e}, "
           f"a_lim {st.a_lim_used:.4g}")
     assert ea.max() <= 1e-3 and ep.max() <= 1e-3
+
+
+def test_list_statistics_vs_oracle():
+    """ot_stats counts: the list-length histogram covers every block once;
+    accepted non-cell entries and opened nodes summed over the blocks equal
+    the oracle's lists (opened = the proper ancestors of each list's entries,
+    accepted = its entries that are not cells)."""
+    from test_oracle_mac import node_geometry, visited
+    g = workloads.small_amr()
+    kw = dict(mac="ape", a_lim=3e-3)
+    t = oracle.Tree(g, **kw)
+    _, _, _, parent = node_geometry(t, g)
+    ncell0 = t.na + 72 * g.nb
+    n_open = n_acc = 0
+    lens = []
+    for b in range(g.nb):
+        ids = t.block_list(b)
+        acc, opened = visited(ids, parent)
+        n_open += opened.size
+        n_acc += int((acc < ncell0).sum())
+        lens.append(ids.size)
+    _, _, st, _ = ot.run(g, **kw)
+    hist = np.array(st.list_hist)
+    assert hist.sum() == g.nb
+    ref = np.bincount(np.floor(np.log2(lens)).astype(int), minlength=32)
+    assert np.array_equal(hist, ref)
+    assert st.n_accepted == n_acc and st.n_opened == n_open
+    assert st.total_list == sum(lens)

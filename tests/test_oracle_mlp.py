@@ -20,8 +20,8 @@ def _numpy_forward(p, x):
     b2 = p[o:o + 64]; o += 64
     W3 = p[o:o + 4096].reshape(64, 64); o += 4096
     b3 = p[o:o + 64]; o += 64
-    W4 = p[o:o + 256].reshape(4, 64); o += 256
-    b4 = p[o:o + 4]
+    W4 = p[o:o + 640].reshape(10, 64); o += 640
+    b4 = p[o:o + 10]
     def act(z):
         t = np.clip(z / 6 + 0.5, 0, 1)
         return z * t * t * (3 - 2 * t)
@@ -52,11 +52,12 @@ def test_gradient_vs_central_differences():
     p = _params(2)
     rng = np.random.default_rng(3)
     x = rng.uniform(-1, 1, (16, 3))
-    t = rng.normal(size=(16, 4))
+    t = rng.normal(size=(16, oracle.MLP_NOUT))
     loss, g = oracle.mlp_grad(p, x, t)
     y = oracle.mlp_forward(p, x)
     assert abs(loss - ((y - t) ** 2).mean()) < 1e-14 * max(1.0, loss)
-    idx = np.concatenate([rng.choice(8836, 200, replace=False), [0, 191, 192, 255, 8831, 8835]])
+    n = oracle.MLP_NPARAM
+    idx = np.concatenate([rng.choice(n, 200, replace=False), [0, 191, 192, 255, n - 650, n - 11, n - 10, n - 1]])
     eps = 1e-6
     for i in idx:
         q = p.copy()

@@ -310,6 +310,22 @@ def small_amr(seed=7, bc=(0, 0, 0), nroot=(1, 1, 1)):
                 name="small_amr", meta={"seed": seed})
 
 
+def deep_amr(bc=(1, 1, 1), nroot=(1, 1, 1), seed=19):
+    """AMR test grid with leaf blocks at five levels, cell sizes 1/32 to 1/512
+    of a unit root: a Plummer core (a = 0.01, contrast 1e4) refined from a
+    level-3 base up to level 7 where the block's densest cell exceeds 20, with
+    2:1 balance, times lognormal cell noise (sigma 0.5)."""
+    rng = np.random.default_rng(seed)
+    box = np.array(nroot, dtype=np.float64)
+    centre = np.array([0.41, 0.57, 0.47]) * box
+    dens = plummer_cores_density([centre], 0.01, 1e4)
+    level, coord = amr_blocks(dens, nroot, 1.0, 3, 7, 20.0, bc)
+    xc = cell_centres(1.0, (0.0, 0.0, 0.0), level, coord)
+    rho = dens(xc[..., 0], xc[..., 1], xc[..., 2]) * rng.lognormal(0.0, 0.5, xc.shape[:-1])
+    return Grid(tuple(nroot), 1.0, (0.0, 0.0, 0.0), level, coord, rho, tuple(bc), name="deep_amr",
+                meta={"seed": seed})
+
+
 def shuffled(g: Grid, seed=11):
     """Same grid with the leaf blocks listed in a random order."""
     perm = np.random.default_rng(seed).permutation(g.nb)
