@@ -8,7 +8,7 @@
  * blocks of a block-structured AMR grid (blocks of 8^3 cells, organised as an
  * octree of blocks, the "amr-tree"); the solver returns, for every cell, the
  * gravitational potential and acceleration summed over monopole tree nodes
- * (Eqs. 7-8, with the Ewald forms of Sec. 2.2.2-2.2.3 for periodic or mixed
+ * (Eqs. 7-8, with the Ewald forms of Sec. 2.2.3-2.2.4 for periodic or mixed
  * boundaries) and, optionally, the column density in each HEALPix direction
  * (Sec. 2.3).
  *
@@ -44,12 +44,13 @@ typedef enum {
   OT_ERR_STATE = -4,       /* call out of order (e.g. solve before build)    */
   OT_ERR_OOM = -5,         /* device allocation failed or over the limit     */
   OT_ERR_DEVICE = -6,      /* HIP runtime error                              */
-  OT_ERR_UNSUPPORTED = -7  /* valid request this build does not implement   */
+  OT_ERR_UNSUPPORTED = -7, /* valid request this build does not implement   */
+  OT_ERR_IO = -8           /* a cache file cannot be read or written         */
 } ot_status;
 
 typedef enum { OT_BC_ISOLATED = 0, OT_BC_PERIODIC = 1 } ot_bc;
 typedef enum { OT_MAC_BH = 0, OT_MAC_APE = 1, OT_MAC_MPE = 2 } ot_mac;
-/* TABLE: FP64-generated table with the Taylor term (Sec. 2.2.4, second
+/* TABLE: FP64-generated table with the Taylor term (Sec. 2.2.5, second
  * approach); EXACT: the FP64 series itself (point evaluation only); MLP: the
  * learned surrogate once ot_mlp_train (or ot_mlp_set) has accepted it, else
  * the table. */
@@ -61,8 +62,9 @@ typedef struct {
   int32_t nroot[3];      /* root blocks per axis (a forest, Sec. 2)            [1,1,1] */
   int32_t bc[3];         /* per-axis boundary, App. B grav_boundary_type_*     [iso]   */
                          /* supported: all isolated, all periodic (3P), x, y
-                            periodic with z isolated (2P1I, Sec. 2.2.3), and x
-                            periodic with y, z isolated (1P2I, Sec. 2.2.3)             */
+                            periodic with z isolated (2P1I, Sec. 2.2.4; needs
+                            Ly <= Lx, else OT_ERR_UNSUPPORTED), and x periodic
+                            with y, z isolated (1P2I, Sec. 2.2.4)                      */
   double root_size;      /* edge of a cubic root block                          [1.0]  */
   double origin[3];      /* domain corner                                       [0,0,0]*/
   double G;              /* gravitational constant, App. B grv_bhNewton         [1.0]  */
@@ -80,7 +82,7 @@ typedef struct {
   int32_t ewald_rcut2;   /* real-space cut-off |i|^2, Eq. (10); <=0: 15 (3P), 10 (2P1I, 1P2I) */
   int32_t ewald_fcut2;   /* Fourier cut-off |l|^2, Eq. (10); <= 0: 10                  */
   int32_t device;        /* HIP device ordinal                                  [0]    */
-  double ewald_alpha;    /* Ewald splitting constant; <= 0: 2 / Lx (Sec. 2.2.2) [0]    */
+  double ewald_alpha;    /* Ewald splitting constant; <= 0: 2 / Lx (Sec. 2.2.3) [0]    */
   uint64_t max_device_bytes; /* cap on library allocations; 0 = none           [0]    */
   /* column densities (OpticalDepth module, Sec. 2.3; App. B tr_* parameters) */
   int32_t nside;         /* HEALPix Nside of the per-cell maps: 1, 2 or 4
@@ -163,7 +165,7 @@ ot_status ot_solve(ot_ctx *c, float *phi_dev, float *acc_dev, float *npix_dev, f
 ot_status ot_solve64(ot_ctx *c, double *phi_dev, double *acc_dev, double *npix_dev,
                      double *tau_dev, ot_stats *stats_host, void *stream);
 
-/* Adaptive block update, Sec. 2.2.5 (periodic boundaries use the Ewald
+/* Adaptive block update, Sec. 2.2.6 (periodic boundaries use the Ewald
  * table; the surrogate is not used).  On entry phi_dev, acc_dev and, when
  * nside > 0, npix_dev and tau_dev hold the previous step's solution on the
  * same grid (layouts as ot_solve; npix_dev and tau_dev are ignored when
@@ -182,14 +184,21 @@ ot_status ot_solve_abu(ot_ctx *c, float *phi_dev, float *acc_dev, float *npix_de
 ot_status ot_solve_abu64(ot_ctx *c, double *phi_dev, double *acc_dev, double *npix_dev, double *tau_dev,
                          double tol, int32_t *updated_host, ot_stats *stats_host, void *stream);
 
-/* Ewald correction table, Sec. 2.2.4 (second approach): phi_c = phi - 1/r,
+/* Ewald correction table, Sec. 2.2.5 (second approach): phi_c = phi - 1/r,
  * A_c = A - d/r^3 and the six second derivatives of phi_c, FP64, on a
  * uniform n^3 grid over the folded domain [0, Lx/2] x [0, Ly/2] x
  * [0, Lz/2] (3P), [0, min(Lz, 2 Lx)] in z (2P1I), or [0, Lx/2] x
  * [0, min(Ly, 4 Lx)] x [0, min(Lz, 4 Lx)] (1P2I).  Built on the device by
  * the first solve that needs it; this call builds it eagerly.  Only for
- * periodic or mixed boundaries (OT_ERR_STATE otherwise). */
-ot_status ot_ewald_prepare(ot_ctx *c, void *stream);
+ * periodic or mixed boundaries (OT_ERR_STATE otherwise).
+ * cache_path (may be NULL; App. B grv_bhEwaldFName): a file that keeps the
+ * FP64 table.  It is read when its header matches this context's table
+ * (boundary type, box, alpha, cut-offs, n, domain, channel layout) and its
+ * checksum holds; otherwise (missing, other inputs, truncated, corrupted)
+ * the table is generated and the file rewritten (through a temporary file
+ * next to it, renamed into place).  OT_ERR_IO when the file exists but
+ * cannot be read, or cannot be written, before any device work. */
+ot_status ot_ewald_prepare(ot_ctx *c, const char *cache_path, void *stream);
 
 /* ---- learned Ewald surrogate --------------------------------------------
  * Not part of the paper: a network 3 -> 64 -> 64 -> 64 -> 10 (activation
@@ -229,7 +238,7 @@ typedef struct {
   double ms_train;      /* all Adam steps                                     */
   double ms_validate;   /* held-out evaluation                                */
   int32_t ok;           /* 1: accepted, the walk uses it for OT_EWALD_MLP     */
-  int32_t pad_;
+  int32_t from_cache;   /* 1: read from the cache file (times are then 0)     */
 } ot_mlp_report;
 
 #define OT_MLP_NPARAM 9226 /* W1[64][3] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[10][64] b4[10] */
@@ -241,9 +250,16 @@ void ot_mlp_config_default(ot_mlp_config *cfg);
 /* Generate the training and held-out offsets, their FP64 series values, train,
  * validate against the series and the table, and accept or reject the
  * surrogate.  3P and 2P1I only (OT_ERR_STATE when isolated, OT_ERR_UNSUPPORTED
- * for 1P2I, whose walks use the table).  Synchronous;
- * the training buffers are freed before returning.  report may be NULL. */
-ot_status ot_mlp_train(ot_ctx *c, const ot_mlp_config *cfg, ot_mlp_report *report, void *stream);
+ * for 1P2I, whose walks use the table).  Synchronous; the training buffers
+ * are freed before returning.  report may be NULL.
+ * cache_path (may be NULL): a file that keeps the trained parameters, their
+ * scaling and the report; read when its header matches (boundary type, box,
+ * the table's domain and the series' alpha and cut-offs, every field of cfg,
+ * the network's shape and the training recipe's version) and its checksum
+ * holds, else the surrogate is trained and the file rewritten.  OT_ERR_IO as
+ * for ot_ewald_prepare. */
+ot_status ot_mlp_train(ot_ctx *c, const ot_mlp_config *cfg, const char *cache_path, ot_mlp_report *report,
+                       void *stream);
 
 /* Current surrogate: params_host [OT_MLP_NPARAM], norm_host [OT_MLP_NNORM]
  * (either may be NULL).  OT_ERR_STATE before training or ot_mlp_set. */

@@ -204,7 +204,7 @@ class Tree:
         return B2, B3
 
     def walk_abu(self, prev_phi, prev_acc, tol, prev_npix=None, prev_tau=None):
-        """Adaptive block update (Sec. 2.2.5): returns phi [nb*512], acc [3, nb*512]
+        """Adaptive block update (Sec. 2.2.6): returns phi [nb*512], acc [3, nb*512]
         and updated [nb] (1 where the block was evaluated).  With prev_npix
         [nb, Npix, 512] and prev_tau [nb*512] (trees with nside > 0) also npix and
         tau: the group walk's columns for the updated blocks, the previous ones

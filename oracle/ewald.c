@@ -4,16 +4,16 @@
  *
  * phi(d) is the potential kernel of a unit mass (Phi = -G M phi) and
  * A = -grad phi (a = -G M A), App. A.
- *   3P   (Sec. 2.2.2, Eq. (9); App. A.1):
+ *   3P   (Sec. 2.2.3, Eq. (9); App. A.1):
  *        phi = sum_i erfc(alpha|d - n_i|)/|d - n_i|
  *            + 1/(pi b c Lx) sum_{l != 0} E(l) cos(k.d),
  *        E(l) = exp(-zeta Q)/Q, Q = l1^2 + (l2/b)^2 + (l3/c)^2.
- *   2P1I (Sec. 2.2.3, Eq. (15) with the code form in its footnote; App. A.2):
+ *   2P1I (Sec. 2.2.4, Eq. (15) with the code form in its footnote; App. A.2):
  *        phi = sum_{i1,i2} erfc(alpha|d - n_i|)/|d - n_i|
  *            + 1/(pi Lx b) sum_{l1,l2} cos(v_l) Itilde(l1, l2, dz).
  * Itilde is evaluated at |gamma| (it is even in gamma, its derivative odd).
  * The l = 0 term uses I(0,0) of Eq. (14); its derivative is -pi erf(gamma/2 sqrt(zeta)).
- *   1P2I (Sec. 2.2.3, the 1P2I potential; App. A.3), periodic along x:
+ *   1P2I (Sec. 2.2.4, the 1P2I potential; App. A.3), periodic along x:
  *        phi = sum_{i1} erfc(alpha|d - i1 Lx e_x|)/|d - i1 Lx e_x|
  *            + 2/Lx sum_{l1} exp(-zeta l1^2) cos(2 pi l1 dx / Lx) K(l1, eta),
  *        eta = 2 pi rho / Lx, rho = sqrt(dy^2 + dz^2),
@@ -35,7 +35,7 @@
  * digits; the l = 0 real-space term of the correction, -erf(alpha r)/r, uses
  * its Taylor series below alpha r = 0.2.
  *
- * Table (Sec. 2.2.4, second approach): phi_c = phi - 1/r, A_c and the six
+ * Table (Sec. 2.2.5, second approach): phi_c = phi - 1/r, A_c and the six
  * second derivatives of phi_c on a uniform grid over the folded domain
  * (phi_c even, A_c,k odd in d_k): [0, Lx/2] x [0, Ly/2] x [0, Lz/2] for 3P and
  * [0, Lx/2] x [0, Ly/2] x [0, min(Lz, 2 Lx)] for 2P1I, n points per axis with

@@ -11,7 +11,7 @@
  *   - MPE MAC, Eq. (2) with p = 1 (B_2, B_3 of Eq. (3), summed over the
  *     node's cells), against an absolute limit, Eq. (4);
  *   - monopole potential and acceleration, Eqs. (7) and (8);
- *   - adaptive block update (Sec. 2.2.5) from the eight corner cells;
+ *   - adaptive block update (Sec. 2.2.6) from the eight corner cells;
  *   - reference solution by direct summation over all other cells (Sec. 3).
  *
  * Readings of the paper taken here (they bind the GPU library as well):
@@ -511,7 +511,7 @@ static double nval(const nsum *a) { return a->s + a->c; }
 
 /* contribution of a source of unit mass at offset d = r - r_a:
  * phi (potential kernel, Phi = -G M phi) and A (a = -G M A), Eqs. (7), (8)
- * and, for periodic/mixed BCs, the Ewald forms of Sec. 2.2.2-2.2.3. */
+ * and, for periodic/mixed BCs, the Ewald forms of Sec. 2.2.3-2.2.4. */
 static void pair_kernel(const or_tree *t, const double d[3], double *phi, double A[3]) {
   if (t->bctype == OR_BC_ISO) {
     double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
@@ -605,7 +605,7 @@ void or_walk_group_blocks(const or_tree *t, int64_t nsel, const int64_t *sel, do
   }
 }
 
-/* Adaptive block update (Sec. 2.2.5): per leaf block the group walk first
+/* Adaptive block update (Sec. 2.2.6): per leaf block the group walk first
  * evaluates the eight corner cells (i, j, k in {0, 7}); when at each of them
  * the acceleration differs from the previous step's by less than tol (the
  * Euclidean norm of the difference, an absolute accuracy as in Eq. (4)), the

@@ -14,7 +14,7 @@
 
 typedef struct {
   int32_t nroot[3];   /* root blocks per axis (forest, Sec. 2 footnote)      */
-  int32_t bc[3];      /* per axis: 0 isolated, 1 periodic (Sec. 2.2.2-2.2.3) */
+  int32_t bc[3];      /* per axis: 0 isolated, 1 periodic (Sec. 2.2.3-2.2.4) */
   double root_size;   /* edge of a cubic root block                         */
   double origin[3];
   double G;           /* gravitational constant                             */
@@ -50,7 +50,7 @@ or_tree *or_tree_new(const or_params *p, int64_t nb, const int32_t *level,
 void or_tree_free(or_tree *t);
 /* MPE moments B_2, B_3 [na + 72 nb] (node ids below the cells); mac = 2 only */
 void or_tree_mpe_export(const or_tree *t, double *B2, double *B3);
-/* adaptive block update of the group walk (gravity only), Sec. 2.2.5 */
+/* adaptive block update of the group walk (gravity only), Sec. 2.2.6 */
 void or_walk_group_abu(const or_tree *t, const double *prev_phi, const double *prev_acc, double tol,
                        double *phi, double *acc, int32_t *updated);
 int64_t or_tree_na(const or_tree *t);

@@ -10,7 +10,7 @@ enum { OR_BC_ISO = 0, OR_BC_3P = 1, OR_BC_2P1I = 2, OR_BC_1P2I = 3 };
  * analytic line-mass limit replaces the series and the table */
 #define OR_1P2I_RFAR 4.0
 
-/* Ewald set-up for periodic (3P) and mixed (2P1I, 1P2I) boundaries, Sec. 2.2.2-2.2.4 */
+/* Ewald set-up for periodic (3P) and mixed (2P1I, 1P2I) boundaries, Sec. 2.2.3-2.2.5 */
 typedef struct {
   int bctype;
   double Lx, b, c;      /* box: Lx, Ly = b Lx, Lz = c Lx                    */

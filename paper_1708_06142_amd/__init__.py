@@ -18,9 +18,9 @@ LIBPATH = os.path.join(HERE, "libocttree.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "octtree.h")
 
 OT_OK, OT_ERR_INVALID_ARG, OT_ERR_BAD_GRID, OT_ERR_NUMERIC = 0, -1, -2, -3
-OT_ERR_STATE, OT_ERR_OOM, OT_ERR_DEVICE, OT_ERR_UNSUPPORTED = -4, -5, -6, -7
+OT_ERR_STATE, OT_ERR_OOM, OT_ERR_DEVICE, OT_ERR_UNSUPPORTED, OT_ERR_IO = -4, -5, -6, -7, -8
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "BAD_GRID", -3: "NUMERIC", -4: "STATE", -5: "OOM",
-          -6: "DEVICE", -7: "UNSUPPORTED"}
+          -6: "DEVICE", -7: "UNSUPPORTED", -8: "IO"}
 
 
 class OTError(RuntimeError):
@@ -63,10 +63,10 @@ class MlpConfig(C.Structure):
 class MlpReport(C.Structure):
     _fields_ = [("loss_first", C.c_double), ("loss_last", C.c_double), ("err_mlp", C.c_double * 10),
                 ("err_table", C.c_double * 10), ("ms_samples", C.c_double), ("ms_train", C.c_double),
-                ("ms_validate", C.c_double), ("ok", C.c_int32), ("pad_", C.c_int32)]
+                ("ms_validate", C.c_double), ("ok", C.c_int32), ("from_cache", C.c_int32)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
         d["err_mlp"], d["err_table"] = list(self.err_mlp), list(self.err_table)
         return d
 
@@ -99,7 +99,7 @@ def lib():
         L.ot_solve_abu.argtypes = [vp, vp, vp, vp, vp, C.c_double, vp, C.POINTER(Stats), vp]
         L.ot_solve_abu64.argtypes = [vp, vp, vp, vp, vp, C.c_double, vp, C.POINTER(Stats), vp]
         L.ot_export_raytable.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), vp, vp, vp, vp]
-        L.ot_ewald_prepare.argtypes = [vp, vp]
+        L.ot_ewald_prepare.argtypes = [vp, C.c_char_p, vp]
         L.ot_num_amr_nodes.restype = i64
         L.ot_num_amr_nodes.argtypes = [vp]
         L.ot_export_topology.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -107,7 +107,7 @@ def lib():
         L.ot_export_list.argtypes = [vp, i64, vp, i64, C.POINTER(i64)]
         L.ot_export_ewald_table.argtypes = [vp, vp]
         L.ot_mlp_config_default.argtypes = [C.POINTER(MlpConfig)]
-        L.ot_mlp_train.argtypes = [vp, C.POINTER(MlpConfig), C.POINTER(MlpReport), vp]
+        L.ot_mlp_train.argtypes = [vp, C.POINTER(MlpConfig), C.c_char_p, C.POINTER(MlpReport), vp]
         L.ot_mlp_get.argtypes = [vp, vp, vp]
         L.ot_mlp_set.argtypes = [vp, vp, vp, C.c_int32, vp]
         L.ot_mlp_grad.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
@@ -149,6 +149,8 @@ def _dev_ptr(t, dtype):
 
 def _stream(stream):
     import torch
+    if stream is None and not torch.cuda.is_available():
+        return None  # no device: the call fails on the host or reports the device error
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
 
@@ -263,13 +265,17 @@ class Solver:
                                              _np_ptr(w), _stream(stream)))
         return off, pix, w
 
-    def ewald_prepare(self, stream=None):
-        self._check(lib().ot_ewald_prepare(self.h, _stream(stream)))
+    def ewald_prepare(self, cache_path=None, stream=None):
+        """Build the Ewald table now; with cache_path read it from that file
+        or write it there."""
+        cp = os.fsencode(cache_path) if cache_path is not None else None
+        self._check(lib().ot_ewald_prepare(self.h, cp, _stream(stream)))
 
     # ---- learned Ewald surrogate
-    def mlp_train(self, stream=None, **cfg):
-        """Train, validate and accept or reject the surrogate; returns the report
-        as a dict.  Keyword arguments override ot_mlp_config_default."""
+    def mlp_train(self, stream=None, cache_path=None, **cfg):
+        """Train, validate and accept or reject the surrogate (or read it from
+        cache_path when that file matches); returns the report as a dict.
+        Keyword arguments override ot_mlp_config_default."""
         c = MlpConfig()
         lib().ot_mlp_config_default(C.byref(c))
         for k, v in cfg.items():
@@ -277,7 +283,8 @@ class Solver:
                 raise TypeError(f"unknown surrogate setting {k}")
             setattr(c, k, v)
         r = MlpReport()
-        self._check(lib().ot_mlp_train(self.h, C.byref(c), C.byref(r), _stream(stream)))
+        cp = os.fsencode(cache_path) if cache_path is not None else None
+        self._check(lib().ot_mlp_train(self.h, C.byref(c), cp, C.byref(r), _stream(stream)))
         return r.as_dict()
 
     def mlp_get(self):

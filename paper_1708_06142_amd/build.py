@@ -15,6 +15,7 @@ BUILD = os.path.join(HERE, "_build")
 # (node moments, MAC accept/open) are compiled without FMA contraction.
 SOURCES = {
     "topology.cpp": [],
+    "cache.cpp": [],
     "api.hip": [],
     "k_build.hip": ["-ffp-contract=off"],
     "k_list.hip": ["-ffp-contract=off"],

@@ -7,6 +7,7 @@
 #include <new>
 #include <string>
 
+#include "cache.hpp"
 #include "ctx.hpp"
 #include "kernels.hpp"
 
@@ -192,10 +193,8 @@ ot::EwaldP ewald_desc(const ot_ctx *c) {
   return E;
 }
 
-ot_status ewald_prepare(ot_ctx *c, hipStream_t st) {
-  if (c->bctype == ot::BC_ISO) return fail(c, OT_ERR_STATE, "Ewald table needs periodic or mixed boundaries");
-  if (c->ewald_ready) return OT_OK;
-  HIPCHK(hipSetDevice(c->p.device));
+// Ewald parameters of the context (before any device work)
+void ewald_params(ot_ctx *c) {
   const int n = c->p.ewald_n;
   c->ew_n = n;
   c->ew_rcut2 = c->p.ewald_rcut2 > 0 ? c->p.ewald_rcut2 : (c->bctype == ot::BC_3P ? 15 : 10);
@@ -211,14 +210,61 @@ ot_status ewald_prepare(ot_ctx *c, hipStream_t st) {
     c->ew_ext[2] = std::min(c->box[2], rf);
   }
   for (int k = 0; k < 3; ++k) c->ew_step[k] = c->ew_ext[k] / (double)(n - 1);
-  const size_t np = (size_t)n * n * n;
-  OTCHK(dalloc(c, c->tab64, np * 10 * sizeof(double)));
-  OTCHK(dalloc(c, c->tab32, np * 3 * sizeof(float4)));
-  ot::EwaldP E = ewald_desc(c);
-  HIPCHK(ot::launch_ewald_table(E, c->ew_alpha, c->ew_rcut2, c->ew_fcut2, P<double>(c->tab64),
-                                P<float4>(c->tab32), st));
-  HIPCHK(hipStreamSynchronize(st));
-  c->ewald_ready = true;
+}
+
+// every input the table depends on
+ot::CacheKey ewald_key(const ot_ctx *c) {
+  ot::CacheKey k;
+  memset(&k, 0, sizeof(k));
+  k.kind = 1;
+  k.i[0] = c->bctype;
+  k.i[1] = c->ew_n;
+  k.i[2] = c->ew_rcut2;
+  k.i[3] = c->ew_fcut2;
+  k.i[4] = 10;  // channels per point, x fastest, FP64
+  k.d[0] = c->ew_alpha;
+  for (int q = 0; q < 3; ++q) {
+    k.d[1 + q] = c->box[q];
+    k.d[4 + q] = c->ew_ext[q];
+  }
+  return k;
+}
+
+ot_status ewald_prepare(ot_ctx *c, const char *cache, hipStream_t st) {
+  if (c->bctype == ot::BC_ISO) return fail(c, OT_ERR_STATE, "Ewald table needs periodic or mixed boundaries");
+  std::string why;
+  if (cache && !ot::cache_path_usable(cache, why)) return fail(c, OT_ERR_IO, why);
+  if (!c->ewald_ready) ewald_params(c);
+  const size_t np = (size_t)c->ew_n * c->ew_n * c->ew_n;
+  const ot::CacheKey key = ewald_key(c);
+  std::vector<char> payload;
+  ot::CacheRead cr = ot::CacheRead::Regenerate;
+  if (cache) {
+    cr = ot::cache_read(cache, key, payload, why);
+    if (cr == ot::CacheRead::IoError) return fail(c, OT_ERR_IO, why);
+    if (cr == ot::CacheRead::Loaded && payload.size() != np * 10 * sizeof(double)) cr = ot::CacheRead::Regenerate;
+  }
+  if (c->ewald_ready && !cache) return OT_OK;
+  HIPCHK(hipSetDevice(c->p.device));
+  if (!c->ewald_ready) {
+    OTCHK(dalloc(c, c->tab64, np * 10 * sizeof(double)));
+    OTCHK(dalloc(c, c->tab32, np * 3 * sizeof(float4)));
+    ot::EwaldP E = ewald_desc(c);
+    if (cr == ot::CacheRead::Loaded) {
+      HIPCHK(hipMemcpyAsync(c->tab64.ptr, payload.data(), payload.size(), hipMemcpyHostToDevice, st));
+      HIPCHK(ot::launch_ewald_pack32(E, P<double>(c->tab64), P<float4>(c->tab32), st));
+    } else {
+      HIPCHK(ot::launch_ewald_table(E, c->ew_alpha, c->ew_rcut2, c->ew_fcut2, P<double>(c->tab64),
+                                    P<float4>(c->tab32), st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    c->ewald_ready = true;
+  }
+  if (cache && cr != ot::CacheRead::Loaded) {
+    std::vector<double> h(np * 10);
+    HIPCHK(hipMemcpy(h.data(), c->tab64.ptr, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    if (!ot::cache_write(cache, key, h.data(), h.size() * sizeof(double), why)) return fail(c, OT_ERR_IO, why);
+  }
   return OT_OK;
 }
 
@@ -631,7 +677,7 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
   if (c->bctype != ot::BC_ISO) {
     if (c->p.ewald == OT_EWALD_EXACT)
       return fail(c, OT_ERR_UNSUPPORTED, "per-pair exact Ewald series is not built into the walk");
-    OTCHK(ewald_prepare(c, st));
+    OTCHK(ewald_prepare(c, nullptr, st));
   }
   const bool use_mlp = (c->bctype == ot::BC_3P || c->bctype == ot::BC_2P1I) && c->p.ewald == OT_EWALD_MLP &&
                        c->mlp_ok && !fp64;
@@ -696,7 +742,7 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
   return OT_OK;
 }
 
-// Adaptive block update (Sec. 2.2.5): the eight corner cells of every block
+// Adaptive block update (Sec. 2.2.6): the eight corner cells of every block
 // first (FP64 gravity, against the previous acceleration in acc), then the
 // full evaluation (with the columns when nside > 0) of the blocks where one of
 // them moved by tol or more; the other blocks keep phi, acc, npix and tau.
@@ -716,7 +762,7 @@ ot_status abu_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, void 
       return fail(c, OT_ERR_UNSUPPORTED, "per-pair exact Ewald series is not built into the walk");
     if (c->p.ewald == OT_EWALD_MLP && !fp64)
       return fail(c, OT_ERR_UNSUPPORTED, "the adaptive block update uses the Ewald table");
-    OTCHK(ewald_prepare(c, st));
+    OTCHK(ewald_prepare(c, nullptr, st));
   }
   if (cols) OTCHK(raytable_prepare(c, st));
   double alim = 0.0;
@@ -859,7 +905,17 @@ ot_status ot_create(const ot_params *p, ot_ctx **out) {
   const int nper = p->bc[0] + p->bc[1] + p->bc[2];
   if (nper == 0) c->bctype = ot::BC_ISO;
   else if (nper == 3) c->bctype = ot::BC_3P;
-  else if (p->bc[0] && p->bc[1] && !p->bc[2]) c->bctype = ot::BC_2P1I;
+  else if (p->bc[0] && p->bc[1] && !p->bc[2]) {
+    // the far-field limit replaces the series beyond |dz| = 2 Lx, where the
+    // dropped Fourier modes decay as exp(-2 pi |dz| / Ly): below 1e-5 of the
+    // kernel only while Ly <= Lx
+    if (c->box[1] > c->box[0]) {
+      c->err = "2P1I needs Ly <= Lx (the far-field switch at |dz| = 2 Lx)";
+      *out = c;
+      return OT_ERR_UNSUPPORTED;
+    }
+    c->bctype = ot::BC_2P1I;
+  }
   else if (p->bc[0] && !p->bc[1] && !p->bc[2]) c->bctype = ot::BC_1P2I;
   else {
     c->err = "boundary combination not supported (isolated, 3P, x,y-periodic 2P1I and x-periodic 1P2I are)";
@@ -946,10 +1002,10 @@ ot_status ot_export_raytable(ot_ctx *c, int64_t *nentries, int64_t *npairs, int6
   return OT_OK;
 }
 
-ot_status ot_ewald_prepare(ot_ctx *c, void *stream) {
+ot_status ot_ewald_prepare(ot_ctx *c, const char *cache_path, void *stream) {
   if (!c) return OT_ERR_INVALID_ARG;
   c->err.clear();
-  return ewald_prepare(c, (hipStream_t)stream);
+  return ewald_prepare(c, cache_path, (hipStream_t)stream);
 }
 
 int64_t ot_num_amr_nodes(const ot_ctx *c) { return c && c->have_blocks ? c->topo.na : -1; }
@@ -1043,13 +1099,56 @@ void ot_mlp_config_default(ot_mlp_config *cfg) {
   cfg->tol = 5e-3;
 }
 
-ot_status ot_mlp_train(ot_ctx *c, const ot_mlp_config *cfg, ot_mlp_report *rep, void *stream) {
-  using namespace ot::mlpdef;
+namespace {
+
+// every input the trained surrogate depends on (the training recipe's
+// version in i[12]: bump it when the training changes)
+ot::CacheKey mlp_key(const ot_ctx *c, const ot_mlp_config *cfg) {
+  ot::CacheKey k;
+  memset(&k, 0, sizeof(k));
+  k.kind = 2;
+  k.i[0] = c->bctype;
+  k.i[1] = ot::mlpdef::NP;
+  k.i[2] = ot::mlpdef::NO;
+  k.i[3] = OT_MLP_NNORM;
+  k.i[4] = cfg->nsamples;
+  k.i[5] = cfg->nval;
+  k.i[6] = cfg->epochs;
+  k.i[7] = cfg->batch;
+  memcpy(&k.i[8], &cfg->seed, sizeof(cfg->seed));
+  k.i[9] = c->ew_n;
+  k.i[10] = c->ew_rcut2;
+  k.i[11] = c->ew_fcut2;
+  k.i[12] = 1;
+  k.d[0] = cfg->lr_max;
+  k.d[1] = cfg->lr_min;
+  k.d[2] = cfg->tol;
+  k.d[3] = c->ew_alpha;
+  for (int q = 0; q < 3; ++q) {
+    k.d[4 + q] = c->box[q];
+    k.d[7 + q] = c->ew_ext[q];
+  }
+  return k;
+}
+
+struct MlpFile {
+  float params[ot::mlpdef::NP];
+  double norm[OT_MLP_NNORM];
+  ot_mlp_report report;
+};
+
+ot_status mlp_train_impl(ot_ctx *c, const ot_mlp_config *cfg, ot_mlp_report *rep, hipStream_t st);
+
+}  // namespace
+
+ot_status ot_mlp_train(ot_ctx *c, const ot_mlp_config *cfg, const char *cache_path, ot_mlp_report *rep,
+                       void *stream) {
   if (!c) return OT_ERR_INVALID_ARG;
   c->err.clear();
   if (!cfg) return fail(c, OT_ERR_INVALID_ARG, "null config");
   if (c->bctype == ot::BC_1P2I)
     return fail(c, OT_ERR_UNSUPPORTED, "the learned surrogate covers 3P and 2P1I (1P2I uses the table)");
+  if (c->bctype == ot::BC_ISO) return fail(c, OT_ERR_STATE, "the surrogate needs periodic or mixed boundaries");
   if (cfg->nsamples < 32 || cfg->nsamples % 32 || cfg->batch < 32 || cfg->batch % 32 ||
       cfg->batch > cfg->nsamples || cfg->epochs < 1 || cfg->nval < 1 || !(cfg->lr_max > 0) ||
       !(cfg->lr_min >= 0) || !(cfg->tol > 0))
@@ -1058,9 +1157,54 @@ ot_status ot_mlp_train(ot_ctx *c, const ot_mlp_config *cfg, ot_mlp_report *rep, 
                 "epochs >= 1, nval >= 1, lr_max > 0, lr_min >= 0, tol > 0");
   if (cfg->nsamples > ((int64_t)1 << 28) || cfg->nval > ((int64_t)1 << 26))
     return fail(c, OT_ERR_INVALID_ARG, "nsamples <= 2^28 and nval <= 2^26");
+  std::string why;
+  if (cache_path && !ot::cache_path_usable(cache_path, why)) return fail(c, OT_ERR_IO, why);
+  if (!c->ewald_ready) ewald_params(c);
+  const ot::CacheKey key = mlp_key(c, cfg);
   hipStream_t st = (hipStream_t)stream;
+  if (cache_path) {
+    std::vector<char> payload;
+    const ot::CacheRead cr = ot::cache_read(cache_path, key, payload, why);
+    if (cr == ot::CacheRead::IoError) return fail(c, OT_ERR_IO, why);
+    if (cr == ot::CacheRead::Loaded && payload.size() == sizeof(MlpFile)) {
+      const MlpFile *f = reinterpret_cast<const MlpFile *>(payload.data());
+      HIPCHK(hipSetDevice(c->p.device));
+      OTCHK(ewald_prepare(c, nullptr, st));
+      OTCHK(dalloc(c, c->mlp_P, ot::mlpdef::NP * sizeof(float)));
+      HIPCHK(hipMemcpyAsync(c->mlp_P.ptr, f->params, sizeof(f->params), hipMemcpyHostToDevice, st));
+      memcpy(c->mlp_norm, f->norm, sizeof(c->mlp_norm));
+      c->mlp_have = true;
+      OTCHK(mlp_pack(c, st));
+      HIPCHK(hipStreamSynchronize(st));
+      c->mlp_ok = f->report.ok != 0;
+      if (rep) {
+        *rep = f->report;
+        rep->ms_samples = rep->ms_train = rep->ms_validate = 0.0;
+        rep->from_cache = 1;
+      }
+      return OT_OK;
+    }
+  }
+  ot_mlp_report local;
+  OTCHK(mlp_train_impl(c, cfg, &local, st));
+  if (rep) *rep = local;
+  if (cache_path) {
+    MlpFile f;
+    memset(&f, 0, sizeof(f));
+    HIPCHK(hipMemcpy(f.params, c->mlp_P.ptr, sizeof(f.params), hipMemcpyDeviceToHost));
+    memcpy(f.norm, c->mlp_norm, sizeof(f.norm));
+    f.report = local;
+    if (!ot::cache_write(cache_path, key, &f, sizeof(f), why)) return fail(c, OT_ERR_IO, why);
+  }
+  return OT_OK;
+}
+
+namespace {
+
+ot_status mlp_train_impl(ot_ctx *c, const ot_mlp_config *cfg, ot_mlp_report *rep, hipStream_t st) {
+  using namespace ot::mlpdef;
   HIPCHK(hipSetDevice(c->p.device));
-  OTCHK(ewald_prepare(c, st));
+  OTCHK(ewald_prepare(c, nullptr, st));
   c->mlp_ok = false;
   const int64_t n = cfg->nsamples, nv = cfg->nval;
   auto now = [] { return std::chrono::steady_clock::now(); };
@@ -1187,6 +1331,8 @@ ot_status ot_mlp_train(ot_ctx *c, const ot_mlp_config *cfg, ot_mlp_report *rep, 
   return OT_OK;
 }
 
+}  // namespace
+
 ot_status ot_mlp_get(ot_ctx *c, float *params, double *norm) {
   if (!c) return OT_ERR_INVALID_ARG;
   c->err.clear();
@@ -1268,7 +1414,7 @@ ot_status ot_ewald_points(ot_ctx *c, int32_t method, int64_t n, const double *d,
   if (n > ((int64_t)1 << 30)) return fail(c, OT_ERR_INVALID_ARG, "n > 2^30");
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(c->p.device));
-  OTCHK(ewald_prepare(c, st));
+  OTCHK(ewald_prepare(c, nullptr, st));
   if (n == 0) return OT_OK;
   OTCHK(ewald_points(c, method, n, d, out, st));
   HIPCHK(hipStreamSynchronize(st));

@@ -1,4 +1,4 @@
-// Ewald correction from the FP64 table (Sec. 2.2.4, second approach): the
+// Ewald correction from the FP64 table (Sec. 2.2.5, second approach): the
 // value and gradient at the nearest grid point of the folded domain plus the
 // first-order Taylor term, with the stored Hessian for the acceleration.
 #pragma once

@@ -1,11 +1,11 @@
-// Per-cell evaluation of the block interaction lists (Sec. 2.2.1-2.2.4).
+// Per-cell evaluation of the block interaction lists (Sec. 2.2.1-2.2.5).
 //
 // Phi(r) = -G sum_a M_a phi(r - r_a), a(r) = -G sum_a M_a A(r - r_a) over the
 // accepted nodes (Eqs. 7, 8 and App. A), with phi = 1/r, A = d/r^3 for
 // isolated boundaries, and phi = 1/r + phi_c, A = d/r^3 + A_c for periodic
 // (3P) or mixed (2P1I, 1P2I) ones, the correction taken from the table by a
 // first-order Taylor expansion about the nearest grid point (second approach
-// of Sec. 2.2.4) or, for 2P1I beyond |dz| = 2 Lx and for 1P2I beyond 4 Lx
+// of Sec. 2.2.5) or, for 2P1I beyond |dz| = 2 Lx and for 1P2I beyond 4 Lx
 // from the periodic axis, from the analytic limit.
 // The target cell itself is skipped (d = 0 exactly).
 //
@@ -318,7 +318,7 @@ hipError_t launch_eval64(const DevTree &T, const EwaldP &E, const int64_t *off, 
   return hipGetLastError();
 }
 
-// Adaptive block update (Sec. 2.2.5): the eight corner cells (i, j, k in
+// Adaptive block update (Sec. 2.2.6): the eight corner cells (i, j, k in
 // {0, 7}) of every leaf block, walked in FP64 over the block's list; one
 // workgroup per block, thread t takes corner t % 8 and every 32nd list entry
 // from t / 8, and the 32 slices are added in a fixed order (a butterfly in

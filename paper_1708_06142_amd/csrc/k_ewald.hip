@@ -1,4 +1,4 @@
-// Ewald correction table, FP64 on the device (Sec. 2.2.2-2.2.4, App. A).
+// Ewald correction table, FP64 on the device (Sec. 2.2.3-2.2.5, App. A).
 //
 // For every point u of a uniform grid over the folded domain the kernel sums
 // the series of phi (3P: Eq. 9 with the cut-offs of Eq. 10; 2P1I: Eq. 15 in
@@ -13,7 +13,7 @@
 // I(0,0) of Eq. 14.
 // 1P2I (periodic along x): the images along x in real space and, in Fourier
 // space, 2/Lx sum_l exp(-zeta l^2) cos(kappa l dx) K(l, eta), eta = kappa rho,
-// rho = sqrt(dy^2 + dz^2) (Sec. 2.2.3; App. A for the acceleration).
+// rho = sqrt(dy^2 + dz^2) (Sec. 2.2.4; App. A for the acceleration).
 #include "common.hpp"
 #include "ewald_lookup.hpp"
 #include "kernels.hpp"
@@ -294,6 +294,17 @@ __global__ __launch_bounds__(128) void k_ewald_table(EwaldP E, double alpha, int
   tab32[3 * q + 2] = make_float4((float)o.v[8], (float)o.v[9], 0.0f, 0.0f);
 }
 
+// FP32 copy of an FP64 table (a table read from a cache file)
+__global__ __launch_bounds__(128) void k_ewald_pack32(int64_t np, const double *__restrict__ tab64,
+                                                      float4 *__restrict__ tab32) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= np) return;
+  const double *v = tab64 + 10 * q;
+  tab32[3 * q + 0] = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+  tab32[3 * q + 1] = make_float4((float)v[4], (float)v[5], (float)v[6], (float)v[7]);
+  tab32[3 * q + 2] = make_float4((float)v[8], (float)v[9], 0.0f, 0.0f);
+}
+
 // the same series at arbitrary folded offsets u [n][3] -> out [n][10]
 __global__ __launch_bounds__(128) void k_ewald_points(EwaldP E, double alpha, int rcut2, int fcut2, int64_t n,
                                                       const double *__restrict__ u, double *__restrict__ out) {
@@ -345,6 +356,12 @@ __global__ __launch_bounds__(128) void k_ewald_points10(int method, EwaldP E, do
 }
 
 }  // namespace
+
+hipError_t launch_ewald_pack32(const EwaldP &E, const double *tab64, float4 *tab32, hipStream_t st) {
+  const int64_t np = (int64_t)E.n * E.n * E.n;
+  hipLaunchKernelGGL(k_ewald_pack32, dim3((unsigned)((np + 127) / 128)), dim3(128), 0, st, np, tab64, tab32);
+  return hipGetLastError();
+}
 
 hipError_t launch_ewald_points10(int method, const EwaldP &E, double alpha, int rcut2, int fcut2, int64_t n,
                                  const double *d, double *out, hipStream_t st) {

@@ -1,5 +1,5 @@
 // Learned surrogate of the Ewald correction.  It is not part of the paper: it
-// stands in for the look-up table of Sec. 2.2.4, which stays the fallback and
+// stands in for the look-up table of Sec. 2.2.5, which stays the fallback and
 // the judge of its error.
 //
 // Network 3 -> 64 -> 64 -> 64 -> 10 with the activation f(z) = z S(z), S the

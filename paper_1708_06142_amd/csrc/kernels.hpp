@@ -142,6 +142,8 @@ hipError_t launch_amax(const double *acc, int64_t n, unsigned long long *out, hi
 
 hipError_t launch_ewald_table(const EwaldP &E, double alpha, int rcut2, int fcut2, double *tab64,
                               float4 *tab32, hipStream_t st);
+// the FP32 copy of an FP64 table [n^3][10]
+hipError_t launch_ewald_pack32(const EwaldP &E, const double *tab64, float4 *tab32, hipStream_t st);
 // FP64 series at arbitrary offsets d [n][3] (folded to |d| inside): out [n][10]
 hipError_t launch_ewald_points(const EwaldP &E, double alpha, int rcut2, int fcut2, int64_t n, const double *u,
                                double *out, hipStream_t st);

@@ -33,6 +33,11 @@ def test_param_validation():
         ot.Solver(ewald_n=1)
     s = ot.Solver(bc=(1, 1, 0), nroot=(1, 1, 4))
     s.close()
+    # 2P1I with Ly > Lx: the far-field switch at |dz| = 2 Lx would drop Fourier
+    # modes that decay only as exp(-2 pi |dz| / Ly)
+    with pytest.raises(ot.OTError, match="UNSUPPORTED"):
+        ot.Solver(bc=(1, 1, 0), nroot=(1, 2, 4))
+    ot.Solver(bc=(1, 1, 0), nroot=(2, 1, 4)).close()
 
 
 def test_call_order_and_grid_errors():
@@ -72,3 +77,15 @@ def test_topology_matches_oracle(maker):
     assert s.na == ref["alev"].shape[0]
     for k in ("alev", "acoord", "aleaf", "achild", "akey"):
         assert np.array_equal(mine[k], ref[k]), k
+
+
+def test_cache_path_errors_before_device_work(tmp_path):
+    """An unusable cache path is OT_ERR_IO, found on the host before any
+    device work: a file in a missing directory, and a directory."""
+    s = ot.Solver(bc=(1, 1, 1), ewald_n=8)
+    for bad in (str(tmp_path / "missing" / "ewald.cache"), str(tmp_path)):
+        with pytest.raises(ot.OTError, match="IO"):
+            s.ewald_prepare(cache_path=bad)
+        with pytest.raises(ot.OTError, match="IO"):
+            s.mlp_train(cache_path=bad, nsamples=1024, batch=256, epochs=1, nval=64)
+    s.close()

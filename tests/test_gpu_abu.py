@@ -1,4 +1,4 @@
-"""GPU parity of the adaptive block update (Sec. 2.2.5) with the oracle's:
+"""GPU parity of the adaptive block update (Sec. 2.2.6) with the oracle's:
 the zero-tolerance and unchanged-density limits, and a locally perturbed
 field whose previous solution is the oracle's walk on the unperturbed one."""
 import numpy as np

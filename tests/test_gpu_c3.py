@@ -55,12 +55,16 @@ def test_c3_sampled_parity(c3):
 
 
 def test_c3_tree_vs_direct(c3):
+    """FP32 walk (BH theta 0.5, 64^3 table) against the oracle's direct sum
+    over all other cells with the same table, on 128 seeded cells and the 32
+    of largest |a|: the metric's e_a,max and e_Phi,max <= 1e-3."""
     g = c3
     p, a, st, _ = solve(g, False, theta=0.5, ewald_n=64)
-    tg = np.sort(np.random.default_rng(6).choice(g.ncells, 96, replace=False))
+    top = np.argsort((a ** 2).sum(0))[-32:]
+    tg = np.unique(np.concatenate([np.random.default_rng(6).choice(g.ncells, 128, replace=False), top]))
     pd, ad = oracle.Tree(g, ewald="table", ew_n=64).direct(tg)
     amax = np.sqrt((ad ** 2).sum(0)).max()
     ea = np.sqrt(((a[:, tg] - ad) ** 2).sum(0)) / amax
     ep = np.abs(p[tg] - pd) / np.abs(pd).max()
     print(f"C3 tree (BH 0.5) vs direct: e_a max {ea.max():.3e}, e_phi max (of max |Phi|) {ep.max():.3e}")
-    assert ea.max() < 5e-3 and ep.max() < 1e-3
+    assert ea.max() <= 1e-3 and ep.max() <= 1e-3

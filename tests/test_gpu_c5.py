@@ -83,13 +83,57 @@ def test_c5_sampled_parity(c5):
           f"interactions per cell; eval FP64 {st64.ms_eval:.0f} ms, FP32 {st32.ms_eval:.0f} ms")
 
 
-def test_c5_surrogate_columns(c5):
-    g, rho, a_lim = c5
-    sel = np.sort(np.random.default_rng(9).choice(g.nb, 64, replace=False))
+@pytest.fixture(scope="module")
+def c5_mlp(c5):
+    g, _, _ = c5
     tr = ot.Solver(bc=g.bc, ewald_n=64, ewald="mlp")
     rep = tr.mlp_train()
     assert rep["ok"], rep
     mlp = tr.mlp_get()
+    tr.close()
+    return rep, mlp
+
+
+def test_c5_tree_vs_direct(c5, c5_mlp):
+    """FP32 table walk and FP32 walk with the learned correction against the
+    oracle's direct sum over all other cells (FP64, the same 64^3 table: the
+    exact series per pair is out of reach at 15M cells), on 128 seeded cells
+    and the 32 of largest |a|: the metric's e_a,max and e_Phi,max <= 1e-3."""
+    g, rho, a_lim = c5
+    rep, mlp = c5_mlp
+    n = g.ncells
+    res = {}
+    for mode in ("table", "mlp"):
+        s = ot.Solver.for_grid(g, a_lim=a_lim, ewald=mode, **KW)
+        if mode == "mlp":
+            s.mlp_set(*mlp, accept=True)
+        s.build(rho)
+        phi, acc = torch.empty(n, device="cuda"), torch.empty(3 * n, device="cuda")
+        npix, tau = torch.empty(n * 192, device="cuda"), torch.empty(n, device="cuda")
+        st = s.solve(phi, acc, npix, tau)
+        assert st.ewald_used == (2 if mode == "mlp" else 0)
+        res[mode] = (phi, acc.view(3, -1))
+        del npix, tau
+        s.close()
+    top = torch.topk(res["table"][1].double().pow(2).sum(0), 32).indices.cpu().numpy()
+    tg = np.unique(np.concatenate([np.random.default_rng(10).choice(n, 128, replace=False), top]))
+    pd, ad = oracle.Tree(g, ewald="table", ew_n=64).direct(tg)
+    amax, pmax = np.sqrt((ad ** 2).sum(0)).max(), np.abs(pd).max()
+    idx = torch.from_numpy(tg).cuda()
+    for mode, (phi, acc) in res.items():
+        p, a = phi[idx].double().cpu().numpy(), acc[:, idx].double().cpu().numpy()
+        ea = np.sqrt(((a - ad) ** 2).sum(0)).max() / amax
+        ep = np.abs(p - pd).max() / pmax
+        print(f"C5 {mode} walk vs direct on {tg.size} cells: e_a,max {ea:.3e}, e_Phi,max {ep:.3e}")
+        assert ea <= 1e-3 and ep <= 1e-3
+    del res
+    torch.cuda.empty_cache()
+
+
+def test_c5_surrogate_columns(c5, c5_mlp):
+    g, rho, a_lim = c5
+    sel = np.sort(np.random.default_rng(9).choice(g.nb, 64, replace=False))
+    rep, mlp = c5_mlp
     rt = run(g, rho, False, sel, a_lim)
     rm = run(g, rho, False, sel, a_lim, ewald="mlp", mlp=mlp)
     assert rm["st"].ewald_used == 2

@@ -101,6 +101,11 @@ def test_fp32_kahan_walk(name):
 
 
 def test_tree_vs_direct_sphere():
+    """The voxel sphere against the direct sum over every cell.  BH at the
+    paper's theta = 0.5 leaves e_a,max at 2.9e-3 (the maximum sits at the
+    sphere's centre, where opposing contributions cancel); the metric's
+    e_a,max <= 1e-3 and e_Phi,max <= 1e-3 are reached at theta = 0.3, the
+    setting reported for this configuration."""
     g = workloads.c1_sphere()
     pd, ad = oracle.Tree(g).direct()
     amax = np.sqrt((ad ** 2).sum(0)).max()
@@ -109,6 +114,11 @@ def test_tree_vs_direct_sphere():
         ea = np.sqrt(((a - ad) ** 2).sum(0)) / amax
         assert ea.max() < 3.5e-3 and np.quantile(ea, 0.99) < 2e-3
         assert np.abs(p / pd - 1).max() < 1e-3
+        p, a, _, _ = gpu(g, fp64=fp64, theta=0.3)
+        ea = np.sqrt(((a - ad) ** 2).sum(0)) / amax
+        ep = np.abs(p - pd) / np.abs(pd).max()
+        print(f"C1 theta 0.3 {'FP64' if fp64 else 'FP32'}: e_a,max {ea.max():.3e}, e_Phi,max {ep.max():.3e}")
+        assert ea.max() <= 1e-3 and ep.max() <= 1e-3
 
 
 def test_determinism():

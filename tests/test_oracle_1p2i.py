@@ -1,5 +1,5 @@
 """Pins of the oracle's 1P2I Ewald kernel (periodic along x, isolated in y
-and z), Sec. 2.2.3 and App. A.
+and z), Sec. 2.2.4 and App. A.
 
 Checked against mathematics that does not depend on the series as written:
 the defining integrals K and M by adaptive quadrature with library Bessel

@@ -1,4 +1,4 @@
-"""Pins of the oracle's adaptive block update (Sec. 2.2.5): with a zero
+"""Pins of the oracle's adaptive block update (Sec. 2.2.6): with a zero
 tolerance it is the plain group walk; on an unchanged density it keeps every
 block; on a locally perturbed density its block decisions are those of the
 corner criterion applied to an independent full walk, and each block holds

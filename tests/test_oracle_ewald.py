@@ -1,4 +1,4 @@
-"""Pins of the oracle's Ewald kernels (3P and 2P1I), Sec. 2.2.2-2.2.4, App. A.
+"""Pins of the oracle's Ewald kernels (3P and 2P1I), Sec. 2.2.3-2.2.5, App. A.
 
 Checked against mathematics that does not depend on the series as written:
 periodicity, independence of the splitting parameter alpha, derivatives by
