@@ -119,9 +119,11 @@ typedef struct {
   int64_t list_hist[32];   /* blocks whose list length L has 2^k <= L < 2^(k+1) */
   int64_t n_mlp_evals;     /* network evaluations of the surrogate walk
                               (cell groups x list entries); 0 without it      */
-  double ms_gravity;       /* device time of the surrogate gravity walk       */
+  double ms_gravity;       /* device time of the surrogate gravity walk; 0 when
+                              the column walk carries it (maps in memory)     */
   double ms_columns;       /* device time of the column walk (with the table,
-                              it computes the gravity too)                    */
+                              or with the surrogate and maps in memory, it
+                              computes the gravity too)                       */
 } ot_stats;
 
 void ot_params_default(ot_params *p);

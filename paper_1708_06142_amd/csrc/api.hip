@@ -692,12 +692,21 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
   ot::DevTree T = dev_tree(c);
   ot::EwaldP E = ewald_desc(c);
   int wg_per_cu = 0;
-  if (use_mlp)
+  // with the surrogate and maps too large for LDS, one kernel carries both
+  // the surrogate's gravity and the columns
+  const bool fused = use_mlp && cols && ot::cols_lds_cpw(npix_of(c), false, col_params(c).nthr) == 0;
+  if (fused) OTCHK(dalloc(c, c->llat, (size_t)c->list_cap * sizeof(int32_t)));
+  if (use_mlp && !fused)
     // gravity from the surrogate walk (the columns, if any, follow without gravity)
     HIPCHK(ot::launch_eval_mlp(T, E, c->mlp_pk.ptr, P<int64_t>(c->loff), P<double4>(c->lrec), (float *)phi,
                                (float *)acc, c->p.G, mlp_tmax(c), cell_size_max(c), st));
   HIPCHK(hipEventRecord(c->ev[4], st));
-  if (cols) {
+  if (fused) {
+    HIPCHK(ot::launch_eval_cols_mlp(T, E, col_params(c), c->mlp_pk.ptr, P<int64_t>(c->loff), P<double4>(c->lrec),
+                                    P<int32_t>(c->lid), P<double>(c->lh), P<int32_t>(c->llat), (float *)phi,
+                                    (float *)acc, (float *)npix, (float *)tau,
+                                    c->p.G, mlp_tmax(c), cell_size_max(c), &wg_per_cu, st));
+  } else if (cols) {
     // maps in LDS when 128 or more cells' maps fit there, else in npix
     const ot::ColP C = col_params(c);
     HIPCHK(ot::launch_eval_cols(fp64, T, E, C, P<int64_t>(c->loff), P<double4>(c->lrec), P<int32_t>(c->lid),
@@ -731,7 +740,7 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
     stats->ewald_used = use_mlp ? OT_EWALD_MLP : OT_EWALD_TABLE;
     stats->eval_wg_per_cu = wg_per_cu;
     if (use_mlp) {
-      stats->ms_gravity = elapsed(c->ev[1], c->ev[4]);
+      stats->ms_gravity = fused ? 0.0 : elapsed(c->ev[1], c->ev[4]);
       const double tmax = mlp_tmax(c);
       for (int64_t b = 0; b < c->topo.nb; ++b)
         stats->n_mlp_evals += (int64_t)ot::mlp_groups(ot::size_at(c->p.root_size, c->topo.blev[b]) / 8.0, tmax) *
@@ -1441,7 +1450,7 @@ void ot_destroy(ot_ctx *c) {
   if (c->dev_bytes || c->ev[0]) (void)hipSetDevice(c->p.device);
   DevBuf *all[] = {&c->alev, &c->acoord, &c->achild0, &c->aleaf, &c->blev,   &c->bcoord,
                    &c->bamr, &c->amc,    &c->aS,      &c->btmc,  &c->cm,     &c->flag,
-                   &c->lcount, &c->lnodes, &c->loff, &c->lrec,    &c->lid,   &c->lscratch, &c->tab64,
+                   &c->lcount, &c->lnodes, &c->llat, &c->loff, &c->lrec,    &c->lid,   &c->lscratch, &c->tab64,
                    &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_rows, &c->rt_ent, &c->rt_rows8, &c->rt_quad64, &c->mpe_a, &c->mpe_b, &c->mpe_pnode, &c->mpe_pblock, &c->mpe_poff, &c->mpe_part, &c->abu_flag, &c->abu_blist, &c->rt_lut,
                    &c->rt_thr, &c->lh, &c->mlp_P, &c->mlp_pk, &c->mlp_part, &c->mlp_lossp,
                    &c->mlp_loss};

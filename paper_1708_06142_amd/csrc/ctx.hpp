@@ -58,7 +58,7 @@ struct ot_ctx {
   int64_t mpe_npairs = 0;
   ot::DevBuf abu_flag, abu_blist;  // adaptive block update: per-block flags, updated blocks
   // interaction lists
-  ot::DevBuf lcount, lnodes, loff, lrec, lid, lscratch;
+  ot::DevBuf lcount, lnodes, loff, lrec, lid, lscratch, llat;
   int64_t list_cap = 0;
   int64_t scratch_per_wg = 0;
   int list_grid = 0;

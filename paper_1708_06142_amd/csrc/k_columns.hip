@@ -24,6 +24,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "mlp_infer.hpp"
 
 namespace ot {
 
@@ -696,6 +697,288 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   tau[o] = (Real)(-log(se / (double)C.npix));
 }
 
+// Lattice row of every list entry for the walk with the learned surrogate:
+// the row of the table that a cell of the target block's own size at a
+// lattice offset takes for the block's first cell (the walk adds each cell's
+// own index), or -1 (not such a cell, offsets of the block's cells outside
+// the table, or a periodic image possible).  One workgroup per leaf block.
+template <int BC>
+__global__ __launch_bounds__(256) void k_lattice_index(DevTree T, EwaldP E, ColP C, const int64_t *__restrict__ off,
+                                                      const double4 *__restrict__ rec,
+                                                      const int32_t *__restrict__ ids,
+                                                      const double *__restrict__ lh, int32_t *__restrict__ llat) {
+  const int64_t b = blockIdx.x;
+  const double h = size_at(T.root_size, T.blev[b]) / 8.0;
+  const double inv_h = 1.0 / h;  // exact: h is a power of two on a dyadic grid
+  const double b0[3] = {centre_coord(T.org[0], 8 * (int64_t)T.bcoord[3 * b], h),
+                        centre_coord(T.org[1], 8 * (int64_t)T.bcoord[3 * b + 1], h),
+                        centre_coord(T.org[2], 8 * (int64_t)T.bcoord[3 * b + 2], h)};
+  const int64_t cell0 = T.na + 72 * T.nb;
+  const int lat_w = 2 * C.lat_r + 1;
+  auto lat_axis = [&](double d0, int ax) {
+    const bool per = BC == 1 || (BC == 2 && ax < 2) || (BC == 3 && ax == 0);
+    if (per && !(d0 > -0.5 * E.L[ax] + h && d0 + 8.0 * h < 0.5 * E.L[ax])) return 1 << 20;
+    const double n0 = d0 * inv_h;
+    return fabs(n0) < (double)(1 << 20) && n0 == rint(n0) ? (int)n0 : 1 << 20;
+  };
+  const int64_t start = off[b], n = off[b + 1] - start;
+  for (int64_t q = threadIdx.x; q < n; q += 256) {
+    int32_t v = -1;
+    if (C.lat_r > 0 && ids[start + q] >= cell0 && lh[start + q] == h) {
+      const double4 r = rec[start + q];
+      const int nx = lat_axis(b0[0] - r.x, 0), ny = lat_axis(b0[1] - r.y, 1), nz = lat_axis(b0[2] - r.z, 2);
+      const int lo = -C.lat_r, hi = C.lat_r - 7;
+      if (nx >= lo && nx <= hi && ny >= lo && ny <= hi && nz >= lo && nz <= hi)
+        v = C.lat0 + ((nz + C.lat_r) * lat_w + (ny + C.lat_r)) * lat_w + (nx + C.lat_r);
+    }
+    llat[start + q] = v;
+  }
+}
+
+// FP32 column walk with the learned surrogate's gravity, maps in memory (the
+// 192-pixel walk): one workgroup of 512 threads per leaf block, thread t owns
+// cell t, the block's list streams through LDS once.  Per chunk of list
+// entries each wave first runs its batch of 32 (cell group, entry) pairs
+// through the network on the matrix cores (the groups and the Taylor step of
+// the surrogate walk: the ten channels at the group centre, unfolded, left in
+// LDS), then every thread takes, for each entry of the chunk, the gravity
+// from its group's channels and the column binning and map update of the
+// column walk.  Waves in their network phase and waves waiting on map
+// traffic share each compute unit.
+// list entries per LDS tile: the column walk's, so that the rows of more than
+// four pixels finish at the same points of the list and the maps agree bit
+// for bit with the table walk's
+constexpr int FTILE = TILE;
+
+template <int BC>
+__global__ __launch_bounds__(512) void k_eval_cols_mlp(DevTree T, EwaldP E, ColP C, const void *__restrict__ pk,
+                                                       const int64_t *__restrict__ off,
+                                                       const double4 *__restrict__ rec,
+                                                       const int32_t *__restrict__ llat,
+                                                       const double *__restrict__ lh, float *__restrict__ phi,
+                                                       float *__restrict__ acc, float *__restrict__ npix,
+                                                       float *__restrict__ tau, float negG, double tmax) {
+  using namespace mlpdef;
+  __shared__ uint8_t lut[LUT_BYTES];
+  __shared__ f16x8 wl[64 * NPK];
+  __shared__ ColRec tile[FTILE];
+  extern __shared__ __align__(16) unsigned char smem[];
+  double *thr = reinterpret_cast<double *>(smem);
+  float *slot = reinterpret_cast<float *>(thr + ((C.nthr + 1) & ~1));  // 16-byte aligned
+  const int64_t b = blockIdx.x;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, m = l & 31;
+  const int ci = tid, ii = ci & 7, jj = (ci >> 3) & 7, kk = ci >> 6;
+  const int64_t ncell = T.nb * 512;
+  const double h = size_at(T.root_size, T.blev[b]) / 8.0;
+  const int64_t bx = T.bcoord[3 * b], by = T.bcoord[3 * b + 1], bz = T.bcoord[3 * b + 2];
+  const double cx = centre_coord(T.org[0], 8 * bx + ii, h);
+  const double cy = centre_coord(T.org[1], 8 * by + jj, h);
+  const double cz = centre_coord(T.org[2], 8 * bz + kk, h);
+  for (int q = tid; q < LUT_BYTES; q += 512) lut[q] = C.lut[q];
+  for (int q = tid; q < C.nthr; q += 512) thr[q] = C.thr[q];
+  const mlpinf::Ops W = mlpinf::load_ops(pk, wl);  // ends with a barrier
+  const f16x8 one = mlpinf::ones();
+  // this cell's map in the output (a wave's 64 cells are adjacent)
+  char *const mcell = reinterpret_cast<char *>(npix + b * C.npix * 512 + ci);
+  constexpr int lmap = 11;  // pixel p of the cell at byte offset p << 11 (512 floats per pixel)
+  for (int p = 0; p < C.npix; ++p) *reinterpret_cast<float *>(mcell + (p << lmap)) = 0.0f;
+  const float inv_omega = (float)(1.0 / C.omega);
+  // groups of the surrogate walk
+  const int gl = mlp_group_level(h, tmax);
+  const int gs = 1 << gl, ga = 8 >> gl, G = ga * ga * ga;
+  const int P = taylor_pairs(gl), CH = P / G;
+  const double gsz = h * (double)gs;
+  auto gcentre = [&](int g, double c[3]) {
+    const int gx = g % ga, gy = (g / ga) % ga, gz = g / (ga * ga);
+    c[0] = centre_coord(T.org[0], ga * bx + gx, gsz);
+    c[1] = centre_coord(T.org[1], ga * by + gy, gsz);
+    c[2] = centre_coord(T.org[2], ga * bz + gz, gsz);
+  };
+  const int mg = (ii >> gl) + ga * ((jj >> gl) + ga * (kk >> gl));
+  float dlx, dly, dlz;
+  {
+    double gc[3];
+    gcentre(mg, gc);
+    dlx = (float)(cx - gc[0]);
+    dly = (float)(cy - gc[1]);
+    dlz = (float)(cz - gc[2]);
+  }
+  const float fa = (float)E.far_phi_a, fb = (float)E.far_phi_b, faz = (float)E.far_az;
+  float ks = 0.f, kc = 0.f, ax = 0.f, ay = 0.f, az = 0.f;
+  // Cells of this block's size at lattice offsets take their table row from
+  // the lattice rows (their entries' rows for the block's first cell come
+  // with the list, llat >= 0), as in the column walk with its maps in LDS
+  const int lat_w = 2 * C.lat_r + 1;
+  const int lat_lane = (kk * lat_w + jj) * lat_w + ii;
+  // rows of more than four pixels finish from a per-thread queue at the
+  // tile's end (as in the column walk)
+  constexpr int DQ = 4;
+  uint32_t dq_code[DQ] = {};
+  float dq_base[DQ] = {};
+  int dq_n = 0;
+  auto long_row = [&](uint32_t code, float base) {
+    const int o0 = (int)(code & 0x3ffffffu), o1 = o0 + (int)(code >> 26);
+    const float base24 = base * (1.0f / 16777216.0f);
+    for (int o = o0 + 4; o < o1; o += 2) {
+      const uint32_t v = C.ent[o], u = o + 1 < o1 ? C.ent[o + 1] : 0u;
+      float *const qv = reinterpret_cast<float *>(mcell + ((v >> 24) << lmap));
+      *qv += (float)(v & 0xffffffu) * base24;
+      float *const qu = reinterpret_cast<float *>(mcell + ((u >> 24) << lmap));
+      *qu += (float)(u & 0xffffffu) * base24;
+    }
+  };
+  const int64_t start = off[b], n = off[b + 1] - start;
+  for (int64_t t0 = 0; t0 < n; t0 += FTILE) {
+    const int mt = (int)(n - t0 < FTILE ? n - t0 : FTILE);
+    __syncthreads();  // the previous tile is consumed
+    if (tid < mt) {
+      const double4 rq = rec[start + t0 + tid];
+      const double hn = lh[start + t0 + tid];
+      const double rh = C.req * hn;  // radius of the equal-volume sphere
+      tile[tid].x = rq.x;
+      tile[tid].y = rq.y;
+      tile[tid].z = rq.z;
+      tile[tid].w = rq.w;
+      // rhs carries the lattice flag in its sign
+      const int32_t li = llat[start + t0 + tid];
+      const bool lat = li >= 0;
+      if (lat) tile[tid].lat = li;
+      else tile[tid].rh2 = rh * rh;
+      tile[tid].rhs = (lat ? -1.0f : 1.0f) * ((float)rh * C.lut_ps);
+      tile[tid].m = (float)rq.w;
+    }
+    float tx = 0.f, ty = 0.f, tz = 0.f;
+    for (int j0 = 0; j0 < mt; j0 += CH) {
+      __syncthreads();  // tile loaded; the previous chunk's channels are consumed
+      // network phase: pairs 32 (w + 8 q) + m, entry p / G, group p % G;
+      // entries past the tile's end repeat its last (their channels are never read)
+      for (int q = 0; q < P / 256; ++q) {
+        const int p = 32 * (w + 8 * q) + m;
+        const int j = j0 + p / G < mt ? j0 + p / G : mt - 1;
+        double gc[3];
+        gcentre(p % G, gc);
+        const ColRec &r = tile[j];
+        const double ex = wrap_axis(gc[0] - r.x, E.L[0], E.inv_L[0], 1);
+        const double ey = wrap_axis(gc[1] - r.y, E.L[1], E.inv_L[1], 1);
+        const double ez = wrap_axis(gc[2] - r.z, E.L[2], E.inv_L[2], BC == 1);
+        const float dx = (float)ex, dy = (float)ey, dz = (float)ez;
+        float y[NO];
+        mlpinf::forward(W, mlpinf::input(fabsf(dx), fabsf(dy), fabsf(dz)), one, y);
+        const float sx = ex < 0 ? -1.f : 1.f, sy = ey < 0 ? -1.f : 1.f, sz = ez < 0 ? -1.f : 1.f;
+        const bool far = BC == 2 && fabs(ez) > E.zfar;
+        float4 *o = reinterpret_cast<float4 *>(slot + TSLOT * (32 * (w + 8 * q) + m));
+        if (l < 32) {
+          o[0] = make_float4(y[0], sx * y[1], sy * y[2], sz * y[3]);
+          o[1] = make_float4(y[4], y[5], y[6], sx * sy * y[7]);
+        } else {
+          o[2] = make_float4(sx * sz * y[8], sy * sz * y[9], dx, dy);
+          o[3] = make_float4(dz, far ? 1.f : 0.f, 0.f, 0.f);
+        }
+      }
+      __syncthreads();
+      // cell phase
+      const int mc = mt - j0 < CH ? mt - j0 : CH;
+      for (int j = 0; j < mc; ++j) {
+        const ColRec r = tile[j0 + j];
+        // gravity: Newtonian part and the Taylor step from the group's channels
+        {
+          const float4 *o = reinterpret_cast<const float4 *>(slot + TSLOT * (j * G + mg));
+          const float4 v0 = o[0], v1 = o[1], v2 = o[2], v3 = o[3];
+          const float dx = v2.z + dlx, dy = v2.w + dly, dz = v3.x + dlz;
+          const float r2 = dx * dx + dy * dy + dz * dz;
+          const bool valid = r2 != 0.0f;
+          const float inv = valid ? __builtin_amdgcn_rsqf(fmaxf(r2, 1e-30f)) : 0.0f;
+          const float inv3 = inv * inv * inv;
+          float ph, A0, A1, A2;
+          if (BC == 2 && v3.y != 0.0f) {
+            ph = fa * fabsf(dz) + fb;
+            A0 = 0.0f;
+            A1 = 0.0f;
+            A2 = dz < 0 ? -faz : faz;
+          } else {
+            ph = inv + (v0.x - (v0.y * dlx + v0.z * dly + v0.w * dlz));
+            A0 = dx * inv3 + (v0.y - (v1.x * dlx + v1.w * dly + v2.x * dlz));
+            A1 = dy * inv3 + (v0.z - (v1.w * dlx + v1.y * dly + v2.y * dlz));
+            A2 = dz * inv3 + (v0.w - (v2.x * dlx + v2.y * dly + v1.z * dlz));
+          }
+          const float mw = valid ? r.m : 0.0f;
+          const float yk = mw * ph - kc, tk = ks + yk;
+          kc = (tk - ks) - yk;
+          ks = tk;
+          tx += mw * A0;
+          ty += mw * A1;
+          tz += mw * A2;
+        }
+        // columns: the minimum-image offset of the cell, its direction bins
+        // and the table row's four-slot record
+        double qx = cx - r.x, qy = cy - r.y, qz = cz - r.z;
+        wrap3<BC>(E, qx, qy, qz);
+        const double q2 = qx * qx + qy * qy + qz * qz;
+        const bool col = q2 != 0.0 && q2 <= C.max_dist2;
+        const float q2f = (float)q2;
+        const float rd = __builtin_amdgcn_rsqf(fmaxf(q2f, 1e-30f));
+        // (the record is the workgroup's: a uniform branch)
+        int e;
+        if (__builtin_amdgcn_readfirstlane(r.rhs < 0.0f ? 1 : 0))
+          e = r.lat + lat_lane;
+        else
+          e = col ? table_row(C, thr, lut, qx, qy, qz, (float)qx, (float)qy, (float)qz, q2, q2f, rd, r.rh2, r.rhs) : 0;
+        const char *const rq8 = reinterpret_cast<const char *>(C.rows8) + ((uint32_t)e << 5);
+        const uint4 pq = *reinterpret_cast<const uint4 *>(rq8);
+        const uint4 wq = *reinterpret_cast<const uint4 *>(rq8 + 16);
+        const float mr2 = (col ? r.m : 0.0f) * rd * rd;  // M / r^2
+        const float base = mr2 * inv_omega;
+        const float w0 = __uint_as_float(wq.x), w1 = __uint_as_float(wq.y), w2 = __uint_as_float(wq.z),
+                    w3 = __uint_as_float(wq.w);
+        float *const p0 = reinterpret_cast<float *>(mcell + (pq.x << lmap));
+        float *const p1 = reinterpret_cast<float *>(mcell + (pq.y << lmap));
+        float *const p2 = reinterpret_cast<float *>(mcell + (pq.z << lmap));
+        float *const p3 = reinterpret_cast<float *>(mcell + (pq.w << lmap));
+        // the padding slots (weight 0) are skipped: they would cost traffic
+        const bool u1 = w1 != 0.0f, u2 = w2 != 0.0f, u3 = w3 != 0.0f;
+        float v1 = 0.f, v2 = 0.f, v3 = 0.f;
+        const float v0 = *p0;
+        if (u1) v1 = *p1;
+        if (u2) v2 = *p2;
+        if (u3) v3 = *p3;
+        *p0 = fmaf(w0, base, v0);
+        if (u1) *p1 = fmaf(w1, base, v1);
+        if (u2) *p2 = fmaf(w2, base, v2);
+        if (u3) *p3 = fmaf(w3, base, v3);
+        if ((int)pq.x < 0 && col) {
+          const uint32_t cnt = (pq.x >> 23) & 63u;
+          const uint32_t o0 = (pq.y >> 23) | ((pq.z >> 23) << 9) | ((pq.w >> 23) << 18);
+          if (dq_n == DQ) {
+            long_row(dq_code[DQ - 1], dq_base[DQ - 1]);
+            --dq_n;
+          }
+          for (int k = DQ - 1; k > 0; --k) {
+            dq_code[k] = dq_code[k - 1];
+            dq_base[k] = dq_base[k - 1];
+          }
+          dq_code[0] = (cnt << 26) | o0;
+          dq_base[0] = base;
+          ++dq_n;
+        }
+      }
+    }
+    for (int k = 0; k < DQ; ++k)
+      if (k < dq_n) long_row(dq_code[k], dq_base[k]);
+    dq_n = 0;
+    ax += tx;
+    ay += ty;
+    az += tz;
+  }
+  const int64_t o = b * 512 + ci;
+  phi[o] = negG * (ks - kc);
+  acc[o] = negG * ax;
+  acc[ncell + o] = negG * ay;
+  acc[2 * ncell + o] = negG * az;
+  double se = 0.0;
+  for (int p = 0; p < C.npix; ++p) se += exp(-C.kappa * (double)*reinterpret_cast<const float *>(mcell + (p << lmap)));
+  tau[o] = (float)(-log(se / (double)C.npix));
+}
+
 // table rows of arbitrary offsets d = cell - node with the walk's binning
 // (thresholds and look-up tables in LDS as in the walk); -1 for d = 0
 __global__ __launch_bounds__(256) void k_column_bins(ColP C, int64_t n, const double *__restrict__ d,
@@ -853,6 +1136,30 @@ int cols_lds_cpw(int npix, bool fp64, int nthr) {
   for (int cpw : {256, 128})
     if (cols_smem_bytes(npix, cpw, fp64, nthr) <= 65536) return cpw;
   return 0;
+}
+
+hipError_t launch_eval_cols_mlp(const DevTree &T, const EwaldP &E, const ColP &C, const void *pk, const int64_t *off,
+                                const double4 *rec, const int32_t *ids, const double *lh, int32_t *llat, float *phi,
+                                float *acc, float *npix, float *tau, double G, double tmax, double h_max,
+                                int *wg_per_cu, hipStream_t st) {
+  const size_t sm = (size_t)((C.nthr + 1) & ~1) * sizeof(double) +
+                    (size_t)taylor_pairs(mlp_group_level(h_max, tmax)) * TSLOT * sizeof(float);
+  dim3 grid((unsigned)T.nb), blk(512);
+  const float ng = (float)(-G);
+#define OT_LAUNCH_CM(B)                                                                                    \
+  do {                                                                                                     \
+    if (wg_per_cu &&                                                                                       \
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, k_eval_cols_mlp<B>, 512, sm) != hipSuccess) \
+      *wg_per_cu = 0;                                                                                      \
+    hipLaunchKernelGGL((k_lattice_index<B>), grid, dim3(256), 0, st, T, E, C, off, rec, ids, lh, llat);         \
+    hipLaunchKernelGGL((k_eval_cols_mlp<B>), grid, blk, sm, st, T, E, C, pk, off, rec, llat, lh, phi, acc, npix, \
+                       tau, ng, tmax);                                                                     \
+  } while (0)
+  if (E.bctype == 1) OT_LAUNCH_CM(1);
+  else if (E.bctype == 2) OT_LAUNCH_CM(2);
+  else return hipErrorInvalidValue;
+#undef OT_LAUNCH_CM
+  return hipGetLastError();
 }
 
 hipError_t launch_raytable_pack(const RayTableP &P, const int64_t *off, const uint16_t *pix, const double *w,

@@ -32,6 +32,7 @@
 #include "common.hpp"
 #include "ewald_lookup.hpp"
 #include "kernels.hpp"
+#include "mlp_infer.hpp"
 
 namespace ot {
 
@@ -39,8 +40,6 @@ namespace {
 
 using namespace mlpdef;
 
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ inline uint64_t splitmix64(uint64_t x) {
   x += 0x9E3779B97F4A7C15ull;
@@ -54,11 +53,6 @@ __device__ inline double uniform01(uint64_t seed, uint64_t i) {
   return (double)(splitmix64(splitmix64(seed) + i) >> 11) * 0x1.0p-53;
 }
 
-__device__ inline float gate_t(float z) { return fminf(fmaxf(fmaf(z, 1.0f / 6.0f, 0.5f), 0.0f), 1.0f); }
-__device__ inline float act(float z) {
-  const float t = gate_t(z);
-  return z * (t * t * fmaf(t, -2.0f, 3.0f));
-}
 // f'(z) = S(z) + z t (1 - t)
 __device__ inline float dact(float z) {
   const float t = gate_t(z);
@@ -346,100 +340,6 @@ __global__ void k_mlp_pack(const float *__restrict__ P, MlpNorm N, f16x8 *__rest
 
 }  // namespace
 
-// ------------------------------------------------------------- inference
-namespace mlpinf {
-
-__device__ inline f32x16 mma(f16x8 a, f16x8 b, f32x16 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
-}
-
-// The packed operands live in LDS (27.6 KB per workgroup); each lane reads
-// its 16 bytes of an operand just before the instruction that needs it, which
-// keeps them out of the registers the products and activations need.
-struct Ops {
-  const f16x8 *lds;  // [NPK][64]
-  int lane;          // this lane's slot, hidden from the compiler per call (see forward)
-  __device__ f16x8 operator[](int i) const { return lds[64 * i + lane]; }
-};
-
-// all threads of the workgroup copy the operands into lds (then a barrier)
-__device__ inline Ops load_ops(const void *pk, f16x8 *lds) {
-  const f16x8 *p = reinterpret_cast<const f16x8 *>(pk);
-  for (int i = threadIdx.x; i < 64 * NPK; i += blockDim.x) lds[i] = p[i];
-  __syncthreads();
-  return Ops{lds, (int)(threadIdx.x & 63)};
-}
-
-// B operand of the first layer: u split into FP16 high and low parts, with
-// the constant inputs for the bias; lane group 1 passes u_hi for the low
-// parts of the weights
-__device__ inline f16x8 input(float u0, float u1, float u2) {
-  f16x8 b;
-  const bool g1 = (threadIdx.x & 63) >= 32;
-  const _Float16 h0 = (_Float16)u0, h1 = (_Float16)u1, h2 = (_Float16)u2;
-  const _Float16 one = (_Float16)(g1 ? 0.0f : 1.0f), zero = (_Float16)0.0f;
-  b[0] = h0;
-  b[1] = h1;
-  b[2] = h2;
-  b[3] = one;
-  b[4] = g1 ? zero : (_Float16)(u0 - (float)h0);
-  b[5] = g1 ? zero : (_Float16)(u1 - (float)h1);
-  b[6] = g1 ? zero : (_Float16)(u2 - (float)h2);
-  b[7] = one;
-  return b;
-}
-
-__device__ inline f16x8 ones() {
-  f16x8 b;
-  const bool g0 = (threadIdx.x & 63) < 32;
-  for (int j = 0; j < 8; ++j) b[j] = (_Float16)((j < 2 && g0) ? 1.0f : 0.0f);
-  return b;
-}
-
-__device__ inline void act_tile(const f32x16 &d, f16x8 &c0, f16x8 &c1) {
-  for (int j = 0; j < 8; ++j) {
-    c0[j] = (_Float16)act(d[j]);
-    c1[j] = (_Float16)act(d[8 + j]);
-  }
-}
-
-// The ten channels at the folded offsets of the 32 pairs of this wave: lane l
-// passes the B operand of pair l % 32 and receives its outputs (both lane
-// groups receive all ten).
-__device__ inline void forward(const Ops &W0, const f16x8 &xin, const f16x8 &one, float y[NO]) {
-  // An empty asm makes the lane slot opaque, so the operand reads are not
-  // hoisted out of the walk's loops into registers (which would leave the
-  // products in accumulation registers and cut the occupancy).
-  Ops W = W0;
-  asm volatile("" : "+v"(W.lane));
-  const f32x16 z = {0};
-  f16x8 h[4];
-  {
-    const f32x16 d0 = mma(W[PK_L1], xin, z);
-    const f32x16 d1 = mma(W[PK_L1 + 1], xin, z);
-    act_tile(d0, h[0], h[1]);
-    act_tile(d1, h[2], h[3]);
-  }
-#pragma unroll
-  for (int layer = 0; layer < 2; ++layer) {
-    const int A0 = layer == 0 ? PK_L2 : PK_L3, B0 = layer == 0 ? PK_L2B : PK_L3B;
-    f32x16 d0 = mma(W[B0], one, z);
-    f32x16 d1 = mma(W[B0 + 1], one, z);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      d0 = mma(W[A0 + c], h[c], d0);
-      d1 = mma(W[A0 + 4 + c], h[c], d1);
-    }
-    act_tile(d0, h[0], h[1]);
-    act_tile(d1, h[2], h[3]);
-  }
-  f32x16 o = mma(W[PK_L4B], one, z);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) o = mma(W[PK_L4 + c], h[c], o);
-  for (int k = 0; k < NO; ++k) y[k] = o[k];
-}
-
-}  // namespace mlpinf
 
 namespace {
 
@@ -499,15 +399,12 @@ __global__ __launch_bounds__(256) void k_mlp_points_eval(const void *__restrict_
 // over the chunk.  Phi is Kahan-compensated, a summed per tile of entries.
 constexpr int TW = 512;       // threads (cells) per workgroup
 constexpr int TTILE = 64;     // list entries per LDS tile
-constexpr int TSLOT = 16;     // floats per (group, entry) pair in LDS
 
 struct __align__(16) TRec {
   double x, y, z;
   float m, pad;
 };
 
-// pairs per chunk: 512 single cells with one entry, else 256
-__host__ __device__ inline int taylor_pairs(int gl) { return gl == 0 ? 512 : 256; }
 
 template <int BC>
 __global__ __launch_bounds__(TW) void k_eval_mlp_taylor(DevTree T, EwaldP E, const void *__restrict__ pk,

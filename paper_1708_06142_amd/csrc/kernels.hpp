@@ -101,6 +101,14 @@ hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const 
                             const double4 *rec, const int32_t *ids, const double *lh, void *phi, void *acc,
                             void *npix, void *tau, double G, int cpw, bool no_gravity, int *wg_per_cu,
                             hipStream_t st, const int32_t *blist = nullptr, int64_t nblist = 0);
+// FP32 walk with the surrogate's gravity and columns with the maps in npix
+// (one workgroup of 512 cells per block; groups and Taylor step as
+// launch_eval_mlp); 3P and 2P1I.  llat [list entries]: scratch for the
+// entries' lattice rows
+hipError_t launch_eval_cols_mlp(const DevTree &T, const EwaldP &E, const ColP &C, const void *pk, const int64_t *off,
+                                const double4 *rec, const int32_t *ids, const double *lh, int32_t *llat, float *phi,
+                                float *acc, float *npix, float *tau, double G, double tmax, double h_max,
+                                int *wg_per_cu, hipStream_t st);
 // rows of the offsets (i, j, k) cell sizes between two cells of one size,
 // |i|, |j|, |k| <= R (k slowest, i fastest), written at rows C.lat0 + ... of
 // rows, rows8 and quad_w64: copies of the table rows that the walk's binning

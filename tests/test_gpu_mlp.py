@@ -328,7 +328,8 @@ GRIDS = {"3p": ((1, 1, 1), (1, 1, 1)), "2p1i": ((1, 1, 0), (1, 1, 4))}
 
 
 def solve32(g, rho, mode, mlp=None, **kw):
-    s = ot.Solver.for_grid(g, theta=0.5, ewald_n=64, ewald=mode, **kw)
+    kw.setdefault("theta", 0.5)
+    s = ot.Solver.for_grid(g, ewald_n=64, ewald=mode, **kw)
     if mlp is not None:
         s.mlp_set(*mlp, accept=True)
     s.build(rho)
@@ -481,3 +482,32 @@ def test_column_walk_with_surrogate(trained, name):
     print(f"{name} columns: |dPhi| {dphi:.3e} (max|Phi| {np.abs(pt).max():.3e}), |da| {da:.3e} "
           f"(max|a| {np.abs(at).max():.3e}); ms_eval table {st_t.ms_eval:.2f}, surrogate {st_m.ms_eval:.2f}")
     assert dphi <= 1e-4 * np.abs(pt).max() and da <= 1e-4 * np.abs(at).max()
+
+
+@pytest.mark.parametrize("name", list(BOXES))
+def test_fused_column_walk_with_surrogate(trained, name):
+    """192-pixel maps (in memory): one kernel carries the surrogate's gravity
+    and the columns.  BH at theta = theta_pix = 0.25 gives the same lists with
+    and without columns, so its Phi and a must equal the surrogate walk
+    without columns (same network batches and Taylor step, the sums blocked
+    per 60 instead of 64 entries: the FP32 walk's bars, 1e-6 of max |Phi|
+    with its compensated sum and 1e-5 of max |a|) and its maps and tau the
+    FP32 table column walk's bit for bit."""
+    s_tr, _ = trained[name]
+    params, norm = s_tr.mlp_get()
+    bc, nroot = GRIDS[name]
+    g = workloads.deep_amr(bc, nroot)
+    rho = dev(g.rho.reshape(-1))
+    kw = dict(theta=0.25)
+    (pg, ag), st_g, s = solve32(g, rho, "mlp", (params, norm), **kw)
+    (pf, af, nf, tf), st_f, sf = solve32(g, rho, "mlp", (params, norm), nside=4, **kw)
+    (pt, at, nt, tt), st_t, _ = solve32(g, rho, "table", nside=4, **kw)
+    assert st_f.ewald_used == 2 and st_f.total_list == st_g.total_list == st_t.total_list
+    for b in (0, g.nb // 2, g.nb - 1):
+        assert np.array_equal(s.export_list(b), sf.export_list(b))
+    assert np.abs(pf - pg).max() <= 1e-6 * np.abs(pg).max()
+    assert np.abs(af - ag).max() <= 1e-5 * np.abs(ag).max()
+    assert np.array_equal(nf, nt) and np.array_equal(tf, tt)
+    assert np.abs(pf - pt).max() <= 1e-4 * np.abs(pt).max() and np.abs(af - at).max() <= 1e-4 * np.abs(at).max()
+    print(f"{name} fused 192-pixel walk: eval {st_f.ms_eval:.2f} ms (gravity walk {st_g.ms_eval:.2f} ms, "
+          f"table column walk {st_t.ms_eval:.2f} ms)")
