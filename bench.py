@@ -56,6 +56,11 @@ PEAK_FP64_VALU = 78.6
 PEAK_FP16_MFMA = 2500.0  # TFLOP/s, MI355X dense FP16 matrix
 
 
+def progress(msg):
+    """One line per finished leg on stderr (the JSON line stays alone on stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +73,8 @@ def parse():
                     help="seeded cells (plus half as many of largest |a|) for the error against the direct sum")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB: one fill + one sum of that size before timing (HBM counter calibration)")
+    ap.add_argument("--mlp-cache", default=None,
+                    help="cache file of the trained surrogate (loaded when it matches, else trained and written)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-side", action="store_true", help="skip the table walks beside the headline")
     ap.add_argument("--no-direct", action="store_true", help="skip the error against the direct sum")
@@ -215,7 +222,7 @@ def cols_roofline(st, flop_pair, fp64, kernel):
             "frac": fl / peak, "flop_per_pair": flop_pair, "ms": ms}
 
 
-def c5_setup():
+def c5_setup(mlp_cache=None):
     """The headline workload, its APE limit (BH FP64 pre-pass) and the
     surrogate trained for its boundaries (untimed)."""
     import torch
@@ -233,14 +240,14 @@ def c5_setup():
     s.close()
     tr = ot.Solver(bc=g.bc, ewald_n=64, ewald="mlp")
     t0 = time.perf_counter()
-    rep = tr.mlp_train()
+    rep = tr.mlp_train(cache_path=mlp_cache)
     train_s = time.perf_counter() - t0
     mlp = tr.mlp_get()
     tr.close()
     info = {"generate_s": gen_s, "a_lim": a_lim,
             "training": {"seconds": train_s, "ok": rep["ok"], "err_mlp": rep["err_mlp"],
                          "err_table": rep["err_table"], "loss_first": rep["loss_first"],
-                         "loss_last": rep["loss_last"]}}
+                         "loss_last": rep["loss_last"], "from_cache": bool(rep["from_cache"])}}
     return g, rho, kw, a_lim, mlp, rep, info
 
 
@@ -569,9 +576,11 @@ def main():
         total = src.sum()                         # reduction: reads exactly nc * 4 bytes
         torch.cuda.synchronize()
         del src, total
-    g, rho, kw, a_lim, mlp, rep, info = c5_setup()
+    g, rho, kw, a_lim, mlp, rep, info = c5_setup(args.mlp_cache)
+    progress(f"large AMR set up: {g.nb} blocks, a_lim {a_lim:.4g}, surrogate ok={rep['ok']}")
     n = g.ncells
     outs, st, e = c5_run(g, rho, kw, a_lim, "mlp", False, args.steps, args.warmup, mlp, bool(rep["ok"]))
+    progress(f"headline: {e['ms_per_step']:.1f} ms/step")
     if st.ms_gravity > 0:
         # surrogate gravity walk, then a column walk without gravity
         rl_grav = mlp_roofline(st)
@@ -619,6 +628,7 @@ def main():
         e32.update(maxnorm_diffs(o32, o64))
         out["fp32_table"] = e32
         del o32
+        progress("FP64- and FP32-table walks done")
     else:
         o64 = None
     torch.cuda.synchronize()
@@ -630,6 +640,7 @@ def main():
                 out["fp64_table"]["accuracy_vs_direct"] = direct_errors(t, g, o64[0], o64[1], args.direct_cells)
         if not args.no_cpu:
             out["cpu_baseline"] = cpu_baseline(t, tree_s, g, args.cpu_blocks)
+        progress("oracle legs done")
         del t
     del outs, o64
     torch.cuda.empty_cache()
@@ -637,16 +648,20 @@ def main():
         c2, grid, rho2, a2 = c2_leg(args.c2_steps, 2)
         if not args.no_c2:
             out["c2"] = c2
+        progress("128^3 lognormal leg done")
         if not args.no_surrogate:
             out["surrogate_3p"] = surrogate_leg(grid, rho2, args.surrogate_steps, 2)
+            progress("3P surrogate leg done")
         if not args.no_abu:
             out["abu"] = abu_leg(grid, a2)
             out["abu_columns"] = abu_leg(grid, a2, nside=2)
+            progress("adaptive block update legs done")
         if not args.no_mpe:
             out["mpe"] = mpe_leg(grid, rho2, a2, max(2, args.c2_steps // 2), 2)
         del rho2
     if not args.no_c3:
         out["c3"] = c3_leg(4)
+        progress("filament leg done")
     if not args.no_p1:
         out["p1"] = p1_leg(4)
     print(json.dumps(out))
