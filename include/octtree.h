@@ -171,20 +171,25 @@ ot_status ot_solve64(ot_ctx *c, double *phi_dev, double *acc_dev, double *npix_d
  * table; the surrogate is not used).  On entry phi_dev, acc_dev and, when
  * nside > 0, npix_dev and tau_dev hold the previous step's solution on the
  * same grid (layouts as ot_solve; npix_dev and tau_dev are ignored when
- * nside = 0).  After building the lists, the walk first evaluates the
- * gravity of the eight corner cells (i, j, k in {0, 7}) of every leaf block
- * in FP64; a block whose corners all moved by less than tol (Euclidean norm
- * of the acceleration change, an absolute accuracy) keeps all its previous
- * values, the others are evaluated in full, with their columns (FP32-Kahan,
+ * nside = 0).  After building the lists, the walk first evaluates the eight
+ * corner cells (i, j, k in {0, 7}) of every leaf block in FP64: their
+ * acceleration and, when nside > 0, their maps (the section counts the
+ * optical depth among the quantities compared at the corners).  A block
+ * whose corners all moved by less than tol (Euclidean norm of the
+ * acceleration change, an absolute accuracy) and, with columns, whose
+ * corners' optical depth kappa N_p moved by less than tol_tau in every pixel
+ * (absolute; this also bounds the change of tau_avg by tol_tau) keeps all
+ * its previous values; the others are evaluated in full, with their columns (FP32-Kahan,
  * or FP64 for ot_solve_abu64).  updated_host [nb] (may be NULL) receives 1
- * per evaluated block.  tol = 0 evaluates every block.
+ * per evaluated block.  tol = 0 (or tol_tau = 0 with columns) evaluates
+ * every block; tol_tau is ignored when nside = 0.
  * stats->n_interactions counts the pairs of the evaluated blocks.  Errors:
- * OT_ERR_INVALID_ARG (tol < 0 or not finite, npix_dev or tau_dev NULL with
- * nside > 0), OT_ERR_STATE (no build). */
+ * OT_ERR_INVALID_ARG (tol < 0 or not finite, npix_dev or tau_dev NULL or
+ * tol_tau < 0 or not finite with nside > 0), OT_ERR_STATE (no build). */
 ot_status ot_solve_abu(ot_ctx *c, float *phi_dev, float *acc_dev, float *npix_dev, float *tau_dev, double tol,
-                       int32_t *updated_host, ot_stats *stats_host, void *stream);
+                       double tol_tau, int32_t *updated_host, ot_stats *stats_host, void *stream);
 ot_status ot_solve_abu64(ot_ctx *c, double *phi_dev, double *acc_dev, double *npix_dev, double *tau_dev,
-                         double tol, int32_t *updated_host, ot_stats *stats_host, void *stream);
+                         double tol, double tol_tau, int32_t *updated_host, ot_stats *stats_host, void *stream);
 
 /* Ewald correction table, Sec. 2.2.5 (second approach): phi_c = phi - 1/r,
  * A_c = A - d/r^3 and the six second derivatives of phi_c, FP64, on a

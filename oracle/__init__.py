@@ -88,7 +88,7 @@ def _load(path):
     L.or_tree_nn.argtypes = [vp]
     L.or_tree_export.argtypes = [vp] + [vp] * 7
     L.or_tree_mpe_export.argtypes = [vp, vp, vp]
-    L.or_walk_group_abu.argtypes = [vp, vp, vp, C.c_double, vp, vp, vp]
+    L.or_walk_group_abu.argtypes = [vp, vp, vp, C.c_double, vp, C.c_double, vp, vp, vp]
     L.or_block_list.restype = i64
     L.or_block_list.argtypes = [vp, i64, vp, i64]
     L.or_walk_group.argtypes = [vp, vp, vp, vp]
@@ -203,17 +203,26 @@ class Tree:
         lib().or_tree_mpe_export(self.h, _ptr(B2), _ptr(B3))
         return B2, B3
 
-    def walk_abu(self, prev_phi, prev_acc, tol, prev_npix=None, prev_tau=None):
+    def walk_abu(self, prev_phi, prev_acc, tol, prev_npix=None, prev_tau=None, tol_tau=None):
         """Adaptive block update (Sec. 2.2.6): returns phi [nb*512], acc [3, nb*512]
         and updated [nb] (1 where the block was evaluated).  With prev_npix
-        [nb, Npix, 512] and prev_tau [nb*512] (trees with nside > 0) also npix and
-        tau: the group walk's columns for the updated blocks, the previous ones
-        for the others (the decision is the gravity corner test either way)."""
+        [nb, Npix, 512], prev_tau [nb*512] and tol_tau (trees with nside > 0)
+        a block is also evaluated when at a corner the optical depth kappa N_p
+        of a direction moved by tol_tau or more, and npix and tau are returned
+        too: the group walk's columns for the updated blocks, the previous
+        ones for the others."""
         n = 512 * self.nb
         pp = np.ascontiguousarray(prev_phi, dtype=np.float64).reshape(n)
         pa = np.ascontiguousarray(prev_acc, dtype=np.float64).reshape(3, n)
         phi, acc, upd = np.empty(n), np.empty((3, n)), np.empty(self.nb, np.int32)
-        lib().or_walk_group_abu(self.h, _ptr(pp), _ptr(pa), float(tol), _ptr(phi), _ptr(acc), _ptr(upd))
+        pn = None
+        if prev_npix is not None:
+            if tol_tau is None:
+                raise TypeError("walk_abu with columns needs tol_tau")
+            pn = np.ascontiguousarray(prev_npix, dtype=np.float64).reshape(-1)
+            assert pn.size == n * 12 * self.params.nside ** 2
+        lib().or_walk_group_abu(self.h, _ptr(pp), _ptr(pa), float(tol), _ptr(pn),
+                                float(tol_tau if tol_tau is not None else 0.0), _ptr(phi), _ptr(acc), _ptr(upd))
         if prev_npix is None:
             return phi, acc, upd
         npix = np.array(prev_npix, dtype=np.float64).reshape(self.nb, -1, 512)

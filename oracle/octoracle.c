@@ -608,29 +608,40 @@ void or_walk_group_blocks(const or_tree *t, int64_t nsel, const int64_t *sel, do
 /* Adaptive block update (Sec. 2.2.6): per leaf block the group walk first
  * evaluates the eight corner cells (i, j, k in {0, 7}); when at each of them
  * the acceleration differs from the previous step's by less than tol (the
- * Euclidean norm of the difference, an absolute accuracy as in Eq. (4)), the
+ * Euclidean norm of the difference, an absolute accuracy as in Eq. (4)) and,
+ * with columns (prev_npix not NULL, the tree's ray table built), the optical
+ * depth kappa N_p of every direction differs from the previous one by less
+ * than tol_tau (the section names the optical depth among the quantities
+ * compared at the corners; this also bounds the change of tau_avg), the
  * block keeps the previous values of all its cells, else all 512 cells are
  * evaluated.  prev_* and the outputs are full-size ([nb*512], acc
- * [3][nb*512]); updated[lb] = 1 where the block was evaluated. */
+ * [3][nb*512], prev_npix [nb][Npix][512]); updated[lb] = 1 where the block
+ * was evaluated. */
 void or_walk_group_abu(const or_tree *t, const double *prev_phi, const double *prev_acc, double tol,
-                       double *phi, double *acc, int32_t *updated) {
+                       const double *prev_npix, double tol_tau, double *phi, double *acc, int32_t *updated) {
   const int64_t ncell = 512 * t->nb;
+  const int cols = prev_npix && t->rt.off;
+  const int np = t->rt.npix;
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t lb = 0; lb < t->nb; ++lb) {
     idlist l = group_list(t, lb);
+    double *map = cols ? (double *)malloc(sizeof(double) * np) : NULL;
     int changed = 0;
     for (int k = 0; k < 8; ++k) {
       const int ci = 7 * (k & 1) + 56 * ((k >> 1) & 1) + 448 * ((k >> 2) & 1);
       double x[3], ph, a[3];
       or_cell_centre(t, lb, ci, x);
-      sum_list(t, x, l.v, l.n, &ph, a, NULL);
+      sum_list(t, x, l.v, l.n, &ph, a, map);
       double d2 = 0.0;
       for (int q = 0; q < 3; ++q) {
         const double d = a[q] - prev_acc[q * ncell + 512 * lb + ci];
         d2 = d2 + d * d;
       }
       if (!(sqrt(d2) < tol)) changed = 1;
+      for (int p = 0; cols && p < np; ++p)
+        if (!(t->p.kappa * fabs(map[p] - prev_npix[(lb * np + p) * 512 + ci]) < tol_tau)) changed = 1;
     }
+    free(map);
     updated[lb] = changed;
     for (int ci = 0; ci < 512; ++ci) {
       const int64_t o = 512 * lb + ci;

@@ -52,7 +52,7 @@ void or_tree_free(or_tree *t);
 void or_tree_mpe_export(const or_tree *t, double *B2, double *B3);
 /* adaptive block update of the group walk (gravity only), Sec. 2.2.6 */
 void or_walk_group_abu(const or_tree *t, const double *prev_phi, const double *prev_acc, double tol,
-                       double *phi, double *acc, int32_t *updated);
+                       const double *prev_npix, double tol_tau, double *phi, double *acc, int32_t *updated);
 int64_t or_tree_na(const or_tree *t);
 int64_t or_tree_nn(const or_tree *t);
 #endif

@@ -96,8 +96,8 @@ def lib():
         L.ot_build.argtypes = [vp, vp, vp]
         L.ot_solve.argtypes = [vp, vp, vp, vp, vp, C.POINTER(Stats), vp]
         L.ot_solve64.argtypes = [vp, vp, vp, vp, vp, C.POINTER(Stats), vp]
-        L.ot_solve_abu.argtypes = [vp, vp, vp, vp, vp, C.c_double, vp, C.POINTER(Stats), vp]
-        L.ot_solve_abu64.argtypes = [vp, vp, vp, vp, vp, C.c_double, vp, C.POINTER(Stats), vp]
+        L.ot_solve_abu.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_double, vp, C.POINTER(Stats), vp]
+        L.ot_solve_abu64.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_double, vp, C.POINTER(Stats), vp]
         L.ot_export_raytable.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), vp, vp, vp, vp]
         L.ot_ewald_prepare.argtypes = [vp, C.c_char_p, vp]
         L.ot_num_amr_nodes.restype = i64
@@ -243,17 +243,21 @@ class Solver:
                                      _dev_ptr(tau, f), C.byref(st), _stream(stream)))
         return st
 
-    def solve_abu(self, phi, acc, tol, fp64=False, npix=None, tau=None, stream=None):
+    def solve_abu(self, phi, acc, tol, fp64=False, npix=None, tau=None, stream=None, tol_tau=None):
         """Adaptive block update: phi, acc (and npix, tau when nside > 0) hold
         the previous step's solution and are updated in place where a block's
-        corner cells moved by tol or more.  Returns (stats, updated [nb] int32)."""
+        corner cells moved by tol or more in acceleration (or, with columns,
+        by tol_tau or more in the optical depth kappa N_p of a pixel).
+        Returns (stats, updated [nb] int32)."""
+        if self.params.nside and tol_tau is None:
+            raise TypeError("solve_abu with columns needs tol_tau")
         import torch
         st = Stats()
         f = torch.float64 if fp64 else torch.float32
         upd = np.empty(self.nb, np.int32)
         fn = lib().ot_solve_abu64 if fp64 else lib().ot_solve_abu
         self._check(fn(self.h, _dev_ptr(phi, f), _dev_ptr(acc, f), _dev_ptr(npix, f), _dev_ptr(tau, f),
-                       float(tol), _np_ptr(upd), C.byref(st), _stream(stream)))
+                       float(tol), float(tol_tau or 0.0), _np_ptr(upd), C.byref(st), _stream(stream)))
         return st, upd
 
     def export_raytable(self, stream=None):

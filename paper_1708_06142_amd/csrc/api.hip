@@ -756,13 +756,15 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
 // full evaluation (with the columns when nside > 0) of the blocks where one of
 // them moved by tol or more; the other blocks keep phi, acc, npix and tau.
 ot_status abu_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, void *tau, double tol,
-                   int32_t *updated, ot_stats *stats, void *stream) {
+                   double tol_tau, int32_t *updated, ot_stats *stats, void *stream) {
   if (!c) return OT_ERR_INVALID_ARG;
   c->err.clear();
   if (!phi || !acc) return fail(c, OT_ERR_INVALID_ARG, "phi and acc must be device pointers");
   if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(c, OT_ERR_INVALID_ARG, "tol must be finite and >= 0");
   const bool cols = c->p.nside > 0;
   if (cols && (!npix || !tau)) return fail(c, OT_ERR_INVALID_ARG, "nside > 0 needs npix and tau");
+  if (cols && (!(tol_tau >= 0.0) || !std::isfinite(tol_tau)))
+    return fail(c, OT_ERR_INVALID_ARG, "tol_tau must be finite and >= 0");
   if (!c->built) return fail(c, OT_ERR_STATE, "ot_solve_abu before a successful ot_build");
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(c->p.device));
@@ -792,6 +794,9 @@ ot_status abu_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, void 
   HIPCHK(hipMemsetAsync(c->abu_flag.ptr, 0, nb * sizeof(int32_t), st));
   HIPCHK(ot::launch_abu_corners(fp64, T, E, P<int64_t>(c->loff), P<double4>(c->lrec), acc, c->p.G, tol,
                                 P<int32_t>(c->abu_flag), st));
+  if (cols)
+    HIPCHK(ot::launch_abu_corner_cols(fp64, T, E, col_params(c), P<int64_t>(c->loff), P<double4>(c->lrec),
+                                      P<double>(c->lh), npix, tol_tau, P<int32_t>(c->abu_flag), st));
   std::vector<int32_t> flag(nb), blist;
   HIPCHK(hipMemcpyAsync(flag.data(), c->abu_flag.ptr, nb * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -837,14 +842,14 @@ ot_status abu_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, void 
 
 extern "C" {
 
-ot_status ot_solve_abu(ot_ctx *c, float *phi, float *acc, float *npix, float *tau, double tol,
+ot_status ot_solve_abu(ot_ctx *c, float *phi, float *acc, float *npix, float *tau, double tol, double tol_tau,
                        int32_t *updated_host, ot_stats *stats, void *stream) {
-  return abu_impl(c, false, phi, acc, npix, tau, tol, updated_host, stats, stream);
+  return abu_impl(c, false, phi, acc, npix, tau, tol, tol_tau, updated_host, stats, stream);
 }
 
 ot_status ot_solve_abu64(ot_ctx *c, double *phi, double *acc, double *npix, double *tau, double tol,
-                         int32_t *updated_host, ot_stats *stats, void *stream) {
-  return abu_impl(c, true, phi, acc, npix, tau, tol, updated_host, stats, stream);
+                         double tol_tau, int32_t *updated_host, ot_stats *stats, void *stream) {
+  return abu_impl(c, true, phi, acc, npix, tau, tol, tol_tau, updated_host, stats, stream);
 }
 
 void ot_params_default(ot_params *p) {

@@ -697,6 +697,77 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   tau[o] = (Real)(-log(se / (double)C.npix));
 }
 
+// Adaptive block update with columns (Sec. 2.2.6 names the optical depth
+// among the quantities compared at the corner cells): the maps of the eight
+// corner cells (i, j, k in {0, 7}) of every leaf block, summed in FP64 over
+// the block's list with the FP64 walk's bins and weights.  One workgroup of
+// eight waves per block, wave w takes corner w: its lanes bin 64 list entries
+// at a time and add each entry's pixels to the corner's map in LDS (FP64 adds
+// that only this wave makes, in list order per lane, so the sum is the same
+// run to run).  flags[b] = 1 when at one corner the optical depth kappa N_p
+// of a direction moved from the previous map by tol_tau or more (which also
+// bounds the change of tau_avg); the flags are only ever set here.
+template <int BC, typename Real>
+__global__ __launch_bounds__(512) void k_abu_corner_cols(DevTree T, EwaldP E, ColP C,
+                                                         const int64_t *__restrict__ off,
+                                                         const double4 *__restrict__ rec,
+                                                         const double *__restrict__ lh,
+                                                         const Real *__restrict__ prev_npix, double tol_tau,
+                                                         int32_t *__restrict__ flags) {
+  __shared__ uint8_t lut[LUT_BYTES];
+  extern __shared__ __align__(16) unsigned char smem[];
+  double *const thr = reinterpret_cast<double *>(smem);
+  double *const maps = thr + ((C.nthr + 1) & ~1);  // [8][npix]
+  const int64_t b = blockIdx.x;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  for (int q = tid; q < LUT_BYTES; q += 512) lut[q] = C.lut[q];
+  for (int q = tid; q < C.nthr; q += 512) thr[q] = C.thr[q];
+  for (int q = tid; q < 8 * C.npix; q += 512) maps[q] = 0.0;
+  __syncthreads();
+  double *const map = maps + w * C.npix;
+  const int ci = 7 * (w & 1) + 56 * ((w >> 1) & 1) + 448 * ((w >> 2) & 1);
+  const double h = size_at(T.root_size, T.blev[b]) / 8.0;
+  const double cx = centre_coord(T.org[0], 8 * (int64_t)T.bcoord[3 * b] + (ci & 7), h);
+  const double cy = centre_coord(T.org[1], 8 * (int64_t)T.bcoord[3 * b + 1] + ((ci >> 3) & 7), h);
+  const double cz = centre_coord(T.org[2], 8 * (int64_t)T.bcoord[3 * b + 2] + (ci >> 6), h);
+  const int64_t start = off[b], end = off[b + 1];
+  for (int64_t j0 = start; j0 < end; j0 += 64) {
+    const int64_t j = j0 + l < end ? j0 + l : end - 1;
+    const double4 r = rec[j];
+    double dx = cx - r.x, dy = cy - r.y, dz = cz - r.z;
+    wrap3<BC>(E, dx, dy, dz);
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const bool col = j0 + l < end && r2 != 0.0 && r2 <= C.max_dist2;
+    const float r2f = (float)r2;
+    const float rd = __builtin_amdgcn_rsqf(fmaxf(r2f, 1e-30f));
+    const double rh = C.req * lh[j];
+    const int e = col ? table_row(C, thr, lut, dx, dy, dz, (float)dx, (float)dy, (float)dz, r2, r2f, rd, rh * rh,
+                                  (float)rh * C.lut_ps)
+                      : 0;
+    if (col) {
+      // the row: four pixels with their FP64 weights (zero past the count),
+      // the rest of a longer row in pix / w64
+      const double base = r.w / (C.omega * r2);
+      const uint4 pq = C.rows8[2 * (int64_t)e];
+      const double *const wq = C.quad_w64 + 4 * (int64_t)e;
+      unsafeAtomicAdd(&map[pq.x & 0x7fffffu], wq[0] * base);
+      unsafeAtomicAdd(&map[pq.y & 0x7fffffu], wq[1] * base);
+      unsafeAtomicAdd(&map[pq.z & 0x7fffffu], wq[2] * base);
+      unsafeAtomicAdd(&map[pq.w & 0x7fffffu], wq[3] * base);
+      if ((int)pq.x < 0) {
+        const int cnt = (int)((pq.x >> 23) & 63u);
+        const int o0 = (int)((pq.y >> 23) | ((pq.z >> 23) << 9) | ((pq.w >> 23) << 18));
+        for (int o = o0 + 4; o < o0 + cnt; ++o) unsafeAtomicAdd(&map[C.pix[o]], C.w64[o] * base);
+      }
+    }
+  }
+  __syncthreads();
+  bool moved = false;
+  for (int p = l; p < C.npix; p += 64)
+    moved = moved || !(C.kappa * fabs(map[p] - (double)prev_npix[(b * C.npix + p) * 512 + ci]) < tol_tau);
+  if (__any(moved) && l == 0) flags[b] = 1;
+}
+
 // Lattice row of every list entry for the walk with the learned surrogate:
 // the row of the table that a cell of the target block's own size at a
 // lattice offset takes for the block's first cell (the walk adds each cell's
@@ -1136,6 +1207,33 @@ int cols_lds_cpw(int npix, bool fp64, int nthr) {
   for (int cpw : {256, 128})
     if (cols_smem_bytes(npix, cpw, fp64, nthr) <= 65536) return cpw;
   return 0;
+}
+
+hipError_t launch_abu_corner_cols(bool fp64, const DevTree &T, const EwaldP &E, const ColP &C, const int64_t *off,
+                                  const double4 *rec, const double *lh, const void *prev_npix, double tol_tau,
+                                  int32_t *flags, hipStream_t st) {
+  const size_t sm = (size_t)(((C.nthr + 1) & ~1) + 8 * C.npix) * sizeof(double);
+  dim3 grid((unsigned)T.nb), blk(512);
+#define OT_ABC(B, R)                                                                                       \
+  hipLaunchKernelGGL((k_abu_corner_cols<B, R>), grid, blk, sm, st, T, E, C, off, rec, lh, (const R *)prev_npix, \
+                     tol_tau, flags)
+  if (fp64) {
+    switch (E.bctype) {
+      case 0: OT_ABC(0, double); break;
+      case 1: OT_ABC(1, double); break;
+      case 2: OT_ABC(2, double); break;
+      default: OT_ABC(3, double); break;
+    }
+  } else {
+    switch (E.bctype) {
+      case 0: OT_ABC(0, float); break;
+      case 1: OT_ABC(1, float); break;
+      case 2: OT_ABC(2, float); break;
+      default: OT_ABC(3, float); break;
+    }
+  }
+#undef OT_ABC
+  return hipGetLastError();
 }
 
 hipError_t launch_eval_cols_mlp(const DevTree &T, const EwaldP &E, const ColP &C, const void *pk, const int64_t *off,

@@ -101,6 +101,13 @@ hipError_t launch_eval_cols(bool fp64, const DevTree &T, const EwaldP &E, const 
                             const double4 *rec, const int32_t *ids, const double *lh, void *phi, void *acc,
                             void *npix, void *tau, double G, int cpw, bool no_gravity, int *wg_per_cu,
                             hipStream_t st, const int32_t *blist = nullptr, int64_t nblist = 0);
+// Adaptive block update with columns: flags[b] = 1 where at one of the
+// block's eight corner cells (FP64 maps over the block's list) kappa N_p of a
+// pixel moved from prev_npix (FP64 or FP32 as fp64) by tol_tau or more
+hipError_t launch_abu_corner_cols(bool fp64, const DevTree &T, const EwaldP &E, const ColP &C, const int64_t *off,
+                                  const double4 *rec, const double *lh, const void *prev_npix, double tol_tau,
+                                  int32_t *flags, hipStream_t st);
+
 // FP32 walk with the surrogate's gravity and columns with the maps in npix
 // (one workgroup of 512 cells per block; groups and Taylor step as
 // launch_eval_mlp); 3P and 2P1I.  llat [list entries]: scratch for the

@@ -89,9 +89,13 @@ def test_abu_perturbed_matches_oracle(fp64, bc):
 
 @pytest.mark.parametrize("fp64", [True, False])
 def test_abu_columns_matches_oracle(fp64):
-    """With 12-pixel columns: kept blocks keep phi, acc, the maps and tau bit
-    for bit; updated blocks match the oracle's walk with columns at the walk's
-    bar (1e-12 FP64, 1e-6 / 1e-5 FP32; maps relative to the largest column)."""
+    """With 12-pixel columns the corner test also compares the optical depth
+    of every pixel.  With the two tolerances at the 60% quantiles of the
+    corners' changes (so that each test alone updates some blocks) the
+    decisions are the oracle's, up to corners within 1e-9 of a tolerance; kept blocks keep phi, acc, the maps
+    and tau bit for bit; updated blocks match the oracle's walk with columns
+    at the walk's bar (1e-12 FP64, 1e-6 / 1e-5 FP32; maps relative to the
+    largest column)."""
     g = workloads.small_amr()
     kw = dict(theta=0.5, nside=1)
     p0, a0, _, n0, t0 = oracle.Tree(g, **kw).walk_group(columns=True)
@@ -99,18 +103,25 @@ def test_abu_columns_matches_oracle(fp64):
         p0, a0, n0, t0 = (x.astype(np.float32).astype(np.float64) for x in (p0, a0, n0, t0))
     g1 = _perturbed(g)
     t1 = oracle.Tree(g1, **kw)
-    a1 = t1.walk_group()[1]
-    tol = 1e-3 * np.sqrt((a1 ** 2).sum(0)).max()
-    pr, ar, upd_r, nr, tr = t1.walk_abu(p0, a0, tol, n0, t0)
+    _, a1, _, n1, _ = t1.walk_group(columns=True)
+    da = np.sqrt(((a1 - a0) ** 2).sum(0)).reshape(g.nb, 512)[:, CORNERS].max(1)
+    dtau = np.abs(n1 - n0).reshape(g.nb, -1, 512)[:, :, CORNERS].max((1, 2))  # kappa = 1
+    tol, tol_tau = np.quantile(da, 0.6), np.quantile(dtau, 0.6)
+    pr, ar, upd_r, nr, tr = t1.walk_abu(p0, a0, tol, n0, t0, tol_tau=tol_tau)
     s = _solver(g1, nside=1)
     dt = torch.float64 if fp64 else torch.float32
     phi, acc = (torch.from_numpy(x.reshape(-1).copy()).to(dt).cuda() for x in (p0, a0))
     npix, tau = (torch.from_numpy(x.reshape(-1).copy()).to(dt).cuda() for x in (n0, t0))
-    st, upd = s.solve_abu(phi, acc, tol, fp64=fp64, npix=npix, tau=tau)
+    with pytest.raises(ot.OTError, match="INVALID_ARG"):
+        s.solve_abu(phi, acc, tol, fp64=fp64, npix=npix, tau=tau, tol_tau=-1.0)
+    with pytest.raises(TypeError):
+        s.solve_abu(phi, acc, tol, fp64=fp64, npix=npix, tau=tau)
+    st, upd = s.solve_abu(phi, acc, tol, fp64=fp64, npix=npix, tau=tau, tol_tau=tol_tau)
     assert 0 < upd_r.sum() < g.nb
-    da = np.sqrt(((a1 - a0) ** 2).sum(0)).reshape(g.nb, 512)[:, CORNERS].max(1)
+    assert ((dtau >= tol_tau) & (da < tol) & (upd_r == 1)).any()  # updated for tau alone
     differ = upd != upd_r
-    assert np.all(np.abs(da[differ] - tol) <= 1e-9 * tol)
+    near = (np.abs(da - tol) <= 1e-9 * tol) | (np.abs(dtau - tol_tau) <= 1e-9 * tol_tau)
+    assert np.all(near[differ]), np.nonzero(differ)
     keep, ev = ~differ & (upd == 0), ~differ & (upd == 1)
     got = [x.cpu().numpy().astype(np.float64) for x in (phi, acc, npix, tau)]
     shapes = [(g.nb, 512), (3, g.nb, 512), (g.nb, -1, 512), (g.nb, 512)]
@@ -123,6 +134,27 @@ def test_abu_columns_matches_oracle(fp64):
             assert np.array_equal(xb[keep], x0b[keep])
             e = np.abs(xb[ev] - xrb[ev]).max() / np.abs(xrb).max()
         assert e <= (1e-12 if fp64 else 1e-5), e
+
+
+@pytest.mark.parametrize("nside", [2, 4])
+@pytest.mark.parametrize("fp64", [True, False])
+def test_abu_columns_zero_tolerance_is_the_plain_solve(fp64, nside):
+    """Tolerances 0 evaluate every block through the update's block-list
+    walk (48-pixel maps in LDS, 192-pixel maps in memory): phi, acc, the maps
+    and tau equal the plain solve's bit for bit."""
+    g = workloads.small_amr()
+    s = _solver(g, nside=nside)
+    n, npx = 512 * g.nb, 12 * nside * nside
+    dt = torch.float64 if fp64 else torch.float32
+    outs = [torch.empty(m, dtype=dt, device="cuda") for m in (n, 3 * n, n * npx, n)]
+    (s.solve64 if fp64 else s.solve)(*outs)
+    ref = [o.cpu().numpy() for o in outs]
+    for o in outs:
+        o.zero_()
+    st, upd = s.solve_abu(outs[0], outs[1], 0.0, fp64=fp64, npix=outs[2], tau=outs[3], tol_tau=0.0)
+    assert upd.all()
+    for o, r in zip(outs, ref):
+        assert np.array_equal(o.cpu().numpy(), r)
 
 
 def test_abu_after_regrid_to_more_blocks():
