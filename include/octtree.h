@@ -284,6 +284,18 @@ ot_status ot_mlp_set(ot_ctx *c, const float *params_host, const double *norm_hos
 ot_status ot_mlp_grad(ot_ctx *c, const float *params_dev, int64_t batch, const float *x_dev,
                       const float *t_dev, float *grad_dev, float *loss_host, void *stream);
 
+/* One training step of the surrogate, in place: the batch loss and gradient
+ * at params_dev as ot_mlp_grad, then the Adam update the trainer applies
+ * (beta1 0.9, beta2 0.999, eps 1e-8, bias corrections 1 - beta^step) with
+ * step size lr to params_dev [NPARAM] and its moment estimates m_dev, v_dev
+ * [NPARAM].  step >= 1 is the update's index; *loss_host gets the loss at
+ * the parameters before the update.  An inspection entry for tests (the
+ * trainer runs the same kernels).  Errors: OT_ERR_INVALID_ARG (null pointer,
+ * batch as ot_mlp_grad, step < 1, lr <= 0 or not finite). */
+ot_status ot_mlp_adam_step(ot_ctx *c, float *params_dev, float *m_dev, float *v_dev, int64_t batch,
+                           const float *x_dev, const float *t_dev, double lr, int64_t step, float *loss_host,
+                           void *stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight training or serving loops, harnesses that forbid
  * hipMalloc): ot_mlp_grad without any allocation.  The per-workgroup partial

@@ -112,6 +112,7 @@ def lib():
         L.ot_mlp_set.argtypes = [vp, vp, vp, C.c_int32, vp]
         L.ot_mlp_grad.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
         L.ot_mlp_grad_noalloc.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
+        L.ot_mlp_adam_step.argtypes = [vp, vp, vp, vp, i64, vp, vp, C.c_double, i64, vp, vp]
         L.ot_ewald_points.argtypes = [vp, C.c_int32, i64, vp, vp, vp]
         L.ot_column_bins.argtypes = [vp, i64, vp, vp, vp, vp]
         L.ot_last_error.restype = C.c_char_p
@@ -121,7 +122,7 @@ def lib():
                      "ot_solve_abu64",
                      "ot_ewald_prepare", "ot_export_topology", "ot_export_moments",
                      "ot_export_list", "ot_export_ewald_table", "ot_export_raytable", "ot_mlp_train",
-                     "ot_mlp_get", "ot_mlp_set", "ot_mlp_grad", "ot_mlp_grad_noalloc", "ot_ewald_points",
+                     "ot_mlp_get", "ot_mlp_set", "ot_mlp_grad", "ot_mlp_grad_noalloc", "ot_mlp_adam_step", "ot_ewald_points",
                      "ot_column_bins"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -310,6 +311,18 @@ class Solver:
         loss = C.c_float(0.0)
         self._check(lib().ot_mlp_grad(self.h, _dev_ptr(params, f), int(x.shape[0]), _dev_ptr(x, f),
                                       _dev_ptr(t, f), _dev_ptr(grad, f), C.byref(loss), _stream(stream)))
+        return loss.value
+
+    def mlp_adam_step(self, params, m, v, x, t, lr, step, stream=None):
+        """One training step in place on device tensors params, m, v (FP32
+        [NPARAM]): gradient over x [batch, 3], t [batch, 10], then Adam with
+        step size lr and update index step; returns the loss before it."""
+        import torch
+        f = torch.float32
+        loss = C.c_float(0.0)
+        self._check(lib().ot_mlp_adam_step(self.h, _dev_ptr(params, f), _dev_ptr(m, f), _dev_ptr(v, f),
+                                           int(x.shape[0]), _dev_ptr(x, f), _dev_ptr(t, f), float(lr), int(step),
+                                           C.byref(loss), _stream(stream)))
         return loss.value
 
     def mlp_grad_noalloc(self, params, x, t, grad, loss, stream=None):

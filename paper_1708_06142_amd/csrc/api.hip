@@ -1398,6 +1398,26 @@ ot_status ot_mlp_grad(ot_ctx *c, const float *params, int64_t batch, const float
   return OT_OK;
 }
 
+ot_status ot_mlp_adam_step(ot_ctx *c, float *params, float *m, float *v, int64_t batch, const float *x,
+                           const float *t, double lr, int64_t step, float *loss, void *stream) {
+  if (!c) return OT_ERR_INVALID_ARG;
+  c->err.clear();
+  if (!params || !m || !v || !x || !t || !loss) return fail(c, OT_ERR_INVALID_ARG, "null pointer");
+  if (batch < 32 || batch % 32 || batch > ((int64_t)1 << 24))
+    return fail(c, OT_ERR_INVALID_ARG, "batch must be a positive multiple of 32, <= 2^24");
+  if (step < 1 || step > ((int64_t)1 << 30)) return fail(c, OT_ERR_INVALID_ARG, "step must be >= 1");
+  if (!(lr > 0.0) || !std::isfinite(lr)) return fail(c, OT_ERR_INVALID_ARG, "lr must be finite and > 0");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->p.device));
+  OTCHK(mlp_grad_scratch(c, batch));
+  OTCHK(dalloc(c, c->mlp_loss, sizeof(float)));
+  HIPCHK(ot::launch_mlp_step(params, batch, 0, batch, x, t, P<float>(c->mlp_part), P<float>(c->mlp_lossp),
+                             P<float>(c->mlp_loss), m, v, (float)lr, (int)step, st));
+  HIPCHK(hipMemcpyAsync(loss, c->mlp_loss.ptr, sizeof(float), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return OT_OK;
+}
+
 ot_status ot_mlp_grad_noalloc(ot_ctx *c, const float *params, int64_t batch, const float *x, const float *t,
                               float *grad, float *loss, void *stream) {
   if (!c) return OT_ERR_INVALID_ARG;

@@ -952,13 +952,14 @@ __global__ __launch_bounds__(512) void k_eval_cols_mlp(DevTree T, EwaldP E, ColP
       for (int j = 0; j < mc; ++j) {
         const ColRec r = tile[j0 + j];
         // gravity: Newtonian part and the Taylor step from the group's channels
+        float r2, inv;
         {
           const float4 *o = reinterpret_cast<const float4 *>(slot + TSLOT * (j * G + mg));
           const float4 v0 = o[0], v1 = o[1], v2 = o[2], v3 = o[3];
           const float dx = v2.z + dlx, dy = v2.w + dly, dz = v3.x + dlz;
-          const float r2 = dx * dx + dy * dy + dz * dz;
+          r2 = dx * dx + dy * dy + dz * dz;
           const bool valid = r2 != 0.0f;
-          const float inv = valid ? __builtin_amdgcn_rsqf(fmaxf(r2, 1e-30f)) : 0.0f;
+          inv = valid ? __builtin_amdgcn_rsqf(fmaxf(r2, 1e-30f)) : 0.0f;
           const float inv3 = inv * inv * inv;
           float ph, A0, A1, A2;
           if (BC == 2 && v3.y != 0.0f) {
@@ -980,20 +981,28 @@ __global__ __launch_bounds__(512) void k_eval_cols_mlp(DevTree T, EwaldP E, ColP
           ty += mw * A1;
           tz += mw * A2;
         }
-        // columns: the minimum-image offset of the cell, its direction bins
-        // and the table row's four-slot record
-        double qx = cx - r.x, qy = cy - r.y, qz = cz - r.z;
-        wrap3<BC>(E, qx, qy, qz);
-        const double q2 = qx * qx + qy * qy + qz * qz;
-        const bool col = q2 != 0.0 && q2 <= C.max_dist2;
-        const float q2f = (float)q2;
-        const float rd = __builtin_amdgcn_rsqf(fmaxf(q2f, 1e-30f));
-        // (the record is the workgroup's: a uniform branch)
+        // columns: the direction bins and the table row's four-slot record.
+        // A lattice cell's row comes with the list; its offset from the group
+        // centre and the cell's from it are whole multiples of h / 2, so the
+        // gravity's FP32 r^2 is exact and equals the FP64 one: the column
+        // weight uses it directly (the record is the workgroup's: a uniform
+        // branch).  Other records take the FP64 minimum-image offset.
+        bool col;
+        float rd;
         int e;
-        if (__builtin_amdgcn_readfirstlane(r.rhs < 0.0f ? 1 : 0))
+        if (__builtin_amdgcn_readfirstlane(r.rhs < 0.0f ? 1 : 0)) {
           e = r.lat + lat_lane;
-        else
+          col = r2 != 0.0f && (double)r2 <= C.max_dist2;
+          rd = inv;
+        } else {
+          double qx = cx - r.x, qy = cy - r.y, qz = cz - r.z;
+          wrap3<BC>(E, qx, qy, qz);
+          const double q2 = qx * qx + qy * qy + qz * qz;
+          col = q2 != 0.0 && q2 <= C.max_dist2;
+          const float q2f = (float)q2;
+          rd = __builtin_amdgcn_rsqf(fmaxf(q2f, 1e-30f));
           e = col ? table_row(C, thr, lut, qx, qy, qz, (float)qx, (float)qy, (float)qz, q2, q2f, rd, r.rh2, r.rhs) : 0;
+        }
         const char *const rq8 = reinterpret_cast<const char *>(C.rows8) + ((uint32_t)e << 5);
         const uint4 pq = *reinterpret_cast<const uint4 *>(rq8);
         const uint4 wq = *reinterpret_cast<const uint4 *>(rq8 + 16);

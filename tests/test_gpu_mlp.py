@@ -164,6 +164,38 @@ def test_gradient_vs_oracle(batch):
         assert np.abs(gg[sl] - gr[sl]).max() <= 1e-5 * np.abs(gr).max()
 
 
+@pytest.mark.parametrize("step", [1, 7])
+def test_adam_step_vs_oracle(step):
+    """One device training step (the trainer's kernels: FP32 gradient, then
+    Adam with bias corrections for update index step) against the oracle's
+    FP64 gradient and Adam step from the same parameters, moments and batch:
+    parameters within 1e-6 (the updates are about lr = 1e-3), the moment
+    estimates within 1e-5 of their largest value."""
+    s = solver("3p")
+    rng = np.random.default_rng(40 + step)
+    batch, lr = 96, 1e-3
+    p = random_params(50 + step)
+    m = (1e-2 * rng.normal(size=p.size)).astype(np.float32)
+    v = (1e-4 * rng.uniform(0.1, 1.0, p.size)).astype(np.float32)
+    x = rng.uniform(-1, 1, (batch, 3)).astype(np.float32)
+    t = rng.normal(size=(batch, NO)).astype(np.float32)
+    pd, md, vd = (dev(a, torch.float32) for a in (p, m, v))
+    loss = s.mlp_adam_step(pd, md, vd, dev(x, torch.float32), dev(t, torch.float32), lr, step)
+    lr_, pr, mr, vr = oracle.mlp_adam(p.astype(np.float64), m.astype(np.float64), v.astype(np.float64),
+                                      x.astype(np.float64), t.astype(np.float64), lr, step)
+    got = [a.cpu().numpy().astype(np.float64) for a in (pd, md, vd)]
+    ep = np.abs(got[0] - pr).max()
+    em = np.abs(got[1] - mr).max() / np.abs(mr).max()
+    ev = np.abs(got[2] - vr).max() / np.abs(vr).max()
+    print(f"step {step}: loss {loss:.6g} (oracle {lr_:.6g}); |dP| {ep:.2e}, m {em:.2e}, v {ev:.2e}, "
+          f"largest update {np.abs(pr - p).max():.2e}")
+    assert abs(loss - lr_) <= 1e-5 * lr_
+    assert np.abs(pr - p).max() > 1e-4  # the step moves the parameters
+    assert ep <= 1e-6 and em <= 1e-5 and ev <= 1e-5
+    with pytest.raises(ot.OTError, match="INVALID_ARG"):
+        s.mlp_adam_step(pd, md, vd, dev(x, torch.float32), dev(t, torch.float32), lr, 0)
+
+
 def test_gradient_is_deterministic():
     s = solver("3p")
     rng = np.random.default_rng(9)
