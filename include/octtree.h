@@ -97,6 +97,15 @@ typedef struct {
   double kappa;          /* opacity in tau_avg = -ln <exp(-kappa N_p)>_p       [1]    */
   double max_dist;       /* columns only from nodes closer (tr_bhMaxDist)       [1e99] */
   double psi_max;        /* upper edge of the angular-size bins (rad)          [0.98] */
+  /* learned Ewald surrogate in the walk */
+  double mlp_reach;      /* the walk evaluates the network once per group of cells
+                            and list entry and takes a first-order Taylor step to
+                            each cell; the group is the block's 4^3, 2^3 or single
+                            cells, the largest whose cells lie, per axis, within
+                            mlp_reach times half the Ewald table's smallest grid
+                            spacing of its centre (1: the table's own Taylor
+                            offset, Sec. 2.2.5; larger: fewer evaluations and a
+                            Taylor remainder growing as its square); <= 0: 1 [1] */
 } ot_params;
 
 /* Run statistics of the last solve. */

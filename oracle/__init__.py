@@ -44,7 +44,7 @@ class Params(C.Structure):
                 ("ew_alpha", C.c_double), ("nside", C.c_int32), ("il_ntheta", C.c_int32),
                 ("il_nphi", C.c_int32), ("il_npsi", C.c_int32), ("il_nr", C.c_int32),
                 ("il_nazi", C.c_int32), ("kappa", C.c_double), ("max_dist", C.c_double),
-                ("psi_max", C.c_double)]
+                ("psi_max", C.c_double), ("mlp_reach", C.c_double)]
 
 # defaults of the column machinery (App. B: tr_ilNTheta 25, tr_ilNPhi 50,
 # tr_ilNNS 25, tr_ilNR 50; azimuths and psi_max are this build's readings)
@@ -144,7 +144,7 @@ def bctype(bc):
 
 def make_params(grid, theta=0.5, eta_sb=1.2, mac="bh", a_lim=0.0, theta_pix=0.0, G=1.0,
                 ewald="exact", ew_n=64, ew_alpha=0.0, ew_rcut2=0, ew_fcut2=0, bc=None,
-                nside=0, kappa=1.0, max_dist=1e99, **cols):
+                nside=0, kappa=1.0, max_dist=1e99, mlp_reach=1.0, **cols):
     p = Params()
     for k in range(3):
         p.nroot[k] = int(grid.nroot[k])
@@ -156,6 +156,7 @@ def make_params(grid, theta=0.5, eta_sb=1.2, mac="bh", a_lim=0.0, theta_pix=0.0,
     p.ewald = {"exact": 0, "table": 1}[ewald]
     p.ew_n, p.ew_alpha, p.ew_rcut2, p.ew_fcut2 = ew_n, ew_alpha, ew_rcut2, ew_fcut2
     p.nside, p.kappa, p.max_dist = nside, kappa, max_dist
+    p.mlp_reach = mlp_reach
     c = dict(COLUMN_DEFAULTS, **cols)
     p.il_ntheta, p.il_nphi, p.il_npsi = c["il_ntheta"], c["il_nphi"], c["il_npsi"]
     p.il_nr, p.il_nazi, p.psi_max = c["il_nr"], c["il_nazi"], c["psi_max"]

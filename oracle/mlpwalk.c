@@ -10,8 +10,9 @@
  *
  *   1. For leaf block lb (cell size h) the group is the block-tree node of
  *      side 2^gl cells, gl the largest of 2, 1, 0 with (2^gl - 1) h / 2 <=
- *      tmax, tmax half the table's smallest grid spacing: its cells then lie
- *      within the table's own Taylor offset of the group centre c_g.
+ *      tmax, tmax = mlp_reach x half the table's smallest grid spacing: with
+ *      mlp_reach = 1 its cells lie within the table's own Taylor offset of
+ *      the group centre c_g.
  *   2. The block's interaction list is that of the group walk (or_block_list).
  *   3. Per (group, listed node): d0 = c_g - r_node, minimum image in periodic
  *      axes; network input x_k = 2 |d0_k| / ext_k - 1; output y_o sig_o +
@@ -53,7 +54,7 @@ int or_mlp_group_level(const or_tree *t, int64_t lb) {
   double tmax = e->step[0];
   for (int k = 1; k < 3; ++k)
     if (e->step[k] < tmax) tmax = e->step[k];
-  tmax = 0.5 * tmax;
+  tmax = (t->p.mlp_reach > 0.0 ? t->p.mlp_reach : 1.0) * (0.5 * tmax);
   const double h = or_size_at(t, t->blev[lb]) / 8.0;
   if ((3.0 * h) * 0.5 <= tmax) return 2;
   if ((1.0 * h) * 0.5 <= tmax) return 1;

@@ -38,6 +38,8 @@ typedef struct {
   double kappa;       /* opacity in tau_avg = -ln <exp(-kappa N)>            */
   double max_dist;    /* columns only from nodes closer than this            */
   double psi_max;     /* upper edge of the psi bins                          */
+  double mlp_reach;   /* surrogate walk: group cells within mlp_reach x half the
+                         table's smallest spacing of the group centre (<= 0: 1) */
 } or_params;
 
 typedef struct or_tree or_tree;

@@ -602,7 +602,8 @@ ot::MlpNorm mlp_norm_of(const ot_ctx *c) {
 // Largest Taylor offset per axis the surrogate walk allows (half the Ewald
 // table's smallest spacing) and the grid's largest cell size.
 double mlp_tmax(const ot_ctx *c) {
-  return 0.5 * std::min(c->ew_step[0], std::min(c->ew_step[1], c->ew_step[2]));
+  const double reach = c->p.mlp_reach > 0.0 ? c->p.mlp_reach : 1.0;
+  return reach * (0.5 * std::min(c->ew_step[0], std::min(c->ew_step[1], c->ew_step[2])));
 }
 double cell_size_max(const ot_ctx *c) {
   int lmin = c->topo.lmax;
@@ -876,6 +877,7 @@ void ot_params_default(ot_params *p) {
   p->kappa = 1.0;
   p->max_dist = 1e99;
   p->psi_max = 0.98;
+  p->mlp_reach = 1.0;
 }
 
 ot_status ot_create(const ot_params *p, ot_ctx **out) {
@@ -895,6 +897,7 @@ ot_status ot_create(const ot_params *p, ot_ctx **out) {
     if (p->bc[k] != 0 && p->bc[k] != 1) return bad("bc must be 0 (isolated) or 1 (periodic)");
     c->box[k] = p->nroot[k] * p->root_size;
   }
+  if (!std::isfinite(p->mlp_reach)) return bad("mlp_reach must be finite");
   if (!(p->root_size > 0) || !std::isfinite(p->root_size)) return bad("root_size must be > 0");
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(p->origin[k])) return bad("origin must be finite");

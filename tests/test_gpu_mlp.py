@@ -422,8 +422,9 @@ def test_walk_with_surrogate(trained, name, grid):
     assert dphi <= 1e-4 * np.abs(pt).max() and da <= 1e-4 * np.abs(at).max()
 
 
+@pytest.mark.parametrize("reach", [1.0, 3.0])
 @pytest.mark.parametrize("name", list(BOXES))
-def test_surrogate_walk_vs_oracle(trained, name):
+def test_surrogate_walk_vs_oracle(trained, name, reach):
     """The device walk (network on FP16 matrix instructions, FP32 Taylor step
     and sums) against the oracle's FP64 walk with the same weights and the
     same grouping, cell by cell, on two sampled blocks of each of the deep
@@ -431,21 +432,25 @@ def test_surrogate_walk_vs_oracle(trained, name):
     the per-pair FP16 bound of the network (forward_with_bound, its maximum
     over the folded domain and over the blocks' own offsets, doubled) summed
     over the list's masses, through the Taylor step (|delta| <= reach), plus
-    the FP32 walk's rounding (1e-6 of max |Phi|, 1e-5 of max |a|)."""
+    the FP32 walk's rounding (1e-6 of max |Phi|, 1e-5 of max |a|).  With
+    mlp_reach 3 the groups may reach three times the table's Taylor offset
+    (4^3 groups already at h = 1/128)."""
     s_tr, _ = trained[name]
     params, norm = s_tr.mlp_get()
     bc, nroot = GRIDS[name]
     g = workloads.deep_amr(bc, nroot)
     rho = dev(g.rho.reshape(-1))
-    (pm, am), st, s = solve32(g, rho, "mlp", (params, norm))
+    (pm, am), st, s = solve32(g, rho, "mlp", (params, norm), mlp_reach=reach)
     # the same gravity when columns are on (the column walk leaves it to this walk)
-    (pc, ac, _, _), _, _ = solve32(g, rho, "mlp", (params, norm), nside=1)
+    (pc, ac, _, _), _, _ = solve32(g, rho, "mlp", (params, norm), nside=1, mlp_reach=reach)
     assert np.array_equal(pc, pm) and np.array_equal(ac, am)
     rng = np.random.default_rng(31)
     sel = np.sort(np.concatenate([rng.choice(np.nonzero(g.level == lv)[0], 2, replace=False)
                                   for lv in range(3, 8)]))
-    t = oracle.Tree(g, theta=0.5, ew_n=64)
+    t = oracle.Tree(g, theta=0.5, ew_n=64, mlp_reach=reach)
     assert sorted({t.mlp_group_level(b) for b in sel}) == [0, 1, 2]
+    if reach > 1:
+        assert all(t.mlp_group_level(b) == 2 for b in sel if g.level[b] == 5)
     pr, ar, nint = t.walk_group_mlp(params, norm, sel)
     cells = (512 * sel[:, None] + np.arange(512)).ravel()
     # the per-pair bound: its maximum over random folded offsets and the
@@ -461,7 +466,7 @@ def test_surrogate_walk_vs_oracle(trained, name):
     d = d[np.abs(d[:, 2]) <= extent(name)[2]]
     _, bnd = forward_with_bound(params, norm, d)
     B = 2 * bnd.max(0)
-    r = taylor_reach()
+    r = reach * taylor_reach()
     msum = np.array([ex["M"][t.block_list(b)].sum() for b in sel]).repeat(512)
     bphi = msum * (B[0] + 3 * r * B[1:4].max()) + 1e-6 * np.abs(pr).max()
     ba = msum * (B[1:4].max() + 3 * r * B[4:].max()) + 1e-5 * np.abs(ar).max()

@@ -43,12 +43,12 @@ def lognormal16(bc, nroot):
                           np.concatenate(rho), tuple(bc), "lognormal16")
 
 
-def group_level(h, step):
-    tmax = 0.5 * min(step)
+def group_level(h, step, reach=1.0):
+    tmax = reach * 0.5 * min(step)
     return 2 if 1.5 * h <= tmax else (1 if 0.5 * h <= tmax else 0)
 
 
-def closed_form(t, g, lb, ext_far):
+def closed_form(t, g, lb, ext_far, reach=1.0):
     """Phi [512], a [3, 512] of block lb by the closed form above."""
     ex = t.export()
     ids = t.block_list(lb)
@@ -58,7 +58,7 @@ def closed_form(t, g, lb, ext_far):
     h = g.root_size / 2.0 ** (g.level[lb] - 1) / 8
     n = 64
     step = np.array([0.5 * L[0], 0.5 * L[1], 0.5 * L[2] if per[2] else min(L[2], 2 * L[0])]) / (n - 1)
-    gl = group_level(h, step)
+    gl = group_level(h, step, reach)
     gs = 2 ** gl
     phi, acc = np.zeros(512), np.zeros((3, 512))
     ci = np.arange(512)
@@ -90,20 +90,21 @@ def closed_form(t, g, lb, ext_far):
     return phi, acc, gl
 
 
+@pytest.mark.parametrize("reach", [1.0, 3.0])
 @pytest.mark.parametrize("case", ["3p", "2p1i_far"])
-def test_constant_network_closed_form(case):
+def test_constant_network_closed_form(case, reach):
     if case == "3p":
         g = lognormal16((1, 1, 1), (1, 1, 1))
         ext = np.array([0.5, 0.5, 0.5])
     else:
         g = lognormal16((1, 1, 0), (1, 1, 5))  # box 1 x 1 x 5: pairs beyond |dz| = 2 Lx
         ext = np.array([0.5, 0.5, 2.0])
-    t = oracle.Tree(g, theta=0.5, ewald="table", ew_n=64)
+    t = oracle.Tree(g, theta=0.5, ewald="table", ew_n=64, mlp_reach=reach)
     params, norm = const_surrogate(ext)
     blocks = [0, 5, g.nb - 1]
     phi, acc, _ = t.walk_group_mlp(params, norm, blocks)
     for q, lb in enumerate(blocks):
-        pr, ar, gl = closed_form(t, g, lb, case != "3p")
+        pr, ar, gl = closed_form(t, g, lb, case != "3p", reach)
         assert t.mlp_group_level(lb) == gl
         sl = slice(512 * q, 512 * (q + 1))
         np.testing.assert_allclose(phi[sl], pr, rtol=1e-12)
@@ -125,3 +126,20 @@ def test_group_levels():
     assert group_level(1 / 128, [step] * 3) == 1
     assert group_level(1 / 256, [step] * 3) == 1
     assert group_level(1 / 512, [step] * 3) == 2
+
+
+def test_group_levels_with_reach():
+    """mlp_reach scales the allowed offset: at three times the table's Taylor
+    offset 16^3 per unit root (h = 1/128) already takes 4^3 groups (1.5 h =
+    0.0117 <= 3 x 0.5 x 0.5/63 = 0.0119), 8^3 per root (h = 1/64) 2^3, and a
+    reach <= 0 is the default."""
+    step = [0.5 / 63] * 3
+    assert group_level(1 / 128, step, 3.0) == 2
+    assert group_level(1 / 64, step, 3.0) == 1
+    assert group_level(1 / 32, step, 3.0) == 0
+    g = workloads.small_amr(bc=(1, 1, 1))
+    for reach in (3.0, 0.0):
+        t = oracle.Tree(g, theta=0.5, ewald="table", ew_n=64, mlp_reach=reach)
+        for lb in range(g.nb):
+            h = 1.0 / 2.0 ** (g.level[lb] - 1) / 8
+            assert t.mlp_group_level(lb) == group_level(h, step, reach if reach > 0 else 1.0)
