@@ -13,6 +13,9 @@ cell delta = x - c_g, d = d0 + delta,
 A mistake in the group rule or geometry, the image, a sign, a transposed H
 or the far-field switch changes the result far above rounding.
 """
+import os
+import shutil
+
 import numpy as np
 import pytest
 
@@ -20,6 +23,11 @@ import oracle
 import workloads
 
 CH = np.array([0.7, 0.3, -0.2, 0.5, 1.1, -0.6, 0.9, 0.25, -0.35, 0.15])  # phi_c, A_c, H xx yy zz xy xz yz
+# Ewald table points per axis of the closed-form cases: a coarse 8^3 table
+# (half spacing 0.5/7/2 = 0.036) puts the grids' cells (h = 1/16) in 2^3
+# groups at reach 1 and 4^3 groups at reach 3, so the Taylor step from the
+# group centre (delta up to 1.5 h per axis) is part of what is checked
+EW_N = 8
 
 
 def const_surrogate(ext):
@@ -56,7 +64,7 @@ def closed_form(t, g, lb, ext_far, reach=1.0):
     L = np.asarray(g.nroot, float) * g.root_size
     per = np.asarray(g.bc, bool)
     h = g.root_size / 2.0 ** (g.level[lb] - 1) / 8
-    n = 64
+    n = EW_N
     step = np.array([0.5 * L[0], 0.5 * L[1], 0.5 * L[2] if per[2] else min(L[2], 2 * L[0])]) / (n - 1)
     gl = group_level(h, step, reach)
     gs = 2 ** gl
@@ -99,13 +107,14 @@ def test_constant_network_closed_form(case, reach):
     else:
         g = lognormal16((1, 1, 0), (1, 1, 5))  # box 1 x 1 x 5: pairs beyond |dz| = 2 Lx
         ext = np.array([0.5, 0.5, 2.0])
-    t = oracle.Tree(g, theta=0.5, ewald="table", ew_n=64, mlp_reach=reach)
+    t = oracle.Tree(g, theta=0.5, ewald="table", ew_n=EW_N, mlp_reach=reach)
     params, norm = const_surrogate(ext)
     blocks = [0, 5, g.nb - 1]
     phi, acc, _ = t.walk_group_mlp(params, norm, blocks)
     for q, lb in enumerate(blocks):
         pr, ar, gl = closed_form(t, g, lb, case != "3p", reach)
         assert t.mlp_group_level(lb) == gl
+        assert gl == (1 if reach == 1.0 else 2)
         sl = slice(512 * q, 512 * (q + 1))
         np.testing.assert_allclose(phi[sl], pr, rtol=1e-12)
         assert np.abs(acc[:, sl] - ar).max() <= 1e-12 * np.abs(ar).max()
@@ -143,3 +152,39 @@ def test_group_levels_with_reach():
         for lb in range(g.nb):
             h = 1.0 / 2.0 ** (g.level[lb] - 1) / 8
             assert t.mlp_group_level(lb) == group_level(h, step, reach if reach > 0 else 1.0)
+
+
+# planted mistakes in copies of the oracle's surrogate walk, each of which the
+# closed form must catch
+MUTANTS = {
+    "A_c . delta with the wrong sign": (
+        "p = 1.0 / r + (v[0] - (v[1] * dl[0] + v[2] * dl[1] + v[3] * dl[2]));",
+        "p = 1.0 / r + (v[0] + (v[1] * dl[0] + v[2] * dl[1] + v[3] * dl[2]));"),
+    "H_c with a transposed index": (
+        "static const int hidx[3][3] = {{4, 7, 8}, {7, 5, 9}, {8, 9, 6}};",
+        "static const int hidx[3][3] = {{4, 8, 7}, {7, 5, 9}, {8, 9, 6}};"),
+    "xy second derivative's sign not restored": ("v[7] *= s[0] * s[1];", "v[7] *= s[0];"),
+}
+
+
+@pytest.fixture(scope="module")
+def mutant_libs(tmp_path_factory):
+    src = open(os.path.join(oracle.HERE, "mlpwalk.c")).read()
+    libs = {}
+    for name, (old, new) in MUTANTS.items():
+        assert src.count(old) == 1, name
+        d = tmp_path_factory.mktemp("mutant")
+        for f in os.listdir(oracle.HERE):
+            if f.endswith((".c", ".h")):
+                shutil.copy(os.path.join(oracle.HERE, f), d)
+        (d / "mlpwalk.c").write_text(src.replace(old, new))
+        libs[name] = oracle.build(src_dir=str(d), out=str(d / "liboracle_mutant.so"))
+    return libs
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_closed_form_catches_planted_mistakes(mutant_libs, name):
+    with oracle.using_library(mutant_libs[name]):
+        with pytest.raises(AssertionError):
+            test_constant_network_closed_form("3p", 1.0)
+
