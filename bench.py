@@ -138,7 +138,8 @@ def timed_steps(solver, rho, outs, fp64, steps, warmup):
 
 def surrogate_leg(grid, rho, steps, nside=0):
     """Same field with 3P boundaries and the same MAC: the FP32 walk with the
-    learned correction beside the FP32 and FP64 table walks.  Training (on the
+    learned correction (cell groups at the table's Taylor offset, and reaching
+    three times as far) beside the FP32 and FP64 table walks.  Training (on the
     device, before timing) is reported, not timed as part of a step."""
     import torch
     import paper_1708_06142_amd as ot
@@ -158,11 +159,12 @@ def surrogate_leg(grid, rho, steps, nside=0):
     params, norm = sm.mlp_get()
     sm.close()
     res = {}
-    legs = [("mlp_fp32", "mlp", False, 0), ("table_fp32", "table", False, 0), ("table_fp64", "table", True, 0)]
+    legs = [("mlp_fp32", "mlp", False, 0, 1.0), ("mlp_fp32_reach3", "mlp", False, 0, 3.0),
+            ("table_fp32", "table", False, 0, 1.0), ("table_fp64", "table", True, 0, 1.0)]
     if nside:
-        legs += [("mlp_fp32_cols", "mlp", False, nside), ("table_fp64_cols", "table", True, nside)]
-    for label, mode, fp64, ns in legs:
-        s = ot.Solver.for_grid(g, mac="ape", a_lim=a_lim, theta=0.5, ewald=mode, nside=ns)
+        legs += [("mlp_fp32_cols", "mlp", False, nside, 1.0), ("table_fp64_cols", "table", True, nside, 1.0)]
+    for label, mode, fp64, ns, reach in legs:
+        s = ot.Solver.for_grid(g, mac="ape", a_lim=a_lim, theta=0.5, ewald=mode, nside=ns, mlp_reach=reach)
         if mode == "mlp":
             s.mlp_set(params, norm, accept=bool(rep["ok"]))
         kw = f64 if fp64 else f32
@@ -189,7 +191,7 @@ def surrogate_leg(grid, rho, steps, nside=0):
             e["da_maxnorm_vs_fp64_table"] = float(np.abs(r["acc"] - ref["acc"]).max() / amax)
         if "npix" in r and label != "table_fp64_cols":
             e["dnpix_maxnorm_vs_fp64"] = float(np.abs(r["npix"] - ref["npix"]).max() / np.abs(ref["npix"]).max())
-        if label == "mlp_fp32":
+        if label.startswith("mlp_fp32") and not label.endswith("_cols"):
             e["roofline"] = mlp_roofline(st)
             e["n_mlp_evals"] = st.n_mlp_evals
         out[label] = e
