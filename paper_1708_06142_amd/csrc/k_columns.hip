@@ -947,14 +947,22 @@ __global__ __launch_bounds__(512) void k_eval_cols_mlp(DevTree T, EwaldP E, ColP
         }
       }
       __syncthreads();
-      // cell phase
+      // cell phase, software-pipelined by one entry: entry j + 1's gravity,
+      // bins and row-record load are issued before entry j's map update, so
+      // the record's latency overlaps the map's read-modify-write (the order
+      // of every sum is that of the plain loop)
       const int mc = mt - j0 < CH ? mt - j0 : CH;
-      for (int j = 0; j < mc; ++j) {
-        const ColRec r = tile[j0 + j];
+      struct PendingRow {
+        uint4 pq, wq;  // the row's four-slot record
+        float base;    // M / (r^2 omega), 0 outside the column reach
+        bool col;
+      };
+      auto row_stage = [&](int jj) {
+        const ColRec r = tile[j0 + jj];
         // gravity: Newtonian part and the Taylor step from the group's channels
         float r2, inv;
         {
-          const float4 *o = reinterpret_cast<const float4 *>(slot + TSLOT * (j * G + mg));
+          const float4 *o = reinterpret_cast<const float4 *>(slot + TSLOT * (jj * G + mg));
           const float4 v0 = o[0], v1 = o[1], v2 = o[2], v3 = o[3];
           const float dx = v2.z + dlx, dy = v2.w + dly, dz = v3.x + dlz;
           r2 = dx * dx + dy * dy + dz * dz;
@@ -1006,8 +1014,17 @@ __global__ __launch_bounds__(512) void k_eval_cols_mlp(DevTree T, EwaldP E, ColP
         const char *const rq8 = reinterpret_cast<const char *>(C.rows8) + ((uint32_t)e << 5);
         const uint4 pq = *reinterpret_cast<const uint4 *>(rq8);
         const uint4 wq = *reinterpret_cast<const uint4 *>(rq8 + 16);
-        const float mr2 = (col ? r.m : 0.0f) * rd * rd;  // M / r^2
-        const float base = mr2 * inv_omega;
+        PendingRow p;
+        p.pq = pq;
+        p.wq = wq;
+        p.base = (col ? r.m : 0.0f) * rd * rd * inv_omega;
+        p.col = col;
+        return p;
+      };
+      auto map_stage = [&](const PendingRow &p) {
+        const uint4 pq = p.pq, wq = p.wq;
+        const float base = p.base;
+        const bool col = p.col;
         const float w0 = __uint_as_float(wq.x), w1 = __uint_as_float(wq.y), w2 = __uint_as_float(wq.z),
                     w3 = __uint_as_float(wq.w);
         float *const p0 = reinterpret_cast<float *>(mcell + (pq.x << lmap));
@@ -1040,6 +1057,13 @@ __global__ __launch_bounds__(512) void k_eval_cols_mlp(DevTree T, EwaldP E, ColP
           dq_base[0] = base;
           ++dq_n;
         }
+      };
+      PendingRow cur = row_stage(0);
+      for (int j = 0; j < mc; ++j) {
+        PendingRow nxt = cur;
+        if (j + 1 < mc) nxt = row_stage(j + 1);
+        map_stage(cur);
+        cur = nxt;
       }
     }
     for (int k = 0; k < DQ; ++k)
