@@ -94,6 +94,7 @@ def parse():
     ap.add_argument("--no-mpe", action="store_true", help="skip the MPE MAC leg")
     ap.add_argument("--no-abu", action="store_true", help="skip the adaptive block update leg")
     ap.add_argument("--no-p1", action="store_true", help="skip the 1P2I filament leg")
+    ap.add_argument("--no-cyl", action="store_true", help="skip the isothermal-cylinder accuracy leg")
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the Plummer AMR leg (2.6M cells, box 1x1x4, 2P1I, 64^3 Ewald table)")
     return ap.parse_args()
@@ -431,6 +432,48 @@ def p1_leg(steps):
     return out
 
 
+def cylinder_leg():
+    """Isothermal cylinder in hydrostatic equilibrium (Sec. 3.1.4) at the
+    paper's resolution, 256 x 128 x 128 cells, 1P2I with the 64^3 table: the
+    FP32-Kahan walk's radial acceleration against the closed form
+    g(R) = 2 pi G rho0 R / (1 + R^2 / r0^2) for the MAC settings of the paper's
+    acceleration runs (APE 1e-3 and 1e-2, BH theta 0.5; the APE limits are
+    absolute, that fraction of max g).  e_a,max is the largest relative error
+    per cell between 2h from the axis and 2h inside the cut-off; e_a,max/gmax
+    the largest error over max g."""
+    import torch
+    import paper_1708_06142_amd as ot
+    import workloads
+    n, r0 = 128, 1.0
+    g = workloads.iso_cylinder(n=n, r0=r0)
+    rc = g.meta["rcyl"]
+    x = workloads.cell_centres(1.0, g.origin, g.level, g.coord).reshape(-1, 3)
+    dy, dz = x[:, 1] - 0.5, x[:, 2] - 0.5
+    R = np.hypot(dy, dz)
+    gan = 2 * np.pi * R / (1 + R * R / (r0 * r0))
+    gmax = float(gan[R <= rc].max())
+    sel = (R >= 2.0 / n) & (R <= rc - 2.0 / n)
+    rho = torch.from_numpy(g.rho.reshape(-1)).cuda()
+    nc = g.ncells
+    out = {"workload": f"isothermal cylinder r0 {r0}, cut off at {rc}, box 2x1x1, 256x128x128 cells "
+                       f"({g.nb} blocks), 1P2I, 64^3 Ewald table, FP32-Kahan walk", "gmax": gmax}
+    for label, kw in (("ape_1e-3", dict(mac="ape", a_lim=1e-3 * gmax)), ("ape_1e-2", dict(mac="ape", a_lim=1e-2 * gmax)),
+                      ("bh_0.5", dict(theta=0.5))):
+        s = ot.Solver.for_grid(g, ewald_n=64, **kw)
+        outs = (torch.empty(nc, device="cuda"), torch.empty(3 * nc, device="cuda"))
+        ms, st, ms_eval, _, _ = timed_steps(s, rho, outs, False, 2, 1)
+        s.close()
+        a = outs[1].view(3, -1).double().cpu().numpy()
+        err = (a[1][sel] * dy[sel] + a[2][sel] * dz[sel]) / R[sel] + gan[sel]
+        out[label] = {"e_a_max": float((np.abs(err) / gan[sel]).max()),
+                      "e_a_median": float(np.median(np.abs(err) / gan[sel])),
+                      "e_a_max_over_gmax": float(np.abs(err).max() / gmax),
+                      "axial_over_gmax": float(np.abs(a[0]).max() / gmax),
+                      "ms_per_step": ms, "pairs_per_cell": st.n_interactions / nc}
+    progress("isothermal cylinder leg done")
+    return out
+
+
 def mpe_leg(grid, rho, a_lim, steps, nside):
     """The benchmark field with the MPE MAC (Eq. (2) with p = 1) at the same
     absolute limit: the whole path (tree build with the B_2, B_3 moments,
@@ -694,9 +737,12 @@ def main():
         del rho2
     if not args.no_c3:
         out["c3"] = c3_leg(4)
-        progress("filament leg done")
+        progress("Plummer AMR leg done")
     if not args.no_p1:
         out["p1"] = p1_leg(4)
+        progress("filament leg done")
+    if not args.no_cyl:
+        out["cylinder"] = cylinder_leg()
     print(json.dumps(out))
 
 

@@ -159,6 +159,31 @@ def filament_1p2i(n=64, seed=13, H=0.1, amp=0.3, noise=0.5):
                 name=f"filament{n}", meta={"seed": seed, "H": H})
 
 
+def iso_cylinder(n=32, r0=0.25, rcyl=0.45, amb=1.0 / 2500.0, sub=8):
+    """Isothermal cylinder in hydrostatic equilibrium (Sec. 3.1.4): the
+    profile rho0 / (1 + R^2 / r0^2)^2 (rho0 = 1) about the line y = z = 0.5 of
+    a 2 x 1 x 1 box (roots 2 x 1 x 1, x periodic, y and z isolated), cut off
+    at R = rcyl and embedded in an ambient medium of ``amb`` times the edge
+    density (the paper's sound-speed ratio 0.2 / 10 squared).  Each cell holds
+    the mean of the profile over ``sub`` x ``sub`` points of its (y, z)
+    square (the profile does not depend on x), so the cells' masses follow
+    the continuous profile across its edge.  n cells per root edge
+    (2n x n x n cells)."""
+    nroot = (2, 1, 1)
+    level, coord = uniform_blocks(n, nroot)
+    h = 1.0 / n
+    xc = cell_centres(1.0, (0.0, 0.0, 0.0), level, coord)
+    off = (np.arange(sub) + 0.5) / sub - 0.5
+    edge = 1.0 / (1.0 + rcyl * rcyl / (r0 * r0)) ** 2
+    rho = np.zeros(xc.shape[:-1])
+    for oy in off:
+        for oz in off:
+            r2 = (xc[..., 1] + oy * h - 0.5) ** 2 + (xc[..., 2] + oz * h - 0.5) ** 2
+            rho += np.where(r2 <= rcyl * rcyl, 1.0 / (1.0 + r2 / (r0 * r0)) ** 2, amb * edge)
+    return Grid(nroot, 1.0, (0.0, 0.0, 0.0), level, coord, rho / (sub * sub), (1, 0, 0),
+                name=f"iso_cylinder{n}", meta={"r0": r0, "rcyl": rcyl, "amb": amb})
+
+
 # ---------------------------------------------------------------- AMR
 def _key(l, c):
     return (int(l), int(c[0]), int(c[1]), int(c[2]))
