@@ -101,6 +101,9 @@ def _load(path):
     L.or_raytable_export.restype = i64
     L.or_raytable_export.argtypes = [C.c_int] * 6 + [C.c_double, vp, vp, vp]
     L.or_walk_percell.argtypes = [vp, i64, vp, vp, vp, vp]
+    L.or_point_list.restype = i64
+    L.or_point_list.argtypes = [vp, vp, vp, i64]
+    L.or_walk_points.argtypes = [vp, i64, vp, vp, vp, vp]
     L.or_direct.argtypes = [vp, i64, vp, vp, vp]
     L.or_morton.restype = C.c_uint64
     L.or_morton.argtypes = [C.c_uint64] * 3
@@ -294,6 +297,23 @@ class Tree:
         tg = np.ascontiguousarray(targets, dtype=np.int64)
         phi, acc, nint = np.empty(tg.size), np.empty((3, tg.size)), np.empty(tg.size, np.int64)
         lib().or_walk_percell(self.h, tg.size, _ptr(tg), _ptr(phi), _ptr(acc), _ptr(nint))
+        return phi, acc, nint
+
+    def point_list(self, x):
+        """Interaction list of one target point (Sec. 2.1, MAC at the point)."""
+        xp = np.ascontiguousarray(x, dtype=np.float64).reshape(3)
+        n = lib().or_point_list(self.h, _ptr(xp), None, 0)
+        ids = np.empty(n, np.int64)
+        lib().or_point_list(self.h, _ptr(xp), _ptr(ids), n)
+        return ids
+
+    def walk_points(self, xyz):
+        """Potential [n], acceleration [3, n] and list lengths [n] at arbitrary
+        target points xyz [n, 3], each walked with its own list."""
+        p = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        n = p.shape[0]
+        phi, acc, nint = np.empty(n), np.empty((3, n)), np.empty(n, np.int64)
+        lib().or_walk_points(self.h, n, _ptr(p), _ptr(phi), _ptr(acc), _ptr(nint))
         return phi, acc, nint
 
     def direct(self, targets=None):

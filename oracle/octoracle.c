@@ -667,6 +667,32 @@ void or_walk_group(const or_tree *t, double *phi, double *acc, int64_t *nint) {
   free(sel);
 }
 
+/* Sec. 2.1: the tree walked for one target point, the MAC suite evaluated at
+ * the point itself (a target box of half-extent 0). */
+static idlist point_list(const or_tree *t, const double x[3]) {
+  idlist l = {0, 0, 0};
+  for (int64_t r = 0; r < t->nroots; ++r) visit(t, t->roots[r], x, 0.0, &l);
+  return l;
+}
+
+/* Interaction list of one target point (ids, walk order). */
+int64_t or_point_list(const or_tree *t, const double x[3], int64_t *out, int64_t cap) {
+  idlist l = point_list(t, x);
+  int64_t n = l.n;
+  if (out) for (int64_t i = 0; i < n && i < cap; ++i) out[i] = l.v[i];
+  free(l.v);
+  return n;
+}
+
+/* Potential and acceleration at one target point from its own list; a cell
+ * whose centre is the point itself is skipped. */
+static void walk_point(const or_tree *t, const double x[3], double *phi, double a[3], int64_t *nint) {
+  idlist l = point_list(t, x);
+  sum_list(t, x, l.v, l.n, phi, a, NULL);
+  *nint = l.n;
+  free(l.v);
+}
+
 /* Paper-literal walk: one depth-first traversal per target cell (point MAC).
  * Targets are global cell indices 512*lb + ci. */
 void or_walk_percell(const or_tree *t, int64_t ntg, const int64_t *tg, double *phi,
@@ -676,14 +702,27 @@ void or_walk_percell(const or_tree *t, int64_t ntg, const int64_t *tg, double *p
     int64_t lb = tg[q] / 512;
     int ci = (int)(tg[q] % 512);
     double x[3], ph, a[3];
+    int64_t n;
     or_cell_centre(t, lb, ci, x);
-    idlist l = {0, 0, 0};
-    for (int64_t r = 0; r < t->nroots; ++r) visit(t, t->roots[r], x, 0.0, &l);
-    sum_list(t, x, l.v, l.n, &ph, a, NULL);
+    walk_point(t, x, &ph, a, &n);
     phi[q] = ph;
     for (int k = 0; k < 3; ++k) acc[k * ntg + q] = a[k];
-    if (nint) nint[q] = l.n;
-    free(l.v);
+    if (nint) nint[q] = n;
+  }
+}
+
+/* The same walk at arbitrary target points xyz [n][3] (the position of a sink
+ * particle, say); outputs phi [n], acc [3][n]. */
+void or_walk_points(const or_tree *t, int64_t n, const double *xyz, double *phi, double *acc,
+                    int64_t *nint) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t q = 0; q < n; ++q) {
+    double ph, a[3];
+    int64_t m;
+    walk_point(t, xyz + 3 * q, &ph, a, &m);
+    phi[q] = ph;
+    for (int k = 0; k < 3; ++k) acc[k * n + q] = a[k];
+    if (nint) nint[q] = m;
   }
 }
 

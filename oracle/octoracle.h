@@ -55,6 +55,11 @@ void or_tree_mpe_export(const or_tree *t, double *B2, double *B3);
 /* adaptive block update of the group walk (gravity only), Sec. 2.2.6 */
 void or_walk_group_abu(const or_tree *t, const double *prev_phi, const double *prev_acc, double tol,
                        const double *prev_npix, double tol_tau, double *phi, double *acc, int32_t *updated);
+/* the walk at arbitrary target points (Sec. 2.1): the list of one point, and
+ * phi [n], acc [3][n] at the points xyz [n][3] */
+int64_t or_point_list(const or_tree *t, const double x[3], int64_t *out, int64_t cap);
+void or_walk_points(const or_tree *t, int64_t n, const double *xyz, double *phi, double *acc,
+                    int64_t *nint);
 int64_t or_tree_na(const or_tree *t);
 int64_t or_tree_nn(const or_tree *t);
 #endif

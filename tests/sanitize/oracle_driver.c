@@ -176,6 +176,26 @@ static void exercise_tree(const or_params *p, const char *name) {
   CHECK(all_finite(ph4, 4) && all_finite(ac4, 12));
   or_direct(t, 4, tg, ph4, ac4);
   CHECK(all_finite(ph4, 4) && all_finite(ac4, 12));
+  {
+    /* arbitrary target points: the domain's lower corner, an interior point
+     * and a point a little inside the upper corner */
+    double xyz[9];
+    for (int k = 0; k < 3; ++k) {
+      const double L = p->nroot[k] * p->root_size;
+      xyz[k] = p->origin[k];
+      xyz[3 + k] = p->origin[k] + 0.37 * L;
+      xyz[6 + k] = p->origin[k] + 0.999 * L;
+    }
+    const int64_t len = or_point_list(t, xyz + 3, NULL, 0);
+    int64_t *ids = malloc(sizeof(int64_t) * (len > 0 ? len : 1));
+    CHECK(len > 0 && or_point_list(t, xyz + 3, ids, len) == len);
+    for (int64_t q = 0; q < len; ++q) CHECK(ids[q] >= 0 && ids[q] < nn);
+    free(ids);
+    double ph3[3], ac3[9];
+    int64_t ni3[3];
+    or_walk_points(t, 3, xyz, ph3, ac3, ni3);
+    CHECK(all_finite(ph3, 3) && all_finite(ac3, 9) && ni3[1] == len);
+  }
   const int64_t sel[2] = {1, nb - 1};
   double *sp = malloc(sizeof(double) * 1024), *sa = malloc(sizeof(double) * 3 * 1024);
   double *npix = NULL, *tau = NULL, *prev_npix = NULL;

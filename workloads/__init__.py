@@ -159,6 +159,23 @@ def filament_1p2i(n=64, seed=13, H=0.1, amp=0.3, noise=0.5):
                 name=f"filament{n}", meta={"seed": seed, "H": H})
 
 
+def target_points(grid, n, seed=23):
+    """Seeded target points [m, 3] inside the domain of ``grid`` (sink
+    particles, say): n uniform points, then the domain's lower corner, the
+    point one ulp inside its upper corner, the centres of the first cell of
+    the first and the last block, and a corner shared by eight cells of the
+    first block (a node centre)."""
+    rng = np.random.default_rng(seed)
+    org = np.asarray(grid.origin, np.float64)
+    L = np.asarray(grid.nroot, np.float64) * grid.root_size
+    pts = [org + rng.random((n, 3)) * L, org[None], np.nextafter(org + L, org)[None]]
+    xc = cell_centres(grid.root_size, grid.origin, grid.level, grid.coord)
+    pts += [xc[0, 0, 0, 0][None], xc[-1, 0, 0, 0][None]]
+    h = grid.root_size / 2.0 ** (int(grid.level[0]) + 2)
+    pts.append((org + 8 * h * np.asarray(grid.coord[0], np.float64) + 4 * h)[None])
+    return np.concatenate(pts)
+
+
 def iso_cylinder(n=32, r0=0.25, rcyl=0.45, amb=1.0 / 2500.0, sub=8):
     """Isothermal cylinder in hydrostatic equilibrium (Sec. 3.1.4): the
     profile rho0 / (1 + R^2 / r0^2)^2 (rho0 = 1) about the line y = z = 0.5 of
