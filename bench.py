@@ -95,6 +95,7 @@ def parse():
     ap.add_argument("--no-abu", action="store_true", help="skip the adaptive block update leg")
     ap.add_argument("--no-p1", action="store_true", help="skip the 1P2I filament leg")
     ap.add_argument("--no-cyl", action="store_true", help="skip the isothermal-cylinder accuracy leg")
+    ap.add_argument("--no-points", action="store_true", help="skip the target-point leg")
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the Plummer AMR leg (2.6M cells, box 1x1x4, 2P1I, 64^3 Ewald table)")
     return ap.parse_args()
@@ -432,6 +433,43 @@ def p1_leg(steps):
     return out
 
 
+def points_leg(g, rho, a_lim, npts=20000, steps=3):
+    """Gravity at arbitrary target points (sink particles, say; Sec. 2.1) on
+    the large AMR grid: 20,000 seeded points inside the domain, each walked
+    with its own list under the headline's MAC (APE a_lim; no columns), FP64
+    pair kernels with the 64^3 Ewald table."""
+    import torch
+    import paper_1708_06142_amd as ot
+    import workloads
+    x = torch.from_numpy(workloads.target_points(g, npts - 5, seed=31)).cuda()
+    n = x.shape[0]
+    s = ot.Solver.for_grid(g, mac="ape", a_lim=a_lim, theta=0.5, ewald_n=64)
+    s.build(rho)
+    phi = torch.empty(n, dtype=torch.float64, device="cuda")
+    acc = torch.empty((3, n), dtype=torch.float64, device="cuda")
+    s.solve_points(x, phi, acc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sts = [s.solve_points(x, phi, acc) for _ in range(steps)]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    s.close()
+    st = sts[-1]
+    ms_eval = float(np.mean([q.ms_eval for q in sts]))
+    flop = st.n_interactions * (FLOP_GRAV + FLOP_EWALD_TABLE) / (ms_eval * 1e-3) / 1e12
+    out = {"workload": f"{n} seeded points in the large AMR grid ({g.nb} blocks), 2P1I, APE a_lim {a_lim:.4g}, "
+                       "FP64, 64^3 Ewald table",
+           "value": n / (ms * 1e-3), "unit": "points/s", "ms_per_call": ms,
+           "phases_ms": {"lists": float(np.mean([q.ms_list for q in sts])), "eval": ms_eval},
+           "pairs_per_point": st.n_interactions / n, "max_list": st.max_list,
+           "finite": bool(torch.isfinite(phi).all() and torch.isfinite(acc).all()),
+           "roofline": {"bound": "alu", "kernel": "k_eval_points64<2P1I>", "achieved": flop,
+                        "peak": PEAK_FP64_VALU, "unit": "TFLOP/s", "frac": flop / PEAK_FP64_VALU,
+                        "flop_per_pair": FLOP_GRAV + FLOP_EWALD_TABLE}}
+    progress("target-point leg done")
+    return out
+
+
 def cylinder_leg():
     """Isothermal cylinder in hydrostatic equilibrium (Sec. 3.1.4) at the
     paper's resolution, 256 x 128 x 128 cells, 1P2I with the 64^3 table: the
@@ -707,6 +745,8 @@ def main():
         progress("FP64- and FP32-table walks done")
     else:
         o64 = None
+    if not args.no_points:
+        out["points"] = points_leg(g, rho, a_lim)
     torch.cuda.synchronize()
     if not args.no_direct or not args.no_cpu:
         t, tree_s = oracle_tree(g, kw, a_lim)

@@ -200,6 +200,29 @@ ot_status ot_solve_abu(ot_ctx *c, float *phi_dev, float *acc_dev, float *npix_de
 ot_status ot_solve_abu64(ot_ctx *c, double *phi_dev, double *acc_dev, double *npix_dev, double *tau_dev,
                          double tol, double tol_tau, int32_t *updated_host, ot_stats *stats_host, void *stream);
 
+/* Gravity at arbitrary target points, Sec. 2.1 (the walk for any target
+ * point, e.g. the position of a sink particle): each point gets its own list,
+ * the MAC suite of ot_solve evaluated at the point itself (the safe box about
+ * the node's geometric centre, BH / APE / MPE at the point's distance to the
+ * node's centre of mass; cells always accepted), and the FP64 pair kernels of
+ * ot_solve64 over it (Newtonian, plus the Ewald table or the far-field limit
+ * for periodic and mixed boundaries; the surrogate is not used here).  A cell
+ * whose centre coincides with a point is skipped, so at cell centres this is
+ * the paper's per-cell walk.  APE / MPE take the limit ot_solve uses (a_lim,
+ * or eps_lim times the BH pre-pass maximum).  Needs a successful ot_build.
+ * xyz_dev  [n][3] FP64 device positions, each inside the domain: origin <= x <
+ *          origin + nroot root_size on every axis (periodic ones too), else
+ *          OT_ERR_INVALID_ARG (also for NaN); read to the host once to check.
+ * phi_dev  [n] FP64 device output; acc_dev [3][n] FP64 device output
+ *          (component-major), both owned by the caller.
+ * n        0 <= n <= 2^31; n = 0 returns OT_OK and touches nothing.
+ * The lists of a successful call with n > 0 stay in the context until the
+ * next ot_solve_points (which drops them first, even when it fails), ot_build
+ * or ot_set_blocks (ot_export_point_list); stats: list lengths per point
+ * (n_interactions = total_list = entries summed over the points). */
+ot_status ot_solve_points(ot_ctx *c, int64_t n, const double *xyz_dev, double *phi_dev, double *acc_dev,
+                          ot_stats *stats_host, void *stream);
+
 /* Ewald correction table, Sec. 2.2.5 (second approach): phi_c = phi - 1/r,
  * A_c = A - d/r^3 and the six second derivatives of phi_c, FP64, on a
  * uniform n^3 grid over the folded domain [0, Lx/2] x [0, Ly/2] x
@@ -357,6 +380,8 @@ ot_status ot_export_topology(const ot_ctx *c, int32_t *level_host, int32_t *coor
 ot_status ot_export_moments(ot_ctx *c, double *M_host, double *com_host);
 /* Interaction list of leaf block b from the last solve (global node ids). */
 ot_status ot_export_list(ot_ctx *c, int64_t b, int32_t *ids_host, int64_t cap, int64_t *len);
+/* node ids of target point i's list from the last ot_solve_points (as above) */
+ot_status ot_export_point_list(ot_ctx *c, int64_t i, int32_t *ids_host, int64_t cap, int64_t *len);
 /* Ewald table (n^3 x 10 doubles, x fastest; channels phi_c, A_c[3],
  * H_xx, H_yy, H_zz, H_xy, H_xz, H_yz) after ot_ewald_prepare. */
 ot_status ot_export_ewald_table(ot_ctx *c, double *tab_host);

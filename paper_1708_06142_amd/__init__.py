@@ -105,6 +105,8 @@ def lib():
         L.ot_export_topology.argtypes = [vp, vp, vp, vp, vp, vp]
         L.ot_export_moments.argtypes = [vp, vp, vp]
         L.ot_export_list.argtypes = [vp, i64, vp, i64, C.POINTER(i64)]
+        L.ot_solve_points.argtypes = [vp, i64, vp, vp, vp, C.POINTER(Stats), vp]
+        L.ot_export_point_list.argtypes = [vp, i64, vp, i64, C.POINTER(i64)]
         L.ot_export_ewald_table.argtypes = [vp, vp]
         L.ot_mlp_config_default.argtypes = [C.POINTER(MlpConfig)]
         L.ot_mlp_train.argtypes = [vp, C.POINTER(MlpConfig), C.c_char_p, C.POINTER(MlpReport), vp]
@@ -122,6 +124,7 @@ def lib():
                      "ot_solve_abu64",
                      "ot_ewald_prepare", "ot_export_topology", "ot_export_moments",
                      "ot_export_list", "ot_export_ewald_table", "ot_export_raytable", "ot_mlp_train",
+                     "ot_solve_points", "ot_export_point_list",
                      "ot_mlp_get", "ot_mlp_set", "ot_mlp_grad", "ot_mlp_grad_noalloc", "ot_mlp_adam_step", "ot_ewald_points",
                      "ot_column_bins"):
             getattr(L, name).restype = C.c_int
@@ -244,6 +247,27 @@ class Solver:
         self._check(lib().ot_solve64(self.h, _dev_ptr(phi, f), _dev_ptr(acc, f), _dev_ptr(npix, f),
                                      _dev_ptr(tau, f), C.byref(st), _stream(stream)))
         return st
+
+    def solve_points(self, xyz, phi, acc, stream=None):
+        """Potential phi [n] and acceleration acc [3, n] (FP64 device tensors)
+        at n target points xyz [n, 3] (FP64, inside the domain), each walked
+        with its own list."""
+        import torch
+        f = torch.float64
+        n = xyz.numel() // 3
+        if xyz.numel() != 3 * n or phi.numel() != n or acc.numel() != 3 * n:
+            raise ValueError("need xyz [n, 3], phi [n] and acc [3, n]")
+        st = Stats()
+        self._check(lib().ot_solve_points(self.h, n, _dev_ptr(xyz, f), _dev_ptr(phi, f), _dev_ptr(acc, f),
+                                          C.byref(st), _stream(stream)))
+        return st
+
+    def export_point_list(self, i):
+        n = C.c_int64(0)
+        self._check(lib().ot_export_point_list(self.h, int(i), None, 0, C.byref(n)))
+        ids = np.empty(n.value, np.int32)
+        self._check(lib().ot_export_point_list(self.h, int(i), _np_ptr(ids), n.value, C.byref(n)))
+        return ids
 
     def solve_abu(self, phi, acc, tol, fp64=False, npix=None, tau=None, stream=None, tol_tau=None):
         """Adaptive block update: phi, acc (and npix, tau when nside > 0) hold

@@ -839,9 +839,127 @@ ot_status abu_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, void 
   return OT_OK;
 }
 
+// The walk at arbitrary target points (Sec. 2.1): a list per point with the
+// MAC suite at the point, then the FP64 pair kernels of the cell walks.
+ot_status points_impl(ot_ctx *c, int64_t n, const double *xyz, double *phi, double *acc, ot_stats *stats,
+                      void *stream) {
+  if (!c) return OT_ERR_INVALID_ARG;
+  c->err.clear();
+  c->npts = 0;  // the previous call's lists are gone whatever happens below
+  if (n < 0) return fail(c, OT_ERR_INVALID_ARG, "n must be >= 0");
+  if (n > ((int64_t)1 << 31)) return fail(c, OT_ERR_INVALID_ARG, "at most 2^31 target points per call");
+  if (n > 0 && (!xyz || !phi || !acc)) return fail(c, OT_ERR_INVALID_ARG, "xyz, phi and acc must be device pointers");
+  if (!c->built) return fail(c, OT_ERR_STATE, "ot_solve_points before a successful ot_build");
+  if (stats) memset(stats, 0, sizeof(*stats));
+  if (n == 0) return OT_OK;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->p.device));
+  // every point inside the domain: its offsets to the nodes then stay within
+  // the box on every isolated axis (the Ewald table's range)
+  {
+    std::vector<double> h(3 * (size_t)n);
+    HIPCHK(hipMemcpyAsync(h.data(), xyz, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int64_t i = 0; i < n; ++i)
+      for (int k = 0; k < 3; ++k) {
+        const double lo = c->p.origin[k], hi = lo + c->p.nroot[k] * c->p.root_size, x = h[3 * i + k];
+        if (!(x >= lo && x < hi))
+          return fail(c, OT_ERR_INVALID_ARG, "target point " + std::to_string(i) + " is not inside the domain");
+      }
+  }
+  if (c->bctype != ot::BC_ISO) {
+    if (c->p.ewald == OT_EWALD_EXACT)
+      return fail(c, OT_ERR_UNSUPPORTED, "per-pair exact Ewald series is not built into the walk");
+    OTCHK(ewald_prepare(c, nullptr, st));
+  }
+  double alim = 0.0;
+  if (c->p.mac == OT_MAC_APE || c->p.mac == OT_MAC_MPE) OTCHK(ape_limit(c, st, &alim));
+  for (int i = 0; i < 3; ++i)
+    if (!c->ev[i]) HIPCHK(hipEventCreate(&c->ev[i]));
+  const ot::Topology &t = c->topo;
+  ot::DevTree T = dev_tree(c);
+  const ot::MacP mp = mac_params(c, c->p.mac, alim, false);
+  int64_t capA = 0;
+  for (int l = 1; l <= t.lmax; ++l) capA = std::max(capA, t.level_begin[l + 1] - t.level_begin[l]);
+  const int64_t stride = 2 * capA + 9 * t.nb;
+  int64_t grid = std::min<int64_t>(n, 2048);
+  const int64_t budget = (int64_t)1 << 30;  // scratch bytes
+  while (grid > 64 && grid * stride * 4 > budget) grid /= 2;
+  OTCHK(dalloc(c, c->lscratch, (size_t)(grid * stride * 4)));
+  OTCHK(dalloc(c, c->pcount, n * sizeof(int32_t)));
+  OTCHK(dalloc(c, c->pnodes, 2 * n * sizeof(int32_t)));
+  OTCHK(dalloc(c, c->poff, (n + 1) * sizeof(int64_t)));
+  HIPCHK(hipEventRecord(c->ev[0], st));
+  HIPCHK(ot::launch_lists(false, T, mp, (int)grid, P<int32_t>(c->pcount), P<int32_t>(c->pnodes), nullptr, nullptr,
+                          nullptr, nullptr, P<int32_t>(c->lscratch), stride, capA, st, xyz, n));
+  HIPCHK(ot::launch_scan(P<int32_t>(c->pcount), n, P<int64_t>(c->poff), st));
+  int64_t total = 0;
+  HIPCHK(hipMemcpyAsync(&total, P<int64_t>(c->poff) + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  OTCHK(dalloc(c, c->prec, (size_t)total * sizeof(double4)));
+  OTCHK(dalloc(c, c->pid, (size_t)total * sizeof(int32_t)));
+  HIPCHK(ot::launch_lists(true, T, mp, (int)grid, P<int32_t>(c->pcount), nullptr, P<int64_t>(c->poff),
+                          P<double4>(c->prec), P<int32_t>(c->pid), nullptr, P<int32_t>(c->lscratch), stride, capA,
+                          st, xyz, n));
+  HIPCHK(hipEventRecord(c->ev[1], st));
+  HIPCHK(ot::launch_eval_points64(ewald_desc(c), n, xyz, P<int64_t>(c->poff), P<double4>(c->prec), phi, acc,
+                                  c->p.G, st));
+  HIPCHK(hipEventRecord(c->ev[2], st));
+  c->poff_host.resize(n + 1);
+  HIPCHK(hipMemcpyAsync(c->poff_host.data(), c->poff.ptr, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  std::vector<int32_t> nodes;
+  if (stats) {
+    nodes.resize(2 * n);
+    HIPCHK(hipMemcpyAsync(nodes.data(), c->pnodes.ptr, nodes.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  c->npts = n;
+  if (stats) {
+    int64_t mx = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t len = c->poff_host[i + 1] - c->poff_host[i];
+      mx = std::max(mx, len);
+      int k = 0;
+      while (k < 31 && ((int64_t)2 << k) <= len) ++k;
+      ++stats->list_hist[k];
+      stats->n_opened += nodes[2 * i];
+      stats->n_accepted += len - nodes[2 * i + 1];
+    }
+    stats->total_list = total;
+    stats->max_list = mx;
+    stats->n_interactions = total;
+    stats->a_lim_used = alim;
+    stats->ms_build = c->ms_build;
+    stats->ms_list = elapsed(c->ev[0], c->ev[1]);
+    stats->ms_eval = elapsed(c->ev[1], c->ev[2]);
+    stats->ewald_used = OT_EWALD_TABLE;
+  }
+  return OT_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+ot_status ot_solve_points(ot_ctx *c, int64_t n, const double *xyz, double *phi, double *acc, ot_stats *stats,
+                          void *stream) {
+  return points_impl(c, n, xyz, phi, acc, stats, stream);
+}
+
+ot_status ot_export_point_list(ot_ctx *c, int64_t i, int32_t *ids, int64_t cap, int64_t *len) {
+  if (!c) return OT_ERR_INVALID_ARG;
+  c->err.clear();
+  if (!len) return fail(c, OT_ERR_INVALID_ARG, "len must not be null");
+  if (i < 0 || i >= c->npts) return fail(c, OT_ERR_INVALID_ARG, "no such target point in the last ot_solve_points");
+  const int64_t o0 = c->poff_host[i], o1 = c->poff_host[i + 1];
+  *len = o1 - o0;
+  if (ids && cap > 0) {
+    const int64_t m = std::min(cap, o1 - o0);
+    HIPCHK(hipSetDevice(c->p.device));
+    HIPCHK(hipMemcpy(ids, P<int32_t>(c->pid) + o0, m * sizeof(int32_t), hipMemcpyDeviceToHost));
+  }
+  return OT_OK;
+}
 
 ot_status ot_solve_abu(ot_ctx *c, float *phi, float *acc, float *npix, float *tau, double tol, double tol_tau,
                        int32_t *updated_host, ot_stats *stats, void *stream) {
@@ -957,6 +1075,7 @@ ot_status ot_set_blocks(ot_ctx *c, int64_t nb, const int32_t *level, const int32
   c->dev_topo = false;
   c->built = false;
   c->lists_valid = false;
+  c->npts = 0;
   c->alim_valid = false;
   return OT_OK;
 }
@@ -970,6 +1089,7 @@ ot_status ot_build(ot_ctx *c, const double *rho, void *stream) {
   HIPCHK(hipSetDevice(c->p.device));
   c->built = false;
   c->lists_valid = false;
+  c->npts = 0;
   c->alim_valid = false;
   if (!c->dev_topo) OTCHK(upload_topology(c, st));
   for (int i = 0; i < 4; ++i)
@@ -1479,6 +1599,7 @@ void ot_destroy(ot_ctx *c) {
   DevBuf *all[] = {&c->alev, &c->acoord, &c->achild0, &c->aleaf, &c->blev,   &c->bcoord,
                    &c->bamr, &c->amc,    &c->aS,      &c->btmc,  &c->cm,     &c->flag,
                    &c->lcount, &c->lnodes, &c->llat, &c->loff, &c->lrec,    &c->lid,   &c->lscratch, &c->tab64,
+                   &c->pcount, &c->pnodes, &c->poff, &c->prec, &c->pid,
                    &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_rows, &c->rt_ent, &c->rt_rows8, &c->rt_quad64, &c->mpe_a, &c->mpe_b, &c->mpe_pnode, &c->mpe_pblock, &c->mpe_poff, &c->mpe_part, &c->abu_flag, &c->abu_blist, &c->rt_lut,
                    &c->rt_thr, &c->lh, &c->mlp_P, &c->mlp_pk, &c->mlp_part, &c->mlp_lossp,
                    &c->mlp_loss};

@@ -59,6 +59,10 @@ struct ot_ctx {
   ot::DevBuf abu_flag, abu_blist;  // adaptive block update: per-block flags, updated blocks
   // interaction lists
   ot::DevBuf lcount, lnodes, loff, lrec, lid, lscratch, llat;
+  // lists of the last ot_solve_points call (per target point)
+  ot::DevBuf pcount, pnodes, poff, prec, pid;
+  std::vector<int64_t> poff_host;
+  int64_t npts = 0;
   int64_t list_cap = 0;
   int64_t scratch_per_wg = 0;
   int list_grid = 0;

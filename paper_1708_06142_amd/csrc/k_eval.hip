@@ -127,6 +127,36 @@ __global__ __launch_bounds__(WG) void k_eval64(DevTree T, EwaldP E, const int64_
   }
 }
 
+// Target points (Sec. 2.1, the walk for an arbitrary target point): one wave
+// per point, its lanes take every 64th entry of the point's list with the FP64
+// pair kernel, then a butterfly adds the 64 partial sums.  A cell whose centre
+// is the point gives d = 0 and is skipped, as in the cell walks.
+template <int BC>
+__global__ __launch_bounds__(WG) void k_eval_points64(EwaldP E, int64_t n, const double *__restrict__ xyz,
+                                                      const int64_t *__restrict__ off,
+                                                      const double4 *__restrict__ rec, double *__restrict__ phi,
+                                                      double *__restrict__ acc, double negG) {
+  const int64_t i = (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;  // the whole wave
+  const double cx = xyz[3 * i], cy = xyz[3 * i + 1], cz = xyz[3 * i + 2];
+  double sp = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
+  const int64_t e = off[i + 1];
+  for (int64_t j = off[i] + lane; j < e; j += 64) pair64<BC>(E, cx, cy, cz, rec[j], sp, ax, ay, az);
+  for (int m = 32; m > 0; m >>= 1) {
+    sp += __shfl_xor(sp, m);
+    ax += __shfl_xor(ax, m);
+    ay += __shfl_xor(ay, m);
+    az += __shfl_xor(az, m);
+  }
+  if (lane == 0) {
+    phi[i] = negG * sp;
+    acc[i] = negG * ax;
+    acc[n + i] = negG * ay;
+    acc[2 * n + i] = negG * az;
+  }
+}
+
 // ---------------------------------------------------------------- FP32
 struct Acc32 {
   float s, c;  // Kahan sum of M phi and its compensation
@@ -315,6 +345,21 @@ hipError_t launch_eval64(const DevTree &T, const EwaldP &E, const int64_t *off, 
     default: if (split) OT_E64(3, 1); else OT_E64(3, 2); break;
   }
 #undef OT_E64
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_points64(const EwaldP &E, int64_t n, const double *xyz, const int64_t *off,
+                                const double4 *rec, double *phi, double *acc, double G, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((n + WG / 64 - 1) / (WG / 64))), blk(WG);
+#define OT_EP(B) hipLaunchKernelGGL((k_eval_points64<B>), grid, blk, 0, st, E, n, xyz, off, rec, phi, acc, -G)
+  switch (E.bctype) {
+    case 0: OT_EP(0); break;
+    case 1: OT_EP(1); break;
+    case 2: OT_EP(2); break;
+    default: OT_EP(3); break;
+  }
+#undef OT_EP
   return hipGetLastError();
 }
 

@@ -14,6 +14,11 @@
 // Cells are always accepted.  Compiled with FP contraction off so that the
 // accept/open decisions reproduce exactly.
 //
+// Target points (pts != null): the same traversal for each point, the target
+// box shrunk to the point (half-extent 0), as the paper's walk for an arbitrary
+// target point (a sink particle, say); count, off and the records are then
+// per point.
+//
 // Traversal: a persistent workgroup per target block, level-synchronous over
 // the amr-tree (frontier of amr nodes in global scratch), then over the +1
 // and +2 levels of opened leaf blocks.  Ballot prefix sums give every thread
@@ -118,7 +123,7 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
                                               double4 *__restrict__ rec, int32_t *__restrict__ ids,
                                               double *__restrict__ lh,
                                               int32_t *__restrict__ scratch, int64_t stride,
-                                              int64_t capA) {
+                                              int64_t capA, const double *__restrict__ pts, int64_t npts) {
   __shared__ int swave[3][NW];
   const int tid = threadIdx.x;
   int32_t *fa = scratch + (int64_t)blockIdx.x * stride;
@@ -127,13 +132,20 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
   int32_t *op1 = olb + T.nb;
   const int64_t na = T.na, nb = T.nb;
 
-  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+  const int64_t ntg = pts ? npts : nb;
+  for (int64_t b = blockIdx.x; b < ntg; b += gridDim.x) {
     Target tg;
-    const int blev = T.blev[b];
-    const double sb = size_at(T.root_size, blev);
-    for (int k = 0; k < 3; ++k) tg.c[k] = centre_coord(T.org[k], T.bcoord[3 * b + k], sb);
-    tg.ext = 3.5 * (sb / 8.0);
-    tg.h = sb / 8.0;
+    if (pts) {
+      for (int k = 0; k < 3; ++k) tg.c[k] = pts[3 * b + k];
+      tg.ext = 0.0;
+      tg.h = 0.0;
+    } else {
+      const int blev = T.blev[b];
+      const double sb = size_at(T.root_size, blev);
+      for (int k = 0; k < 3; ++k) tg.c[k] = centre_coord(T.org[k], T.bcoord[3 * b + k], sb);
+      tg.ext = 3.5 * (sb / 8.0);
+      tg.h = sb / 8.0;
+    }
     const int64_t base = FILL ? off[b] : 0;
     int64_t nemit = 0, nopened = 0, ncells = 0;
 
@@ -302,13 +314,13 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ count
 
 hipError_t launch_lists(bool fill, const DevTree &T, const MacP &P, int grid, int32_t *count, int32_t *nodes,
                         const int64_t *off, double4 *rec, int32_t *ids, double *lh, int32_t *scratch,
-                        int64_t stride, int64_t capA, hipStream_t st) {
+                        int64_t stride, int64_t capA, hipStream_t st, const double *pts, int64_t npts) {
   if (fill)
     hipLaunchKernelGGL(k_lists<true>, dim3(grid), dim3(WG), 0, st, T, P, count, nodes, off, rec, ids, lh,
-                       scratch, stride, capA);
+                       scratch, stride, capA, pts, npts);
   else
     hipLaunchKernelGGL(k_lists<false>, dim3(grid), dim3(WG), 0, st, T, P, count, nodes, off, rec, ids, lh,
-                       scratch, stride, capA);
+                       scratch, stride, capA, pts, npts);
   return hipGetLastError();
 }
 

@@ -132,10 +132,13 @@ hipError_t launch_build(const DevTree &T, const double *rho, int *bad,
                         const std::vector<int64_t> &level_begin, int lmax, hipStream_t st);
 
 // count pass (fill false): count [nb] list lengths and, when nodes is not
-// null, nodes [2 nb] = (opened nodes, cells in the list) per block
+// null, nodes [2 nb] = (opened nodes, cells in the list) per block.  With
+// pts [npts][3] (device, FP64) the lists are those of the target points
+// instead, counts and offsets per point.
 hipError_t launch_lists(bool fill, const DevTree &T, const MacP &P, int grid, int32_t *count, int32_t *nodes,
                         const int64_t *off, double4 *rec, int32_t *ids, double *lh, int32_t *scratch,
-                        int64_t scratch_stride, int64_t capA, hipStream_t st);
+                        int64_t scratch_stride, int64_t capA, hipStream_t st, const double *pts = nullptr,
+                        int64_t npts = 0);
 
 hipError_t launch_scan(const int32_t *count, int64_t nb, int64_t *off, hipStream_t st);
 
@@ -143,6 +146,10 @@ hipError_t launch_scan(const int32_t *count, int64_t nb, int64_t *off, hipStream
 hipError_t launch_eval64(const DevTree &T, const EwaldP &E, const int64_t *off, const double4 *rec,
                          double *phi, double *acc, double G, hipStream_t st, const int32_t *blist = nullptr,
                          int64_t nblist = 0);
+// FP64 potential and acceleration at n target points xyz [n][3] from their
+// lists (off [n + 1], rec): phi [n], acc [3][n]
+hipError_t launch_eval_points64(const EwaldP &E, int64_t n, const double *xyz, const int64_t *off,
+                                const double4 *rec, double *phi, double *acc, double G, hipStream_t st);
 hipError_t launch_eval32(const DevTree &T, const EwaldP &E, const int64_t *off, const double4 *rec,
                          const int32_t *ids, float *phi, float *acc, double G, hipStream_t st,
                          const int32_t *blist = nullptr, int64_t nblist = 0);
