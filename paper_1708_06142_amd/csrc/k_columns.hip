@@ -947,10 +947,11 @@ __global__ __launch_bounds__(512) void k_eval_cols_mlp(DevTree T, EwaldP E, ColP
         }
       }
       __syncthreads();
-      // cell phase, software-pipelined by one entry: entry j + 1's gravity,
-      // bins and row-record load are issued before entry j's map update, so
-      // the record's latency overlaps the map's read-modify-write (the order
-      // of every sum is that of the plain loop)
+      // cell phase, software-pipelined by one entry: entry j's map reads are
+      // issued, then entry j + 1's gravity, bins and row-record load, then
+      // entry j's map writes, so the map reads' latency overlaps the next
+      // entry's arithmetic and the record's the map writes (the order of every
+      // sum is that of the plain loop)
       const int mc = mt - j0 < CH ? mt - j0 : CH;
       struct PendingRow {
         uint4 pq, wq;  // the row's four-slot record
@@ -1021,27 +1022,30 @@ __global__ __launch_bounds__(512) void k_eval_cols_mlp(DevTree T, EwaldP E, ColP
         p.col = col;
         return p;
       };
-      auto map_stage = [&](const PendingRow &p) {
+      // map values of a pending row's four slots (the padding slots, weight 0,
+      // are not read: they would cost traffic)
+      struct MapVals {
+        float v0, v1, v2, v3;
+      };
+      auto map_load = [&](const PendingRow &p) {
+        MapVals m;
+        m.v1 = m.v2 = m.v3 = 0.f;
+        m.v0 = *reinterpret_cast<const float *>(mcell + (p.pq.x << lmap));
+        if (__uint_as_float(p.wq.y) != 0.0f) m.v1 = *reinterpret_cast<const float *>(mcell + (p.pq.y << lmap));
+        if (__uint_as_float(p.wq.z) != 0.0f) m.v2 = *reinterpret_cast<const float *>(mcell + (p.pq.z << lmap));
+        if (__uint_as_float(p.wq.w) != 0.0f) m.v3 = *reinterpret_cast<const float *>(mcell + (p.pq.w << lmap));
+        return m;
+      };
+      auto map_store = [&](const PendingRow &p, const MapVals &m) {
         const uint4 pq = p.pq, wq = p.wq;
         const float base = p.base;
         const bool col = p.col;
         const float w0 = __uint_as_float(wq.x), w1 = __uint_as_float(wq.y), w2 = __uint_as_float(wq.z),
                     w3 = __uint_as_float(wq.w);
-        float *const p0 = reinterpret_cast<float *>(mcell + (pq.x << lmap));
-        float *const p1 = reinterpret_cast<float *>(mcell + (pq.y << lmap));
-        float *const p2 = reinterpret_cast<float *>(mcell + (pq.z << lmap));
-        float *const p3 = reinterpret_cast<float *>(mcell + (pq.w << lmap));
-        // the padding slots (weight 0) are skipped: they would cost traffic
-        const bool u1 = w1 != 0.0f, u2 = w2 != 0.0f, u3 = w3 != 0.0f;
-        float v1 = 0.f, v2 = 0.f, v3 = 0.f;
-        const float v0 = *p0;
-        if (u1) v1 = *p1;
-        if (u2) v2 = *p2;
-        if (u3) v3 = *p3;
-        *p0 = fmaf(w0, base, v0);
-        if (u1) *p1 = fmaf(w1, base, v1);
-        if (u2) *p2 = fmaf(w2, base, v2);
-        if (u3) *p3 = fmaf(w3, base, v3);
+        *reinterpret_cast<float *>(mcell + (pq.x << lmap)) = fmaf(w0, base, m.v0);
+        if (w1 != 0.0f) *reinterpret_cast<float *>(mcell + (pq.y << lmap)) = fmaf(w1, base, m.v1);
+        if (w2 != 0.0f) *reinterpret_cast<float *>(mcell + (pq.z << lmap)) = fmaf(w2, base, m.v2);
+        if (w3 != 0.0f) *reinterpret_cast<float *>(mcell + (pq.w << lmap)) = fmaf(w3, base, m.v3);
         if ((int)pq.x < 0 && col) {
           const uint32_t cnt = (pq.x >> 23) & 63u;
           const uint32_t o0 = (pq.y >> 23) | ((pq.z >> 23) << 9) | ((pq.w >> 23) << 18);
@@ -1060,9 +1064,10 @@ __global__ __launch_bounds__(512) void k_eval_cols_mlp(DevTree T, EwaldP E, ColP
       };
       PendingRow cur = row_stage(0);
       for (int j = 0; j < mc; ++j) {
+        const MapVals mv = map_load(cur);
         PendingRow nxt = cur;
         if (j + 1 < mc) nxt = row_stage(j + 1);
-        map_stage(cur);
+        map_store(cur, mv);
         cur = nxt;
       }
     }
