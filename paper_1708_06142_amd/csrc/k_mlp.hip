@@ -227,24 +227,27 @@ __global__ __launch_bounds__(256) void k_mlp_fwdbwd(const float *__restrict__ P,
   }
 }
 
-// Fixed-order sum of the workgroup partials: 64 parameters per block of four
-// waves, wave w summing partials w, w + 4, ..., the four sums added in wave
-// order; then either the gradient is stored or Adam updates the parameter.
-// The last block sums the per-workgroup losses (strided, then a fixed tree).
+// Fixed-order sum of the workgroup partials: 64 parameters per block of RW
+// waves, wave w summing partials w, w + RW, ..., the RW sums then added by a
+// fixed pairwise tree; then either the gradient is stored or Adam updates the
+// parameter.  The last block sums the per-workgroup losses (strided, then a
+// fixed tree).  Sixteen waves per block keep the few partials per lane in
+// flight together (the sum is latency-bound: 146 blocks for 9,226 parameters).
+constexpr int RW = 16;
 template <bool ADAM>
-__global__ __launch_bounds__(256) void k_mlp_reduce(int nwg, const float *__restrict__ partial,
-                                                    const float *__restrict__ lossp, float *__restrict__ grad,
-                                                    float *__restrict__ loss, float *__restrict__ P,
-                                                    float *__restrict__ m, float *__restrict__ v, float lr, float c1,
-                                                    float c2) {
-  __shared__ float red[256];
+__global__ __launch_bounds__(64 * RW) void k_mlp_reduce(int nwg, const float *__restrict__ partial,
+                                                       const float *__restrict__ lossp, float *__restrict__ grad,
+                                                       float *__restrict__ loss, float *__restrict__ P,
+                                                       float *__restrict__ m, float *__restrict__ v, float lr,
+                                                       float c1, float c2) {
+  __shared__ float red[64 * RW];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (blockIdx.x == gridDim.x - 1) {
     float l = 0.0f;
-    for (int q = threadIdx.x; q < nwg; q += 256) l += lossp[q];
+    for (int q = threadIdx.x; q < nwg; q += 64 * RW) l += lossp[q];
     red[threadIdx.x] = l;
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
+    for (int st = 32 * RW; st > 0; st >>= 1) {
       if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
       __syncthreads();
     }
@@ -254,11 +257,15 @@ __global__ __launch_bounds__(256) void k_mlp_reduce(int nwg, const float *__rest
   const int p = blockIdx.x * 64 + lane;
   float g = 0.0f;
   if (p < NP)
-    for (int q = w; q < nwg; q += 4) g += partial[(int64_t)q * NP + p];
+    for (int q = w; q < nwg; q += RW) g += partial[(int64_t)q * NP + p];
   red[threadIdx.x] = g;
   __syncthreads();
+  for (int st = RW / 2; st > 0; st >>= 1) {  // wave w += wave w + st
+    if (w < st) red[threadIdx.x] += red[threadIdx.x + 64 * st];
+    __syncthreads();
+  }
   if (w != 0 || p >= NP) return;
-  const float gs = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
+  const float gs = red[lane];
   if (!ADAM) {
     grad[p] = gs;
     return;
@@ -625,7 +632,7 @@ hipError_t launch_mlp_grad(const float *P, int64_t n, int64_t s0, int64_t batch,
                            float *partial, float *lossp, float *grad, float *loss, hipStream_t st) {
   hipError_t e = fwdbwd(P, n, s0, batch, X, T, partial, lossp, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mlp_reduce<false>, dim3(reduce_blocks()), dim3(256), 0, st, (int)(batch / SB), partial,
+  hipLaunchKernelGGL(k_mlp_reduce<false>, dim3(reduce_blocks()), dim3(64 * RW), 0, st, (int)(batch / SB), partial,
                      lossp, grad, loss, (float *)nullptr, (float *)nullptr, (float *)nullptr, 0.0f, 1.0f, 1.0f);
   return hipGetLastError();
 }
@@ -636,7 +643,7 @@ hipError_t launch_mlp_step(float *P, int64_t n, int64_t s0, int64_t batch, const
   hipError_t e = fwdbwd(P, n, s0, batch, X, T, partial, lossp, st);
   if (e != hipSuccess) return e;
   const float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);
-  hipLaunchKernelGGL(k_mlp_reduce<true>, dim3(reduce_blocks()), dim3(256), 0, st, (int)(batch / SB), partial,
+  hipLaunchKernelGGL(k_mlp_reduce<true>, dim3(reduce_blocks()), dim3(64 * RW), 0, st, (int)(batch / SB), partial,
                      lossp, (float *)nullptr, loss, P, m, v, lr, c1, c2);
   return hipGetLastError();
 }
