@@ -124,20 +124,35 @@ __global__ __launch_bounds__(256) void k_mlp_fwdbwd(const float *__restrict__ P,
     L.h1[s][o] = act(a);
   }
   __syncthreads();
-  for (int j = 0; j < SB / 4; ++j) {
-    const int s = s4 + 4 * j;
-    float a = P[OB2 + o];
-    for (int i = 0; i < H; ++i) a += L.w2[o * WP + i] * L.h1[s][i];
+  // two samples per thread, s4 and s4 + 4, sharing each weight read (each
+  // sum in the same order as one sample at a time)
+  static_assert(SB == 8, "two samples per thread below");
+  {
+    const int s = s4, u = s4 + 4;
+    float a = P[OB2 + o], c = a;
+    for (int i = 0; i < H; ++i) {
+      const float wv = L.w2[o * WP + i];
+      a += wv * L.h1[s][i];
+      c += wv * L.h1[u][i];
+    }
     L.z2[s][o] = a;
     L.h2[s][o] = act(a);
+    L.z2[u][o] = c;
+    L.h2[u][o] = act(c);
   }
   __syncthreads();
-  for (int j = 0; j < SB / 4; ++j) {
-    const int s = s4 + 4 * j;
-    float a = P[OB3 + o];
-    for (int i = 0; i < H; ++i) a += L.w3[o * WP + i] * L.h2[s][i];
+  {
+    const int s = s4, u = s4 + 4;
+    float a = P[OB3 + o], c = a;
+    for (int i = 0; i < H; ++i) {
+      const float wv = L.w3[o * WP + i];
+      a += wv * L.h2[s][i];
+      c += wv * L.h2[u][i];
+    }
     L.z3[s][o] = a;
     L.h3[s][o] = act(a);
+    L.z3[u][o] = c;
+    L.h3[u][o] = act(c);
   }
   __syncthreads();
   float lsum = 0.0f;
@@ -183,11 +198,16 @@ __global__ __launch_bounds__(256) void k_mlp_fwdbwd(const float *__restrict__ P,
     for (int s = 0; s < SB; ++s) gb += L.da[s][t];
     G[OB3 + t] = gb;
   }
-  for (int j = 0; j < SB / 4; ++j) {  // dZ2
-    const int s = s4 + 4 * j;
-    float a = 0.0f;
-    for (int oo = 0; oo < H; ++oo) a += L.da[s][oo] * L.w3[oo * WP + o];
+  {  // dZ2
+    const int s = s4, u = s4 + 4;
+    float a = 0.0f, c = 0.0f;
+    for (int oo = 0; oo < H; ++oo) {
+      const float wv = L.w3[oo * WP + o];
+      a += L.da[s][oo] * wv;
+      c += L.da[u][oo] * wv;
+    }
     L.db[s][o] = a * dact(L.z2[s][o]);
+    L.db[u][o] = c * dact(L.z2[u][o]);
   }
   __syncthreads();
   for (int j = 0; j < H / 4; ++j) {  // dW2
@@ -202,11 +222,16 @@ __global__ __launch_bounds__(256) void k_mlp_fwdbwd(const float *__restrict__ P,
     G[OB2 + t] = gb;
   }
   __syncthreads();  // da is overwritten next
-  for (int j = 0; j < SB / 4; ++j) {  // dZ1
-    const int s = s4 + 4 * j;
-    float a = 0.0f;
-    for (int oo = 0; oo < H; ++oo) a += L.db[s][oo] * L.w2[oo * WP + o];
+  {  // dZ1
+    const int s = s4, u = s4 + 4;
+    float a = 0.0f, c = 0.0f;
+    for (int oo = 0; oo < H; ++oo) {
+      const float wv = L.w2[oo * WP + o];
+      a += L.db[s][oo] * wv;
+      c += L.db[u][oo] * wv;
+    }
     L.da[s][o] = a * dact(L.z1[s][o]);
+    L.da[u][o] = c * dact(L.z1[u][o]);
   }
   __syncthreads();
   if (t < H * NI) {  // dW1
