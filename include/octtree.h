@@ -216,6 +216,8 @@ ot_status ot_solve_abu64(ot_ctx *c, double *phi_dev, double *acc_dev, double *np
  * phi_dev  [n] FP64 device output; acc_dev [3][n] FP64 device output
  *          (component-major), both owned by the caller.
  * n        0 <= n <= 2^31; n = 0 returns OT_OK and touches nothing.
+ * The traversal uses up to 4 GB of device scratch (kept by the context, as
+ * its other buffers).
  * The lists of a successful call with n > 0 stay in the context until the
  * next ot_solve_points (which drops them first, even when it fails), ot_build
  * or ot_set_blocks (ot_export_point_list); stats: list lengths per point

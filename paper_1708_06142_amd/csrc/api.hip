@@ -882,8 +882,10 @@ ot_status points_impl(ot_ctx *c, int64_t n, const double *xyz, double *phi, doub
   int64_t capA = 0;
   for (int l = 1; l <= t.lmax; ++l) capA = std::max(capA, t.level_begin[l + 1] - t.level_begin[l]);
   const int64_t stride = 2 * capA + 9 * t.nb;
-  int64_t grid = std::min<int64_t>(n, 2048);
-  const int64_t budget = (int64_t)1 << 30;  // scratch bytes
+  // one single-wave workgroup per point in flight, each with its own
+  // traversal scratch (sized for the worst case, every node opened)
+  int64_t grid = std::min<int64_t>(n, 8192);
+  const int64_t budget = (int64_t)4 << 30;  // scratch bytes
   while (grid > 64 && grid * stride * 4 > budget) grid /= 2;
   OTCHK(dalloc(c, c->lscratch, (size_t)(grid * stride * 4)));
   OTCHK(dalloc(c, c->pcount, n * sizeof(int32_t)));

@@ -17,7 +17,8 @@
 // Target points (pts != null): the same traversal for each point, the target
 // box shrunk to the point (half-extent 0), as the paper's walk for an arbitrary
 // target point (a sink particle, say); count, off and the records are then
-// per point.
+// per point, and each workgroup is a single wave (a point's frontiers are
+// small).
 //
 // Traversal: a persistent workgroup per target block, level-synchronous over
 // the amr-tree (frontier of amr nodes in global scratch), then over the +1
@@ -31,8 +32,10 @@ namespace ot {
 
 namespace {
 
+// threads per workgroup: 256 for a block's list; one wave for a target
+// point's, whose frontiers are small
 constexpr int WG = 256;
-constexpr int NW = WG / 64;
+constexpr int WG_POINT = 64;
 
 struct Target {
   double c[3];
@@ -83,6 +86,7 @@ struct Scan3 {
   int tot[3];
 };
 
+template <int NW>
 __device__ inline Scan3 scan3(bool f0, bool f1, bool f2, int (*swave)[NW]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -117,13 +121,14 @@ __device__ inline void emit(const DevTree &T, const Target &tg, int64_t pos, int
 // Count pass (FILL false): count[b] = list length of block b and, with
 // nodes != null, nodes[2 b] = nodes the MAC suite opened, nodes[2 b + 1] =
 // cells in the list (children of opened +2 nodes).
-template <bool FILL>
-__global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__restrict__ count,
+template <bool FILL, int WGS>
+__global__ __launch_bounds__(WGS) void k_lists(DevTree T, MacP P, int32_t *__restrict__ count,
                                               int32_t *__restrict__ nodes, const int64_t *__restrict__ off,
                                               double4 *__restrict__ rec, int32_t *__restrict__ ids,
                                               double *__restrict__ lh,
                                               int32_t *__restrict__ scratch, int64_t stride,
                                               int64_t capA, const double *__restrict__ pts, int64_t npts) {
+  constexpr int NW = WGS / 64;
   __shared__ int swave[3][NW];
   const int tid = threadIdx.x;
   int32_t *fa = scratch + (int64_t)blockIdx.x * stride;
@@ -151,12 +156,12 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
 
     // ---- amr-tree levels
     int32_t *cur = fa, *nxt = fb;
-    for (int i = tid; i < T.nroots; i += WG) cur[i] = i;
+    for (int i = tid; i < T.nroots; i += WGS) cur[i] = i;
     __syncthreads();
     int64_t ncur = T.nroots, nolb = 0;
     while (ncur > 0) {
       int64_t nnext = 0;
-      for (int64_t s0 = 0; s0 < ncur; s0 += WG) {
+      for (int64_t s0 = 0; s0 < ncur; s0 += WGS) {
         int64_t i = s0 + tid;
         bool acc = false, oi = false, ol = false;
         int32_t node = -1;
@@ -196,7 +201,7 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
 
     // ---- +1 nodes of opened leaf blocks
     int64_t nop1 = 0;
-    for (int64_t s0 = 0; s0 < 8 * nolb; s0 += WG) {
+    for (int64_t s0 = 0; s0 < 8 * nolb; s0 += WGS) {
       int64_t i = s0 + tid;
       bool acc = false, op = false;
       int32_t lb = 0, o1 = 0;
@@ -225,7 +230,7 @@ __global__ __launch_bounds__(WG) void k_lists(DevTree T, MacP P, int32_t *__rest
     __syncthreads();
 
     // ---- +2 nodes of opened +1 nodes; an opened +2 node emits its 8 cells
-    for (int64_t s0 = 0; s0 < 8 * nop1; s0 += WG) {
+    for (int64_t s0 = 0; s0 < 8 * nop1; s0 += WGS) {
       int64_t i = s0 + tid;
       bool acc = false, op = false;
       int32_t lb = 0, o1 = 0, o2 = 0;
@@ -315,12 +320,17 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ count
 hipError_t launch_lists(bool fill, const DevTree &T, const MacP &P, int grid, int32_t *count, int32_t *nodes,
                         const int64_t *off, double4 *rec, int32_t *ids, double *lh, int32_t *scratch,
                         int64_t stride, int64_t capA, hipStream_t st, const double *pts, int64_t npts) {
-  if (fill)
-    hipLaunchKernelGGL(k_lists<true>, dim3(grid), dim3(WG), 0, st, T, P, count, nodes, off, rec, ids, lh,
-                       scratch, stride, capA, pts, npts);
-  else
-    hipLaunchKernelGGL(k_lists<false>, dim3(grid), dim3(WG), 0, st, T, P, count, nodes, off, rec, ids, lh,
-                       scratch, stride, capA, pts, npts);
+#define OT_LISTS(F, W)                                                                                  \
+  hipLaunchKernelGGL((k_lists<F, W>), dim3(grid), dim3(W), 0, st, T, P, count, nodes, off, rec, ids, lh, scratch, \
+                     stride, capA, pts, npts)
+  if (pts) {
+    if (fill) OT_LISTS(true, WG_POINT);
+    else OT_LISTS(false, WG_POINT);
+  } else {
+    if (fill) OT_LISTS(true, WG);
+    else OT_LISTS(false, WG);
+  }
+#undef OT_LISTS
   return hipGetLastError();
 }
 
