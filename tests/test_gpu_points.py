@@ -7,7 +7,8 @@ and max |a| over the points).  Isolated, 3P, 2P1I and 1P2I small AMR grids
 with BH, APE and MPE, at seeded points that include the domain's lower corner,
 the point one ulp inside its upper corner, cell centres (where the cell itself
 is skipped) and a node centre; the 128^3 lognormal field with 20,000 points
-sampled against the oracle; n = 0; points outside the domain are refused.
+sampled against the oracle; n = 0; points outside the domain are refused; a
+context set up for the surrogate still evaluates points with the table.
 """
 import numpy as np
 import pytest
@@ -105,3 +106,19 @@ def test_points_edge_cases():
     p, a, st = solve_points(s, np.array([[0.5, 0.5, 0.5]]))
     assert np.isfinite(p).all() and st.total_list > 0
     s.close()
+
+
+def test_points_use_the_table_in_a_surrogate_context():
+    """A context set up for the surrogate walk evaluates target points with
+    the Ewald table all the same: the results equal a table context's."""
+    g = workloads.small_amr(**GRIDS["2p1i"])
+    x = workloads.target_points(g, 16)
+    outs = []
+    for ew in ("table", "mlp"):
+        s = ot.Solver.for_grid(g, ewald_n=EW_N, ewald=ew, **MACS["ape"])
+        s.build(dev(g.rho.reshape(-1)))
+        p, a, st = solve_points(s, x)
+        assert st.ewald_used == 0
+        outs.append((p, a))
+        s.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
