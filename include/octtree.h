@@ -10,14 +10,15 @@
  * gravitational potential and acceleration summed over monopole tree nodes
  * (Eqs. 7-8, with the Ewald forms of Sec. 2.2.3-2.2.4 for periodic or mixed
  * boundaries) and, optionally, the column density in each HEALPix direction
- * (Sec. 2.3).
+ * (Sec. 2.3).  The same tree can be walked for arbitrary target points
+ * (Sec. 2.1; ot_solve_points).
  *
  * Conventions for every call:
  *   - Pointers named *_dev are device pointers owned by the caller; the
  *     library never frees them.  Pointers named *_host are host memory.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
  *     their work on it and return after synchronising it, so results are ready
- *     when a call returns OT_OK.
+ *     when a call returns OT_OK (ot_mlp_grad_noalloc alone only enqueues).
  *   - Cell layout: cell (i, j, k) of leaf block b is element b*512 + i + 8 j
  *     + 64 k (x fastest); vector fields are structure-of-arrays, component c at
  *     c*nb*512 + b*512 + cell.
