@@ -18,7 +18,8 @@ LIB = os.path.join(HERE, "liboracle.so")
 SOURCES = ["octoracle.c", "ewald.c", "columns.c", "mlp.c", "mlpwalk.c"]
 
 ERRORS = {1: "bad level/coord", 2: "duplicate block", 3: "overlapping blocks",
-          4: "hole in the block tiling", 5: "bad density", 6: "unsupported BCs"}
+          4: "hole in the block tiling", 5: "bad density", 6: "unsupported BCs",
+          7: "list_group must be 0, 4 or 8"}
 
 
 def build(force=True, src_dir=HERE, out=LIB, extra=()):
@@ -44,7 +45,7 @@ class Params(C.Structure):
                 ("ew_alpha", C.c_double), ("nside", C.c_int32), ("il_ntheta", C.c_int32),
                 ("il_nphi", C.c_int32), ("il_npsi", C.c_int32), ("il_nr", C.c_int32),
                 ("il_nazi", C.c_int32), ("kappa", C.c_double), ("max_dist", C.c_double),
-                ("psi_max", C.c_double), ("mlp_reach", C.c_double)]
+                ("psi_max", C.c_double), ("mlp_reach", C.c_double), ("list_group", C.c_int32)]
 
 # defaults of the column machinery (App. B: tr_ilNTheta 25, tr_ilNPhi 50,
 # tr_ilNNS 25, tr_ilNR 50; azimuths and psi_max are this build's readings)
@@ -91,6 +92,8 @@ def _load(path):
     L.or_walk_group_abu.argtypes = [vp, vp, vp, C.c_double, vp, C.c_double, vp, vp, vp]
     L.or_block_list.restype = i64
     L.or_block_list.argtypes = [vp, i64, vp, i64]
+    L.or_group_list.restype = i64
+    L.or_group_list.argtypes = [vp, i64, C.c_int, vp, i64]
     L.or_walk_group.argtypes = [vp, vp, vp, vp]
     L.or_walk_group_blocks.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
     L.or_raymarch.argtypes = [vp, vp, i64, i64, i64, vp]
@@ -147,7 +150,7 @@ def bctype(bc):
 
 def make_params(grid, theta=0.5, eta_sb=1.2, mac="bh", a_lim=0.0, theta_pix=0.0, G=1.0,
                 ewald="exact", ew_n=64, ew_alpha=0.0, ew_rcut2=0, ew_fcut2=0, bc=None,
-                nside=0, kappa=1.0, max_dist=1e99, mlp_reach=1.0, **cols):
+                nside=0, kappa=1.0, max_dist=1e99, mlp_reach=1.0, list_group=8, **cols):
     p = Params()
     for k in range(3):
         p.nroot[k] = int(grid.nroot[k])
@@ -160,6 +163,7 @@ def make_params(grid, theta=0.5, eta_sb=1.2, mac="bh", a_lim=0.0, theta_pix=0.0,
     p.ew_n, p.ew_alpha, p.ew_rcut2, p.ew_fcut2 = ew_n, ew_alpha, ew_rcut2, ew_fcut2
     p.nside, p.kappa, p.max_dist = nside, kappa, max_dist
     p.mlp_reach = mlp_reach
+    p.list_group = list_group
     c = dict(COLUMN_DEFAULTS, **cols)
     p.il_ntheta, p.il_nphi, p.il_npsi = c["il_ntheta"], c["il_nphi"], c["il_npsi"]
     p.il_nr, p.il_nazi, p.psi_max = c["il_nr"], c["il_nazi"], c["psi_max"]
@@ -244,10 +248,21 @@ class Tree:
         lib().or_block_list(self.h, lb, _ptr(ids), n)
         return ids
 
+    def octant_list(self, lb, so):
+        """Interaction list of octant so (bit a: upper half of axis a) of
+        leaf block lb, the walk target of its 4^3 cells with list_group 4."""
+        if not 0 <= so < 8:
+            raise ValueError("octant must be in [0, 8)")
+        n = lib().or_group_list(self.h, lb, so, None, 0)
+        ids = np.empty(n, np.int64)
+        lib().or_group_list(self.h, lb, so, _ptr(ids), n)
+        return ids
+
     def walk_group(self, blocks=None, columns=False):
         """Group walk over all leaf blocks or a subset.  Returns phi [n*512],
-        acc [3, n*512], nint [n]; with columns also npix [n, Npix, 512] and
-        tau [n*512]."""
+        acc [3, n*512], nint [n] (the lengths of the lists the block's cells
+        use: one, or eight with list_group 4); with columns also npix
+        [n, Npix, 512] and tau [n*512]."""
         sel = np.arange(self.nb) if blocks is None else np.asarray(blocks)
         sel = np.ascontiguousarray(sel, dtype=np.int64)
         nc = 512 * sel.size

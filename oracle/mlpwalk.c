@@ -13,7 +13,10 @@
  *      tmax, tmax = mlp_reach x half the table's smallest grid spacing: with
  *      mlp_reach = 1 its cells lie within the table's own Taylor offset of
  *      the group centre c_g.
- *   2. The block's interaction list is that of the group walk (or_block_list).
+ *   2. The group's interaction list is that of the group walk: the block's
+ *      (or_block_list), or with list_group = 4 that of the block octant
+ *      holding the group (or_group_list; groups of 4^3 cells or fewer never
+ *      straddle two octants).
  *   3. Per (group, listed node): d0 = c_g - r_node, minimum image in periodic
  *      axes; network input x_k = 2 |d0_k| / ext_k - 1; output y_o sig_o +
  *      mu_o; signs restored (A_c,k odd in d_k; the xy, xz, yz derivatives
@@ -37,7 +40,6 @@
 #include <string.h>
 
 void or_mlp_forward(const double *p, int64_t B, const double *x, double *y);
-int64_t or_block_list(const or_tree *t, int64_t lb, int64_t *out, int64_t cap);
 
 enum { NOUT = 10 };
 
@@ -85,10 +87,16 @@ void or_walk_group_mlp(const or_tree *t, const double *params, const double *nor
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t q = 0; q < nsel; ++q) {
     const int64_t lb = sel[q];
-    const int64_t n = or_block_list(t, lb, NULL, 0);
-    int64_t *ids = (int64_t *)malloc(sizeof(int64_t) * (n > 0 ? n : 1));
-    or_block_list(t, lb, ids, n);
-    if (nint) nint[q] = n;
+    const int nl = t->p.list_group == 4 ? 8 : 1;
+    int64_t nl_len[8], *nl_ids[8], tot = 0;
+    for (int so = 0; so < nl; ++so) {
+      const int oct = nl == 8 ? so : -1;
+      nl_len[so] = or_group_list(t, lb, oct, NULL, 0);
+      nl_ids[so] = (int64_t *)malloc(sizeof(int64_t) * (nl_len[so] > 0 ? nl_len[so] : 1));
+      or_group_list(t, lb, oct, nl_ids[so], nl_len[so]);
+      tot += nl_len[so];
+    }
+    if (nint) nint[q] = tot;
     const int gl = or_mlp_group_level(t, lb), gs = 1 << gl, ga = 8 / gs;
     const double h = or_size_at(t, t->blev[lb]) / 8.0, gsz = h * (double)gs;
     msum *ph = (msum *)calloc(512, sizeof(msum)), *ac = (msum *)calloc(3 * 512, sizeof(msum));
@@ -99,6 +107,8 @@ void or_walk_group_mlp(const or_tree *t, const double *params, const double *nor
           double gc[3];
           for (int k = 0; k < 3; ++k)
             gc[k] = t->p.origin[k] + ((double)((int64_t)ga * t->bcoord[3 * lb + k] + gi[k]) + 0.5) * gsz;
+          const int so = nl == 8 ? or_cell_octant(gx * gs + 8 * (gy * gs) + 64 * (gz * gs)) : 0;
+          const int64_t n = nl_len[so], *ids = nl_ids[so];
           for (int64_t j = 0; j < n; ++j) {
             const int64_t id = ids[j];
             double d0[3], v[NOUT];
@@ -146,6 +156,6 @@ void or_walk_group_mlp(const or_tree *t, const double *params, const double *nor
     }
     free(ph);
     free(ac);
-    free(ids);
+    for (int so = 0; so < nl; ++so) free(nl_ids[so]);
   }
 }

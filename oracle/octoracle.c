@@ -291,6 +291,7 @@ or_tree *or_tree_new(const or_params *p, int64_t nb, const int32_t *level,
   else if (p->bc[0] && p->bc[1] && !p->bc[2]) bct = OR_BC_2P1I;
   else if (p->bc[0] && !p->bc[1] && !p->bc[2]) bct = OR_BC_1P2I;
   else { *err = 6; return NULL; }
+  if (p->list_group != 0 && p->list_group != 4 && p->list_group != 8) { *err = 7; return NULL; }
   or_tree *t = (or_tree *)calloc(1, sizeof(or_tree));
   t->p = *p;
   t->bctype = bct;
@@ -483,21 +484,65 @@ void or_block_target(const or_tree *t, int64_t lb, double cT[3], double *ext) {
   *ext = 3.5 * (s / 8.0);
 }
 
-static idlist group_list(const or_tree *t, int64_t lb) {
+/* The group walk's target may also be one octant of the block, the 4^3
+ * cells with the upper (bit a of so set) or lower half on each axis a: the
+ * same closest-point MAC suite, with the box of those cells' centres
+ * (half-extent 1.5 h about the octant's centre).  Every cell's list then
+ * still passes the suite at the cell itself. */
+void or_group_target(const or_tree *t, int64_t lb, int so, double cT[3], double *ext) {
+  or_block_target(t, lb, cT, ext);
+  if (so < 0) return;
+  const double h = or_size_at(t, t->blev[lb]) / 8.0;
+  for (int k = 0; k < 3; ++k) cT[k] += (((so >> k) & 1) ? 2.0 : -2.0) * h;
+  *ext = 1.5 * h;
+}
+
+static idlist group_list(const or_tree *t, int64_t lb, int so) {
   double cT[3], ext;
-  or_block_target(t, lb, cT, &ext);
+  or_group_target(t, lb, so, cT, &ext);
   idlist l = {0, 0, 0};
   for (int64_t r = 0; r < t->nroots; ++r) visit(t, t->roots[r], cT, ext, &l);
   return l;
 }
 
-/* Interaction list of leaf block lb under the group MAC (ids, walk order). */
-int64_t or_block_list(const or_tree *t, int64_t lb, int64_t *out, int64_t cap) {
-  idlist l = group_list(t, lb);
+int64_t or_group_list(const or_tree *t, int64_t lb, int so, int64_t *out, int64_t cap) {
+  idlist l = group_list(t, lb, so);
   int64_t n = l.n;
   if (out) for (int64_t i = 0; i < n && i < cap; ++i) out[i] = l.v[i];
   free(l.v);
   return n;
+}
+
+/* Interaction list of leaf block lb under the group MAC (ids, walk order). */
+int64_t or_block_list(const or_tree *t, int64_t lb, int64_t *out, int64_t cap) {
+  return or_group_list(t, lb, -1, out, cap);
+}
+
+/* The lists the cells of one leaf block use: the block's own, or with
+ * list_group = 4 one per octant. */
+typedef struct {
+  idlist l[8];
+  int n;
+} blists;
+
+static blists block_lists(const or_tree *t, int64_t lb) {
+  blists b;
+  memset(&b, 0, sizeof(b));
+  b.n = t->p.list_group == 4 ? 8 : 1;
+  for (int so = 0; so < b.n; ++so) b.l[so] = group_list(t, lb, b.n == 8 ? so : -1);
+  return b;
+}
+
+static const idlist *cell_list(const blists *b, int ci) { return &b->l[b->n == 8 ? or_cell_octant(ci) : 0]; }
+
+static int64_t blists_len(const blists *b) {
+  int64_t n = 0;
+  for (int so = 0; so < b->n; ++so) n += b->l[so].n;
+  return n;
+}
+
+static void blists_free(blists *b) {
+  for (int so = 0; so < b->n; ++so) free(b->l[so].v);
 }
 
 /* Neumaier-compensated sum */
@@ -586,13 +631,14 @@ void or_walk_group_blocks(const or_tree *t, int64_t nsel, const int64_t *sel, do
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t q = 0; q < nsel; ++q) {
     int64_t lb = sel[q];
-    idlist l = group_list(t, lb);
-    if (nint) nint[q] = l.n;
+    blists bl = block_lists(t, lb);
+    if (nint) nint[q] = blists_len(&bl);
     double *map = cols ? (double *)malloc(sizeof(double) * np) : NULL;
     for (int ci = 0; ci < 512; ++ci) {
       double x[3], ph, a[3];
+      const idlist *l = cell_list(&bl, ci);
       or_cell_centre(t, lb, ci, x);
-      sum_list(t, x, l.v, l.n, &ph, a, map);
+      sum_list(t, x, l->v, l->n, &ph, a, map);
       phi[512 * q + ci] = ph;
       for (int k = 0; k < 3; ++k) acc[k * ncell + 512 * q + ci] = a[k];
       if (cols) {
@@ -601,7 +647,7 @@ void or_walk_group_blocks(const or_tree *t, int64_t nsel, const int64_t *sel, do
       }
     }
     free(map);
-    free(l.v);
+    blists_free(&bl);
   }
 }
 
@@ -624,14 +670,15 @@ void or_walk_group_abu(const or_tree *t, const double *prev_phi, const double *p
   const int np = t->rt.npix;
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t lb = 0; lb < t->nb; ++lb) {
-    idlist l = group_list(t, lb);
+    blists bl = block_lists(t, lb);
     double *map = cols ? (double *)malloc(sizeof(double) * np) : NULL;
     int changed = 0;
     for (int k = 0; k < 8; ++k) {
       const int ci = 7 * (k & 1) + 56 * ((k >> 1) & 1) + 448 * ((k >> 2) & 1);
       double x[3], ph, a[3];
+      const idlist *l = cell_list(&bl, ci);
       or_cell_centre(t, lb, ci, x);
-      sum_list(t, x, l.v, l.n, &ph, a, map);
+      sum_list(t, x, l->v, l->n, &ph, a, map);
       double d2 = 0.0;
       for (int q = 0; q < 3; ++q) {
         const double d = a[q] - prev_acc[q * ncell + 512 * lb + ci];
@@ -647,8 +694,9 @@ void or_walk_group_abu(const or_tree *t, const double *prev_phi, const double *p
       const int64_t o = 512 * lb + ci;
       if (changed) {
         double x[3], ph, a[3];
+        const idlist *l = cell_list(&bl, ci);
         or_cell_centre(t, lb, ci, x);
-        sum_list(t, x, l.v, l.n, &ph, a, NULL);
+        sum_list(t, x, l->v, l->n, &ph, a, NULL);
         phi[o] = ph;
         for (int q = 0; q < 3; ++q) acc[q * ncell + o] = a[q];
       } else {
@@ -656,7 +704,7 @@ void or_walk_group_abu(const or_tree *t, const double *prev_phi, const double *p
         for (int q = 0; q < 3; ++q) acc[q * ncell + o] = prev_acc[q * ncell + o];
       }
     }
-    free(l.v);
+    blists_free(&bl);
   }
 }
 

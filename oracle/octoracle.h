@@ -40,13 +40,15 @@ typedef struct {
   double psi_max;     /* upper edge of the psi bins                          */
   double mlp_reach;   /* surrogate walk: group cells within mlp_reach x half the
                          table's smallest spacing of the group centre (<= 0: 1) */
+  int32_t list_group; /* cells per axis of a walk target: 8 (or 0) one list per
+                         leaf block, 4 one list per 4^3 octant of a block  */
 } or_params;
 
 typedef struct or_tree or_tree;
 
 /* Returns NULL on an invalid grid; *err receives a short reason code:
  * 1 bad level/coord, 2 duplicate block, 3 overlap, 4 hole, 5 bad density,
- * 6 unsupported boundary combination. */
+ * 6 unsupported boundary combination, 7 list_group not 0, 4 or 8. */
 or_tree *or_tree_new(const or_params *p, int64_t nb, const int32_t *level,
                      const int32_t *coord, const double *rho, int *err);
 void or_tree_free(or_tree *t);

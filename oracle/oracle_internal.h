@@ -67,6 +67,15 @@ int64_t or_id_p2(const or_tree *t, int64_t lb, int o1, int o2);
 int64_t or_id_cell(const or_tree *t, int64_t lb, int ci);
 int or_accept(const or_tree *t, int64_t id, const double cT[3], double ext);
 void or_block_target(const or_tree *t, int64_t lb, double cT[3], double *ext);
+/* walk target so of leaf block lb: the block (so < 0) or its octant so */
+void or_group_target(const or_tree *t, int64_t lb, int so, double cT[3], double *ext);
+/* interaction list of walk target so of leaf block lb (ids, walk order) */
+int64_t or_group_list(const or_tree *t, int64_t lb, int so, int64_t *out, int64_t cap);
+/* octant of a block's cell ci = i + 8 j + 64 k: bit a set on the upper half
+ * of axis a */
+static inline int or_cell_octant(int ci) {
+  return ((ci & 7) >> 2) | ((((ci >> 3) & 7) >> 2) << 1) | ((ci >> 8) << 2);
+}
 void or_cell_centre(const or_tree *t, int64_t lb, int ci, double x[3]);
 
 /* Ewald */

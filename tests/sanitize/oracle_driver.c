@@ -17,6 +17,7 @@
 void or_tree_export(const or_tree *t, int32_t *alev, int32_t *acoord, int64_t *aleaf, int64_t *achild,
                     uint64_t *akey, double *M, double *com);
 int64_t or_block_list(const or_tree *t, int64_t lb, int64_t *out, int64_t cap);
+int64_t or_group_list(const or_tree *t, int64_t lb, int so, int64_t *out, int64_t cap);
 void or_walk_group(const or_tree *t, double *phi, double *acc, int64_t *nint);
 void or_walk_group_blocks(const or_tree *t, int64_t nsel, const int64_t *sel, double *phi, double *acc,
                           double *npix, double *tau, int64_t *nint);
@@ -164,6 +165,13 @@ static void exercise_tree(const or_params *p, const char *name) {
     CHECK(or_block_list(t, lb, ids, len) == len);
     for (int64_t q = 0; q < len; ++q) CHECK(ids[q] >= 0 && ids[q] < nn);
     free(ids);
+    for (int so = 0; so < 8; so += 7) {
+      const int64_t lo = or_group_list(t, lb, so, NULL, 0);
+      int64_t *oi = malloc(sizeof(int64_t) * (lo > 0 ? lo : 1));
+      CHECK(lo > 0 && lo <= len && or_group_list(t, lb, so, oi, lo) == lo);
+      for (int64_t q = 0; q < lo; ++q) CHECK(oi[q] >= 0 && oi[q] < nn);
+      free(oi);
+    }
   }
   double *phi = malloc(sizeof(double) * n), *acc = malloc(sizeof(double) * 3 * n);
   int64_t *nint = malloc(sizeof(int64_t) * nb);
@@ -255,6 +263,10 @@ static void exercise_invalid(void) {
   level[1] = 2;
   coord[3] = 1;
   CHECK(or_tree_new(&p, 2, level, coord, rho, &err) == NULL && err != 0); /* holes */
+  coord[3] = 0;
+  level[0] = level[1] = 1;
+  p.list_group = 2;
+  CHECK(or_tree_new(&p, 1, level, coord, rho, &err) == NULL && err == 7); /* list group */
 }
 
 static void exercise_columns_and_healpix(void) {
@@ -353,6 +365,11 @@ int main(void) {
   exercise_tree(&p, "2P1I table");
   p = base_params(line, p1);
   exercise_tree(&p, "1P2I table");
+  p = base_params(tall, p2);
+  p.list_group = 4;
+  p.nside = 1;
+  p.theta_pix = 1.0;
+  exercise_tree(&p, "2P1I table, octant lists, Nside 1");
   exercise_invalid();
   exercise_columns_and_healpix();
   exercise_ewald();

@@ -56,11 +56,11 @@ def group_level(h, step, reach=1.0):
     return 2 if 1.5 * h <= tmax else (1 if 0.5 * h <= tmax else 0)
 
 
-def closed_form(t, g, lb, ext_far, reach=1.0):
-    """Phi [512], a [3, 512] of block lb by the closed form above."""
+def closed_form(t, g, lb, ext_far, reach=1.0, lists=None):
+    """Phi [512], a [3, 512] of block lb by the closed form above; with
+    lists (eight octant lists) each cell sums the list of its octant."""
     ex = t.export()
     ids = t.block_list(lb)
-    com, M = ex["com"][ids], ex["M"][ids]
     L = np.asarray(g.nroot, float) * g.root_size
     per = np.asarray(g.bc, bool)
     h = g.root_size / 2.0 ** (g.level[lb] - 1) / 8
@@ -76,7 +76,10 @@ def closed_form(t, g, lb, ext_far, reach=1.0):
     gc = np.asarray(g.origin) + (8 // gs * g.coord[lb] + gidx + 0.5) * (h * gs)
     H = np.array([[CH[4], CH[7], CH[8]], [CH[7], CH[5], CH[9]], [CH[8], CH[9], CH[6]]])
     bL2 = L[1] / L[0] * L[0] ** 2
+    octs = (ijk // 4) @ np.array([1, 2, 4])
     for c in range(512):
+        cid = ids if lists is None else lists[octs[c]]
+        com, M = ex["com"][cid], ex["M"][cid]
         d0 = gc[c] - com
         d0 = np.where(per, d0 - L * np.floor(d0 / L + 0.5), d0)
         s = np.where(d0 < 0, -1.0, 1.0)
