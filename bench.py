@@ -96,6 +96,8 @@ def parse():
     ap.add_argument("--no-p1", action="store_true", help="skip the 1P2I filament leg")
     ap.add_argument("--no-cyl", action="store_true", help="skip the isothermal-cylinder accuracy leg")
     ap.add_argument("--no-points", action="store_true", help="skip the target-point leg")
+    ap.add_argument("--no-octant", action="store_true",
+                    help="skip the headline walk with one list per 4^3 block octant")
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the Plummer AMR leg (2.6M cells, box 1x1x4, 2P1I, 64^3 Ewald table)")
     return ap.parse_args()
@@ -262,10 +264,11 @@ def c5_setup(mlp_cache=None):
     return g, rho, kw, a_lim, mlp, rep, info
 
 
-def c5_run(g, rho, kw, a_lim, mode, fp64, steps, warmup, mlp=None, accept=True):
+def c5_run(g, rho, kw, a_lim, mode, fp64, steps, warmup, mlp=None, accept=True, list_group=8):
     import torch
     import paper_1708_06142_amd as ot
-    s = ot.Solver.for_grid(g, a_lim=a_lim, ewald=mode, nside=4, mlp_reach=C5_MLP_REACH, **kw)
+    s = ot.Solver.for_grid(g, a_lim=a_lim, ewald=mode, nside=4, mlp_reach=C5_MLP_REACH, list_group=list_group,
+                           **kw)
     if mlp is not None:
         s.mlp_set(*mlp, accept=accept)
     n = g.ncells
@@ -278,7 +281,7 @@ def c5_run(g, rho, kw, a_lim, mode, fp64, steps, warmup, mlp=None, accept=True):
          "phases_ms": {"build": ms_build, "lists": ms_list, "eval": ms_eval, "gravity": st.ms_gravity,
                        "columns": st.ms_columns},
          "ewald_used": ["table", "exact", "mlp"][st.ewald_used], "n_int": st.n_interactions,
-         "eval_wg_per_cu": st.eval_wg_per_cu}
+         "total_list": st.total_list, "eval_wg_per_cu": st.eval_wg_per_cu}
     return outs, st, e
 
 
@@ -329,6 +332,30 @@ def direct_errors(t, g, phi, acc, ncells, seed=17):
             "sample": f"{ncells} seeded cells and the {ncells // 2} of largest |a|",
             "reference": "oracle direct sum over all other cells, FP64, same 64^3 Ewald table",
             "seconds": sec}
+
+
+def raymarch_errors(t, g, maps, ncells=12, seed=19):
+    """Largest |difference| of 192-pixel maps from the oracle's ray-marched
+    column densities (exact integrals of rho through the cells along the
+    Nside-16 pixel-centre rays, averaged per pixel) on seeded cells and the
+    cell of largest reference column, normalised by the largest reference
+    value over those cells; one figure per map set."""
+    import torch
+    rng = np.random.default_rng(seed)
+    tg = np.unique(np.concatenate([rng.choice(g.ncells, ncells, replace=False),
+                                   [int(np.argmax(g.rho.reshape(-1)))]]))
+    t0 = time.perf_counter()
+    ref = np.stack([t.raymarch(int(c), 4) for c in tg])
+    sec = time.perf_counter() - t0
+    rmax = np.abs(ref).max()
+    res = {}
+    for label, npix in maps.items():
+        v = npix.view(g.nb, 192, 512)
+        got = np.stack([v[c // 512, :, c % 512].double().cpu().numpy() for c in tg])
+        res[label] = float(np.abs(got - ref).max() / rmax)
+    return {"maxnorm_vs_raymarch": res, "cells": int(tg.size), "seconds": sec,
+            "sample": f"{ncells} seeded cells and the densest cell",
+            "reference": "oracle ray-marched columns, Nside 16 rays averaged into the 192 pixels"}
 
 
 def cpu_model():
@@ -745,6 +772,20 @@ def main():
         progress("FP64- and FP32-table walks done")
     else:
         o64 = None
+    o_oct = None
+    if not args.no_octant:
+        # the headline walk with one list per 4^3 block octant in place of one
+        # per block: the same MAC suite against each octant's box, so shorter
+        # lists that still pass it at every cell
+        o_oct, st_oct, e_oct = c5_run(g, rho, kw, a_lim, "mlp", False, args.steps, args.warmup, mlp,
+                                      bool(rep["ok"]), list_group=4)
+        e_oct["list_group"] = 4
+        e_oct["n_mlp_evals"] = st_oct.n_mlp_evals
+        e_oct["roofline"] = dict(fused_roofline(st_oct), kernel="k_eval_cols_mlp4")
+        if o64 is not None:
+            e_oct.update(maxnorm_diffs(o_oct, o64))
+        out["octant_lists"] = e_oct
+        progress(f"octant lists: {e_oct['ms_per_step']:.1f} ms/step")
     if not args.no_points:
         out["points"] = points_leg(g, rho, a_lim)
     torch.cuda.synchronize()
@@ -754,11 +795,18 @@ def main():
             out["accuracy_vs_direct"] = direct_errors(t, g, outs[0], outs[1], args.direct_cells)
             if o64 is not None:
                 out["fp64_table"]["accuracy_vs_direct"] = direct_errors(t, g, o64[0], o64[1], args.direct_cells)
+            if o_oct is not None:
+                out["octant_lists"]["accuracy_vs_direct"] = direct_errors(t, g, o_oct[0], o_oct[1],
+                                                                          args.direct_cells)
+                maps = {"block_lists": outs[2], "octant_lists": o_oct[2]}
+                if o64 is not None:
+                    maps["fp64_table"] = o64[2]
+                out["columns_vs_raymarch"] = raymarch_errors(t, g, maps)
         if not args.no_cpu:
             out["cpu_baseline"] = cpu_baseline(t, tree_s, g, args.cpu_blocks)
         progress("oracle legs done")
         del t
-    del outs, o64
+    del outs, o64, o_oct
     torch.cuda.empty_cache()
     if not args.no_c2 or not args.no_surrogate or not args.no_abu or not args.no_mpe:
         c2, grid, rho2, a2 = c2_leg(args.c2_steps, 2)

@@ -107,13 +107,24 @@ typedef struct {
                             spacing of its centre (1: the table's own Taylor
                             offset, Sec. 2.2.5; larger: fewer evaluations and a
                             Taylor remainder growing as its square); <= 0: 1 [1] */
+  int32_t list_group;    /* cells per axis of a walk target (Sec. 2.1's group walk
+                            with a smaller group): 8 (or 0) one interaction list
+                            per leaf block; 4 one list per 4^3 octant of a block,
+                            the same MAC suite against the box of the octant's
+                            cell centres (shorter lists, each still passing the
+                            suite at every cell it serves).  4 is walked by the
+                            FP32 solve with an accepted surrogate, Nside 4 maps
+                            and cell groups of 2^3 or 4^3 cells; other solves of
+                            such a context, and the adaptive update, return
+                            OT_ERR_UNSUPPORTED                              [8] */
 } ot_params;
 
 /* Run statistics of the last solve. */
 typedef struct {
   int64_t n_interactions;  /* sum over cells of accepted list entries (N_int) */
-  int64_t max_list;        /* longest block interaction list                 */
-  int64_t total_list;      /* sum of block list lengths                      */
+  int64_t max_list;        /* longest interaction list (one per block, or per
+                              block octant with list_group 4)               */
+  int64_t total_list;      /* sum of the list lengths                         */
   double a_lim_used;       /* APE/MPE limit actually used (0 for BH)         */
   double ms_build;         /* tree build (moments), device time              */
   double ms_list;          /* interaction-list construction, device time      */
@@ -122,11 +133,11 @@ typedef struct {
                               also for isolated boundaries)                   */
   int32_t eval_wg_per_cu;  /* workgroups of the column walk resident per compute
                               unit (its occupancy); 0 without columns         */
-  int64_t n_opened;        /* nodes the MAC suite opened, summed over blocks  */
+  int64_t n_opened;        /* nodes the MAC suite opened, summed over lists   */
   int64_t n_accepted;      /* list entries that are not cells: nodes the MAC
-                              suite accepted, summed over blocks (ot_solve,
+                              suite accepted, summed over lists (ot_solve,
                               ot_solve64; 0 for the adaptive update)          */
-  int64_t list_hist[32];   /* blocks whose list length L has 2^k <= L < 2^(k+1) */
+  int64_t list_hist[32];   /* lists whose length L has 2^k <= L < 2^(k+1)     */
   int64_t n_mlp_evals;     /* network evaluations of the surrogate walk
                               (cell groups x list entries); 0 without it      */
   double ms_gravity;       /* device time of the surrogate gravity walk; 0 when
@@ -381,7 +392,9 @@ ot_status ot_export_topology(const ot_ctx *c, int32_t *level_host, int32_t *coor
  * 8 +1 nodes of each leaf block, the 64 +2 nodes, the 512 cells.
  * M_host [nn], com_host [nn*3] with nn = na + 584 nb. */
 ot_status ot_export_moments(ot_ctx *c, double *M_host, double *com_host);
-/* Interaction list of leaf block b from the last solve (global node ids). */
+/* Interaction list b from the last solve (global node ids): that of leaf
+ * block b, or with list_group 4 that of octant b % 8 of block b / 8 (bit a
+ * of the octant set for the upper half of axis a), b < 8 nb. */
 ot_status ot_export_list(ot_ctx *c, int64_t b, int32_t *ids_host, int64_t cap, int64_t *len);
 /* node ids of target point i's list from the last ot_solve_points (as above) */
 ot_status ot_export_point_list(ot_ctx *c, int64_t i, int32_t *ids_host, int64_t cap, int64_t *len);

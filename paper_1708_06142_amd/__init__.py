@@ -39,7 +39,7 @@ class Params(C.Structure):
                 ("nside", C.c_int32), ("il_ntheta", C.c_int32), ("il_nphi", C.c_int32),
                 ("il_npsi", C.c_int32), ("il_nr", C.c_int32), ("il_nazi", C.c_int32),
                 ("theta_pix", C.c_double), ("kappa", C.c_double), ("max_dist", C.c_double),
-                ("psi_max", C.c_double), ("mlp_reach", C.c_double)]
+                ("psi_max", C.c_double), ("mlp_reach", C.c_double), ("list_group", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -165,7 +165,8 @@ MAC = {"bh": 0, "ape": 1, "mpe": 2}
 def make_params(nroot=(1, 1, 1), root_size=1.0, origin=(0.0, 0.0, 0.0), bc=(0, 0, 0), G=1.0,
                 theta=0.5, eta_sb=1.2, mac="bh", a_lim=0.0, eps_lim=1e-3, ewald="table",
                 ewald_n=64, ewald_rcut2=0, ewald_fcut2=0, ewald_alpha=0.0, device=0,
-                max_device_bytes=0, nside=0, theta_pix=0.0, kappa=1.0, max_dist=1e99, mlp_reach=1.0, **table):
+                max_device_bytes=0, nside=0, theta_pix=0.0, kappa=1.0, max_dist=1e99, mlp_reach=1.0,
+                list_group=8, **table):
     p = Params()
     lib().ot_params_default(C.byref(p))
     for k in range(3):
@@ -178,6 +179,7 @@ def make_params(nroot=(1, 1, 1), root_size=1.0, origin=(0.0, 0.0, 0.0), bc=(0, 0
     p.ewald_alpha, p.device, p.max_device_bytes = float(ewald_alpha), int(device), int(max_device_bytes)
     p.nside, p.theta_pix, p.kappa, p.max_dist = int(nside), float(theta_pix), float(kappa), float(max_dist)
     p.mlp_reach = float(mlp_reach)
+    p.list_group = int(list_group)
     for k, v in table.items():
         if k not in ("il_ntheta", "il_nphi", "il_npsi", "il_nr", "il_nazi", "psi_max"):
             raise TypeError(f"unknown parameter {k}")

@@ -496,32 +496,34 @@ ot::ColP col_params(ot_ctx *c) {
 }
 
 // Interaction lists for the given MAC: count, scan, fill.
-ot_status build_lists(ot_ctx *c, const ot::MacP &mp, bool sizes, hipStream_t st) {
+ot_status build_lists(ot_ctx *c, const ot::MacP &mp, bool sizes, hipStream_t st, int sub = 0) {
   const ot::Topology &t = c->topo;
   ot::DevTree T = dev_tree(c);
+  const int64_t ntg = sub ? 8 * t.nb : t.nb;
   int64_t capA = 0;
   for (int l = 1; l <= t.lmax; ++l) capA = std::max(capA, t.level_begin[l + 1] - t.level_begin[l]);
   const int64_t stride = 2 * capA + 9 * t.nb;
-  int64_t grid = std::min<int64_t>(t.nb, 2048);
+  int64_t grid = std::min<int64_t>(ntg, 2048);
   const int64_t budget = (int64_t)1 << 30;  // scratch bytes
   while (grid > 64 && grid * stride * 4 > budget) grid /= 2;
   OTCHK(dalloc(c, c->lscratch, (size_t)(grid * stride * 4)));
-  OTCHK(dalloc(c, c->lcount, t.nb * sizeof(int32_t)));
-  OTCHK(dalloc(c, c->loff, (t.nb + 1) * sizeof(int64_t)));
-  OTCHK(dalloc(c, c->lnodes, 2 * t.nb * sizeof(int32_t)));
+  OTCHK(dalloc(c, c->lcount, ntg * sizeof(int32_t)));
+  OTCHK(dalloc(c, c->loff, (ntg + 1) * sizeof(int64_t)));
+  OTCHK(dalloc(c, c->lnodes, 2 * ntg * sizeof(int32_t)));
   HIPCHK(ot::launch_lists(false, T, mp, (int)grid, P<int32_t>(c->lcount), P<int32_t>(c->lnodes), nullptr, nullptr, nullptr,
-                          nullptr, P<int32_t>(c->lscratch), stride, capA, st));
-  HIPCHK(ot::launch_scan(P<int32_t>(c->lcount), t.nb, P<int64_t>(c->loff), st));
+                          nullptr, P<int32_t>(c->lscratch), stride, capA, st, nullptr, 0, sub));
+  HIPCHK(ot::launch_scan(P<int32_t>(c->lcount), ntg, P<int64_t>(c->loff), st));
   int64_t total = 0;
-  HIPCHK(hipMemcpyAsync(&total, P<int64_t>(c->loff) + t.nb, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&total, P<int64_t>(c->loff) + ntg, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   OTCHK(dalloc(c, c->lrec, (size_t)total * sizeof(double4)));
   OTCHK(dalloc(c, c->lid, (size_t)total * sizeof(int32_t)));
   if (sizes) OTCHK(dalloc(c, c->lh, (size_t)total * sizeof(double)));
   HIPCHK(ot::launch_lists(true, T, mp, (int)grid, P<int32_t>(c->lcount), nullptr, P<int64_t>(c->loff),
                           P<double4>(c->lrec), P<int32_t>(c->lid), sizes ? P<double>(c->lh) : nullptr,
-                          P<int32_t>(c->lscratch), stride, capA, st));
+                          P<int32_t>(c->lscratch), stride, capA, st, nullptr, 0, sub));
   c->list_cap = total;
+  c->list_sub = sub;
   return OT_OK;
 }
 
@@ -643,7 +645,8 @@ ot_status mlp_grad_scratch(ot_ctx *c, int64_t batch) {
 void list_stats(const ot_ctx *c, const std::vector<int32_t> &nodes, ot_stats *stats) {
   memset(stats, 0, sizeof(*stats));
   int64_t mx = 0;
-  for (int64_t b = 0; b < c->topo.nb; ++b) {
+  const int64_t ntg = c->list_sub ? 8 * c->topo.nb : c->topo.nb;
+  for (int64_t b = 0; b < ntg; ++b) {
     const int64_t len = c->off_host[b + 1] - c->off_host[b];
     mx = std::max(mx, len);
     int k = 0;
@@ -654,9 +657,9 @@ void list_stats(const ot_ctx *c, const std::vector<int32_t> &nodes, ot_stats *st
       stats->n_accepted += len - nodes[2 * b + 1];
     }
   }
-  stats->total_list = c->off_host[c->topo.nb];
+  stats->total_list = c->off_host[ntg];
   stats->max_list = mx;
-  stats->n_interactions = 512 * (stats->total_list - c->topo.nb);
+  stats->n_interactions = (c->list_sub ? 64 : 512) * (stats->total_list - ntg);
 }
 
 float elapsed(hipEvent_t a, hipEvent_t b) {
@@ -687,15 +690,22 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
   if (c->p.mac == OT_MAC_APE || c->p.mac == OT_MAC_MPE) OTCHK(ape_limit(c, st, &alim));
   for (int i = 0; i < 6; ++i)
     if (!c->ev[i]) HIPCHK(hipEventCreate(&c->ev[i]));
+  // with the surrogate and maps too large for LDS, one kernel carries both
+  // the surrogate's gravity and the columns
+  const bool fused = use_mlp && cols && ot::cols_lds_cpw(npix_of(c), false, col_params(c).nthr) == 0;
+  // one list per 4^3 block octant: only this kernel walks them, and its
+  // octants hold whole cell groups of 2^3 or 4^3 cells
+  const int sub = c->p.list_group == 4 ? 1 : 0;
+  if (sub && !(fused && ot::mlp_group_level(cell_size_max(c), mlp_tmax(c)) >= 1))
+    return fail(c, OT_ERR_UNSUPPORTED,
+                "list_group 4 needs the FP32 walk with an accepted surrogate (3P or 2P1I), Nside 4 columns and "
+                "cell groups of 2^3 or more cells");
   HIPCHK(hipEventRecord(c->ev[0], st));
-  OTCHK(build_lists(c, mac_params(c, c->p.mac, alim, cols), cols, st));
+  OTCHK(build_lists(c, mac_params(c, c->p.mac, alim, cols), cols, st, sub));
   HIPCHK(hipEventRecord(c->ev[1], st));
   ot::DevTree T = dev_tree(c);
   ot::EwaldP E = ewald_desc(c);
   int wg_per_cu = 0;
-  // with the surrogate and maps too large for LDS, one kernel carries both
-  // the surrogate's gravity and the columns
-  const bool fused = use_mlp && cols && ot::cols_lds_cpw(npix_of(c), false, col_params(c).nthr) == 0;
   if (fused) OTCHK(dalloc(c, c->llat, (size_t)c->list_cap * sizeof(int32_t)));
   if (use_mlp && !fused)
     // gravity from the surrogate walk (the columns, if any, follow without gravity)
@@ -706,7 +716,7 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
     HIPCHK(ot::launch_eval_cols_mlp(T, E, col_params(c), c->mlp_pk.ptr, P<int64_t>(c->loff), P<double4>(c->lrec),
                                     P<int32_t>(c->lid), P<double>(c->lh), P<int32_t>(c->llat), (float *)phi,
                                     (float *)acc, (float *)npix, (float *)tau,
-                                    c->p.G, mlp_tmax(c), cell_size_max(c), &wg_per_cu, st));
+                                    c->p.G, mlp_tmax(c), cell_size_max(c), &wg_per_cu, st, sub));
   } else if (cols) {
     // maps in LDS when 128 or more cells' maps fit there, else in npix
     const ot::ColP C = col_params(c);
@@ -721,12 +731,13 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
     HIPCHK(ot::launch_eval32(T, E, P<int64_t>(c->loff), P<double4>(c->lrec), P<int32_t>(c->lid),
                              (float *)phi, (float *)acc, c->p.G, st));
   HIPCHK(hipEventRecord(c->ev[2], st));
-  c->off_host.resize(c->topo.nb + 1);
-  HIPCHK(hipMemcpyAsync(c->off_host.data(), c->loff.ptr, (c->topo.nb + 1) * sizeof(int64_t),
+  const int64_t ntg = sub ? 8 * c->topo.nb : c->topo.nb;
+  c->off_host.resize(ntg + 1);
+  HIPCHK(hipMemcpyAsync(c->off_host.data(), c->loff.ptr, (ntg + 1) * sizeof(int64_t),
                         hipMemcpyDeviceToHost, st));
   std::vector<int32_t> nodes;
   if (stats) {
-    nodes.resize(2 * c->topo.nb);
+    nodes.resize(2 * ntg);
     HIPCHK(hipMemcpyAsync(nodes.data(), c->lnodes.ptr, nodes.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
                           st));
   }
@@ -743,9 +754,11 @@ ot_status solve_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, voi
     if (use_mlp) {
       stats->ms_gravity = fused ? 0.0 : elapsed(c->ev[1], c->ev[4]);
       const double tmax = mlp_tmax(c);
-      for (int64_t b = 0; b < c->topo.nb; ++b)
-        stats->n_mlp_evals += (int64_t)ot::mlp_groups(ot::size_at(c->p.root_size, c->topo.blev[b]) / 8.0, tmax) *
-                              (c->off_host[b + 1] - c->off_host[b]);
+      for (int64_t q = 0; q < ntg; ++q) {
+        const int64_t b = sub ? q >> 3 : q;
+        stats->n_mlp_evals += (int64_t)ot::mlp_groups(ot::size_at(c->p.root_size, c->topo.blev[b]) / 8.0, tmax) /
+                              (sub ? 8 : 1) * (c->off_host[q + 1] - c->off_host[q]);
+      }
     }
     if (cols) stats->ms_columns = elapsed(c->ev[4], c->ev[2]);
   }
@@ -767,6 +780,7 @@ ot_status abu_impl(ot_ctx *c, bool fp64, void *phi, void *acc, void *npix, void 
   if (cols && (!(tol_tau >= 0.0) || !std::isfinite(tol_tau)))
     return fail(c, OT_ERR_INVALID_ARG, "tol_tau must be finite and >= 0");
   if (!c->built) return fail(c, OT_ERR_STATE, "ot_solve_abu before a successful ot_build");
+  if (c->p.list_group == 4) return fail(c, OT_ERR_UNSUPPORTED, "the adaptive update walks one list per block");
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(c->p.device));
   if (c->bctype != ot::BC_ISO) {
@@ -998,6 +1012,7 @@ void ot_params_default(ot_params *p) {
   p->max_dist = 1e99;
   p->psi_max = 0.98;
   p->mlp_reach = 1.0;
+  p->list_group = 8;
 }
 
 ot_status ot_create(const ot_params *p, ot_ctx **out) {
@@ -1018,6 +1033,7 @@ ot_status ot_create(const ot_params *p, ot_ctx **out) {
     c->box[k] = p->nroot[k] * p->root_size;
   }
   if (!std::isfinite(p->mlp_reach)) return bad("mlp_reach must be finite");
+  if (p->list_group != 0 && p->list_group != 4 && p->list_group != 8) return bad("list_group must be 0, 4 or 8");
   if (!(p->root_size > 0) || !std::isfinite(p->root_size)) return bad("root_size must be > 0");
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(p->origin[k])) return bad("origin must be finite");
@@ -1204,7 +1220,8 @@ ot_status ot_export_moments(ot_ctx *c, double *M, double *com) {
 ot_status ot_export_list(ot_ctx *c, int64_t b, int32_t *ids, int64_t cap, int64_t *len) {
   if (!c) return OT_ERR_INVALID_ARG;
   if (!c->lists_valid) return fail(c, OT_ERR_STATE, "no lists: call ot_solve first");
-  if (b < 0 || b >= c->topo.nb || !len) return fail(c, OT_ERR_INVALID_ARG, "bad block index");
+  const int64_t ntg = c->list_sub ? 8 * c->topo.nb : c->topo.nb;
+  if (b < 0 || b >= ntg || !len) return fail(c, OT_ERR_INVALID_ARG, "bad list index");
   const int64_t n = c->off_host[b + 1] - c->off_host[b];
   *len = n;
   if (ids && cap > 0) {

@@ -63,6 +63,7 @@ struct ot_ctx {
   ot::DevBuf pcount, pnodes, poff, prec, pid;
   std::vector<int64_t> poff_host;
   int64_t npts = 0;
+  int list_sub = 0;
   int64_t list_cap = 0;
   int64_t scratch_per_wg = 0;
   int list_grid = 0;

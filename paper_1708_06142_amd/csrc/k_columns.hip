@@ -813,36 +813,42 @@ __global__ __launch_bounds__(512) void k_abu_corner_cols(DevTree T, EwaldP E, Co
 }
 
 // Lattice row of every list entry for the walk with the learned surrogate:
-// the row of the table that a cell of the target block's own size at a
-// lattice offset takes for the block's first cell (the walk adds each cell's
-// own index), or -1 (not such a cell, offsets of the block's cells outside
-// the table, or a periodic image possible).  One workgroup per leaf block.
+// the row of the table that a cell of the target's own size at a lattice
+// offset takes for the target's first cell (the walk adds each cell's own
+// index), or -1 (not such a cell, offsets of the target's cells outside the
+// table, or a periodic image possible).  One workgroup per list target: a
+// leaf block, or with sub set a 4^3 octant of one (list b, block b / 8,
+// octant b % 8).
 template <int BC>
 __global__ __launch_bounds__(256) void k_lattice_index(DevTree T, EwaldP E, ColP C, const int64_t *__restrict__ off,
                                                       const double4 *__restrict__ rec,
                                                       const int32_t *__restrict__ ids,
-                                                      const double *__restrict__ lh, int32_t *__restrict__ llat) {
-  const int64_t b = blockIdx.x;
+                                                      const double *__restrict__ lh, int32_t *__restrict__ llat,
+                                                      int sub) {
+  const int64_t tgt = blockIdx.x;
+  const int64_t b = sub ? tgt >> 3 : tgt;
+  const int so = sub ? (int)(tgt & 7) : 0;
+  const int ext = sub ? 4 : 8;  // cells per axis of the target
   const double h = size_at(T.root_size, T.blev[b]) / 8.0;
   const double inv_h = 1.0 / h;  // exact: h is a power of two on a dyadic grid
-  const double b0[3] = {centre_coord(T.org[0], 8 * (int64_t)T.bcoord[3 * b], h),
-                        centre_coord(T.org[1], 8 * (int64_t)T.bcoord[3 * b + 1], h),
-                        centre_coord(T.org[2], 8 * (int64_t)T.bcoord[3 * b + 2], h)};
+  const double b0[3] = {centre_coord(T.org[0], 8 * (int64_t)T.bcoord[3 * b] + 4 * (so & 1), h),
+                        centre_coord(T.org[1], 8 * (int64_t)T.bcoord[3 * b + 1] + 4 * ((so >> 1) & 1), h),
+                        centre_coord(T.org[2], 8 * (int64_t)T.bcoord[3 * b + 2] + 4 * (so >> 2), h)};
   const int64_t cell0 = T.na + 72 * T.nb;
   const int lat_w = 2 * C.lat_r + 1;
   auto lat_axis = [&](double d0, int ax) {
     const bool per = BC == 1 || (BC == 2 && ax < 2) || (BC == 3 && ax == 0);
-    if (per && !(d0 > -0.5 * E.L[ax] + h && d0 + 8.0 * h < 0.5 * E.L[ax])) return 1 << 20;
+    if (per && !(d0 > -0.5 * E.L[ax] + h && d0 + (double)ext * h < 0.5 * E.L[ax])) return 1 << 20;
     const double n0 = d0 * inv_h;
     return fabs(n0) < (double)(1 << 20) && n0 == rint(n0) ? (int)n0 : 1 << 20;
   };
-  const int64_t start = off[b], n = off[b + 1] - start;
+  const int64_t start = off[tgt], n = off[tgt + 1] - start;
   for (int64_t q = threadIdx.x; q < n; q += 256) {
     int32_t v = -1;
     if (C.lat_r > 0 && ids[start + q] >= cell0 && lh[start + q] == h) {
       const double4 r = rec[start + q];
       const int nx = lat_axis(b0[0] - r.x, 0), ny = lat_axis(b0[1] - r.y, 1), nz = lat_axis(b0[2] - r.z, 2);
-      const int lo = -C.lat_r, hi = C.lat_r - 7;
+      const int lo = -C.lat_r, hi = C.lat_r - (ext - 1);
       if (nx >= lo && nx <= hi && ny >= lo && ny <= hi && nz >= lo && nz <= hi)
         v = C.lat0 + ((nz + C.lat_r) * lat_w + (ny + C.lat_r)) * lat_w + (nx + C.lat_r);
     }
@@ -1132,6 +1138,311 @@ __global__ __launch_bounds__(512) void k_eval_cols_mlp(DevTree T, EwaldP E, ColP
   tau[o] = (float)(-log(se / (double)C.npix));
 }
 
+// LDS written by lanes of a wave, then read by other lanes of the same wave
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The same walk with one list per 4^3 octant of the block (the group walk's
+// MAC suite against the octant's box: shorter lists).  Wave w owns octant w
+// (bit a: upper half of axis a) and walks its list alone: its own LDS tile of
+// 32 entries, its own network batch (32 (cell group, entry) pairs, the cell
+// groups of 2^3 or 4^3 cells lying inside the octant) and wave-level
+// synchronisation only, so the eight waves of a workgroup never wait on each
+// other inside the walk.  Lane l owns cell (l & 3, (l >> 2) & 3, l >> 4) of
+// the octant.  A wave's 64 maps are accumulated in adjacent slots of each
+// pixel row of npix (slot 64 w + l), and put in the cell order i + 8 j + 64 k
+// at the end, eight pixel rows at a time between workgroup barriers.
+// Occupancy: 4 waves per SIMD (two workgroups per compute unit) at up to 128
+// registers.
+template <int BC>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_cols_mlp4(
+    DevTree T, EwaldP E, ColP C, const void *__restrict__ pk, const int64_t *__restrict__ off,
+    const double4 *__restrict__ rec, const int32_t *__restrict__ llat, const double *__restrict__ lh,
+    float *__restrict__ phi, float *__restrict__ acc, float *__restrict__ npix, float *__restrict__ tau,
+    float negG, double tmax) {
+  using namespace mlpdef;
+  __shared__ uint8_t lut[LUT_BYTES];
+  __shared__ f16x8 wl[64 * NPK];
+  constexpr int FT4 = 32;  // list entries per wave tile
+  __shared__ ColRec tiles[8][FT4];
+  extern __shared__ __align__(16) unsigned char smem[];
+  double *thr = reinterpret_cast<double *>(smem);
+  const int64_t b = blockIdx.x;
+  // the wave index is uniform across the wave: kept in a scalar register, so
+  // that each wave's list bounds and loops stay scalar
+  const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, m = l & 31;
+  float *slot = reinterpret_cast<float *>(thr + ((C.nthr + 1) & ~1)) + 32 * TSLOT * w;
+  // wave w walks octant w (4^3 cells) with its own list; lane l its cell
+  const int sx = w & 1, sy = (w >> 1) & 1, sz = w >> 2;
+  const int lx = l & 3, ly = (l >> 2) & 3, lz = l >> 4;
+  const int ii = 4 * sx + lx, jj = 4 * sy + ly, kk = 4 * sz + lz;
+  const int ci = ii + 8 * jj + 64 * kk;
+  ColRec *const tile = tiles[w];
+  const int64_t ncell = T.nb * 512;
+  const double h = size_at(T.root_size, T.blev[b]) / 8.0;
+  const int64_t bx = T.bcoord[3 * b], by = T.bcoord[3 * b + 1], bz = T.bcoord[3 * b + 2];
+  const double cx = centre_coord(T.org[0], 8 * bx + ii, h);
+  const double cy = centre_coord(T.org[1], 8 * by + jj, h);
+  const double cz = centre_coord(T.org[2], 8 * bz + kk, h);
+  for (int q = tid; q < LUT_BYTES; q += 512) lut[q] = C.lut[q];
+  for (int q = tid; q < C.nthr; q += 512) thr[q] = C.thr[q];
+  const mlpinf::Ops W = mlpinf::load_ops(pk, wl);  // ends with a barrier
+  const f16x8 one = mlpinf::ones();
+  // this cell's map in the output while the walk runs: slot 64 w + l = tid
+  // of each pixel row
+  char *const mcell = reinterpret_cast<char *>(npix + b * C.npix * 512 + tid);
+  constexpr int lmap = 11;  // pixel p of the cell at byte offset p << 11 (512 floats per pixel)
+  for (int p = 0; p < C.npix; ++p) *reinterpret_cast<float *>(mcell + (p << lmap)) = 0.0f;
+  const float inv_omega = (float)(1.0 / C.omega);
+  // groups of the surrogate walk
+  const int gl = mlp_group_level(h, tmax);  // 1 or 2: the host checks the largest cells
+  const int gs = 1 << gl, ga = 8 >> gl, g4 = 4 >> gl, G = g4 * g4 * g4;
+  const int CH = 32 / G;
+  const double gsz = h * (double)gs;
+  auto gcentre = [&](int g, double c[3]) {
+    const int gx = g % g4, gy = (g / g4) % g4, gz = g / (g4 * g4);
+    c[0] = centre_coord(T.org[0], ga * bx + g4 * sx + gx, gsz);
+    c[1] = centre_coord(T.org[1], ga * by + g4 * sy + gy, gsz);
+    c[2] = centre_coord(T.org[2], ga * bz + g4 * sz + gz, gsz);
+  };
+  const int mg = (lx >> gl) + g4 * ((ly >> gl) + g4 * (lz >> gl));
+  float dlx, dly, dlz;
+  {
+    double gc[3];
+    gcentre(mg, gc);
+    dlx = (float)(cx - gc[0]);
+    dly = (float)(cy - gc[1]);
+    dlz = (float)(cz - gc[2]);
+  }
+  const float fa = (float)E.far_phi_a, fb = (float)E.far_phi_b, faz = (float)E.far_az;
+  float ks = 0.f, kc = 0.f, ax = 0.f, ay = 0.f, az = 0.f;
+  // Cells of this block's size at lattice offsets take their table row from
+  // the lattice rows (their entries' rows for the octant's first cell come
+  // with the list, llat >= 0), as in the column walk with its maps in LDS
+  const int lat_w = 2 * C.lat_r + 1;
+  const int lat_lane = (lz * lat_w + ly) * lat_w + lx;
+  // rows of more than four pixels finish from a per-thread queue at the
+  // tile's end (as in the column walk)
+  constexpr int DQ = 4;
+  uint32_t dq_code[DQ] = {};
+  float dq_base[DQ] = {};
+  int dq_n = 0;
+  auto long_row = [&](uint32_t code, float base) {
+    const int o0 = (int)(code & 0x3ffffffu), o1 = o0 + (int)(code >> 26);
+    const float base24 = base * (1.0f / 16777216.0f);
+    for (int o = o0 + 4; o < o1; o += 2) {
+      const uint32_t v = C.ent[o], u = o + 1 < o1 ? C.ent[o + 1] : 0u;
+      float *const qv = reinterpret_cast<float *>(mcell + ((v >> 24) << lmap));
+      *qv += (float)(v & 0xffffffu) * base24;
+      float *const qu = reinterpret_cast<float *>(mcell + ((u >> 24) << lmap));
+      *qu += (float)(u & 0xffffffu) * base24;
+    }
+  };
+  const int64_t start = off[8 * b + w], n = off[8 * b + w + 1] - start;
+  for (int64_t t0 = 0; t0 < n; t0 += FT4) {
+    const int mt = (int)(n - t0 < FT4 ? n - t0 : FT4);
+    wave_sync();  // the previous tile is consumed
+    if (l < mt) {
+      const int tid = l;
+      const double4 rq = rec[start + t0 + tid];
+      const double hn = lh[start + t0 + tid];
+      const double rh = C.req * hn;  // radius of the equal-volume sphere
+      tile[tid].x = rq.x;
+      tile[tid].y = rq.y;
+      tile[tid].z = rq.z;
+      tile[tid].w = rq.w;
+      // rhs carries the lattice flag in its sign
+      const int32_t li = llat[start + t0 + tid];
+      const bool lat = li >= 0;
+      if (lat) tile[tid].lat = li;
+      else tile[tid].rh2 = rh * rh;
+      tile[tid].rhs = (lat ? -1.0f : 1.0f) * ((float)rh * C.lut_ps);
+      tile[tid].m = (float)rq.w;
+    }
+    float tx = 0.f, ty = 0.f, tz = 0.f;
+    for (int j0 = 0; j0 < mt; j0 += CH) {
+      wave_sync();  // tile loaded; the previous chunk's channels are consumed
+      // network phase: pairs m, entry m / G, group m % G of this sub-block
+      {
+        const int p = m;
+        const int j = j0 + p / G < mt ? j0 + p / G : mt - 1;
+        double gc[3];
+        gcentre(p % G, gc);
+        const ColRec &r = tile[j];
+        const double ex = wrap_axis(gc[0] - r.x, E.L[0], E.inv_L[0], 1);
+        const double ey = wrap_axis(gc[1] - r.y, E.L[1], E.inv_L[1], 1);
+        const double ez = wrap_axis(gc[2] - r.z, E.L[2], E.inv_L[2], BC == 1);
+        const float dx = (float)ex, dy = (float)ey, dz = (float)ez;
+        float y[NO];
+        mlpinf::forward(W, mlpinf::input(fabsf(dx), fabsf(dy), fabsf(dz)), one, y);
+        const float sx = ex < 0 ? -1.f : 1.f, sy = ey < 0 ? -1.f : 1.f, sz = ez < 0 ? -1.f : 1.f;
+        const bool far = BC == 2 && fabs(ez) > E.zfar;
+        float4 *o = reinterpret_cast<float4 *>(slot + TSLOT * p);
+        if (l < 32) {
+          o[0] = make_float4(y[0], sx * y[1], sy * y[2], sz * y[3]);
+          o[1] = make_float4(y[4], y[5], y[6], sx * sy * y[7]);
+        } else {
+          o[2] = make_float4(sx * sz * y[8], sy * sz * y[9], dx, dy);
+          o[3] = make_float4(dz, far ? 1.f : 0.f, 0.f, 0.f);
+        }
+      }
+      wave_sync();
+      // cell phase, software-pipelined by one entry: entry j's map reads are
+      // issued, then entry j + 1's gravity, bins and row-record load, then
+      // entry j's map writes, so the map reads' latency overlaps the next
+      // entry's arithmetic and the record's the map writes (the order of every
+      // sum is that of the plain loop)
+      const int mc = mt - j0 < CH ? mt - j0 : CH;
+      struct PendingRow {
+        uint4 pq, wq;  // the row's four-slot record
+        float base;    // M / (r^2 omega), 0 outside the column reach
+        bool col;
+      };
+      auto row_stage = [&](int jj) {
+        const ColRec r = tile[j0 + jj];
+        // gravity: Newtonian part and the Taylor step from the group's channels
+        float r2, inv;
+        {
+          const float4 *o = reinterpret_cast<const float4 *>(slot + TSLOT * (jj * G + mg));
+          const float4 v0 = o[0], v1 = o[1], v2 = o[2], v3 = o[3];
+          const float dx = v2.z + dlx, dy = v2.w + dly, dz = v3.x + dlz;
+          r2 = dx * dx + dy * dy + dz * dz;
+          const bool valid = r2 != 0.0f;
+          inv = valid ? __builtin_amdgcn_rsqf(fmaxf(r2, 1e-30f)) : 0.0f;
+          const float inv3 = inv * inv * inv;
+          float ph, A0, A1, A2;
+          if (BC == 2 && v3.y != 0.0f) {
+            ph = fa * fabsf(dz) + fb;
+            A0 = 0.0f;
+            A1 = 0.0f;
+            A2 = dz < 0 ? -faz : faz;
+          } else {
+            ph = inv + (v0.x - (v0.y * dlx + v0.z * dly + v0.w * dlz));
+            A0 = dx * inv3 + (v0.y - (v1.x * dlx + v1.w * dly + v2.x * dlz));
+            A1 = dy * inv3 + (v0.z - (v1.w * dlx + v1.y * dly + v2.y * dlz));
+            A2 = dz * inv3 + (v0.w - (v2.x * dlx + v2.y * dly + v1.z * dlz));
+          }
+          const float mw = valid ? r.m : 0.0f;
+          const float yk = mw * ph - kc, tk = ks + yk;
+          kc = (tk - ks) - yk;
+          ks = tk;
+          tx += mw * A0;
+          ty += mw * A1;
+          tz += mw * A2;
+        }
+        // columns: the direction bins and the table row's four-slot record.
+        // A lattice cell's row comes with the list; its offset from the group
+        // centre and the cell's from it are whole multiples of h / 2, so the
+        // gravity's FP32 r^2 is exact and equals the FP64 one: the column
+        // weight uses it directly (the record is the workgroup's: a uniform
+        // branch).  Other records take the FP64 minimum-image offset.
+        bool col;
+        float rd;
+        int e;
+        if (__builtin_amdgcn_readfirstlane(r.rhs < 0.0f ? 1 : 0)) {
+          e = r.lat + lat_lane;
+          col = r2 != 0.0f && (double)r2 <= C.max_dist2;
+          rd = inv;
+        } else {
+          double qx = cx - r.x, qy = cy - r.y, qz = cz - r.z;
+          wrap3<BC>(E, qx, qy, qz);
+          const double q2 = qx * qx + qy * qy + qz * qz;
+          col = q2 != 0.0 && q2 <= C.max_dist2;
+          const float q2f = (float)q2;
+          rd = __builtin_amdgcn_rsqf(fmaxf(q2f, 1e-30f));
+          e = col ? table_row(C, thr, lut, qx, qy, qz, (float)qx, (float)qy, (float)qz, q2, q2f, rd, r.rh2, r.rhs) : 0;
+        }
+        const char *const rq8 = reinterpret_cast<const char *>(C.rows8) + ((uint32_t)e << 5);
+        const uint4 pq = *reinterpret_cast<const uint4 *>(rq8);
+        const uint4 wq = *reinterpret_cast<const uint4 *>(rq8 + 16);
+        PendingRow p;
+        p.pq = pq;
+        p.wq = wq;
+        p.base = (col ? r.m : 0.0f) * rd * rd * inv_omega;
+        p.col = col;
+        return p;
+      };
+      // map values of a pending row's four slots (the padding slots, weight 0,
+      // are not read: they would cost traffic)
+      struct MapVals {
+        float v0, v1, v2, v3;
+      };
+      auto map_load = [&](const PendingRow &p) {
+        MapVals m;
+        m.v1 = m.v2 = m.v3 = 0.f;
+        m.v0 = *reinterpret_cast<const float *>(mcell + (p.pq.x << lmap));
+        if (__uint_as_float(p.wq.y) != 0.0f) m.v1 = *reinterpret_cast<const float *>(mcell + (p.pq.y << lmap));
+        if (__uint_as_float(p.wq.z) != 0.0f) m.v2 = *reinterpret_cast<const float *>(mcell + (p.pq.z << lmap));
+        if (__uint_as_float(p.wq.w) != 0.0f) m.v3 = *reinterpret_cast<const float *>(mcell + (p.pq.w << lmap));
+        return m;
+      };
+      auto map_store = [&](const PendingRow &p, const MapVals &m) {
+        const uint4 pq = p.pq, wq = p.wq;
+        const float base = p.base;
+        const bool col = p.col;
+        const float w0 = __uint_as_float(wq.x), w1 = __uint_as_float(wq.y), w2 = __uint_as_float(wq.z),
+                    w3 = __uint_as_float(wq.w);
+        *reinterpret_cast<float *>(mcell + (pq.x << lmap)) = fmaf(w0, base, m.v0);
+        if (w1 != 0.0f) *reinterpret_cast<float *>(mcell + (pq.y << lmap)) = fmaf(w1, base, m.v1);
+        if (w2 != 0.0f) *reinterpret_cast<float *>(mcell + (pq.z << lmap)) = fmaf(w2, base, m.v2);
+        if (w3 != 0.0f) *reinterpret_cast<float *>(mcell + (pq.w << lmap)) = fmaf(w3, base, m.v3);
+        if ((int)pq.x < 0 && col) {
+          const uint32_t cnt = (pq.x >> 23) & 63u;
+          const uint32_t o0 = (pq.y >> 23) | ((pq.z >> 23) << 9) | ((pq.w >> 23) << 18);
+          if (dq_n == DQ) {
+            long_row(dq_code[DQ - 1], dq_base[DQ - 1]);
+            --dq_n;
+          }
+          for (int k = DQ - 1; k > 0; --k) {
+            dq_code[k] = dq_code[k - 1];
+            dq_base[k] = dq_base[k - 1];
+          }
+          dq_code[0] = (cnt << 26) | o0;
+          dq_base[0] = base;
+          ++dq_n;
+        }
+      };
+      PendingRow cur = row_stage(0);
+      for (int j = 0; j < mc; ++j) {
+        const MapVals mv = map_load(cur);
+        PendingRow nxt = cur;
+        if (j + 1 < mc) nxt = row_stage(j + 1);
+        map_store(cur, mv);
+        cur = nxt;
+      }
+    }
+    for (int k = 0; k < DQ; ++k)
+      if (k < dq_n) long_row(dq_code[k], dq_base[k]);
+    dq_n = 0;
+    ax += tx;
+    ay += ty;
+    az += tz;
+  }
+  const int64_t o = b * 512 + ci;
+  phi[o] = negG * (ks - kc);
+  acc[o] = negG * ax;
+  acc[ncell + o] = negG * ay;
+  acc[2 * ncell + o] = negG * az;
+  double se = 0.0;
+  for (int p = 0; p < C.npix; ++p) se += exp(-C.kappa * (double)*reinterpret_cast<const float *>(mcell + (p << lmap)));
+  tau[o] = (float)(-log(se / (double)C.npix));
+  // slot order -> cell order, eight pixel rows at a time (every slot of a
+  // row is read before any is overwritten)
+  float *const rows = npix + b * C.npix * 512;
+  for (int p0 = 0; p0 < C.npix; p0 += 8) {
+    float v[8];
+    __syncthreads();
+    for (int q = 0; q < 8; ++q) v[q] = p0 + q < C.npix ? rows[(p0 + q) * 512 + tid] : 0.0f;
+    __syncthreads();
+    for (int q = 0; q < 8; ++q)
+      if (p0 + q < C.npix) rows[(p0 + q) * 512 + ci] = v[q];
+  }
+}
+
+
 // table rows of arbitrary offsets d = cell - node with the walk's binning
 // (thresholds and look-up tables in LDS as in the walk); -1 for d = 0
 __global__ __launch_bounds__(256) void k_column_bins(ColP C, int64_t n, const double *__restrict__ d,
@@ -1321,19 +1632,30 @@ hipError_t launch_abu_corner_cols(bool fp64, const DevTree &T, const EwaldP &E, 
 hipError_t launch_eval_cols_mlp(const DevTree &T, const EwaldP &E, const ColP &C, const void *pk, const int64_t *off,
                                 const double4 *rec, const int32_t *ids, const double *lh, int32_t *llat, float *phi,
                                 float *acc, float *npix, float *tau, double G, double tmax, double h_max,
-                                int *wg_per_cu, hipStream_t st) {
+                                int *wg_per_cu, hipStream_t st, int sub) {
   const size_t sm = (size_t)((C.nthr + 1) & ~1) * sizeof(double) +
                     (size_t)taylor_pairs(mlp_group_level(h_max, tmax)) * TSLOT * sizeof(float);
+  // octant lists (sub): eight waves of 32 network pairs each; cell groups of
+  // 2^3 or 4^3 cells, so that each octant holds whole groups
+  const size_t sm4 = (size_t)((C.nthr + 1) & ~1) * sizeof(double) + (size_t)8 * 32 * TSLOT * sizeof(float);
+  if (sub && mlp_group_level(h_max, tmax) < 1) return hipErrorInvalidValue;
   dim3 grid((unsigned)T.nb), blk(512);
   const float ng = (float)(-G);
 #define OT_LAUNCH_CM(B)                                                                                    \
   do {                                                                                                     \
     if (wg_per_cu &&                                                                                       \
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, k_eval_cols_mlp<B>, 512, sm) != hipSuccess) \
+        (sub ? hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, k_eval_cols_mlp4<B>, 512, sm4)     \
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, k_eval_cols_mlp<B>, 512, sm)) !=   \
+            hipSuccess)                                                                                    \
       *wg_per_cu = 0;                                                                                      \
-    hipLaunchKernelGGL((k_lattice_index<B>), grid, dim3(256), 0, st, T, E, C, off, rec, ids, lh, llat);         \
-    hipLaunchKernelGGL((k_eval_cols_mlp<B>), grid, blk, sm, st, T, E, C, pk, off, rec, llat, lh, phi, acc, npix, \
-                       tau, ng, tmax);                                                                     \
+    hipLaunchKernelGGL((k_lattice_index<B>), dim3((unsigned)(sub ? 8 * T.nb : T.nb)), dim3(256), 0, st, T, E, \
+                       C, off, rec, ids, lh, llat, sub);                                                    \
+    if (sub)                                                                                               \
+      hipLaunchKernelGGL((k_eval_cols_mlp4<B>), grid, blk, sm4, st, T, E, C, pk, off, rec, llat, lh, phi, acc, \
+                         npix, tau, ng, tmax);                                                             \
+    else                                                                                                   \
+      hipLaunchKernelGGL((k_eval_cols_mlp<B>), grid, blk, sm, st, T, E, C, pk, off, rec, llat, lh, phi, acc,  \
+                         npix, tau, ng, tmax);                                                             \
   } while (0)
   if (E.bctype == 1) OT_LAUNCH_CM(1);
   else if (E.bctype == 2) OT_LAUNCH_CM(2);

@@ -127,7 +127,8 @@ __global__ __launch_bounds__(WGS) void k_lists(DevTree T, MacP P, int32_t *__res
                                               double4 *__restrict__ rec, int32_t *__restrict__ ids,
                                               double *__restrict__ lh,
                                               int32_t *__restrict__ scratch, int64_t stride,
-                                              int64_t capA, const double *__restrict__ pts, int64_t npts) {
+                                              int64_t capA, const double *__restrict__ pts, int64_t npts,
+                                              int sub) {
   constexpr int NW = WGS / 64;
   __shared__ int swave[3][NW];
   const int tid = threadIdx.x;
@@ -137,13 +138,22 @@ __global__ __launch_bounds__(WGS) void k_lists(DevTree T, MacP P, int32_t *__res
   int32_t *op1 = olb + T.nb;
   const int64_t na = T.na, nb = T.nb;
 
-  const int64_t ntg = pts ? npts : nb;
+  const int64_t ntg = pts ? npts : (sub ? 8 * nb : nb);
   for (int64_t b = blockIdx.x; b < ntg; b += gridDim.x) {
     Target tg;
     if (pts) {
       for (int k = 0; k < 3; ++k) tg.c[k] = pts[3 * b + k];
       tg.ext = 0.0;
       tg.h = 0.0;
+    } else if (sub) {
+      // octant b & 7 of block b >> 3: the box of its 4^3 cell centres
+      const int64_t bb = b >> 3;
+      const int o = (int)(b & 7);
+      const double sb = size_at(T.root_size, T.blev[bb]);
+      for (int k = 0; k < 3; ++k)
+        tg.c[k] = centre_coord(T.org[k], 2 * (int64_t)T.bcoord[3 * bb + k] + ((o >> k) & 1), 0.5 * sb);
+      tg.ext = 1.5 * (sb / 8.0);
+      tg.h = sb / 8.0;
     } else {
       const int blev = T.blev[b];
       const double sb = size_at(T.root_size, blev);
@@ -319,10 +329,11 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ count
 
 hipError_t launch_lists(bool fill, const DevTree &T, const MacP &P, int grid, int32_t *count, int32_t *nodes,
                         const int64_t *off, double4 *rec, int32_t *ids, double *lh, int32_t *scratch,
-                        int64_t stride, int64_t capA, hipStream_t st, const double *pts, int64_t npts) {
+                        int64_t stride, int64_t capA, hipStream_t st, const double *pts, int64_t npts,
+                        int sub) {
 #define OT_LISTS(F, W)                                                                                  \
   hipLaunchKernelGGL((k_lists<F, W>), dim3(grid), dim3(W), 0, st, T, P, count, nodes, off, rec, ids, lh, scratch, \
-                     stride, capA, pts, npts)
+                     stride, capA, pts, npts, sub)
   if (pts) {
     if (fill) OT_LISTS(true, WG_POINT);
     else OT_LISTS(false, WG_POINT);

@@ -111,11 +111,13 @@ hipError_t launch_abu_corner_cols(bool fp64, const DevTree &T, const EwaldP &E, 
 // FP32 walk with the surrogate's gravity and columns with the maps in npix
 // (one workgroup of 512 cells per block; groups and Taylor step as
 // launch_eval_mlp); 3P and 2P1I.  llat [list entries]: scratch for the
-// entries' lattice rows
+// entries' lattice rows.  sub: the lists are per 4^3 block octant (8 nb of
+// them, list b of block b / 8 and octant b % 8); needs cell groups of 2^3 or
+// more cells at h_max
 hipError_t launch_eval_cols_mlp(const DevTree &T, const EwaldP &E, const ColP &C, const void *pk, const int64_t *off,
                                 const double4 *rec, const int32_t *ids, const double *lh, int32_t *llat, float *phi,
                                 float *acc, float *npix, float *tau, double G, double tmax, double h_max,
-                                int *wg_per_cu, hipStream_t st);
+                                int *wg_per_cu, hipStream_t st, int sub = 0);
 // rows of the offsets (i, j, k) cell sizes between two cells of one size,
 // |i|, |j|, |k| <= R (k slowest, i fastest), written at rows C.lat0 + ... of
 // rows, rows8 and quad_w64: copies of the table rows that the walk's binning
@@ -134,11 +136,13 @@ hipError_t launch_build(const DevTree &T, const double *rho, int *bad,
 // count pass (fill false): count [nb] list lengths and, when nodes is not
 // null, nodes [2 nb] = (opened nodes, cells in the list) per block.  With
 // pts [npts][3] (device, FP64) the lists are those of the target points
-// instead, counts and offsets per point.
+// instead, counts and offsets per point; with sub set (and no pts) those of
+// the 4^3 octants of the blocks, list b of block b / 8 and octant b % 8 (bit a
+// set for the upper half of axis a).
 hipError_t launch_lists(bool fill, const DevTree &T, const MacP &P, int grid, int32_t *count, int32_t *nodes,
                         const int64_t *off, double4 *rec, int32_t *ids, double *lh, int32_t *scratch,
                         int64_t scratch_stride, int64_t capA, hipStream_t st, const double *pts = nullptr,
-                        int64_t npts = 0);
+                        int64_t npts = 0, int sub = 0);
 
 hipError_t launch_scan(const int32_t *count, int64_t nb, int64_t *off, hipStream_t st);
 

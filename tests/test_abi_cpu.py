@@ -38,6 +38,16 @@ def test_param_validation():
     with pytest.raises(ot.OTError, match="UNSUPPORTED"):
         ot.Solver(bc=(1, 1, 0), nroot=(1, 2, 4))
     ot.Solver(bc=(1, 1, 0), nroot=(2, 1, 4)).close()
+    # targets of the walk: whole blocks (8, or 0) or 4^3 octants (4)
+    for bad in (2, 16, -4):
+        with pytest.raises(ot.OTError, match="INVALID_ARG"):
+            ot.Solver(list_group=bad)
+    for good in (0, 4, 8):
+        ot.Solver(list_group=good).close()
+    # the binding's struct ends where the library's does: its defaults read back
+    p = ot.Params()
+    ot.lib().ot_params_default(C.byref(p))
+    assert p.list_group == 8 and p.mlp_reach == 1.0 and p.psi_max == 0.98
 
 
 def test_call_order_and_grid_errors():

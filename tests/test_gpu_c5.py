@@ -146,3 +146,64 @@ def test_c5_surrogate_columns(c5, c5_mlp):
           f"eval table {rt['st'].ms_eval:.0f} ms, surrogate {rm['st'].ms_eval:.0f} ms; "
           f"dPhi {dphi:.2e}, da {da:.2e} (of the maxima, on 64 sampled blocks)")
     assert dphi <= 1e-4 and da <= 1e-4
+
+
+def test_c5_octant_lists(c5, c5_mlp):
+    """One list per 4^3 block octant (list_group 4) on the full workload, in
+    the fused walk at mlp_reach 3 as benchmarked: 16 seeded blocks against
+    the oracle with the same octant lists: lists identical as sets on four
+    of them; maps within 1e-5 of their maximum and tau within 1e-5 (the FP32
+    column walk's bars); Phi and a within 1e-4 of their maxima against the
+    oracle's FP64 surrogate walk (same weights, groups and Taylor step: the
+    FP16 network and FP32 sums), and within the metric's 1e-3 against its
+    FP64 table walk (the surrogate at three times the table's Taylor offset
+    adds its own error); e_a,max, e_Phi,max <= 1e-3 against the direct sum
+    on 96 seeded cells and the 16 of largest |a|."""
+    g, rho, a_lim = c5
+    _, mlp = c5_mlp
+    s = ot.Solver.for_grid(g, a_lim=a_lim, ewald="mlp", mlp_reach=3.0, list_group=4, **KW)
+    s.mlp_set(*mlp, accept=True)
+    s.build(rho)
+    n = g.ncells
+    phi, acc = torch.empty(n, device="cuda"), torch.empty(3 * n, device="cuda")
+    npix, tau = torch.empty(n * 192, device="cuda"), torch.empty(n, device="cuda")
+    st = s.solve(phi, acc, npix, tau)
+    assert st.ewald_used == 2 and st.n_interactions == 64 * (st.total_list - 8 * g.nb)
+    sel = np.sort(np.random.default_rng(12).choice(g.nb, 16, replace=False))
+    t = oracle.Tree(g, a_lim=a_lim, ewald="table", ew_n=64, list_group=4, mlp_reach=3.0,
+                    **{k: v for k, v in KW.items() if k != "ewald_n"})
+    for b in sel[:4]:
+        for so in range(8):
+            got = np.sort(s.export_list(8 * b + so).astype(np.int64))
+            assert np.array_equal(got, np.sort(t.octant_list(b, so))), (b, so)
+    pr, ar, nr, npr, tr = t.walk_group(sel, columns=True)
+    pm, am, nm = t.walk_group_mlp(*mlp, sel)
+    assert np.array_equal(nm, nr)
+    cells = torch.from_numpy((512 * sel[:, None] + np.arange(512)).ravel()).cuda()
+    p = phi[cells].double().cpu().numpy()
+    a = acc.view(3, -1)[:, cells].double().cpu().numpy()
+    m = npix.view(g.nb, 192, 512)[torch.from_numpy(sel).cuda()].double().cpu().numpy()
+    ta = tau[cells].double().cpu().numpy()
+    dphi = np.abs(p - pm).max() / np.abs(pm).max()
+    da = np.abs(a - am).max() / np.sqrt((am ** 2).sum(0)).max()
+    dphi_t = np.abs(p - pr).max() / np.abs(pr).max()
+    da_t = np.abs(a - ar).max() / np.sqrt((ar ** 2).sum(0)).max()
+    dn = np.abs(m - npr).max() / np.abs(npr).max()
+    dt = np.abs(ta - tr).max() / max(np.abs(tr).max(), 1.0)
+    top = torch.topk(acc.view(3, -1).double().pow(2).sum(0), 16).indices.cpu().numpy()
+    tg = np.unique(np.concatenate([np.random.default_rng(13).choice(n, 96, replace=False), top]))
+    pd, ad = oracle.Tree(g, ewald="table", ew_n=64).direct(tg)
+    idx = torch.from_numpy(tg).cuda()
+    pw, aw = phi[idx].double().cpu().numpy(), acc.view(3, -1)[:, idx].double().cpu().numpy()
+    ea = np.sqrt(((aw - ad) ** 2).sum(0)).max() / np.sqrt((ad ** 2).sum(0)).max()
+    ep = np.abs(pw - pd).max() / np.abs(pd).max()
+    print(f"C5 octant lists: {st.total_list} entries ({st.n_interactions / n:.0f} per cell), eval "
+          f"{st.ms_eval:.0f} ms; vs the oracle's surrogate walk dPhi {dphi:.2e}, da {da:.2e}, table walk dPhi "
+          f"{dphi_t:.2e}, da {da_t:.2e}; maps {dn:.2e}, tau {dt:.2e}; vs direct e_a,max {ea:.3e}, "
+          f"e_Phi,max {ep:.3e}")
+    assert dphi <= 1e-4 and da <= 1e-4 and dphi_t <= 1e-3 and da_t <= 1e-3
+    assert dn <= 1e-5 and dt <= 1e-5
+    assert ea <= 1e-3 and ep <= 1e-3
+    s.close()
+    del phi, acc, npix, tau
+    torch.cuda.empty_cache()

@@ -548,3 +548,105 @@ def test_fused_column_walk_with_surrogate(trained, name):
     assert np.abs(pf - pt).max() <= 1e-4 * np.abs(pt).max() and np.abs(af - at).max() <= 1e-4 * np.abs(at).max()
     print(f"{name} fused 192-pixel walk: eval {st_f.ms_eval:.2f} ms (gravity walk {st_g.ms_eval:.2f} ms, "
           f"table column walk {st_t.ms_eval:.2f} ms)")
+
+
+# --------------------------------------------- one list per 4^3 block octant
+OCT_REACH = 6.0  # cell groups of 2^3 or 4^3 cells at every level of the deep grid
+
+
+@pytest.mark.parametrize("name", list(BOXES))
+def test_octant_lists_fused_walk_vs_oracle(trained, name):
+    """list_group 4: the fused walk (surrogate gravity and 192-pixel maps)
+    with one list per 4^3 octant of each block, against the oracle with the
+    same octant lists, on two sampled blocks of each of the deep grid's five
+    levels.  Lists bit-exact as sets (the device orders them level by level);
+    Phi and a within the network's FP16 bound summed over each cell's own
+    list masses plus the FP32 walk's rounding, as for the block lists; maps
+    within 1e-5 of their maximum and tau within 1e-5 (the FP32 column walk's
+    bars)."""
+    s_tr, _ = trained[name]
+    params, norm = s_tr.mlp_get()
+    bc, nroot = GRIDS[name]
+    g = workloads.deep_amr(bc, nroot)
+    rho = dev(g.rho.reshape(-1))
+    kw = dict(theta=0.25, mlp_reach=OCT_REACH)
+    (pf, af, nf, tf), st, s = solve32(g, rho, "mlp", (params, norm), nside=4, list_group=4, **kw)
+    assert st.ewald_used == 2
+    assert st.n_interactions == 64 * (st.total_list - 8 * g.nb)
+    rng = np.random.default_rng(37)
+    sel = np.sort(np.concatenate([rng.choice(np.nonzero(g.level == lv)[0], 2, replace=False)
+                                  for lv in range(3, 8)]))
+    t = oracle.Tree(g, theta=0.25, ewald="table", ew_n=64, mlp_reach=OCT_REACH, list_group=4, nside=4)
+    assert sorted({t.mlp_group_level(b) for b in sel}) == [1, 2]
+    lists = {}
+    for b in sel:
+        for so in range(8):
+            lists[b, so] = t.octant_list(b, so)
+            got = np.sort(s.export_list(8 * b + so).astype(np.int64))
+            assert np.array_equal(got, np.sort(lists[b, so])), (b, so)
+    pr, ar, nint = t.walk_group_mlp(params, norm, sel)
+    _, _, _, npr, tr = t.walk_group(sel, columns=True)
+    cells = (512 * sel[:, None] + np.arange(512)).ravel()
+    ex = t.export()
+    d = [offsets(name, 20000, 43)]
+    for b in sel:
+        cT = (np.asarray(g.coord[b]) + 0.5) / 2.0 ** (g.level[b] - 1)
+        d.append(cT - ex["com"][np.concatenate([lists[b, so] for so in range(8)])])
+    d = np.concatenate(d)
+    L = np.asarray(g.nroot, float)
+    d = np.where(np.asarray(g.bc, bool), d - L * np.floor(d / L + 0.5), d)
+    d = d[np.abs(d[:, 2]) <= extent(name)[2]]
+    _, bnd = forward_with_bound(params, norm, d)
+    B = 2 * bnd.max(0)
+    r = OCT_REACH * taylor_reach()
+    ci = np.arange(512)
+    octs = ((ci % 8) // 4) + 2 * (((ci // 8) % 8) // 4) + 4 * ((ci // 64) // 4)
+    msum = np.concatenate([np.array([ex["M"][lists[b, so]].sum() for so in range(8)])[octs] for b in sel])
+    bphi = msum * (B[0] + 3 * r * B[1:4].max()) + 1e-6 * np.abs(pr).max()
+    ba = msum * (B[1:4].max() + 3 * r * B[4:].max()) + 1e-5 * np.abs(ar).max()
+    dphi = np.abs(pf[cells] - pr)
+    da = np.abs(af[:, cells] - ar).max(0)
+    nsel = nf.reshape(g.nb, 192, 512)[sel]
+    dn = np.abs(nsel - npr).max() / np.abs(npr).max()
+    dt = np.abs(tf[cells] - tr).max() / max(np.abs(tr).max(), 1.0)
+    print(f"{name} octant lists: {st.total_list} entries over {8 * g.nb} lists; max |dPhi| / bound "
+          f"{(dphi / bphi).max():.3f}, max |da| / bound {(da / ba).max():.3f}; maps {dn:.2e}, tau {dt:.2e}; "
+          f"eval {st.ms_eval:.2f} ms")
+    assert (dphi <= bphi).all() and (da <= ba).all()
+    assert dn <= 1e-5 and dt <= 1e-5
+    assert nint.sum() == sum(len(v) for v in lists.values())
+
+
+def test_octant_lists_need_the_fused_walk(trained):
+    """list_group 4 runs only in the fused walk: other solves of such a
+    context and the adaptive update refuse it; list_group must be 0, 4 or 8."""
+    s_tr, _ = trained["3p"]
+    params, norm = s_tr.mlp_get()
+    bc, nroot = GRIDS["3p"]
+    g = workloads.deep_amr(bc, nroot)
+    rho = dev(g.rho.reshape(-1))
+    n = g.nb * 512
+    cases = (("table", dict(nside=4, mlp_reach=OCT_REACH)),         # no surrogate
+             ("mlp", dict(mlp_reach=OCT_REACH)),                     # no columns
+             ("mlp", dict(nside=2, mlp_reach=OCT_REACH)),            # maps in LDS
+             ("mlp", dict(nside=4)))                                 # single-cell groups at level 3
+    for mode, kw in cases:
+        with pytest.raises(ot.OTError) as e:
+            solve32(g, rho, mode, (params, norm) if mode == "mlp" else None, list_group=4, **kw)
+        assert e.value.status == ot.OT_ERR_UNSUPPORTED, (mode, kw)
+    s = ot.Solver.for_grid(g, theta=0.5, ewald_n=64, ewald="mlp", nside=4, list_group=4, mlp_reach=OCT_REACH)
+    s.mlp_set(params, norm, accept=True)
+    s.build(rho)
+    out = [torch.empty(k, dtype=torch.float64, device="cuda") for k in (n, 3 * n, 192 * n, n)]
+    with pytest.raises(ot.OTError) as e:
+        s.solve64(*out)
+    assert e.value.status == ot.OT_ERR_UNSUPPORTED
+    out = [o.float() for o in out]
+    with pytest.raises(ot.OTError) as e:
+        s.solve_abu(out[0], out[1], 1e-3, npix=out[2], tau=out[3], tol_tau=1e-3)
+    assert e.value.status == ot.OT_ERR_UNSUPPORTED
+    s.close()
+    for bad in (2, 16):
+        with pytest.raises(ot.OTError) as e:
+            ot.Solver(bc=bc, list_group=bad)
+        assert e.value.status == ot.OT_ERR_INVALID_ARG
