@@ -781,7 +781,10 @@ def main():
                                       bool(rep["ok"]), list_group=4)
         e_oct["list_group"] = 4
         e_oct["n_mlp_evals"] = st_oct.n_mlp_evals
-        e_oct["roofline"] = dict(fused_roofline(st_oct), kernel="k_eval_cols_mlp4")
+        tr_oct = measured_traffic("profiles/eval_cols_mlp4_c5amr_nside4_hbm_traffic.txt",
+                                  "paper_1708_06142_amd/csrc/k_columns.hip")
+        e_oct["roofline"] = dict(fused_roofline(st_oct), kernel="k_eval_cols_mlp4",
+                                 traffic=tr_oct["bytes"] if tr_oct else None, traffic_detail=tr_oct)
         if o64 is not None:
             e_oct.update(maxnorm_diffs(o_oct, o64))
         out["octant_lists"] = e_oct
