@@ -330,12 +330,13 @@ def direct_errors(t, g, phi, acc, ncells, seed=17):
     ep = np.abs(pw - pd) / np.abs(pd).max()
     return {"e_a_max": float(ea.max()), "e_phi_max": float(ep.max()), "cells": int(tg.size),
             "sample": f"{ncells} seeded cells and the {ncells // 2} of largest |a|",
-            "reference": "oracle direct sum over all other cells, FP64, same 64^3 Ewald table",
+            "reference": "oracle direct sum over all other cells, FP64" +
+                         (", same 64^3 Ewald table" if any(g.bc) else " (isolated)"),
             "seconds": sec, "seconds_per_target": sec / tg.size}
 
 
-def raymarch_errors(t, g, maps, ncells=12, seed=19):
-    """Largest |difference| of 192-pixel maps from the oracle's ray-marched
+def raymarch_errors(t, g, maps, ncells=12, seed=19, nside=4):
+    """Largest |difference| of the per-cell maps from the oracle's ray-marched
     column densities (exact integrals of rho through the cells along the
     Nside-16 pixel-centre rays, averaged per pixel) on seeded cells and the
     cell of largest reference column, normalised by the largest reference
@@ -345,17 +346,18 @@ def raymarch_errors(t, g, maps, ncells=12, seed=19):
     tg = np.unique(np.concatenate([rng.choice(g.ncells, ncells, replace=False),
                                    [int(np.argmax(g.rho.reshape(-1)))]]))
     t0 = time.perf_counter()
-    ref = np.stack([t.raymarch(int(c), 4) for c in tg])
+    ref = np.stack([t.raymarch(int(c), nside) for c in tg])
     sec = time.perf_counter() - t0
     rmax = np.abs(ref).max()
+    npx = 12 * nside * nside
     res = {}
     for label, npix in maps.items():
-        v = npix.view(g.nb, 192, 512)
+        v = npix.view(g.nb, npx, 512)
         got = np.stack([v[c // 512, :, c % 512].double().cpu().numpy() for c in tg])
         res[label] = float(np.abs(got - ref).max() / rmax)
     return {"maxnorm_vs_raymarch": res, "cells": int(tg.size), "seconds": sec,
             "sample": f"{ncells} seeded cells and the densest cell",
-            "reference": "oracle ray-marched columns, Nside 16 rays averaged into the 192 pixels"}
+            "reference": f"oracle ray-marched columns, Nside 16 rays averaged into the {npx} pixels"}
 
 
 def cpu_model():
@@ -672,10 +674,12 @@ def abu_leg(grid, a_lim, nsnap=6, seed=12, nside=0, tol_a=2.5e-4, tol_tau=1e-3):
     return out
 
 
-def c2_leg(steps, warmup, nside=2):
+def c2_leg(steps, warmup, nside=2, oracle_checks=True):
     """128^3 lognormal field (sigma_ln 1.5, seed 2), isolated, APE a_lim =
     1e-3 a_max, 48-pixel columns: the FP32-Kahan column walk with its maps in
-    LDS, beside the FP64 walk; with its HBM counters when committed."""
+    LDS, beside the FP64 walk; with its HBM counters when committed.  With
+    oracle_checks, the FP32 walk's errors against the oracle's direct sum and
+    its maps against the oracle's ray-marched columns."""
     import torch
     import paper_1708_06142_amd as ot
     import workloads
@@ -710,7 +714,15 @@ def c2_leg(steps, warmup, nside=2):
     out["fp64_walk"] = {"value": n / (ms64 * 1e-3), "ms_per_step": ms64, "ms_eval": e64,
                         "roofline": cols_roofline(st64, FLOP_PAIR_COLS, True, "k_eval_cols<double, isolated>"),
                         "eval_wg_per_cu": st64.eval_wg_per_cu}
+    out["fp32_vs_fp64"] = {k.replace("_vs_fp64_table", ""): v for k, v in maxnorm_diffs(outs, outs64).items()}
     s.close()
+    del outs64
+    if oracle_checks:
+        import oracle
+        t = oracle.Tree(grid, mac="ape", a_lim=a_lim, nside=nside)
+        out["accuracy_vs_direct"] = direct_errors(t, grid, outs[0], outs[1], 256)
+        out["columns_vs_raymarch"] = raymarch_errors(t, grid, {"fp32": outs[2]}, nside=nside)
+        del t
     return out, grid, rho, a_lim
 
 
@@ -823,7 +835,7 @@ def main():
     del outs, o64, o_oct
     torch.cuda.empty_cache()
     if not args.no_c2 or not args.no_surrogate or not args.no_abu or not args.no_mpe:
-        c2, grid, rho2, a2 = c2_leg(args.c2_steps, 2)
+        c2, grid, rho2, a2 = c2_leg(args.c2_steps, 2, oracle_checks=not args.no_direct and not args.no_c2)
         if not args.no_c2:
             out["c2"] = c2
         progress("128^3 lognormal leg done")

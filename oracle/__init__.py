@@ -191,9 +191,11 @@ class Tree:
         self.nn = lib().or_tree_nn(self.h)
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().or_tree_free(self.h)
-            self.h = None
+        h, self.h = getattr(self, "h", None), None
+        # at interpreter exit the module's globals may already be gone (the
+        # process frees the memory then)
+        if h and callable(lib):
+            lib().or_tree_free(h)
 
     def export(self):
         na, nn = self.na, self.nn
