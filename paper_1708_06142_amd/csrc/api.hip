@@ -869,17 +869,22 @@ ot_status points_impl(ot_ctx *c, int64_t n, const double *xyz, double *phi, doub
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(c->p.device));
   // every point inside the domain: its offsets to the nodes then stay within
-  // the box on every isolated axis (the Ewald table's range)
+  // the box on every isolated axis (the Ewald table's range).  Checked on the
+  // device; the host reads one index per checking workgroup.
   {
-    std::vector<double> h(3 * (size_t)n);
-    HIPCHK(hipMemcpyAsync(h.data(), xyz, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    ot::Box3 box;
+    for (int k = 0; k < 3; ++k) {
+      box.lo[k] = c->p.origin[k];
+      box.hi[k] = c->p.origin[k] + c->p.nroot[k] * c->p.root_size;
+    }
+    const int cgrid = (int)std::min<int64_t>((n + 255) / 256, 1024);
+    OTCHK(dalloc(c, c->pcheck, (size_t)cgrid * sizeof(int64_t)));
+    HIPCHK(ot::launch_points_check(xyz, n, box, cgrid, P<int64_t>(c->pcheck), st));
+    std::vector<int64_t> first(cgrid);
+    HIPCHK(hipMemcpyAsync(first.data(), c->pcheck.ptr, first.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    for (int64_t i = 0; i < n; ++i)
-      for (int k = 0; k < 3; ++k) {
-        const double lo = c->p.origin[k], hi = lo + c->p.nroot[k] * c->p.root_size, x = h[3 * i + k];
-        if (!(x >= lo && x < hi))
-          return fail(c, OT_ERR_INVALID_ARG, "target point " + std::to_string(i) + " is not inside the domain");
-      }
+    const int64_t bad = *std::min_element(first.begin(), first.end());
+    if (bad < n) return fail(c, OT_ERR_INVALID_ARG, "target point " + std::to_string(bad) + " is not inside the domain");
   }
   if (c->bctype != ot::BC_ISO) {
     if (c->p.ewald == OT_EWALD_EXACT)
@@ -1618,7 +1623,7 @@ void ot_destroy(ot_ctx *c) {
   DevBuf *all[] = {&c->alev, &c->acoord, &c->achild0, &c->aleaf, &c->blev,   &c->bcoord,
                    &c->bamr, &c->amc,    &c->aS,      &c->btmc,  &c->cm,     &c->flag,
                    &c->lcount, &c->lnodes, &c->llat, &c->loff, &c->lrec,    &c->lid,   &c->lscratch, &c->tab64,
-                   &c->pcount, &c->pnodes, &c->poff, &c->prec, &c->pid,
+                   &c->pcount, &c->pnodes, &c->poff, &c->prec, &c->pid, &c->pcheck,
                    &c->tab32, &c->rt_off, &c->rt_pix, &c->rt_w64, &c->rt_rows, &c->rt_ent, &c->rt_rows8, &c->rt_quad64, &c->mpe_a, &c->mpe_b, &c->mpe_pnode, &c->mpe_pblock, &c->mpe_poff, &c->mpe_part, &c->abu_flag, &c->abu_blist, &c->rt_lut,
                    &c->rt_thr, &c->lh, &c->mlp_P, &c->mlp_pk, &c->mlp_part, &c->mlp_lossp,
                    &c->mlp_loss};

@@ -60,7 +60,7 @@ struct ot_ctx {
   // interaction lists
   ot::DevBuf lcount, lnodes, loff, lrec, lid, lscratch, llat;
   // lists of the last ot_solve_points call (per target point)
-  ot::DevBuf pcount, pnodes, poff, prec, pid;
+  ot::DevBuf pcount, pnodes, poff, prec, pid, pcheck;
   std::vector<int64_t> poff_host;
   int64_t npts = 0;
   int list_sub = 0;

@@ -325,7 +325,41 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ count
   if (tid == 0) off[nb] = carry;
 }
 
+// Index of the first target point outside [lo, hi) on some axis (a NaN
+// coordinate fails every comparison), or n when all lie inside: workgroup w
+// writes the smallest such index of its grid-strided points to first[w].
+__global__ __launch_bounds__(256) void k_points_check(const double *__restrict__ xyz, int64_t n, Box3 box,
+                                                      int64_t *__restrict__ first) {
+  __shared__ int64_t wmin[4];
+  int64_t m = n;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    bool in = true;
+    for (int k = 0; k < 3; ++k) {
+      const double x = xyz[3 * i + k];
+      in = in && x >= box.lo[k] && x < box.hi[k];
+    }
+    if (!in && i < m) m = i;
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    const int64_t o = __shfl_xor(m, d);
+    m = o < m ? o : m;
+  }
+  if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t r = wmin[0];
+    for (int w = 1; w < 4; ++w) r = wmin[w] < r ? wmin[w] : r;
+    first[blockIdx.x] = r;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_points_check(const double *xyz, int64_t n, const Box3 &box, int grid, int64_t *first,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_points_check, dim3(grid), dim3(256), 0, st, xyz, n, box, first);
+  return hipGetLastError();
+}
 
 hipError_t launch_lists(bool fill, const DevTree &T, const MacP &P, int grid, int32_t *count, int32_t *nodes,
                         const int64_t *off, double4 *rec, int32_t *ids, double *lh, int32_t *scratch,

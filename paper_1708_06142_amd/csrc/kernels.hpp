@@ -133,6 +133,15 @@ hipError_t launch_mpe(const DevTree &T, int64_t npairs, const int32_t *pnode, co
 hipError_t launch_build(const DevTree &T, const double *rho, int *bad,
                         const std::vector<int64_t> &level_begin, int lmax, hipStream_t st);
 
+// target points: first[w] (w < grid) = the smallest index of a point of
+// xyz [n][3] (device, FP64) outside [box.lo, box.hi) on some axis or not a
+// number, among those of workgroup w (grid-strided), n if none
+struct Box3 {
+  double lo[3], hi[3];
+};
+hipError_t launch_points_check(const double *xyz, int64_t n, const Box3 &box, int grid, int64_t *first,
+                               hipStream_t st);
+
 // count pass (fill false): count [nb] list lengths and, when nodes is not
 // null, nodes [2 nb] = (opened nodes, cells in the list) per block.  With
 // pts [npts][3] (device, FP64) the lists are those of the target points

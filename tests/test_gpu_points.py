@@ -7,7 +7,8 @@ and max |a| over the points).  Isolated, 3P, 2P1I and 1P2I small AMR grids
 with BH, APE and MPE, at seeded points that include the domain's lower corner,
 the point one ulp inside its upper corner, cell centres (where the cell itself
 is skipped) and a node centre; the 128^3 lognormal field with 20,000 points
-sampled against the oracle; n = 0; points outside the domain are refused; a
+sampled against the oracle; n = 0; points outside the domain or not a number
+are refused, the first of them named; a
 context set up for the surrogate still evaluates points with the table.
 """
 import numpy as np
@@ -98,8 +99,13 @@ def test_points_edge_cases():
                         torch.empty((3, 0), dtype=torch.float64, device="cuda"))
     assert st.total_list == 0
     for bad in ([1.0, 0.5, 0.5], [0.5, -1e-17, 0.5], [np.nan, 0.5, 0.5]):
-        with pytest.raises(ot.OTError):
+        with pytest.raises(ot.OTError, match="target point 1 is not inside"):
             solve_points(s, np.array([[0.5, 0.5, 0.5], bad]))
+    # the first point outside is named, among 1,000 with several outside
+    x = workloads.target_points(g, 1000)
+    x[[617, 618, 940], 1] = [1.5, np.nan, -0.25]
+    with pytest.raises(ot.OTError, match="target point 617 is not inside"):
+        solve_points(s, x)
     # a failed call leaves no lists behind; a good one works after it
     with pytest.raises(ot.OTError):
         s.export_point_list(0)
