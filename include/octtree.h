@@ -224,7 +224,8 @@ ot_status ot_solve_abu64(ot_ctx *c, double *phi_dev, double *acc_dev, double *np
  * or eps_lim times the BH pre-pass maximum).  Needs a successful ot_build.
  * xyz_dev  [n][3] FP64 device positions, each inside the domain: origin <= x <
  *          origin + nroot root_size on every axis (periodic ones too), else
- *          OT_ERR_INVALID_ARG (also for NaN); read to the host once to check.
+ *          OT_ERR_INVALID_ARG naming the first such point (also for NaN);
+ *          checked on the device before any list is built.
  * phi_dev  [n] FP64 device output; acc_dev [3][n] FP64 device output
  *          (component-major), both owned by the caller.
  * n        0 <= n <= 2^31; n = 0 returns OT_OK and touches nothing.
