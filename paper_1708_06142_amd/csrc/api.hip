@@ -497,6 +497,9 @@ ot::ColP col_params(ot_ctx *c) {
 
 // Interaction lists for the given MAC: count, scan, fill.
 ot_status build_lists(ot_ctx *c, const ot::MacP &mp, bool sizes, hipStream_t st, int sub = 0) {
+  // the host's copy of the offsets describes the previous lists until the
+  // caller refreshes it: exports wait for that
+  c->lists_valid = false;
   const ot::Topology &t = c->topo;
   ot::DevTree T = dev_tree(c);
   const int64_t ntg = sub ? 8 * t.nb : t.nb;
