@@ -800,8 +800,14 @@ def main():
         # the headline walk with one list per 4^3 block octant in place of one
         # per block: the same MAC suite against each octant's box, so shorter
         # lists that still pass it at every cell
-        o_oct, st_oct, e_oct = c5_run(g, rho, kw, a_lim, "mlp", False, args.steps, args.warmup, mlp,
-                                      bool(rep["ok"]), list_group=4)
+        import paper_1708_06142_amd as ot
+        try:
+            o_oct, st_oct, e_oct = c5_run(g, rho, kw, a_lim, "mlp", False, args.steps, args.warmup, mlp,
+                                          bool(rep["ok"]), list_group=4)
+        except (ot.OTError, torch.cuda.OutOfMemoryError) as ex:  # no room for eight lists per block
+            o_oct, st_oct, e_oct = None, None, {"error": str(ex)}
+            torch.cuda.empty_cache()
+    if o_oct is not None:
         e_oct["list_group"] = 4
         e_oct["n_mlp_evals"] = st_oct.n_mlp_evals
         tr_oct = measured_traffic("profiles/eval_cols_mlp4_c5amr_nside4_hbm_traffic.txt",
@@ -810,8 +816,9 @@ def main():
                                  traffic=tr_oct["bytes"] if tr_oct else None, traffic_detail=tr_oct)
         if o64 is not None:
             e_oct.update(maxnorm_diffs(o_oct, o64))
-        out["octant_lists"] = e_oct
         progress(f"octant lists: {e_oct['ms_per_step']:.1f} ms/step")
+    if not args.no_octant:
+        out["octant_lists"] = e_oct
     if not args.no_points:
         out["points"] = points_leg(g, rho, a_lim)
     torch.cuda.synchronize()
