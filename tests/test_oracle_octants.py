@@ -15,6 +15,9 @@ walk, with a smaller target group).
 * The surrogate walk picks the list of the octant that holds each cell group:
   the constant-network closed form of the surrogate pins, with the octant
   lists, to 1e-12 (2^3 and 4^3 groups).
+* The adaptive update over octant lists: tolerance 0 is the octant-list walk
+  bit for bit, an unchanged density keeps every block, and a local bump's
+  decisions follow the corner criterion read from independent full walks.
 * Planted mistakes (octant bits transposed, the octant centre mirrored, the
   block's extent kept) are each caught.
 """
@@ -27,6 +30,7 @@ import pytest
 import oracle
 import workloads
 from test_oracle_mac import decide, node_geometry, visited
+from test_oracle_abu import _perturbed
 from test_oracle_mlpwalk import EW_N, closed_form, const_surrogate, lognormal16
 from test_oracle_tree import _node_cells
 
@@ -203,3 +207,30 @@ def test_octant_pins_catch_planted_mistakes(oct_mutants, name):
             except AssertionError:
                 caught += 1
     assert caught, f"no pin catches the mutant '{name}'"
+
+
+def test_adaptive_update_with_octant_lists():
+    """The adaptive update walks each cell over its octant's list too:
+    tolerance 0 is the octant-list group walk bit for bit, an unchanged
+    density keeps every block, and on a perturbed density the decisions
+    follow the corner criterion read from independent full walks."""
+    g = workloads.small_amr()
+    t = oracle.Tree(g, theta=0.5, list_group=4)
+    p0, a0, _ = t.walk_group()
+    p, a, upd = t.walk_abu(np.zeros_like(p0), np.zeros_like(a0), 0.0)
+    assert upd.all() and np.array_equal(p, p0) and np.array_equal(a, a0)
+    p, a, upd = t.walk_abu(p0, a0, 1e-12)
+    assert not upd.any() and np.array_equal(p, p0) and np.array_equal(a, a0)
+    # a local bump in the density
+    g1 = _perturbed(g)
+    t1 = oracle.Tree(g1, theta=0.5, list_group=4)
+    p1, a1, _ = t1.walk_group()
+    tol = 1e-3 * np.sqrt((a1 ** 2).sum(0)).max()
+    p, a, upd = t1.walk_abu(p0, a0, tol)
+    corners = [7 * (k & 1) + 56 * ((k >> 1) & 1) + 448 * (k >> 2) for k in range(8)]
+    da = np.sqrt(((a1 - a0) ** 2).sum(0)).reshape(g.nb, 512)[:, corners].max(1)
+    assert np.array_equal(upd.astype(bool), ~(da < tol))
+    assert 0 < upd.sum() < g.nb
+    pb = p.reshape(g.nb, 512)
+    assert np.array_equal(pb[upd == 1], p1.reshape(g.nb, 512)[upd == 1])
+    assert np.array_equal(pb[upd == 0], p0.reshape(g.nb, 512)[upd == 0])
