@@ -650,3 +650,30 @@ def test_octant_lists_need_the_fused_walk(trained):
         with pytest.raises(ot.OTError) as e:
             ot.Solver(bc=bc, list_group=bad)
         assert e.value.status == ot.OT_ERR_INVALID_ARG
+
+
+def test_octant_lists_on_a_single_block(trained):
+    """The degenerate grid: one 8^3 block filling a 3P box, mlp_reach 16 so
+    that the 1/8 cells form 2^3 groups.  Every octant's list against the
+    oracle's (as sets), Phi and a within 1e-4 of their maxima of the oracle's
+    FP64 surrogate walk with the same lists and weights, maps 1e-5 and tau
+    1e-5 of the oracle's walk."""
+    s_tr, _ = trained["3p"]
+    params, norm = s_tr.mlp_get()
+    rho = np.random.default_rng(41).lognormal(0.0, 1.0, (1, 8, 8, 8))
+    g = workloads.Grid((1, 1, 1), 1.0, (0.0, 0.0, 0.0), np.array([1], np.int32), np.zeros((1, 3), np.int32),
+                       rho, (1, 1, 1), "one block")
+    kw = dict(theta=0.25, mlp_reach=16.0)
+    (pf, af, nf, tf), st, s = solve32(g, dev(g.rho.reshape(-1)), "mlp", (params, norm), nside=4, list_group=4,
+                                      **kw)
+    t = oracle.Tree(g, theta=0.25, ewald="table", ew_n=64, mlp_reach=16.0, list_group=4, nside=4)
+    assert t.mlp_group_level(0) == 1
+    for so in range(8):
+        assert np.array_equal(np.sort(s.export_list(so).astype(np.int64)), np.sort(t.octant_list(0, so)))
+    pm, am, _ = t.walk_group_mlp(params, norm, [0])
+    _, _, _, npr, tr = t.walk_group([0], columns=True)
+    assert np.abs(pf - pm).max() <= 1e-4 * np.abs(pm).max()
+    assert np.abs(af - am).max() <= 1e-4 * np.sqrt((am ** 2).sum(0)).max()
+    assert np.abs(nf.reshape(1, 192, 512) - npr).max() <= 1e-5 * np.abs(npr).max()
+    assert np.abs(tf - tr).max() <= 1e-5 * max(np.abs(tr).max(), 1.0)
+    assert st.total_list == sum(len(t.octant_list(0, so)) for so in range(8))
