@@ -120,6 +120,24 @@ def measured_traffic(path, source):
             "write_factor": float(kv["write_factor"]), "summary": path}
 
 
+def measured_limiter(path, source, prefix=""):
+    """Busy fractions of the address units and the vector ALU issue from a
+    committed counter summary, or None when the kernel's source has changed
+    since the counters were taken."""
+    import hashlib
+    try:
+        kv = dict(l.split(": ", 1) for l in open(os.path.join(ROOT, path)).read().splitlines()
+                  if l and not l.startswith("#") and ": " in l)
+        sha = hashlib.sha256(open(os.path.join(ROOT, source), "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if not sha.startswith(kv.get("source_sha256_prefix", "-")):
+        return None
+    return {"address_units_busy": float(kv[prefix + "ta_busy"]),
+            "valu_issue_busy": float(kv[prefix + "valu_issue_busy"]),
+            "source": "rocprofv3 counters (TA_TA_BUSY_sum, SQ_INSTS_VALU)", "summary": path}
+
+
 def timed_steps(solver, rho, outs, fp64, steps, warmup):
     import torch
     solve = solver.solve64 if fp64 else solver.solve
@@ -763,6 +781,9 @@ def main():
                                    "paper_1708_06142_amd/csrc/k_columns.hip")
         kernels = {"gravity_and_columns": dominant}
     dominant = dict(dominant, traffic=traffic["bytes"] if traffic else None, traffic_detail=traffic)
+    if st.ms_gravity <= 0:
+        dominant["busy_units"] = measured_limiter("profiles/eval_cols_mlp_c5amr_nside4_limiter.txt",
+                                                  "paper_1708_06142_amd/csrc/k_columns.hip")
     out = {
         "metric": "cells/s for potential+accel+N_pix column densities at <=1e-3 rel err",
         "value": e["value"], "unit": "cells/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -813,7 +834,9 @@ def main():
         tr_oct = measured_traffic("profiles/eval_cols_mlp4_c5amr_nside4_hbm_traffic.txt",
                                   "paper_1708_06142_amd/csrc/k_columns.hip")
         e_oct["roofline"] = dict(fused_roofline(st_oct), kernel="k_eval_cols_mlp4",
-                                 traffic=tr_oct["bytes"] if tr_oct else None, traffic_detail=tr_oct)
+                                 traffic=tr_oct["bytes"] if tr_oct else None, traffic_detail=tr_oct,
+                                 busy_units=measured_limiter("profiles/eval_cols_mlp_c5amr_nside4_limiter.txt",
+                                                             "paper_1708_06142_amd/csrc/k_columns.hip", "octant_"))
         if o64 is not None:
             e_oct.update(maxnorm_diffs(o_oct, o64))
         progress(f"octant lists: {e_oct['ms_per_step']:.1f} ms/step")
